@@ -1,0 +1,557 @@
+"""Plain FP64 CPU oracle for the generalized Sinkhorn scaling iteration of
+entropic unbalanced optimal transport (Chizat, Peyre, Schmitzer, Vialard,
+"Scaling algorithms for unbalanced optimal transport problems").
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports this module:
+only the tests, the package smoke check and the CPU-baseline leg of the
+benchmark do.  It shares no code with the HIP path; the two meet only in the
+seeded input generators (which hold none of the method's arithmetic).
+
+Conventions (discrete setting of Sec. 4 "Numerical algorithm for discrete
+measures"):
+  * X = {x_i}, Y = {y_j}, reference weights dx_i, dy_j > 0;
+  * densities p = mu/dx, q = nu/dy (Sec. 5.1, eq. (UOT));
+  * potentials u = eps log a, v = eps log b (Prop. "alternating"), so the plan
+    w.r.t. dx (x) dy is R_ij = exp((u_i + v_j - C_ij)/eps) (Thm. "duality");
+  * all arrays are float64 and log-densities carry -inf where the density is 0
+    (convention 0/0 = 0 of Sec. 1 "Notation").
+
+Functions without an independent pin in tests/ are flagged "parity unpinned"
+in their docstring; at the time of writing every function is pinned.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Callable, List, Optional, Sequence
+
+import numpy as np
+
+LOG2 = np.log(2.0)
+
+
+# ---------------------------------------------------------------------------
+# elementary helpers
+# ---------------------------------------------------------------------------
+def lse(a: np.ndarray, axis) -> np.ndarray:
+    """log(sum(exp(a))) along `axis`; an all -inf slice gives -inf."""
+    a = np.asarray(a, dtype=np.float64)
+    m = np.max(a, axis=axis, keepdims=True)
+    m_safe = np.where(np.isfinite(m), m, 0.0)
+    with np.errstate(divide="ignore", over="ignore", invalid="ignore"):
+        s = np.sum(np.exp(a - m_safe), axis=axis, keepdims=True)
+        out = np.log(s) + m_safe
+    return np.squeeze(out, axis=axis)
+
+
+def safe_log(x: np.ndarray) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        return np.log(x)
+
+
+# ---------------------------------------------------------------------------
+# divergences: Sec. 2.1 (entropy functions, Examples KL / TV / = / RG)
+# ---------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Div:
+    """A marginal functional F(s) = sum_i dx_i Dbar_phi(s_i | p_i) (eq.
+    "divergencefunctions"), scaled by `lam` for KL and TV.
+
+    kind: "eq" (equality constraint), "kl" (lam * KL), "tv" (lam * TV),
+    "rg" (range constraint RG[alpha, beta], 0 <= alpha <= beta <= inf).
+    """
+    kind: str
+    lam: float = 1.0
+    alpha: float = 0.0
+    beta: float = np.inf
+
+
+EQ = Div("eq")
+
+
+def KL(lam):
+    return Div("kl", lam=float(lam))
+
+
+def TV(lam):
+    return Div("tv", lam=float(lam))
+
+
+def RG(alpha, beta):
+    return Div("rg", alpha=float(alpha), beta=float(beta))
+
+
+# ---------------------------------------------------------------------------
+# proxdiv: Table "proximalexplicit" (Sec. 5.1), stabilized form of eq.
+# (proxdiv) in Sec. 4.3.  proxdiv_F(s, u, eps) = prox^KL_{F/eps}(e^{-u/eps} s) / s
+# ---------------------------------------------------------------------------
+def proxdiv_log(F: Div, logp: np.ndarray, logs: np.ndarray, ubar, eps: float) -> np.ndarray:
+    """Logarithm of the stabilized proxdiv of Table proximalexplicit, with
+    absorbed offset `ubar` (0 gives the plain proxdiv of eq. (proxdiv_a)).
+
+    Rows (log of the table's right column):
+      =      : log p - log s
+      lam KL : lam/(lam+eps) (log p - log s) - ubar/(lam+eps)
+      lam TV : clamp(log p - log s, -(lam+ubar)/eps, (lam-ubar)/eps)
+      RG     : min(log beta + log p - log s, max(log alpha + log p - log s, -ubar/eps))
+    """
+    logp = np.asarray(logp, dtype=np.float64)
+    logs = np.asarray(logs, dtype=np.float64)
+    ubar = np.broadcast_to(np.asarray(ubar, dtype=np.float64), logp.shape)
+    with np.errstate(invalid="ignore"):
+        d = logp - logs
+    if F.kind == "eq":
+        return d
+    if F.kind == "kl":
+        z = F.lam / (F.lam + eps)
+        return z * d - ubar / (F.lam + eps)
+    if F.kind == "tv":
+        lo = -(F.lam + ubar) / eps
+        hi = (F.lam - ubar) / eps
+        return np.minimum(np.maximum(d, lo), hi)
+    if F.kind == "rg":
+        lower = (np.log(F.alpha) + d) if F.alpha > 0 else np.full_like(d, -np.inf)
+        inner = np.maximum(lower, -ubar / eps)
+        if np.isinf(F.beta):
+            return inner
+        return np.minimum(np.log(F.beta) + d, inner)
+    raise ValueError(F.kind)
+
+
+def proxdiv_scaling(F: Div, p: np.ndarray, s: np.ndarray, ubar, eps: float) -> np.ndarray:
+    """Table proximalexplicit, right column, evaluated in the scaling domain
+    (plain exponentials; used by the literal Algorithms 1 and 2).  0/0 = 0."""
+    p = np.asarray(p, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    ubar = np.broadcast_to(np.asarray(ubar, dtype=np.float64), p.shape)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where((p == 0) & (s == 0), 0.0, p / s)
+    if F.kind == "eq":
+        return ratio
+    if F.kind == "kl":
+        z = F.lam / (F.lam + eps)
+        return ratio ** z * np.exp(-ubar / (F.lam + eps))
+    if F.kind == "tv":
+        return np.minimum(np.exp((F.lam - ubar) / eps), np.maximum(np.exp(-(F.lam + ubar) / eps), ratio))
+    if F.kind == "rg":
+        inner = np.maximum(F.alpha * ratio, np.exp(-ubar / eps))
+        if np.isinf(F.beta):
+            return inner
+        return np.minimum(F.beta * ratio, inner)
+    raise ValueError(F.kind)
+
+
+# ---------------------------------------------------------------------------
+# F and F* (Sec. 5.1 eq. (UOT); conjugates from the appendix "Properties of
+# divergence functionals", phi* of each entropy function), dx-weighted.
+# ---------------------------------------------------------------------------
+def F_value(F: Div, s: np.ndarray, p: np.ndarray, dx: np.ndarray) -> float:
+    """F(s) = sum_i dx_i Dbar_phi(s_i | p_i); set constraints give 0 or inf."""
+    s = np.asarray(s, np.float64)
+    p = np.asarray(p, np.float64)
+    if F.kind == "kl":
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = np.where(s > 0, s * np.log(s / p), 0.0)
+        t = np.where((p == 0) & (s > 0), np.inf, t)
+        return float(F.lam * np.sum(dx * (t - s + p)))
+    if F.kind == "tv":
+        return float(F.lam * np.sum(dx * np.abs(s - p)))
+    if F.kind == "eq":
+        ok = np.allclose(s, p, rtol=1e-9, atol=1e-300)
+        return 0.0 if ok else np.inf
+    if F.kind == "rg":
+        ok = np.all(s >= F.alpha * p * (1 - 1e-9)) and np.all(s <= F.beta * p * (1 + 1e-9))
+        return 0.0 if ok else np.inf
+    raise ValueError(F.kind)
+
+
+def F_conj(F: Div, w: np.ndarray, p: np.ndarray, dx: np.ndarray) -> float:
+    """F*(w) = sum_i dx_i p_i lam phi*(w_i/lam) (+ the domain constraint w <= lam phi'_inf).
+
+      KL: phi*(t) = e^t - 1        TV: phi*(t) = max(t, -1), t <= 1
+      =  : phi*(t) = t             RG: phi*(t) = max(alpha t, beta t)
+    """
+    w = np.asarray(w, np.float64)
+    p = np.asarray(p, np.float64)
+    if F.kind == "kl":
+        with np.errstate(invalid="ignore", over="ignore"):
+            t = np.where(p > 0, p * np.expm1(w / F.lam), 0.0)
+        return float(np.sum(dx * F.lam * t))
+    if F.kind == "tv":
+        if np.any(w > F.lam * (1 + 1e-12) + 1e-300):
+            return np.inf
+        return float(np.sum(dx * p * np.maximum(w, -F.lam)))
+    if F.kind == "eq":
+        with np.errstate(invalid="ignore"):
+            return float(np.sum(dx * np.where(p > 0, p * w, 0.0)))
+    if F.kind == "rg":
+        hi = np.where(w > 0, (F.beta * w if np.isfinite(F.beta) else np.where(p > 0, np.inf, 0.0)), F.alpha * w)
+        with np.errstate(invalid="ignore"):
+            t = np.where(p > 0, p * hi, 0.0)
+        return float(np.sum(dx * t))
+    raise ValueError(F.kind)
+
+
+# ---------------------------------------------------------------------------
+# geometries: the Gibbs operators of eq. (gibbs-convolution) in log form
+# ---------------------------------------------------------------------------
+class DenseGeom:
+    """Explicit cost matrix C (I x J).  lse_x(w) = log K(e^w) with
+    (K e^w)_i = sum_j exp(-C_ij/eps + w_j); lse_y is the transposed product."""
+
+    def __init__(self, C: np.ndarray):
+        self.C = np.asarray(C, dtype=np.float64)
+        self.N, self.M = self.C.shape
+
+    def lse_x(self, w, eps):
+        return lse(-self.C / eps + np.asarray(w)[None, :], axis=1)
+
+    def lse_y(self, w, eps):
+        return lse(-self.C / eps + np.asarray(w)[:, None], axis=0)
+
+    def cost_moment_log(self, wx, wy, eps):
+        """log sum_ij C_ij exp(wx_i + wy_j - C_ij/eps)."""
+        with np.errstate(divide="ignore"):
+            L = np.log(self.C) - self.C / eps + np.asarray(wx)[:, None] + np.asarray(wy)[None, :]
+        return float(lse(L.reshape(-1), axis=0))
+
+
+def sq_dist(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """C_ij = |x_i - y_j|^2 computed as a sum of squared coordinate gaps."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    if y.ndim == 1:
+        y = y[:, None]
+    C = np.zeros((x.shape[0], y.shape[0]))
+    for k in range(x.shape[1]):
+        C += (x[:, k][:, None] - y[:, k][None, :]) ** 2
+    return C
+
+
+class PointsGeom(DenseGeom):
+    """Point clouds with the squared Euclidean cost (Sec. 2.3 GHK cost |x-y|^2)."""
+
+    def __init__(self, x, y):
+        super().__init__(sq_dist(x, y))
+
+
+class GridGeom:
+    """X = Y = a regular grid of cell centres with cost |x - y|^2, for which
+    K is a tensor product of 1-D Gaussian kernels, applied by successive 1-D
+    passes (Sec. 4.4, "Computing the matrix multiplications": separable
+    kernel).  Each 1-D pass is evaluated as a log-sum-exp, which is the same
+    sum as the paper's convolution written in the log domain."""
+
+    def __init__(self, shape: Sequence[int], h: Sequence[float]):
+        self.shape = tuple(int(n) for n in shape)
+        self.h = tuple(float(v) for v in h)
+        self.N = self.M = int(np.prod(self.shape))
+        self.C1 = [((np.arange(n)[:, None] - np.arange(n)[None, :]) * hh) ** 2
+                   for n, hh in zip(self.shape, self.h)]
+
+    def _sep(self, w, logkers):
+        t = np.asarray(w, np.float64).reshape(self.shape)
+        for ax, L in enumerate(logkers):
+            # out[..., i_ax, ...] = LSE_j (L[i_ax, j] + t[..., j, ...])
+            t = np.moveaxis(t, ax, -1)                        # (..., n_ax)
+            t = lse(t[..., None, :] + L, axis=-1)             # (..., n_ax[i])
+            t = np.moveaxis(t, -1, ax)
+        return t.reshape(-1)
+
+    def lse_x(self, w, eps):
+        return self._sep(w, [-C / eps for C in self.C1])
+
+    lse_y = lse_x  # X = Y and C symmetric
+
+    def cost_moment_log(self, wx, wy, eps):
+        """log sum_ij C_ij exp(wx_i + wy_j - C_ij/eps) with C = sum_axes C^(a):
+        axis a carries the kernel C^(a) e^{-C^(a)/eps}, the others e^{-C/eps}."""
+        terms = []
+        for a in range(len(self.shape)):
+            kers = []
+            for b, C in enumerate(self.C1):
+                if a == b:
+                    with np.errstate(divide="ignore"):
+                        kers.append(np.log(C) - C / eps)
+                else:
+                    kers.append(-C / eps)
+            terms.append(lse(np.asarray(wx) + self._sep(wy, kers), axis=0))
+        return float(lse(np.array(terms), axis=0))
+
+    def dense(self) -> DenseGeom:
+        axes = [(np.arange(n) + 0.5) * hh for n, hh in zip(self.shape, self.h)]
+        mesh = np.meshgrid(*axes, indexing="ij")
+        pts = np.stack([m.reshape(-1) for m in mesh], axis=1)
+        return PointsGeom(pts, pts)
+
+
+# ---------------------------------------------------------------------------
+# residual: relative L1 violation of the X marginal against its prox target
+# (stopping criterion, which the paper leaves unspecified in Alg. 1 / 2)
+# ---------------------------------------------------------------------------
+def marginal_residual(S, u_old, u_new, logdx, eps) -> float:
+    """r = sum_i dx_i |e^{S_i + u_old_i/eps} - e^{S_i + u_new_i/eps}|
+           / sum_i dx_i e^{S_i + u_new_i/eps}."""
+    la = S + u_old / eps + logdx
+    lb = S + u_new / eps + logdx
+    m = np.max(lb)
+    with np.errstate(over="ignore", invalid="ignore"):
+        ea = np.exp(la - m)
+        eb = np.exp(lb - m)
+        num = np.where(np.isneginf(la) & np.isneginf(lb), 0.0, np.abs(ea - eb))
+    den = np.sum(eb)
+    return float(np.sum(num) / den)
+
+
+# ---------------------------------------------------------------------------
+# the scaling iteration (S) / Algorithm 1, in the log domain (Algorithm 2 with
+# an absorption after every half-step), with the eps-scaling heuristic of
+# Sec. 4.4 ("Gradually decreasing eps")
+# ---------------------------------------------------------------------------
+def eps_schedule(eps: float, eps0: Optional[float], n_stages: int = 10, iters_per_stage: int = 100):
+    """List of (eps_k, n_iter_k) annealing stages before the final eps; empty
+    when eps0 is None.  eps_k = eps0 * f^k, f = (eps/eps0)^(1/n_stages)."""
+    if eps0 is None or n_stages <= 0:
+        return []
+    f = (eps / eps0) ** (1.0 / n_stages)
+    return [(eps0 * f ** k, iters_per_stage) for k in range(n_stages)]
+
+
+def solve(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, eps: float,
+          tol: float = 1e-6, max_iter: int = 10000, v0=None, u0=None,
+          eps0: Optional[float] = None, n_stages: int = 10, iters_per_stage: int = 100,
+          record: bool = False):
+    """Scaling iterations (S): each iteration is an X half-step
+        S = log K(b (.) dy),  u <- eps log proxdiv_F1(e^S)
+    followed by a Y half-step
+        T = log K^T(a (.) dx), v <- eps log proxdiv_F2(e^T),
+    all in the log domain.  Stops after the first iteration whose residual
+    r <= tol at the final eps (annealing iterations count), or at max_iter.
+
+    Returns dict(u, v, iters, res (list), S_last).
+    """
+    N = len(logp)
+    M = len(logq)
+    v = np.zeros(M) if v0 is None else np.array(v0, np.float64)
+    u = np.zeros(N) if u0 is None else np.array(u0, np.float64)
+    stages = eps_schedule(eps, eps0, n_stages, iters_per_stage)
+    res = []
+    hist = []
+    it = 0
+    plan = [(e, n, False) for e, n in stages] + [(eps, None, True)]
+    for e, n_it, final in plan:
+        k = 0
+        while True:
+            if it >= max_iter:
+                return dict(u=u, v=v, iters=it, res=res, converged=False, hist=hist)
+            if n_it is not None and k >= n_it:
+                break
+            S = geom.lse_x(v / e + logdy, e)
+            u_new = e * proxdiv_log(F1, logp, S, 0.0, e)
+            r = marginal_residual(S, u, u_new, logdx, e)
+            u = u_new
+            T = geom.lse_y(u / e + logdx, e)
+            v = e * proxdiv_log(F2, logq, T, 0.0, e)
+            it += 1
+            k += 1
+            res.append(r)
+            if record:
+                hist.append((u.copy(), v.copy()))
+            if final and r <= tol:
+                return dict(u=u, v=v, iters=it, res=res, converged=True, hist=hist)
+    raise AssertionError("unreachable")
+
+
+def half_step_x(geom, logp, logdx, logdy, F1: Div, eps, u_old, v):
+    """One X half-step from a given state: returns (S, u_new, r)."""
+    S = geom.lse_x(v / eps + logdy, eps)
+    u_new = eps * proxdiv_log(F1, logp, S, 0.0, eps)
+    return S, u_new, marginal_residual(S, u_old, u_new, logdx, eps)
+
+
+def half_step_y(geom, logq, logdx, F2: Div, eps, u):
+    T = geom.lse_y(u / eps + logdx, eps)
+    return T, eps * proxdiv_log(F2, logq, T, 0.0, eps)
+
+
+# ---------------------------------------------------------------------------
+# objectives: (P_eps), (D_eps) of Thm. "duality", discrete form with the
+# dx dy-weighted entropy; gap in Fenchel-Young form
+# ---------------------------------------------------------------------------
+def objective(geom, p, q, dx, dy, F1: Div, F2: Div, eps, u, v) -> dict:
+    """Primal, dual, gap, transport cost and marginals at the plan
+    R_ij = exp((u_i + v_j - C_ij)/eps) (w.r.t. dx dy).
+
+      pi1 = R dy = e^{u/eps + S(v)},  pi2 = R^T dx = e^{v/eps + T(u)}
+      P = F1(pi1) + F2(pi2) + <u,pi1>_dx + <v,pi2>_dy - eps m(pi1) + eps m(K)
+      D = -F1*(-u) - F2*(-v) - eps m(pi1) + eps m(K)
+      gap = [F1(pi1) + F1*(-u) + <u,pi1>] + [F2(pi2) + F2*(-v) + <v,pi2>]
+    """
+    p = np.asarray(p, np.float64)
+    q = np.asarray(q, np.float64)
+    dx = np.asarray(dx, np.float64)
+    dy = np.asarray(dy, np.float64)
+    logdx, logdy = np.log(dx), np.log(dy)
+    S = geom.lse_x(v / eps + logdy, eps)
+    T = geom.lse_y(u / eps + logdx, eps)
+    with np.errstate(invalid="ignore"):
+        pi1 = np.exp(u / eps + S)
+        pi2 = np.exp(v / eps + T)
+    pi1 = np.nan_to_num(pi1, nan=0.0)
+    pi2 = np.nan_to_num(pi2, nan=0.0)
+    m1 = float(np.sum(dx * pi1))
+    m2 = float(np.sum(dy * pi2))
+    mK = float(np.exp(lse(logdx + geom.lse_x(logdy, eps), axis=0)))
+    with np.errstate(invalid="ignore"):
+        up = float(np.sum(np.where(pi1 > 0, dx * u * pi1, 0.0)))
+        vp = float(np.sum(np.where(pi2 > 0, dy * v * pi2, 0.0)))
+    f1 = F_value(F1, pi1, p, dx)
+    f2 = F_value(F2, pi2, q, dy)
+    c1 = F_conj(F1, -u, p, dx)
+    c2 = F_conj(F2, -v, q, dy)
+    primal = f1 + f2 + up + vp - eps * m1 + eps * mK
+    dual = -c1 - c2 - eps * m1 + eps * mK
+    gap = (f1 + c1 + up) + (f2 + c2 + vp)
+    with np.errstate(invalid="ignore"):
+        wx = np.where(np.isneginf(u), -np.inf, u / eps + logdx)
+        wy = np.where(np.isneginf(v), -np.inf, v / eps + logdy)
+    cost = float(np.exp(geom.cost_moment_log(wx, wy, eps)))
+    return dict(primal=primal, dual=dual, gap=gap, transport_cost=cost,
+                mass=m1, mass2=m2, pi1=pi1, pi2=pi2, mK=mK)
+
+
+def dual_value(geom, p, q, dx, dy, F1, F2, eps, u, v) -> float:
+    """(D_eps) at (u, v)."""
+    o = objective(geom, p, q, dx, dy, F1, F2, eps, u, v)
+    return o["dual"]
+
+
+# ---------------------------------------------------------------------------
+# literal Algorithm 1 (ScalingAlgo) and Algorithm 2 (ScalingAlgo2), dense
+# kernels; used to cross-check the log-domain iteration above
+# ---------------------------------------------------------------------------
+def scaling_algo(C, p, q, dx, dy, F1, F2, eps, n_iter, b0=None):
+    """Algorithm 1: b = 1; repeat a = proxdiv_F1(K(b dy)), b = proxdiv_F2(K^T(a dx)).
+    Returns the potentials (eps log a, eps log b) after each iteration."""
+    K = np.exp(-np.asarray(C, np.float64) / eps)
+    b = np.ones(len(q)) if b0 is None else np.asarray(b0, np.float64)
+    out = []
+    for _ in range(n_iter):
+        a = proxdiv_scaling(F1, p, K @ (b * dy), 0.0, eps)
+        b = proxdiv_scaling(F2, q, K.T @ (a * dx), 0.0, eps)
+        with np.errstate(divide="ignore"):
+            out.append((eps * np.log(a), eps * np.log(b)))
+    return out
+
+
+def scaling_algo2(C, p, q, dx, dy, F1, F2, eps, n_iter, tau, eps0=None, n_stages=10, iters_per_stage=100):
+    """Algorithm 2 with absorption when max |log a~|, |log b~| > tau, and the
+    eps-scaling heuristic (absorb, then change eps, then rebuild K~).
+    Returns total potentials (u + eps log a~, v + eps log b~) per iteration."""
+    C = np.asarray(C, np.float64)
+    N, M = C.shape
+    stages = eps_schedule(eps, eps0, n_stages, iters_per_stage)
+    eps_of_iter = []
+    for e, n in stages:
+        eps_of_iter += [e] * n
+    e = eps_of_iter[0] if eps_of_iter else eps
+    u = np.zeros(N)
+    v = np.zeros(M)
+    at = np.ones(N)
+    bt = np.ones(M)
+    Kt = np.exp(-C / e)
+    out = []
+    for it in range(n_iter):
+        e_it = eps_of_iter[it] if it < len(eps_of_iter) else eps
+        if e_it != e:
+            # absorption, then the new eps, then the rebuilt stabilized kernel
+            u = u + e * np.log(at)
+            v = v + e * np.log(bt)
+            e = e_it
+            Kt = np.exp((u[:, None] + v[None, :] - C) / e)
+            at = np.ones(N)
+            bt = np.ones(M)
+        at = proxdiv_scaling(F1, p, Kt @ (bt * dy), u, e)
+        bt = proxdiv_scaling(F2, q, Kt.T @ (at * dx), v, e)
+        with np.errstate(divide="ignore"):
+            la, lb = np.log(at), np.log(bt)
+        out.append((u + e * la, v + e * lb))
+        big = max(np.max(np.abs(la[np.isfinite(la)]), initial=0.0), np.max(np.abs(lb[np.isfinite(lb)]), initial=0.0))
+        if big > tau:
+            u = u + e * la
+            v = v + e * lb
+            Kt = np.exp((u[:, None] + v[None, :] - C) / e)
+            at = np.ones(N)
+            bt = np.ones(M)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# barycentres: Sec. 5.2 (weighted KL, K_k = exp(-c_k/(alpha_k eps)) with
+# c_k = alpha_k c so that every K_k = K; Table estimatebary rows (i) and (ii))
+# ---------------------------------------------------------------------------
+def bary_logh(T: np.ndarray, alpha: np.ndarray, eps: float, F2: Div) -> np.ndarray:
+    """log h from Table estimatebary, given T_k = log s_k (shape (n, J)).
+
+      (i)  =     : h = (prod_k s_k^alpha_k)^(1/sum alpha)
+      (ii) lam KL: h = (sum_k alpha_k s_k^(eps/(eps+lam)) / sum alpha)^((eps+lam)/eps)
+    """
+    alpha = np.asarray(alpha, np.float64)
+    A = alpha.sum()
+    if F2.kind == "eq":
+        return np.sum(alpha[:, None] * T, axis=0) / A
+    if F2.kind == "kl":
+        g = eps / (eps + F2.lam)
+        return (lse(np.log(alpha)[:, None] + g * T, axis=0) - np.log(A)) / g
+    raise ValueError("barycentre F2 kind %s is not supported" % F2.kind)
+
+
+def barycenter(geom, logp, alpha, logdx, logdy, F1: Div, F2: Div, eps: float,
+               tol: float = 1e-6, max_iter: int = 10000, v0=None):
+    """Multi-coupling scaling iterations for the barycentre (Sec. 4.4 "Multiple
+    couplings", Sec. 5.2).  For each k: S_k = log K(b_k dy),
+    u_k = eps log proxdiv_F1(p_k)(e^S_k); T_k = log K^T(a_k dx); h from Table
+    estimatebary; v_k = eps log proxdiv_F2(h)(e^T_k).  The residual is the
+    relative L1 X-marginal violation aggregated over all k.
+    Returns dict(u, v, logh, iters, res)."""
+    logp = np.asarray(logp, np.float64)
+    n, N = logp.shape
+    M = len(logdy)
+    v = np.zeros((n, M)) if v0 is None else np.array(v0, np.float64)
+    u = np.zeros((n, N))
+    res = []
+    logh = None
+    for it in range(1, max_iter + 1):
+        num = 0.0
+        den = 0.0
+        S = np.stack([geom.lse_x(v[k] / eps + logdy, eps) for k in range(n)])
+        u_new = eps * proxdiv_log(F1, logp, S, 0.0, eps)
+        la = S + u / eps + logdx
+        lb = S + u_new / eps + logdx
+        m = np.max(lb)
+        with np.errstate(over="ignore", invalid="ignore"):
+            num = np.sum(np.where(np.isneginf(la) & np.isneginf(lb), 0.0, np.abs(np.exp(la - m) - np.exp(lb - m))))
+        den = np.sum(np.exp(lb - m))
+        r = float(num / den)
+        u = u_new
+        T = np.stack([geom.lse_y(u[k] / eps + logdx, eps) for k in range(n)])
+        logh = bary_logh(T, alpha, eps, F2)
+        v = eps * proxdiv_log(F2, np.broadcast_to(logh, T.shape), T, 0.0, eps)
+        res.append(r)
+        if r <= tol:
+            return dict(u=u, v=v, logh=logh, iters=it, res=res, converged=True)
+    return dict(u=u, v=v, logh=logh, iters=max_iter, res=res, converged=False)
+
+
+# ---------------------------------------------------------------------------
+# batches: independent problems, one after the other
+# ---------------------------------------------------------------------------
+def solve_batch(problems, F1, F2, eps, tol, max_iter, **kw):
+    """problems: iterable of (x, y, p, q, dx, dy); dense squared-Euclidean cost."""
+    out = []
+    for (x, y, p, q, dx, dy) in problems:
+        g = PointsGeom(x, y)
+        out.append(solve(g, safe_log(p), safe_log(q), np.log(dx), np.log(dy), F1, F2, eps, tol, max_iter, **kw))
+    return out
