@@ -1,0 +1,224 @@
+/*
+ * uot.h -- C ABI of libuot: entropic unbalanced optimal transport by the
+ * generalized Sinkhorn scaling iteration, hand-written HIP kernels for
+ * MI355X (gfx950).
+ *
+ * Method: Chizat, Peyre, Schmitzer, Vialard, "Scaling algorithms for
+ * unbalanced optimal transport problems".
+ *
+ *   problem      (P_eps)  min_R F1(R dy) + F2(R^T dx) + eps KL(R | K),
+ *                K = exp(-C/eps), dx (x) dy-weighted entropy   (Sec. 3.2, eq. (P_eps))
+ *   iteration    (S)      a <- proxdiv_F1(K(b dy)), b <- proxdiv_F2(K^T(a dx))
+ *                                                        (Sec. 3.3, Algorithm 1)
+ *   proxdiv      Table "proximalexplicit" (Sec. 5.1), stabilized form (Sec. 4.3)
+ *
+ * Everything runs in the log domain: the library stores the dual potentials
+ * u = eps log a and v = eps log b (Prop. "alternating"), i.e. Algorithm 2 with
+ * an absorption after every half-step, so that no kernel entry ever over- or
+ * underflows for small eps.  The plan w.r.t. dx (x) dy is
+ *     R_ij = exp((u_i + v_j - C_ij)/eps)                  (Thm. "duality").
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers (hipMalloc'd or torch CUDA
+ *     tensors), caller-owned; the library neither frees nor retains them.
+ *   - Float arrays have the problem's dtype (UOT_F64 = double, UOT_F32 = float).
+ *   - p, q are DENSITIES w.r.t. the reference weights dx, dy (p = mu/dx,
+ *     Sec. 5.1); p_i = 0 is allowed and gives u_i = -inf under KL/=/RG.
+ *   - Workspace: the caller allocates ws_bytes >= uot_*_workspace_size(...)
+ *     bytes of device memory (256-byte aligned); the library allocates no
+ *     device memory inside any solve.
+ *   - Work is enqueued on the stream given to uot_create (NULL = the legacy
+ *     default stream).  Calls that return scalar results synchronise that
+ *     stream before returning.
+ *   - Return value: UOT_OK (0), UOT_NOT_CONVERGED (1, informational), or a
+ *     negative error; no exception ever crosses the ABI.  uot_last_error()
+ *     gives a message for the last error on the calling thread.
+ */
+#ifndef UOT_H
+#define UOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UOT_ABI_VERSION 1
+
+enum uot_status_code {
+  UOT_OK = 0,
+  UOT_NOT_CONVERGED = 1,   /* max_iter reached before residual <= tol        */
+  UOT_E_INVALID = -1,      /* bad shape, pointer, eps <= 0, lambda <= 0 ...  */
+  UOT_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. dim > 3)       */
+  UOT_E_NONFINITE = -3,    /* a NaN residual was detected on the device      */
+  UOT_E_HIP = -4,          /* a HIP runtime call failed                       */
+  UOT_E_WORKSPACE = -5     /* workspace missing, too small or misaligned     */
+};
+
+/* Marginal penalties F(s) = sum_i dx_i Dbar_phi(s_i | p_i)  (Sec. 2.1 and
+ * eq. "divergencefunctions"); proxdiv rows of Table proximalexplicit:
+ *   UOT_DIV_EQ : equality constraint, proxdiv = p/s
+ *   UOT_DIV_KL : lambda KL,           proxdiv = (p/s)^(lambda/(lambda+eps))
+ *   UOT_DIV_TV : lambda TV,           proxdiv = min(e^(lambda/eps), max(e^(-lambda/eps), p/s))
+ *   UOT_DIV_RG : range [alpha, beta], proxdiv = min(beta p/s, max(alpha p/s, 1))
+ * beta = +inf (and alpha = 0) are allowed for RG. */
+enum uot_div_kind { UOT_DIV_EQ = 0, UOT_DIV_KL = 1, UOT_DIV_TV = 2, UOT_DIV_RG = 3 };
+
+enum uot_dtype { UOT_F64 = 0, UOT_F32 = 1 };
+
+/* Geometry of the cost C_ij = |x_i - y_j|^2 (squared Euclidean, Sec. 2.3).
+ *   UOT_GEOM_POINTS: point clouds; x is dim x N, y is dim x M, coordinate-major
+ *                    (x[k*N + i] = k-th coordinate of x_i); 1 <= dim <= 3.
+ *                    The Gibbs product is a dense log-sum-exp that recomputes
+ *                    C_ij from the coordinates in registers (Sec. 4.4,
+ *                    "Computing the matrix multiplications").
+ *   UOT_GEOM_GRID:   X = Y = a regular grid of cell centres (i + 1/2) h[k]
+ *                    with n[0] x ... x n[dim-1] cells, row-major (last axis
+ *                    fastest); 1 <= dim <= 3.  K is a tensor product of 1-D
+ *                    Gaussian kernels applied axis by axis (Sec. 4.4,
+ *                    separable kernel), each 1-D pass evaluated as a
+ *                    log-sum-exp.  N = M = prod(n). */
+enum uot_geom_kind { UOT_GEOM_POINTS = 0, UOT_GEOM_GRID = 1 };
+
+typedef struct uot_div {
+  int32_t kind;      /* enum uot_div_kind                              */
+  int32_t reserved;
+  double lambda;     /* KL / TV weight, > 0                            */
+  double alpha;      /* RG lower factor, 0 <= alpha <= beta            */
+  double beta;       /* RG upper factor, may be +inf                   */
+} uot_div;
+
+typedef struct uot_geom {
+  int32_t kind;      /* enum uot_geom_kind                             */
+  int32_t dim;       /* coordinate dimension (POINTS) / axes (GRID)    */
+  int64_t N, M;      /* POINTS: number of points of X and Y            */
+  const void *x;     /* POINTS: device, dim x N                        */
+  const void *y;     /* POINTS: device, dim x M                        */
+  int64_t n[3];      /* GRID: cells per axis                           */
+  double h[3];       /* GRID: spacing per axis                         */
+} uot_geom;
+
+typedef struct uot_problem {
+  int32_t dtype;     /* enum uot_dtype of every float array            */
+  int32_t reserved;
+  uot_geom geom;
+  const void *p;     /* device, N: density of mu w.r.t. dx (>= 0)      */
+  const void *q;     /* device, M: density of nu w.r.t. dy (>= 0)      */
+  const void *dx;    /* device, N: reference weights (> 0)             */
+  const void *dy;    /* device, M: reference weights (> 0)             */
+  uot_div F1, F2;
+} uot_problem;
+
+/* Iteration control.  eps-scaling (Sec. 4.4, "Gradually decreasing eps"):
+ * when eps0 > eps and eps_stages > 0 the first eps_stages * iters_per_stage
+ * iterations run at eps_k = eps0 * f^k (k = 0..eps_stages-1, f =
+ * (eps/eps0)^(1/eps_stages)), then the iteration continues at eps until the
+ * residual r <= tol or max_iter iterations in total.  The residual of an
+ * iteration is the relative L1 violation of the X marginal against its prox
+ * target, measured before the u update:
+ *   r = sum_i dx_i |e^{S_i + u_i/eps} - e^{S_i + u'_i/eps}| / sum_i dx_i e^{S_i + u'_i/eps}
+ * with S = log K(b dy) and u' the updated potential; it is only tested at the
+ * final eps. */
+typedef struct uot_params {
+  double eps;            /* final regularisation, > 0                        */
+  double eps0;           /* annealing start; <= eps or <= 0 disables it      */
+  int32_t eps_stages;    /* number of eps divisions (10 in the paper)        */
+  int32_t iters_per_stage; /* iterations per annealing stage (100)           */
+  double tol;            /* residual tolerance (>= 0)                         */
+  int64_t max_iter;      /* iteration cap, >= 1                               */
+  int32_t check_every;   /* iterations between host convergence polls (>= 1) */
+  int32_t use_graph;     /* 1: replay check_every iterations as a hipGraph   */
+  const void *v0;        /* optional device warm start for v (M), or NULL    */
+  double *res_hist;      /* optional device array (max_iter) receiving r     */
+} uot_params;
+
+typedef struct uot_result {
+  int64_t iters;         /* iterations performed                              */
+  double residual;       /* residual of the last iteration                    */
+  int32_t status;        /* UOT_OK / UOT_NOT_CONVERGED / UOT_E_NONFINITE      */
+  int32_t reserved;
+  double elapsed_ms;     /* host wall time of the iteration loop              */
+} uot_result;
+
+/* Values at the plan R = exp((u + v - C)/eps) (Thm. "duality"):
+ *   primal = F1(pi1) + F2(pi2) + <u,pi1>_dx + <v,pi2>_dy - eps m(pi1) + eps m(K)
+ *   dual   = -F1*(-u) - F2*(-v) - eps m(pi1) + eps m(K)
+ *   gap    = Fenchel-Young form of primal - dual (NaN unless both F are KL/TV)
+ *   transport_cost = <C, R>_{dx dy};  mass1 = sum dx pi1, mass2 = sum dy pi2
+ * pi1 = R dy, pi2 = R^T dx.  Reductions are accumulated in FP64. */
+typedef struct uot_objective_values {
+  double primal, dual, gap, transport_cost, mass1, mass2, massK;
+} uot_objective_values;
+
+typedef struct uot_ctx uot_ctx;
+
+/* Context bound to one HIP stream (hipStream_t passed as void*, NULL allowed).
+ * Holds a small device control block and pinned host mirror, allocated here
+ * once.  One context must not be used by two threads at the same time. */
+int uot_create(uot_ctx **out, void *stream);
+int uot_destroy(uot_ctx *ctx);
+const char *uot_status_string(int status);
+const char *uot_last_error(void);
+int uot_abi_version(void);
+
+/* Workspace bytes needed by uot_solve / uot_half_step / uot_objective for
+ * this problem (depends only on sizes, dtype and geometry kind). */
+int uot_workspace_size(const uot_problem *pb, size_t *bytes);
+
+/* Scaling iterations (S) from v = v0 (or 0), u = 0, until convergence.
+ * u (N) and v (M): device output buffers of the problem dtype, written with
+ * the final potentials (u may hold -inf where p = 0).  res: host struct. */
+int uot_solve(uot_ctx *ctx, const uot_problem *pb, const uot_params *pr,
+              void *u, void *v, void *ws, size_t ws_bytes, uot_result *res);
+
+/* One half-step of (S) from a given state, for checking a single step.
+ * side 0 (X half-step): S = log K(e^{v/eps} dy) with v = pot_in (M);
+ *   pot_io (N) holds u_old on entry and u' = eps log proxdiv_F1(e^S) on exit;
+ *   *residual receives r (definition above).
+ * side 1 (Y half-step): T = log K^T(e^{u/eps} dx) with u = pot_in (N);
+ *   pot_io (M) receives v' = eps log proxdiv_F2(e^T); *residual is set to 0.
+ * lse_out (optional, N or M) receives S or T (natural log). */
+int uot_half_step(uot_ctx *ctx, const uot_problem *pb, double eps, int side,
+                  const void *pot_in, void *pot_io, void *lse_out,
+                  double *residual, void *ws, size_t ws_bytes);
+
+/* Objective values, marginals (pi1: N, pi2: M, optional) at (u, v). */
+int uot_objective(uot_ctx *ctx, const uot_problem *pb, double eps,
+                  const void *u, const void *v, void *pi1, void *pi2,
+                  uot_objective_values *out, void *ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------------------
+ * Barycentres (Sec. 5.2): n densities p_k on one regular grid (X = Y), with
+ * alpha_k-weighted entropy and K_k = exp(-alpha_k c/(alpha_k eps)) = K, F1 =
+ * sum_k F1(. | p_k) (any uot_div kind, applied per coupling) and F2(s) =
+ * min_h lambda sum_k alpha_k D(s_k | h) with D = KL (Table estimatebary (ii))
+ * or equality (row (i)).  Per iteration: for every k an X half-step
+ * u_k = eps log proxdiv_F1(e^{S_k}); then T_k = log K^T(a_k dx),
+ *   log h = ((eps+lam)/eps) [LSE_k(log alpha_k + eps/(eps+lam) T_k) - log sum alpha]
+ * and v_k = eps log proxdiv_{lam KL(.|h)}(e^{T_k}).  The residual is the
+ * relative L1 X-marginal violation summed over all k.
+ * ------------------------------------------------------------------------- */
+typedef struct uot_bary_problem {
+  int32_t dtype;         /* UOT_F32 or UOT_F64                               */
+  int32_t n;             /* number of marginals, >= 1                        */
+  uot_geom geom;         /* must be UOT_GEOM_GRID                            */
+  const void *p;         /* device, n x size, densities                      */
+  const double *alpha;   /* HOST, n weights > 0                              */
+  const void *dx;        /* device, size                                     */
+  const void *dy;        /* device, size                                     */
+  uot_div F1;            /* per-coupling first-marginal penalty              */
+  uot_div F2;            /* kind UOT_DIV_KL (lambda) or UOT_DIV_EQ           */
+} uot_bary_problem;
+
+int uot_bary_workspace_size(const uot_bary_problem *pb, size_t *bytes);
+/* u, v: device n x size outputs; logh: device size output (log h, w.r.t. dy).
+ * pr->v0, if set, is an n x size warm start for v. */
+int uot_barycenter(uot_ctx *ctx, const uot_bary_problem *pb, const uot_params *pr,
+                   void *u, void *v, void *logh, void *ws, size_t ws_bytes,
+                   uot_result *res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UOT_H */

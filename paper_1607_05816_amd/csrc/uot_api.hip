@@ -1,0 +1,735 @@
+// C ABI of libuot (declared in include/uot.h): validation, workspace layout,
+// the iteration driver (direct launches or replayed hipGraph chunks) and the
+// objective / barycentre / single half-step entry points.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/uot.h"
+#include "uot_device.h"
+#include "uot_launch.h"
+
+using namespace uot;
+
+struct uot_ctx {
+  hipStream_t user = nullptr;   // caller's stream
+  hipStream_t work = nullptr;   // library stream (capture-capable)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  Ctrl* pinned = nullptr;       // host mirror of the control block
+  int device = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(UOT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+DivDev to_dev(const uot_div& d) {
+  DivDev r{};
+  r.kind = d.kind;
+  r.lam = d.lambda;
+  r.has_lo = (d.kind == UOT_DIV_RG && d.alpha > 0) ? 1 : 0;
+  r.has_hi = (d.kind == UOT_DIV_RG && std::isfinite(d.beta)) ? 1 : 0;
+  r.log_alpha = r.has_lo ? std::log(d.alpha) : 0.0;
+  r.log_beta = r.has_hi ? std::log(d.beta) : 0.0;
+  return r;
+}
+
+int check_div(const uot_div& d, const char* name) {
+  if (d.kind < 0 || d.kind > 3) return fail(UOT_E_INVALID, std::string(name) + ": unknown divergence kind");
+  if ((d.kind == UOT_DIV_KL || d.kind == UOT_DIV_TV) && !(d.lambda > 0 && std::isfinite(d.lambda)))
+    return fail(UOT_E_INVALID, std::string(name) + ": lambda must be finite and > 0");
+  if (d.kind == UOT_DIV_RG && !(d.alpha >= 0 && d.beta >= d.alpha && d.beta > 0))
+    return fail(UOT_E_INVALID, std::string(name) + ": RG needs 0 <= alpha <= beta, beta > 0");
+  return UOT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// problem plan + workspace layout
+// ---------------------------------------------------------------------------
+struct Plan {
+  int dtype = 0;
+  size_t esz = 0;
+  int geom = 0;
+  int dim = 0;
+  int64_t N = 0, M = 0;
+  int64_t n[3] = {1, 1, 1};
+  double h[3] = {0, 0, 0};
+  int nb = 1;            // fields (barycentre marginals)
+  int nst = 1;           // eps stages incl. the final one (tables per axis)
+  // dense split configuration per side (0: rows X, 1: rows Y)
+  int R[2] = {1, 1};
+  int splits[2] = {1, 1};
+  int64_t cps[2] = {0, 0};
+  int nparts_x = 0;      // residual partials written by the X epilogue
+  // workspace offsets
+  size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
+      o_gcost, o_obj, o_scal, total;
+  int64_t obj_doubles = 0;
+};
+
+int grid_final_parts(const Plan& P) {
+  const int64_t nb = P.nb;
+  if (P.dim == 1) return grid_contig_parts<float>((int)P.n[0], nb);
+  if (P.dim == 2) return grid_strided_parts<float>((int)P.n[0], nb, P.n[1]);
+  return grid_strided_parts<float>((int)P.n[0], nb, P.n[1] * P.n[2]);
+}
+
+void dense_config(Plan& P, int side) {
+  const int64_t Nr = side == 0 ? P.N : P.M;
+  const int64_t Mc = side == 0 ? P.M : P.N;
+  const int R = (P.dtype == UOT_F32) ? 2 : 1;
+  const int64_t rt = (Nr + 256 * R - 1) / (256 * R);
+  int64_t sp = (2048 + rt - 1) / rt;
+  const int64_t maxsp = (Mc + 31) / 32;
+  if (sp > maxsp) sp = maxsp;
+  if (sp < 1) sp = 1;
+  int64_t cps = (Mc + sp - 1) / sp;
+  cps = (cps + 31) / 32 * 32;
+  sp = (Mc + cps - 1) / cps;
+  P.R[side] = R;
+  P.splits[side] = (int)sp;
+  P.cps[side] = cps;
+}
+
+int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst) {
+  if (dtype != UOT_F32 && dtype != UOT_F64) return fail(UOT_E_INVALID, "dtype must be UOT_F32 or UOT_F64");
+  P.dtype = dtype;
+  P.esz = dtype == UOT_F32 ? 4 : 8;
+  P.geom = g.kind;
+  P.dim = g.dim;
+  P.nb = nb;
+  P.nst = nst;
+  if (g.dim < 1 || g.dim > 3) return fail(UOT_E_UNSUPPORTED, "dim must be 1, 2 or 3");
+  if (g.kind == UOT_GEOM_POINTS) {
+    if (g.N < 1 || g.M < 1) return fail(UOT_E_INVALID, "N and M must be >= 1");
+    if (!g.x || !g.y) return fail(UOT_E_INVALID, "point coordinates x and y are required");
+    if (nb != 1) return fail(UOT_E_UNSUPPORTED, "several fields need a grid geometry");
+    P.N = g.N;
+    P.M = g.M;
+  } else if (g.kind == UOT_GEOM_GRID) {
+    int64_t sz = 1;
+    for (int k = 0; k < g.dim; ++k) {
+      if (g.n[k] < 1 || g.n[k] > 4096) return fail(UOT_E_UNSUPPORTED, "grid axes must have 1..4096 cells");
+      if (!(g.h[k] > 0)) return fail(UOT_E_INVALID, "grid spacing must be > 0");
+      P.n[k] = g.n[k];
+      P.h[k] = g.h[k];
+      sz *= g.n[k];
+    }
+    if (g.dim == 3 && (int64_t)nb * g.n[0] > 65535) return fail(UOT_E_UNSUPPORTED, "fields x n[0] must be <= 65535");
+    P.N = P.M = sz;
+  } else {
+    return fail(UOT_E_INVALID, "unknown geometry kind");
+  }
+  const size_t e = P.esz;
+  const int64_t F = (int64_t)nb * std::max(P.N, P.M);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  P.o_ctrl = take(sizeof(Ctrl));
+  P.o_logp = take(e * nb * P.N);
+  P.o_logq = take(e * P.M);
+  P.o_logdx = take(e * P.N);
+  P.o_logdy = take(e * P.M);
+  P.o_wu = take(e * nb * P.N);
+  P.o_wv = take(e * nb * P.M);
+  P.o_t1 = take(e * F);
+  P.o_t2 = take(e * F);
+  P.o_t3 = take(e * F);
+  if (P.geom == UOT_GEOM_POINTS) {
+    dense_config(P, 0);
+    dense_config(P, 1);
+    const int64_t np = std::max((int64_t)P.splits[0] * P.N, (int64_t)P.splits[1] * P.M);
+    P.o_pm = take(e * np);
+    P.o_ps = take(e * np);
+    P.nparts_x = (int)((P.N + 255) / 256);
+  } else {
+    P.o_pm = P.o_ps = take(0);
+    P.nparts_x = grid_final_parts(P);
+  }
+  P.o_parts = take(sizeof(ResPart) * std::max(P.nparts_x, 1));
+  for (int k = 0; k < 3; ++k) P.o_gtab[k] = take(P.geom == UOT_GEOM_GRID && k < P.dim ? e * (2 * P.n[k] - 1) * nst : 0);
+  int64_t gmax = 1;
+  for (int k = 0; k < P.dim; ++k) gmax = std::max(gmax, 2 * P.n[k] - 1);
+  P.o_gcost = take(P.geom == UOT_GEOM_GRID ? e * gmax : 0);
+  P.obj_doubles = 4 * ((std::max(P.N, P.M) + 255) / 256) * 2 + 8 * ((std::max(P.N, P.M) + 255) / 256);
+  P.o_obj = take(sizeof(double) * P.obj_doubles);
+  P.o_scal = take(sizeof(double) * 8);
+  P.total = o;
+  return UOT_OK;
+}
+
+template <typename T> T* at(char* ws, size_t off) { return reinterpret_cast<T*>(ws + off); }
+
+int check_ws(const Plan& P, void* ws, size_t bytes) {
+  if (!ws) return fail(UOT_E_WORKSPACE, "workspace pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(UOT_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < P.total) return fail(UOT_E_WORKSPACE, "workspace too small: need " + std::to_string(P.total));
+  return UOT_OK;
+}
+
+Ctrl make_ctrl(double eps, double eps0, int stages, int ips, double tol, int64_t max_iter) {
+  Ctrl c{};
+  const bool anneal = eps0 > eps && stages > 0 && ips > 0;
+  c.n_stages = anneal ? stages : 0;
+  c.iters_per_stage = anneal ? ips : 0;
+  if (anneal) {
+    const double f = std::pow(eps / eps0, 1.0 / stages);
+    for (int k = 0; k < stages; ++k) c.eps_tab[k] = eps0 * std::pow(f, k);
+  }
+  c.eps_tab[c.n_stages] = eps;
+  c.stage_x = c.stage_y = 0;
+  c.eps_x = c.eps_y = c.eps_tab[0];
+  c.tol = tol;
+  c.max_iter = max_iter;
+  c.iter = 0;
+  c.stop = 0;
+  c.yskip = 0;
+  c.status = 1;
+  c.res = INFINITY;
+  return c;
+}
+
+// stream handshake: work waits for the caller's stream, and vice versa at the end
+int begin(uot_ctx* ctx) {
+  HIP_TRY(hipEventRecord(ctx->ev_in, ctx->user));
+  HIP_TRY(hipStreamWaitEvent(ctx->work, ctx->ev_in, 0));
+  return UOT_OK;
+}
+
+int finish(uot_ctx* ctx) {
+  HIP_TRY(hipEventRecord(ctx->ev_out, ctx->work));
+  HIP_TRY(hipStreamWaitEvent(ctx->user, ctx->ev_out, 0));
+  return UOT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Gibbs-product chains
+// ---------------------------------------------------------------------------
+template <typename T> struct Bufs {
+  Ctrl* ctrl;
+  T *logp, *logq, *logdx, *logdy, *wu, *wv, *t1, *t2, *t3, *pm, *ps;
+  ResPart* parts;
+  T* gtab[3];
+  T* gcost;
+  double* obj;
+  double* scal;
+};
+
+template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
+  Bufs<T> b;
+  b.ctrl = at<Ctrl>(ws, P.o_ctrl);
+  b.logp = at<T>(ws, P.o_logp);
+  b.logq = at<T>(ws, P.o_logq);
+  b.logdx = at<T>(ws, P.o_logdx);
+  b.logdy = at<T>(ws, P.o_logdy);
+  b.wu = at<T>(ws, P.o_wu);
+  b.wv = at<T>(ws, P.o_wv);
+  b.t1 = at<T>(ws, P.o_t1);
+  b.t2 = at<T>(ws, P.o_t2);
+  b.t3 = at<T>(ws, P.o_t3);
+  b.pm = at<T>(ws, P.o_pm);
+  b.ps = at<T>(ws, P.o_ps);
+  b.parts = at<ResPart>(ws, P.o_parts);
+  for (int k = 0; k < 3; ++k) b.gtab[k] = at<T>(ws, P.o_gtab[k]);
+  b.gcost = at<T>(ws, P.o_gcost);
+  b.obj = at<double>(ws, P.o_obj);
+  b.scal = at<double>(ws, P.o_scal);
+  return b;
+}
+
+// separable grid product on nb fields: input w (log2 units), per-axis tables
+template <typename T>
+void grid_chain(const Plan& P, const T* w, T* const* tabs, int side, Ctrl* c, const EpiArgs<T>& ep, T* tmp1,
+                T* tmp2, hipStream_t s) {
+  const int64_t nb = P.nb;
+  EpiArgs<T> raw{};
+  raw.mode = EPI_RAW;
+  if (P.dim == 1) {
+    launch_grid_contig<T>(w, nb, (int)P.n[0], tabs[0], side, c, ep, s);
+  } else if (P.dim == 2) {
+    raw.out = tmp1;
+    launch_grid_contig<T>(w, nb * P.n[0], (int)P.n[1], tabs[1], side, c, raw, s);
+    launch_grid_strided<T>(tmp1, nb, (int)P.n[0], P.n[1], tabs[0], side, c, ep, s);
+  } else {
+    raw.out = tmp1;
+    launch_grid_contig<T>(w, nb * P.n[0] * P.n[1], (int)P.n[2], tabs[2], side, c, raw, s);
+    raw.out = tmp2;
+    launch_grid_strided<T>(tmp1, nb * P.n[0], (int)P.n[1], P.n[2], tabs[1], side, c, raw, s);
+    launch_grid_strided<T>(tmp2, nb, (int)P.n[0], P.n[1] * P.n[2], tabs[0], side, c, ep, s);
+  }
+}
+
+// dense point-cloud product for one side; returns the residual partial count
+template <typename T>
+void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Bufs<T>& B, Ctrl* c,
+                const EpiArgs<T>& ep, hipStream_t s) {
+  const T* rows = static_cast<const T*>(side == 0 ? g.x : g.y);
+  const T* cols = static_cast<const T*>(side == 0 ? g.y : g.x);
+  const int64_t Nr = side == 0 ? P.N : P.M;
+  const int64_t Mc = side == 0 ? P.M : P.N;
+  launch_dense_lse<T>(P.dim, P.R[side], rows, Nr, cols, w_cols, Mc, P.splits[side], P.cps[side], B.pm, B.ps, side, c,
+                      s);
+  launch_dense_epi<T>(B.pm, B.ps, P.splits[side], Nr, side, c, ep, s);
+}
+
+template <typename T>
+EpiArgs<T> prox_epi(T* pot, T* wnext, const T* logp, const T* logd, T* lse_out, ResPart* part, int64_t size,
+                    const uot_div& F) {
+  EpiArgs<T> ep{};
+  ep.mode = EPI_PROX;
+  ep.pot = pot;
+  ep.wnext = wnext;
+  ep.logp = logp;
+  ep.logd = logd;
+  ep.lse_out = lse_out;
+  ep.part = part;
+  ep.size = size;
+  ep.F = to_dev(F);
+  return ep;
+}
+
+// one half-step (X: side 0 reads wv, writes u / wu; Y: side 1 reads wu, writes v / wv)
+template <typename T>
+void half_step(const Plan& P, const uot_problem& pb, int side, Bufs<T>& B, T* pot, T* lse_out, bool with_res,
+               hipStream_t s) {
+  if (side == 0) {
+    EpiArgs<T> ep = prox_epi<T>(pot, B.wu, B.logp, B.logdx, lse_out, with_res ? B.parts : nullptr, P.N, pb.F1);
+    if (P.geom == UOT_GEOM_GRID) grid_chain<T>(P, B.wv, B.gtab, 0, B.ctrl, ep, B.t1, B.t2, s);
+    else dense_half<T>(P, pb.geom, 0, B.wv, B, B.ctrl, ep, s);
+  } else {
+    EpiArgs<T> ep = prox_epi<T>(pot, B.wv, B.logq, B.logdy, lse_out, nullptr, P.M, pb.F2);
+    if (P.geom == UOT_GEOM_GRID) grid_chain<T>(P, B.wu, B.gtab, 1, B.ctrl, ep, B.t1, B.t2, s);
+    else dense_half<T>(P, pb.geom, 1, B.wu, B, B.ctrl, ep, s);
+  }
+}
+
+int validate_problem(const uot_problem* pb) {
+  if (!pb) return fail(UOT_E_INVALID, "problem is NULL");
+  if (!pb->p || !pb->q || !pb->dx || !pb->dy) return fail(UOT_E_INVALID, "p, q, dx, dy are required");
+  int r = check_div(pb->F1, "F1");
+  if (r) return r;
+  return check_div(pb->F2, "F2");
+}
+
+int validate_params(const uot_params* pr) {
+  if (!pr) return fail(UOT_E_INVALID, "params is NULL");
+  if (!(pr->eps > 0 && std::isfinite(pr->eps))) return fail(UOT_E_INVALID, "eps must be finite and > 0");
+  if (pr->max_iter < 1) return fail(UOT_E_INVALID, "max_iter must be >= 1");
+  if (!(pr->tol >= 0)) return fail(UOT_E_INVALID, "tol must be >= 0");
+  if (pr->eps_stages < 0 || pr->eps_stages > kMaxStages) return fail(UOT_E_INVALID, "eps_stages must be in [0, 32]");
+  if (pr->check_every < 0) return fail(UOT_E_INVALID, "check_every must be >= 0");
+  return UOT_OK;
+}
+
+// drive iterations until the device sets stop; `iteration` enqueues one
+template <typename F>
+int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot_result* res) {
+  hipStream_t s = ctx->work;
+  const int chunk = pr->check_every > 0 ? pr->check_every : 50;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  if (pr->use_graph) {
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < chunk; ++k) iteration();
+    HIP_TRY(hipStreamEndCapture(s, &graph));
+    HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  int64_t launched = 0;
+  int rc = UOT_OK;
+  while (true) {
+    if (exec) {
+      if (hipGraphLaunch(exec, s) != hipSuccess) { rc = fail(UOT_E_HIP, "hipGraphLaunch failed"); break; }
+    } else {
+      for (int k = 0; k < chunk; ++k) iteration();
+    }
+    launched += chunk;
+    if (hipMemcpyAsync(ctx->pinned, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = fail(UOT_E_HIP, std::string("iteration chunk failed: ") + hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    if (ctx->pinned->stop) break;
+    if (launched > pr->max_iter + chunk) { rc = fail(UOT_E_HIP, "control block did not stop"); break; }
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (rc) return rc;
+  res->iters = ctx->pinned->iter;
+  res->residual = ctx->pinned->res;
+  res->status = ctx->pinned->status;
+  res->elapsed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  return UOT_OK;
+}
+
+template <typename T>
+int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* v, char* ws, size_t wsb,
+            uot_result* res) {
+  Plan P;
+  const bool anneal = pr->eps0 > pr->eps && pr->eps_stages > 0 && pr->iters_per_stage > 0;
+  int rc = make_plan(P, pb->dtype, pb->geom, 1, anneal ? pr->eps_stages + 1 : 1);
+  if (rc) return rc;
+  if ((rc = check_ws(P, ws, wsb))) return rc;
+  if (!u || !v) return fail(UOT_E_INVALID, "u and v output buffers are required");
+  hipStream_t s = ctx->work;
+  if ((rc = begin(ctx))) return rc;
+  Bufs<T> B = carve<T>(P, ws);
+  Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, pr->tol, pr->max_iter);
+  launch_ctrl_init(B.ctrl, init, s);
+  launch_log<T>(static_cast<const T*>(pb->p), B.logp, P.N, 1, s);
+  launch_log<T>(static_cast<const T*>(pb->q), B.logq, P.M, 1, s);
+  launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, P.N, 0, s);
+  launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
+  if (P.geom == UOT_GEOM_GRID)
+    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, P.nst, s);
+  launch_init_pot<T>(nullptr, B.logdx, u, nullptr, P.N, P.N, B.ctrl, 0, s);
+  launch_init_pot<T>(static_cast<const T*>(pr->v0), B.logdy, v, B.wv, P.M, P.M, B.ctrl, 0, s);
+  HIP_TRY(hipGetLastError());
+  auto iteration = [&]() {
+    half_step<T>(P, *pb, 0, B, u, nullptr, true, s);
+    launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s);
+    half_step<T>(P, *pb, 1, B, v, nullptr, false, s);
+  };
+  rc = run_loop(ctx, B.ctrl, pr, iteration, res);
+  if (rc) return rc;
+  if ((rc = finish(ctx))) return rc;
+  if (res->status == -3) return fail(UOT_E_NONFINITE, "non-finite residual");
+  return res->status == 0 ? UOT_OK : UOT_NOT_CONVERGED;
+}
+
+template <typename T>
+int half_step_t(uot_ctx* ctx, const uot_problem* pb, double eps, int side, const T* pot_in, T* pot_io, T* lse_out,
+                double* residual, char* ws, size_t wsb) {
+  Plan P;
+  int rc = make_plan(P, pb->dtype, pb->geom, 1, 1);
+  if (rc) return rc;
+  if ((rc = check_ws(P, ws, wsb))) return rc;
+  if (!pot_in || !pot_io) return fail(UOT_E_INVALID, "pot_in and pot_io are required");
+  if (!(eps > 0)) return fail(UOT_E_INVALID, "eps must be > 0");
+  hipStream_t s = ctx->work;
+  if ((rc = begin(ctx))) return rc;
+  Bufs<T> B = carve<T>(P, ws);
+  Ctrl init = make_ctrl(eps, 0, 0, 0, 0, 1);
+  launch_ctrl_init(B.ctrl, init, s);
+  launch_log<T>(static_cast<const T*>(pb->p), B.logp, P.N, 1, s);
+  launch_log<T>(static_cast<const T*>(pb->q), B.logq, P.M, 1, s);
+  launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, P.N, 0, s);
+  launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
+  if (P.geom == UOT_GEOM_GRID)
+    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, 1, s);
+  if (side == 0) {
+    launch_init_pot<T>(pot_in, B.logdy, nullptr, B.wv, P.M, P.M, B.ctrl, 0, s);
+    half_step<T>(P, *pb, 0, B, pot_io, lse_out, true, s);
+    launch_res_reduce(B.parts, P.nparts_x, B.scal, s);
+  } else {
+    launch_init_pot<T>(pot_in, B.logdx, nullptr, B.wu, P.N, P.N, B.ctrl, 0, s);
+    half_step<T>(P, *pb, 1, B, pot_io, lse_out, false, s);
+  }
+  HIP_TRY(hipGetLastError());
+  double r = 0.0;
+  if (side == 0) {
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, B.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (side == 0) std::memcpy(&r, ctx->pinned, sizeof(double));
+  if (residual) *residual = r;
+  return finish(ctx);
+}
+
+template <typename T>
+int objective_t(uot_ctx* ctx, const uot_problem* pb, double eps, const T* u, const T* v, T* pi1, T* pi2,
+                uot_objective_values* out, char* ws, size_t wsb) {
+  Plan P;
+  int rc = make_plan(P, pb->dtype, pb->geom, 1, 1);
+  if (rc) return rc;
+  if ((rc = check_ws(P, ws, wsb))) return rc;
+  if (!u || !v || !out) return fail(UOT_E_INVALID, "u, v and out are required");
+  if (!(eps > 0)) return fail(UOT_E_INVALID, "eps must be > 0");
+  hipStream_t s = ctx->work;
+  if ((rc = begin(ctx))) return rc;
+  Bufs<T> B = carve<T>(P, ws);
+  Ctrl init = make_ctrl(eps, 0, 0, 0, 0, 1);
+  launch_ctrl_init(B.ctrl, init, s);
+  launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, P.N, 0, s);
+  launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
+  if (P.geom == UOT_GEOM_GRID)
+    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, 1, s);
+  // w fields of u and v, and of the zero potential (for m(K))
+  launch_init_pot<T>(v, B.logdy, nullptr, B.wv, P.M, P.M, B.ctrl, 0, s);
+  launch_init_pot<T>(u, B.logdx, nullptr, B.wu, P.N, P.N, B.ctrl, 0, s);
+  EpiArgs<T> raw{};
+  raw.mode = EPI_RAW;
+  auto product = [&](int side, const T* w, T* outp, T* const* tabs) {
+    raw.out = outp;
+    if (P.geom == UOT_GEOM_GRID) {
+      grid_chain<T>(P, w, tabs, side, B.ctrl, raw, B.t2, B.t3, s);
+    } else {
+      dense_half<T>(P, pb->geom, side, w, B, B.ctrl, raw, s);
+    }
+  };
+  // S(v) -> t1, T(u) -> pm region is busy in dense mode, so T goes to t2 after S is consumed
+  double* part = B.obj;
+  const int64_t nbx = (P.N + 255) / 256, nby = (P.M + 255) / 256;
+  product(0, B.wv, B.t1, B.gtab);
+  launch_obj_side<T>(u, B.t1, static_cast<const T*>(pb->p), static_cast<const T*>(pb->dx), P.N, eps,
+                     to_dev(pb->F1), pi1, part, s);
+  product(1, B.wu, B.t1, B.gtab);
+  launch_obj_side<T>(v, B.t1, static_cast<const T*>(pb->q), static_cast<const T*>(pb->dy), P.M, eps,
+                     to_dev(pb->F2), pi2, part + 4 * nbx, s);
+  double* part2 = part + 4 * (nbx + nby);
+  // m(K) = sum_i dx_i e^{S0_i}, S0 = log K(dy):  w = log2 dy  (zero potential)
+  launch_init_pot<T>(nullptr, B.logdy, nullptr, B.t3, P.M, P.M, B.ctrl, 0, s);
+  launch_init_pot<T>(nullptr, B.logdx, nullptr, B.t2, P.N, P.N, B.ctrl, 0, s);
+  if (P.geom == UOT_GEOM_GRID) {
+    // product() uses t2/t3 as temporaries on grids: keep the two w fields in logp/logq
+    launch_init_pot<T>(nullptr, B.logdy, nullptr, B.logq, P.M, P.M, B.ctrl, 0, s);
+    launch_init_pot<T>(nullptr, B.logdx, nullptr, B.logp, P.N, P.N, B.ctrl, 0, s);
+    product(0, B.logq, B.t1, B.gtab);
+    launch_sum_exp2<T>(B.logp, B.t1, P.N, part2, s);
+  } else {
+    product(0, B.t3, B.t1, B.gtab);
+    launch_sum_exp2<T>(B.t2, B.t1, P.N, part2, s);
+  }
+  double* part3 = part2 + nbx;
+  // <C, R>: one product per axis with that axis' kernel times C (grid), or a direct pass (points)
+  int ncost = 0;
+  if (P.geom == UOT_GEOM_GRID) {
+    for (int a = 0; a < P.dim; ++a) {
+      launch_gtab_cost<T>(B.gcost, (int)P.n[a], P.h[a], eps, s);
+      T* tabs[3] = {B.gtab[0], B.gtab[1], B.gtab[2]};
+      tabs[a] = B.gcost;
+      product(0, B.wv, B.t1, tabs);
+      launch_sum_exp2<T>(B.wu, B.t1, P.N, part3 + ncost * nbx, s);
+      ++ncost;
+    }
+  } else {
+    launch_dense_cost<T>(P.dim, static_cast<const T*>(pb->geom.x), P.N, static_cast<const T*>(pb->geom.y), B.wv, P.M,
+                         eps, B.t1, s);
+    launch_sum_exp2<T>(B.wu, B.t1, P.N, part3, s);
+    ncost = 1;
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t tot = 4 * (nbx + nby) + nbx * (1 + ncost);
+  std::vector<double> h(tot);
+  HIP_TRY(hipMemcpy(h.data(), part, sizeof(double) * tot, hipMemcpyDeviceToHost));
+  double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0}, mK = 0, cost = 0;
+  for (int64_t b = 0; b < nbx; ++b)
+    for (int q = 0; q < 4; ++q) sx[q] += h[b * 4 + q];
+  for (int64_t b = 0; b < nby; ++b)
+    for (int q = 0; q < 4; ++q) sy[q] += h[4 * nbx + b * 4 + q];
+  for (int64_t b = 0; b < nbx; ++b) mK += h[4 * (nbx + nby) + b];
+  for (int k = 0; k < ncost; ++k)
+    for (int64_t b = 0; b < nbx; ++b) cost += h[4 * (nbx + nby) + nbx * (1 + k) + b];
+  out->mass1 = sx[0];
+  out->mass2 = sy[0];
+  out->massK = mK;
+  out->transport_cost = cost;
+  out->primal = sx[2] + sy[2] + sx[1] + sy[1] - eps * sx[0] + eps * mK;
+  out->dual = -sx[3] - sy[3] - eps * sx[0] + eps * mK;
+  const bool finite_gap = (pb->F1.kind == UOT_DIV_KL || pb->F1.kind == UOT_DIV_TV) &&
+                          (pb->F2.kind == UOT_DIV_KL || pb->F2.kind == UOT_DIV_TV);
+  out->gap = finite_gap ? (sx[2] + sx[3] + sx[1]) + (sy[2] + sy[3] + sy[1]) : NAN;
+  if (!finite_gap) out->primal = NAN;
+  return finish(ctx);
+}
+
+template <typename T>
+int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u, T* v, T* logh, char* ws, size_t wsb,
+           uot_result* res) {
+  Plan P;
+  const bool anneal = pr->eps0 > pr->eps && pr->eps_stages > 0 && pr->iters_per_stage > 0;
+  int rc = make_plan(P, pb->dtype, pb->geom, pb->n, anneal ? pr->eps_stages + 1 : 1);
+  if (rc) return rc;
+  if ((rc = check_ws(P, ws, wsb))) return rc;
+  if (!u || !v) return fail(UOT_E_INVALID, "u and v output buffers are required");
+  hipStream_t s = ctx->work;
+  if ((rc = begin(ctx))) return rc;
+  Bufs<T> B = carve<T>(P, ws);
+  const int64_t size = P.N, nb = pb->n;
+  Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, pr->tol, pr->max_iter);
+  launch_ctrl_init(B.ctrl, init, s);
+  launch_log<T>(static_cast<const T*>(pb->p), B.logp, nb * size, 1, s);
+  launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, size, 0, s);
+  launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, size, 0, s);
+  for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, P.nst, s);
+  launch_init_pot<T>(nullptr, B.logdx, u, nullptr, nb * size, size, B.ctrl, 0, s);
+  launch_init_pot<T>(static_cast<const T*>(pr->v0), B.logdy, v, B.wv, nb * size, size, B.ctrl, 0, s);
+  HIP_TRY(hipGetLastError());
+  BaryW la{};
+  double asum = 0;
+  for (int k = 0; k < pb->n; ++k) {
+    la.v[k] = std::log(pb->alpha[k]);
+    asum += pb->alpha[k];
+  }
+  const DivDev F2 = to_dev(pb->F2);
+  auto iteration = [&]() {
+    EpiArgs<T> ep = prox_epi<T>(u, B.wu, B.logp, B.logdx, nullptr, B.parts, size, pb->F1);
+    grid_chain<T>(P, B.wv, B.gtab, 0, B.ctrl, ep, B.t1, B.t2, s);
+    launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s);
+    EpiArgs<T> raw{};
+    raw.mode = EPI_RAW;
+    raw.out = B.t3;
+    grid_chain<T>(P, B.wu, B.gtab, 1, B.ctrl, raw, B.t1, B.t2, s);
+    launch_bary_combine<T>(B.t3, pb->n, size, la, std::log(asum), F2, B.logdy, v, B.wv, logh, B.ctrl, s);
+  };
+  rc = run_loop(ctx, B.ctrl, pr, iteration, res);
+  if (rc) return rc;
+  if ((rc = finish(ctx))) return rc;
+  if (res->status == -3) return fail(UOT_E_NONFINITE, "non-finite residual");
+  return res->status == 0 ? UOT_OK : UOT_NOT_CONVERGED;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// exported C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int uot_abi_version(void) { return UOT_ABI_VERSION; }
+
+const char* uot_last_error(void) { return g_err.c_str(); }
+
+const char* uot_status_string(int st) {
+  switch (st) {
+    case UOT_OK: return "ok";
+    case UOT_NOT_CONVERGED: return "not converged (max_iter reached)";
+    case UOT_E_INVALID: return "invalid argument";
+    case UOT_E_UNSUPPORTED: return "unsupported configuration";
+    case UOT_E_NONFINITE: return "non-finite residual";
+    case UOT_E_HIP: return "HIP runtime error";
+    case UOT_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    default: return "unknown status";
+  }
+}
+
+int uot_create(uot_ctx** out, void* stream) {
+  if (!out) return fail(UOT_E_INVALID, "out is NULL");
+  uot_ctx* c = new (std::nothrow) uot_ctx();
+  if (!c) return fail(UOT_E_INVALID, "out of host memory");
+  c->user = static_cast<hipStream_t>(stream);
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->pinned), sizeof(Ctrl), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    uot_destroy(c);
+    return fail(UOT_E_HIP, std::string("uot_create: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return UOT_OK;
+}
+
+int uot_destroy(uot_ctx* c) {
+  if (!c) return UOT_OK;
+  if (c->work) (void)hipStreamSynchronize(c->work);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  if (c->work) (void)hipStreamDestroy(c->work);
+  delete c;
+  return UOT_OK;
+}
+
+int uot_workspace_size(const uot_problem* pb, size_t* bytes) {
+  if (!pb || !bytes) return fail(UOT_E_INVALID, "NULL argument");
+  Plan P;
+  int rc = make_plan(P, pb->dtype, pb->geom, 1, kMaxStages + 1);
+  if (rc) return rc;
+  *bytes = P.total;
+  return UOT_OK;
+}
+
+int uot_solve(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, void* u, void* v, void* ws, size_t wsb,
+              uot_result* res) {
+  if (!ctx || !res) return fail(UOT_E_INVALID, "ctx and res are required");
+  int rc = validate_problem(pb);
+  if (rc) return rc;
+  if ((rc = validate_params(pr))) return rc;
+  if (pb->dtype == UOT_F32)
+    return solve_t<float>(ctx, pb, pr, static_cast<float*>(u), static_cast<float*>(v), static_cast<char*>(ws), wsb, res);
+  return solve_t<double>(ctx, pb, pr, static_cast<double*>(u), static_cast<double*>(v), static_cast<char*>(ws), wsb, res);
+}
+
+int uot_half_step(uot_ctx* ctx, const uot_problem* pb, double eps, int side, const void* pot_in, void* pot_io,
+                  void* lse_out, double* residual, void* ws, size_t wsb) {
+  if (!ctx) return fail(UOT_E_INVALID, "ctx is required");
+  int rc = validate_problem(pb);
+  if (rc) return rc;
+  if (side != 0 && side != 1) return fail(UOT_E_INVALID, "side must be 0 or 1");
+  if (pb->dtype == UOT_F32)
+    return half_step_t<float>(ctx, pb, eps, side, static_cast<const float*>(pot_in), static_cast<float*>(pot_io),
+                              static_cast<float*>(lse_out), residual, static_cast<char*>(ws), wsb);
+  return half_step_t<double>(ctx, pb, eps, side, static_cast<const double*>(pot_in), static_cast<double*>(pot_io),
+                             static_cast<double*>(lse_out), residual, static_cast<char*>(ws), wsb);
+}
+
+int uot_objective(uot_ctx* ctx, const uot_problem* pb, double eps, const void* u, const void* v, void* pi1, void* pi2,
+                  uot_objective_values* out, void* ws, size_t wsb) {
+  if (!ctx) return fail(UOT_E_INVALID, "ctx is required");
+  int rc = validate_problem(pb);
+  if (rc) return rc;
+  if (pb->dtype == UOT_F32)
+    return objective_t<float>(ctx, pb, eps, static_cast<const float*>(u), static_cast<const float*>(v),
+                              static_cast<float*>(pi1), static_cast<float*>(pi2), out, static_cast<char*>(ws), wsb);
+  return objective_t<double>(ctx, pb, eps, static_cast<const double*>(u), static_cast<const double*>(v),
+                             static_cast<double*>(pi1), static_cast<double*>(pi2), out, static_cast<char*>(ws), wsb);
+}
+
+int uot_bary_workspace_size(const uot_bary_problem* pb, size_t* bytes) {
+  if (!pb || !bytes) return fail(UOT_E_INVALID, "NULL argument");
+  if (pb->geom.kind != UOT_GEOM_GRID) return fail(UOT_E_UNSUPPORTED, "barycentres need a grid geometry");
+  if (pb->n < 1 || pb->n > kMaxBary) return fail(UOT_E_UNSUPPORTED, "1 <= n <= 64 marginals");
+  Plan P;
+  int rc = make_plan(P, pb->dtype, pb->geom, pb->n, kMaxStages + 1);
+  if (rc) return rc;
+  *bytes = P.total;
+  return UOT_OK;
+}
+
+int uot_barycenter(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, void* u, void* v, void* logh,
+                   void* ws, size_t wsb, uot_result* res) {
+  if (!ctx || !pb || !res) return fail(UOT_E_INVALID, "ctx, problem and res are required");
+  if (pb->geom.kind != UOT_GEOM_GRID) return fail(UOT_E_UNSUPPORTED, "barycentres need a grid geometry");
+  if (pb->n < 1 || pb->n > kMaxBary) return fail(UOT_E_UNSUPPORTED, "1 <= n <= 64 marginals");
+  if (!pb->p || !pb->dx || !pb->dy || !pb->alpha) return fail(UOT_E_INVALID, "p, dx, dy, alpha are required");
+  for (int k = 0; k < pb->n; ++k)
+    if (!(pb->alpha[k] > 0)) return fail(UOT_E_INVALID, "alpha_k must be > 0");
+  int rc = check_div(pb->F1, "F1");
+  if (rc) return rc;
+  if ((rc = check_div(pb->F2, "F2"))) return rc;
+  if (pb->F2.kind != UOT_DIV_KL && pb->F2.kind != UOT_DIV_EQ)
+    return fail(UOT_E_UNSUPPORTED, "barycentre F2 must be KL or equality");
+  if ((rc = validate_params(pr))) return rc;
+  if (pb->dtype == UOT_F32)
+    return bary_t<float>(ctx, pb, pr, static_cast<float*>(u), static_cast<float*>(v), static_cast<float*>(logh),
+                         static_cast<char*>(ws), wsb, res);
+  return bary_t<double>(ctx, pb, pr, static_cast<double*>(u), static_cast<double*>(v), static_cast<double*>(logh),
+                        static_cast<char*>(ws), wsb, res);
+}
+
+}  // extern "C"

@@ -1,0 +1,182 @@
+// Device-side building blocks of libuot (gfx950, wave64).
+//
+// All log-sum-exps run in base 2 (v_exp_f32 / v_log_f32 are base-2
+// instructions): a field w stored "in log2 units" means w = (pot/eps + log d)
+// * log2(e), and a pass returns log2 of the Gibbs product.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace uot {
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLn2 = 0.6931471805599453094;
+constexpr int kMaxStages = 32;
+
+// ---------------------------------------------------------------------------
+// scalar math per precision
+// ---------------------------------------------------------------------------
+template <typename T> struct Num;
+
+template <> struct Num<float> {
+  static __device__ __forceinline__ float ninf() { return -__builtin_inff(); }
+  static __device__ __forceinline__ float pinf() { return __builtin_inff(); }
+  // hardware v_exp_f32 / v_log_f32 (base 2); inputs below -126 give 0
+  static __device__ __forceinline__ float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+  static __device__ __forceinline__ float log2(float x) { return __builtin_amdgcn_logf(x); }
+  static __device__ __forceinline__ float expm1(float x) { return ::expm1f(x); }
+  static __device__ __forceinline__ float exp(float x) { return ::expf(x); }
+  static __device__ __forceinline__ float log(float x) { return ::logf(x); }
+  static __device__ __forceinline__ float fmax(float a, float b) { return __builtin_fmaxf(a, b); }
+  static __device__ __forceinline__ float fmin(float a, float b) { return __builtin_fminf(a, b); }
+};
+
+template <> struct Num<double> {
+  static __device__ __forceinline__ double ninf() { return -__builtin_inf(); }
+  static __device__ __forceinline__ double pinf() { return __builtin_inf(); }
+  static __device__ __forceinline__ double exp2(double x) { return ::exp2(x); }
+  static __device__ __forceinline__ double log2(double x) { return ::log2(x); }
+  static __device__ __forceinline__ double expm1(double x) { return ::expm1(x); }
+  static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+  static __device__ __forceinline__ double log(double x) { return ::log(x); }
+  static __device__ __forceinline__ double fmax(double a, double b) { return __builtin_fmax(a, b); }
+  static __device__ __forceinline__ double fmin(double a, double b) { return __builtin_fmin(a, b); }
+};
+
+// ---------------------------------------------------------------------------
+// running log2-sum-exp2 with a chunked online maximum: the value is
+// m + log2(s).  add<C>() folds C terms with one rescale, so the per-term
+// cost is one max, one subtract, one exp2 and one add.
+// ---------------------------------------------------------------------------
+template <typename T> struct Lse2 {
+  T m, s;
+  __device__ __forceinline__ void init() { m = Num<T>::ninf(); s = T(0); }
+
+  template <int C>
+  __device__ __forceinline__ void add(const T* t) {
+    T cm = t[0];
+#pragma unroll
+    for (int k = 1; k < C; ++k) cm = Num<T>::fmax(cm, t[k]);
+    const T mn = Num<T>::fmax(m, cm);
+    const T sh = (mn == Num<T>::ninf()) ? T(0) : mn;   // all -inf so far: keep s = 0
+    T acc = s * Num<T>::exp2(m - sh);
+#pragma unroll
+    for (int k = 0; k < C; ++k) acc += Num<T>::exp2(t[k] - sh);
+    m = mn;
+    s = acc;
+  }
+
+  __device__ __forceinline__ void merge(T m2, T s2) {
+    const T mn = Num<T>::fmax(m, m2);
+    if (mn == Num<T>::ninf()) return;
+    s = s * Num<T>::exp2(m - mn) + s2 * Num<T>::exp2(m2 - mn);
+    m = mn;
+  }
+
+  // log2 of the sum; -inf for an empty / all -inf sum
+  __device__ __forceinline__ T result() const { return m + Num<T>::log2(s); }
+};
+
+// ---------------------------------------------------------------------------
+// control block: one per solve, lives in the workspace.  Every kernel reads
+// eps and its skip flag here, so a captured chunk of iterations is the same
+// graph for every eps stage and stops by itself once converged.
+// ---------------------------------------------------------------------------
+struct Ctrl {
+  int32_t stop;      // X half-steps and the control kernel skip when set
+  int32_t yskip;     // Y half-steps skip when set
+  int32_t status;    // 0 ok, 1 not converged, -3 non-finite residual
+  int32_t stage_x;   // eps stage of the X half-step about to run
+  int32_t stage_y;   // eps stage of the Y half-step about to run
+  int32_t n_stages;  // annealing stages before the final eps
+  int32_t iters_per_stage;
+  int32_t pad;
+  int64_t iter;      // completed X half-steps (= iteration index of the next)
+  int64_t max_iter;
+  double tol;
+  double res;        // residual of the last iteration
+  double eps_x, eps_y;
+  double eps_tab[kMaxStages + 1];
+};
+
+// residual partial (per block): value = e^m * {den, num}
+struct ResPart {
+  double m, den, num;
+};
+
+// ---------------------------------------------------------------------------
+// proxdiv rows of Table proximalexplicit in the log domain, returning the new
+// potential eps*log(a) from S = log K(b dy) (natural log), zero absorbed offset.
+// ---------------------------------------------------------------------------
+struct DivDev {
+  int kind;          // 0 =, 1 KL, 2 TV, 3 RG
+  int has_lo, has_hi;
+  int pad;
+  double lam, log_alpha, log_beta;
+};
+
+template <typename T>
+__device__ __forceinline__ T proxdiv_pot(const DivDev& F, T logp, T S, T eps) {
+  const T d = logp - S;                 // -inf where p = 0
+  switch (F.kind) {
+    case 0:
+      return eps * d;
+    case 1: {
+      const T lam = T(F.lam);
+      return (eps * lam / (lam + eps)) * d;
+    }
+    case 2: {
+      const T lam = T(F.lam);
+      return Num<T>::fmin(Num<T>::fmax(eps * d, -lam), lam);
+    }
+    default: {
+      const T lo = F.has_lo ? eps * (T(F.log_alpha) + d) : Num<T>::ninf();
+      const T hi = F.has_hi ? eps * (T(F.log_beta) + d) : Num<T>::pinf();
+      return Num<T>::fmin(hi, Num<T>::fmax(lo, T(0)));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// wave64 / block reductions
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void res_merge(T& m, T& den, T& num, T m2, T den2, T num2) {
+  const T mn = Num<T>::fmax(m, m2);
+  if (mn == Num<T>::ninf()) return;
+  const T f1 = Num<T>::exp2(m - mn), f2 = Num<T>::exp2(m2 - mn);
+  den = den * f1 + den2 * f2;
+  num = num * f1 + num2 * f2;
+  m = mn;
+}
+
+// Reduce (m, den, num) over a block of 256 threads (m in log2 units); thread
+// 0 writes the result.  Every thread of the block must call this.
+template <typename T>
+__device__ __forceinline__ void block_res_reduce(T m, T den, T num, ResPart* out) {
+  __shared__ double sm[4][3];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    T m2 = __shfl_xor(m, off, 64);
+    T d2 = __shfl_xor(den, off, 64);
+    T n2 = __shfl_xor(num, off, 64);
+    res_merge(m, den, num, m2, d2, n2);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sm[w][0] = double(m);
+    sm[w][1] = double(den);
+    sm[w][2] = double(num);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double M = sm[0][0], D = sm[0][1], U = sm[0][2];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) res_merge<double>(M, D, U, sm[k][0], sm[k][1], sm[k][2]);
+    out->m = M;
+    out->den = D;
+    out->num = U;
+  }
+}
+
+}  // namespace uot

@@ -1,0 +1,665 @@
+// HIP kernels of libuot for gfx950 (MI355X).
+//
+// One half-step of the scaling iteration (S) is
+//   (1) a Gibbs product in the log domain, S = log K(b dy), and
+//   (2) a pointwise proxdiv epilogue (Table proximalexplicit), plus on the X
+//       side the partial sums of the marginal residual.
+// (1) has two forms:
+//   * regular grids: K is a tensor product of 1-D Gaussian kernels (Sec. 4.4,
+//     separable kernel); every 1-D pass is a batched log-sum-exp
+//     out[a][i][b] = LSE2_j(g[i-j] + in[a][j][b]), with g = -C1/eps in log2
+//     units taken from a per-stage table;
+//   * point clouds: dense log-sum-exp over all columns, C_ij = |x_i - y_j|^2
+//     recomputed from coordinates staged in LDS (Sec. 4.4, "Computing the
+//     matrix multiplications"); columns are split across blocks and the
+//     per-split (max, sum) pairs merged by the epilogue kernel.
+#include "uot_device.h"
+#include "uot_launch.h"
+
+namespace uot {
+
+constexpr int kBlock = 256;
+constexpr int kChunk = 8;       // terms per online-max rescale
+constexpr int kMaxLine = 4096;  // longest grid axis (LDS table of the contiguous pass)
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+__device__ __forceinline__ bool skip_side(const Ctrl* c, int side) {
+  return side == 0 ? (c->stop != 0) : (c->yskip != 0);
+}
+
+// ---------------------------------------------------------------------------
+// input preparation: log densities (-inf at 0), log reference weights
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_log(const T* __restrict__ src, T* __restrict__ dst, int64_t n, int zero_is_ninf) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = src[i];
+  dst[i] = (s > T(0)) ? Num<T>::log(s) : (zero_is_ninf ? Num<T>::ninf() : Num<T>::log(s));
+}
+
+// pot = v0 (or 0), w = (pot/eps + logd) * log2(e)
+template <typename T>
+__global__ void k_init_pot(const T* __restrict__ v0, const T* __restrict__ logd, T* __restrict__ pot,
+                           T* __restrict__ w, int64_t n, int64_t size, const Ctrl* __restrict__ c,
+                           int which_eps) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T eps = T(which_eps == 0 ? c->eps_x : c->eps_y);
+  T p = v0 ? v0[i] : T(0);
+  if (pot) pot[i] = p;
+  if (w) w[i] = (p / eps + logd[i % size]) * T(kLog2e);
+}
+
+// g tables of one grid axis for every eps stage: tab[s][k] = -((k-(n-1)) h)^2 / eps_s * log2(e)
+template <typename T>
+__global__ void k_gtab(T* __restrict__ tab, int n, double h, const Ctrl* __restrict__ c, int nst) {
+  const int len = 2 * n - 1;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)len * nst) return;
+  const int s = (int)(t / len), k = (int)(t % len);
+  const double d = double(k - (n - 1)) * h;
+  tab[t] = T(-(d * d) / c->eps_tab[s] * kLog2e);
+}
+
+// ---------------------------------------------------------------------------
+// epilogue shared by every Gibbs product: S2 = log2 of the product at element e
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void epilogue(int64_t e, T S2, bool valid, const Ctrl* __restrict__ c, int side,
+                                         const EpiArgs<T>& ep, int part_index) {
+  if (ep.mode == EPI_RAW) {
+    if (valid) ep.out[e] = S2;
+    return;
+  }
+  const T eps = T(side == 0 ? c->eps_x : c->eps_y);
+  const T eps_w = T(c->eps_x);       // w feeds the next half-step, which runs at eps_x
+  T m = Num<T>::ninf(), den = T(0), num = T(0);
+  if (valid) {
+    const T S = S2 * T(kLn2);
+    const T ld = ep.logd[e % ep.size];
+    const T uo = ep.pot[e];
+    const T un = proxdiv_pot<T>(ep.F, ep.logp[e], S, eps);
+    ep.pot[e] = un;
+    if (ep.wnext) ep.wnext[e] = (un / eps_w + ld) * T(kLog2e);
+    if (ep.lse_out) ep.lse_out[e] = S;
+    if (ep.part) {
+      if (un == Num<T>::ninf()) {
+        if (uo != Num<T>::ninf()) {
+          m = (S + uo / eps + ld) * T(kLog2e);
+          num = T(1);
+        }
+      } else {
+        m = (S + un / eps + ld) * T(kLog2e);
+        den = T(1);
+        num = Num<T>::fmax(Num<T>::expm1((uo - un) / eps), -Num<T>::expm1((uo - un) / eps));
+      }
+    }
+  }
+  if (ep.part) block_res_reduce<T>(m, den, num, ep.part + part_index);
+}
+
+// ---------------------------------------------------------------------------
+// grid pass along a strided axis: lanes over b (contiguous), output index i
+// uniform per block, so g[i-j] is a wave-uniform (scalar) load.
+//   out[a][i][b] = LSE2_j ( g[i - j] + in[a][j][b] )
+// grid = (ceil(B/256), n, A)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_grid_strided(const T* __restrict__ in, int n, int64_t B,
+                                                          const T* __restrict__ gtab, int side,
+                                                          const Ctrl* __restrict__ c, EpiArgs<T> ep) {
+  if (skip_side(c, side)) return;
+  const int stage = side == 0 ? c->stage_x : c->stage_y;
+  const T* __restrict__ gi = gtab + (int64_t)stage * (2 * n - 1) + blockIdx.y + (n - 1);   // g[i - j] = gi[-j]
+  const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = b < B;
+  const int64_t a = blockIdx.z;
+  const T* __restrict__ col = in + (a * n) * B + (valid ? b : 0);
+  Lse2<T> acc;
+  acc.init();
+  int j = 0;
+  for (; j + kChunk <= n; j += kChunk) {
+    T t[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) t[k] = gi[-(j + k)] + col[(int64_t)(j + k) * B];
+    acc.template add<kChunk>(t);
+  }
+  if (j < n) {
+    T t[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) t[k] = (j + k < n) ? gi[-(j + k)] + col[(int64_t)(j + k) * B] : Num<T>::ninf();
+    acc.template add<kChunk>(t);
+  }
+  const int64_t e = (a * n + blockIdx.y) * B + b;
+  const int part = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  epilogue<T>(e, acc.result(), valid, c, side, ep, part);
+}
+
+// ---------------------------------------------------------------------------
+// grid pass along the contiguous axis: lanes over the output index i, line
+// a uniform per block, so in[a][j] is a wave-uniform (scalar) load and g[i-j]
+// comes from an LDS copy of the stage's table.
+//   out[a][i] = LSE2_j ( g[i - j] + in[a][j] )
+// grid = (ceil(n/256), A_lo, A_hi) with a = blockIdx.z * gridDim.y + blockIdx.y
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in, int n, int64_t A,
+                                                         const T* __restrict__ gtab, int side,
+                                                         const Ctrl* __restrict__ c, EpiArgs<T> ep) {
+  if (skip_side(c, side)) return;
+  extern __shared__ __align__(16) unsigned char gl_raw[];
+  T* gl = reinterpret_cast<T*>(gl_raw);
+  const int stage = side == 0 ? c->stage_x : c->stage_y;
+  const T* __restrict__ g = gtab + (int64_t)stage * (2 * n - 1);
+  for (int k = threadIdx.x; k < 2 * n - 1; k += kBlock) gl[k] = g[k];
+  __syncthreads();
+  const int64_t a = (int64_t)blockIdx.z * gridDim.y + blockIdx.y;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = (i < n) && (a < A);
+  const int ic = valid ? i : 0;
+  const T* __restrict__ line = in + (a < A ? a : 0) * (int64_t)n;
+  const T* gli = gl + ic + (n - 1);      // g[i - j] = gli[-j]
+  Lse2<T> acc;
+  acc.init();
+  int j = 0;
+  for (; j + kChunk <= n; j += kChunk) {
+    T t[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) t[k] = gli[-(j + k)] + line[j + k];
+    acc.template add<kChunk>(t);
+  }
+  if (j < n) {
+    T t[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) t[k] = (j + k < n) ? gli[-(j + k)] + line[j + k] : Num<T>::ninf();
+    acc.template add<kChunk>(t);
+  }
+  const int64_t e = a * n + i;
+  const int part = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  epilogue<T>(e, acc.result(), valid, c, side, ep, part);
+}
+
+// ---------------------------------------------------------------------------
+// dense point-cloud product: partial LSE over one column split.
+//   part[split][i] = (m, s) with  m + log2 s = LSE2_{j in split}( w_j - sc |x_i - y_j|^2 )
+// rows: xr (DIM x Nr), columns: yc (DIM x Mc) and w (Mc, log2 units).
+// grid = (ceil(Nr / (256 R)), splits)
+// ---------------------------------------------------------------------------
+template <typename T, int DIM, int R>
+__global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, int64_t Nr,
+                                                       const T* __restrict__ yc, const T* __restrict__ w,
+                                                       int64_t Mc, int64_t cols_per_split,
+                                                       T* __restrict__ pm, T* __restrict__ ps, int side,
+                                                       const Ctrl* __restrict__ c) {
+  if (skip_side(c, side)) return;
+  using V4 = typename Vec4<T>::type;
+  __shared__ V4 tile[kBlock];
+  const T sc = T(kLog2e / (side == 0 ? c->eps_x : c->eps_y));
+  T xi[R][DIM];
+  int64_t rows[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    rows[r] = (int64_t)blockIdx.x * (kBlock * R) + r * kBlock + threadIdx.x;
+    const int64_t rr = rows[r] < Nr ? rows[r] : 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xi[r][d] = xr[d * Nr + rr];
+  }
+  Lse2<T> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r].init();
+  const int64_t cb = (int64_t)blockIdx.y * cols_per_split;
+  const int64_t ce = (cb + cols_per_split < Mc) ? cb + cols_per_split : Mc;
+  for (int64_t c0 = cb; c0 < ce; c0 += kBlock) {
+    const int64_t cc = c0 + threadIdx.x;
+    V4 rec;
+    rec.x = rec.y = rec.z = T(0);
+    if (cc < ce) {
+      rec.x = yc[cc];
+      if (DIM > 1) rec.y = yc[Mc + cc];
+      if (DIM > 2) rec.z = yc[2 * Mc + cc];
+      rec.w = w[cc];
+    } else {
+      rec.w = Num<T>::ninf();
+    }
+    __syncthreads();
+    tile[threadIdx.x] = rec;
+    __syncthreads();
+    const int64_t rem = ce - c0;
+    const int cnt = rem < kBlock ? (int)rem : kBlock;
+    for (int jj = 0; jj < cnt; jj += kChunk) {
+      V4 q[kChunk];
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k) q[k] = tile[jj + k];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        T t[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+          T d0 = xi[r][0] - q[k].x;
+          T cst = d0 * d0;
+          if (DIM > 1) { T d1 = xi[r][1] - q[k].y; cst = __builtin_fma(d1, d1, cst); }
+          if (DIM > 2) { T d2 = xi[r][2] - q[k].z; cst = __builtin_fma(d2, d2, cst); }
+          t[k] = __builtin_fma(-sc, cst, q[k].w);
+        }
+        acc[r].template add<kChunk>(t);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (rows[r] < Nr) {
+      pm[blockIdx.y * Nr + rows[r]] = acc[r].m;
+      ps[blockIdx.y * Nr + rows[r]] = acc[r].s;
+    }
+  }
+}
+
+// merge the column splits of k_dense_lse, then the epilogue; grid = ceil(Nr/256)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, const T* __restrict__ ps,
+                                                       int nsplit, int64_t Nr, int side,
+                                                       const Ctrl* __restrict__ c, EpiArgs<T> ep) {
+  if (skip_side(c, side)) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = i < Nr;
+  Lse2<T> acc;
+  acc.init();
+  if (valid)
+    for (int s = 0; s < nsplit; ++s) acc.merge(pm[s * Nr + i], ps[s * Nr + i]);
+  epilogue<T>(i, acc.result(), valid, c, side, ep, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// control kernel (one block), between the X and the Y half-step: reduce the
+// residual partials, count the iteration, pick the next eps, set stop flags.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_control(Ctrl* __restrict__ c, const ResPart* __restrict__ part,
+                                                     int nparts, double* __restrict__ hist) {
+  if (c->stop) {
+    if (threadIdx.x == 0) c->yskip = 1;
+    return;
+  }
+  double m = -__builtin_inf(), den = 0.0, num = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += kBlock) res_merge<double>(m, den, num, part[k].m, part[k].den, part[k].num);
+  __shared__ double sm[kBlock][3];
+  sm[threadIdx.x][0] = m;
+  sm[threadIdx.x][1] = den;
+  sm[threadIdx.x][2] = num;
+  __syncthreads();
+  for (int off = kBlock / 2; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      double M = sm[threadIdx.x][0], D = sm[threadIdx.x][1], U = sm[threadIdx.x][2];
+      res_merge<double>(M, D, U, sm[threadIdx.x + off][0], sm[threadIdx.x + off][1], sm[threadIdx.x + off][2]);
+      sm[threadIdx.x][0] = M;
+      sm[threadIdx.x][1] = D;
+      sm[threadIdx.x][2] = U;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double r = sm[0][2] / sm[0][1];
+  const int64_t l = c->iter;
+  if (hist) hist[l] = r;
+  c->res = r;
+  c->iter = l + 1;
+  c->yskip = 0;
+  const bool final_stage = c->stage_x >= c->n_stages;
+  c->stage_y = c->stage_x;
+  c->eps_y = c->eps_x;
+  int64_t sn = c->iters_per_stage > 0 ? (l + 1) / c->iters_per_stage : c->n_stages;
+  if (sn > c->n_stages) sn = c->n_stages;
+  c->stage_x = (int)sn;
+  c->eps_x = c->eps_tab[sn];
+  if (r != r) {
+    c->stop = 1;
+    c->status = -3;
+  } else if (final_stage && r <= c->tol) {
+    c->stop = 1;
+    c->status = 0;
+  } else if (l + 1 >= c->max_iter) {
+    c->stop = 1;
+    c->status = 1;
+  }
+}
+
+// plain reduction of residual partials into out[0] (single half-step entry)
+__global__ void k_res_reduce(const ResPart* __restrict__ part, int nparts, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double m = -__builtin_inf(), den = 0.0, num = 0.0;
+  for (int k = 0; k < nparts; ++k) res_merge<double>(m, den, num, part[k].m, part[k].den, part[k].num);
+  out[0] = num / den;
+}
+
+__global__ void k_ctrl_init(Ctrl* __restrict__ c, Ctrl init) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = init;
+}
+
+// ---------------------------------------------------------------------------
+// barycentre combine (Table estimatebary rows (i)/(ii), log form) after the
+// Y Gibbs product: T2 (n x size, log2 units) ->  log h (natural), and
+//   v_k = eps log proxdiv_{F2(.|h)}(e^{T_k}),  w_k = (v_k/eps_next + log dy) log2(e)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bary_combine(const T* __restrict__ T2, int nm, int64_t size,
+                                                          BaryW log_alpha, double log_sum_alpha,
+                                                          DivDev F2, const T* __restrict__ logdy,
+                                                          T* __restrict__ v, T* __restrict__ w, T* __restrict__ logh_out,
+                                                          const Ctrl* __restrict__ c) {
+  if (c->yskip) return;
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= size) return;
+  const T eps = T(c->eps_y);
+  const T eps_w = T(c->eps_x);
+  T logh;
+  if (F2.kind == 0) {
+    double acc = 0.0, asum = 0.0;
+    for (int k = 0; k < nm; ++k) {
+      const double al = ::exp(log_alpha.v[k]);
+      acc += al * double(T2[k * size + j]) * kLn2;
+      asum += al;
+    }
+    logh = T(acc / asum);
+  } else {
+    const T gam = eps / (eps + T(F2.lam));           // eps/(eps+lam)
+    Lse2<T> a;
+    a.init();
+    for (int k = 0; k < nm; ++k) {
+      T t[1] = {T(log_alpha.v[k] * kLog2e) + gam * T2[k * size + j]};
+      a.template add<1>(t);
+    }
+    logh = (a.result() * T(kLn2) - T(log_sum_alpha)) / gam;
+  }
+  if (logh_out) logh_out[j] = logh;
+  const T ld = logdy[j];
+  for (int k = 0; k < nm; ++k) {
+    const T S = T2[k * size + j] * T(kLn2);
+    const T vn = proxdiv_pot<T>(F2, logh, S, eps);
+    v[k * size + j] = vn;
+    w[k * size + j] = (vn / eps_w + ld) * T(kLog2e);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// objective terms in FP64 (Thm. duality at the plan R = e^{(u+v-C)/eps}):
+// per element of one side, with S = log of the Gibbs product of the other
+// side's scaling (natural log):
+//   pi = e^{pot/eps + S};  acc[0] += d pi; acc[1] += d pot pi;
+//   acc[2] += d f(pi | p); acc[3] += d f*(-pot | p)
+// written as per-block partials (4 doubles each).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_obj_side(const T* __restrict__ pot, const T* __restrict__ S,
+                                                      const T* __restrict__ p, const T* __restrict__ d,
+                                                      int64_t n, double eps, DivDev F, T* __restrict__ pi_out,
+                                                      double* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  if (i < n) {
+    const double u = double(pot[i]);
+    const double s = double(S[i]) * kLn2;   // S arrives in log2 units
+    const double pp = double(p[i]);
+    const double dd = double(d[i]);
+    const double pi = (u == -__builtin_inf()) ? 0.0 : ::exp(u / eps + s);
+    if (pi_out) pi_out[i] = T(pi);
+    a0 = dd * pi;
+    a1 = (pi > 0) ? dd * u * pi : 0.0;
+    const double w = -u;   // conjugate argument
+    const double lam = F.lam;
+    switch (F.kind) {
+      case 1:  // lam KL
+        a2 = dd * lam * ((pi > 0 ? pi * ::log(pi / pp) : 0.0) - pi + pp);
+        if (pp == 0.0 && pi > 0) a2 = __builtin_inf();
+        a3 = (pp > 0) ? dd * lam * pp * ::expm1(w / lam) : 0.0;
+        break;
+      case 2:  // lam TV
+        a2 = dd * lam * ::fabs(pi - pp);
+        a3 = (w > lam * (1 + 1e-6)) ? __builtin_inf() : dd * pp * ::fmax(w, -lam);
+        break;
+      default:  // = / RG: indicator terms are not finite-valued; gap reported as NaN by the host
+        a2 = 0.0;
+        a3 = 0.0;
+        if (F.kind == 0) a3 = (pp > 0) ? dd * pp * w : 0.0;
+        else {
+          const double al = F.has_lo ? ::exp(F.log_alpha) : 0.0;
+          const double be = F.has_hi ? ::exp(F.log_beta) : __builtin_inf();
+          a3 = (pp > 0) ? dd * pp * ((w > 0) ? be * w : al * w) : 0.0;
+        }
+        break;
+    }
+  }
+  __shared__ double sm[4][kBlock];
+  sm[0][threadIdx.x] = a0;
+  sm[1][threadIdx.x] = a1;
+  sm[2][threadIdx.x] = a2;
+  sm[3][threadIdx.x] = a3;
+  __syncthreads();
+  for (int off = kBlock / 2; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int q = 0; q < 4; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+// sum_i exp2(a_i + b_i) (or exp2(b_i) when a is null) in FP64, per-block partials
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sum_exp2(const T* __restrict__ a, const T* __restrict__ b, int64_t n,
+                                                      double* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    const double x = (a ? double(a[i]) : 0.0) + double(b[i]);
+    v = (x == -__builtin_inf()) ? 0.0 : ::exp2(x);
+  }
+  __shared__ double sm[kBlock];
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = kBlock / 2; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off) sm[threadIdx.x] += sm[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+// dense transport-cost moment: for row i, log2 sum_j C_ij 2^{w_j - sc C_ij}
+// (single block column loop; one thread per row; used once per objective)
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_dense_cost(const T* __restrict__ xr, int64_t Nr,
+                                                        const T* __restrict__ yc, const T* __restrict__ w,
+                                                        int64_t Mc, double eps, T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= Nr) return;
+  const double sc = kLog2e / eps;
+  double xi[3] = {0, 0, 0};
+  for (int d = 0; d < DIM; ++d) xi[d] = double(xr[d * Nr + i]);
+  double m = -__builtin_inf(), s = 0.0;
+  for (int64_t j = 0; j < Mc; ++j) {
+    double cst = 0.0;
+    for (int d = 0; d < DIM; ++d) {
+      const double dd = xi[d] - double(yc[d * Mc + j]);
+      cst += dd * dd;
+    }
+    const double t = double(w[j]) - sc * cst;
+    if (t == -__builtin_inf() || cst == 0.0) continue;
+    const double tt = t + ::log2(cst);
+    if (tt > m) {
+      s = s * ::exp2(m - tt) + 1.0;
+      m = tt;
+    } else {
+      s += ::exp2(tt - m);
+    }
+  }
+  out[i] = T(m + ::log2(s));
+}
+
+// grid cost table: tab[k] = g_s[k] + log2(C1(k)) at the current X stage (-inf at 0 offset)
+template <typename T>
+__global__ void k_gtab_cost(T* __restrict__ tab, int n, double h, double eps) {
+  const int len = 2 * n - 1;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  const double d = double(k - (n - 1)) * h;
+  const double cst = d * d;
+  tab[k] = (cst == 0.0) ? T(-__builtin_inf()) : T(-cst / eps * kLog2e + ::log2(cst));
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <typename T>
+void launch_log(const T* src, T* dst, int64_t n, int zero_is_ninf, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_log<T>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, src, dst, n, zero_is_ninf);
+}
+
+template <typename T>
+void launch_init_pot(const T* v0, const T* logd, T* pot, T* w, int64_t n, int64_t size, const Ctrl* c, int which,
+                     hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_init_pot<T>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, v0, logd, pot, w, n, size, c, which);
+}
+
+template <typename T>
+void launch_gtab(T* tab, int n, double h, const Ctrl* c, int nst, hipStream_t s) {
+  const int64_t tot = (int64_t)(2 * n - 1) * nst;
+  hipLaunchKernelGGL(k_gtab<T>, dim3(ceil_div(tot, kBlock)), dim3(kBlock), 0, s, tab, n, h, c, nst);
+}
+
+template <typename T>
+void launch_gtab_cost(T* tab, int n, double h, double eps, hipStream_t s) {
+  hipLaunchKernelGGL(k_gtab_cost<T>, dim3(ceil_div(2 * n - 1, kBlock)), dim3(kBlock), 0, s, tab, n, h, eps);
+}
+
+template <typename T>
+int grid_strided_parts(int n, int64_t A, int64_t B) {
+  return (int)(ceil_div(B, kBlock) * (int64_t)n * A);
+}
+
+template <typename T>
+int grid_contig_parts(int n, int64_t A) {
+  const int64_t ylim = 65535;
+  const int64_t gy = A < ylim ? A : ylim;
+  const int64_t gz = (A + gy - 1) / gy;
+  return (int)(ceil_div(n, kBlock) * gy * gz);
+}
+
+template <typename T>
+void launch_grid_strided(const T* in, int64_t A, int n, int64_t B, const T* gtab, int side, const Ctrl* c,
+                         const EpiArgs<T>& ep, hipStream_t s) {
+  dim3 grid(ceil_div(B, kBlock), (unsigned)n, (unsigned)A);
+  hipLaunchKernelGGL(k_grid_strided<T>, grid, dim3(kBlock), 0, s, in, n, B, gtab, side, c, ep);
+}
+
+template <typename T>
+void launch_grid_contig(const T* in, int64_t A, int n, const T* gtab, int side, const Ctrl* c,
+                        const EpiArgs<T>& ep, hipStream_t s) {
+  const int64_t ylim = 65535;
+  const int64_t gy = A < ylim ? A : ylim;
+  const int64_t gz = (A + gy - 1) / gy;
+  dim3 grid(ceil_div(n, kBlock), (unsigned)gy, (unsigned)gz);
+  const size_t lds = (size_t)(2 * n - 1) * sizeof(T);
+  hipLaunchKernelGGL(k_grid_contig<T>, grid, dim3(kBlock), lds, s, in, n, A, gtab, side, c, ep);
+}
+
+template <typename T, int DIM, int R>
+static void launch_dense_lse_t(const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, int nsplit,
+                               int64_t cps, T* pm, T* ps, int side, const Ctrl* c, hipStream_t s) {
+  dim3 grid(ceil_div(Nr, kBlock * R), (unsigned)nsplit);
+  hipLaunchKernelGGL((k_dense_lse<T, DIM, R>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side, c);
+}
+
+template <typename T>
+void launch_dense_lse(int dim, int R, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, int nsplit,
+                      int64_t cps, T* pm, T* ps, int side, const Ctrl* c, hipStream_t s) {
+#define UOT_DL(D, RR) launch_dense_lse_t<T, D, RR>(xr, Nr, yc, w, Mc, nsplit, cps, pm, ps, side, c, s)
+  if (R == 1) {
+    if (dim == 1) UOT_DL(1, 1); else if (dim == 2) UOT_DL(2, 1); else UOT_DL(3, 1);
+  } else if (R == 2) {
+    if (dim == 1) UOT_DL(1, 2); else if (dim == 2) UOT_DL(2, 2); else UOT_DL(3, 2);
+  } else {
+    if (dim == 1) UOT_DL(1, 4); else if (dim == 2) UOT_DL(2, 4); else UOT_DL(3, 4);
+  }
+#undef UOT_DL
+}
+
+template <typename T>
+void launch_dense_epi(const T* pm, const T* ps, int nsplit, int64_t Nr, int side, const Ctrl* c,
+                      const EpiArgs<T>& ep, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_epi<T>, dim3(ceil_div(Nr, kBlock)), dim3(kBlock), 0, s, pm, ps, nsplit, Nr, side, c, ep);
+}
+
+void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, c, part, nparts, hist);
+}
+
+void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_res_reduce, dim3(1), dim3(64), 0, s, part, nparts, out);
+}
+
+void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, c, init);
+}
+
+template <typename T>
+void launch_bary_combine(const T* T2, int nm, int64_t size, const BaryW& log_alpha, double log_sum_alpha,
+                         const DivDev& F2, const T* logdy, T* v, T* w, T* logh, const Ctrl* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_bary_combine<T>, dim3(ceil_div(size, kBlock)), dim3(kBlock), 0, s, T2, nm, size, log_alpha,
+                     log_sum_alpha, F2, logdy, v, w, logh, c);
+}
+
+template <typename T>
+int launch_obj_side(const T* pot, const T* S, const T* p, const T* d, int64_t n, double eps, const DivDev& F,
+                    T* pi_out, double* part, hipStream_t s) {
+  const unsigned nb = ceil_div(n, kBlock);
+  hipLaunchKernelGGL(k_obj_side<T>, dim3(nb), dim3(kBlock), 0, s, pot, S, p, d, n, eps, F, pi_out, part);
+  return (int)nb;
+}
+
+template <typename T>
+int launch_sum_exp2(const T* a, const T* b, int64_t n, double* part, hipStream_t s) {
+  const unsigned nb = ceil_div(n, kBlock);
+  hipLaunchKernelGGL(k_sum_exp2<T>, dim3(nb), dim3(kBlock), 0, s, a, b, n, part);
+  return (int)nb;
+}
+
+template <typename T>
+void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, double eps, T* out,
+                       hipStream_t s) {
+  dim3 grid(ceil_div(Nr, kBlock));
+  if (dim == 1) hipLaunchKernelGGL((k_dense_cost<T, 1>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, eps, out);
+  else if (dim == 2) hipLaunchKernelGGL((k_dense_cost<T, 2>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, eps, out);
+  else hipLaunchKernelGGL((k_dense_cost<T, 3>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, eps, out);
+}
+
+#define UOT_INSTANTIATE(T)                                                                                         \
+  template void launch_log<T>(const T*, T*, int64_t, int, hipStream_t);                                           \
+  template void launch_init_pot<T>(const T*, const T*, T*, T*, int64_t, int64_t, const Ctrl*, int, hipStream_t);  \
+  template void launch_gtab<T>(T*, int, double, const Ctrl*, int, hipStream_t);                                   \
+  template void launch_gtab_cost<T>(T*, int, double, double, hipStream_t);                                        \
+  template int grid_strided_parts<T>(int, int64_t, int64_t);                                                      \
+  template int grid_contig_parts<T>(int, int64_t);                                                                \
+  template void launch_grid_strided<T>(const T*, int64_t, int, int64_t, const T*, int, const Ctrl*,              \
+                                       const EpiArgs<T>&, hipStream_t);                                          \
+  template void launch_grid_contig<T>(const T*, int64_t, int, const T*, int, const Ctrl*, const EpiArgs<T>&,     \
+                                      hipStream_t);                                                               \
+  template void launch_dense_lse<T>(int, int, const T*, int64_t, const T*, const T*, int64_t, int, int64_t, T*,  \
+                                    T*, int, const Ctrl*, hipStream_t);                                           \
+  template void launch_dense_epi<T>(const T*, const T*, int, int64_t, int, const Ctrl*, const EpiArgs<T>&,       \
+                                    hipStream_t);                                                                 \
+  template void launch_bary_combine<T>(const T*, int, int64_t, const BaryW&, double, const DivDev&, const T*,    \
+                                       T*, T*, T*, const Ctrl*, hipStream_t);                                    \
+  template int launch_obj_side<T>(const T*, const T*, const T*, const T*, int64_t, double, const DivDev&, T*,    \
+                                  double*, hipStream_t);                                                          \
+  template int launch_sum_exp2<T>(const T*, const T*, int64_t, double*, hipStream_t);                            \
+  template void launch_dense_cost<T>(int, const T*, int64_t, const T*, const T*, int64_t, double, T*, hipStream_t);
+
+UOT_INSTANTIATE(float)
+UOT_INSTANTIATE(double)
+
+}  // namespace uot

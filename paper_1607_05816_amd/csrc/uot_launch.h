@@ -1,0 +1,70 @@
+// Host-side launch interface between the C ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "uot_device.h"
+
+namespace uot {
+
+enum EpiMode { EPI_RAW = 0, EPI_PROX = 1 };
+
+// What the last pass of a Gibbs product does with S2 = log2 of the product.
+//  EPI_RAW : out[e] = S2
+//  EPI_PROX: pot[e] = eps log proxdiv_F(e^S) (old value read first), wnext[e] =
+//            (pot/eps_next + logd) log2(e), lse_out[e] = S (optional), and,
+//            when part != nullptr, residual partials per block.
+template <typename T> struct EpiArgs {
+  int mode;
+  int pad;
+  T* out;
+  T* pot;
+  T* wnext;
+  const T* logp;
+  const T* logd;
+  T* lse_out;
+  ResPart* part;
+  int64_t size;   // elements per field: logd is indexed by e % size
+  DivDev F;
+};
+
+template <typename T> void launch_log(const T* src, T* dst, int64_t n, int zero_is_ninf, hipStream_t s);
+template <typename T>
+void launch_init_pot(const T* v0, const T* logd, T* pot, T* w, int64_t n, int64_t size, const Ctrl* c, int which,
+                     hipStream_t s);
+template <typename T> void launch_gtab(T* tab, int n, double h, const Ctrl* c, int nst, hipStream_t s);
+template <typename T> void launch_gtab_cost(T* tab, int n, double h, double eps, hipStream_t s);
+template <typename T> int grid_strided_parts(int n, int64_t A, int64_t B);
+template <typename T> int grid_contig_parts(int n, int64_t A);
+template <typename T>
+void launch_grid_strided(const T* in, int64_t A, int n, int64_t B, const T* gtab, int side, const Ctrl* c,
+                         const EpiArgs<T>& ep, hipStream_t s);
+template <typename T>
+void launch_grid_contig(const T* in, int64_t A, int n, const T* gtab, int side, const Ctrl* c,
+                        const EpiArgs<T>& ep, hipStream_t s);
+template <typename T>
+void launch_dense_lse(int dim, int R, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, int nsplit,
+                      int64_t cps, T* pm, T* ps, int side, const Ctrl* c, hipStream_t s);
+template <typename T>
+void launch_dense_epi(const T* pm, const T* ps, int nsplit, int64_t Nr, int side, const Ctrl* c,
+                      const EpiArgs<T>& ep, hipStream_t s);
+void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s);
+void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t s);
+void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s);
+constexpr int kMaxBary = 64;
+struct BaryW {
+  double v[kMaxBary];   // log alpha_k
+};
+template <typename T>
+void launch_bary_combine(const T* T2, int nm, int64_t size, const BaryW& log_alpha, double log_sum_alpha,
+                         const DivDev& F2, const T* logdy, T* v, T* w, T* logh, const Ctrl* c, hipStream_t s);
+template <typename T>
+int launch_obj_side(const T* pot, const T* S, const T* p, const T* d, int64_t n, double eps, const DivDev& F,
+                    T* pi_out, double* part, hipStream_t s);
+template <typename T> int launch_sum_exp2(const T* a, const T* b, int64_t n, double* part, hipStream_t s);
+template <typename T>
+void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, double eps, T* out,
+                       hipStream_t s);
+
+}  // namespace uot

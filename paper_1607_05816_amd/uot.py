@@ -1,0 +1,364 @@
+"""Thin Python binding of libuot's C ABI (include/uot.h).
+
+Argument marshalling only: every step of the scaling iteration runs in the
+HIP kernels of libuot.so.  PyTorch supplies device memory and the stream.
+There is no fallback: if the shared library is missing or fails to load,
+every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libuot.so")
+
+UOT_OK, UOT_NOT_CONVERGED = 0, 1
+UOT_DIV_EQ, UOT_DIV_KL, UOT_DIV_TV, UOT_DIV_RG = 0, 1, 2, 3
+UOT_F64, UOT_F32 = 0, 1
+UOT_GEOM_POINTS, UOT_GEOM_GRID = 0, 1
+
+c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class UotDiv(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("reserved", c_i32), ("lam", c_dbl), ("alpha", c_dbl), ("beta", c_dbl)]
+
+
+class UotGeom(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("dim", c_i32), ("N", c_i64), ("M", c_i64), ("x", c_vp), ("y", c_vp),
+                ("n", c_i64 * 3), ("h", c_dbl * 3)]
+
+
+class UotProblem(ctypes.Structure):
+    _fields_ = [("dtype", c_i32), ("reserved", c_i32), ("geom", UotGeom), ("p", c_vp), ("q", c_vp),
+                ("dx", c_vp), ("dy", c_vp), ("F1", UotDiv), ("F2", UotDiv)]
+
+
+class UotParams(ctypes.Structure):
+    _fields_ = [("eps", c_dbl), ("eps0", c_dbl), ("eps_stages", c_i32), ("iters_per_stage", c_i32),
+                ("tol", c_dbl), ("max_iter", c_i64), ("check_every", c_i32), ("use_graph", c_i32),
+                ("v0", c_vp), ("res_hist", c_vp)]
+
+
+class UotResult(ctypes.Structure):
+    _fields_ = [("iters", c_i64), ("residual", c_dbl), ("status", c_i32), ("reserved", c_i32),
+                ("elapsed_ms", c_dbl)]
+
+
+class UotObjectiveValues(ctypes.Structure):
+    _fields_ = [("primal", c_dbl), ("dual", c_dbl), ("gap", c_dbl), ("transport_cost", c_dbl),
+                ("mass1", c_dbl), ("mass2", c_dbl), ("massK", c_dbl)]
+
+
+class UotBaryProblem(ctypes.Structure):
+    _fields_ = [("dtype", c_i32), ("n", c_i32), ("geom", UotGeom), ("p", c_vp),
+                ("alpha", ctypes.POINTER(c_dbl)), ("dx", c_vp), ("dy", c_vp), ("F1", UotDiv), ("F2", UotDiv)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libuot.so (once).  Raises if it is missing: there is no CPU path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libuot.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    sig = {
+        "uot_abi_version": (c_i32, []),
+        "uot_status_string": (ctypes.c_char_p, [c_i32]),
+        "uot_last_error": (ctypes.c_char_p, []),
+        "uot_create": (c_i32, [P(c_vp), c_vp]),
+        "uot_destroy": (c_i32, [c_vp]),
+        "uot_workspace_size": (c_i32, [P(UotProblem), P(ctypes.c_size_t)]),
+        "uot_solve": (c_i32, [c_vp, P(UotProblem), P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t, P(UotResult)]),
+        "uot_half_step": (c_i32, [c_vp, P(UotProblem), c_dbl, c_i32, c_vp, c_vp, c_vp, P(c_dbl), c_vp,
+                                  ctypes.c_size_t]),
+        "uot_objective": (c_i32, [c_vp, P(UotProblem), c_dbl, c_vp, c_vp, c_vp, c_vp, P(UotObjectiveValues), c_vp,
+                                  ctypes.c_size_t]),
+        "uot_bary_workspace_size": (c_i32, [P(UotBaryProblem), P(ctypes.c_size_t)]),
+        "uot_barycenter": (c_i32, [c_vp, P(UotBaryProblem), P(UotParams), c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t,
+                                   P(UotResult)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+class UotError(RuntimeError):
+    def __init__(self, code, where):
+        L = lib()
+        super().__init__("%s failed: %s (%d): %s" % (where, L.uot_status_string(code).decode(), code,
+                                                     L.uot_last_error().decode()))
+        self.code = code
+
+
+def _check(code, where, allow_not_converged=True):
+    if code == UOT_OK or (allow_not_converged and code == UOT_NOT_CONVERGED):
+        return code
+    raise UotError(code, where)
+
+
+# ---------------------------------------------------------------------------
+# divergences (Table proximalexplicit rows)
+# ---------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Div:
+    kind: int
+    lam: float = 1.0
+    alpha: float = 0.0
+    beta: float = math.inf
+
+    def c(self) -> UotDiv:
+        return UotDiv(self.kind, 0, float(self.lam), float(self.alpha), float(self.beta))
+
+
+def EQ():
+    return Div(UOT_DIV_EQ)
+
+
+def KL(lam):
+    return Div(UOT_DIV_KL, lam=float(lam))
+
+
+def TV(lam):
+    return Div(UOT_DIV_TV, lam=float(lam))
+
+
+def RG(alpha, beta):
+    return Div(UOT_DIV_RG, alpha=float(alpha), beta=float(beta))
+
+
+# ---------------------------------------------------------------------------
+# context and helpers
+# ---------------------------------------------------------------------------
+class Context:
+    """A libuot context bound to torch's current stream on the current device."""
+
+    def __init__(self, stream: Optional[torch.cuda.Stream] = None):
+        L = lib()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._h = c_vp()
+        _check(L.uot_create(ctypes.byref(self._h), c_vp(s.cuda_stream)), "uot_create", False)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().uot_destroy(self._h)
+            self._h = c_vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context() -> Context:
+    key = (torch.cuda.current_device(), torch.cuda.current_stream().cuda_stream)
+    if key not in _default_ctx:
+        _default_ctx[key] = Context()
+    return _default_ctx[key]
+
+
+def _dt(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return UOT_F32
+    if t.dtype == torch.float64:
+        return UOT_F64
+    raise TypeError("tensors must be float32 or float64, got %s" % t.dtype)
+
+
+def _dev(t: torch.Tensor, dtype, n=None, name="tensor") -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s has dtype %s, expected %s" % (name, t.dtype, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if n is not None and t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+    return t
+
+
+def _ptr(t):
+    return c_vp(t.data_ptr()) if t is not None else c_vp()
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + max(int(nbytes), 256)]
+
+
+class Problem:
+    """A UOT problem: geometry + densities + reference weights + penalties.
+    Holds references to every tensor it points to."""
+
+    def __init__(self, geom: UotGeom, dtype, p, q, dx, dy, F1: Div, F2: Div, keep=()):
+        self.dtype = dtype
+        self.p, self.q, self.dx, self.dy = p, q, dx, dy
+        self._keep = keep
+        self.N, self.M = p.numel(), q.numel()
+        self.c = UotProblem(_dt(p), 0, geom, _ptr(p), _ptr(q), _ptr(dx), _ptr(dy), F1.c(), F2.c())
+        self.F1, self.F2 = F1, F2
+        self._ws = None
+
+    def workspace(self) -> torch.Tensor:
+        if self._ws is None:
+            n = ctypes.c_size_t()
+            _check(lib().uot_workspace_size(ctypes.byref(self.c), ctypes.byref(n)), "uot_workspace_size", False)
+            self._ws = workspace(n.value, self.p.device)
+        return self._ws
+
+
+def points_problem(x, y, p, q, dx, dy, F1: Div, F2: Div) -> Problem:
+    """x: (N, d) or (d, N) coordinate tensors are accepted as (N, d); stored
+    coordinate-major for the kernels."""
+    dtype = p.dtype
+    N, M = p.numel(), q.numel()
+    if x.dim() == 1:
+        x = x[:, None]
+    if y.dim() == 1:
+        y = y[:, None]
+    if x.shape[0] == N and x.shape[1] != N:
+        x = x.t()
+    if y.shape[0] == M and y.shape[1] != M:
+        y = y.t()
+    xs = _dev(x.contiguous(), dtype, name="x")
+    ys = _dev(y.contiguous(), dtype, name="y")
+    d = xs.shape[0]
+    if ys.shape[0] != d:
+        raise ValueError("x and y must have the same dimension")
+    for t, n, nm in ((p, N, "p"), (q, M, "q"), (dx, N, "dx"), (dy, M, "dy")):
+        _dev(t, dtype, n, nm)
+    g = UotGeom(UOT_GEOM_POINTS, d, N, M, _ptr(xs), _ptr(ys), (c_i64 * 3)(0, 0, 0), (c_dbl * 3)(0, 0, 0))
+    return Problem(g, dtype, p, q, dx, dy, F1, F2, keep=(xs, ys))
+
+
+def grid_problem(shape: Sequence[int], h: Sequence[float], p, q, dx, dy, F1: Div, F2: Div) -> Problem:
+    dtype = p.dtype
+    size = int(math.prod(shape))
+    for t, nm in ((p, "p"), (q, "q"), (dx, "dx"), (dy, "dy")):
+        _dev(t, dtype, size, nm)
+    n = list(shape) + [1] * (3 - len(shape))
+    hh = list(h) + [0.0] * (3 - len(h))
+    g = UotGeom(UOT_GEOM_GRID, len(shape), size, size, c_vp(), c_vp(), (c_i64 * 3)(*n), (c_dbl * 3)(*hh))
+    return Problem(g, dtype, p, q, dx, dy, F1, F2)
+
+
+def params(eps, tol=1e-6, max_iter=10000, eps0=None, eps_stages=10, iters_per_stage=100, check_every=50,
+           use_graph=True, v0=None, res_hist=None) -> UotParams:
+    return UotParams(float(eps), float(eps0 or 0.0), int(eps_stages if eps0 else 0), int(iters_per_stage),
+                     float(tol), int(max_iter), int(check_every), int(bool(use_graph)), _ptr(v0), _ptr(res_hist))
+
+
+def solve(prob: Problem, eps, ctx: Optional[Context] = None, v0=None, record=False, **kw):
+    """Scaling iterations until residual <= tol.  Returns (u, v, info)."""
+    ctx = ctx or default_context()
+    dev = prob.p.device
+    u = torch.empty(prob.N, dtype=prob.dtype, device=dev)
+    v = torch.empty(prob.M, dtype=prob.dtype, device=dev)
+    max_iter = kw.get("max_iter", 10000)
+    hist = torch.full((max_iter,), float("nan"), dtype=torch.float64, device=dev) if record else None
+    if v0 is not None:
+        _dev(v0, prob.dtype, prob.M, "v0")
+    pr = params(eps, v0=v0, res_hist=hist, **kw)
+    res = UotResult()
+    ws = prob.workspace()
+    code = lib().uot_solve(ctx.handle, ctypes.byref(prob.c), ctypes.byref(pr), _ptr(u), _ptr(v), _ptr(ws),
+                           ws.numel(), ctypes.byref(res))
+    _check(code, "uot_solve")
+    info = dict(iters=res.iters, residual=res.residual, status=res.status, elapsed_ms=res.elapsed_ms,
+                converged=(code == UOT_OK))
+    if record:
+        info["res_hist"] = hist[:res.iters].cpu()
+    return u, v, info
+
+
+def half_step(prob: Problem, eps, side, pot_in, pot_old, ctx: Optional[Context] = None):
+    """One half-step from a given state.  side 0: pot_in = v, pot_old = u;
+    returns (u_new, S, r).  side 1: pot_in = u; returns (v_new, T, 0.0)."""
+    ctx = ctx or default_context()
+    n_out = prob.N if side == 0 else prob.M
+    n_in = prob.M if side == 0 else prob.N
+    _dev(pot_in, prob.dtype, n_in, "pot_in")
+    out = _dev(pot_old, prob.dtype, n_out, "pot_old").clone()
+    lse = torch.empty(n_out, dtype=prob.dtype, device=out.device)
+    r = c_dbl()
+    ws = prob.workspace()
+    _check(lib().uot_half_step(ctx.handle, ctypes.byref(prob.c), float(eps), int(side), _ptr(pot_in), _ptr(out),
+                               _ptr(lse), ctypes.byref(r), _ptr(ws), ws.numel()), "uot_half_step", False)
+    return out, lse, r.value
+
+
+def objective(prob: Problem, eps, u, v, ctx: Optional[Context] = None, marginals=False):
+    """Primal / dual / gap / <C,R> / masses at (u, v), FP64 reductions."""
+    ctx = ctx or default_context()
+    _dev(u, prob.dtype, prob.N, "u")
+    _dev(v, prob.dtype, prob.M, "v")
+    pi1 = torch.empty(prob.N, dtype=prob.dtype, device=u.device) if marginals else None
+    pi2 = torch.empty(prob.M, dtype=prob.dtype, device=u.device) if marginals else None
+    o = UotObjectiveValues()
+    ws = prob.workspace()
+    _check(lib().uot_objective(ctx.handle, ctypes.byref(prob.c), float(eps), _ptr(u), _ptr(v), _ptr(pi1), _ptr(pi2),
+                               ctypes.byref(o), _ptr(ws), ws.numel()), "uot_objective", False)
+    d = {k: getattr(o, k) for k, _ in UotObjectiveValues._fields_}
+    if marginals:
+        d["pi1"], d["pi2"] = pi1, pi2
+    return d
+
+
+def barycenter(shape, h, p, alpha, dx, dy, F1: Div, F2: Div, eps, ctx: Optional[Context] = None, v0=None,
+               record=False, **kw):
+    """Unbalanced barycentre of n densities p (n x size) on a grid.
+    Returns (u, v, logh, info)."""
+    ctx = ctx or default_context()
+    dtype = p.dtype
+    nm = p.shape[0]
+    size = int(math.prod(shape))
+    _dev(p, dtype, nm * size, "p")
+    _dev(dx, dtype, size, "dx")
+    _dev(dy, dtype, size, "dy")
+    n = list(shape) + [1] * (3 - len(shape))
+    hh = list(h) + [0.0] * (3 - len(h))
+    g = UotGeom(UOT_GEOM_GRID, len(shape), size, size, c_vp(), c_vp(), (c_i64 * 3)(*n), (c_dbl * 3)(*hh))
+    al = (c_dbl * nm)(*[float(a) for a in alpha])
+    bp = UotBaryProblem(_dt(p), nm, g, _ptr(p), ctypes.cast(al, ctypes.POINTER(c_dbl)), _ptr(dx), _ptr(dy),
+                        F1.c(), F2.c())
+    nb = ctypes.c_size_t()
+    _check(lib().uot_bary_workspace_size(ctypes.byref(bp), ctypes.byref(nb)), "uot_bary_workspace_size", False)
+    ws = workspace(nb.value, p.device)
+    u = torch.empty(nm, size, dtype=dtype, device=p.device)
+    v = torch.empty(nm, size, dtype=dtype, device=p.device)
+    logh = torch.empty(size, dtype=dtype, device=p.device)
+    max_iter = kw.get("max_iter", 10000)
+    hist = torch.full((max_iter,), float("nan"), dtype=torch.float64, device=p.device) if record else None
+    pr = params(eps, v0=v0, res_hist=hist, **kw)
+    res = UotResult()
+    code = lib().uot_barycenter(ctx.handle, ctypes.byref(bp), ctypes.byref(pr), _ptr(u), _ptr(v), _ptr(logh),
+                                _ptr(ws), ws.numel(), ctypes.byref(res))
+    _check(code, "uot_barycenter")
+    info = dict(iters=res.iters, residual=res.residual, status=res.status, elapsed_ms=res.elapsed_ms,
+                converged=(code == UOT_OK))
+    if record:
+        info["res_hist"] = hist[:res.iters].cpu()
+    return u, v, logh, info
