@@ -131,6 +131,12 @@ typedef struct uot_params {
   int32_t use_graph;     /* 1: replay check_every iterations as a hipGraph   */
   const void *v0;        /* optional device warm start for v (M), or NULL    */
   double *res_hist;      /* optional device array (max_iter) receiving r     */
+  double *kernel_ms;     /* optional HOST array [4]: when set, the solve runs
+                            without graphs and adds the HIP-event duration of
+                            every launch per kernel class: [0] first Gibbs
+                            pass / dense LSE, [1] later passes / split merge +
+                            epilogue, [2] control, [3] unused              */
+  int64_t *kernel_launches; /* optional HOST array [4]: launches per class   */
 } uot_params;
 
 typedef struct uot_result {
@@ -217,6 +223,71 @@ int uot_bary_workspace_size(const uot_bary_problem *pb, size_t *bytes);
 int uot_barycenter(uot_ctx *ctx, const uot_bary_problem *pb, const uot_params *pr,
                    void *u, void *v, void *logh, void *ws, size_t ws_bytes,
                    uot_result *res);
+
+/* ---------------------------------------------------------------------------
+ * Ragged batches: B independent point-cloud problems of uneven sizes, solved
+ * together (Sec. 4.4 "Multiple couplings": the products run coupling by
+ * coupling).  Each half-step is one persistent launch whose blocks pull work
+ * items (problem, tile of 256 R rows) from an atomic cursor; every problem has
+ * its own residual, stopping test and iteration count, and its items are
+ * skipped once it has stopped.  Chunks of check_every iterations are replayed
+ * as one hipGraph; the host polls the number of active problems once per
+ * chunk.  Tile rows (256 R) and persistent blocks per compute unit are chosen
+ * by a built-in autotuner (two timed iterations per candidate from the
+ * initial state), cached per batch signature in the context.
+ * Layout: the points of problem b are rows offN[b] .. offN[b+1]-1 of the
+ * concatenated arrays (x: dim x offN[B], coordinate-major); likewise for Y.
+ * eps, the eps schedule, tol and max_iter of uot_params apply to every
+ * problem; v0 (optional) is a concatenated warm start (offM[B]).
+ * ------------------------------------------------------------------------- */
+typedef struct uot_batch_problem {
+  int32_t dtype;         /* UOT_F32 or UOT_F64                               */
+  int32_t dim;           /* 1..3                                             */
+  int64_t B;             /* number of problems                               */
+  const int64_t *offN;   /* HOST, B+1 offsets (offN[0] = 0)                  */
+  const int64_t *offM;   /* HOST, B+1 offsets (offM[0] = 0)                  */
+  const void *x, *y;     /* device, dim x offN[B] / dim x offM[B]            */
+  const void *p, *q;     /* device, densities, concatenated                  */
+  const void *dx, *dy;   /* device, reference weights, concatenated          */
+  uot_div F1, F2;        /* shared by every problem                          */
+} uot_batch_problem;
+
+typedef struct uot_batch_result {
+  int64_t *iters;        /* HOST [B] or NULL: iterations per problem         */
+  double *residual;      /* HOST [B] or NULL: last residual per problem      */
+  double *latency_ms;    /* HOST [B] or NULL: device time from the start of
+                            the iteration until the problem stopped         */
+  int32_t *status;       /* HOST [B] or NULL: 0 converged, 1 max_iter, -3 NaN */
+  int64_t iters_max;     /* iterations of the longest problem               */
+  int64_t n_converged;
+  double elapsed_ms;     /* host wall time of the iteration loop            */
+  int32_t tile_rows;     /* autotuned rows per work item                    */
+  int32_t blocks_per_cu; /* autotuned persistent blocks per compute unit    */
+  double tune_ms;        /* time spent tuning (0 if the cached choice was used) */
+} uot_batch_result;
+
+int uot_batch_workspace_size(const uot_batch_problem *pb, size_t *bytes);
+/* u: device offN[B], v: device offM[B] outputs (problem dtype). */
+int uot_solve_batched(uot_ctx *ctx, const uot_batch_problem *pb, const uot_params *pr,
+                      void *u, void *v, void *ws, size_t ws_bytes, uot_batch_result *res);
+
+/* ---------------------------------------------------------------------------
+ * Measurement helpers (roofline evidence; not part of the iteration).
+ * ------------------------------------------------------------------------- */
+/* Average device time in ms of each Gibbs-product kernel of one X half-step
+ * (the state v is given), measured with HIP events around `reps` back-to-back
+ * launches of that kernel alone on the library stream.
+ *   grid   : ms[0] contiguous-axis pass, ms[1..] strided passes (the last
+ *            one carries the proxdiv epilogue and residual partials);
+ *   points : ms[0] column-split log-sum-exp, ms[1] split merge + epilogue.
+ * *n_kernels receives the number of entries written (<= 3). */
+int uot_time_half_step(uot_ctx *ctx, const uot_problem *pb, double eps, const void *v,
+                       int reps, double *ms, int *n_kernels, void *ws, size_t ws_bytes);
+
+/* Throughput probe of the current device: v_exp_f32 results per second and
+ * v_add_f32 results per second, from 8 independent dependency chains per lane
+ * on 64 waves per compute unit.  Allocates a small scratch buffer itself. */
+int uot_probe_rates(uot_ctx *ctx, double *exp_per_s, double *add_per_s);
 
 #ifdef __cplusplus
 }

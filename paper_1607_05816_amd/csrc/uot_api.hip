@@ -7,6 +7,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <functional>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -22,6 +25,7 @@ struct uot_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   Ctrl* pinned = nullptr;       // host mirror of the control block
   int device = 0;
+  std::map<std::string, std::pair<int, int>> batch_tuned;   // batch signature -> (R, blocks per CU)
 };
 
 namespace {
@@ -40,6 +44,57 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Per-launch HIP-event timing of the kernels of a solve (when requested): every
+// launch enqueued through timed() is bracketed by two events on the library
+// stream; after each chunk the host adds the elapsed times per kernel class.
+struct KTimer {
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> cls;
+  size_t used = 0;
+  double ms[4] = {0, 0, 0, 0};
+  int64_t count[4] = {0, 0, 0, 0};
+  ~KTimer() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+  void collect() {
+    for (size_t k = 0; k < used; ++k) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]) == hipSuccess) {
+        ms[cls[k]] += t;
+        count[cls[k]] += 1;
+      }
+    }
+    used = 0;
+    cls.clear();
+  }
+};
+thread_local KTimer* g_timer = nullptr;
+
+template <typename F>
+void timed(int c, F&& launch) {
+  KTimer* t = g_timer;
+  if (!t) {
+    launch();
+    return;
+  }
+  if (2 * (t->used + 1) > t->pool.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        launch();
+        return;
+      }
+      t->pool.push_back(e);
+    }
+  }
+  (void)hipEventRecord(t->pool[2 * t->used], t->s);
+  launch();
+  (void)hipEventRecord(t->pool[2 * t->used + 1], t->s);
+  t->cls.push_back(c);
+  t->used += 1;
+}
 
 DivDev to_dev(const uot_div& d) {
   DivDev r{};
@@ -266,17 +321,18 @@ void grid_chain(const Plan& P, const T* w, T* const* tabs, int side, Ctrl* c, co
   EpiArgs<T> raw{};
   raw.mode = EPI_RAW;
   if (P.dim == 1) {
-    launch_grid_contig<T>(w, nb, (int)P.n[0], tabs[0], side, c, ep, s);
+    timed(0, [&] { launch_grid_contig<T>(w, nb, (int)P.n[0], tabs[0], side, c, ep, s); });
   } else if (P.dim == 2) {
     raw.out = tmp1;
-    launch_grid_contig<T>(w, nb * P.n[0], (int)P.n[1], tabs[1], side, c, raw, s);
-    launch_grid_strided<T>(tmp1, nb, (int)P.n[0], P.n[1], tabs[0], side, c, ep, s);
+    timed(0, [&] { launch_grid_contig<T>(w, nb * P.n[0], (int)P.n[1], tabs[1], side, c, raw, s); });
+    timed(1, [&] { launch_grid_strided<T>(tmp1, nb, (int)P.n[0], P.n[1], tabs[0], side, c, ep, s); });
   } else {
     raw.out = tmp1;
-    launch_grid_contig<T>(w, nb * P.n[0] * P.n[1], (int)P.n[2], tabs[2], side, c, raw, s);
-    raw.out = tmp2;
-    launch_grid_strided<T>(tmp1, nb * P.n[0], (int)P.n[1], P.n[2], tabs[1], side, c, raw, s);
-    launch_grid_strided<T>(tmp2, nb, (int)P.n[0], P.n[1] * P.n[2], tabs[0], side, c, ep, s);
+    timed(0, [&] { launch_grid_contig<T>(w, nb * P.n[0] * P.n[1], (int)P.n[2], tabs[2], side, c, raw, s); });
+    EpiArgs<T> raw2 = raw;
+    raw2.out = tmp2;
+    timed(1, [&] { launch_grid_strided<T>(tmp1, nb * P.n[0], (int)P.n[1], P.n[2], tabs[1], side, c, raw2, s); });
+    timed(1, [&] { launch_grid_strided<T>(tmp2, nb, (int)P.n[0], P.n[1] * P.n[2], tabs[0], side, c, ep, s); });
   }
 }
 
@@ -288,9 +344,11 @@ void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Buf
   const T* cols = static_cast<const T*>(side == 0 ? g.y : g.x);
   const int64_t Nr = side == 0 ? P.N : P.M;
   const int64_t Mc = side == 0 ? P.M : P.N;
-  launch_dense_lse<T>(P.dim, P.R[side], rows, Nr, cols, w_cols, Mc, P.splits[side], P.cps[side], B.pm, B.ps, side, c,
-                      s);
-  launch_dense_epi<T>(B.pm, B.ps, P.splits[side], Nr, side, c, ep, s);
+  timed(0, [&] {
+    launch_dense_lse<T>(P.dim, P.R[side], rows, Nr, cols, w_cols, Mc, P.splits[side], P.cps[side], B.pm, B.ps, side,
+                        c, s);
+  });
+  timed(1, [&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[side], Nr, side, c, ep, s); });
 }
 
 template <typename T>
@@ -349,7 +407,14 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
   const int chunk = pr->check_every > 0 ? pr->check_every : 50;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  if (pr->use_graph) {
+  KTimer timer;
+  timer.s = s;
+  const bool timing = pr->kernel_ms != nullptr;
+  if (timing) g_timer = &timer;
+  struct Reset {
+    ~Reset() { g_timer = nullptr; }
+  } reset_timer;
+  if (pr->use_graph && !timing) {
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < chunk; ++k) iteration();
     HIP_TRY(hipStreamEndCapture(s, &graph));
@@ -370,8 +435,15 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
       rc = fail(UOT_E_HIP, std::string("iteration chunk failed: ") + hipGetErrorString(hipGetLastError()));
       break;
     }
+    if (timing) timer.collect();
     if (ctx->pinned->stop) break;
     if (launched > pr->max_iter + chunk) { rc = fail(UOT_E_HIP, "control block did not stop"); break; }
+  }
+  if (timing) {
+    for (int k = 0; k < 4; ++k) {
+      pr->kernel_ms[k] = timer.ms[k];
+      if (pr->kernel_launches) pr->kernel_launches[k] = timer.count[k];
+    }
   }
   auto t1 = std::chrono::steady_clock::now();
   if (exec) (void)hipGraphExecDestroy(exec);
@@ -409,7 +481,7 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   HIP_TRY(hipGetLastError());
   auto iteration = [&]() {
     half_step<T>(P, *pb, 0, B, u, nullptr, true, s);
-    launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s);
+    timed(2, [&] { launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s); });
     half_step<T>(P, *pb, 1, B, v, nullptr, false, s);
   };
   rc = run_loop(ctx, B.ctrl, pr, iteration, res);
@@ -602,6 +674,386 @@ int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u,
   return res->status == 0 ? UOT_OK : UOT_NOT_CONVERGED;
 }
 
+// average device time of each Gibbs-product kernel of one X half-step, with
+// HIP events around `reps` back-to-back launches of that kernel alone
+template <typename T>
+int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, double eps, const T* v, int reps, double* ms, int* nk,
+                     char* ws, size_t wsb) {
+  Plan P;
+  int rc = make_plan(P, pb->dtype, pb->geom, 1, 1);
+  if (rc) return rc;
+  if ((rc = check_ws(P, ws, wsb))) return rc;
+  if (!v || !ms || !nk || reps < 1) return fail(UOT_E_INVALID, "v, ms, n_kernels and reps >= 1 are required");
+  hipStream_t s = ctx->work;
+  if ((rc = begin(ctx))) return rc;
+  Bufs<T> B = carve<T>(P, ws);
+  Ctrl init = make_ctrl(eps, 0, 0, 0, 0, 1);
+  launch_ctrl_init(B.ctrl, init, s);
+  launch_log<T>(static_cast<const T*>(pb->p), B.logp, P.N, 1, s);
+  launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, P.N, 0, s);
+  launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
+  if (P.geom == UOT_GEOM_GRID)
+    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, 1, s);
+  launch_init_pot<T>(v, B.logdy, nullptr, B.wv, P.M, P.M, B.ctrl, 0, s);
+  launch_init_pot<T>(nullptr, B.logdx, B.t3, nullptr, P.N, P.N, B.ctrl, 0, s);   // u = 0 in t3
+  EpiArgs<T> ep = prox_epi<T>(B.t3, B.wu, B.logp, B.logdx, nullptr, B.parts, P.N, pb->F1);
+  EpiArgs<T> raw{};
+  raw.mode = EPI_RAW;
+  std::vector<std::function<void()>> ks;
+  if (P.geom == UOT_GEOM_GRID) {
+    const int64_t nb = 1;
+    if (P.dim == 1) {
+      ks.push_back([&] { launch_grid_contig<T>(B.wv, nb, (int)P.n[0], B.gtab[0], 0, B.ctrl, ep, s); });
+    } else if (P.dim == 2) {
+      raw.out = B.t1;
+      ks.push_back([&] { launch_grid_contig<T>(B.wv, nb * P.n[0], (int)P.n[1], B.gtab[1], 0, B.ctrl, raw, s); });
+      ks.push_back([&] { launch_grid_strided<T>(B.t1, nb, (int)P.n[0], P.n[1], B.gtab[0], 0, B.ctrl, ep, s); });
+    } else {
+      EpiArgs<T> raw2 = raw;
+      raw.out = B.t1;
+      raw2.out = B.t2;
+      ks.push_back([&, raw] { launch_grid_contig<T>(B.wv, nb * P.n[0] * P.n[1], (int)P.n[2], B.gtab[2], 0, B.ctrl, raw, s); });
+      ks.push_back([&, raw2] { launch_grid_strided<T>(B.t1, nb * P.n[0], (int)P.n[1], P.n[2], B.gtab[1], 0, B.ctrl, raw2, s); });
+      ks.push_back([&] { launch_grid_strided<T>(B.t2, nb, (int)P.n[0], P.n[1] * P.n[2], B.gtab[0], 0, B.ctrl, ep, s); });
+    }
+  } else {
+    const T* rows = static_cast<const T*>(pb->geom.x);
+    const T* cols = static_cast<const T*>(pb->geom.y);
+    ks.push_back([&] {
+      launch_dense_lse<T>(P.dim, P.R[0], rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps, 0, B.ctrl, s);
+    });
+    ks.push_back([&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[0], P.N, 0, B.ctrl, ep, s); });
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  for (auto& k : ks) k();   // warm: every intermediate exists before timing
+  for (size_t q = 0; q < ks.size(); ++q) {
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) ks[q]();
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    ms[q] = double(t) / reps;
+  }
+  *nk = (int)ks.size();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
+
+// ---------------------------------------------------------------------------
+// ragged batches
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+  int dtype = 0, dim = 0;
+  size_t esz = 0;
+  int64_t B = 0, totN = 0, totM = 0;
+  int64_t max_items = 0;       // items per side at R = 1 (upper bound for any R)
+  size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_stop, o_yskip, o_status, o_iters, o_res, o_clock,
+      o_itx, o_ity, o_pstart, o_parts, o_curs, o_offN, o_offM, total;
+};
+
+int make_batch_plan(BatchPlan& P, const uot_batch_problem* pb) {
+  if (pb->dtype != UOT_F32 && pb->dtype != UOT_F64) return fail(UOT_E_INVALID, "dtype must be UOT_F32 or UOT_F64");
+  if (pb->dim < 1 || pb->dim > 3) return fail(UOT_E_UNSUPPORTED, "dim must be 1, 2 or 3");
+  if (pb->B < 1 || pb->B > (1 << 24)) return fail(UOT_E_INVALID, "B must be in [1, 2^24]");
+  if (!pb->offN || !pb->offM) return fail(UOT_E_INVALID, "offN and offM are required");
+  P.dtype = pb->dtype;
+  P.dim = pb->dim;
+  P.esz = pb->dtype == UOT_F32 ? 4 : 8;
+  P.B = pb->B;
+  if (pb->offN[0] != 0 || pb->offM[0] != 0) return fail(UOT_E_INVALID, "offsets must start at 0");
+  int64_t items = 0, itemsy = 0;
+  for (int64_t b = 0; b < pb->B; ++b) {
+    const int64_t n = pb->offN[b + 1] - pb->offN[b], m = pb->offM[b + 1] - pb->offM[b];
+    if (n < 1 || m < 1) return fail(UOT_E_INVALID, "every problem needs N, M >= 1");
+    if (n > (1 << 30) || m > (1 << 30)) return fail(UOT_E_UNSUPPORTED, "problem too large for a batch");
+    items += (n + 255) / 256;
+    itemsy += (m + 255) / 256;
+  }
+  P.totN = pb->offN[pb->B];
+  P.totM = pb->offM[pb->B];
+  P.max_items = std::max(items, itemsy);
+  const size_t e = P.esz;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  P.o_ctrl = take(align_up(sizeof(Ctrl), 64) + sizeof(BCtrl));
+  P.o_logp = take(e * P.totN);
+  P.o_logq = take(e * P.totM);
+  P.o_logdx = take(e * P.totN);
+  P.o_logdy = take(e * P.totM);
+  P.o_wu = take(e * P.totN);
+  P.o_wv = take(e * P.totM);
+  P.o_stop = take(4 * P.B);
+  P.o_yskip = take(4 * P.B);
+  P.o_status = take(4 * P.B);
+  P.o_iters = take(8 * P.B);
+  P.o_res = take(8 * P.B);
+  P.o_clock = take(8 * P.B);
+  P.o_itx = take(sizeof(BItem) * P.max_items);
+  P.o_ity = take(sizeof(BItem) * P.max_items);
+  P.o_pstart = take(4 * (P.B + 1));
+  P.o_parts = take(sizeof(ResPart) * P.max_items);
+  P.o_curs = take(4 * 2);
+  P.o_offN = take(8 * (P.B + 1));
+  P.o_offM = take(8 * (P.B + 1));
+  P.total = o;
+  return UOT_OK;
+}
+
+// work items of one side for rows per item 256*R, sorted by cost (largest first);
+// X items also get problem-major residual slots (pstart)
+void build_items(const int64_t* offR, const int64_t* offC, int64_t B, int R, std::vector<BItem>& items,
+                 std::vector<int32_t>* pstart) {
+  items.clear();
+  if (pstart) pstart->assign(B + 1, 0);
+  const int rows = 256 * R;
+  int32_t slot = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    const int64_t n = offR[b + 1] - offR[b];
+    if (pstart) (*pstart)[b] = slot;
+    for (int64_t r0 = 0; r0 < n; r0 += rows) {
+      BItem it;
+      it.prob = (int32_t)b;
+      it.row0 = (int32_t)r0;
+      it.nrows = (int32_t)std::min<int64_t>(rows, n - r0);
+      it.part = slot++;
+      items.push_back(it);
+    }
+  }
+  if (pstart) (*pstart)[B] = slot;
+  std::stable_sort(items.begin(), items.end(), [&](const BItem& a, const BItem& c) {
+    const int64_t ca = (int64_t)a.nrows * (offC[a.prob + 1] - offC[a.prob]);
+    const int64_t cc = (int64_t)c.nrows * (offC[c.prob + 1] - offC[c.prob]);
+    return ca > cc;
+  });
+}
+
+template <typename T>
+int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* u, T* v, char* ws, size_t wsb,
+            uot_batch_result* res) {
+  BatchPlan P;
+  int rc = make_batch_plan(P, pb);
+  if (rc) return rc;
+  if (!ws) return fail(UOT_E_WORKSPACE, "workspace pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(UOT_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (wsb < P.total) return fail(UOT_E_WORKSPACE, "workspace too small: need " + std::to_string(P.total));
+  if (!u || !v || !pb->x || !pb->y || !pb->p || !pb->q || !pb->dx || !pb->dy)
+    return fail(UOT_E_INVALID, "x, y, p, q, dx, dy, u, v are required");
+  hipStream_t s = ctx->work;
+  if ((rc = begin(ctx))) return rc;
+  Ctrl* ctrl = at<Ctrl>(ws, P.o_ctrl);
+  T *logp = at<T>(ws, P.o_logp), *logq = at<T>(ws, P.o_logq), *logdx = at<T>(ws, P.o_logdx),
+    *logdy = at<T>(ws, P.o_logdy), *wu = at<T>(ws, P.o_wu), *wv = at<T>(ws, P.o_wv);
+  BCtrl bc;
+  bc.stop = at<int32_t>(ws, P.o_stop);
+  bc.yskip = at<int32_t>(ws, P.o_yskip);
+  bc.status = at<int32_t>(ws, P.o_status);
+  bc.iters = at<int64_t>(ws, P.o_iters);
+  bc.res = at<double>(ws, P.o_res);
+  bc.clock = at<uint64_t>(ws, P.o_clock);
+  BItem* itx = at<BItem>(ws, P.o_itx);
+  BItem* ity = at<BItem>(ws, P.o_ity);
+  int32_t* pstart_d = at<int32_t>(ws, P.o_pstart);
+  ResPart* parts = at<ResPart>(ws, P.o_parts);
+  int* curs = at<int>(ws, P.o_curs);
+  int64_t* offN_d = at<int64_t>(ws, P.o_offN);
+  int64_t* offM_d = at<int64_t>(ws, P.o_offM);
+  BCtrl* bc_dev = nullptr;   // BCtrl itself travels by value inside a small device copy
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(offN_d, pb->offN, 8 * (P.B + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(offM_d, pb->offM, 8 * (P.B + 1), hipMemcpyHostToDevice));
+  // the BCtrl pointer block lives right after the Ctrl struct in the control slot
+  bc_dev = reinterpret_cast<BCtrl*>(reinterpret_cast<char*>(ctrl) + align_up(sizeof(Ctrl), 64));
+  HIP_TRY(hipMemcpy(bc_dev, &bc, sizeof(BCtrl), hipMemcpyHostToDevice));
+
+  int ncu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  int clock_khz = 0;
+  HIP_TRY(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, ctx->device));
+  const uot_geom dummy{};
+  (void)dummy;
+
+  std::vector<BItem> hx, hy;
+  std::vector<int32_t> pst;
+  auto upload_items = [&](int R) -> int {
+    build_items(pb->offN, pb->offM, P.B, R, hx, &pst);
+    build_items(pb->offM, pb->offN, P.B, R, hy, nullptr);
+    HIP_TRY(hipMemcpy(itx, hx.data(), sizeof(BItem) * hx.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ity, hy.data(), sizeof(BItem) * hy.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(pstart_d, pst.data(), 4 * (P.B + 1), hipMemcpyHostToDevice));
+    return UOT_OK;
+  };
+  auto init_state = [&]() {
+    Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, pr->tol, pr->max_iter);
+    launch_ctrl_init(ctrl, init, s);
+    launch_batch_init(bc_dev, (int)P.B, ctrl, s);
+    launch_set_int(curs, 2, 0, s);
+    launch_log<T>(static_cast<const T*>(pb->p), logp, P.totN, 1, s);
+    launch_log<T>(static_cast<const T*>(pb->q), logq, P.totM, 1, s);
+    launch_log<T>(static_cast<const T*>(pb->dx), logdx, P.totN, 0, s);
+    launch_log<T>(static_cast<const T*>(pb->dy), logdy, P.totM, 0, s);
+    launch_init_pot<T>(nullptr, logdx, u, nullptr, P.totN, P.totN, ctrl, 0, s);
+    launch_init_pot<T>(static_cast<const T*>(pr->v0), logdy, v, wv, P.totM, P.totM, ctrl, 0, s);
+  };
+  int R = 1, bpc = 8;
+  auto iteration = [&]() {
+    EpiArgs<T> epx = prox_epi<T>(u, wu, logp, logdx, nullptr, parts, P.totN, pb->F1);
+    EpiArgs<T> epy = prox_epi<T>(v, wv, logq, logdy, nullptr, nullptr, P.totM, pb->F2);
+    timed(0, [&] {
+      launch_batch_lse<T>(P.dim, R, ncu * bpc, itx, (int)hx.size(), curs + 0, offN_d, offM_d,
+                          static_cast<const T*>(pb->x), P.totN, static_cast<const T*>(pb->y), P.totM, wv, bc_dev,
+                          ctrl, 0, epx, s);
+    });
+    timed(2, [&] { launch_batch_control(ctrl, bc_dev, (int)P.B, parts, pstart_d, curs, s); });
+    timed(1, [&] {
+      launch_batch_lse<T>(P.dim, R, ncu * bpc, ity, (int)hy.size(), curs + 1, offM_d, offN_d,
+                          static_cast<const T*>(pb->y), P.totM, static_cast<const T*>(pb->x), P.totN, wu, bc_dev,
+                          ctrl, 1, epy, s);
+    });
+  };
+
+  // autotuner: rows per item (256 R) and persistent blocks per CU, measured on
+  // two iterations from the initial state; cached per batch signature
+  std::string key = std::to_string(P.dtype) + ":" + std::to_string(P.dim) + ":" + std::to_string(P.B) + ":" +
+                    std::to_string(P.totN) + ":" + std::to_string(P.totM);
+  {
+    uint64_t hsh = 1469598103934665603ull;
+    for (int64_t b = 0; b <= P.B; ++b) hsh = (hsh ^ (uint64_t)(pb->offN[b] * 31 + pb->offM[b])) * 1099511628211ull;
+    key += ":" + std::to_string(hsh);
+  }
+  double tune_ms = 0.0;
+  auto found = ctx->batch_tuned.find(key);
+  if (found != ctx->batch_tuned.end()) {
+    R = found->second.first;
+    bpc = found->second.second;
+  } else {
+    auto t0 = std::chrono::steady_clock::now();
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bestR = 1, bestB = 8;
+    const int Rs[3] = {1, 2, 4};
+    const int Bs[3] = {4, 8, 16};
+    for (int ri = 0; ri < 3; ++ri) {
+      if ((rc = upload_items(Rs[ri]))) return rc;
+      for (int bi = 0; bi < 3; ++bi) {
+        R = Rs[ri];
+        bpc = Bs[bi];
+        init_state();
+        iteration();   // first iteration: caches and code warm
+        HIP_TRY(hipEventRecord(e0, s));
+        iteration();
+        iteration();
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        if (t < best) {
+          best = t;
+          bestR = R;
+          bestB = bpc;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    R = bestR;
+    bpc = bestB;
+    ctx->batch_tuned[key] = {R, bpc};
+    tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if ((rc = upload_items(R))) return rc;
+  init_state();
+  HIP_TRY(hipGetLastError());
+
+  // iteration loop: graph chunks (or timed direct launches) until no problem is active
+  const int chunk = pr->check_every > 0 ? pr->check_every : 50;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  KTimer timer;
+  timer.s = s;
+  const bool timing = pr->kernel_ms != nullptr;
+  if (timing) g_timer = &timer;
+  struct Reset {
+    ~Reset() { g_timer = nullptr; }
+  } reset_timer;
+  if (pr->use_graph && !timing) {
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < chunk; ++k) iteration();
+    HIP_TRY(hipStreamEndCapture(s, &graph));
+    HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  int64_t launched = 0;
+  rc = UOT_OK;
+  while (true) {
+    if (exec) {
+      if (hipGraphLaunch(exec, s) != hipSuccess) { rc = fail(UOT_E_HIP, "hipGraphLaunch failed"); break; }
+    } else {
+      for (int k = 0; k < chunk; ++k) iteration();
+    }
+    launched += chunk;
+    if (hipMemcpyAsync(ctx->pinned, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = fail(UOT_E_HIP, std::string("batch chunk failed: ") + hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    if (timing) timer.collect();
+    const int64_t L = ctx->pinned->iter;
+    if (L > 0 && ctx->pinned->active[(L - 1) & 1] == 0) break;
+    if (launched > pr->max_iter + chunk) { rc = fail(UOT_E_HIP, "batch did not stop"); break; }
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (rc) return rc;
+  if (timing) {
+    for (int k = 0; k < 4; ++k) {
+      pr->kernel_ms[k] = timer.ms[k];
+      if (pr->kernel_launches) pr->kernel_launches[k] = timer.count[k];
+    }
+  }
+  std::vector<int64_t> it(P.B);
+  std::vector<double> rs(P.B);
+  std::vector<int32_t> st(P.B);
+  std::vector<uint64_t> ck(P.B);
+  HIP_TRY(hipMemcpy(it.data(), bc.iters, 8 * P.B, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(rs.data(), bc.res, 8 * P.B, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(st.data(), bc.status, 4 * P.B, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(ck.data(), bc.clock, 8 * P.B, hipMemcpyDeviceToHost));
+  const uint64_t t0c = ctx->pinned->t0_clock;
+  int64_t nconv = 0, itmax = 0;
+  bool nonfinite = false;
+  for (int64_t b = 0; b < P.B; ++b) {
+    if (res->iters) res->iters[b] = it[b];
+    if (res->residual) res->residual[b] = rs[b];
+    if (res->status) res->status[b] = st[b];
+    if (res->latency_ms) res->latency_ms[b] = double(ck[b] - t0c) / double(clock_khz);
+    nconv += (st[b] == 0);
+    nonfinite |= (st[b] == -3);
+    itmax = std::max(itmax, it[b]);
+  }
+  res->iters_max = itmax;
+  res->n_converged = nconv;
+  res->elapsed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  res->tile_rows = 256 * R;
+  res->blocks_per_cu = bpc;
+  res->tune_ms = tune_ms;
+  if ((rc = finish(ctx))) return rc;
+  if (nonfinite) return fail(UOT_E_NONFINITE, "non-finite residual in a batch problem");
+  return nconv == P.B ? UOT_OK : UOT_NOT_CONVERGED;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -698,6 +1150,71 @@ int uot_objective(uot_ctx* ctx, const uot_problem* pb, double eps, const void* u
                               static_cast<float*>(pi1), static_cast<float*>(pi2), out, static_cast<char*>(ws), wsb);
   return objective_t<double>(ctx, pb, eps, static_cast<const double*>(u), static_cast<const double*>(v),
                              static_cast<double*>(pi1), static_cast<double*>(pi2), out, static_cast<char*>(ws), wsb);
+}
+
+int uot_time_half_step(uot_ctx* ctx, const uot_problem* pb, double eps, const void* v, int reps, double* ms,
+                       int* n_kernels, void* ws, size_t wsb) {
+  if (!ctx) return fail(UOT_E_INVALID, "ctx is required");
+  int rc = validate_problem(pb);
+  if (rc) return rc;
+  if (!(eps > 0)) return fail(UOT_E_INVALID, "eps must be > 0");
+  if (pb->dtype == UOT_F32)
+    return time_half_step_t<float>(ctx, pb, eps, static_cast<const float*>(v), reps, ms, n_kernels,
+                                   static_cast<char*>(ws), wsb);
+  return time_half_step_t<double>(ctx, pb, eps, static_cast<const double*>(v), reps, ms, n_kernels,
+                                  static_cast<char*>(ws), wsb);
+}
+
+int uot_probe_rates(uot_ctx* ctx, double* exp_per_s, double* add_per_s) {
+  if (!ctx || !exp_per_s || !add_per_s) return fail(UOT_E_INVALID, "NULL argument");
+  int ncu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  const int blocks = ncu * 16;     // 64 waves per CU: the issue ports stay busy
+  const int iters = 4096;
+  float* buf = nullptr;
+  HIP_TRY(hipMalloc(&buf, sizeof(float) * (size_t)blocks * 256));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double rates[2];
+  for (int which = 0; which < 2; ++which) {
+    launch_probe(which, buf, blocks, iters, ctx->work);   // warm-up
+    HIP_TRY(hipEventRecord(e0, ctx->work));
+    launch_probe(which, buf, blocks, iters, ctx->work);
+    HIP_TRY(hipEventRecord(e1, ctx->work));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    rates[which] = double(blocks) * 256.0 * iters * 8.0 / (double(t) * 1e-3);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(hipFree(buf));
+  *exp_per_s = rates[0];
+  *add_per_s = rates[1];
+  return UOT_OK;
+}
+
+int uot_batch_workspace_size(const uot_batch_problem* pb, size_t* bytes) {
+  if (!pb || !bytes) return fail(UOT_E_INVALID, "NULL argument");
+  BatchPlan P;
+  int rc = make_batch_plan(P, pb);
+  if (rc) return rc;
+  *bytes = P.total;
+  return UOT_OK;
+}
+
+int uot_solve_batched(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, void* u, void* v, void* ws,
+                      size_t wsb, uot_batch_result* res) {
+  if (!ctx || !pb || !res) return fail(UOT_E_INVALID, "ctx, problem and res are required");
+  int rc = check_div(pb->F1, "F1");
+  if (rc) return rc;
+  if ((rc = check_div(pb->F2, "F2"))) return rc;
+  if ((rc = validate_params(pr))) return rc;
+  if (pb->dtype == UOT_F32)
+    return batch_t<float>(ctx, pb, pr, static_cast<float*>(u), static_cast<float*>(v), static_cast<char*>(ws), wsb, res);
+  return batch_t<double>(ctx, pb, pr, static_cast<double*>(u), static_cast<double*>(v), static_cast<char*>(ws), wsb,
+                         res);
 }
 
 int uot_bary_workspace_size(const uot_bary_problem* pb, size_t* bytes) {

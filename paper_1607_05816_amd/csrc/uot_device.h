@@ -98,6 +98,25 @@ struct Ctrl {
   double res;        // residual of the last iteration
   double eps_x, eps_y;
   double eps_tab[kMaxStages + 1];
+  // ragged batches only
+  int32_t active[2];  // problems still active after the last iteration (slot = iteration parity)
+  uint64_t t0_clock;  // device wall clock at the start of the solve
+};
+
+// per-problem state of a ragged batch (arrays of length B in the workspace)
+struct BCtrl {
+  int32_t* stop;
+  int32_t* yskip;
+  int32_t* status;
+  int64_t* iters;
+  double* res;
+  uint64_t* clock;   // device wall clock when the problem stopped
+};
+
+// one work item of a ragged batch: rows [row0, row0 + nrows) of problem prob;
+// its residual partial goes to slot part
+struct BItem {
+  int32_t prob, row0, nrows, part;
 };
 
 // residual partial (per block): value = e^m * {den, num}

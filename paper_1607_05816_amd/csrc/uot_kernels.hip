@@ -13,6 +13,8 @@
 //     recomputed from coordinates staged in LDS (Sec. 4.4, "Computing the
 //     matrix multiplications"); columns are split across blocks and the
 //     per-split (max, sum) pairs merged by the epilogue kernel.
+#include <cstdlib>
+
 #include "uot_device.h"
 #include "uot_launch.h"
 
@@ -66,87 +68,157 @@ __global__ void k_gtab(T* __restrict__ tab, int n, double h, const Ctrl* __restr
 }
 
 // ---------------------------------------------------------------------------
-// epilogue shared by every Gibbs product: S2 = log2 of the product at element e
+// epilogue shared by every Gibbs product.  epi_elem handles one element with
+// S2 = log2 of the product; epi_finish reduces the residual partials of the
+// block (every thread of the block must call it).
 // ---------------------------------------------------------------------------
+template <typename T> struct ResAcc {
+  T m, den, num;
+  __device__ __forceinline__ void init() {
+    m = Num<T>::ninf();
+    den = T(0);
+    num = T(0);
+  }
+  __device__ __forceinline__ void add(T m2, T d2, T n2) { res_merge<T>(m, den, num, m2, d2, n2); }
+};
+
 template <typename T>
-__device__ __forceinline__ void epilogue(int64_t e, T S2, bool valid, const Ctrl* __restrict__ c, int side,
-                                         const EpiArgs<T>& ep, int part_index) {
+__device__ __forceinline__ void epi_elem(int64_t e, T S2, const Ctrl* __restrict__ c, int side,
+                                         const EpiArgs<T>& ep, ResAcc<T>& ra) {
   if (ep.mode == EPI_RAW) {
-    if (valid) ep.out[e] = S2;
+    ep.out[e] = S2;
     return;
   }
   const T eps = T(side == 0 ? c->eps_x : c->eps_y);
   const T eps_w = T(c->eps_x);       // w feeds the next half-step, which runs at eps_x
-  T m = Num<T>::ninf(), den = T(0), num = T(0);
-  if (valid) {
-    const T S = S2 * T(kLn2);
-    const T ld = ep.logd[e % ep.size];
-    const T uo = ep.pot[e];
-    const T un = proxdiv_pot<T>(ep.F, ep.logp[e], S, eps);
-    ep.pot[e] = un;
-    if (ep.wnext) ep.wnext[e] = (un / eps_w + ld) * T(kLog2e);
-    if (ep.lse_out) ep.lse_out[e] = S;
-    if (ep.part) {
-      if (un == Num<T>::ninf()) {
-        if (uo != Num<T>::ninf()) {
-          m = (S + uo / eps + ld) * T(kLog2e);
-          num = T(1);
-        }
-      } else {
-        m = (S + un / eps + ld) * T(kLog2e);
-        den = T(1);
-        num = Num<T>::fmax(Num<T>::expm1((uo - un) / eps), -Num<T>::expm1((uo - un) / eps));
-      }
+  const T S = S2 * T(kLn2);
+  const T ld = ep.logd[e % ep.size];
+  const T uo = ep.pot[e];
+  const T un = proxdiv_pot<T>(ep.F, ep.logp[e], S, eps);
+  ep.pot[e] = un;
+  if (ep.wnext) ep.wnext[e] = (un / eps_w + ld) * T(kLog2e);
+  if (ep.lse_out) ep.lse_out[e] = S;
+  if (ep.part) {
+    if (un == Num<T>::ninf()) {
+      if (uo != Num<T>::ninf()) ra.add((S + uo / eps + ld) * T(kLog2e), T(0), T(1));
+    } else {
+      const T d = Num<T>::expm1((uo - un) / eps);
+      ra.add((S + un / eps + ld) * T(kLog2e), T(1), Num<T>::fmax(d, -d));
     }
   }
-  if (ep.part) block_res_reduce<T>(m, den, num, ep.part + part_index);
+}
+
+template <typename T>
+__device__ __forceinline__ void epi_finish(const EpiArgs<T>& ep, const ResAcc<T>& ra, int part_index) {
+  if (ep.mode != EPI_RAW && ep.part) block_res_reduce<T>(ra.m, ra.den, ra.num, ep.part + part_index);
+}
+
+// merge the per-wave partial LSEs of a block (4 waves split the taps); the
+// merged value for (output r, lane) is returned to wave 0
+template <typename T, int RI>
+__device__ __forceinline__ void merge_waves(Lse2<T> (&acc)[RI]) {
+  __shared__ T smm[4][RI][64], sms[4][RI][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < RI; ++r) {
+    smm[wv][r][lane] = acc[r].m;
+    sms[wv][r][lane] = acc[r].s;
+  }
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int r = 0; r < RI; ++r)
+#pragma unroll
+      for (int k = 1; k < 4; ++k) acc[r].merge(smm[k][r][lane], sms[k][r][lane]);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// grid pass along a strided axis: lanes over b (contiguous), output index i
-// uniform per block, so g[i-j] is a wave-uniform (scalar) load.
-//   out[a][i][b] = LSE2_j ( g[i - j] + in[a][j][b] )
-// grid = (ceil(B/256), n, A)
+// grid pass along a strided axis:  out[a][i][b] = LSE2_j ( g[i - j] + in[a][j][b] )
+// lanes over 64 consecutive b, RI outputs i per lane (uniform, so g[i-j] is a
+// scalar load), the 4 waves of a block take a quarter of the taps j each.
+// grid = (ceil(B/64), ceil(n/RI), A)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int RI>
 __global__ __launch_bounds__(kBlock) void k_grid_strided(const T* __restrict__ in, int n, int64_t B,
                                                           const T* __restrict__ gtab, int side,
                                                           const Ctrl* __restrict__ c, EpiArgs<T> ep) {
   if (skip_side(c, side)) return;
+  // the stage's table in LDS: the lookups g[i - j] are wave-uniform broadcasts
+  extern __shared__ __align__(16) unsigned char gl_raw[];
+  T* gl = reinterpret_cast<T*>(gl_raw);
   const int stage = side == 0 ? c->stage_x : c->stage_y;
-  const T* __restrict__ gi = gtab + (int64_t)stage * (2 * n - 1) + blockIdx.y + (n - 1);   // g[i - j] = gi[-j]
-  const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = b < B;
+  const T* __restrict__ gsrc = gtab + (int64_t)stage * (2 * n - 1);
+  for (int k = threadIdx.x; k < 2 * n - 1; k += kBlock) gl[k] = gsrc[k];
+  __syncthreads();
+  const T* g = gl + (n - 1);    // g[d] for d in [-(n-1), n-1]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t b = (int64_t)blockIdx.x * 64 + lane;
+  const bool valid_b = b < B;
   const int64_t a = blockIdx.z;
-  const T* __restrict__ col = in + (a * n) * B + (valid ? b : 0);
-  Lse2<T> acc;
-  acc.init();
-  int j = 0;
-  for (; j + kChunk <= n; j += kChunk) {
-    T t[kChunk];
+  const int i0 = blockIdx.y * RI;
+  int ii[RI];
 #pragma unroll
-    for (int k = 0; k < kChunk; ++k) t[k] = gi[-(j + k)] + col[(int64_t)(j + k) * B];
-    acc.template add<kChunk>(t);
-  }
-  if (j < n) {
-    T t[kChunk];
+  for (int r = 0; r < RI; ++r) ii[r] = (i0 + r < n) ? i0 + r : n - 1;
+  const T* __restrict__ col = in + (a * n) * B + (valid_b ? b : 0);
+  const int jq = (n + 3) >> 2;
+  const int j0 = wv * jq;
+  const int j1 = (j0 + jq < n) ? j0 + jq : n;
+  Lse2<T> acc[RI];
 #pragma unroll
-    for (int k = 0; k < kChunk; ++k) t[k] = (j + k < n) ? gi[-(j + k)] + col[(int64_t)(j + k) * B] : Num<T>::ninf();
-    acc.template add<kChunk>(t);
+  for (int r = 0; r < RI; ++r) acc[r].init();
+  int j = j0;
+  for (; j + kChunk <= j1; j += kChunk) {
+    T w[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) w[k] = col[(int64_t)(j + k) * B];
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      T t[kChunk];
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k) t[k] = g[ii[r] - (j + k)] + w[k];
+      acc[r].template add<kChunk>(t);
+    }
   }
-  const int64_t e = (a * n + blockIdx.y) * B + b;
-  const int part = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  epilogue<T>(e, acc.result(), valid, c, side, ep, part);
+  if (j < j1) {
+    // tail: indices clamped into [j, j1), surplus terms replaced by -inf
+    T w[kChunk];
+    int jc[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      jc[k] = (j + k < j1) ? j + k : j1 - 1;
+      w[k] = col[(int64_t)jc[k] * B];
+    }
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      T t[kChunk];
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k) {
+        const T tk = g[ii[r] - jc[k]] + w[k];
+        t[k] = (j + k < j1) ? tk : Num<T>::ninf();
+      }
+      acc[r].template add<kChunk>(t);
+    }
+  }
+  merge_waves<T, RI>(acc);
+  ResAcc<T> ra;
+  ra.init();
+  if (wv == 0 && valid_b) {
+#pragma unroll
+    for (int r = 0; r < RI; ++r)
+      if (i0 + r < n) epi_elem<T>((a * n + i0 + r) * B + b, acc[r].result(), c, side, ep, ra);
+  }
+  epi_finish<T>(ep, ra, (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
-// grid pass along the contiguous axis: lanes over the output index i, line
-// a uniform per block, so in[a][j] is a wave-uniform (scalar) load and g[i-j]
-// comes from an LDS copy of the stage's table.
-//   out[a][i] = LSE2_j ( g[i - j] + in[a][j] )
-// grid = (ceil(n/256), A_lo, A_hi) with a = blockIdx.z * gridDim.y + blockIdx.y
+// grid pass along the contiguous axis:  out[a][i] = LSE2_j ( g[i - j] + in[a][j] )
+// lanes over 64 consecutive outputs i (RI groups of 64 per block), the line a
+// uniform, so in[a][j] is a scalar load and g[i-j] comes from an LDS copy of
+// the stage's table; the 4 waves split the taps j.
+// grid = (ceil(n / (64 RI)), A_lo, A_hi) with a = blockIdx.z * gridDim.y + blockIdx.y
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int RI>
 __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in, int n, int64_t A,
                                                          const T* __restrict__ gtab, int side,
                                                          const Ctrl* __restrict__ c, EpiArgs<T> ep) {
@@ -157,30 +229,66 @@ __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in
   const T* __restrict__ g = gtab + (int64_t)stage * (2 * n - 1);
   for (int k = threadIdx.x; k < 2 * n - 1; k += kBlock) gl[k] = g[k];
   __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t a = (int64_t)blockIdx.z * gridDim.y + blockIdx.y;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = (i < n) && (a < A);
-  const int ic = valid ? i : 0;
-  const T* __restrict__ line = in + (a < A ? a : 0) * (int64_t)n;
-  const T* gli = gl + ic + (n - 1);      // g[i - j] = gli[-j]
-  Lse2<T> acc;
-  acc.init();
-  int j = 0;
-  for (; j + kChunk <= n; j += kChunk) {
-    T t[kChunk];
+  const bool valid_a = a < A;
+  const T* __restrict__ line = in + (valid_a ? a : 0) * (int64_t)n;
+  int ii[RI];
 #pragma unroll
-    for (int k = 0; k < kChunk; ++k) t[k] = gli[-(j + k)] + line[j + k];
-    acc.template add<kChunk>(t);
+  for (int r = 0; r < RI; ++r) {
+    const int i = (blockIdx.x * RI + r) * 64 + lane;
+    ii[r] = (i < n ? i : n - 1) + (n - 1);          // index of g[i - 0] in the LDS table
   }
-  if (j < n) {
-    T t[kChunk];
+  const int jq = (n + 3) >> 2;
+  const int j0 = wv * jq;
+  const int j1 = (j0 + jq < n) ? j0 + jq : n;
+  Lse2<T> acc[RI];
 #pragma unroll
-    for (int k = 0; k < kChunk; ++k) t[k] = (j + k < n) ? gli[-(j + k)] + line[j + k] : Num<T>::ninf();
-    acc.template add<kChunk>(t);
+  for (int r = 0; r < RI; ++r) acc[r].init();
+  int j = j0;
+  for (; j + kChunk <= j1; j += kChunk) {
+    T w[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) w[k] = line[j + k];
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      T t[kChunk];
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k) t[k] = gl[ii[r] - (j + k)] + w[k];
+      acc[r].template add<kChunk>(t);
+    }
   }
-  const int64_t e = a * n + i;
-  const int part = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  epilogue<T>(e, acc.result(), valid, c, side, ep, part);
+  if (j < j1) {
+    // tail: indices clamped into [j, j1), surplus terms replaced by -inf
+    int jc[kChunk];
+    T w[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      jc[k] = (j + k < j1) ? j + k : j1 - 1;
+      w[k] = line[jc[k]];
+    }
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      T t[kChunk];
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k) {
+        const T tk = gl[ii[r] - jc[k]] + w[k];
+        t[k] = (j + k < j1) ? tk : Num<T>::ninf();
+      }
+      acc[r].template add<kChunk>(t);
+    }
+  }
+  merge_waves<T, RI>(acc);
+  ResAcc<T> ra;
+  ra.init();
+  if (wv == 0 && valid_a) {
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      const int i = (blockIdx.x * RI + r) * 64 + lane;
+      if (i < n) epi_elem<T>(a * n + i, acc[r].result(), c, side, ep, ra);
+    }
+  }
+  epi_finish<T>(ep, ra, (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -266,11 +374,15 @@ __global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, 
   if (skip_side(c, side)) return;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool valid = i < Nr;
-  Lse2<T> acc;
-  acc.init();
-  if (valid)
+  ResAcc<T> ra;
+  ra.init();
+  if (valid) {
+    Lse2<T> acc;
+    acc.init();
     for (int s = 0; s < nsplit; ++s) acc.merge(pm[s * Nr + i], ps[s * Nr + i]);
-  epilogue<T>(i, acc.result(), valid, c, side, ep, blockIdx.x);
+    epi_elem<T>(i, acc.result(), c, side, ep, ra);
+  }
+  epi_finish<T>(ep, ra, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -536,35 +648,62 @@ void launch_gtab_cost(T* tab, int n, double h, double eps, hipStream_t s) {
   hipLaunchKernelGGL(k_gtab_cost<T>, dim3(ceil_div(2 * n - 1, kBlock)), dim3(kBlock), 0, s, tab, n, h, eps);
 }
 
+// outputs per lane: 2 when one output per lane would already give more than
+// 8 waves per SIMD, else 1 (latency hiding for small grids)
+static int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return v ? atoi(v) : dflt;
+}
+static inline int strided_ri(int n, int64_t A, int64_t B) {
+  static const int forced = env_int("UOT_STRIDED_RI", 0);
+  if (forced == 1 || forced == 2) return forced;
+  const int64_t blocks1 = (int64_t)ceil_div(B, 64) * n * A;
+  return blocks1 * 4 > 8 * 1024 ? 2 : 1;
+}
+static inline int contig_ri(int n, int64_t A) {
+  const int64_t blocks1 = (int64_t)ceil_div(n, 64) * A;
+  return blocks1 * 4 > 8 * 1024 ? 2 : 1;
+}
+static inline void contig_grid(int n, int64_t A, int ri, unsigned& gx, unsigned& gy, unsigned& gz) {
+  const int64_t ylim = 65535;
+  const int64_t y = A < ylim ? A : ylim;
+  gx = ceil_div(n, 64 * ri);
+  gy = (unsigned)y;
+  gz = (unsigned)((A + y - 1) / y);
+}
+
 template <typename T>
 int grid_strided_parts(int n, int64_t A, int64_t B) {
-  return (int)(ceil_div(B, kBlock) * (int64_t)n * A);
+  const int ri = strided_ri(n, A, B);
+  return (int)(ceil_div(B, 64) * (int64_t)ceil_div(n, ri) * A);
 }
 
 template <typename T>
 int grid_contig_parts(int n, int64_t A) {
-  const int64_t ylim = 65535;
-  const int64_t gy = A < ylim ? A : ylim;
-  const int64_t gz = (A + gy - 1) / gy;
-  return (int)(ceil_div(n, kBlock) * gy * gz);
+  unsigned gx, gy, gz;
+  contig_grid(n, A, contig_ri(n, A), gx, gy, gz);
+  return (int)((int64_t)gx * gy * gz);
 }
 
 template <typename T>
 void launch_grid_strided(const T* in, int64_t A, int n, int64_t B, const T* gtab, int side, const Ctrl* c,
                          const EpiArgs<T>& ep, hipStream_t s) {
-  dim3 grid(ceil_div(B, kBlock), (unsigned)n, (unsigned)A);
-  hipLaunchKernelGGL(k_grid_strided<T>, grid, dim3(kBlock), 0, s, in, n, B, gtab, side, c, ep);
+  const int ri = strided_ri(n, A, B);
+  dim3 grid(ceil_div(B, 64), ceil_div(n, ri), (unsigned)A);
+  const size_t lds = (size_t)(2 * n - 1) * sizeof(T);
+  if (ri == 2) hipLaunchKernelGGL((k_grid_strided<T, 2>), grid, dim3(kBlock), lds, s, in, n, B, gtab, side, c, ep);
+  else hipLaunchKernelGGL((k_grid_strided<T, 1>), grid, dim3(kBlock), lds, s, in, n, B, gtab, side, c, ep);
 }
 
 template <typename T>
 void launch_grid_contig(const T* in, int64_t A, int n, const T* gtab, int side, const Ctrl* c,
                         const EpiArgs<T>& ep, hipStream_t s) {
-  const int64_t ylim = 65535;
-  const int64_t gy = A < ylim ? A : ylim;
-  const int64_t gz = (A + gy - 1) / gy;
-  dim3 grid(ceil_div(n, kBlock), (unsigned)gy, (unsigned)gz);
+  const int ri = contig_ri(n, A);
+  unsigned gx, gy, gz;
+  contig_grid(n, A, ri, gx, gy, gz);
   const size_t lds = (size_t)(2 * n - 1) * sizeof(T);
-  hipLaunchKernelGGL(k_grid_contig<T>, grid, dim3(kBlock), lds, s, in, n, A, gtab, side, c, ep);
+  if (ri == 2) hipLaunchKernelGGL((k_grid_contig<T, 2>), dim3(gx, gy, gz), dim3(kBlock), lds, s, in, n, A, gtab, side, c, ep);
+  else hipLaunchKernelGGL((k_grid_contig<T, 1>), dim3(gx, gy, gz), dim3(kBlock), lds, s, in, n, A, gtab, side, c, ep);
 }
 
 template <typename T, int DIM, int R>
@@ -661,5 +800,246 @@ void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w
 
 UOT_INSTANTIATE(float)
 UOT_INSTANTIATE(double)
+
+}  // namespace uot
+
+// ---------------------------------------------------------------------------
+// throughput probes for the roofline of the log-sum-exp passes: 8 independent
+// dependency chains per lane of v_exp_f32 (x <- 2^-x stays in [0.5, 1]) or of
+// v_add_f32; each lane writes its sum so nothing is optimised away.
+// ---------------------------------------------------------------------------
+namespace uot {
+
+__global__ __launch_bounds__(kBlock) void k_probe_exp(float* __restrict__ out, int iters) {
+  float x[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = 0.01f * (threadIdx.x + k);
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = __builtin_amdgcn_exp2f(-x[k]);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += x[k];
+  out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_probe_add(float* __restrict__ out, int iters, float c) {
+  float x[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = 0.01f * (threadIdx.x + k);
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = x[k] + c;
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += x[k];
+  out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+void launch_probe(int which, float* out, int blocks, int iters, hipStream_t s) {
+  if (which == 0) hipLaunchKernelGGL(k_probe_exp, dim3(blocks), dim3(kBlock), 0, s, out, iters);
+  else hipLaunchKernelGGL(k_probe_add, dim3(blocks), dim3(kBlock), 0, s, out, iters, 1e-7f);
+}
+
+}  // namespace uot
+
+// ---------------------------------------------------------------------------
+// ragged batches of independent point-cloud problems.  One persistent launch
+// per half-step: each block pulls work items (problem, row tile) from an
+// atomic cursor until the list is exhausted; items of problems that already
+// stopped are skipped.  Items are pre-sorted by cost (rows x columns),
+// largest first, so the tail of the launch is made of small items.
+// ---------------------------------------------------------------------------
+namespace uot {
+
+template <typename T, int DIM, int R>
+__global__ __launch_bounds__(kBlock) void k_batch_lse(const BItem* __restrict__ items, int n_items,
+                                                       int* __restrict__ cursor, const int64_t* __restrict__ offR,
+                                                       const int64_t* __restrict__ offC, const T* __restrict__ xr,
+                                                       int64_t totR, const T* __restrict__ yc, int64_t totC,
+                                                       const T* __restrict__ w, const BCtrl* __restrict__ bc,
+                                                       const Ctrl* __restrict__ c, int side, EpiArgs<T> ep) {
+  using V4 = typename Vec4<T>::type;
+  __shared__ V4 tile[kBlock];
+  __shared__ int item_sh;
+  const T sc = T(kLog2e / (side == 0 ? c->eps_x : c->eps_y));
+  const int32_t* __restrict__ skip = side == 0 ? bc->stop : bc->yskip;
+  while (true) {
+    __syncthreads();
+    if (threadIdx.x == 0) item_sh = atomicAdd(cursor, 1);
+    __syncthreads();
+    const int it = item_sh;
+    if (it >= n_items) break;
+    const BItem I = items[it];
+    if (skip[I.prob]) continue;
+    const int64_t rb = offR[I.prob];
+    const int64_t cb = offC[I.prob], ce = offC[I.prob + 1];
+    T xi[R][DIM];
+    bool vr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int lr = I.row0 + r * kBlock + threadIdx.x;
+      vr[r] = lr < I.row0 + I.nrows;
+      const int64_t g = rb + (vr[r] ? lr : I.row0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) xi[r][d] = xr[d * totR + g];
+    }
+    Lse2<T> acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r].init();
+    for (int64_t c0 = cb; c0 < ce; c0 += kBlock) {
+      const int64_t cc = c0 + threadIdx.x;
+      V4 rec;
+      rec.x = rec.y = rec.z = T(0);
+      if (cc < ce) {
+        rec.x = yc[cc];
+        if (DIM > 1) rec.y = yc[totC + cc];
+        if (DIM > 2) rec.z = yc[2 * totC + cc];
+        rec.w = w[cc];
+      } else {
+        rec.w = Num<T>::ninf();
+      }
+      __syncthreads();
+      tile[threadIdx.x] = rec;
+      __syncthreads();
+      const int64_t rem = ce - c0;
+      const int cnt = rem < kBlock ? (int)rem : kBlock;
+      for (int jj = 0; jj < cnt; jj += kChunk) {
+        V4 q[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) q[k] = tile[jj + k];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          T t[kChunk];
+#pragma unroll
+          for (int k = 0; k < kChunk; ++k) {
+            T d0 = xi[r][0] - q[k].x;
+            T cst = d0 * d0;
+            if (DIM > 1) { T d1 = xi[r][1] - q[k].y; cst = __builtin_fma(d1, d1, cst); }
+            if (DIM > 2) { T d2 = xi[r][2] - q[k].z; cst = __builtin_fma(d2, d2, cst); }
+            t[k] = __builtin_fma(-sc, cst, q[k].w);
+          }
+          acc[r].template add<kChunk>(t);
+        }
+      }
+    }
+    ResAcc<T> ra;
+    ra.init();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (vr[r]) epi_elem<T>(rb + I.row0 + r * kBlock + threadIdx.x, acc[r].result(), c, side, ep, ra);
+    epi_finish<T>(ep, ra, I.part);
+  }
+}
+
+// per-problem control (one thread per problem) between the X and Y half-steps
+__global__ __launch_bounds__(kBlock) void k_batch_control(Ctrl* __restrict__ c, BCtrl* __restrict__ bc, int B,
+                                                           const ResPart* __restrict__ part,
+                                                           const int32_t* __restrict__ pstart, int* __restrict__ cursors) {
+  const int b = blockIdx.x * kBlock + threadIdx.x;
+  const int64_t l_glob = c->iter;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // cursors of the next launches, the global eps schedule and the counter slot
+    cursors[0] = 0;
+    cursors[1] = 0;
+    c->active[(l_glob + 1) & 1] = 0;
+  }
+  if (b >= B) return;
+  if (bc->stop[b]) {
+    bc->yskip[b] = 1;
+    return;
+  }
+  bc->yskip[b] = 0;
+  double m = -__builtin_inf(), den = 0.0, num = 0.0;
+  for (int k = pstart[b]; k < pstart[b + 1]; ++k) res_merge<double>(m, den, num, part[k].m, part[k].den, part[k].num);
+  const double r = num / den;
+  const int64_t l = bc->iters[b];
+  bc->res[b] = r;
+  bc->iters[b] = l + 1;
+  const bool final_stage = c->iters_per_stage <= 0 || l >= (int64_t)c->n_stages * c->iters_per_stage;
+  int stop = 0;
+  if (r != r) { stop = 1; bc->status[b] = -3; }
+  else if (final_stage && r <= c->tol) { stop = 1; bc->status[b] = 0; }
+  else if (l + 1 >= c->max_iter) { stop = 1; bc->status[b] = 1; }
+  if (stop) {
+    bc->stop[b] = 1;
+    bc->clock[b] = wall_clock64();
+  } else {
+    atomicAdd(&c->active[l & 1], 1);
+  }
+}
+
+// global eps bookkeeping after the per-problem control (single thread)
+__global__ void k_batch_advance(Ctrl* __restrict__ c) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t l = c->iter;
+  c->iter = l + 1;
+  c->stage_y = c->stage_x;
+  c->eps_y = c->eps_x;
+  int64_t sn = c->iters_per_stage > 0 ? (l + 1) / c->iters_per_stage : c->n_stages;
+  if (sn > c->n_stages) sn = c->n_stages;
+  c->stage_x = (int)sn;
+  c->eps_x = c->eps_tab[sn];
+}
+
+__global__ void k_batch_init(BCtrl* __restrict__ bc, int B, Ctrl* __restrict__ c) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b == 0) {
+    c->t0_clock = wall_clock64();
+    c->active[0] = c->active[1] = B;
+  }
+  if (b >= B) return;
+  bc->stop[b] = 0;
+  bc->yskip[b] = 0;
+  bc->iters[b] = 0;
+  bc->status[b] = 1;
+  bc->res[b] = __builtin_inf();
+  bc->clock[b] = 0;
+}
+
+__global__ void k_set_int(int* __restrict__ p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T>
+void launch_batch_lse(int dim, int R, int blocks, const BItem* items, int n_items, int* cursor, const int64_t* offR,
+                      const int64_t* offC, const T* xr, int64_t totR, const T* yc, int64_t totC, const T* w,
+                      const BCtrl* bc, const Ctrl* c, int side, const EpiArgs<T>& ep, hipStream_t s) {
+#define UOT_BL(D, RR)                                                                                          \
+  hipLaunchKernelGGL((k_batch_lse<T, D, RR>), dim3(blocks), dim3(kBlock), 0, s, items, n_items, cursor, offR, \
+                     offC, xr, totR, yc, totC, w, bc, c, side, ep)
+  if (R == 1) {
+    if (dim == 1) UOT_BL(1, 1); else if (dim == 2) UOT_BL(2, 1); else UOT_BL(3, 1);
+  } else if (R == 2) {
+    if (dim == 1) UOT_BL(1, 2); else if (dim == 2) UOT_BL(2, 2); else UOT_BL(3, 2);
+  } else {
+    if (dim == 1) UOT_BL(1, 4); else if (dim == 2) UOT_BL(2, 4); else UOT_BL(3, 4);
+  }
+#undef UOT_BL
+}
+
+void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const int32_t* pstart, int* cursors,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_control, dim3(ceil_div(B, kBlock)), dim3(kBlock), 0, s, c, bc, B, part, pstart, cursors);
+  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, c);
+}
+
+void launch_batch_init(BCtrl* bc, int B, Ctrl* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_init, dim3(ceil_div(B, kBlock)), dim3(kBlock), 0, s, bc, B, c);
+}
+
+void launch_set_int(int* p, int n, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, p, n, v);
+}
+
+template void launch_batch_lse<float>(int, int, int, const BItem*, int, int*, const int64_t*, const int64_t*,
+                                      const float*, int64_t, const float*, int64_t, const float*, const BCtrl*,
+                                      const Ctrl*, int, const EpiArgs<float>&, hipStream_t);
+template void launch_batch_lse<double>(int, int, int, const BItem*, int, int*, const int64_t*, const int64_t*,
+                                       const double*, int64_t, const double*, int64_t, const double*, const BCtrl*,
+                                       const Ctrl*, int, const EpiArgs<double>&, hipStream_t);
 
 }  // namespace uot

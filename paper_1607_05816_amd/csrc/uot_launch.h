@@ -67,4 +67,14 @@ template <typename T>
 void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, double eps, T* out,
                        hipStream_t s);
 
+void launch_probe(int which, float* out, int blocks, int iters, hipStream_t s);
+template <typename T>
+void launch_batch_lse(int dim, int R, int blocks, const BItem* items, int n_items, int* cursor, const int64_t* offR,
+                      const int64_t* offC, const T* xr, int64_t totR, const T* yc, int64_t totC, const T* w,
+                      const BCtrl* bc, const Ctrl* c, int side, const EpiArgs<T>& ep, hipStream_t s);
+void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const int32_t* pstart, int* cursors,
+                          hipStream_t s);
+void launch_batch_init(BCtrl* bc, int B, Ctrl* c, hipStream_t s);
+void launch_set_int(int* p, int n, int v, hipStream_t s);
+
 }  // namespace uot

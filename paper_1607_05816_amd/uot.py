@@ -43,7 +43,8 @@ class UotProblem(ctypes.Structure):
 class UotParams(ctypes.Structure):
     _fields_ = [("eps", c_dbl), ("eps0", c_dbl), ("eps_stages", c_i32), ("iters_per_stage", c_i32),
                 ("tol", c_dbl), ("max_iter", c_i64), ("check_every", c_i32), ("use_graph", c_i32),
-                ("v0", c_vp), ("res_hist", c_vp)]
+                ("v0", c_vp), ("res_hist", c_vp), ("kernel_ms", ctypes.POINTER(c_dbl)),
+                ("kernel_launches", ctypes.POINTER(c_i64))]
 
 
 class UotResult(ctypes.Structure):
@@ -59,6 +60,19 @@ class UotObjectiveValues(ctypes.Structure):
 class UotBaryProblem(ctypes.Structure):
     _fields_ = [("dtype", c_i32), ("n", c_i32), ("geom", UotGeom), ("p", c_vp),
                 ("alpha", ctypes.POINTER(c_dbl)), ("dx", c_vp), ("dy", c_vp), ("F1", UotDiv), ("F2", UotDiv)]
+
+
+class UotBatchProblem(ctypes.Structure):
+    _fields_ = [("dtype", c_i32), ("dim", c_i32), ("B", c_i64), ("offN", ctypes.POINTER(c_i64)),
+                ("offM", ctypes.POINTER(c_i64)), ("x", c_vp), ("y", c_vp), ("p", c_vp), ("q", c_vp),
+                ("dx", c_vp), ("dy", c_vp), ("F1", UotDiv), ("F2", UotDiv)]
+
+
+class UotBatchResult(ctypes.Structure):
+    _fields_ = [("iters", ctypes.POINTER(c_i64)), ("residual", ctypes.POINTER(c_dbl)),
+                ("latency_ms", ctypes.POINTER(c_dbl)), ("status", ctypes.POINTER(c_i32)), ("iters_max", c_i64),
+                ("n_converged", c_i64), ("elapsed_ms", c_dbl), ("tile_rows", c_i32), ("blocks_per_cu", c_i32),
+                ("tune_ms", c_dbl)]
 
 
 _lib = None
@@ -88,6 +102,12 @@ def lib():
         "uot_bary_workspace_size": (c_i32, [P(UotBaryProblem), P(ctypes.c_size_t)]),
         "uot_barycenter": (c_i32, [c_vp, P(UotBaryProblem), P(UotParams), c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t,
                                    P(UotResult)]),
+        "uot_time_half_step": (c_i32, [c_vp, P(UotProblem), c_dbl, c_vp, c_i32, P(c_dbl), P(c_i32), c_vp,
+                                       ctypes.c_size_t]),
+        "uot_probe_rates": (c_i32, [c_vp, P(c_dbl), P(c_dbl)]),
+        "uot_batch_workspace_size": (c_i32, [P(UotBatchProblem), P(ctypes.c_size_t)]),
+        "uot_solve_batched": (c_i32, [c_vp, P(UotBatchProblem), P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t,
+                                      P(UotBatchResult)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -266,13 +286,16 @@ def grid_problem(shape: Sequence[int], h: Sequence[float], p, q, dx, dy, F1: Div
 
 
 def params(eps, tol=1e-6, max_iter=10000, eps0=None, eps_stages=10, iters_per_stage=100, check_every=50,
-           use_graph=True, v0=None, res_hist=None) -> UotParams:
+           use_graph=True, v0=None, res_hist=None, kernel_ms=None, kernel_launches=None) -> UotParams:
     return UotParams(float(eps), float(eps0 or 0.0), int(eps_stages if eps0 else 0), int(iters_per_stage),
-                     float(tol), int(max_iter), int(check_every), int(bool(use_graph)), _ptr(v0), _ptr(res_hist))
+                     float(tol), int(max_iter), int(check_every), int(bool(use_graph)), _ptr(v0), _ptr(res_hist),
+                     kernel_ms, kernel_launches)
 
 
-def solve(prob: Problem, eps, ctx: Optional[Context] = None, v0=None, record=False, **kw):
-    """Scaling iterations until residual <= tol.  Returns (u, v, info)."""
+def solve(prob: Problem, eps, ctx: Optional[Context] = None, v0=None, record=False, time_kernels=False, **kw):
+    """Scaling iterations until residual <= tol.  Returns (u, v, info).
+    time_kernels: run without graphs and report per-class kernel times
+    (HIP events around every launch) in info["kernel_ms"] / ["kernel_launches"]."""
     ctx = ctx or default_context()
     dev = prob.p.device
     u = torch.empty(prob.N, dtype=prob.dtype, device=dev)
@@ -281,7 +304,9 @@ def solve(prob: Problem, eps, ctx: Optional[Context] = None, v0=None, record=Fal
     hist = torch.full((max_iter,), float("nan"), dtype=torch.float64, device=dev) if record else None
     if v0 is not None:
         _dev(v0, prob.dtype, prob.M, "v0")
-    pr = params(eps, v0=v0, res_hist=hist, **kw)
+    kms = (c_dbl * 4)() if time_kernels else None
+    kcnt = (c_i64 * 4)() if time_kernels else None
+    pr = params(eps, v0=v0, res_hist=hist, kernel_ms=kms, kernel_launches=kcnt, **kw)
     res = UotResult()
     ws = prob.workspace()
     code = lib().uot_solve(ctx.handle, ctypes.byref(prob.c), ctypes.byref(pr), _ptr(u), _ptr(v), _ptr(ws),
@@ -291,6 +316,9 @@ def solve(prob: Problem, eps, ctx: Optional[Context] = None, v0=None, record=Fal
                 converged=(code == UOT_OK))
     if record:
         info["res_hist"] = hist[:res.iters].cpu()
+    if time_kernels:
+        info["kernel_ms"] = [kms[k] for k in range(4)]
+        info["kernel_launches"] = [kcnt[k] for k in range(4)]
     return u, v, info
 
 
@@ -362,3 +390,97 @@ def barycenter(shape, h, p, alpha, dx, dy, F1: Div, F2: Div, eps, ctx: Optional[
     if record:
         info["res_hist"] = hist[:res.iters].cpu()
     return u, v, logh, info
+
+
+def time_half_step(prob: Problem, eps, v, reps=50, ctx: Optional[Context] = None):
+    """Average ms of each Gibbs-product kernel of one X half-step (HIP events)."""
+    ctx = ctx or default_context()
+    _dev(v, prob.dtype, prob.M, "v")
+    ms = (c_dbl * 4)()
+    nk = c_i32()
+    ws = prob.workspace()
+    _check(lib().uot_time_half_step(ctx.handle, ctypes.byref(prob.c), float(eps), _ptr(v), int(reps), ms,
+                                    ctypes.byref(nk), _ptr(ws), ws.numel()), "uot_time_half_step", False)
+    return [ms[k] for k in range(nk.value)]
+
+
+def probe_rates(ctx: Optional[Context] = None):
+    """(exp2 results/s, fp32 add results/s) measured on the current device."""
+    ctx = ctx or default_context()
+    e, a = c_dbl(), c_dbl()
+    _check(lib().uot_probe_rates(ctx.handle, ctypes.byref(e), ctypes.byref(a)), "uot_probe_rates", False)
+    return e.value, a.value
+
+
+class BatchProblem:
+    """B independent point-cloud problems of uneven sizes, concatenated.
+
+    xs, ys: lists of (N_b, d) / (M_b, d) tensors (or one concatenated tensor
+    each with sizes Ns / Ms); p, q, dx, dy likewise concatenated."""
+
+    def __init__(self, Ns, Ms, x, y, p, q, dx, dy, F1: Div, F2: Div):
+        import numpy as np
+        dtype = p.dtype
+        self.B = len(Ns)
+        self.offN = np.zeros(self.B + 1, dtype=np.int64)
+        self.offM = np.zeros(self.B + 1, dtype=np.int64)
+        self.offN[1:] = np.cumsum(np.asarray(Ns, dtype=np.int64))
+        self.offM[1:] = np.cumsum(np.asarray(Ms, dtype=np.int64))
+        totN, totM = int(self.offN[-1]), int(self.offM[-1])
+        if x.shape[0] == totN:
+            x = x.t()
+        if y.shape[0] == totM:
+            y = y.t()
+        self.x = _dev(x.contiguous(), dtype, name="x")
+        self.y = _dev(y.contiguous(), dtype, name="y")
+        d = self.x.shape[0]
+        for t, n, nm in ((p, totN, "p"), (q, totM, "q"), (dx, totN, "dx"), (dy, totM, "dy")):
+            _dev(t, dtype, n, nm)
+        self.p, self.q, self.dx, self.dy = p, q, dx, dy
+        self.dtype = dtype
+        self.totN, self.totM = totN, totM
+        self._offN_c = self.offN.ctypes.data_as(ctypes.POINTER(c_i64))
+        self._offM_c = self.offM.ctypes.data_as(ctypes.POINTER(c_i64))
+        self.c = UotBatchProblem(_dt(p), d, self.B, self._offN_c, self._offM_c, _ptr(self.x), _ptr(self.y), _ptr(p),
+                                 _ptr(q), _ptr(dx), _ptr(dy), F1.c(), F2.c())
+        self._ws = None
+
+    def workspace(self):
+        if self._ws is None:
+            n = ctypes.c_size_t()
+            _check(lib().uot_batch_workspace_size(ctypes.byref(self.c), ctypes.byref(n)), "uot_batch_workspace_size",
+                   False)
+            self._ws = workspace(n.value, self.p.device)
+        return self._ws
+
+
+def solve_batched(bp: BatchProblem, eps, ctx: Optional[Context] = None, v0=None, time_kernels=False, **kw):
+    """Solve every problem of the batch.  Returns (u, v, info) with u, v
+    concatenated and per-problem arrays in info."""
+    import numpy as np
+    ctx = ctx or default_context()
+    dev = bp.p.device
+    u = torch.empty(bp.totN, dtype=bp.dtype, device=dev)
+    v = torch.empty(bp.totM, dtype=bp.dtype, device=dev)
+    if v0 is not None:
+        _dev(v0, bp.dtype, bp.totM, "v0")
+    kms = (c_dbl * 4)() if time_kernels else None
+    kcnt = (c_i64 * 4)() if time_kernels else None
+    pr = params(eps, v0=v0, kernel_ms=kms, kernel_launches=kcnt, **kw)
+    it = np.zeros(bp.B, dtype=np.int64)
+    rs = np.zeros(bp.B, dtype=np.float64)
+    lat = np.zeros(bp.B, dtype=np.float64)
+    st = np.zeros(bp.B, dtype=np.int32)
+    res = UotBatchResult(it.ctypes.data_as(ctypes.POINTER(c_i64)), rs.ctypes.data_as(ctypes.POINTER(c_dbl)),
+                         lat.ctypes.data_as(ctypes.POINTER(c_dbl)), st.ctypes.data_as(ctypes.POINTER(c_i32)))
+    ws = bp.workspace()
+    code = lib().uot_solve_batched(ctx.handle, ctypes.byref(bp.c), ctypes.byref(pr), _ptr(u), _ptr(v), _ptr(ws),
+                                   ws.numel(), ctypes.byref(res))
+    _check(code, "uot_solve_batched")
+    info = dict(iters=it, residual=rs, latency_ms=lat, status=st, iters_max=res.iters_max,
+                n_converged=res.n_converged, elapsed_ms=res.elapsed_ms, tile_rows=res.tile_rows,
+                blocks_per_cu=res.blocks_per_cu, tune_ms=res.tune_ms, converged=(code == UOT_OK))
+    if time_kernels:
+        info["kernel_ms"] = [kms[k] for k in range(4)]
+        info["kernel_launches"] = [kcnt[k] for k in range(4)]
+    return u, v, info

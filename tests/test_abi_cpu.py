@@ -47,8 +47,10 @@ _PROBE = r"""
 #define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
   S(uot_div) S(uot_geom) S(uot_problem) S(uot_params) S(uot_result) S(uot_objective_values) S(uot_bary_problem)
+  S(uot_batch_problem) S(uot_batch_result)
+  O(uot_batch_problem, F2) O(uot_batch_problem, dy) O(uot_batch_result, tune_ms) O(uot_batch_result, tile_rows)
   O(uot_geom, n) O(uot_geom, h) O(uot_problem, geom) O(uot_problem, F1) O(uot_problem, F2)
-  O(uot_params, v0) O(uot_params, res_hist) O(uot_params, check_every)
+  O(uot_params, v0) O(uot_params, res_hist) O(uot_params, check_every) O(uot_params, kernel_ms) O(uot_params, kernel_launches)
   O(uot_bary_problem, alpha) O(uot_bary_problem, F2) O(uot_result, elapsed_ms)
   return 0;
 }
@@ -68,7 +70,8 @@ def test_ctypes_layout_matches_c_header():
         c[k] = int(v)
     py = {"uot_div": uot.UotDiv, "uot_geom": uot.UotGeom, "uot_problem": uot.UotProblem,
           "uot_params": uot.UotParams, "uot_result": uot.UotResult,
-          "uot_objective_values": uot.UotObjectiveValues, "uot_bary_problem": uot.UotBaryProblem}
+          "uot_objective_values": uot.UotObjectiveValues, "uot_bary_problem": uot.UotBaryProblem,
+          "uot_batch_problem": uot.UotBatchProblem, "uot_batch_result": uot.UotBatchResult}
     for k, T in py.items():
         assert ctypes.sizeof(T) == c[k], k
     pyname = {"F1": "F1", "F2": "F2"}
@@ -135,3 +138,21 @@ def test_binding_has_no_cpu_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(mod, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         mod.lib()
+
+
+def test_batch_workspace_and_validation():
+    import numpy as np
+    L = uot.lib()
+    Ns = np.array([0, 64, 1000, 4096], dtype=np.int64)
+    Ms = np.array([0, 100, 3000, 3064], dtype=np.int64)
+    bp = uot.UotBatchProblem()
+    bp.dtype, bp.dim, bp.B = uot.UOT_F32, 2, 3
+    bp.offN = Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    bp.offM = Ms.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    n = ctypes.c_size_t()
+    assert L.uot_batch_workspace_size(ctypes.byref(bp), ctypes.byref(n)) == 0
+    assert n.value > 4 * 3 * (4096 + 3064)
+    bad = np.array([0, 64, 64, 100], dtype=np.int64)        # an empty problem
+    bp.offN = bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    assert L.uot_batch_workspace_size(ctypes.byref(bp), ctypes.byref(n)) == -1
+    assert b"N, M >= 1" in L.uot_last_error()
