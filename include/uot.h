@@ -137,6 +137,11 @@ typedef struct uot_params {
                             pass / dense LSE, [1] later passes / split merge +
                             epilogue, [2] control, [3] unused              */
   int64_t *kernel_launches; /* optional HOST array [4]: launches per class   */
+  int32_t grid_kernel;   /* grids: 0 default (= 1), 1 direct log-sum-exp
+                            passes, 2 tile-factored FP32 MFMA passes (FP32
+                            problems, axes with a multiple of 16 cells; other
+                            axes use direct passes)                        */
+  int32_t reserved;
 } uot_params;
 
 typedef struct uot_result {
@@ -177,6 +182,16 @@ int uot_workspace_size(const uot_problem *pb, size_t *bytes);
  * the final potentials (u may hold -inf where p = 0).  res: host struct. */
 int uot_solve(uot_ctx *ctx, const uot_problem *pb, const uot_params *pr,
               void *u, void *v, void *ws, size_t ws_bytes, uot_result *res);
+
+/* nb independent problems on one regular grid, solved together: p and q
+ * point to nb x size arrays (field k at offset k*size), dx and dy are shared
+ * (size), F1/F2/eps/schedule are shared.  u, v: device nb x size outputs.
+ * Every launch processes all fields; the residual of an iteration is the
+ * largest per-field residual, so the batch stops when every field has
+ * r <= tol.  pr->v0, if set, is an nb x size warm start. */
+int uot_fields_workspace_size(const uot_problem *pb, int nb, size_t *bytes);
+int uot_solve_fields(uot_ctx *ctx, const uot_problem *pb, int nb, const uot_params *pr,
+                     void *u, void *v, void *ws, size_t ws_bytes, uot_result *res);
 
 /* One half-step of (S) from a given state, for checking a single step.
  * side 0 (X half-step): S = log K(e^{v/eps} dy) with v = pot_in (M);
@@ -270,6 +285,61 @@ int uot_batch_workspace_size(const uot_batch_problem *pb, size_t *bytes);
 /* u: device offN[B], v: device offM[B] outputs (problem dtype). */
 int uot_solve_batched(uot_ctx *ctx, const uot_batch_problem *pb, const uot_params *pr,
                       void *u, void *v, void *ws, size_t ws_bytes, uot_batch_result *res);
+
+/* ---------------------------------------------------------------------------
+ * Warm-start network.  By Prop. "alternating" only v^(0) enters the iterates
+ * (the first X half-step overwrites u), so predicting v from the two input
+ * measures shortens the iteration while the plain iteration still decides
+ * the answer (a wrong prediction costs iterations, never accuracy).
+ * Net: 4-layer MLP n_in -> width -> width -> width -> n_out with ReLU hidden
+ * layers; every GEMM input (weights, activations) is BF16 (round to nearest
+ * even), accumulation FP32 on MFMA; FP32 master weights, Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8, bias-corrected).  Loss: mean squared error over the
+ * batch x n_out outputs.  Parameter layout of every parameter-sized array:
+ * W1 [width x n_in], b1, W2 [width x width], b2, W3, b3, W4 [n_out x width], b4.
+ * Sizes must be multiples of 8.  x: batch x n_in FP32 (normalised inside as
+ * in_scale * x + in_shift), targets/outputs batch x n_out FP32.
+ * ------------------------------------------------------------------------- */
+typedef struct uot_net {
+  int32_t n_in, width, n_out, reserved;
+  float in_scale, in_shift;
+  float *master;         /* device, FP32 parameters                         */
+  uint16_t *wbf16;       /* device, BF16 copy used by the GEMMs             */
+  float *adam_m;         /* device, Adam first moments (training only)      */
+  float *adam_v;         /* device, Adam second moments (training only)     */
+  int64_t step;          /* Adam step count, advanced by each train step    */
+} uot_net;
+
+int uot_net_param_count(const uot_net *net, int64_t *count);
+int uot_net_workspace_size(const uot_net *net, int64_t batch, size_t *bytes);
+/* refresh wbf16 from master */
+int uot_net_sync(uot_ctx *ctx, const uot_net *net);
+/* forward pass: y = net(x) */
+int uot_warmstart_infer(uot_ctx *ctx, const uot_net *net, const float *x, float *y,
+                        int64_t batch, void *ws, size_t ws_bytes);
+/* loss and its gradient w.r.t. the parameters (straight through the BF16
+ * rounding), without updating anything; grad is device, parameter-sized */
+int uot_net_grad(uot_ctx *ctx, const uot_net *net, const float *x, const float *target,
+                 int64_t batch, float *grad, double *loss, void *ws, size_t ws_bytes);
+/* one Adam step on a batch; *loss (optional) receives the batch loss */
+int uot_warmstart_train_step(uot_ctx *ctx, uot_net *net, const float *x, const float *target,
+                             int64_t batch, float lr, double *loss, void *ws, size_t ws_bytes);
+/* network input of nb grid pairs: average-pool p and q (nb x R x R) to r x r
+ * (R a multiple of r) and write x[b] = [log p_r, log q_r] (nb x 2 r^2) */
+int uot_warmstart_features(uot_ctx *ctx, const float *p, const float *q, int64_t nb,
+                           int R, int r, float *x);
+/* first barycentre estimate for warm starts: Table estimatebary (ii) (KL,
+ * lambda = F2->lambda) or (i) (equality) applied pointwise to the input
+ * densities p (n x size, FP32) with weights alpha (HOST, n); h: size */
+int uot_bary_estimate(uot_ctx *ctx, const float *p, int n, int64_t size, const double *alpha,
+                      double eps, const uot_div *F2, float *h);
+/* bilinear upsampling of nb cell-centred r x r fields to R x R */
+int uot_grid_upsample(uot_ctx *ctx, const float *y, int64_t nb, int r, int R, float *out);
+/* the MFMA BF16 GEMM of the network, exposed for checking:
+ * C[M x N] = op(A) op(B), op(A)[m][k] = ta ? A[k*lda+m] : A[m*lda+k],
+ * op(B)[k][n] = tb ? B[n*ldb+k] : B[k*ldb+n]; A, B BF16 bits, C FP32 */
+int uot_gemm_bf16(uot_ctx *ctx, int ta, int tb, int M, int N, int K, const uint16_t *A,
+                  int64_t lda, const uint16_t *B, int64_t ldb, float *C, int64_t ldc);
 
 /* ---------------------------------------------------------------------------
  * Measurement helpers (roofline evidence; not part of the iteration).

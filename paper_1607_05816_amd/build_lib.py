@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libuot.so")
-SOURCES = ["uot_kernels.hip", "uot_api.hip"]
+SOURCES = ["uot_kernels.hip", "uot_api.hip", "uot_net.hip"]
 ARCH = os.environ.get("UOT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -21,7 +21,7 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
+def build(verbose: bool = False, jobs: int = 3) -> str:
     """Compile each source to an object, then link libuot.so; returns its path."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []

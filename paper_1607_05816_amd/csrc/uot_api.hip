@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <type_traits>
 #include <functional>
 #include <map>
 #include <string>
@@ -19,29 +20,17 @@
 
 using namespace uot;
 
-struct uot_ctx {
-  hipStream_t user = nullptr;   // caller's stream
-  hipStream_t work = nullptr;   // library stream (capture-capable)
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  Ctrl* pinned = nullptr;       // host mirror of the control block
-  int device = 0;
-  std::map<std::string, std::pair<int, int>> batch_tuned;   // batch signature -> (R, blocks per CU)
-};
+#include "uot_ctx.h"
 
-namespace {
-
+namespace uot {
 thread_local std::string g_err;
-
 int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
 }
+}  // namespace uot
 
-#define HIP_TRY(expr)                                                                       \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess) return fail(UOT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+namespace {
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -134,17 +123,21 @@ struct Plan {
   int splits[2] = {1, 1};
   int64_t cps[2] = {0, 0};
   int nparts_x = 0;      // residual partials written by the X epilogue
+  int gk = 1;            // grid passes: 1 direct log-sum-exp, 2 tile-factored MFMA (FP32, axes % 16 == 0)
   // workspace offsets
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
       o_gcost, o_obj, o_scal, total;
   int64_t obj_doubles = 0;
 };
 
+bool use_tf(const Plan& P, int axis) { return P.gk == 2 && P.dtype == UOT_F32 && P.n[axis] % 16 == 0; }
+
 int grid_final_parts(const Plan& P) {
   const int64_t nb = P.nb;
-  if (P.dim == 1) return grid_contig_parts<float>((int)P.n[0], nb);
-  if (P.dim == 2) return grid_strided_parts<float>((int)P.n[0], nb, P.n[1]);
-  return grid_strided_parts<float>((int)P.n[0], nb, P.n[1] * P.n[2]);
+  if (P.dim == 1)
+    return use_tf(P, 0) ? grid_tf_parts((int)P.n[0], nb, 1, false) : grid_contig_parts<float>((int)P.n[0], nb);
+  const int64_t B = P.dim == 2 ? P.n[1] : P.n[1] * P.n[2];
+  return use_tf(P, 0) ? grid_tf_parts((int)P.n[0], nb, B, true) : grid_strided_parts<float>((int)P.n[0], nb, B);
 }
 
 void dense_config(Plan& P, int side) {
@@ -164,8 +157,10 @@ void dense_config(Plan& P, int side) {
   P.cps[side] = cps;
 }
 
-int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst) {
+int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_kernel = 0) {
   if (dtype != UOT_F32 && dtype != UOT_F64) return fail(UOT_E_INVALID, "dtype must be UOT_F32 or UOT_F64");
+  if (grid_kernel < 0 || grid_kernel > 2) return fail(UOT_E_INVALID, "grid_kernel must be 0, 1 or 2");
+  P.gk = grid_kernel == 0 ? 1 : grid_kernel;
   P.dtype = dtype;
   P.esz = dtype == UOT_F32 ? 4 : 8;
   P.geom = g.kind;
@@ -203,7 +198,7 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst) {
   };
   P.o_ctrl = take(sizeof(Ctrl));
   P.o_logp = take(e * nb * P.N);
-  P.o_logq = take(e * P.M);
+  P.o_logq = take(e * nb * P.M);
   P.o_logdx = take(e * P.N);
   P.o_logdy = take(e * P.M);
   P.o_wu = take(e * nb * P.N);
@@ -265,18 +260,6 @@ Ctrl make_ctrl(double eps, double eps0, int stages, int ips, double tol, int64_t
   return c;
 }
 
-// stream handshake: work waits for the caller's stream, and vice versa at the end
-int begin(uot_ctx* ctx) {
-  HIP_TRY(hipEventRecord(ctx->ev_in, ctx->user));
-  HIP_TRY(hipStreamWaitEvent(ctx->work, ctx->ev_in, 0));
-  return UOT_OK;
-}
-
-int finish(uot_ctx* ctx) {
-  HIP_TRY(hipEventRecord(ctx->ev_out, ctx->work));
-  HIP_TRY(hipStreamWaitEvent(ctx->user, ctx->ev_out, 0));
-  return UOT_OK;
-}
 
 // ---------------------------------------------------------------------------
 // Gibbs-product chains
@@ -314,6 +297,31 @@ template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
 }
 
 // separable grid product on nb fields: input w (log2 units), per-axis tables
+// (direct passes) or the tile-factored MFMA pass where the plan selects it
+template <typename T>
+void contig_pass(const Plan& P, int axis, const T* w, int64_t A, T* const* tabs, int side, Ctrl* c,
+                 const EpiArgs<T>& ep, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (use_tf(P, axis)) {
+      timed(0, [&] { launch_grid_tf(w, A, (int)P.n[axis], 1, false, P.h[axis], side, c, ep, s); });
+      return;
+    }
+  }
+  timed(0, [&] { launch_grid_contig<T>(w, A, (int)P.n[axis], tabs[axis], side, c, ep, s); });
+}
+
+template <typename T>
+void strided_pass(const Plan& P, int axis, const T* w, int64_t A, int64_t B, T* const* tabs, int side, Ctrl* c,
+                  const EpiArgs<T>& ep, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (use_tf(P, axis)) {
+      timed(1, [&] { launch_grid_tf(w, A, (int)P.n[axis], B, true, P.h[axis], side, c, ep, s); });
+      return;
+    }
+  }
+  timed(1, [&] { launch_grid_strided<T>(w, A, (int)P.n[axis], B, tabs[axis], side, c, ep, s); });
+}
+
 template <typename T>
 void grid_chain(const Plan& P, const T* w, T* const* tabs, int side, Ctrl* c, const EpiArgs<T>& ep, T* tmp1,
                 T* tmp2, hipStream_t s) {
@@ -321,18 +329,18 @@ void grid_chain(const Plan& P, const T* w, T* const* tabs, int side, Ctrl* c, co
   EpiArgs<T> raw{};
   raw.mode = EPI_RAW;
   if (P.dim == 1) {
-    timed(0, [&] { launch_grid_contig<T>(w, nb, (int)P.n[0], tabs[0], side, c, ep, s); });
+    contig_pass<T>(P, 0, w, nb, tabs, side, c, ep, s);
   } else if (P.dim == 2) {
     raw.out = tmp1;
-    timed(0, [&] { launch_grid_contig<T>(w, nb * P.n[0], (int)P.n[1], tabs[1], side, c, raw, s); });
-    timed(1, [&] { launch_grid_strided<T>(tmp1, nb, (int)P.n[0], P.n[1], tabs[0], side, c, ep, s); });
+    contig_pass<T>(P, 1, w, nb * P.n[0], tabs, side, c, raw, s);
+    strided_pass<T>(P, 0, tmp1, nb, P.n[1], tabs, side, c, ep, s);
   } else {
     raw.out = tmp1;
-    timed(0, [&] { launch_grid_contig<T>(w, nb * P.n[0] * P.n[1], (int)P.n[2], tabs[2], side, c, raw, s); });
+    contig_pass<T>(P, 2, w, nb * P.n[0] * P.n[1], tabs, side, c, raw, s);
     EpiArgs<T> raw2 = raw;
     raw2.out = tmp2;
-    timed(1, [&] { launch_grid_strided<T>(tmp1, nb * P.n[0], (int)P.n[1], P.n[2], tabs[1], side, c, raw2, s); });
-    timed(1, [&] { launch_grid_strided<T>(tmp2, nb, (int)P.n[0], P.n[1] * P.n[2], tabs[0], side, c, ep, s); });
+    strided_pass<T>(P, 1, tmp1, nb * P.n[0], P.n[2], tabs, side, c, raw2, s);
+    strided_pass<T>(P, 0, tmp2, nb, P.n[1] * P.n[2], tabs, side, c, ep, s);
   }
 }
 
@@ -458,10 +466,10 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
 
 template <typename T>
 int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* v, char* ws, size_t wsb,
-            uot_result* res) {
+            uot_result* res, int nb = 1) {
   Plan P;
   const bool anneal = pr->eps0 > pr->eps && pr->eps_stages > 0 && pr->iters_per_stage > 0;
-  int rc = make_plan(P, pb->dtype, pb->geom, 1, anneal ? pr->eps_stages + 1 : 1);
+  int rc = make_plan(P, pb->dtype, pb->geom, nb, anneal ? pr->eps_stages + 1 : 1, pr->grid_kernel);
   if (rc) return rc;
   if ((rc = check_ws(P, ws, wsb))) return rc;
   if (!u || !v) return fail(UOT_E_INVALID, "u and v output buffers are required");
@@ -470,18 +478,19 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   Bufs<T> B = carve<T>(P, ws);
   Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, pr->tol, pr->max_iter);
   launch_ctrl_init(B.ctrl, init, s);
-  launch_log<T>(static_cast<const T*>(pb->p), B.logp, P.N, 1, s);
-  launch_log<T>(static_cast<const T*>(pb->q), B.logq, P.M, 1, s);
+  launch_log<T>(static_cast<const T*>(pb->p), B.logp, nb * P.N, 1, s);
+  launch_log<T>(static_cast<const T*>(pb->q), B.logq, nb * P.M, 1, s);
   launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, P.N, 0, s);
   launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
   if (P.geom == UOT_GEOM_GRID)
     for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, P.nst, s);
-  launch_init_pot<T>(nullptr, B.logdx, u, nullptr, P.N, P.N, B.ctrl, 0, s);
-  launch_init_pot<T>(static_cast<const T*>(pr->v0), B.logdy, v, B.wv, P.M, P.M, B.ctrl, 0, s);
+  launch_init_pot<T>(nullptr, B.logdx, u, nullptr, nb * P.N, P.N, B.ctrl, 0, s);
+  launch_init_pot<T>(static_cast<const T*>(pr->v0), B.logdy, v, B.wv, nb * P.M, P.M, B.ctrl, 0, s);
   HIP_TRY(hipGetLastError());
+  const int nfields = nb > 1 ? nb : 0;
   auto iteration = [&]() {
     half_step<T>(P, *pb, 0, B, u, nullptr, true, s);
-    timed(2, [&] { launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s); });
+    timed(2, [&] { launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s, nfields); });
     half_step<T>(P, *pb, 1, B, v, nullptr, false, s);
   };
   rc = run_loop(ctx, B.ctrl, pr, iteration, res);
@@ -633,7 +642,7 @@ int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u,
            uot_result* res) {
   Plan P;
   const bool anneal = pr->eps0 > pr->eps && pr->eps_stages > 0 && pr->iters_per_stage > 0;
-  int rc = make_plan(P, pb->dtype, pb->geom, pb->n, anneal ? pr->eps_stages + 1 : 1);
+  int rc = make_plan(P, pb->dtype, pb->geom, pb->n, anneal ? pr->eps_stages + 1 : 1, pr->grid_kernel);
   if (rc) return rc;
   if ((rc = check_ws(P, ws, wsb))) return rc;
   if (!u || !v) return fail(UOT_E_INVALID, "u and v output buffers are required");
@@ -1125,6 +1134,32 @@ int uot_solve(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, void* u
   if (pb->dtype == UOT_F32)
     return solve_t<float>(ctx, pb, pr, static_cast<float*>(u), static_cast<float*>(v), static_cast<char*>(ws), wsb, res);
   return solve_t<double>(ctx, pb, pr, static_cast<double*>(u), static_cast<double*>(v), static_cast<char*>(ws), wsb, res);
+}
+
+int uot_fields_workspace_size(const uot_problem* pb, int nb, size_t* bytes) {
+  if (!pb || !bytes) return fail(UOT_E_INVALID, "NULL argument");
+  if (pb->geom.kind != UOT_GEOM_GRID) return fail(UOT_E_UNSUPPORTED, "field batches need a grid geometry");
+  if (nb < 1) return fail(UOT_E_INVALID, "nb must be >= 1");
+  Plan P;
+  int rc = make_plan(P, pb->dtype, pb->geom, nb, kMaxStages + 1);
+  if (rc) return rc;
+  *bytes = P.total;
+  return UOT_OK;
+}
+
+int uot_solve_fields(uot_ctx* ctx, const uot_problem* pb, int nb, const uot_params* pr, void* u, void* v, void* ws,
+                     size_t wsb, uot_result* res) {
+  if (!ctx || !res) return fail(UOT_E_INVALID, "ctx and res are required");
+  int rc = validate_problem(pb);
+  if (rc) return rc;
+  if ((rc = validate_params(pr))) return rc;
+  if (pb->geom.kind != UOT_GEOM_GRID) return fail(UOT_E_UNSUPPORTED, "field batches need a grid geometry");
+  if (nb < 1) return fail(UOT_E_INVALID, "nb must be >= 1");
+  if (pb->dtype == UOT_F32)
+    return solve_t<float>(ctx, pb, pr, static_cast<float*>(u), static_cast<float*>(v), static_cast<char*>(ws), wsb,
+                          res, nb);
+  return solve_t<double>(ctx, pb, pr, static_cast<double*>(u), static_cast<double*>(v), static_cast<char*>(ws), wsb,
+                         res, nb);
 }
 
 int uot_half_step(uot_ctx* ctx, const uot_problem* pb, double eps, int side, const void* pot_in, void* pot_io,

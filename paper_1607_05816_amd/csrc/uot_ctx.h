@@ -1,0 +1,47 @@
+// Library context and shared host helpers of the C ABI implementation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <utility>
+
+#include "../../include/uot.h"
+#include "uot_device.h"
+
+struct uot_ctx {
+  hipStream_t user = nullptr;   // caller's stream
+  hipStream_t work = nullptr;   // library stream (capture-capable)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  uot::Ctrl* pinned = nullptr;  // host mirror of the control block
+  int device = 0;
+  std::map<std::string, std::pair<int, int>> batch_tuned;   // batch signature -> (R, blocks per CU)
+};
+
+namespace uot {
+
+extern thread_local std::string g_err;
+int fail(int code, const std::string& msg);
+
+#define HIP_TRY(expr)                                                                                  \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess) return ::uot::fail(UOT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// stream handshake: the library stream waits for the caller's stream at the
+// start of a call, and the caller's stream waits for the library's at the end
+inline int begin(uot_ctx* ctx) {
+  HIP_TRY(hipEventRecord(ctx->ev_in, ctx->user));
+  HIP_TRY(hipStreamWaitEvent(ctx->work, ctx->ev_in, 0));
+  return UOT_OK;
+}
+
+inline int finish(uot_ctx* ctx) {
+  HIP_TRY(hipEventRecord(ctx->ev_out, ctx->work));
+  HIP_TRY(hipStreamWaitEvent(ctx->user, ctx->ev_out, 0));
+  return UOT_OK;
+}
+
+}  // namespace uot

@@ -390,30 +390,54 @@ __global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, 
 // residual partials, count the iteration, pick the next eps, set stop flags.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_control(Ctrl* __restrict__ c, const ResPart* __restrict__ part,
-                                                     int nparts, double* __restrict__ hist) {
+                                                     int nparts, double* __restrict__ hist, int nfields) {
   if (c->stop) {
     if (threadIdx.x == 0) c->yskip = 1;
     return;
   }
-  double m = -__builtin_inf(), den = 0.0, num = 0.0;
-  for (int k = threadIdx.x; k < nparts; k += kBlock) res_merge<double>(m, den, num, part[k].m, part[k].den, part[k].num);
+  // nfields == 0: one residual over all partials; nfields > 0: the partials
+  // form nfields equal contiguous ranges (one per field) and r is the largest
+  // per-field residual
   __shared__ double sm[kBlock][3];
-  sm[threadIdx.x][0] = m;
-  sm[threadIdx.x][1] = den;
-  sm[threadIdx.x][2] = num;
-  __syncthreads();
-  for (int off = kBlock / 2; off >= 1; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      double M = sm[threadIdx.x][0], D = sm[threadIdx.x][1], U = sm[threadIdx.x][2];
-      res_merge<double>(M, D, U, sm[threadIdx.x + off][0], sm[threadIdx.x + off][1], sm[threadIdx.x + off][2]);
-      sm[threadIdx.x][0] = M;
-      sm[threadIdx.x][1] = D;
-      sm[threadIdx.x][2] = U;
+  __shared__ double smax[kBlock];
+  double rmax = -1.0;
+  if (nfields > 0) {
+    const int per = nparts / nfields;
+    for (int f = threadIdx.x; f < nfields; f += kBlock) {
+      double m = -__builtin_inf(), den = 0.0, num = 0.0;
+      for (int k = f * per; k < (f + 1) * per; ++k) res_merge<double>(m, den, num, part[k].m, part[k].den, part[k].num);
+      const double rf = num / den;
+      rmax = (rf != rf || rmax != rmax) ? rf : (rf > rmax ? rf : rmax);
     }
+    smax[threadIdx.x] = rmax;
     __syncthreads();
+    for (int off = kBlock / 2; off >= 1; off >>= 1) {
+      if ((int)threadIdx.x < off) {
+        const double a = smax[threadIdx.x], b = smax[threadIdx.x + off];
+        smax[threadIdx.x] = (a != a || b != b) ? (a != a ? a : b) : (a > b ? a : b);
+      }
+      __syncthreads();
+    }
+  } else {
+    double m = -__builtin_inf(), den = 0.0, num = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kBlock) res_merge<double>(m, den, num, part[k].m, part[k].den, part[k].num);
+    sm[threadIdx.x][0] = m;
+    sm[threadIdx.x][1] = den;
+    sm[threadIdx.x][2] = num;
+    __syncthreads();
+    for (int off = kBlock / 2; off >= 1; off >>= 1) {
+      if ((int)threadIdx.x < off) {
+        double M = sm[threadIdx.x][0], D = sm[threadIdx.x][1], U = sm[threadIdx.x][2];
+        res_merge<double>(M, D, U, sm[threadIdx.x + off][0], sm[threadIdx.x + off][1], sm[threadIdx.x + off][2]);
+        sm[threadIdx.x][0] = M;
+        sm[threadIdx.x][1] = D;
+        sm[threadIdx.x][2] = U;
+      }
+      __syncthreads();
+    }
   }
   if (threadIdx.x != 0) return;
-  const double r = sm[0][2] / sm[0][1];
+  const double r = nfields > 0 ? smax[0] : sm[0][2] / sm[0][1];
   const int64_t l = c->iter;
   if (hist) hist[l] = r;
   c->res = r;
@@ -733,8 +757,8 @@ void launch_dense_epi(const T* pm, const T* ps, int nsplit, int64_t Nr, int side
   hipLaunchKernelGGL(k_dense_epi<T>, dim3(ceil_div(Nr, kBlock)), dim3(kBlock), 0, s, pm, ps, nsplit, Nr, side, c, ep);
 }
 
-void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, c, part, nparts, hist);
+void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s, int nfields) {
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, c, part, nparts, hist, nfields);
 }
 
 void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t s) {
@@ -1041,5 +1065,153 @@ template void launch_batch_lse<float>(int, int, int, const BItem*, int, int*, co
 template void launch_batch_lse<double>(int, int, int, const BItem*, int, int*, const int64_t*, const int64_t*,
                                        const double*, int64_t, const double*, int64_t, const double*, const BCtrl*,
                                        const Ctrl*, int, const EpiArgs<double>&, hipStream_t);
+
+}  // namespace uot
+
+// ---------------------------------------------------------------------------
+// Tile-factored separable pass on FP32 MFMA.  For output tile I and tap tile J
+// of 16 cells each (centres cI, cJ, offsets e = i - cI, f = j - cJ, D = cI -
+// cJ, all in cells) the 1-D kernel g(i - j) = -c (i - j)^2 (c = h^2 log2(e) /
+// eps) splits exactly as
+//   g = [-c e (e + 2D)] + [-c f (f - 2D)] - c D^2 + 2 c e f,
+// so  sum_j 2^{g + w_j} = 2^{-c e (e+2D) - c D^2 + m} * sum_j Khat[e][f] E_j,
+//   Khat[e][f] = 2^{2 c e f}  (one 16 x 16 matrix, |2 c e f| <= 2 c 7.5^2),
+//   E_j = 2^{w_j - c f (f - 2D) - m},  m = max_j (w_j - c f (f - 2D)),
+// and the inner sums of 16 lines at once are one 16x16x16 FP32 MFMA product.
+// The J tiles of an output are combined by an online log-sum-exp.  Exact up
+// to FP32 rounding; exp2 count per output: 16/16 (E) + 2 per J tile instead of
+// 16 per J tile.  Requires n % 16 == 0.
+//   STRIDED = false: in[a][j], lines a (16 per group);  out[a][i]
+//   STRIDED = true : in[a][j][b], lines (a, b), 16 consecutive b per group
+// grid = (n/16 output tiles, line groups (y, z)), 4 waves split the J tiles.
+// ---------------------------------------------------------------------------
+namespace uot {
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+template <bool STRIDED>
+__global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in, int n, int64_t A, int64_t B,
+                                                     double h, int side, const Ctrl* __restrict__ c,
+                                                     EpiArgs<float> ep) {
+  if (skip_side(c, side)) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int q = lane >> 4, li = lane & 15;
+  const float cc = float(h * h * kLog2e / (side == 0 ? c->eps_x : c->eps_y));
+  // line group -> 16 lines; lane's line is li
+  const int64_t grp = (int64_t)blockIdx.z * gridDim.y + blockIdx.y;
+  int64_t a, bb;
+  bool valid;
+  if (STRIDED) {
+    const int64_t gpa = (B + 15) / 16;     // groups per a
+    a = grp / gpa;
+    bb = (grp % gpa) * 16 + li;
+    valid = (a < A) && (bb < B);
+  } else {
+    a = grp * 16 + li;
+    bb = 0;
+    valid = a < A;
+  }
+  const int64_t base = valid ? (STRIDED ? a * (int64_t)n * B + bb : a * (int64_t)n) : 0;
+  const int64_t tstride = STRIDED ? B : 1;
+  const int I0 = blockIdx.x * 16;
+  // Khat as MFMA A operands: k-step s -> Khat[i = li][k = 4 s + q]
+  float kh[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const float e = float(li) - 7.5f, f = float(4 * s + q) - 7.5f;
+    kh[s] = __builtin_amdgcn_exp2f(2.f * cc * e * f);
+  }
+  // running LSE of the 4 outputs i = 4q + r of this lane's line li... (D layout)
+  float M[4], S[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    M[r] = -__builtin_inff();
+    S[r] = 0.f;
+  }
+  const int nt = n / 16;
+  for (int jt = wv; jt < nt; jt += 4) {
+    const int J0 = jt * 16;
+    const float D = float(I0 - J0);
+    // column factors for taps b = 4 s + q of this lane's line
+    float beta[4];
+    float mloc = -__builtin_inff();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float f = float(4 * s + q) - 7.5f;
+      const float w = valid ? in[base + (int64_t)(J0 + 4 * s + q) * tstride] : -__builtin_inff();
+      beta[s] = w - cc * (f * (f - 2.f * D));
+      mloc = fmaxf(mloc, beta[s]);
+    }
+    // max over the 16 taps of the line: the four lane groups q share a line
+    mloc = fmaxf(mloc, __shfl_xor(mloc, 16, 64));
+    mloc = fmaxf(mloc, __shfl_xor(mloc, 32, 64));
+    const float msh = (mloc == -__builtin_inff()) ? 0.f : mloc;
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float E = __builtin_amdgcn_exp2f(beta[s] - msh);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(kh[s], E, acc, 0, 0, 0);
+    }
+    // acc[r] = sum_f Khat[e_i][f] E_f for output i = 4 q + r of line li
+    const float cD2 = cc * D * D;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float e = float(4 * q + r) - 7.5f;
+      const float al = (mloc == -__builtin_inff()) ? -__builtin_inff() : (mloc - cc * (e * (e + 2.f * D)) - cD2);
+      const float mn = fmaxf(M[r], al);
+      const float sh = (mn == -__builtin_inff()) ? 0.f : mn;
+      S[r] = S[r] * __builtin_amdgcn_exp2f(M[r] - sh) + acc[r] * __builtin_amdgcn_exp2f(al - sh);
+      M[r] = mn;
+    }
+  }
+  // merge the four waves (each saw a quarter of the J tiles)
+  __shared__ float smM[4][64][4], smS[4][64][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    smM[wv][lane][r] = M[r];
+    smS[wv][lane][r] = S[r];
+  }
+  __syncthreads();
+  ResAcc<float> ra;
+  ra.init();
+  if (wv == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Lse2<float> t;
+      t.m = M[r];
+      t.s = S[r];
+      for (int k = 1; k < 4; ++k) t.merge(smM[k][lane][r], smS[k][lane][r]);
+      if (valid) {
+        const int i = I0 + 4 * q + r;
+        const int64_t e = STRIDED ? (a * (int64_t)n + i) * B + bb : a * (int64_t)n + i;
+        epi_elem<float>(e, t.result(), c, side, ep, ra);
+      }
+    }
+  }
+  epi_finish<float>(ep, ra, (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+}
+
+static inline void tf_grid(int n, int64_t A, int64_t B, bool strided, unsigned& gx, unsigned& gy, unsigned& gz) {
+  const int64_t groups = strided ? A * ((B + 15) / 16) : (A + 15) / 16;
+  const int64_t ylim = 65535;
+  const int64_t y = groups < ylim ? groups : ylim;
+  gx = (unsigned)(n / 16);
+  gy = (unsigned)y;
+  gz = (unsigned)((groups + y - 1) / y);
+}
+
+int grid_tf_parts(int n, int64_t A, int64_t B, bool strided) {
+  unsigned gx, gy, gz;
+  tf_grid(n, A, B, strided, gx, gy, gz);
+  return (int)((int64_t)gx * gy * gz);
+}
+
+void launch_grid_tf(const float* in, int64_t A, int n, int64_t B, bool strided, double h, int side, const Ctrl* c,
+                    const EpiArgs<float>& ep, hipStream_t s) {
+  unsigned gx, gy, gz;
+  tf_grid(n, A, B, strided, gx, gy, gz);
+  if (strided) hipLaunchKernelGGL(k_grid_tf<true>, dim3(gx, gy, gz), dim3(kBlock), 0, s, in, n, A, B, h, side, c, ep);
+  else hipLaunchKernelGGL(k_grid_tf<false>, dim3(gx, gy, gz), dim3(kBlock), 0, s, in, n, A, B, h, side, c, ep);
+}
 
 }  // namespace uot

@@ -1,0 +1,535 @@
+// Warm-start network for the scaling iteration: a 4-layer MLP
+//   n_in -> width -> width -> width -> n_out   (ReLU on the hidden layers)
+// predicting the dual potential v from the two input measures.  Only v^(0)
+// matters for the iterates (Prop. "alternating": the first X half-step
+// overwrites u), so a good v^(0) shortens the iteration while the iteration
+// itself still decides the answer.
+//
+// Every GEMM input (weights and activations) is BF16, accumulation is FP32 on
+// MFMA (v_mfma_f32_16x16x32_bf16); the optimiser keeps FP32 master weights
+// (Adam).  Parameter layout in every parameter-sized array:
+//   W1 [width x n_in], b1 [width], W2 [width x width], b2, W3 [width x width],
+//   b3, W4 [n_out x width], b4 [n_out].
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "uot_ctx.h"
+#include "uot_launch.h"
+
+namespace uot {
+namespace net {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+constexpr int kB = 256;
+
+// FP32 -> BF16 bits, round to nearest even (NaN stays NaN)
+__device__ __forceinline__ u16 f2bf(float f) {
+  uint32_t x = __float_as_uint(f);
+  if ((x & 0x7f800000u) == 0x7f800000u) return (u16)((x >> 16) | ((x & 0xffffu) ? 0x40u : 0u));
+  x += 0x7fffu + ((x >> 16) & 1u);
+  return (u16)(x >> 16);
+}
+__device__ __forceinline__ float bf2f(u16 b) { return __uint_as_float((uint32_t)b << 16); }
+
+static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// C[M x N] = op(A)[M x K] * op(B)[K x N] (+ bias[n]) (ReLU), BF16 in, FP32 acc.
+//   TA = false: A[m][k] = A[m*lda + k];  TA = true: A[m][k] = A[k*lda + m]
+//   TB = false: B[k][n] = B[k*ldb + n];  TB = true: B[k][n] = B[n*ldb + k]
+// Block tile 64 x 64, K tile 32, 4 waves of 32 x 32 (2 x 2 MFMA 16x16x32).
+// ---------------------------------------------------------------------------
+constexpr int TM = 64, TN = 64, TK = 32, LK = TK + 8;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(kB) void k_gemm(const u16* __restrict__ A, int64_t lda, const u16* __restrict__ Bm,
+                                              int64_t ldb, int M, int N, int K, float* __restrict__ C, int64_t ldc,
+                                              u16* __restrict__ Cb, const float* __restrict__ bias, int relu) {
+  __shared__ __align__(16) u16 As[TM][LK];
+  __shared__ __align__(16) u16 Bs[TN][LK];
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    if (!TA) {
+      const int r = tid >> 2, c = (tid & 3) * 8;
+      const int m = m0 + r;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + c + j;
+        As[r][c + j] = (m < M && k < K) ? A[(int64_t)m * lda + k] : (u16)0;
+      }
+    } else {
+      const int kk = tid >> 3, c = (tid & 7) * 8;
+      const int k = k0 + kk;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int m = m0 + c + j;
+        As[c + j][kk] = (m < M && k < K) ? A[(int64_t)k * lda + m] : (u16)0;
+      }
+    }
+    if (TB) {
+      const int r = tid >> 2, c = (tid & 3) * 8;
+      const int n = n0 + r;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + c + j;
+        Bs[r][c + j] = (n < N && k < K) ? Bm[(int64_t)n * ldb + k] : (u16)0;
+      }
+    } else {
+      const int kk = tid >> 3, c = (tid & 7) * 8;
+      const int k = k0 + kk;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int n = n0 + c + j;
+        Bs[c + j][kk] = (n < N && k < K) ? Bm[(int64_t)k * ldb + n] : (u16)0;
+      }
+    }
+    __syncthreads();
+    // operand layout of v_mfma_f32_16x16x32_bf16: lane l holds row (l % 16)
+    // of A and column (l % 16) of B, k = 8 (l / 16) .. 8 (l / 16) + 7
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 16 + (lane & 15)][(lane >> 4) * 8]);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // result layout: lane l holds rows 4 (l / 16) + r (r = 0..3), column l % 16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < M && n < N) {
+          float x = acc[i][j][r];
+          if (bias) x += bias[n];
+          if (relu) x = x > 0.f ? x : 0.f;
+          if (C) C[(int64_t)m * ldc + n] = x;
+          if (Cb) Cb[(int64_t)m * ldc + n] = f2bf(x);
+        }
+      }
+}
+
+template <bool TA, bool TB>
+static void gemm(const u16* A, int64_t lda, const u16* B, int64_t ldb, int M, int N, int K, float* C, int64_t ldc,
+                 u16* Cb, const float* bias, int relu, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm<TA, TB>), dim3(cdiv(N, TN), cdiv(M, TM)), dim3(kB), 0, s, A, lda, B, ldb, M, N, K, C, ldc,
+                     Cb, bias, relu);
+}
+
+// y = bf16(scale * x + shift)
+__global__ void k_cast(const float* __restrict__ x, u16* __restrict__ y, int64_t n, float scale, float shift) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i < n) y[i] = f2bf(scale * x[i] + shift);
+}
+
+// g = bf16(coef * (y - t)); part[block] = sum (y - t)^2
+__global__ void k_loss_grad(const float* __restrict__ y, const float* __restrict__ t, u16* __restrict__ g, int64_t n,
+                            float coef, double* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  double e2 = 0.0;
+  if (i < n) {
+    const float d = y[i] - t[i];
+    if (g) g[i] = f2bf(coef * d);
+    e2 = double(d) * double(d);
+  }
+  __shared__ double sm[kB];
+  sm[threadIdx.x] = e2;
+  __syncthreads();
+  for (int off = kB / 2; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off) sm[threadIdx.x] += sm[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+// g = bf16(dh) where the pre-activation z > 0, else 0
+__global__ void k_relu_grad(const float* __restrict__ dh, const float* __restrict__ z, u16* __restrict__ g, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i < n) g[i] = z[i] > 0.f ? f2bf(dh[i]) : (u16)0;
+}
+
+// out[n] = sum_b g[b][n]  (bias gradients)
+__global__ void k_colsum(const u16* __restrict__ g, int rows, int cols, float* __restrict__ out) {
+  const int n = blockIdx.x * kB + threadIdx.x;
+  if (n >= cols) return;
+  float s = 0.f;
+  for (int b = 0; b < rows; ++b) s += bf2f(g[(int64_t)b * cols + n]);
+  out[n] = s;
+}
+
+// Adam with bias correction; refreshes the BF16 copy of the weights
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       u16* __restrict__ wb, int64_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  wb[i] = f2bf(wi);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ w, u16* __restrict__ wb, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i < n) wb[i] = f2bf(w[i]);
+}
+
+// features of a grid pair: 2x2..sxs average pooling of p and q from R x R to
+// r x r (R = s r), then x[b] = [log p_r, log q_r]
+__global__ void k_features(const float* __restrict__ p, const float* __restrict__ q, int64_t nb, int R, int r,
+                           float* __restrict__ x) {
+  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+  const int64_t per = (int64_t)r * r;
+  if (t >= nb * per * 2) return;
+  const int64_t b = t / (2 * per);
+  const int which = (int)((t / per) % 2);
+  const int64_t cell = t % per;
+  const int i = (int)(cell / r), j = (int)(cell % r);
+  const int s = R / r;
+  const float* src = (which == 0 ? p : q) + b * (int64_t)R * R;
+  float acc = 0.f;
+  for (int a = 0; a < s; ++a)
+    for (int c = 0; c < s; ++c) acc += src[(int64_t)(i * s + a) * R + (j * s + c)];
+  acc /= float(s * s);
+  x[b * 2 * per + which * per + cell] = acc > 0.f ? logf(acc) : -80.f;
+}
+
+// bilinear upsampling of r x r cell-centred fields to R x R (clamped at the border)
+__global__ void k_upsample(const float* __restrict__ y, int64_t nb, int r, int R, float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+  const int64_t per = (int64_t)R * R;
+  if (t >= nb * per) return;
+  const int64_t b = t / per;
+  const int i = (int)((t % per) / R), j = (int)(t % R);
+  const float sc = float(r) / float(R);
+  float fi = (i + 0.5f) * sc - 0.5f, fj = (j + 0.5f) * sc - 0.5f;
+  fi = fminf(fmaxf(fi, 0.f), float(r - 1));
+  fj = fminf(fmaxf(fj, 0.f), float(r - 1));
+  const int i0 = (int)floorf(fi), j0 = (int)floorf(fj);
+  const int i1 = i0 + 1 < r ? i0 + 1 : r - 1, j1 = j0 + 1 < r ? j0 + 1 : r - 1;
+  const float a = fi - i0, c = fj - j0;
+  const float* src = y + b * (int64_t)r * r;
+  out[t] = (1 - a) * ((1 - c) * src[i0 * r + j0] + c * src[i0 * r + j1]) +
+           a * ((1 - c) * src[i1 * r + j0] + c * src[i1 * r + j1]);
+}
+
+// first barycentre estimate for the warm start: the pointwise combination of
+// Table estimatebary applied to the input densities themselves,
+// (i) equality: log h = sum_k alpha_k log p_k / sum alpha;
+// (ii) lam KL: log h = ((eps+lam)/eps) [LSE_k(log alpha_k + eps/(eps+lam) log p_k) - log sum alpha]
+__global__ void k_bary_estimate(const float* __restrict__ p, int n, int64_t size, BaryW la, double log_sum_alpha,
+                                float eps, float lam, int kind, float* __restrict__ h) {
+  const int64_t j = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (j >= size) return;
+  float logh;
+  if (kind == 0) {
+    double acc = 0.0, asum = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double al = ::exp(la.v[k]);
+      acc += al * ::log((double)p[k * size + j]);
+      asum += al;
+    }
+    logh = float(acc / asum);
+  } else {
+    const float g = eps / (eps + lam);
+    float m = -__builtin_inff();
+    for (int k = 0; k < n; ++k) m = fmaxf(m, float(la.v[k]) + g * logf(p[k * size + j]));
+    float s = 0.f;
+    for (int k = 0; k < n; ++k) s += expf(float(la.v[k]) + g * logf(p[k * size + j]) - m);
+    logh = (m + logf(s) - float(log_sum_alpha)) / g;
+  }
+  h[j] = expf(logh);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct Layout {
+  int64_t w[4], b[4], total;
+  int in[4], out[4];
+};
+
+Layout layout(const uot_net* n) {
+  Layout L;
+  const int ins[4] = {n->n_in, n->width, n->width, n->width};
+  const int outs[4] = {n->width, n->width, n->width, n->n_out};
+  int64_t o = 0;
+  for (int l = 0; l < 4; ++l) {
+    L.in[l] = ins[l];
+    L.out[l] = outs[l];
+    L.w[l] = o;
+    o += (int64_t)ins[l] * outs[l];
+    L.b[l] = o;
+    o += outs[l];
+  }
+  L.total = o;
+  return L;
+}
+
+struct Act {
+  u16* xb;          // batch x n_in
+  float* z[3];      // pre-activations, batch x width
+  u16* h[3];        // BF16 hidden activations
+  float* y;         // batch x n_out
+  u16* g4;          // batch x n_out
+  float* dh;        // batch x width
+  u16* g;           // batch x width
+  double* part;     // loss partials
+  float* grad;      // gradient (parameter-sized)
+  size_t total;
+};
+
+Act carve(const uot_net* n, int64_t batch, char* ws) {
+  Act a;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = (o + bytes + 255) / 256 * 256;
+    return ws ? ws + r : nullptr;
+  };
+  const Layout L = layout(n);
+  a.xb = reinterpret_cast<u16*>(take(2 * batch * n->n_in));
+  for (int l = 0; l < 3; ++l) {
+    a.z[l] = reinterpret_cast<float*>(take(4 * batch * n->width));
+    a.h[l] = reinterpret_cast<u16*>(take(2 * batch * n->width));
+  }
+  a.y = reinterpret_cast<float*>(take(4 * batch * n->n_out));
+  a.g4 = reinterpret_cast<u16*>(take(2 * batch * n->n_out));
+  a.dh = reinterpret_cast<float*>(take(4 * batch * n->width));
+  a.g = reinterpret_cast<u16*>(take(2 * batch * n->width));
+  a.part = reinterpret_cast<double*>(take(8 * (size_t)cdiv(batch * n->n_out, kB)));
+  a.grad = reinterpret_cast<float*>(take(4 * L.total));
+  a.total = o;
+  return a;
+}
+
+int check_net(const uot_net* n) {
+  if (!n) return fail(UOT_E_INVALID, "net is NULL");
+  if (n->n_in < 1 || n->width < 1 || n->n_out < 1) return fail(UOT_E_INVALID, "net sizes must be >= 1");
+  if (n->width % 8 || n->n_in % 8 || n->n_out % 8) return fail(UOT_E_UNSUPPORTED, "net sizes must be multiples of 8");
+  return UOT_OK;
+}
+
+void forward(const uot_net* n, const Layout& L, const Act& a, const float* x, int64_t batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast, dim3(cdiv(batch * n->n_in, kB)), dim3(kB), 0, s, x, a.xb, batch * n->n_in, n->in_scale,
+                     n->in_shift);
+  const u16* inp = a.xb;
+  for (int l = 0; l < 3; ++l) {
+    gemm<false, true>(inp, L.in[l], n->wbf16 + L.w[l], L.in[l], (int)batch, L.out[l], L.in[l], a.z[l], L.out[l],
+                      nullptr, n->master + L.b[l], 0, s);
+    // ReLU copy in BF16 (z keeps the pre-activation for the backward mask)
+    hipLaunchKernelGGL(k_relu_grad, dim3(cdiv(batch * L.out[l], kB)), dim3(kB), 0, s, a.z[l], a.z[l], a.h[l],
+                       batch * L.out[l]);
+    inp = a.h[l];
+  }
+  gemm<false, true>(inp, L.in[3], n->wbf16 + L.w[3], L.in[3], (int)batch, L.out[3], L.in[3], a.y, L.out[3], nullptr,
+                    n->master + L.b[3], 0, s);
+}
+
+// gradient of loss = mean (y - t)^2 over batch x n_out into a.grad
+void backward(const uot_net* n, const Layout& L, const Act& a, const float* t, int64_t batch, hipStream_t s) {
+  const int64_t ny = batch * n->n_out;
+  hipLaunchKernelGGL(k_loss_grad, dim3(cdiv(ny, kB)), dim3(kB), 0, s, a.y, t, a.g4, ny, 2.f / float(ny), a.part);
+  const u16* g = a.g4;
+  for (int l = 3; l >= 0; --l) {
+    const u16* inp = l == 0 ? a.xb : a.h[l - 1];
+    // dW_l [out x in] = g^T [out x batch] * inp [batch x in]
+    gemm<true, false>(g, L.out[l], inp, L.in[l], L.out[l], L.in[l], (int)batch, a.grad + L.w[l], L.in[l], nullptr,
+                      nullptr, 0, s);
+    hipLaunchKernelGGL(k_colsum, dim3(cdiv(L.out[l], kB)), dim3(kB), 0, s, g, (int)batch, L.out[l], a.grad + L.b[l]);
+    if (l == 0) break;
+    // dh_{l-1} [batch x in] = g [batch x out] * W_l [out x in], then the ReLU mask
+    gemm<false, false>(g, L.out[l], n->wbf16 + L.w[l], L.in[l], (int)batch, L.in[l], L.out[l], a.dh, L.in[l], nullptr,
+                       nullptr, 0, s);
+    hipLaunchKernelGGL(k_relu_grad, dim3(cdiv(batch * L.in[l], kB)), dim3(kB), 0, s, a.dh, a.z[l - 1], a.g,
+                       batch * L.in[l]);
+    g = a.g;
+  }
+}
+
+double loss_from_parts(const Act& a, int64_t ny, hipStream_t s, int* rc) {
+  const int nb = (int)cdiv(ny, kB);
+  std::vector<double> h(nb);
+  *rc = UOT_OK;
+  if (hipStreamSynchronize(s) != hipSuccess || hipMemcpy(h.data(), a.part, 8 * nb, hipMemcpyDeviceToHost) != hipSuccess) {
+    *rc = fail(UOT_E_HIP, "loss readback failed");
+    return 0.0;
+  }
+  double tot = 0.0;
+  for (double v : h) tot += v;
+  return tot / double(ny);
+}
+
+}  // namespace net
+}  // namespace uot
+
+using namespace uot;
+using namespace uot::net;
+
+extern "C" {
+
+int uot_net_param_count(const uot_net* n, int64_t* count) {
+  int rc = check_net(n);
+  if (rc) return rc;
+  if (!count) return fail(UOT_E_INVALID, "count is NULL");
+  *count = layout(n).total;
+  return UOT_OK;
+}
+
+int uot_net_workspace_size(const uot_net* n, int64_t batch, size_t* bytes) {
+  int rc = check_net(n);
+  if (rc) return rc;
+  if (batch < 1 || !bytes) return fail(UOT_E_INVALID, "batch >= 1 and bytes are required");
+  *bytes = carve(n, batch, nullptr).total;
+  return UOT_OK;
+}
+
+int uot_net_sync(uot_ctx* ctx, const uot_net* n) {
+  int rc = check_net(n);
+  if (rc) return rc;
+  if (!ctx || !n->master || !n->wbf16) return fail(UOT_E_INVALID, "ctx, master and wbf16 are required");
+  if ((rc = begin(ctx))) return rc;
+  const int64_t tot = layout(n).total;
+  hipLaunchKernelGGL(k_to_bf16, dim3(cdiv(tot, kB)), dim3(kB), 0, ctx->work, n->master, n->wbf16, tot);
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
+int uot_warmstart_infer(uot_ctx* ctx, const uot_net* n, const float* x, float* y, int64_t batch, void* ws,
+                        size_t wsb) {
+  int rc = check_net(n);
+  if (rc) return rc;
+  if (!ctx || !x || !y || batch < 1 || !n->master || !n->wbf16) return fail(UOT_E_INVALID, "bad arguments");
+  const Act a0 = carve(n, batch, nullptr);
+  if (!ws || wsb < a0.total) return fail(UOT_E_WORKSPACE, "workspace too small");
+  if ((rc = begin(ctx))) return rc;
+  const Layout L = layout(n);
+  Act a = carve(n, batch, static_cast<char*>(ws));
+  forward(n, L, a, x, batch, ctx->work);
+  HIP_TRY(hipMemcpyAsync(y, a.y, 4 * batch * n->n_out, hipMemcpyDeviceToDevice, ctx->work));
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
+int uot_net_grad(uot_ctx* ctx, const uot_net* n, const float* x, const float* t, int64_t batch, float* grad,
+                 double* loss, void* ws, size_t wsb) {
+  int rc = check_net(n);
+  if (rc) return rc;
+  if (!ctx || !x || !t || !grad || batch < 1 || !n->master || !n->wbf16) return fail(UOT_E_INVALID, "bad arguments");
+  const Act a0 = carve(n, batch, nullptr);
+  if (!ws || wsb < a0.total) return fail(UOT_E_WORKSPACE, "workspace too small");
+  if ((rc = begin(ctx))) return rc;
+  const Layout L = layout(n);
+  Act a = carve(n, batch, static_cast<char*>(ws));
+  forward(n, L, a, x, batch, ctx->work);
+  backward(n, L, a, t, batch, ctx->work);
+  HIP_TRY(hipMemcpyAsync(grad, a.grad, 4 * L.total, hipMemcpyDeviceToDevice, ctx->work));
+  HIP_TRY(hipGetLastError());
+  const double l = loss_from_parts(a, batch * n->n_out, ctx->work, &rc);
+  if (rc) return rc;
+  if (loss) *loss = l;
+  return finish(ctx);
+}
+
+int uot_warmstart_train_step(uot_ctx* ctx, uot_net* n, const float* x, const float* t, int64_t batch, float lr,
+                             double* loss, void* ws, size_t wsb) {
+  int rc = check_net(n);
+  if (rc) return rc;
+  if (!ctx || !x || !t || batch < 1 || !n->master || !n->wbf16 || !n->adam_m || !n->adam_v)
+    return fail(UOT_E_INVALID, "bad arguments");
+  const Act a0 = carve(n, batch, nullptr);
+  if (!ws || wsb < a0.total) return fail(UOT_E_WORKSPACE, "workspace too small");
+  if ((rc = begin(ctx))) return rc;
+  const Layout L = layout(n);
+  Act a = carve(n, batch, static_cast<char*>(ws));
+  forward(n, L, a, x, batch, ctx->work);
+  backward(n, L, a, t, batch, ctx->work);
+  n->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, (float)n->step), c2 = 1.f - std::pow(b2, (float)n->step);
+  hipLaunchKernelGGL(k_adam, dim3(cdiv(L.total, kB)), dim3(kB), 0, ctx->work, n->master, a.grad, n->adam_m, n->adam_v,
+                     n->wbf16, L.total, lr, b1, b2, 1e-8f, c1, c2);
+  HIP_TRY(hipGetLastError());
+  if (loss) {
+    *loss = loss_from_parts(a, batch * n->n_out, ctx->work, &rc);
+    if (rc) return rc;
+  }
+  return finish(ctx);
+}
+
+int uot_warmstart_features(uot_ctx* ctx, const float* p, const float* q, int64_t nb, int R, int r, float* x) {
+  if (!ctx || !p || !q || !x || nb < 1 || r < 1 || R < r || R % r) return fail(UOT_E_INVALID, "bad arguments");
+  int rc = begin(ctx);
+  if (rc) return rc;
+  const int64_t tot = nb * (int64_t)r * r * 2;
+  hipLaunchKernelGGL(k_features, dim3(cdiv(tot, kB)), dim3(kB), 0, ctx->work, p, q, nb, R, r, x);
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
+int uot_grid_upsample(uot_ctx* ctx, const float* y, int64_t nb, int r, int R, float* out) {
+  if (!ctx || !y || !out || nb < 1 || r < 1 || R < 1) return fail(UOT_E_INVALID, "bad arguments");
+  int rc = begin(ctx);
+  if (rc) return rc;
+  const int64_t tot = nb * (int64_t)R * R;
+  hipLaunchKernelGGL(k_upsample, dim3(cdiv(tot, kB)), dim3(kB), 0, ctx->work, y, nb, r, R, out);
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
+int uot_bary_estimate(uot_ctx* ctx, const float* p, int n, int64_t size, const double* alpha, double eps,
+                      const uot_div* F2, float* h) {
+  if (!ctx || !p || !alpha || !F2 || !h || n < 1 || n > kMaxBary || size < 1) return fail(UOT_E_INVALID, "bad arguments");
+  if (F2->kind != UOT_DIV_KL && F2->kind != UOT_DIV_EQ) return fail(UOT_E_UNSUPPORTED, "F2 must be KL or equality");
+  BaryW la{};
+  double asum = 0.0;
+  for (int k = 0; k < n; ++k) {
+    if (!(alpha[k] > 0)) return fail(UOT_E_INVALID, "alpha_k must be > 0");
+    la.v[k] = std::log(alpha[k]);
+    asum += alpha[k];
+  }
+  int rc = begin(ctx);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_bary_estimate, dim3(cdiv(size, kB)), dim3(kB), 0, ctx->work, p, n, size, la, std::log(asum),
+                     (float)eps, (float)F2->lambda, F2->kind == UOT_DIV_KL ? 1 : 0, h);
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
+int uot_gemm_bf16(uot_ctx* ctx, int ta, int tb, int M, int N, int K, const uint16_t* A, int64_t lda, const uint16_t* B,
+                  int64_t ldb, float* C, int64_t ldc) {
+  if (!ctx || !A || !B || !C || M < 1 || N < 1 || K < 1) return fail(UOT_E_INVALID, "bad arguments");
+  int rc = begin(ctx);
+  if (rc) return rc;
+  hipStream_t s = ctx->work;
+  if (!ta && !tb) gemm<false, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
+  else if (!ta && tb) gemm<false, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
+  else if (ta && !tb) gemm<true, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
+  else gemm<true, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
+}  // extern "C"

@@ -44,7 +44,7 @@ class UotParams(ctypes.Structure):
     _fields_ = [("eps", c_dbl), ("eps0", c_dbl), ("eps_stages", c_i32), ("iters_per_stage", c_i32),
                 ("tol", c_dbl), ("max_iter", c_i64), ("check_every", c_i32), ("use_graph", c_i32),
                 ("v0", c_vp), ("res_hist", c_vp), ("kernel_ms", ctypes.POINTER(c_dbl)),
-                ("kernel_launches", ctypes.POINTER(c_i64))]
+                ("kernel_launches", ctypes.POINTER(c_i64)), ("grid_kernel", c_i32), ("reserved", c_i32)]
 
 
 class UotResult(ctypes.Structure):
@@ -73,6 +73,12 @@ class UotBatchResult(ctypes.Structure):
                 ("latency_ms", ctypes.POINTER(c_dbl)), ("status", ctypes.POINTER(c_i32)), ("iters_max", c_i64),
                 ("n_converged", c_i64), ("elapsed_ms", c_dbl), ("tile_rows", c_i32), ("blocks_per_cu", c_i32),
                 ("tune_ms", c_dbl)]
+
+
+class UotNet(ctypes.Structure):
+    _fields_ = [("n_in", c_i32), ("width", c_i32), ("n_out", c_i32), ("reserved", c_i32), ("in_scale", ctypes.c_float),
+                ("in_shift", ctypes.c_float), ("master", c_vp), ("wbf16", c_vp), ("adam_m", c_vp), ("adam_v", c_vp),
+                ("step", c_i64)]
 
 
 _lib = None
@@ -105,7 +111,21 @@ def lib():
         "uot_time_half_step": (c_i32, [c_vp, P(UotProblem), c_dbl, c_vp, c_i32, P(c_dbl), P(c_i32), c_vp,
                                        ctypes.c_size_t]),
         "uot_probe_rates": (c_i32, [c_vp, P(c_dbl), P(c_dbl)]),
+        "uot_fields_workspace_size": (c_i32, [P(UotProblem), c_i32, P(ctypes.c_size_t)]),
+        "uot_solve_fields": (c_i32, [c_vp, P(UotProblem), c_i32, P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t,
+                                     P(UotResult)]),
         "uot_batch_workspace_size": (c_i32, [P(UotBatchProblem), P(ctypes.c_size_t)]),
+        "uot_net_param_count": (c_i32, [P(UotNet), P(c_i64)]),
+        "uot_net_workspace_size": (c_i32, [P(UotNet), c_i64, P(ctypes.c_size_t)]),
+        "uot_net_sync": (c_i32, [c_vp, P(UotNet)]),
+        "uot_warmstart_infer": (c_i32, [c_vp, P(UotNet), c_vp, c_vp, c_i64, c_vp, ctypes.c_size_t]),
+        "uot_net_grad": (c_i32, [c_vp, P(UotNet), c_vp, c_vp, c_i64, c_vp, P(c_dbl), c_vp, ctypes.c_size_t]),
+        "uot_warmstart_train_step": (c_i32, [c_vp, P(UotNet), c_vp, c_vp, c_i64, ctypes.c_float, P(c_dbl), c_vp,
+                                             ctypes.c_size_t]),
+        "uot_warmstart_features": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_i32, c_i32, c_vp]),
+        "uot_grid_upsample": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, c_vp]),
+        "uot_bary_estimate": (c_i32, [c_vp, c_vp, c_i32, c_i64, P(c_dbl), c_dbl, P(UotDiv), c_vp]),
+        "uot_gemm_bf16": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64]),
         "uot_solve_batched": (c_i32, [c_vp, P(UotBatchProblem), P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t,
                                       P(UotBatchResult)]),
     }
@@ -285,11 +305,15 @@ def grid_problem(shape: Sequence[int], h: Sequence[float], p, q, dx, dy, F1: Div
     return Problem(g, dtype, p, q, dx, dy, F1, F2)
 
 
+GRID_AUTO, GRID_DIRECT, GRID_MFMA = 0, 1, 2
+
+
 def params(eps, tol=1e-6, max_iter=10000, eps0=None, eps_stages=10, iters_per_stage=100, check_every=50,
-           use_graph=True, v0=None, res_hist=None, kernel_ms=None, kernel_launches=None) -> UotParams:
+           use_graph=True, v0=None, res_hist=None, kernel_ms=None, kernel_launches=None,
+           grid_kernel=GRID_AUTO) -> UotParams:
     return UotParams(float(eps), float(eps0 or 0.0), int(eps_stages if eps0 else 0), int(iters_per_stage),
                      float(tol), int(max_iter), int(check_every), int(bool(use_graph)), _ptr(v0), _ptr(res_hist),
-                     kernel_ms, kernel_launches)
+                     kernel_ms, kernel_launches, int(grid_kernel), 0)
 
 
 def solve(prob: Problem, eps, ctx: Optional[Context] = None, v0=None, record=False, time_kernels=False, **kw):
@@ -484,3 +508,161 @@ def solve_batched(bp: BatchProblem, eps, ctx: Optional[Context] = None, v0=None,
         info["kernel_ms"] = [kms[k] for k in range(4)]
         info["kernel_launches"] = [kcnt[k] for k in range(4)]
     return u, v, info
+
+
+def solve_fields(shape, h, p, q, dx, dy, F1: Div, F2: Div, eps, ctx: Optional[Context] = None, v0=None,
+                 record=False, **kw):
+    """nb independent UOT problems on one grid (p, q: nb x size).  Returns
+    (u, v, info) with u, v of shape (nb, size)."""
+    ctx = ctx or default_context()
+    nb = p.shape[0]
+    size = int(math.prod(shape))
+    dtype = p.dtype
+    _dev(p, dtype, nb * size, "p")
+    _dev(q, dtype, nb * size, "q")
+    _dev(dx, dtype, size, "dx")
+    _dev(dy, dtype, size, "dy")
+    n = list(shape) + [1] * (3 - len(shape))
+    hh = list(h) + [0.0] * (3 - len(h))
+    g = UotGeom(UOT_GEOM_GRID, len(shape), size, size, c_vp(), c_vp(), (c_i64 * 3)(*n), (c_dbl * 3)(*hh))
+    pb = UotProblem(_dt(p), 0, g, _ptr(p), _ptr(q), _ptr(dx), _ptr(dy), F1.c(), F2.c())
+    nbytes = ctypes.c_size_t()
+    _check(lib().uot_fields_workspace_size(ctypes.byref(pb), nb, ctypes.byref(nbytes)), "uot_fields_workspace_size",
+           False)
+    ws = workspace(nbytes.value, p.device)
+    u = torch.empty(nb, size, dtype=dtype, device=p.device)
+    v = torch.empty(nb, size, dtype=dtype, device=p.device)
+    if v0 is not None:
+        _dev(v0, dtype, nb * size, "v0")
+    max_iter = kw.get("max_iter", 10000)
+    hist = torch.full((max_iter,), float("nan"), dtype=torch.float64, device=p.device) if record else None
+    pr = params(eps, v0=v0, res_hist=hist, **kw)
+    res = UotResult()
+    code = lib().uot_solve_fields(ctx.handle, ctypes.byref(pb), nb, ctypes.byref(pr), _ptr(u), _ptr(v), _ptr(ws),
+                                  ws.numel(), ctypes.byref(res))
+    _check(code, "uot_solve_fields")
+    info = dict(iters=res.iters, residual=res.residual, status=res.status, elapsed_ms=res.elapsed_ms,
+                converged=(code == UOT_OK))
+    if record:
+        info["res_hist"] = hist[:res.iters].cpu()
+    return u, v, info
+
+
+# ---------------------------------------------------------------------------
+# warm-start network
+# ---------------------------------------------------------------------------
+def bf16_bits(t: torch.Tensor) -> torch.Tensor:
+    """BF16 bit patterns (int16 view) of a float tensor, round to nearest even."""
+    return t.to(torch.bfloat16).view(torch.int16)
+
+
+def gemm_bf16(A_bits, B_bits, M, N, K, ta=False, tb=False, lda=None, ldb=None, ctx: Optional[Context] = None):
+    ctx = ctx or default_context()
+    C = torch.empty(M, N, dtype=torch.float32, device=A_bits.device)
+    lda = lda if lda is not None else (M if ta else K)
+    ldb = ldb if ldb is not None else (K if tb else N)
+    _check(lib().uot_gemm_bf16(ctx.handle, int(ta), int(tb), M, N, K, _ptr(A_bits), lda, _ptr(B_bits), ldb, _ptr(C),
+                               N), "uot_gemm_bf16", False)
+    return C
+
+
+class WarmStartNet:
+    """4-layer MLP of the C ABI: parameters, BF16 copy and Adam state on the
+    device; every computation runs in libuot's kernels."""
+
+    def __init__(self, n_in, width, n_out, device, seed=0, in_scale=1.0, in_shift=0.0, params=None):
+        import numpy as np
+        self.c = UotNet(n_in, width, n_out, 0, in_scale, in_shift)
+        cnt = c_i64()
+        _check(lib().uot_net_param_count(ctypes.byref(self.c), ctypes.byref(cnt)), "uot_net_param_count", False)
+        self.n_params = cnt.value
+        if params is None:
+            params = init_params(n_in, width, n_out, seed)
+        self.master = torch.tensor(np.asarray(params, dtype=np.float32), device=device)
+        assert self.master.numel() == self.n_params
+        self.wbf16 = torch.empty(self.n_params, dtype=torch.int16, device=device)
+        self.m = torch.zeros(self.n_params, dtype=torch.float32, device=device)
+        self.v = torch.zeros(self.n_params, dtype=torch.float32, device=device)
+        self.c.master, self.c.wbf16 = self.master.data_ptr(), self.wbf16.data_ptr()
+        self.c.adam_m, self.c.adam_v = self.m.data_ptr(), self.v.data_ptr()
+        self._ws = {}
+        _check(lib().uot_net_sync(default_context().handle, ctypes.byref(self.c)), "uot_net_sync", False)
+
+    def _workspace(self, batch):
+        if batch not in self._ws:
+            n = ctypes.c_size_t()
+            _check(lib().uot_net_workspace_size(ctypes.byref(self.c), batch, ctypes.byref(n)),
+                   "uot_net_workspace_size", False)
+            self._ws = {batch: workspace(n.value, self.master.device)}
+        return self._ws[batch]
+
+    def infer(self, x, ctx: Optional[Context] = None):
+        ctx = ctx or default_context()
+        batch = x.shape[0]
+        _dev(x, torch.float32, batch * self.c.n_in, "x")
+        y = torch.empty(batch, self.c.n_out, dtype=torch.float32, device=x.device)
+        ws = self._workspace(batch)
+        _check(lib().uot_warmstart_infer(ctx.handle, ctypes.byref(self.c), _ptr(x), _ptr(y), batch, _ptr(ws),
+                                         ws.numel()), "uot_warmstart_infer", False)
+        return y
+
+    def grad(self, x, t, ctx: Optional[Context] = None):
+        ctx = ctx or default_context()
+        batch = x.shape[0]
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = c_dbl()
+        ws = self._workspace(batch)
+        _check(lib().uot_net_grad(ctx.handle, ctypes.byref(self.c), _ptr(x), _ptr(t), batch, _ptr(g),
+                                  ctypes.byref(loss), _ptr(ws), ws.numel()), "uot_net_grad", False)
+        return g, loss.value
+
+    def train_step(self, x, t, lr, want_loss=False, ctx: Optional[Context] = None):
+        ctx = ctx or default_context()
+        batch = x.shape[0]
+        loss = c_dbl()
+        ws = self._workspace(batch)
+        _check(lib().uot_warmstart_train_step(ctx.handle, ctypes.byref(self.c), _ptr(x), _ptr(t), batch,
+                                              ctypes.c_float(lr), ctypes.byref(loss) if want_loss else None,
+                                              _ptr(ws), ws.numel()), "uot_warmstart_train_step", False)
+        return loss.value if want_loss else None
+
+
+def init_params(n_in, width, n_out, seed):
+    """He-normal weights, zero biases, in the layout of the C ABI."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for fi, fo in ((n_in, width), (width, width), (width, width), (width, n_out)):
+        out.append(rng.standard_normal(fi * fo) * np.sqrt(2.0 / fi))
+        out.append(np.zeros(fo))
+    return np.concatenate(out).astype(np.float32)
+
+
+def warmstart_features(p, q, R, r, ctx: Optional[Context] = None):
+    """x (nb x 2 r^2): log of the r x r average-pooled densities p and q."""
+    ctx = ctx or default_context()
+    nb = p.shape[0]
+    x = torch.empty(nb, 2 * r * r, dtype=torch.float32, device=p.device)
+    _check(lib().uot_warmstart_features(ctx.handle, _ptr(p), _ptr(q), nb, R, r, _ptr(x)), "uot_warmstart_features",
+           False)
+    return x
+
+
+def grid_upsample(y, r, R, ctx: Optional[Context] = None):
+    ctx = ctx or default_context()
+    nb = y.shape[0]
+    out = torch.empty(nb, R * R, dtype=torch.float32, device=y.device)
+    _check(lib().uot_grid_upsample(ctx.handle, _ptr(y), nb, r, R, _ptr(out)), "uot_grid_upsample", False)
+    return out
+
+
+def bary_estimate(p, alpha, eps, F2: Div, ctx: Optional[Context] = None):
+    """Pointwise Table estimatebary combination of the inputs (n x size) -> h (size)."""
+    ctx = ctx or default_context()
+    n, size = p.shape
+    h = torch.empty(size, dtype=torch.float32, device=p.device)
+    al = (c_dbl * n)(*[float(a) for a in alpha])
+    f = F2.c()
+    _check(lib().uot_bary_estimate(ctx.handle, _ptr(p), n, size, al, float(eps), ctypes.byref(f), _ptr(h)),
+           "uot_bary_estimate", False)
+    return h

@@ -1,0 +1,136 @@
+"""Learned warm start for grid UOT and barycentres.
+
+The network (4-layer MLP, BF16 weights, FP32 accumulation; kernels in
+csrc/uot_net.hip) maps a pair of 64 x 64 densities (p, q) to the dual
+potential v of UOT(p, q) with KL penalties (lambda = 0.5) at eps = 2e-3.  Its
+training targets come from the library's own grid solver (uot_solve_fields).
+For a barycentre of n images at a finer resolution R = s * 64, the first
+estimate h0 (Table estimatebary applied to the inputs) stands in for the
+unknown barycentre: the net predicts v_k for (p_k, h0) at 64 x 64 and the
+prediction is upsampled to R x R as v^(0).  The plain iteration then runs to
+the same tolerance, so the prediction only changes the number of iterations.
+
+Everything here is orchestration: every arithmetic step runs in libuot.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import synth
+from . import uot as U
+
+RES = 64
+LAM = 0.5
+EPS = 2e-3
+EPS0 = 1e-1
+TOL = 1e-6
+IN_SCALE, IN_SHIFT = 0.15, 0.5       # log densities in [-14, 3] -> about [-1.6, 1]
+
+
+def pair_densities(seeds, res=RES):
+    """(p, q) float32 arrays (len(seeds) x res^2) of blob image pairs."""
+    P = np.empty((len(seeds), res * res), np.float32)
+    Q = np.empty((len(seeds), res * res), np.float32)
+    for k, s in enumerate(seeds):
+        pr = synth.pair_blobs(int(s), n=res)
+        P[k] = pr.p
+        Q[k] = pr.q
+    return P, Q
+
+
+def solve_pairs(P, Q, device, batch=2048, res=RES, ctx=None):
+    """Targets: v of UOT(p, q) (KL lambda=0.5 both sides, eps=2e-3, eps-scaling
+    from 1e-1) for every pair, solved batch by batch on the grid.
+    Returns (V on device, list of per-batch info)."""
+    h = (1.0 / res, 1.0 / res)
+    d = torch.full((res * res,), h[0] * h[1], dtype=torch.float32, device=device)
+    F = U.KL(LAM)
+    out = torch.empty(P.shape[0], res * res, dtype=torch.float32, device=device)
+    infos = []
+    for a in range(0, P.shape[0], batch):
+        p = torch.tensor(P[a:a + batch], device=device)
+        q = torch.tensor(Q[a:a + batch], device=device)
+        _, v, info = U.solve_fields((res, res), h, p, q, d, d, F, F, EPS, eps0=EPS0, tol=TOL, max_iter=20000,
+                                    check_every=100, ctx=ctx)
+        out[a:a + batch] = v
+        infos.append(info)
+    return out, infos
+
+
+def features(P, Q, R, device, ctx=None):
+    p = P if isinstance(P, torch.Tensor) else torch.tensor(P, device=device)
+    q = Q if isinstance(Q, torch.Tensor) else torch.tensor(Q, device=device)
+    return U.warmstart_features(p.contiguous(), q.contiguous(), R, RES, ctx=ctx)
+
+
+@dataclass
+class TrainLog:
+    epochs: int = 0
+    steps: int = 0
+    seconds: float = 0.0
+    train_loss: list = field(default_factory=list)
+    val_loss: list = field(default_factory=list)
+
+
+def train(net: U.WarmStartNet, X, V, Xval, Vval, epochs=30, batch=256, lr=1e-3, seed=0) -> TrainLog:
+    """Adam on the mean squared error of v, cosine learning-rate decay."""
+    log = TrainLog()
+    n = X.shape[0]
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    steps_per_epoch = n // batch
+    total = epochs * steps_per_epoch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step = 0
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(X.device)
+        losses = []
+        for b in range(steps_per_epoch):
+            idx = perm[b * batch:(b + 1) * batch]
+            xb = X.index_select(0, idx).contiguous()
+            vb = V.index_select(0, idx).contiguous()
+            cur = lr * 0.5 * (1.0 + np.cos(np.pi * step / max(total, 1)))
+            want = (b == steps_per_epoch - 1)
+            l = net.train_step(xb, vb, cur, want_loss=want)
+            if want:
+                losses.append(l)
+            step += 1
+        log.train_loss.append(float(np.mean(losses)) if losses else float("nan"))
+        log.val_loss.append(validation_loss(net, Xval, Vval))
+    torch.cuda.synchronize()
+    log.seconds = time.perf_counter() - t0
+    log.epochs = epochs
+    log.steps = step
+    return log
+
+
+def validation_loss(net, Xval, Vval, batch=512):
+    tot, cnt = 0.0, 0
+    for a in range(0, Xval.shape[0], batch):
+        y = net.infer(Xval[a:a + batch].contiguous())
+        d = (y - Vval[a:a + batch]).double()
+        tot += float((d * d).sum())
+        cnt += d.numel()
+    return tot / max(cnt, 1)
+
+
+def barycenter_v0(net: U.WarmStartNet, p, alpha, R, ctx=None):
+    """Warm start v^(0) (n x R^2) for the barycentre of p (n x R^2, FP32)."""
+    n = p.shape[0]
+    h0 = U.bary_estimate(p, alpha, EPS, U.KL(LAM), ctx=ctx)
+    x = U.warmstart_features(p, h0.expand(n, -1).contiguous(), R, RES, ctx=ctx)
+    y = net.infer(x, ctx=ctx)
+    return U.grid_upsample(y, RES, R, ctx=ctx)
+
+
+def barycenter_solve(p, alpha, R, v0=None, eps0=None, ctx=None, max_iter=20000, check_every=50):
+    h = (1.0 / R, 1.0 / R)
+    d = torch.full((R * R,), h[0] * h[1], dtype=torch.float32, device=p.device)
+    F = U.KL(LAM)
+    return U.barycenter((R, R), h, p, alpha, d, d, F, F, EPS, v0=v0, eps0=eps0, tol=TOL, max_iter=max_iter,
+                        check_every=check_every, ctx=ctx)

@@ -354,3 +354,46 @@ def test_not_converged_status_and_validation_errors():
     assert info["status"] == U.UOT_NOT_CONVERGED and info["iters"] == 3 and not info["converged"]
     with pytest.raises(U.UotError):
         U.solve(prob, -1.0, tol=1e-6, max_iter=3)
+
+
+# ---------------------------------------------------------------------------
+# tile-factored MFMA grid passes (FP32)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(64,), (48, 32), (48, 29), (16, 32, 16)])
+def test_grid_mfma_passes_fixed_iterations(shape):
+    rng = np.random.default_rng(91 + shape[0])
+    h, p, q, d = grid_case(rng, shape, torch.float32)
+    eps = 0.01
+    G = O.GridGeom(shape, h)
+    for F in (U.KL(0.5), U.TV(0.1)):
+        say("case grid mfma", shape, F)
+        prob = U.grid_problem(shape, h, T(p, torch.float32), T(q, torch.float32), T(d, torch.float32),
+                              T(d, torch.float32), F, F)
+        u, v, info = U.solve(prob, eps, tol=0.0, max_iter=20, grid_kernel=U.GRID_MFMA)
+        ref = O.solve(G, np.log(p), np.log(q), np.log(d), np.log(d), oracle_div(F), oracle_div(F), eps, tol=0.0,
+                      max_iter=20)
+        assert pot_rel_err(u.cpu(), ref["u"], eps) < 1e-5, F
+        assert pot_rel_err(v.cpu(), ref["v"], eps) < 1e-5, F
+
+
+def test_grid_mfma_solve_256_matches_direct_and_oracle_residual():
+    """The 256 x 256 workload (KL 0.1, eps 1e-1 -> 1e-3, residual 1e-6) with
+    MFMA passes: same potentials as the direct passes to FP32 tolerance, and
+    the oracle's residual at the returned state is at the tolerance."""
+    pr = synth.blobs2d(0, n=256)
+    npd = np.float32
+    p, q = rounded(pr.p, npd), rounded(pr.q, npd)
+    d = rounded(np.full(pr.size, pr.h[0] * pr.h[1]), npd)
+    F = U.KL(0.1)
+    say("case grid mfma 256")
+    prob = U.grid_problem(pr.shape, pr.h, T(p, torch.float32), T(q, torch.float32), T(d, torch.float32),
+                          T(d, torch.float32), F, F)
+    u1, v1, i1 = U.solve(prob, 1e-3, eps0=1e-1, tol=1e-6, max_iter=5000, grid_kernel=U.GRID_DIRECT)
+    u2, v2, i2 = U.solve(prob, 1e-3, eps0=1e-1, tol=1e-6, max_iter=5000, grid_kernel=U.GRID_MFMA)
+    assert i1["converged"] and i2["converged"]
+    assert abs(i1["iters"] - i2["iters"]) <= 10
+    assert pot_rel_err(u2.cpu(), u1.cpu().numpy().astype(np.float64), 1e-3) < 1e-5
+    G = O.GridGeom(pr.shape, pr.h)
+    _, _, r = O.half_step_x(G, np.log(p), np.log(d), np.log(d), O.KL(0.1), 1e-3,
+                            u2.cpu().numpy().astype(np.float64), v2.cpu().numpy().astype(np.float64))
+    assert r < 5e-6, r
