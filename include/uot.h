@@ -137,7 +137,7 @@ typedef struct uot_params {
                             pass / dense LSE, [1] later passes / split merge +
                             epilogue, [2] control, [3] unused              */
   int64_t *kernel_launches; /* optional HOST array [4]: launches per class   */
-  int32_t grid_kernel;   /* grids: 0 default (= 1), 1 direct log-sum-exp
+  int32_t grid_kernel;   /* grids: 0 default (2 for FP32, 1 for FP64), 1 direct log-sum-exp
                             passes, 2 tile-factored FP32 MFMA passes (FP32
                             problems, axes with a multiple of 16 cells; other
                             axes use direct passes)                        */
@@ -352,7 +352,8 @@ int uot_gemm_bf16(uot_ctx *ctx, int ta, int tb, int M, int N, int K, const uint1
  *   points : ms[0] column-split log-sum-exp, ms[1] split merge + epilogue.
  * *n_kernels receives the number of entries written (<= 3). */
 int uot_time_half_step(uot_ctx *ctx, const uot_problem *pb, double eps, const void *v,
-                       int reps, double *ms, int *n_kernels, void *ws, size_t ws_bytes);
+                       int reps, double *ms, int *n_kernels, void *ws, size_t ws_bytes,
+                       int grid_kernel);   /* as uot_params.grid_kernel */
 
 /* Throughput probe of the current device: v_exp_f32 results per second and
  * v_add_f32 results per second, from 8 independent dependency chains per lane

@@ -123,22 +123,30 @@ struct Plan {
   int splits[2] = {1, 1};
   int64_t cps[2] = {0, 0};
   int nparts_x = 0;      // residual partials written by the X epilogue
-  int gk = 1;            // grid passes: 1 direct log-sum-exp, 2 tile-factored MFMA (FP32, axes % 16 == 0)
+  int gk = 1;            // grid passes: 1 direct log-sum-exp, 2 tile-factored MFMA where allowed
+  bool tf_axis[3] = {false, false, false};   // tile-factored pass used on this axis
   // workspace offsets
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
       o_gcost, o_obj, o_scal, total;
   int64_t obj_doubles = 0;
 };
 
-bool use_tf(const Plan& P, int axis) { return P.gk == 2 && P.dtype == UOT_F32 && P.n[axis] % 16 == 0; }
+bool use_tf(const Plan& P, int axis) { return P.tf_axis[axis]; }
 
-int grid_final_parts(const Plan& P) {
+// The tile-factored pass multiplies by Khat = 2^{2 c e f} with |e|, |f| <= 7.5
+// and c = h^2 log2(e) / eps; it is used on an axis only while 2 c 7.5^2 stays
+// far inside the FP32 range (c <= 0.5, i.e. |log2 Khat| <= 56.25) at the
+// smallest eps of the schedule, and only for FP32 axes of a multiple of 16 cells.
+constexpr double kTfMaxC = 0.5;
+
+int grid_final_parts_for(const Plan& P, bool tf0) {
   const int64_t nb = P.nb;
-  if (P.dim == 1)
-    return use_tf(P, 0) ? grid_tf_parts((int)P.n[0], nb, 1, false) : grid_contig_parts<float>((int)P.n[0], nb);
+  if (P.dim == 1) return tf0 ? grid_tf_parts((int)P.n[0], nb, 1, false) : grid_contig_parts<float>((int)P.n[0], nb);
   const int64_t B = P.dim == 2 ? P.n[1] : P.n[1] * P.n[2];
-  return use_tf(P, 0) ? grid_tf_parts((int)P.n[0], nb, B, true) : grid_strided_parts<float>((int)P.n[0], nb, B);
+  return tf0 ? grid_tf_parts((int)P.n[0], nb, B, true) : grid_strided_parts<float>((int)P.n[0], nb, B);
 }
+
+int grid_final_parts(const Plan& P) { return grid_final_parts_for(P, use_tf(P, 0)); }
 
 void dense_config(Plan& P, int side) {
   const int64_t Nr = side == 0 ? P.N : P.M;
@@ -157,10 +165,10 @@ void dense_config(Plan& P, int side) {
   P.cps[side] = cps;
 }
 
-int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_kernel = 0) {
+int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_kernel = 0, double eps_min = 0.0) {
   if (dtype != UOT_F32 && dtype != UOT_F64) return fail(UOT_E_INVALID, "dtype must be UOT_F32 or UOT_F64");
   if (grid_kernel < 0 || grid_kernel > 2) return fail(UOT_E_INVALID, "grid_kernel must be 0, 1 or 2");
-  P.gk = grid_kernel == 0 ? 1 : grid_kernel;
+  P.gk = grid_kernel == 0 ? (dtype == UOT_F32 ? 2 : 1) : grid_kernel;
   P.dtype = dtype;
   P.esz = dtype == UOT_F32 ? 4 : 8;
   P.geom = g.kind;
@@ -185,6 +193,9 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
     }
     if (g.dim == 3 && (int64_t)nb * g.n[0] > 65535) return fail(UOT_E_UNSUPPORTED, "fields x n[0] must be <= 65535");
     P.N = P.M = sz;
+    for (int k = 0; k < g.dim; ++k)
+      P.tf_axis[k] = P.gk == 2 && dtype == UOT_F32 && g.n[k] % 16 == 0 && eps_min > 0 &&
+                     g.h[k] * g.h[k] * kLog2e / eps_min <= kTfMaxC;
   } else {
     return fail(UOT_E_INVALID, "unknown geometry kind");
   }
@@ -217,7 +228,11 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
     P.o_pm = P.o_ps = take(0);
     P.nparts_x = grid_final_parts(P);
   }
-  P.o_parts = take(sizeof(ResPart) * std::max(P.nparts_x, 1));
+  // room for either pass kind, so a size query without eps fits every solve
+  const int parts_room = P.geom == UOT_GEOM_GRID
+                             ? std::max(grid_final_parts_for(P, false), P.n[0] % 16 == 0 ? grid_final_parts_for(P, true) : 0)
+                             : P.nparts_x;
+  P.o_parts = take(sizeof(ResPart) * std::max(parts_room, 1));
   for (int k = 0; k < 3; ++k) P.o_gtab[k] = take(P.geom == UOT_GEOM_GRID && k < P.dim ? e * (2 * P.n[k] - 1) * nst : 0);
   int64_t gmax = 1;
   for (int k = 0; k < P.dim; ++k) gmax = std::max(gmax, 2 * P.n[k] - 1);
@@ -469,7 +484,7 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
             uot_result* res, int nb = 1) {
   Plan P;
   const bool anneal = pr->eps0 > pr->eps && pr->eps_stages > 0 && pr->iters_per_stage > 0;
-  int rc = make_plan(P, pb->dtype, pb->geom, nb, anneal ? pr->eps_stages + 1 : 1, pr->grid_kernel);
+  int rc = make_plan(P, pb->dtype, pb->geom, nb, anneal ? pr->eps_stages + 1 : 1, pr->grid_kernel, pr->eps);
   if (rc) return rc;
   if ((rc = check_ws(P, ws, wsb))) return rc;
   if (!u || !v) return fail(UOT_E_INVALID, "u and v output buffers are required");
@@ -504,7 +519,7 @@ template <typename T>
 int half_step_t(uot_ctx* ctx, const uot_problem* pb, double eps, int side, const T* pot_in, T* pot_io, T* lse_out,
                 double* residual, char* ws, size_t wsb) {
   Plan P;
-  int rc = make_plan(P, pb->dtype, pb->geom, 1, 1);
+  int rc = make_plan(P, pb->dtype, pb->geom, 1, 1, 0, eps);
   if (rc) return rc;
   if ((rc = check_ws(P, ws, wsb))) return rc;
   if (!pot_in || !pot_io) return fail(UOT_E_INVALID, "pot_in and pot_io are required");
@@ -642,7 +657,7 @@ int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u,
            uot_result* res) {
   Plan P;
   const bool anneal = pr->eps0 > pr->eps && pr->eps_stages > 0 && pr->iters_per_stage > 0;
-  int rc = make_plan(P, pb->dtype, pb->geom, pb->n, anneal ? pr->eps_stages + 1 : 1, pr->grid_kernel);
+  int rc = make_plan(P, pb->dtype, pb->geom, pb->n, anneal ? pr->eps_stages + 1 : 1, pr->grid_kernel, pr->eps);
   if (rc) return rc;
   if ((rc = check_ws(P, ws, wsb))) return rc;
   if (!u || !v) return fail(UOT_E_INVALID, "u and v output buffers are required");
@@ -687,9 +702,9 @@ int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u,
 // HIP events around `reps` back-to-back launches of that kernel alone
 template <typename T>
 int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, double eps, const T* v, int reps, double* ms, int* nk,
-                     char* ws, size_t wsb) {
+                     char* ws, size_t wsb, int grid_kernel) {
   Plan P;
-  int rc = make_plan(P, pb->dtype, pb->geom, 1, 1);
+  int rc = make_plan(P, pb->dtype, pb->geom, 1, 1, grid_kernel, eps);
   if (rc) return rc;
   if ((rc = check_ws(P, ws, wsb))) return rc;
   if (!v || !ms || !nk || reps < 1) return fail(UOT_E_INVALID, "v, ms, n_kernels and reps >= 1 are required");
@@ -712,18 +727,18 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, double eps, const T* v
   if (P.geom == UOT_GEOM_GRID) {
     const int64_t nb = 1;
     if (P.dim == 1) {
-      ks.push_back([&] { launch_grid_contig<T>(B.wv, nb, (int)P.n[0], B.gtab[0], 0, B.ctrl, ep, s); });
+      ks.push_back([&] { contig_pass<T>(P, 0, B.wv, nb, B.gtab, 0, B.ctrl, ep, s); });
     } else if (P.dim == 2) {
       raw.out = B.t1;
-      ks.push_back([&] { launch_grid_contig<T>(B.wv, nb * P.n[0], (int)P.n[1], B.gtab[1], 0, B.ctrl, raw, s); });
-      ks.push_back([&] { launch_grid_strided<T>(B.t1, nb, (int)P.n[0], P.n[1], B.gtab[0], 0, B.ctrl, ep, s); });
+      ks.push_back([&] { contig_pass<T>(P, 1, B.wv, nb * P.n[0], B.gtab, 0, B.ctrl, raw, s); });
+      ks.push_back([&] { strided_pass<T>(P, 0, B.t1, nb, P.n[1], B.gtab, 0, B.ctrl, ep, s); });
     } else {
       EpiArgs<T> raw2 = raw;
       raw.out = B.t1;
       raw2.out = B.t2;
-      ks.push_back([&, raw] { launch_grid_contig<T>(B.wv, nb * P.n[0] * P.n[1], (int)P.n[2], B.gtab[2], 0, B.ctrl, raw, s); });
-      ks.push_back([&, raw2] { launch_grid_strided<T>(B.t1, nb * P.n[0], (int)P.n[1], P.n[2], B.gtab[1], 0, B.ctrl, raw2, s); });
-      ks.push_back([&] { launch_grid_strided<T>(B.t2, nb, (int)P.n[0], P.n[1] * P.n[2], B.gtab[0], 0, B.ctrl, ep, s); });
+      ks.push_back([&, raw] { contig_pass<T>(P, 2, B.wv, nb * P.n[0] * P.n[1], B.gtab, 0, B.ctrl, raw, s); });
+      ks.push_back([&, raw2] { strided_pass<T>(P, 1, B.t1, nb * P.n[0], P.n[2], B.gtab, 0, B.ctrl, raw2, s); });
+      ks.push_back([&] { strided_pass<T>(P, 0, B.t2, nb, P.n[1] * P.n[2], B.gtab, 0, B.ctrl, ep, s); });
     }
   } else {
     const T* rows = static_cast<const T*>(pb->geom.x);
@@ -1188,16 +1203,16 @@ int uot_objective(uot_ctx* ctx, const uot_problem* pb, double eps, const void* u
 }
 
 int uot_time_half_step(uot_ctx* ctx, const uot_problem* pb, double eps, const void* v, int reps, double* ms,
-                       int* n_kernels, void* ws, size_t wsb) {
+                       int* n_kernels, void* ws, size_t wsb, int grid_kernel) {
   if (!ctx) return fail(UOT_E_INVALID, "ctx is required");
   int rc = validate_problem(pb);
   if (rc) return rc;
   if (!(eps > 0)) return fail(UOT_E_INVALID, "eps must be > 0");
   if (pb->dtype == UOT_F32)
     return time_half_step_t<float>(ctx, pb, eps, static_cast<const float*>(v), reps, ms, n_kernels,
-                                   static_cast<char*>(ws), wsb);
+                                   static_cast<char*>(ws), wsb, grid_kernel);
   return time_half_step_t<double>(ctx, pb, eps, static_cast<const double*>(v), reps, ms, n_kernels,
-                                  static_cast<char*>(ws), wsb);
+                                  static_cast<char*>(ws), wsb, grid_kernel);
 }
 
 int uot_probe_rates(uot_ctx* ctx, double* exp_per_s, double* add_per_s) {

@@ -30,6 +30,7 @@ template <> struct Num<float> {
   static __device__ __forceinline__ float log(float x) { return ::logf(x); }
   static __device__ __forceinline__ float fmax(float a, float b) { return __builtin_fmaxf(a, b); }
   static __device__ __forceinline__ float fmin(float a, float b) { return __builtin_fminf(a, b); }
+  static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 };
 
 template <> struct Num<double> {
@@ -42,6 +43,7 @@ template <> struct Num<double> {
   static __device__ __forceinline__ double log(double x) { return ::log(x); }
   static __device__ __forceinline__ double fmax(double a, double b) { return __builtin_fmax(a, b); }
   static __device__ __forceinline__ double fmin(double a, double b) { return __builtin_fmin(a, b); }
+  static __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 };
 
 // ---------------------------------------------------------------------------
@@ -119,9 +121,9 @@ struct BItem {
   int32_t prob, row0, nrows, part;
 };
 
-// residual partial (per block): value = e^m * {den, num}
+// residual partial (per block): value = 2^m * {den, num} (m in log2 units)
 struct ResPart {
-  double m, den, num;
+  float m, den, num, pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -171,27 +173,30 @@ __device__ __forceinline__ void res_merge(T& m, T& den, T& num, T m2, T den2, T 
 }
 
 // Reduce (m, den, num) over a block of 256 threads (m in log2 units); thread
-// 0 writes the result.  Every thread of the block must call this.
+// 0 writes the result.  Every thread of the block must call this.  The
+// partials only feed the stopping test, so FP32 with the hardware exp2 is
+// enough (relative error ~1e-7 on r).
 template <typename T>
-__device__ __forceinline__ void block_res_reduce(T m, T den, T num, ResPart* out) {
-  __shared__ double sm[4][3];
+__device__ __forceinline__ void block_res_reduce(T m_in, T den_in, T num_in, ResPart* out) {
+  __shared__ float sm[4][3];
+  float m = float(m_in), den = float(den_in), num = float(num_in);
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
-    T m2 = __shfl_xor(m, off, 64);
-    T d2 = __shfl_xor(den, off, 64);
-    T n2 = __shfl_xor(num, off, 64);
-    res_merge(m, den, num, m2, d2, n2);
+    float m2 = __shfl_xor(m, off, 64);
+    float d2 = __shfl_xor(den, off, 64);
+    float n2 = __shfl_xor(num, off, 64);
+    res_merge<float>(m, den, num, m2, d2, n2);
   }
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    sm[w][0] = double(m);
-    sm[w][1] = double(den);
-    sm[w][2] = double(num);
+    sm[w][0] = m;
+    sm[w][1] = den;
+    sm[w][2] = num;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double M = sm[0][0], D = sm[0][1], U = sm[0][2];
-    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) res_merge<double>(M, D, U, sm[k][0], sm[k][1], sm[k][2]);
+    float M = sm[0][0], D = sm[0][1], U = sm[0][2];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) res_merge<float>(M, D, U, sm[k][0], sm[k][1], sm[k][2]);
     out->m = M;
     out->den = D;
     out->num = U;

@@ -349,9 +349,9 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
         for (int k = 0; k < kChunk; ++k) {
           T d0 = xi[r][0] - q[k].x;
           T cst = d0 * d0;
-          if (DIM > 1) { T d1 = xi[r][1] - q[k].y; cst = __builtin_fma(d1, d1, cst); }
-          if (DIM > 2) { T d2 = xi[r][2] - q[k].z; cst = __builtin_fma(d2, d2, cst); }
-          t[k] = __builtin_fma(-sc, cst, q[k].w);
+          if (DIM > 1) { T d1 = xi[r][1] - q[k].y; cst = Num<T>::fma(d1, d1, cst); }
+          if (DIM > 2) { T d2 = xi[r][2] - q[k].z; cst = Num<T>::fma(d2, d2, cst); }
+          t[k] = Num<T>::fma(-sc, cst, q[k].w);
         }
         acc[r].template add<kChunk>(t);
       }
@@ -398,37 +398,37 @@ __global__ __launch_bounds__(kBlock) void k_control(Ctrl* __restrict__ c, const 
   // nfields == 0: one residual over all partials; nfields > 0: the partials
   // form nfields equal contiguous ranges (one per field) and r is the largest
   // per-field residual
-  __shared__ double sm[kBlock][3];
-  __shared__ double smax[kBlock];
-  double rmax = -1.0;
+  __shared__ float sm[kBlock][3];
+  __shared__ float smax[kBlock];
+  float rmax = -1.0f;
   if (nfields > 0) {
     const int per = nparts / nfields;
     for (int f = threadIdx.x; f < nfields; f += kBlock) {
-      double m = -__builtin_inf(), den = 0.0, num = 0.0;
-      for (int k = f * per; k < (f + 1) * per; ++k) res_merge<double>(m, den, num, part[k].m, part[k].den, part[k].num);
-      const double rf = num / den;
+      float m = -__builtin_inff(), den = 0.f, num = 0.f;
+      for (int k = f * per; k < (f + 1) * per; ++k) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
+      const float rf = num / den;
       rmax = (rf != rf || rmax != rmax) ? rf : (rf > rmax ? rf : rmax);
     }
     smax[threadIdx.x] = rmax;
     __syncthreads();
     for (int off = kBlock / 2; off >= 1; off >>= 1) {
       if ((int)threadIdx.x < off) {
-        const double a = smax[threadIdx.x], b = smax[threadIdx.x + off];
+        const float a = smax[threadIdx.x], b = smax[threadIdx.x + off];
         smax[threadIdx.x] = (a != a || b != b) ? (a != a ? a : b) : (a > b ? a : b);
       }
       __syncthreads();
     }
   } else {
-    double m = -__builtin_inf(), den = 0.0, num = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += kBlock) res_merge<double>(m, den, num, part[k].m, part[k].den, part[k].num);
+    float m = -__builtin_inff(), den = 0.f, num = 0.f;
+    for (int k = threadIdx.x; k < nparts; k += kBlock) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
     sm[threadIdx.x][0] = m;
     sm[threadIdx.x][1] = den;
     sm[threadIdx.x][2] = num;
     __syncthreads();
     for (int off = kBlock / 2; off >= 1; off >>= 1) {
       if ((int)threadIdx.x < off) {
-        double M = sm[threadIdx.x][0], D = sm[threadIdx.x][1], U = sm[threadIdx.x][2];
-        res_merge<double>(M, D, U, sm[threadIdx.x + off][0], sm[threadIdx.x + off][1], sm[threadIdx.x + off][2]);
+        float M = sm[threadIdx.x][0], D = sm[threadIdx.x][1], U = sm[threadIdx.x][2];
+        res_merge<float>(M, D, U, sm[threadIdx.x + off][0], sm[threadIdx.x + off][1], sm[threadIdx.x + off][2]);
         sm[threadIdx.x][0] = M;
         sm[threadIdx.x][1] = D;
         sm[threadIdx.x][2] = U;
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_control(Ctrl* __restrict__ c, const 
     }
   }
   if (threadIdx.x != 0) return;
-  const double r = nfields > 0 ? smax[0] : sm[0][2] / sm[0][1];
+  const double r = nfields > 0 ? double(smax[0]) : double(sm[0][2]) / double(sm[0][1]);
   const int64_t l = c->iter;
   if (hist) hist[l] = r;
   c->res = r;
@@ -941,9 +941,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_lse(const BItem* __restrict__ 
           for (int k = 0; k < kChunk; ++k) {
             T d0 = xi[r][0] - q[k].x;
             T cst = d0 * d0;
-            if (DIM > 1) { T d1 = xi[r][1] - q[k].y; cst = __builtin_fma(d1, d1, cst); }
-            if (DIM > 2) { T d2 = xi[r][2] - q[k].z; cst = __builtin_fma(d2, d2, cst); }
-            t[k] = __builtin_fma(-sc, cst, q[k].w);
+            if (DIM > 1) { T d1 = xi[r][1] - q[k].y; cst = Num<T>::fma(d1, d1, cst); }
+            if (DIM > 2) { T d2 = xi[r][2] - q[k].z; cst = Num<T>::fma(d2, d2, cst); }
+            t[k] = Num<T>::fma(-sc, cst, q[k].w);
           }
           acc[r].template add<kChunk>(t);
         }
@@ -976,9 +976,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_control(Ctrl* __restrict__ c, 
     return;
   }
   bc->yskip[b] = 0;
-  double m = -__builtin_inf(), den = 0.0, num = 0.0;
-  for (int k = pstart[b]; k < pstart[b + 1]; ++k) res_merge<double>(m, den, num, part[k].m, part[k].den, part[k].num);
-  const double r = num / den;
+  float m = -__builtin_inff(), den = 0.f, num = 0.f;
+  for (int k = pstart[b]; k < pstart[b + 1]; ++k) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
+  const double r = double(num) / double(den);
   const int64_t l = bc->iters[b];
   bc->res[b] = r;
   bc->iters[b] = l + 1;

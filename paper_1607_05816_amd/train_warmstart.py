@@ -101,7 +101,8 @@ def main():
     V, infos = W.solve_pairs(P, Q, dev)
     torch.cuda.synchronize()
     solve_s = time.perf_counter() - t1
-    log("solved %d pairs in %.1f s (iterations per batch: %s)" % (args.pairs, solve_s, [i["iters"] for i in infos]))
+    log("solved %d pairs in %.1f s (%d iterations per batch; largest per-field residual of the last iteration "
+        "per batch: %s)" % (args.pairs, solve_s, W.SOLVE_ITERS, ["%.1e" % i["residual"] for i in infos]))
     X = W.features(P, Q, W.RES, dev)
     ntr = args.pairs - args.val
     net = U.WarmStartNet(2 * W.RES * W.RES, WIDTH, W.RES * W.RES, dev, seed=0, in_scale=W.IN_SCALE,
@@ -118,6 +119,7 @@ def main():
                           ms_mean=float(np.mean([r[k]["ms"] for r in rows])),
                           all_converged=all(r[k]["converged"] for r in rows))
     report = dict(pairs=args.pairs, solve_seconds=solve_s, solve_iters=[int(i["iters"]) for i in infos],
+                  solve_final_max_residual=[float(i["residual"]) for i in infos],
                   train_seconds=tl.seconds, train_steps=tl.steps, val_loss=tl.val_loss, train_loss=tl.train_loss,
                   val_target_mean_square=vscale, eval=rows, summary=summary)
     log(json.dumps(summary))

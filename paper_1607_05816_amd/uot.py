@@ -109,7 +109,7 @@ def lib():
         "uot_barycenter": (c_i32, [c_vp, P(UotBaryProblem), P(UotParams), c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t,
                                    P(UotResult)]),
         "uot_time_half_step": (c_i32, [c_vp, P(UotProblem), c_dbl, c_vp, c_i32, P(c_dbl), P(c_i32), c_vp,
-                                       ctypes.c_size_t]),
+                                       ctypes.c_size_t, c_i32]),
         "uot_probe_rates": (c_i32, [c_vp, P(c_dbl), P(c_dbl)]),
         "uot_fields_workspace_size": (c_i32, [P(UotProblem), c_i32, P(ctypes.c_size_t)]),
         "uot_solve_fields": (c_i32, [c_vp, P(UotProblem), c_i32, P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t,
@@ -416,7 +416,7 @@ def barycenter(shape, h, p, alpha, dx, dy, F1: Div, F2: Div, eps, ctx: Optional[
     return u, v, logh, info
 
 
-def time_half_step(prob: Problem, eps, v, reps=50, ctx: Optional[Context] = None):
+def time_half_step(prob: Problem, eps, v, reps=50, ctx: Optional[Context] = None, grid_kernel=0):
     """Average ms of each Gibbs-product kernel of one X half-step (HIP events)."""
     ctx = ctx or default_context()
     _dev(v, prob.dtype, prob.M, "v")
@@ -424,7 +424,8 @@ def time_half_step(prob: Problem, eps, v, reps=50, ctx: Optional[Context] = None
     nk = c_i32()
     ws = prob.workspace()
     _check(lib().uot_time_half_step(ctx.handle, ctypes.byref(prob.c), float(eps), _ptr(v), int(reps), ms,
-                                    ctypes.byref(nk), _ptr(ws), ws.numel()), "uot_time_half_step", False)
+                                    ctypes.byref(nk), _ptr(ws), ws.numel(), int(grid_kernel)),
+           "uot_time_half_step", False)
     return [ms[k] for k in range(nk.value)]
 
 

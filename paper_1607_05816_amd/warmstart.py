@@ -42,9 +42,17 @@ def pair_densities(seeds, res=RES):
     return P, Q
 
 
+SOLVE_ITERS = 2600
+
+
 def solve_pairs(P, Q, device, batch=2048, res=RES, ctx=None):
     """Targets: v of UOT(p, q) (KL lambda=0.5 both sides, eps=2e-3, eps-scaling
-    from 1e-1) for every pair, solved batch by batch on the grid.
+    from 1e-1: 1000 annealing iterations) for every pair, solved batch by batch
+    on the grid for a fixed 2600 iterations.  At this eps the FP32 fixed point
+    carries a residual noise floor near 1e-6 for some fields, so a batch that
+    waits for its largest per-field residual to reach 1e-6 may never stop;
+    2600 iterations bring every field to that floor (the largest per-field
+    residual of the last iteration is reported).
     Returns (V on device, list of per-batch info)."""
     h = (1.0 / res, 1.0 / res)
     d = torch.full((res * res,), h[0] * h[1], dtype=torch.float32, device=device)
@@ -54,8 +62,8 @@ def solve_pairs(P, Q, device, batch=2048, res=RES, ctx=None):
     for a in range(0, P.shape[0], batch):
         p = torch.tensor(P[a:a + batch], device=device)
         q = torch.tensor(Q[a:a + batch], device=device)
-        _, v, info = U.solve_fields((res, res), h, p, q, d, d, F, F, EPS, eps0=EPS0, tol=TOL, max_iter=20000,
-                                    check_every=100, ctx=ctx)
+        _, v, info = U.solve_fields((res, res), h, p, q, d, d, F, F, EPS, eps0=EPS0, tol=0.0,
+                                    max_iter=SOLVE_ITERS, check_every=100, ctx=ctx)
         out[a:a + batch] = v
         infos.append(info)
     return out, infos

@@ -77,7 +77,9 @@ def test_hist1d_fp64_fixed_iterations_and_converged():
         assert info["iters"] == 40
         assert pot_rel_err(u.cpu(), ref["u"], 1e-2) < 1e-11
         assert pot_rel_err(v.cpu(), ref["v"], 1e-2) < 1e-11
-        np.testing.assert_allclose(info["res_hist"].numpy()[1:], ref["res"][1:], rtol=1e-8)
+        # residual partials are merged in FP32 on the device (they only feed the
+        # stopping test): 1e-6 relative on r
+        np.testing.assert_allclose(info["res_hist"].numpy()[1:], ref["res"][1:], rtol=1e-6)
         # converged to 1e-9
         u, v, info = U.solve(prob, 1e-2, tol=1e-9, max_iter=5000)
         ref = oracle_points_run(xs, xs, pr.p, pr.q, dxv, dxv, F, F, 1e-2, 5000, tol=1e-9)
