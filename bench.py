@@ -60,6 +60,77 @@ def cpu_baseline(prob_np, budget_s=15.0):
                        "(numpy FP64, one thread), %.1f s" % (it, dt))
 
 
+def warm_batched(U, ctx, dev, np, torch):
+    """Warm+batched forms against the plain cold single-problem iteration:
+    (a) ragged batch of 4096 point-cloud problems (N, M log-uniform on
+        [64, 4096], uniform points in [0,1]^2, KL 1, eps 5e-3, tol 1e-6) in
+        one persistent launch per half-step vs plain solves of a 16-problem
+        sample (extrapolated);
+    (b) unbalanced barycentre of 8 blob images at 128 x 128 (KL 0.5, eps 2e-3,
+        tol 1e-6): plain = cold start with eps-scaling, warm = v^(0) from the
+        trained network (no annealing)."""
+    from paper_1607_05816_amd import synth, warmstart as W
+    from paper_1607_05816_amd.train_warmstart import load_weights
+    out = {}
+    probs = synth.ragged_batch(0, B=4096)
+    Ns = [p.x.shape[0] for p in probs]
+    Ms = [p.y.shape[0] for p in probs]
+    cat = lambda f: torch.tensor(np.concatenate([f(p) for p in probs]).astype(np.float32), device=dev)
+    F = U.KL(1.0)
+    bp = U.BatchProblem(Ns, Ms, cat(lambda p: p.x), cat(lambda p: p.y), cat(lambda p: p.p), cat(lambda p: p.q),
+                        cat(lambda p: p.dx), cat(lambda p: p.dy), F, F)
+    U.solve_batched(bp, 5e-3, tol=1e-6, max_iter=20000, check_every=50, ctx=ctx)       # tunes, warms
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, info = U.solve_batched(bp, 5e-3, tol=1e-6, max_iter=20000, check_every=50, ctx=ctx)
+    torch.cuda.synchronize()
+    bs = time.perf_counter() - t0
+    it = info["iters"]
+    pairs = np.array(Ns, float) * np.array(Ms, float)
+    rng = np.random.default_rng(1)
+    idx = rng.choice(len(probs), 16, replace=False)
+    plain = 0.0
+    T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
+    for k in idx:
+        p = probs[k]
+        pb = U.points_problem(T(p.x), T(p.y), T(p.p), T(p.q), T(p.dx), T(p.dy), F, F)
+        pb.workspace()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        U.solve(pb, 5e-3, tol=1e-6, max_iter=20000, check_every=50, ctx=ctx)
+        torch.cuda.synchronize()
+        plain += time.perf_counter() - a
+    plain_per = plain / len(idx)
+    out["ragged_batch_4096"] = {
+        "converged": int(info["n_converged"]), "problems": len(probs), "seconds": bs,
+        "problems_per_s": len(probs) / bs, "problem_iters_per_s": float(it.sum()) / bs,
+        "pair_evals_per_s": float((pairs * it).sum()) * 2 / bs,
+        "latency_ms_p50": float(np.percentile(info["latency_ms"], 50)),
+        "latency_ms_p99": float(np.percentile(info["latency_ms"], 99)),
+        "tile_rows": info["tile_rows"], "blocks_per_cu": info["blocks_per_cu"],
+        "plain_ms_per_problem_sample16": plain_per * 1e3,
+        "speedup_vs_plain": plain_per * len(probs) / bs}
+    net = load_weights(os.path.join(ROOT, "paper_1607_05816_amd", "data", "warmstart_mlp64.npz"), dev)
+    pr = synth.bary_blobs(0, n_marg=8, n=128)
+    p = torch.tensor(pr.p, dtype=torch.float32, device=dev)
+    res = {}
+    for name in ("plain_cold_eps_scaling", "warm"):
+        for rep in range(2):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            if name == "warm":
+                v0 = W.barycenter_v0(net, p, pr.alpha, 128, ctx=ctx)
+                _, _, _, bi = W.barycenter_solve(p, pr.alpha, 128, v0=v0.contiguous(), ctx=ctx)
+            else:
+                _, _, _, bi = W.barycenter_solve(p, pr.alpha, 128, eps0=W.EPS0, ctx=ctx)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - a) * 1e3
+        res[name] = {"iters": int(bi["iters"]), "ms": ms, "converged": bool(bi["converged"])}
+    res["speedup"] = res["plain_cold_eps_scaling"]["ms"] / res["warm"]["ms"]
+    out["barycenter_8x128"] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +139,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-warm-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -158,6 +230,8 @@ def main():
         "gap": {o[0]: o[2]["gap"] for o in last},
         "roofline": roofline,
     }
+    if not args.no_warm_batched:
+        line["warm_batched_vs_plain"] = warm_batched(U, ctx, dev, np, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pr, args.cpu_budget)
     print(json.dumps(line), flush=True)

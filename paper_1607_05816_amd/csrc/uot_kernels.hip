@@ -389,12 +389,12 @@ __global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, 
 // control kernel (one block), between the X and the Y half-step: reduce the
 // residual partials, count the iteration, pick the next eps, set stop flags.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_control(Ctrl* __restrict__ c, const ResPart* __restrict__ part,
-                                                     int nparts, double* __restrict__ hist, int nfields) {
-  if (c->stop) {
-    if (threadIdx.x == 0) c->yskip = 1;
-    return;
-  }
+// control step (one block of 256 threads): reduce the residual partials,
+// count the iteration, pick the next eps, set the stop flag.  (Folding this
+// step into the last block of the final pass needs a device-scope fence in
+// every block, which on a multi-XCD MI355X costs more than the launch.)
+__device__ void control_step(Ctrl* __restrict__ c, const ResPart* __restrict__ part, int nparts,
+                             double* __restrict__ hist, int nfields) {
   // nfields == 0: one residual over all partials; nfields > 0: the partials
   // form nfields equal contiguous ranges (one per field) and r is the largest
   // per-field residual
@@ -460,6 +460,15 @@ __global__ __launch_bounds__(kBlock) void k_control(Ctrl* __restrict__ c, const 
     c->stop = 1;
     c->status = 1;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_control(Ctrl* __restrict__ c, const ResPart* __restrict__ part,
+                                                     int nparts, double* __restrict__ hist, int nfields) {
+  if (c->stop) {
+    if (threadIdx.x == 0) c->yskip = 1;
+    return;
+  }
+  control_step(c, part, nparts, hist, nfields);
 }
 
 // plain reduction of residual partials into out[0] (single half-step entry)
@@ -1129,7 +1138,21 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
     S[r] = 0.f;
   }
   const int nt = n / 16;
-  for (int jt = wv; jt < nt; jt += 4) {
+  // the wave's tap tiles jt = wv, wv + 4, ... in chunks of 4: the 16 loads of
+  // a chunk are issued together, then the chunk is computed
+  for (int jc = wv; jc < nt; jc += 16) {
+    float wv4[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int jt = jc + 4 * t;
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        wv4[t][s] = (valid && jt < nt) ? in[base + (int64_t)(jt * 16 + 4 * s + q) * tstride] : -__builtin_inff();
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+    const int jt = jc + 4 * t;
+    if (jt >= nt) break;
     const int J0 = jt * 16;
     const float D = float(I0 - J0);
     // column factors for taps b = 4 s + q of this lane's line
@@ -1138,8 +1161,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const float f = float(4 * s + q) - 7.5f;
-      const float w = valid ? in[base + (int64_t)(J0 + 4 * s + q) * tstride] : -__builtin_inff();
-      beta[s] = w - cc * (f * (f - 2.f * D));
+      beta[s] = wv4[t][s] - cc * (f * (f - 2.f * D));
       mloc = fmaxf(mloc, beta[s]);
     }
     // max over the 16 taps of the line: the four lane groups q share a line
@@ -1162,6 +1184,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
       const float sh = (mn == -__builtin_inff()) ? 0.f : mn;
       S[r] = S[r] * __builtin_amdgcn_exp2f(M[r] - sh) + acc[r] * __builtin_amdgcn_exp2f(al - sh);
       M[r] = mn;
+    }
     }
   }
   // merge the four waves (each saw a quarter of the J tiles)
