@@ -131,6 +131,55 @@ def warm_batched(U, ctx, dev, np, torch):
     return out
 
 
+PASS_NAMES = ["k_grid_tf<false, 4>", "k_grid_tf<true, 4>"]
+
+
+def exp2_executed_per_launch(lines, n, tpc=4):
+    """exp2 instructions one tile-factored pass executes, counted from the
+    kernel, per (line, 16-cell output tile): 16 column factors per tap tile,
+    16 (1 + tpc) per chunk of tpc tap tiles for the online combination, 64
+    for the Khat operands and 96 for merging the four waves."""
+    nt = n // 16
+    return float(lines) * nt * (nt * 16 + (nt // tpc) * 16 * (1 + tpc) + 64 + 96)
+
+
+def grid_roofline(U, probs, last, ctx, torch, np, nb_fields=256):
+    """Roofline of the dominant kernel: the two Gibbs-product passes of one X
+    half-step at the final eps (KL problem, converged v), each launched back
+    to back between two HIP events on the library stream.  Algorithmic work
+    of a pass = one exp per tap, n1 n2 n taps per field (the separable
+    product written as direct log-sum-exps), priced against the v_exp_f32
+    issue peak.  Measured on the single 256 x 256 problem of the headline
+    (latency-bound: 256 blocks, one per CU) and on a batch of nb_fields
+    fields of the same size in one launch (throughput-bound)."""
+    ms = U.time_half_step(probs[0][1], EPS, last[0][3], reps=200, ctx=ctx)
+    k = int(np.argmax(ms))
+    taps = float(N_GRID) ** 3
+    peak = exp_peak()
+    out = {"bound": "alu", "achieved": taps / (ms[k] * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "Texp/s",
+           "frac": taps / (ms[k] * 1e-3) / peak, "traffic": None, "kernel": PASS_NAMES[k], "kernel_avg_ms": ms[k],
+           "work_per_launch": taps, "work_unit": "exp (one per tap: n1 n2 n)",
+           "exp2_executed_per_launch": exp2_executed_per_launch(N_GRID, N_GRID),
+           "avg_ms_by_kernel": dict(zip(PASS_NAMES, ms)), "launch": "single 256x256 problem"}
+    out["executed_exp2_frac"] = out["exp2_executed_per_launch"] / (ms[k] * 1e-3) / peak
+    pb = probs[0][1]
+    p = pb.p.reshape(1, -1).expand(nb_fields, -1).contiguous()
+    v = last[0][3].reshape(1, -1).expand(nb_fields, -1).contiguous()
+    h = (1.0 / N_GRID, 1.0 / N_GRID)
+    msb = U.time_fields_half_step((N_GRID, N_GRID), h, p, pb.dx, pb.dy, U.KL(PENALTIES[0][1]), EPS, v, reps=20,
+                                  ctx=ctx)
+    kb = int(np.argmax(msb))
+    tb = taps * nb_fields
+    out["batched"] = {"fields": nb_fields, "kernel": PASS_NAMES[kb], "kernel_avg_ms": msb[kb],
+                      "achieved": tb / (msb[kb] * 1e-3) / 1e12, "frac": tb / (msb[kb] * 1e-3) / peak,
+                      "work_per_launch": tb, "avg_ms_by_kernel": dict(zip(PASS_NAMES, msb)),
+                      "exp2_executed_per_launch": exp2_executed_per_launch(nb_fields * N_GRID, N_GRID)}
+    out["batched"]["executed_exp2_frac"] = out["batched"]["exp2_executed_per_launch"] / (msb[kb] * 1e-3) / peak
+    del p, v
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,27 +236,7 @@ def main():
     dt = time.perf_counter() - t0
     converged = all(o[1]["converged"] for o in last)
 
-    # roofline of the dominant kernel: the Gibbs-product kernels of one X
-    # half-step at the final eps (KL problem, converged v), each launched 200
-    # times back to back between two HIP events on the library stream.
-    # For an FP32 256 x 256 grid both passes are tile-factored MFMA passes
-    # (k_grid_tf<false> along the contiguous axis, k_grid_tf<true> along the
-    # strided one); per (line, 16-cell output tile, 16-cell tap tile) a pass
-    # evaluates 16 exp2 for the column factors and 2 x 16 for the online
-    # combination of the output tile: 48 exp2.
-    ms = U.time_half_step(probs[0][1], EPS, last[0][3], reps=200, ctx=ctx)
-    names = ["k_grid_tf<false>", "k_grid_tf<true>"]
-    k = int(np.argmax(ms))
-    nt = N_GRID // 16
-    exps = float(N_GRID) * nt * nt * 48           # per launch: lines x tiles x tiles x 48
-    taps = float(N_GRID) ** 3                     # the same product as n1 n2 n direct taps
-    achieved = exps / (ms[k] * 1e-3)
-    peak = exp_peak()
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "Texp/s",
-                "frac": achieved / peak, "traffic": None, "kernel": names[k], "kernel_avg_ms": ms[k],
-                "exp2_per_launch": exps, "taps_per_s": taps / (ms[k] * 1e-3),
-                "avg_ms_by_kernel": dict(zip(names, ms))}
-
+    roofline = grid_roofline(U, probs, last, ctx, torch, np)
     line = {
         "metric": "Sinkhorn iters/s and time-to-residual 1e-6 (2-D grid 256x256, KL+TV, eps 1e-1->1e-3)",
         "value": iters / dt,

@@ -354,6 +354,12 @@ int uot_gemm_bf16(uot_ctx *ctx, int ta, int tb, int M, int N, int K, const uint1
 int uot_time_half_step(uot_ctx *ctx, const uot_problem *pb, double eps, const void *v,
                        int reps, double *ms, int *n_kernels, void *ws, size_t ws_bytes,
                        int grid_kernel);   /* as uot_params.grid_kernel */
+/* The same over nb fields on one grid (the layout of uot_solve_fields: pb->p
+ * is nb x size, v is nb x size, workspace from uot_fields_workspace_size);
+ * every launch processes all nb fields.  nb = 1 is uot_time_half_step. */
+int uot_time_fields_half_step(uot_ctx *ctx, const uot_problem *pb, int nb, double eps,
+                              const void *v, int reps, double *ms, int *n_kernels, void *ws,
+                              size_t ws_bytes, int grid_kernel);
 
 /* Throughput probe of the current device: v_exp_f32 results per second and
  * v_add_f32 results per second, from 8 independent dependency chains per lane

@@ -698,13 +698,15 @@ int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u,
   return res->status == 0 ? UOT_OK : UOT_NOT_CONVERGED;
 }
 
-// average device time of each Gibbs-product kernel of one X half-step, with
-// HIP events around `reps` back-to-back launches of that kernel alone
+// average device time of each Gibbs-product kernel of one X half-step over nb
+// fields (grids; points: nb = 1), with HIP events around `reps` back-to-back
+// launches of that kernel alone
 template <typename T>
-int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, double eps, const T* v, int reps, double* ms, int* nk,
-                     char* ws, size_t wsb, int grid_kernel) {
+int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, const T* v, int reps, double* ms,
+                     int* nk, char* ws, size_t wsb, int grid_kernel) {
   Plan P;
-  int rc = make_plan(P, pb->dtype, pb->geom, 1, 1, grid_kernel, eps);
+  if (nb < 1) return fail(UOT_E_INVALID, "nb must be >= 1");
+  int rc = make_plan(P, pb->dtype, pb->geom, nb, 1, grid_kernel, eps);
   if (rc) return rc;
   if ((rc = check_ws(P, ws, wsb))) return rc;
   if (!v || !ms || !nk || reps < 1) return fail(UOT_E_INVALID, "v, ms, n_kernels and reps >= 1 are required");
@@ -713,32 +715,32 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, double eps, const T* v
   Bufs<T> B = carve<T>(P, ws);
   Ctrl init = make_ctrl(eps, 0, 0, 0, 0, 1);
   launch_ctrl_init(B.ctrl, init, s);
-  launch_log<T>(static_cast<const T*>(pb->p), B.logp, P.N, 1, s);
+  launch_log<T>(static_cast<const T*>(pb->p), B.logp, nb * P.N, 1, s);
   launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, P.N, 0, s);
   launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
   if (P.geom == UOT_GEOM_GRID)
     for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, 1, s);
-  launch_init_pot<T>(v, B.logdy, nullptr, B.wv, P.M, P.M, B.ctrl, 0, s);
-  launch_init_pot<T>(nullptr, B.logdx, B.t3, nullptr, P.N, P.N, B.ctrl, 0, s);   // u = 0 in t3
+  launch_init_pot<T>(v, B.logdy, nullptr, B.wv, nb * P.M, P.M, B.ctrl, 0, s);
+  launch_init_pot<T>(nullptr, B.logdx, B.t3, nullptr, nb * P.N, P.N, B.ctrl, 0, s);   // u = 0 in t3
   EpiArgs<T> ep = prox_epi<T>(B.t3, B.wu, B.logp, B.logdx, nullptr, B.parts, P.N, pb->F1);
   EpiArgs<T> raw{};
   raw.mode = EPI_RAW;
   std::vector<std::function<void()>> ks;
   if (P.geom == UOT_GEOM_GRID) {
-    const int64_t nb = 1;
+    const int64_t nbf = nb;
     if (P.dim == 1) {
-      ks.push_back([&] { contig_pass<T>(P, 0, B.wv, nb, B.gtab, 0, B.ctrl, ep, s); });
+      ks.push_back([&] { contig_pass<T>(P, 0, B.wv, nbf, B.gtab, 0, B.ctrl, ep, s); });
     } else if (P.dim == 2) {
       raw.out = B.t1;
-      ks.push_back([&] { contig_pass<T>(P, 1, B.wv, nb * P.n[0], B.gtab, 0, B.ctrl, raw, s); });
-      ks.push_back([&] { strided_pass<T>(P, 0, B.t1, nb, P.n[1], B.gtab, 0, B.ctrl, ep, s); });
+      ks.push_back([&] { contig_pass<T>(P, 1, B.wv, nbf * P.n[0], B.gtab, 0, B.ctrl, raw, s); });
+      ks.push_back([&] { strided_pass<T>(P, 0, B.t1, nbf, P.n[1], B.gtab, 0, B.ctrl, ep, s); });
     } else {
       EpiArgs<T> raw2 = raw;
       raw.out = B.t1;
       raw2.out = B.t2;
-      ks.push_back([&, raw] { contig_pass<T>(P, 2, B.wv, nb * P.n[0] * P.n[1], B.gtab, 0, B.ctrl, raw, s); });
-      ks.push_back([&, raw2] { strided_pass<T>(P, 1, B.t1, nb * P.n[0], P.n[2], B.gtab, 0, B.ctrl, raw2, s); });
-      ks.push_back([&] { strided_pass<T>(P, 0, B.t2, nb, P.n[1] * P.n[2], B.gtab, 0, B.ctrl, ep, s); });
+      ks.push_back([&, raw] { contig_pass<T>(P, 2, B.wv, nbf * P.n[0] * P.n[1], B.gtab, 0, B.ctrl, raw, s); });
+      ks.push_back([&, raw2] { strided_pass<T>(P, 1, B.t1, nbf * P.n[0], P.n[2], B.gtab, 0, B.ctrl, raw2, s); });
+      ks.push_back([&] { strided_pass<T>(P, 0, B.t2, nbf, P.n[1] * P.n[2], B.gtab, 0, B.ctrl, ep, s); });
     }
   } else {
     const T* rows = static_cast<const T*>(pb->geom.x);
@@ -1202,17 +1204,22 @@ int uot_objective(uot_ctx* ctx, const uot_problem* pb, double eps, const void* u
                              static_cast<double*>(pi1), static_cast<double*>(pi2), out, static_cast<char*>(ws), wsb);
 }
 
-int uot_time_half_step(uot_ctx* ctx, const uot_problem* pb, double eps, const void* v, int reps, double* ms,
-                       int* n_kernels, void* ws, size_t wsb, int grid_kernel) {
+int uot_time_fields_half_step(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, const void* v, int reps,
+                              double* ms, int* n_kernels, void* ws, size_t wsb, int grid_kernel) {
   if (!ctx) return fail(UOT_E_INVALID, "ctx is required");
   int rc = validate_problem(pb);
   if (rc) return rc;
   if (!(eps > 0)) return fail(UOT_E_INVALID, "eps must be > 0");
   if (pb->dtype == UOT_F32)
-    return time_half_step_t<float>(ctx, pb, eps, static_cast<const float*>(v), reps, ms, n_kernels,
+    return time_half_step_t<float>(ctx, pb, nb, eps, static_cast<const float*>(v), reps, ms, n_kernels,
                                    static_cast<char*>(ws), wsb, grid_kernel);
-  return time_half_step_t<double>(ctx, pb, eps, static_cast<const double*>(v), reps, ms, n_kernels,
+  return time_half_step_t<double>(ctx, pb, nb, eps, static_cast<const double*>(v), reps, ms, n_kernels,
                                   static_cast<char*>(ws), wsb, grid_kernel);
+}
+
+int uot_time_half_step(uot_ctx* ctx, const uot_problem* pb, double eps, const void* v, int reps, double* ms,
+                       int* n_kernels, void* ws, size_t wsb, int grid_kernel) {
+  return uot_time_fields_half_step(ctx, pb, 1, eps, v, reps, ms, n_kernels, ws, wsb, grid_kernel);
 }
 
 int uot_probe_rates(uot_ctx* ctx, double* exp_per_s, double* add_per_s) {

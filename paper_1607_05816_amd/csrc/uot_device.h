@@ -172,6 +172,72 @@ __device__ __forceinline__ void res_merge(T& m, T& den, T& num, T m2, T den2, T 
   m = mn;
 }
 
+// Cross-lane exchanges that stay in the VALU (no LDS crossbar).
+//   lane_xor16 / lane_xor32 (gfx950 v_permlane16_swap / v_permlane32_swap):
+//     with both operands x, the swap leaves x and its partner at distance
+//     16 (32) in the two results, in some order; callers combine the pair
+//     with a symmetric operation, so the order does not matter.
+//   dpp_* : row-local DPP moves (quad_perm [1,0,3,2], [2,3,0,1], row half
+//     mirror, row mirror) that complete a reduction over a row of 16 lanes.
+struct LanePair {
+  float a, b;
+};
+__device__ __forceinline__ LanePair lane_xor16(float x) {
+  const unsigned u = __float_as_uint(x);
+  const auto p = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  return {__uint_as_float(p[0]), __uint_as_float(p[1])};
+}
+__device__ __forceinline__ LanePair lane_xor32(float x) {
+  const unsigned u = __float_as_uint(x);
+  const auto p = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  return {__uint_as_float(p[0]), __uint_as_float(p[1])};
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i of 8 <- lane 7 - i
+constexpr int kDppMirror = 0x140;      // lane i of 16 <- lane 15 - i
+
+// max over the four lanes l % 16 + {0, 16, 32, 48}
+__device__ __forceinline__ float max_over_rows(float x) {
+  const LanePair p = lane_xor16(x);
+  const float y = fmaxf(p.a, p.b);
+  const LanePair r = lane_xor32(y);
+  return fmaxf(r.a, r.b);
+}
+
+// Reduce (m, den, num) over a wave with res_merge; every lane ends with the
+// wave total (up to rounding order).
+__device__ __forceinline__ void wave_res_reduce(float& m, float& den, float& num) {
+#define UOT_RES_STEP(MOVE)                                  \
+  {                                                         \
+    const float m2 = MOVE(m), d2 = MOVE(den), n2 = MOVE(num); \
+    res_merge<float>(m, den, num, m2, d2, n2);              \
+  }
+  UOT_RES_STEP(dpp_mov<kDppXor1>)
+  UOT_RES_STEP(dpp_mov<kDppXor2>)
+  UOT_RES_STEP(dpp_mov<kDppHalfMirror>)
+  UOT_RES_STEP(dpp_mov<kDppMirror>)
+#undef UOT_RES_STEP
+  {
+    const LanePair pm = lane_xor16(m), pd = lane_xor16(den), pn = lane_xor16(num);
+    m = pm.a;
+    den = pd.a;
+    num = pn.a;
+    res_merge<float>(m, den, num, pm.b, pd.b, pn.b);
+  }
+  {
+    const LanePair pm = lane_xor32(m), pd = lane_xor32(den), pn = lane_xor32(num);
+    m = pm.a;
+    den = pd.a;
+    num = pn.a;
+    res_merge<float>(m, den, num, pm.b, pd.b, pn.b);
+  }
+}
+
 // Reduce (m, den, num) over a block of 256 threads (m in log2 units); thread
 // 0 writes the result.  Every thread of the block must call this.  The
 // partials only feed the stopping test, so FP32 with the hardware exp2 is
@@ -180,13 +246,7 @@ template <typename T>
 __device__ __forceinline__ void block_res_reduce(T m_in, T den_in, T num_in, ResPart* out) {
   __shared__ float sm[4][3];
   float m = float(m_in), den = float(den_in), num = float(num_in);
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    float m2 = __shfl_xor(m, off, 64);
-    float d2 = __shfl_xor(den, off, 64);
-    float n2 = __shfl_xor(num, off, 64);
-    res_merge<float>(m, den, num, m2, d2, n2);
-  }
+  wave_res_reduce(m, den, num);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     sm[w][0] = m;

@@ -82,9 +82,27 @@ template <typename T> struct ResAcc {
   __device__ __forceinline__ void add(T m2, T d2, T n2) { res_merge<T>(m, den, num, m2, d2, n2); }
 };
 
+// operands of one element's epilogue, loadable ahead of the product
+template <typename T> struct EpiIn {
+  T ld, uo, lp;
+};
+
 template <typename T>
-__device__ __forceinline__ void epi_elem(int64_t e, T S2, const Ctrl* __restrict__ c, int side,
-                                         const EpiArgs<T>& ep, ResAcc<T>& ra) {
+__device__ __forceinline__ EpiIn<T> epi_load(int64_t e, const EpiArgs<T>& ep) {
+  EpiIn<T> x;
+  if (ep.mode == EPI_RAW) {
+    x.ld = x.uo = x.lp = T(0);
+    return x;
+  }
+  x.ld = ep.logd[e < ep.size ? e : e % ep.size];
+  x.uo = ep.pot[e];
+  x.lp = ep.logp[e];
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ void epi_apply(int64_t e, T S2, const EpiIn<T>& x, const Ctrl* __restrict__ c, int side,
+                                          const EpiArgs<T>& ep, ResAcc<T>& ra) {
   if (ep.mode == EPI_RAW) {
     ep.out[e] = S2;
     return;
@@ -92,9 +110,9 @@ __device__ __forceinline__ void epi_elem(int64_t e, T S2, const Ctrl* __restrict
   const T eps = T(side == 0 ? c->eps_x : c->eps_y);
   const T eps_w = T(c->eps_x);       // w feeds the next half-step, which runs at eps_x
   const T S = S2 * T(kLn2);
-  const T ld = ep.logd[e % ep.size];
-  const T uo = ep.pot[e];
-  const T un = proxdiv_pot<T>(ep.F, ep.logp[e], S, eps);
+  const T ld = x.ld;
+  const T uo = x.uo;
+  const T un = proxdiv_pot<T>(ep.F, x.lp, S, eps);
   ep.pot[e] = un;
   if (ep.wnext) ep.wnext[e] = (un / eps_w + ld) * T(kLog2e);
   if (ep.lse_out) ep.lse_out[e] = S;
@@ -106,6 +124,12 @@ __device__ __forceinline__ void epi_elem(int64_t e, T S2, const Ctrl* __restrict
       ra.add((S + un / eps + ld) * T(kLog2e), T(1), Num<T>::fmax(d, -d));
     }
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void epi_elem(int64_t e, T S2, const Ctrl* __restrict__ c, int side,
+                                         const EpiArgs<T>& ep, ResAcc<T>& ra) {
+  epi_apply<T>(e, S2, epi_load<T>(e, ep), c, side, ep, ra);
 }
 
 template <typename T>
@@ -393,51 +417,35 @@ __global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, 
 // count the iteration, pick the next eps, set the stop flag.  (Folding this
 // step into the last block of the final pass needs a device-scope fence in
 // every block, which on a multi-XCD MI355X costs more than the launch.)
+__device__ void control_finish(Ctrl* __restrict__ c, double r, double* __restrict__ hist);
+
 __device__ void control_step(Ctrl* __restrict__ c, const ResPart* __restrict__ part, int nparts,
                              double* __restrict__ hist, int nfields) {
-  // nfields == 0: one residual over all partials; nfields > 0: the partials
-  // form nfields equal contiguous ranges (one per field) and r is the largest
-  // per-field residual
-  __shared__ float sm[kBlock][3];
+  // nfields > 0: the partials form nfields equal contiguous ranges (one per
+  // field) and r is the largest per-field residual
   __shared__ float smax[kBlock];
   float rmax = -1.0f;
-  if (nfields > 0) {
-    const int per = nparts / nfields;
-    for (int f = threadIdx.x; f < nfields; f += kBlock) {
-      float m = -__builtin_inff(), den = 0.f, num = 0.f;
-      for (int k = f * per; k < (f + 1) * per; ++k) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
-      const float rf = num / den;
-      rmax = (rf != rf || rmax != rmax) ? rf : (rf > rmax ? rf : rmax);
-    }
-    smax[threadIdx.x] = rmax;
-    __syncthreads();
-    for (int off = kBlock / 2; off >= 1; off >>= 1) {
-      if ((int)threadIdx.x < off) {
-        const float a = smax[threadIdx.x], b = smax[threadIdx.x + off];
-        smax[threadIdx.x] = (a != a || b != b) ? (a != a ? a : b) : (a > b ? a : b);
-      }
-      __syncthreads();
-    }
-  } else {
+  const int per = nparts / nfields;
+  for (int f = threadIdx.x; f < nfields; f += kBlock) {
     float m = -__builtin_inff(), den = 0.f, num = 0.f;
-    for (int k = threadIdx.x; k < nparts; k += kBlock) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
-    sm[threadIdx.x][0] = m;
-    sm[threadIdx.x][1] = den;
-    sm[threadIdx.x][2] = num;
-    __syncthreads();
-    for (int off = kBlock / 2; off >= 1; off >>= 1) {
-      if ((int)threadIdx.x < off) {
-        float M = sm[threadIdx.x][0], D = sm[threadIdx.x][1], U = sm[threadIdx.x][2];
-        res_merge<float>(M, D, U, sm[threadIdx.x + off][0], sm[threadIdx.x + off][1], sm[threadIdx.x + off][2]);
-        sm[threadIdx.x][0] = M;
-        sm[threadIdx.x][1] = D;
-        sm[threadIdx.x][2] = U;
-      }
-      __syncthreads();
-    }
+    for (int k = f * per; k < (f + 1) * per; ++k) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
+    const float rf = num / den;
+    rmax = (rf != rf || rmax != rmax) ? rf : (rf > rmax ? rf : rmax);
   }
-  if (threadIdx.x != 0) return;
-  const double r = nfields > 0 ? double(smax[0]) : double(sm[0][2]) / double(sm[0][1]);
+  smax[threadIdx.x] = rmax;
+  __syncthreads();
+  for (int off = kBlock / 2; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      const float a = smax[threadIdx.x], b = smax[threadIdx.x + off];
+      smax[threadIdx.x] = (a != a || b != b) ? (a != a ? a : b) : (a > b ? a : b);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) control_finish(c, double(smax[0]), hist);
+}
+
+// thread 0: record r, count the iteration, pick the next eps, set stop
+__device__ void control_finish(Ctrl* __restrict__ c, double r, double* __restrict__ hist) {
   const int64_t l = c->iter;
   if (hist) hist[l] = r;
   c->res = r;
@@ -462,13 +470,30 @@ __device__ void control_step(Ctrl* __restrict__ c, const ResPart* __restrict__ p
   }
 }
 
+// control step of a single problem: one residual over all partials.  The
+// partials are loaded before the stop flag is read, then reduced with wave
+// shuffles (as the passes reduce theirs).
 __global__ __launch_bounds__(kBlock) void k_control(Ctrl* __restrict__ c, const ResPart* __restrict__ part,
                                                      int nparts, double* __restrict__ hist, int nfields) {
+  if (nfields > 0) {
+    if (c->stop) {
+      if (threadIdx.x == 0) c->yskip = 1;
+      return;
+    }
+    control_step(c, part, nparts, hist, nfields);
+    return;
+  }
+  float m = -__builtin_inff(), den = 0.f, num = 0.f;
+  for (int k = threadIdx.x; k < nparts; k += kBlock) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
+  asm volatile("" ::"v"(m), "v"(den), "v"(num));
   if (c->stop) {
     if (threadIdx.x == 0) c->yskip = 1;
     return;
   }
-  control_step(c, part, nparts, hist, nfields);
+  __shared__ ResPart tot;
+  block_res_reduce<float>(m, den, num, &tot);
+  __syncthreads();
+  if (threadIdx.x == 0) control_finish(c, double(tot.num) / double(tot.den), hist);
 }
 
 // plain reduction of residual partials into out[0] (single half-step entry)
@@ -1098,14 +1123,12 @@ namespace uot {
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-template <bool STRIDED>
+template <bool STRIDED, int TPC>
 __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in, int n, int64_t A, int64_t B,
                                                      double h, int side, const Ctrl* __restrict__ c,
                                                      EpiArgs<float> ep) {
-  if (skip_side(c, side)) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int q = lane >> 4, li = lane & 15;
-  const float cc = float(h * h * kLog2e / (side == 0 ? c->eps_x : c->eps_y));
   // line group -> 16 lines; lane's line is li
   const int64_t grp = (int64_t)blockIdx.z * gridDim.y + blockIdx.y;
   int64_t a, bb;
@@ -1123,6 +1146,43 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
   const int64_t base = valid ? (STRIDED ? a * (int64_t)n * B + bb : a * (int64_t)n) : 0;
   const int64_t tstride = STRIDED ? B : 1;
   const int I0 = blockIdx.x * 16;
+  const int nt = n / 16;
+  // The wave's tap tiles jt = wv, wv + 4, ... are taken in chunks of TPC
+  // (4 TPC loads issued together).  The first chunk and the operands of the
+  // epilogue this wave finishes (outputs i = I0 + 4 q + wv of line li) are
+  // loaded before the control block is read, so the latencies overlap.
+  // Tap (jt, s) of the lane's line is cell jt * 16 + 4 s + q; tiles past the
+  // end are read at the last tile (in bounds) and replaced by -inf.  Lanes of
+  // a line past the end read line 0 unconditionally: lines never mix (MFMA
+  // columns and the max exchanges stay within a line) and their outputs are
+  // dropped, while a masked load would serialise the loads.
+  const float* __restrict__ pl = in + base + (int64_t)q * tstride;
+  const int64_t st4 = 4 * tstride;
+  auto load_chunk = [&](float (&w)[TPC][4], int jc) {
+#pragma unroll
+    for (int t = 0; t < TPC; ++t) {
+      const int jt = jc + 4 * t;
+      const int jtc = jt < nt ? jt : nt - 1;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const float x = pl[(int64_t)(jtc * 4 + s) * st4];
+        w[t][s] = jt < nt ? x : -__builtin_inff();
+      }
+    }
+  };
+  float wv4[TPC][4];
+  load_chunk(wv4, wv);
+  const int ie = I0 + 4 * q + wv;
+  const int64_t eo = valid ? (STRIDED ? (a * (int64_t)n + ie) * B + bb : a * (int64_t)n + ie) : 0;
+  const EpiIn<float> xin = epi_load<float>(eo, ep);
+  // keep those loads ahead of the branch (otherwise they may be moved past it)
+#pragma unroll
+  for (int t = 0; t < TPC; ++t)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) asm volatile("" ::"v"(wv4[t][s]));
+  asm volatile("" ::"v"(xin.ld), "v"(xin.uo), "v"(xin.lp));
+  if (skip_side(c, side)) return;
+  const float cc = float(h * h * kLog2e / (side == 0 ? c->eps_x : c->eps_y));
   // Khat as MFMA A operands: k-step s -> Khat[i = li][k = 4 s + q]
   float kh[4];
 #pragma unroll
@@ -1130,87 +1190,84 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
     const float e = float(li) - 7.5f, f = float(4 * s + q) - 7.5f;
     kh[s] = __builtin_amdgcn_exp2f(2.f * cc * e * f);
   }
-  // running LSE of the 4 outputs i = 4q + r of this lane's line li... (D layout)
+  // running LSE of the 4 outputs i = 4q + r of this lane's line li (D layout)
   float M[4], S[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     M[r] = -__builtin_inff();
     S[r] = 0.f;
   }
-  const int nt = n / 16;
-  // the wave's tap tiles jt = wv, wv + 4, ... in chunks of 4: the 16 loads of
-  // a chunk are issued together, then the chunk is computed
-  for (int jc = wv; jc < nt; jc += 16) {
-    float wv4[4][4];
+  for (int jc = wv; jc < nt; jc += 4 * TPC) {
+    if (jc != wv) load_chunk(wv4, jc);
+    // the TPC tiles of a chunk are independent until the final merge:
+    // column factors and their line maxima first, then the products, so the
+    // exchanges and the MFMA chains of different tiles overlap
+    float D[TPC], mloc[TPC], beta[TPC][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int jt = jc + 4 * t;
+    for (int t = 0; t < TPC; ++t) {
+      D[t] = float(I0 - (jc + 4 * t) * 16);
+      mloc[t] = -__builtin_inff();
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-        wv4[t][s] = (valid && jt < nt) ? in[base + (int64_t)(jt * 16 + 4 * s + q) * tstride] : -__builtin_inff();
+      for (int s = 0; s < 4; ++s) {
+        const float f = float(4 * s + q) - 7.5f;
+        beta[t][s] = wv4[t][s] - cc * (f * (f - 2.f * D[t]));
+        mloc[t] = fmaxf(mloc[t], beta[t][s]);
+      }
+    }
+    // max over the 16 taps of the line: the four lane rows q share a line
+#pragma unroll
+    for (int t = 0; t < TPC; ++t) mloc[t] = max_over_rows(mloc[t]);
+    f32x4_t acc[TPC];
+    float E[TPC][4];
+#pragma unroll
+    for (int t = 0; t < TPC; ++t) {
+      acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      const float msh = (mloc[t] == -__builtin_inff()) ? 0.f : mloc[t];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) E[t][s] = __builtin_amdgcn_exp2f(beta[t][s] - msh);
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-    const int jt = jc + 4 * t;
-    if (jt >= nt) break;
-    const int J0 = jt * 16;
-    const float D = float(I0 - J0);
-    // column factors for taps b = 4 s + q of this lane's line
-    float beta[4];
-    float mloc = -__builtin_inff();
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const float f = float(4 * s + q) - 7.5f;
-      beta[s] = wv4[t][s] - cc * (f * (f - 2.f * D));
-      mloc = fmaxf(mloc, beta[s]);
-    }
-    // max over the 16 taps of the line: the four lane groups q share a line
-    mloc = fmaxf(mloc, __shfl_xor(mloc, 16, 64));
-    mloc = fmaxf(mloc, __shfl_xor(mloc, 32, 64));
-    const float msh = (mloc == -__builtin_inff()) ? 0.f : mloc;
-    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const float E = __builtin_amdgcn_exp2f(beta[s] - msh);
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(kh[s], E, acc, 0, 0, 0);
-    }
-    // acc[r] = sum_f Khat[e_i][f] E_f for output i = 4 q + r of line li
-    const float cD2 = cc * D * D;
+      for (int t = 0; t < TPC; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(kh[s], E[t][s], acc[t], 0, 0, 0);
+    // acc[t][r] = sum_f Khat[e_i][f] E_f for output i = 4 q + r of line li;
+    // one rescale of the running sum per chunk
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float e = float(4 * q + r) - 7.5f;
-      const float al = (mloc == -__builtin_inff()) ? -__builtin_inff() : (mloc - cc * (e * (e + 2.f * D)) - cD2);
-      const float mn = fmaxf(M[r], al);
+      float al[TPC];
+      float mn = M[r];
+#pragma unroll
+      for (int t = 0; t < TPC; ++t) {
+        al[t] = (mloc[t] == -__builtin_inff()) ? -__builtin_inff()
+                                               : (mloc[t] - cc * (e * (e + 2.f * D[t])) - cc * D[t] * D[t]);
+        mn = fmaxf(mn, al[t]);
+      }
       const float sh = (mn == -__builtin_inff()) ? 0.f : mn;
-      S[r] = S[r] * __builtin_amdgcn_exp2f(M[r] - sh) + acc[r] * __builtin_amdgcn_exp2f(al - sh);
+      float sum = S[r] * __builtin_amdgcn_exp2f(M[r] - sh);
+#pragma unroll
+      for (int t = 0; t < TPC; ++t) sum += acc[t][r] * __builtin_amdgcn_exp2f(al[t] - sh);
+      S[r] = sum;
       M[r] = mn;
     }
-    }
   }
-  // merge the four waves (each saw a quarter of the J tiles)
-  __shared__ float smM[4][64][4], smS[4][64][4];
+  // merge the four waves (each saw a quarter of the J tiles); wave w then
+  // finishes output row r = w of every lane
+  __shared__ float smM[4][4][64], smS[4][4][64];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    smM[wv][lane][r] = M[r];
-    smS[wv][lane][r] = S[r];
+    smM[wv][r][lane] = M[r];
+    smS[wv][r][lane] = S[r];
   }
   __syncthreads();
+  Lse2<float> tot;
+  tot.m = smM[0][wv][lane];
+  tot.s = smS[0][wv][lane];
+#pragma unroll
+  for (int k = 1; k < 4; ++k) tot.merge(smM[k][wv][lane], smS[k][wv][lane]);
   ResAcc<float> ra;
   ra.init();
-  if (wv == 0) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      Lse2<float> t;
-      t.m = M[r];
-      t.s = S[r];
-      for (int k = 1; k < 4; ++k) t.merge(smM[k][lane][r], smS[k][lane][r]);
-      if (valid) {
-        const int i = I0 + 4 * q + r;
-        const int64_t e = STRIDED ? (a * (int64_t)n + i) * B + bb : a * (int64_t)n + i;
-        epi_elem<float>(e, t.result(), c, side, ep, ra);
-      }
-    }
-  }
+  if (valid) epi_apply<float>(eo, tot.result(), xin, c, side, ep, ra);
   epi_finish<float>(ep, ra, (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
 }
 
@@ -1233,8 +1290,16 @@ void launch_grid_tf(const float* in, int64_t A, int n, int64_t B, bool strided, 
                     const EpiArgs<float>& ep, hipStream_t s) {
   unsigned gx, gy, gz;
   tf_grid(n, A, B, strided, gx, gy, gz);
-  if (strided) hipLaunchKernelGGL(k_grid_tf<true>, dim3(gx, gy, gz), dim3(kBlock), 0, s, in, n, A, B, h, side, c, ep);
-  else hipLaunchKernelGGL(k_grid_tf<false>, dim3(gx, gy, gz), dim3(kBlock), 0, s, in, n, A, B, h, side, c, ep);
+  // tiles per chunk: as many of a wave's tiles as exist, up to 4
+  const int per_wave = (n / 16 + 3) / 4;
+#define UOT_TF(ST, TP) \
+  hipLaunchKernelGGL((k_grid_tf<ST, TP>), dim3(gx, gy, gz), dim3(kBlock), 0, s, in, n, A, B, h, side, c, ep)
+  if (strided) {
+    if (per_wave >= 4) UOT_TF(true, 4); else if (per_wave >= 2) UOT_TF(true, 2); else UOT_TF(true, 1);
+  } else {
+    if (per_wave >= 4) UOT_TF(false, 4); else if (per_wave >= 2) UOT_TF(false, 2); else UOT_TF(false, 1);
+  }
+#undef UOT_TF
 }
 
 }  // namespace uot

@@ -110,6 +110,8 @@ def lib():
                                    P(UotResult)]),
         "uot_time_half_step": (c_i32, [c_vp, P(UotProblem), c_dbl, c_vp, c_i32, P(c_dbl), P(c_i32), c_vp,
                                        ctypes.c_size_t, c_i32]),
+        "uot_time_fields_half_step": (c_i32, [c_vp, P(UotProblem), c_i32, c_dbl, c_vp, c_i32, P(c_dbl), P(c_i32), c_vp,
+                                       ctypes.c_size_t, c_i32]),
         "uot_probe_rates": (c_i32, [c_vp, P(c_dbl), P(c_dbl)]),
         "uot_fields_workspace_size": (c_i32, [P(UotProblem), c_i32, P(ctypes.c_size_t)]),
         "uot_solve_fields": (c_i32, [c_vp, P(UotProblem), c_i32, P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t,
@@ -426,6 +428,34 @@ def time_half_step(prob: Problem, eps, v, reps=50, ctx: Optional[Context] = None
     _check(lib().uot_time_half_step(ctx.handle, ctypes.byref(prob.c), float(eps), _ptr(v), int(reps), ms,
                                     ctypes.byref(nk), _ptr(ws), ws.numel(), int(grid_kernel)),
            "uot_time_half_step", False)
+    return [ms[k] for k in range(nk.value)]
+
+
+def time_fields_half_step(shape, h, p, dx, dy, F1: Div, eps, v, reps=20, ctx: Optional[Context] = None,
+                          grid_kernel=0):
+    """time_half_step over nb fields on one grid (p, v: nb x size); every
+    timed launch processes all fields."""
+    ctx = ctx or default_context()
+    nb = p.shape[0]
+    size = int(math.prod(shape))
+    dtype = p.dtype
+    _dev(p, dtype, nb * size, "p")
+    _dev(v, dtype, nb * size, "v")
+    _dev(dx, dtype, size, "dx")
+    _dev(dy, dtype, size, "dy")
+    n = list(shape) + [1] * (3 - len(shape))
+    hh = list(h) + [0.0] * (3 - len(h))
+    g = UotGeom(UOT_GEOM_GRID, len(shape), size, size, c_vp(), c_vp(), (c_i64 * 3)(*n), (c_dbl * 3)(*hh))
+    pb = UotProblem(_dt(p), 0, g, _ptr(p), _ptr(p), _ptr(dx), _ptr(dy), F1.c(), F1.c())
+    nbytes = ctypes.c_size_t()
+    _check(lib().uot_fields_workspace_size(ctypes.byref(pb), nb, ctypes.byref(nbytes)), "uot_fields_workspace_size",
+           False)
+    ws = workspace(nbytes.value, p.device)
+    ms = (c_dbl * 4)()
+    nk = c_i32()
+    _check(lib().uot_time_fields_half_step(ctx.handle, ctypes.byref(pb), nb, float(eps), _ptr(v), int(reps), ms,
+                                           ctypes.byref(nk), _ptr(ws), ws.numel(), int(grid_kernel)),
+           "uot_time_fields_half_step", False)
     return [ms[k] for k in range(nk.value)]
 
 
