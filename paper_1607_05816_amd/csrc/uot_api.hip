@@ -263,13 +263,13 @@ Ctrl make_ctrl(double eps, double eps0, int stages, int ips, double tol, int64_t
     for (int k = 0; k < stages; ++k) c.eps_tab[k] = eps0 * std::pow(f, k);
   }
   c.eps_tab[c.n_stages] = eps;
-  c.stage_x = c.stage_y = 0;
-  c.eps_x = c.eps_y = c.eps_tab[0];
+  c.stage[0] = c.stage[1] = 0;
+  c.eps[0] = c.eps[1] = c.eps_tab[0];
   c.tol = tol;
   c.max_iter = max_iter;
   c.iter = 0;
   c.stop = 0;
-  c.yskip = 0;
+  c.skip[0] = c.skip[1] = 0;
   c.status = 1;
   c.res = INFINITY;
   return c;
@@ -337,24 +337,41 @@ void strided_pass(const Plan& P, int axis, const T* w, int64_t A, int64_t B, T* 
   timed(1, [&] { launch_grid_strided<T>(w, A, (int)P.n[axis], B, tabs[axis], side, c, ep, s); });
 }
 
+// control step hosted by the first pass of a chain (see k_control)
+struct CtlHost {
+  Ctrl* c = nullptr;
+  const ResPart* parts = nullptr;
+  int nparts = 0;
+  double* hist = nullptr;
+};
+
 template <typename T>
 void grid_chain(const Plan& P, const T* w, T* const* tabs, int side, Ctrl* c, const EpiArgs<T>& ep, T* tmp1,
-                T* tmp2, hipStream_t s) {
+                T* tmp2, hipStream_t s, const CtlHost* host = nullptr) {
   const int64_t nb = P.nb;
-  EpiArgs<T> raw{};
-  raw.mode = EPI_RAW;
+  // first pass (no epilogue on 2 or 3 axes): writes tmp1 and may host the
+  // control step; only such a pass may, as an epilogue reads the slot the
+  // control step writes
+  EpiArgs<T> first{};
+  first.mode = EPI_RAW;
+  first.out = tmp1;
+  if (host) {
+    first.host_ctl = host->c;
+    first.host_parts = host->parts;
+    first.host_nparts = host->nparts;
+    first.host_hist = host->hist;
+  }
   if (P.dim == 1) {
     contig_pass<T>(P, 0, w, nb, tabs, side, c, ep, s);
   } else if (P.dim == 2) {
-    raw.out = tmp1;
-    contig_pass<T>(P, 1, w, nb * P.n[0], tabs, side, c, raw, s);
+    contig_pass<T>(P, 1, w, nb * P.n[0], tabs, side, c, first, s);
     strided_pass<T>(P, 0, tmp1, nb, P.n[1], tabs, side, c, ep, s);
   } else {
-    raw.out = tmp1;
-    contig_pass<T>(P, 2, w, nb * P.n[0] * P.n[1], tabs, side, c, raw, s);
-    EpiArgs<T> raw2 = raw;
-    raw2.out = tmp2;
-    strided_pass<T>(P, 1, tmp1, nb * P.n[0], P.n[2], tabs, side, c, raw2, s);
+    contig_pass<T>(P, 2, w, nb * P.n[0] * P.n[1], tabs, side, c, first, s);
+    EpiArgs<T> mid{};
+    mid.mode = EPI_RAW;
+    mid.out = tmp2;
+    strided_pass<T>(P, 1, tmp1, nb * P.n[0], P.n[2], tabs, side, c, mid, s);
     strided_pass<T>(P, 0, tmp2, nb, P.n[1] * P.n[2], tabs, side, c, ep, s);
   }
 }
@@ -363,15 +380,16 @@ void grid_chain(const Plan& P, const T* w, T* const* tabs, int side, Ctrl* c, co
 template <typename T>
 void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Bufs<T>& B, Ctrl* c,
                 const EpiArgs<T>& ep, hipStream_t s) {
-  const T* rows = static_cast<const T*>(side == 0 ? g.x : g.y);
-  const T* cols = static_cast<const T*>(side == 0 ? g.y : g.x);
-  const int64_t Nr = side == 0 ? P.N : P.M;
-  const int64_t Mc = side == 0 ? P.M : P.N;
+  const int half = side & 1;
+  const T* rows = static_cast<const T*>(half == 0 ? g.x : g.y);
+  const T* cols = static_cast<const T*>(half == 0 ? g.y : g.x);
+  const int64_t Nr = half == 0 ? P.N : P.M;
+  const int64_t Mc = half == 0 ? P.M : P.N;
   timed(0, [&] {
-    launch_dense_lse<T>(P.dim, P.R[side], rows, Nr, cols, w_cols, Mc, P.splits[side], P.cps[side], B.pm, B.ps, side,
+    launch_dense_lse<T>(P.dim, P.R[half], rows, Nr, cols, w_cols, Mc, P.splits[half], P.cps[half], B.pm, B.ps, side,
                         c, s);
   });
-  timed(1, [&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[side], Nr, side, c, ep, s); });
+  timed(1, [&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[half], Nr, side, c, ep, s); });
 }
 
 template <typename T>
@@ -390,18 +408,19 @@ EpiArgs<T> prox_epi(T* pot, T* wnext, const T* logp, const T* logd, T* lse_out, 
   return ep;
 }
 
-// one half-step (X: side 0 reads wv, writes u / wu; Y: side 1 reads wu, writes v / wv)
+// one half-step (X: side 0 reads wv, writes u / wu; Y: side 1 reads wu, writes
+// v / wv); bit 1 of side is the parity of the iteration
 template <typename T>
 void half_step(const Plan& P, const uot_problem& pb, int side, Bufs<T>& B, T* pot, T* lse_out, bool with_res,
-               hipStream_t s) {
-  if (side == 0) {
+               hipStream_t s, const CtlHost* host = nullptr) {
+  if ((side & 1) == 0) {
     EpiArgs<T> ep = prox_epi<T>(pot, B.wu, B.logp, B.logdx, lse_out, with_res ? B.parts : nullptr, P.N, pb.F1);
-    if (P.geom == UOT_GEOM_GRID) grid_chain<T>(P, B.wv, B.gtab, 0, B.ctrl, ep, B.t1, B.t2, s);
-    else dense_half<T>(P, pb.geom, 0, B.wv, B, B.ctrl, ep, s);
+    if (P.geom == UOT_GEOM_GRID) grid_chain<T>(P, B.wv, B.gtab, side, B.ctrl, ep, B.t1, B.t2, s);
+    else dense_half<T>(P, pb.geom, side, B.wv, B, B.ctrl, ep, s);
   } else {
     EpiArgs<T> ep = prox_epi<T>(pot, B.wv, B.logq, B.logdy, lse_out, nullptr, P.M, pb.F2);
-    if (P.geom == UOT_GEOM_GRID) grid_chain<T>(P, B.wu, B.gtab, 1, B.ctrl, ep, B.t1, B.t2, s);
-    else dense_half<T>(P, pb.geom, 1, B.wu, B, B.ctrl, ep, s);
+    if (P.geom == UOT_GEOM_GRID) grid_chain<T>(P, B.wu, B.gtab, side, B.ctrl, ep, B.t1, B.t2, s, host);
+    else dense_half<T>(P, pb.geom, side, B.wu, B, B.ctrl, ep, s);
   }
 }
 
@@ -423,11 +442,19 @@ int validate_params(const uot_params* pr) {
   return UOT_OK;
 }
 
-// drive iterations until the device sets stop; `iteration` enqueues one
+// polling interval in iterations, rounded up to even: the iterations of a
+// captured chunk alternate in parity, so every replay starts at an even one
+inline int even_chunk(int check_every) {
+  const int c = check_every > 0 ? check_every : 50;
+  return c + (c & 1);
+}
+
+// drive iterations until the device sets stop; `iteration(par)` enqueues one
+// iteration of parity par
 template <typename F>
 int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot_result* res) {
   hipStream_t s = ctx->work;
-  const int chunk = pr->check_every > 0 ? pr->check_every : 50;
+  const int chunk = even_chunk(pr->check_every);
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   KTimer timer;
@@ -439,7 +466,7 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
   } reset_timer;
   if (pr->use_graph && !timing) {
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < chunk; ++k) iteration();
+    for (int k = 0; k < chunk; ++k) iteration(k & 1);
     HIP_TRY(hipStreamEndCapture(s, &graph));
     HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   }
@@ -450,7 +477,7 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
     if (exec) {
       if (hipGraphLaunch(exec, s) != hipSuccess) { rc = fail(UOT_E_HIP, "hipGraphLaunch failed"); break; }
     } else {
-      for (int k = 0; k < chunk; ++k) iteration();
+      for (int k = 0; k < chunk; ++k) iteration(k & 1);
     }
     launched += chunk;
     if (hipMemcpyAsync(ctx->pinned, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -503,10 +530,20 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   launch_init_pot<T>(static_cast<const T*>(pr->v0), B.logdy, v, B.wv, nb * P.M, P.M, B.ctrl, 0, s);
   HIP_TRY(hipGetLastError());
   const int nfields = nb > 1 ? nb : 0;
-  auto iteration = [&]() {
-    half_step<T>(P, *pb, 0, B, u, nullptr, true, s);
-    timed(2, [&] { launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s, nfields); });
-    half_step<T>(P, *pb, 1, B, v, nullptr, false, s);
+  // a single problem on a grid of 2 or 3 axes: the first Y pass (no
+  // epilogue) hosts the control step; otherwise it is its own launch
+  CtlHost host;
+  const bool hosted = nfields == 0 && P.geom == UOT_GEOM_GRID && P.dim >= 2;
+  if (hosted) {
+    host.c = B.ctrl;
+    host.parts = B.parts;
+    host.nparts = P.nparts_x;
+    host.hist = pr->res_hist;
+  }
+  auto iteration = [&](int par) {
+    half_step<T>(P, *pb, 0 | par << 1, B, u, nullptr, true, s);
+    if (!hosted) timed(2, [&] { launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s, nfields, par); });
+    half_step<T>(P, *pb, 1 | par << 1, B, v, nullptr, false, s, hosted ? &host : nullptr);
   };
   rc = run_loop(ctx, B.ctrl, pr, iteration, res);
   if (rc) return rc;
@@ -681,15 +718,16 @@ int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u,
     asum += pb->alpha[k];
   }
   const DivDev F2 = to_dev(pb->F2);
-  auto iteration = [&]() {
+  auto iteration = [&](int par) {
     EpiArgs<T> ep = prox_epi<T>(u, B.wu, B.logp, B.logdx, nullptr, B.parts, size, pb->F1);
-    grid_chain<T>(P, B.wv, B.gtab, 0, B.ctrl, ep, B.t1, B.t2, s);
-    launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s);
+    grid_chain<T>(P, B.wv, B.gtab, 0 | par << 1, B.ctrl, ep, B.t1, B.t2, s);
+    launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s, 0, par);
     EpiArgs<T> raw{};
     raw.mode = EPI_RAW;
     raw.out = B.t3;
-    grid_chain<T>(P, B.wu, B.gtab, 1, B.ctrl, raw, B.t1, B.t2, s);
-    launch_bary_combine<T>(B.t3, pb->n, size, la, std::log(asum), F2, B.logdy, v, B.wv, logh, B.ctrl, s);
+    grid_chain<T>(P, B.wu, B.gtab, 1 | par << 1, B.ctrl, raw, B.t1, B.t2, s);
+    launch_bary_combine<T>(B.t3, pb->n, size, la, std::log(asum), F2, B.logdy, v, B.wv, logh, B.ctrl, 1 | par << 1,
+                           s);
   };
   rc = run_loop(ctx, B.ctrl, pr, iteration, res);
   if (rc) return rc;
@@ -931,19 +969,19 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
     launch_init_pot<T>(static_cast<const T*>(pr->v0), logdy, v, wv, P.totM, P.totM, ctrl, 0, s);
   };
   int R = 1, bpc = 8;
-  auto iteration = [&]() {
+  auto iteration = [&](int par) {
     EpiArgs<T> epx = prox_epi<T>(u, wu, logp, logdx, nullptr, parts, P.totN, pb->F1);
     EpiArgs<T> epy = prox_epi<T>(v, wv, logq, logdy, nullptr, nullptr, P.totM, pb->F2);
     timed(0, [&] {
       launch_batch_lse<T>(P.dim, R, ncu * bpc, itx, (int)hx.size(), curs + 0, offN_d, offM_d,
                           static_cast<const T*>(pb->x), P.totN, static_cast<const T*>(pb->y), P.totM, wv, bc_dev,
-                          ctrl, 0, epx, s);
+                          ctrl, 0 | par << 1, epx, s);
     });
-    timed(2, [&] { launch_batch_control(ctrl, bc_dev, (int)P.B, parts, pstart_d, curs, s); });
+    timed(2, [&] { launch_batch_control(ctrl, bc_dev, (int)P.B, parts, pstart_d, curs, par, s); });
     timed(1, [&] {
       launch_batch_lse<T>(P.dim, R, ncu * bpc, ity, (int)hy.size(), curs + 1, offM_d, offN_d,
                           static_cast<const T*>(pb->y), P.totM, static_cast<const T*>(pb->x), P.totN, wu, bc_dev,
-                          ctrl, 1, epy, s);
+                          ctrl, 1 | par << 1, epy, s);
     });
   };
 
@@ -976,10 +1014,10 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
         R = Rs[ri];
         bpc = Bs[bi];
         init_state();
-        iteration();   // first iteration: caches and code warm
+        iteration(0);   // first iteration: caches and code warm
         HIP_TRY(hipEventRecord(e0, s));
-        iteration();
-        iteration();
+        iteration(1);
+        iteration(0);
         HIP_TRY(hipEventRecord(e1, s));
         HIP_TRY(hipEventSynchronize(e1));
         float t = 0.f;
@@ -1003,7 +1041,7 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
   HIP_TRY(hipGetLastError());
 
   // iteration loop: graph chunks (or timed direct launches) until no problem is active
-  const int chunk = pr->check_every > 0 ? pr->check_every : 50;
+  const int chunk = even_chunk(pr->check_every);
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   KTimer timer;
@@ -1015,7 +1053,7 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
   } reset_timer;
   if (pr->use_graph && !timing) {
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < chunk; ++k) iteration();
+    for (int k = 0; k < chunk; ++k) iteration(k & 1);
     HIP_TRY(hipStreamEndCapture(s, &graph));
     HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   }
@@ -1026,7 +1064,7 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
     if (exec) {
       if (hipGraphLaunch(exec, s) != hipSuccess) { rc = fail(UOT_E_HIP, "hipGraphLaunch failed"); break; }
     } else {
-      for (int k = 0; k < chunk; ++k) iteration();
+      for (int k = 0; k < chunk; ++k) iteration(k & 1);
     }
     launched += chunk;
     if (hipMemcpyAsync(ctx->pinned, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -86,24 +86,38 @@ template <typename T> struct Lse2 {
 // graph for every eps stage and stops by itself once converged.
 // ---------------------------------------------------------------------------
 struct Ctrl {
-  int32_t stop;      // X half-steps and the control kernel skip when set
-  int32_t yskip;     // Y half-steps skip when set
+  // Per-iteration state lives in two slots indexed by the parity of the
+  // iteration, so the control step of iteration l (which fills the slot of
+  // l + 1) may run inside a kernel whose other blocks still read the slot of l.
+  int32_t stop;      // set once the solve has stopped (read by the host)
   int32_t status;    // 0 ok, 1 not converged, -3 non-finite residual
-  int32_t stage_x;   // eps stage of the X half-step about to run
-  int32_t stage_y;   // eps stage of the Y half-step about to run
+  int32_t skip[2];   // the half-steps of an iteration of parity p skip when skip[p] is set
+  int32_t stage[2];  // eps stage of the iteration of parity p
   int32_t n_stages;  // annealing stages before the final eps
   int32_t iters_per_stage;
-  int32_t pad;
-  int64_t iter;      // completed X half-steps (= iteration index of the next)
+  int64_t iter;      // completed iterations (= index of the next one)
   int64_t max_iter;
   double tol;
   double res;        // residual of the last iteration
-  double eps_x, eps_y;
+  double eps[2];     // eps of the iteration of parity p
   double eps_tab[kMaxStages + 1];
   // ragged batches only
   int32_t active[2];  // problems still active after the last iteration (slot = iteration parity)
   uint64_t t0_clock;  // device wall clock at the start of the solve
 };
+
+// A kernel's `side` argument: bit 0 the half-step (0: X, 1: Y), bit 1 the
+// parity of the iteration it belongs to.
+__device__ __forceinline__ int half_of(int side) { return side & 1; }
+__device__ __forceinline__ int par_of(int side) { return (side >> 1) & 1; }
+__device__ __forceinline__ bool skip_side(const Ctrl* c, int side) { return c->skip[par_of(side)] != 0; }
+__device__ __forceinline__ double eps_of(const Ctrl* c, int side) { return c->eps[par_of(side)]; }
+__device__ __forceinline__ int stage_of(const Ctrl* c, int side) { return c->stage[par_of(side)]; }
+// eps of the half-step that reads this epilogue's w: the Y half-step of the
+// same iteration (X side) or the X half-step of the next one (Y side)
+__device__ __forceinline__ double eps_next_of(const Ctrl* c, int side) {
+  return c->eps[par_of(side) ^ half_of(side)];
+}
 
 // per-problem state of a ragged batch (arrays of length B in the workspace)
 struct BCtrl {

@@ -28,10 +28,6 @@ template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double4; };
 
-__device__ __forceinline__ bool skip_side(const Ctrl* c, int side) {
-  return side == 0 ? (c->stop != 0) : (c->yskip != 0);
-}
-
 // ---------------------------------------------------------------------------
 // input preparation: log densities (-inf at 0), log reference weights
 // ---------------------------------------------------------------------------
@@ -50,7 +46,7 @@ __global__ void k_init_pot(const T* __restrict__ v0, const T* __restrict__ logd,
                            int which_eps) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const T eps = T(which_eps == 0 ? c->eps_x : c->eps_y);
+  const T eps = T(c->eps[which_eps & 1]);
   T p = v0 ? v0[i] : T(0);
   if (pot) pot[i] = p;
   if (w) w[i] = (p / eps + logd[i % size]) * T(kLog2e);
@@ -107,8 +103,8 @@ __device__ __forceinline__ void epi_apply(int64_t e, T S2, const EpiIn<T>& x, co
     ep.out[e] = S2;
     return;
   }
-  const T eps = T(side == 0 ? c->eps_x : c->eps_y);
-  const T eps_w = T(c->eps_x);       // w feeds the next half-step, which runs at eps_x
+  const T eps = T(eps_of(c, side));
+  const T eps_w = T(eps_next_of(c, side));   // w feeds the next half-step
   const T S = S2 * T(kLn2);
   const T ld = x.ld;
   const T uo = x.uo;
@@ -135,6 +131,87 @@ __device__ __forceinline__ void epi_elem(int64_t e, T S2, const Ctrl* __restrict
 template <typename T>
 __device__ __forceinline__ void epi_finish(const EpiArgs<T>& ep, const ResAcc<T>& ra, int part_index) {
   if (ep.mode != EPI_RAW && ep.part) block_res_reduce<T>(ra.m, ra.den, ra.num, ep.part + part_index);
+}
+
+// ---------------------------------------------------------------------------
+// control step of an iteration: reduce the residual partials of the X
+// half-step, count the iteration, pick the next eps, stop when done.  It runs
+// as its own launch (k_control) or in block 0 of the first pass of the Y
+// half-step (grid solves of one problem: that pass only reads the slot of
+// the current iteration, the step writes the slot of the next).
+// ---------------------------------------------------------------------------
+// what the control step of an iteration of parity par reads of the control
+// block, loaded before the residual reduction so those loads overlap the
+// loads of the partials
+struct CtrlSnap {
+  int64_t l, max_iter;
+  int stage, n_stages, sn;
+  double tol, eps_next;
+};
+
+__device__ __forceinline__ CtrlSnap ctrl_snap(const Ctrl* c, int par) {
+  CtrlSnap s;
+  s.l = c->iter;
+  s.max_iter = c->max_iter;
+  s.stage = c->stage[par];
+  s.n_stages = c->n_stages;
+  s.tol = c->tol;
+  int64_t sn = c->iters_per_stage > 0 ? (s.l + 1) / c->iters_per_stage : s.n_stages;
+  if (sn > s.n_stages) sn = s.n_stages;
+  s.sn = (int)sn;
+  s.eps_next = c->eps_tab[sn];
+  return s;
+}
+
+// one thread: record r, count the iteration, fill the slot of the next
+// iteration (parity par ^ 1) with its eps stage, stop when done.  A stopped
+// solve skips the next iteration; the control step of a skipped iteration
+// passes the skip on (control_skip), so every later iteration skips too.
+__device__ void control_finish(Ctrl* c, const CtrlSnap& s, double r, double* __restrict__ hist, int par) {
+  if (hist) hist[s.l] = r;
+  c->res = r;
+  c->iter = s.l + 1;
+  c->stage[par ^ 1] = s.sn;
+  c->eps[par ^ 1] = s.eps_next;
+  const bool final_stage = s.stage >= s.n_stages;
+  int status = 0;
+  bool stop = false;
+  if (r != r) {
+    stop = true;
+    status = -3;
+  } else if (final_stage && r <= s.tol) {
+    stop = true;
+    status = 0;
+  } else if (s.l + 1 >= s.max_iter) {
+    stop = true;
+    status = 1;
+  }
+  if (stop) {
+    c->status = status;
+    c->stop = 1;
+    c->skip[par ^ 1] = 1;
+  }
+}
+
+__device__ __forceinline__ void control_skip(Ctrl* c, int par) { c->skip[par ^ 1] = 1; }
+
+// this thread's share of the residual partials of one problem
+__device__ __forceinline__ void ctl_load(const ResPart* __restrict__ part, int nparts, float& m, float& den,
+                                         float& num) {
+  m = -__builtin_inff();
+  den = num = 0.f;
+  for (int k = threadIdx.x; k < nparts; k += kBlock) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
+}
+
+// block reduction of the shares and the control step (every thread of the
+// block calls it)
+__device__ __forceinline__ void ctl_reduce_finish(Ctrl* c, const CtrlSnap& snap, float m, float den, float num,
+                                                  double* __restrict__ hist, int par) {
+  __shared__ ResPart tot;
+  __syncthreads();   // the block's own reductions before this one are complete
+  block_res_reduce<float>(m, den, num, &tot);
+  __syncthreads();
+  if (threadIdx.x == 0) control_finish(c, snap, double(tot.num) / double(tot.den), hist, par);
 }
 
 // merge the per-wave partial LSEs of a block (4 waves split the taps); the
@@ -171,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_strided(const T* __restrict__ i
   // the stage's table in LDS: the lookups g[i - j] are wave-uniform broadcasts
   extern __shared__ __align__(16) unsigned char gl_raw[];
   T* gl = reinterpret_cast<T*>(gl_raw);
-  const int stage = side == 0 ? c->stage_x : c->stage_y;
+  const int stage = stage_of(c, side);
   const T* __restrict__ gsrc = gtab + (int64_t)stage * (2 * n - 1);
   for (int k = threadIdx.x; k < 2 * n - 1; k += kBlock) gl[k] = gsrc[k];
   __syncthreads();
@@ -246,10 +323,22 @@ template <typename T, int RI>
 __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in, int n, int64_t A,
                                                          const T* __restrict__ gtab, int side,
                                                          const Ctrl* __restrict__ c, EpiArgs<T> ep) {
-  if (skip_side(c, side)) return;
+  // block 0 of a launch that hosts the control step: partials loaded first
+  const bool hosting = ep.host_ctl != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0;
+  const int par = par_of(side);
+  CtrlSnap hsnap{};
+  float hm = -__builtin_inff(), hden = 0.f, hnum = 0.f;
+  if (hosting) {
+    hsnap = ctrl_snap(ep.host_ctl, par);
+    ctl_load(ep.host_parts, ep.host_nparts, hm, hden, hnum);
+  }
+  if (skip_side(c, side)) {
+    if (hosting && threadIdx.x == 0) control_skip(ep.host_ctl, par);
+    return;
+  }
   extern __shared__ __align__(16) unsigned char gl_raw[];
   T* gl = reinterpret_cast<T*>(gl_raw);
-  const int stage = side == 0 ? c->stage_x : c->stage_y;
+  const int stage = stage_of(c, side);
   const T* __restrict__ g = gtab + (int64_t)stage * (2 * n - 1);
   for (int k = threadIdx.x; k < 2 * n - 1; k += kBlock) gl[k] = g[k];
   __syncthreads();
@@ -313,6 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in
     }
   }
   epi_finish<T>(ep, ra, (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+  if (hosting) ctl_reduce_finish(ep.host_ctl, hsnap, hm, hden, hnum, ep.host_hist, par);
 }
 
 // ---------------------------------------------------------------------------
@@ -330,7 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
   if (skip_side(c, side)) return;
   using V4 = typename Vec4<T>::type;
   __shared__ V4 tile[kBlock];
-  const T sc = T(kLog2e / (side == 0 ? c->eps_x : c->eps_y));
+  const T sc = T(kLog2e / eps_of(c, side));
   T xi[R][DIM];
   int64_t rows[R];
 #pragma unroll
@@ -417,13 +507,12 @@ __global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, 
 // count the iteration, pick the next eps, set the stop flag.  (Folding this
 // step into the last block of the final pass needs a device-scope fence in
 // every block, which on a multi-XCD MI355X costs more than the launch.)
-__device__ void control_finish(Ctrl* __restrict__ c, double r, double* __restrict__ hist);
-
 __device__ void control_step(Ctrl* __restrict__ c, const ResPart* __restrict__ part, int nparts,
-                             double* __restrict__ hist, int nfields) {
+                             double* __restrict__ hist, int nfields, int par) {
   // nfields > 0: the partials form nfields equal contiguous ranges (one per
   // field) and r is the largest per-field residual
   __shared__ float smax[kBlock];
+  const CtrlSnap snap = ctrl_snap(c, par);
   float rmax = -1.0f;
   const int per = nparts / nfields;
   for (int f = threadIdx.x; f < nfields; f += kBlock) {
@@ -441,59 +530,31 @@ __device__ void control_step(Ctrl* __restrict__ c, const ResPart* __restrict__ p
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) control_finish(c, double(smax[0]), hist);
+  if (threadIdx.x == 0) control_finish(c, snap, double(smax[0]), hist, par);
 }
 
-// thread 0: record r, count the iteration, pick the next eps, set stop
-__device__ void control_finish(Ctrl* __restrict__ c, double r, double* __restrict__ hist) {
-  const int64_t l = c->iter;
-  if (hist) hist[l] = r;
-  c->res = r;
-  c->iter = l + 1;
-  c->yskip = 0;
-  const bool final_stage = c->stage_x >= c->n_stages;
-  c->stage_y = c->stage_x;
-  c->eps_y = c->eps_x;
-  int64_t sn = c->iters_per_stage > 0 ? (l + 1) / c->iters_per_stage : c->n_stages;
-  if (sn > c->n_stages) sn = c->n_stages;
-  c->stage_x = (int)sn;
-  c->eps_x = c->eps_tab[sn];
-  if (r != r) {
-    c->stop = 1;
-    c->status = -3;
-  } else if (final_stage && r <= c->tol) {
-    c->stop = 1;
-    c->status = 0;
-  } else if (l + 1 >= c->max_iter) {
-    c->stop = 1;
-    c->status = 1;
-  }
-}
-
-// control step of a single problem: one residual over all partials.  The
-// partials are loaded before the stop flag is read, then reduced with wave
-// shuffles (as the passes reduce theirs).
+// control step of iteration parity par as its own launch.  Single problem:
+// the partials and the control fields are loaded before the skip flag is
+// tested, then reduced with wave exchanges.
 __global__ __launch_bounds__(kBlock) void k_control(Ctrl* __restrict__ c, const ResPart* __restrict__ part,
-                                                     int nparts, double* __restrict__ hist, int nfields) {
+                                                     int nparts, double* __restrict__ hist, int nfields, int par) {
   if (nfields > 0) {
-    if (c->stop) {
-      if (threadIdx.x == 0) c->yskip = 1;
+    if (c->skip[par]) {
+      if (threadIdx.x == 0) control_skip(c, par);
       return;
     }
-    control_step(c, part, nparts, hist, nfields);
+    control_step(c, part, nparts, hist, nfields, par);
     return;
   }
-  float m = -__builtin_inff(), den = 0.f, num = 0.f;
-  for (int k = threadIdx.x; k < nparts; k += kBlock) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
+  const CtrlSnap snap = ctrl_snap(c, par);
+  float m, den, num;
+  ctl_load(part, nparts, m, den, num);
   asm volatile("" ::"v"(m), "v"(den), "v"(num));
-  if (c->stop) {
-    if (threadIdx.x == 0) c->yskip = 1;
+  if (c->skip[par]) {
+    if (threadIdx.x == 0) control_skip(c, par);
     return;
   }
-  __shared__ ResPart tot;
-  block_res_reduce<float>(m, den, num, &tot);
-  __syncthreads();
-  if (threadIdx.x == 0) control_finish(c, double(tot.num) / double(tot.den), hist);
+  ctl_reduce_finish(c, snap, m, den, num, hist, par);
 }
 
 // plain reduction of residual partials into out[0] (single half-step entry)
@@ -518,12 +579,12 @@ __global__ __launch_bounds__(kBlock) void k_bary_combine(const T* __restrict__ T
                                                           BaryW log_alpha, double log_sum_alpha,
                                                           DivDev F2, const T* __restrict__ logdy,
                                                           T* __restrict__ v, T* __restrict__ w, T* __restrict__ logh_out,
-                                                          const Ctrl* __restrict__ c) {
-  if (c->yskip) return;
+                                                          const Ctrl* __restrict__ c, int side) {
+  if (skip_side(c, side)) return;
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= size) return;
-  const T eps = T(c->eps_y);
-  const T eps_w = T(c->eps_x);
+  const T eps = T(eps_of(c, side));
+  const T eps_w = T(eps_next_of(c, side));
   T logh;
   if (F2.kind == 0) {
     double acc = 0.0, asum = 0.0;
@@ -791,8 +852,8 @@ void launch_dense_epi(const T* pm, const T* ps, int nsplit, int64_t Nr, int side
   hipLaunchKernelGGL(k_dense_epi<T>, dim3(ceil_div(Nr, kBlock)), dim3(kBlock), 0, s, pm, ps, nsplit, Nr, side, c, ep);
 }
 
-void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s, int nfields) {
-  hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, c, part, nparts, hist, nfields);
+void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s, int nfields, int par) {
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, c, part, nparts, hist, nfields, par);
 }
 
 void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t s) {
@@ -805,9 +866,10 @@ void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s) {
 
 template <typename T>
 void launch_bary_combine(const T* T2, int nm, int64_t size, const BaryW& log_alpha, double log_sum_alpha,
-                         const DivDev& F2, const T* logdy, T* v, T* w, T* logh, const Ctrl* c, hipStream_t s) {
+                         const DivDev& F2, const T* logdy, T* v, T* w, T* logh, const Ctrl* c, int side,
+                         hipStream_t s) {
   hipLaunchKernelGGL(k_bary_combine<T>, dim3(ceil_div(size, kBlock)), dim3(kBlock), 0, s, T2, nm, size, log_alpha,
-                     log_sum_alpha, F2, logdy, v, w, logh, c);
+                     log_sum_alpha, F2, logdy, v, w, logh, c, side);
 }
 
 template <typename T>
@@ -850,7 +912,7 @@ void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w
   template void launch_dense_epi<T>(const T*, const T*, int, int64_t, int, const Ctrl*, const EpiArgs<T>&,       \
                                     hipStream_t);                                                                 \
   template void launch_bary_combine<T>(const T*, int, int64_t, const BaryW&, double, const DivDev&, const T*,    \
-                                       T*, T*, T*, const Ctrl*, hipStream_t);                                    \
+                                       T*, T*, T*, const Ctrl*, int, hipStream_t);                               \
   template int launch_obj_side<T>(const T*, const T*, const T*, const T*, int64_t, double, const DivDev&, T*,    \
                                   double*, hipStream_t);                                                          \
   template int launch_sum_exp2<T>(const T*, const T*, int64_t, double*, hipStream_t);                            \
@@ -922,8 +984,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_lse(const BItem* __restrict__ 
   using V4 = typename Vec4<T>::type;
   __shared__ V4 tile[kBlock];
   __shared__ int item_sh;
-  const T sc = T(kLog2e / (side == 0 ? c->eps_x : c->eps_y));
-  const int32_t* __restrict__ skip = side == 0 ? bc->stop : bc->yskip;
+  const T sc = T(kLog2e / eps_of(c, side));
+  const int32_t* __restrict__ skip = half_of(side) == 0 ? bc->stop : bc->yskip;
   while (true) {
     __syncthreads();
     if (threadIdx.x == 0) item_sh = atomicAdd(cursor, 1);
@@ -1030,16 +1092,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_control(Ctrl* __restrict__ c, 
 }
 
 // global eps bookkeeping after the per-problem control (single thread)
-__global__ void k_batch_advance(Ctrl* __restrict__ c) {
+__global__ void k_batch_advance(Ctrl* __restrict__ c, int par) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int64_t l = c->iter;
   c->iter = l + 1;
-  c->stage_y = c->stage_x;
-  c->eps_y = c->eps_x;
   int64_t sn = c->iters_per_stage > 0 ? (l + 1) / c->iters_per_stage : c->n_stages;
   if (sn > c->n_stages) sn = c->n_stages;
-  c->stage_x = (int)sn;
-  c->eps_x = c->eps_tab[sn];
+  c->stage[par ^ 1] = (int)sn;
+  c->eps[par ^ 1] = c->eps_tab[sn];
 }
 
 __global__ void k_batch_init(BCtrl* __restrict__ bc, int B, Ctrl* __restrict__ c) {
@@ -1080,9 +1140,9 @@ void launch_batch_lse(int dim, int R, int blocks, const BItem* items, int n_item
 }
 
 void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const int32_t* pstart, int* cursors,
-                          hipStream_t s) {
+                          int par, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_control, dim3(ceil_div(B, kBlock)), dim3(kBlock), 0, s, c, bc, B, part, pstart, cursors);
-  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, c);
+  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, c, par);
 }
 
 void launch_batch_init(BCtrl* bc, int B, Ctrl* c, hipStream_t s) {
@@ -1123,14 +1183,19 @@ namespace uot {
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-template <bool STRIDED, int TPC>
+template <bool STRIDED, int TPC, bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in, int n, int64_t A, int64_t B,
-                                                     double h, int side, const Ctrl* __restrict__ c,
+                                                     int opb, double h, int side, const Ctrl* __restrict__ c,
                                                      EpiArgs<float> ep) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int q = lane >> 4, li = lane & 15;
-  // line group -> 16 lines; lane's line is li
-  const int64_t grp = (int64_t)blockIdx.z * gridDim.y + blockIdx.y;
+  const int nt = n / 16;
+  // logical block -> (block of opb output tiles, line group of 16 lines)
+  const int64_t lid = blockIdx.x;
+  const int nob = MULTI ? opb : 1;         // output tiles of this block
+  const int tpb = nt / nob;                // output-tile blocks per line group
+  const int64_t grp = lid / tpb;
+  const int ob = (int)(lid % tpb);
   int64_t a, bb;
   bool valid;
   if (STRIDED) {
@@ -1145,12 +1210,10 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
   }
   const int64_t base = valid ? (STRIDED ? a * (int64_t)n * B + bb : a * (int64_t)n) : 0;
   const int64_t tstride = STRIDED ? B : 1;
-  const int I0 = blockIdx.x * 16;
-  const int nt = n / 16;
   // The wave's tap tiles jt = wv, wv + 4, ... are taken in chunks of TPC
   // (4 TPC loads issued together).  The first chunk and the operands of the
-  // epilogue this wave finishes (outputs i = I0 + 4 q + wv of line li) are
-  // loaded before the control block is read, so the latencies overlap.
+  // first epilogue this wave finishes (outputs i = I0 + 4 q + wv of line li)
+  // are loaded before the control block is read, so the latencies overlap.
   // Tap (jt, s) of the lane's line is cell jt * 16 + 4 s + q; tiles past the
   // end are read at the last tile (in bounds) and replaced by -inf.  Lanes of
   // a line past the end read line 0 unconditionally: lines never mix (MFMA
@@ -1170,19 +1233,36 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
       }
     }
   };
+  // output element of lane (li, q) in output tile o of the block, row wv
+  auto out_elem = [&](int o) -> int64_t {
+    const int ie = (ob * nob + o) * 16 + 4 * q + wv;
+    return valid ? (STRIDED ? (a * (int64_t)n + ie) * B + bb : a * (int64_t)n + ie) : 0;
+  };
   float wv4[TPC][4];
   load_chunk(wv4, wv);
-  const int ie = I0 + 4 * q + wv;
-  const int64_t eo = valid ? (STRIDED ? (a * (int64_t)n + ie) * B + bb : a * (int64_t)n + ie) : 0;
-  const EpiIn<float> xin = epi_load<float>(eo, ep);
+  int64_t eo = out_elem(0);
+  EpiIn<float> xin = epi_load<float>(eo, ep);
+  // block 0 of a launch that hosts the control step loads the residual
+  // partials and control fields now, and finishes the step at the end
+  const bool hosting = ep.host_ctl != nullptr && blockIdx.x == 0;
+  const int par = par_of(side);
+  CtrlSnap hsnap{};
+  float hm = -__builtin_inff(), hden = 0.f, hnum = 0.f;
+  if (hosting) {
+    hsnap = ctrl_snap(ep.host_ctl, par);
+    ctl_load(ep.host_parts, ep.host_nparts, hm, hden, hnum);
+  }
   // keep those loads ahead of the branch (otherwise they may be moved past it)
 #pragma unroll
   for (int t = 0; t < TPC; ++t)
 #pragma unroll
     for (int s = 0; s < 4; ++s) asm volatile("" ::"v"(wv4[t][s]));
   asm volatile("" ::"v"(xin.ld), "v"(xin.uo), "v"(xin.lp));
-  if (skip_side(c, side)) return;
-  const float cc = float(h * h * kLog2e / (side == 0 ? c->eps_x : c->eps_y));
+  if (skip_side(c, side)) {
+    if (hosting && threadIdx.x == 0) control_skip(ep.host_ctl, par);
+    return;
+  }
+  const float cc = float(h * h * kLog2e / eps_of(c, side));
   // Khat as MFMA A operands: k-step s -> Khat[i = li][k = 4 s + q]
   float kh[4];
 #pragma unroll
@@ -1190,114 +1270,145 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
     const float e = float(li) - 7.5f, f = float(4 * s + q) - 7.5f;
     kh[s] = __builtin_amdgcn_exp2f(2.f * cc * e * f);
   }
-  // running LSE of the 4 outputs i = 4q + r of this lane's line li (D layout)
-  float M[4], S[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    M[r] = -__builtin_inff();
-    S[r] = 0.f;
-  }
-  for (int jc = wv; jc < nt; jc += 4 * TPC) {
-    if (jc != wv) load_chunk(wv4, jc);
-    // the TPC tiles of a chunk are independent until the final merge:
-    // column factors and their line maxima first, then the products, so the
-    // exchanges and the MFMA chains of different tiles overlap
-    float D[TPC], mloc[TPC], beta[TPC][4];
-#pragma unroll
-    for (int t = 0; t < TPC; ++t) {
-      D[t] = float(I0 - (jc + 4 * t) * 16);
-      mloc[t] = -__builtin_inff();
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const float f = float(4 * s + q) - 7.5f;
-        beta[t][s] = wv4[t][s] - cc * (f * (f - 2.f * D[t]));
-        mloc[t] = fmaxf(mloc[t], beta[t][s]);
-      }
-    }
-    // max over the 16 taps of the line: the four lane rows q share a line
-#pragma unroll
-    for (int t = 0; t < TPC; ++t) mloc[t] = max_over_rows(mloc[t]);
-    f32x4_t acc[TPC];
-    float E[TPC][4];
-#pragma unroll
-    for (int t = 0; t < TPC; ++t) {
-      acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-      const float msh = (mloc[t] == -__builtin_inff()) ? 0.f : mloc[t];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) E[t][s] = __builtin_amdgcn_exp2f(beta[t][s] - msh);
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int t = 0; t < TPC; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(kh[s], E[t][s], acc[t], 0, 0, 0);
-    // acc[t][r] = sum_f Khat[e_i][f] E_f for output i = 4 q + r of line li;
-    // one rescale of the running sum per chunk
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float e = float(4 * q + r) - 7.5f;
-      float al[TPC];
-      float mn = M[r];
-#pragma unroll
-      for (int t = 0; t < TPC; ++t) {
-        al[t] = (mloc[t] == -__builtin_inff()) ? -__builtin_inff()
-                                               : (mloc[t] - cc * (e * (e + 2.f * D[t])) - cc * D[t] * D[t]);
-        mn = fmaxf(mn, al[t]);
-      }
-      const float sh = (mn == -__builtin_inff()) ? 0.f : mn;
-      float sum = S[r] * __builtin_amdgcn_exp2f(M[r] - sh);
-#pragma unroll
-      for (int t = 0; t < TPC; ++t) sum += acc[t][r] * __builtin_amdgcn_exp2f(al[t] - sh);
-      S[r] = sum;
-      M[r] = mn;
-    }
-  }
-  // merge the four waves (each saw a quarter of the J tiles); wave w then
-  // finishes output row r = w of every lane
-  __shared__ float smM[4][4][64], smS[4][4][64];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    smM[wv][r][lane] = M[r];
-    smS[wv][r][lane] = S[r];
-  }
-  __syncthreads();
-  Lse2<float> tot;
-  tot.m = smM[0][wv][lane];
-  tot.s = smS[0][wv][lane];
-#pragma unroll
-  for (int k = 1; k < 4; ++k) tot.merge(smM[k][wv][lane], smS[k][wv][lane]);
+  // opb > 1 only when one chunk holds all of a wave's tap tiles (the host
+  // picks opb so), so the taps stay in registers across the output tiles
+  __shared__ float smM[2][4][4][64], smS[2][4][4][64];
   ResAcc<float> ra;
   ra.init();
-  if (valid) epi_apply<float>(eo, tot.result(), xin, c, side, ep, ra);
-  epi_finish<float>(ep, ra, (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+  for (int o = 0; o < nob; ++o) {
+    const int I0 = (ob * nob + o) * 16;
+    // epilogue operands of the next output tile, in flight during this one
+    const bool more = MULTI && o + 1 < nob;
+    const int64_t eo_next = more ? out_elem(o + 1) : eo;
+    const EpiIn<float> xin_next = more ? epi_load<float>(eo_next, ep) : xin;
+    // running LSE of the 4 outputs i = 4q + r of this lane's line li (D layout)
+    float M[4], S[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      M[r] = -__builtin_inff();
+      S[r] = 0.f;
+    }
+    for (int jc = wv; jc < nt; jc += 4 * TPC) {
+      if (jc != wv) load_chunk(wv4, jc);
+      // the TPC tiles of a chunk are independent until the final merge:
+      // column factors and their line maxima first, then the products, so
+      // the exchanges and the MFMA chains of different tiles overlap
+      float D[TPC], mloc[TPC], beta[TPC][4];
+#pragma unroll
+      for (int t = 0; t < TPC; ++t) {
+        D[t] = float(I0 - (jc + 4 * t) * 16);
+        mloc[t] = -__builtin_inff();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float f = float(4 * s + q) - 7.5f;
+          beta[t][s] = wv4[t][s] - cc * (f * (f - 2.f * D[t]));
+          mloc[t] = fmaxf(mloc[t], beta[t][s]);
+        }
+      }
+      // max over the 16 taps of the line: the four lane rows q share a line
+#pragma unroll
+      for (int t = 0; t < TPC; ++t) mloc[t] = max_over_rows(mloc[t]);
+      f32x4_t acc[TPC];
+      float E[TPC][4];
+#pragma unroll
+      for (int t = 0; t < TPC; ++t) {
+        acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        const float msh = (mloc[t] == -__builtin_inff()) ? 0.f : mloc[t];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) E[t][s] = __builtin_amdgcn_exp2f(beta[t][s] - msh);
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int t = 0; t < TPC; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(kh[s], E[t][s], acc[t], 0, 0, 0);
+      // acc[t][r] = sum_f Khat[e_i][f] E_f for output i = 4 q + r of line li;
+      // one rescale of the running sum per chunk
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float e = float(4 * q + r) - 7.5f;
+        float al[TPC];
+        float mn = M[r];
+#pragma unroll
+        for (int t = 0; t < TPC; ++t) {
+          al[t] = (mloc[t] == -__builtin_inff()) ? -__builtin_inff()
+                                                 : (mloc[t] - cc * (e * (e + 2.f * D[t])) - cc * D[t] * D[t]);
+          mn = fmaxf(mn, al[t]);
+        }
+        const float sh = (mn == -__builtin_inff()) ? 0.f : mn;
+        float sum = S[r] * __builtin_amdgcn_exp2f(M[r] - sh);
+#pragma unroll
+        for (int t = 0; t < TPC; ++t) sum += acc[t][r] * __builtin_amdgcn_exp2f(al[t] - sh);
+        S[r] = sum;
+        M[r] = mn;
+      }
+    }
+    // merge the four waves (each saw a quarter of the J tiles); wave w then
+    // finishes output row r = w of every lane.  Two LDS buffers alternate
+    // over the output tiles, so one barrier per tile suffices.
+    const int pb = o & 1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      smM[pb][wv][r][lane] = M[r];
+      smS[pb][wv][r][lane] = S[r];
+    }
+    __syncthreads();
+    Lse2<float> tot;
+    tot.m = smM[pb][0][wv][lane];
+    tot.s = smS[pb][0][wv][lane];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) tot.merge(smM[pb][k][wv][lane], smS[pb][k][wv][lane]);
+    if (valid) epi_apply<float>(eo, tot.result(), xin, c, side, ep, ra);
+    eo = eo_next;
+    xin = xin_next;
+  }
+  epi_finish<float>(ep, ra, (int)lid);
+  if (hosting) ctl_reduce_finish(ep.host_ctl, hsnap, hm, hden, hnum, ep.host_hist, par);
 }
 
-static inline void tf_grid(int n, int64_t A, int64_t B, bool strided, unsigned& gx, unsigned& gy, unsigned& gz) {
-  const int64_t groups = strided ? A * ((B + 15) / 16) : (A + 15) / 16;
-  const int64_t ylim = 65535;
-  const int64_t y = groups < ylim ? groups : ylim;
-  gx = (unsigned)(n / 16);
-  gy = (unsigned)y;
-  gz = (unsigned)((groups + y - 1) / y);
+// output tiles per block: 1 unless there are enough line groups to fill the
+// chip with fewer, longer blocks, and only while one chunk of tap tiles
+// holds all of a wave's tiles (so the taps are loaded once per block)
+static inline int tf_tpc(int n) {
+  const int per_wave = (n / 16 + 3) / 4;
+  return per_wave >= 4 ? 4 : (per_wave >= 2 ? 2 : 1);
+}
+
+static inline int tf_opb(int n, int64_t groups) {
+  const int nt = n / 16;
+  if (nt > 4 * tf_tpc(n)) return 1;
+  int opb = 1;
+  while (nt % (opb * 2) == 0 && (int64_t)(nt / (opb * 2)) * groups >= 2048) opb *= 2;
+  return opb;
+}
+
+static inline int64_t tf_groups(int64_t A, int64_t B, bool strided) {
+  return strided ? A * ((B + 15) / 16) : (A + 15) / 16;
 }
 
 int grid_tf_parts(int n, int64_t A, int64_t B, bool strided) {
-  unsigned gx, gy, gz;
-  tf_grid(n, A, B, strided, gx, gy, gz);
-  return (int)((int64_t)gx * gy * gz);
+  const int64_t g = tf_groups(A, B, strided);
+  return (int)((n / 16) / tf_opb(n, g) * g);
 }
 
 void launch_grid_tf(const float* in, int64_t A, int n, int64_t B, bool strided, double h, int side, const Ctrl* c,
                     const EpiArgs<float>& ep, hipStream_t s) {
-  unsigned gx, gy, gz;
-  tf_grid(n, A, B, strided, gx, gy, gz);
-  // tiles per chunk: as many of a wave's tiles as exist, up to 4
-  const int per_wave = (n / 16 + 3) / 4;
-#define UOT_TF(ST, TP) \
-  hipLaunchKernelGGL((k_grid_tf<ST, TP>), dim3(gx, gy, gz), dim3(kBlock), 0, s, in, n, A, B, h, side, c, ep)
+  const int64_t g = tf_groups(A, B, strided);
+  const int opb = tf_opb(n, g);
+  const unsigned blocks = (unsigned)((n / 16) / opb * g);
+  const int tpc = tf_tpc(n);
+#define UOT_TF(ST, TP)                                                                                         \
+  do {                                                                                                         \
+    if (opb > 1)                                                                                               \
+      hipLaunchKernelGGL((k_grid_tf<ST, TP, true>), dim3(blocks), dim3(kBlock), 0, s, in, n, A, B, opb, h, side, \
+                         c, ep);                                                                               \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_grid_tf<ST, TP, false>), dim3(blocks), dim3(kBlock), 0, s, in, n, A, B, 1, h, side, \
+                         c, ep);                                                                               \
+  } while (0)
   if (strided) {
-    if (per_wave >= 4) UOT_TF(true, 4); else if (per_wave >= 2) UOT_TF(true, 2); else UOT_TF(true, 1);
+    if (tpc == 4) UOT_TF(true, 4); else if (tpc == 2) UOT_TF(true, 2); else UOT_TF(true, 1);
   } else {
-    if (per_wave >= 4) UOT_TF(false, 4); else if (per_wave >= 2) UOT_TF(false, 2); else UOT_TF(false, 1);
+    if (tpc == 4) UOT_TF(false, 4); else if (tpc == 2) UOT_TF(false, 2); else UOT_TF(false, 1);
   }
 #undef UOT_TF
 }

@@ -27,6 +27,14 @@ template <typename T> struct EpiArgs {
   ResPart* part;
   int64_t size;   // elements per field: logd is indexed by e % size
   DivDev F;
+  // hosted control step (first Y pass of a single-problem grid solve): when
+  // host_ctl is set, block 0 of the launch also runs the control step of the
+  // iteration on the host_nparts residual partials of the X half-step
+  Ctrl* host_ctl;
+  const ResPart* host_parts;
+  double* host_hist;
+  int host_nparts;
+  int host_pad;
 };
 
 template <typename T> void launch_log(const T* src, T* dst, int64_t n, int zero_is_ninf, hipStream_t s);
@@ -49,7 +57,7 @@ void launch_dense_lse(int dim, int R, const T* xr, int64_t Nr, const T* yc, cons
 template <typename T>
 void launch_dense_epi(const T* pm, const T* ps, int nsplit, int64_t Nr, int side, const Ctrl* c,
                       const EpiArgs<T>& ep, hipStream_t s);
-void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s, int nfields = 0);
+void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s, int nfields, int par);
 void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t s);
 void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s);
 constexpr int kMaxBary = 64;
@@ -58,7 +66,8 @@ struct BaryW {
 };
 template <typename T>
 void launch_bary_combine(const T* T2, int nm, int64_t size, const BaryW& log_alpha, double log_sum_alpha,
-                         const DivDev& F2, const T* logdy, T* v, T* w, T* logh, const Ctrl* c, hipStream_t s);
+                         const DivDev& F2, const T* logdy, T* v, T* w, T* logh, const Ctrl* c, int side,
+                         hipStream_t s);
 template <typename T>
 int launch_obj_side(const T* pot, const T* S, const T* p, const T* d, int64_t n, double eps, const DivDev& F,
                     T* pi_out, double* part, hipStream_t s);
@@ -76,7 +85,7 @@ void launch_batch_lse(int dim, int R, int blocks, const BItem* items, int n_item
                       const int64_t* offC, const T* xr, int64_t totR, const T* yc, int64_t totC, const T* w,
                       const BCtrl* bc, const Ctrl* c, int side, const EpiArgs<T>& ep, hipStream_t s);
 void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const int32_t* pstart, int* cursors,
-                          hipStream_t s);
+                          int par, hipStream_t s);
 void launch_batch_init(BCtrl* bc, int B, Ctrl* c, hipStream_t s);
 void launch_set_int(int* p, int n, int v, hipStream_t s);
 
