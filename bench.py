@@ -105,6 +105,7 @@ def warm_batched(U, ctx, dev, np, torch):
         "converged": int(info["n_converged"]), "problems": len(probs), "seconds": bs,
         "problems_per_s": len(probs) / bs, "problem_iters_per_s": float(it.sum()) / bs,
         "pair_evals_per_s": float((pairs * it).sum()) * 2 / bs,
+        "pair_evals_frac_of_exp_peak": float((pairs * it).sum()) * 2 / bs / exp_peak(),
         "latency_ms_p50": float(np.percentile(info["latency_ms"], 50)),
         "latency_ms_p99": float(np.percentile(info["latency_ms"], 99)),
         "tile_rows": info["tile_rows"], "blocks_per_cu": info["blocks_per_cu"],
@@ -132,6 +133,28 @@ def warm_batched(U, ctx, dev, np, torch):
 
 
 PASS_NAMES = ["k_grid_tf<false, 4>", "k_grid_tf<true, 4>"]
+
+# HBM bytes per launch (calibrated FETCH_SIZE read + WRITE_SIZE written) of the
+# two passes at both launch shapes, from the two counter runs of
+# `bench.py --pmc-workload`; they hold for the kernel source they were taken
+# on (sha256 of csrc/uot_kernels.hip) and are reported as null otherwise.
+TRAFFIC_SOURCE_SHA256 = "a1b49c5388be77e68b89761f105058015900ac8fcd8f2e7bbea6953d2187372d"
+TRAFFIC_BYTES = {
+    ("k_grid_tf<false, 4>", 1): (2262240, 259672),
+    ("k_grid_tf<true, 4>", 1): (3077429, 523333),
+    ("k_grid_tf<false, 4>", 256): (67285400, 67108864),
+    ("k_grid_tf<true, 4>", 256): (406213801, 134348800),
+}
+
+
+def traffic(kernel, fields):
+    """(bytes read, bytes written) per launch, or None once the kernels changed."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1607_05816_amd", "csrc", "uot_kernels.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC_SOURCE_SHA256:
+            return None
+    return TRAFFIC_BYTES.get((kernel, fields))
 
 
 def exp2_executed_per_launch(lines, n, tpc=4):
@@ -162,6 +185,13 @@ def grid_roofline(U, probs, last, ctx, torch, np, nb_fields=256):
            "exp2_executed_per_launch": exp2_executed_per_launch(N_GRID, N_GRID),
            "avg_ms_by_kernel": dict(zip(PASS_NAMES, ms)), "launch": "single 256x256 problem"}
     out["executed_exp2_frac"] = out["exp2_executed_per_launch"] / (ms[k] * 1e-3) / peak
+    tr = traffic(PASS_NAMES[k], 1)
+    if tr is not None:
+        out["traffic"] = float(sum(tr))
+        out["traffic_read_written"] = list(tr)
+        # the X-side strided pass reads its input, log p, u_old, log dx and
+        # writes u, w (4 B each per cell); the contiguous pass reads w, writes t
+        out["traffic_algorithmic"] = float(N_GRID * N_GRID * 4 * (6 if k == 1 else 2))
     pb = probs[0][1]
     p = pb.p.reshape(1, -1).expand(nb_fields, -1).contiguous()
     v = last[0][3].reshape(1, -1).expand(nb_fields, -1).contiguous()
@@ -175,9 +205,59 @@ def grid_roofline(U, probs, last, ctx, torch, np, nb_fields=256):
                       "work_per_launch": tb, "avg_ms_by_kernel": dict(zip(PASS_NAMES, msb)),
                       "exp2_executed_per_launch": exp2_executed_per_launch(nb_fields * N_GRID, N_GRID)}
     out["batched"]["executed_exp2_frac"] = out["batched"]["exp2_executed_per_launch"] / (msb[kb] * 1e-3) / peak
+    trb = traffic(PASS_NAMES[kb], nb_fields)
+    out["batched"]["traffic"] = None if trb is None else float(sum(trb))
     del p, v
     torch.cuda.empty_cache()
     return out
+
+
+def dense_roofline(U, torch, np, dev, ctx, n=20000, eps=1e-3):
+    """Dense point-cloud product (3-D clouds, N = M = 20000, 8-component
+    mixtures, FP32): the column-split log-sum-exp kernel of one X half-step,
+    launched back to back between HIP events.  Algorithmic work: one exp per
+    pair (N M per launch), priced against the v_exp_f32 issue peak."""
+    from paper_1607_05816_amd import synth
+    pr = synth.clouds3d(0, N=n, M=n)
+    T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
+    F = U.KL(1.0)
+    pb = U.points_problem(T(pr.x), T(pr.y), T(pr.p), T(pr.q), T(pr.dx), T(pr.dy), F, F)
+    pb.workspace()
+    v = torch.zeros(n, dtype=torch.float32, device=dev)
+    ms = U.time_half_step(pb, eps, v, reps=20, ctx=ctx)
+    pairs = float(n) * n
+    peak = exp_peak()
+    return {"bound": "alu", "kernel": "k_dense_lse<float, 3, 2>", "kernel_avg_ms": ms[0],
+            "achieved": pairs / (ms[0] * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "Texp/s",
+            "frac": pairs / (ms[0] * 1e-3) / peak, "work_per_launch": pairs, "work_unit": "exp (one per pair)",
+            "epilogue_ms": ms[1], "workload": "clouds3d N=M=%d eps=%g FP32" % (n, eps)}
+
+
+def pmc_workload(U, torch, np, dev, ctx):
+    """The launches the HBM-traffic counters are read on (rocprofv3 --pmc
+    FETCH_SIZE, then WRITE_SIZE): a plain device copy of 256 MiB (the
+    calibration kernel of known size), then the two passes of one X
+    half-step on the headline field (single launch shape) and on a batch of
+    256 such fields."""
+    from paper_1607_05816_amd import synth
+    src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    pr = synth.blobs2d(0, n=N_GRID)
+    t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+    d = np.full(pr.size, pr.h[0] * pr.h[1])
+    F = U.KL(PENALTIES[0][1])
+    pb = U.grid_problem(pr.shape, pr.h, t(pr.p), t(pr.q), t(d), t(d), F, F)
+    u, v, info = U.solve(pb, EPS, eps0=EPS0, tol=TOL, max_iter=MAX_ITER, check_every=50, ctx=ctx)
+    U.time_half_step(pb, EPS, v, reps=20, ctx=ctx)
+    nb = 256
+    p = pb.p.reshape(1, -1).expand(nb, -1).contiguous()
+    vb = v.reshape(1, -1).expand(nb, -1).contiguous()
+    U.time_fields_half_step((N_GRID, N_GRID), pr.h, p, pb.dx, pb.dy, F, EPS, vb, reps=5, ctx=ctx)
+    torch.cuda.synchronize()
+    print("pmc workload done", flush=True)
 
 
 def main():
@@ -189,6 +269,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-warm-batched", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--pmc-workload", action="store_true",
+                    help="only run the launches the HBM-traffic counters are read on")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -204,6 +287,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.pmc_workload:
+        pmc_workload(U, torch, np, dev, U.default_context())
+        return
     pr = synth.blobs2d(args.seed, n=N_GRID)
     t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
     d = np.full(pr.size, pr.h[0] * pr.h[1])
@@ -259,6 +345,8 @@ def main():
         "gap": {o[0]: o[2]["gap"] for o in last},
         "roofline": roofline,
     }
+    if not args.no_dense:
+        line["roofline_dense"] = dense_roofline(U, torch, np, dev, ctx)
     if not args.no_warm_batched:
         line["warm_batched_vs_plain"] = warm_batched(U, ctx, dev, np, torch)
     if not args.no_cpu_baseline:

@@ -1,13 +1,23 @@
-"""Per-launch-shape kernel summary of a rocprofv3 trace database.
+"""Per-launch-shape kernel summaries of rocprofv3 output.
 
     python -m paper_1607_05816_amd.rocpd_summary <run_results.db> [--top N]
+    python -m paper_1607_05816_amd.rocpd_summary --pmc <fetch.csv> <write.csv> [--copy-bytes B]
 
 rocprofv3's own --stats table averages every launch of a kernel symbol; the
 same symbol runs here at several launch shapes (one field vs a batch of
 fields), so this groups the dispatches by (kernel, grid size) and prints a
 markdown table of calls and durations in ns.
+
+--pmc: the counter_collection.csv files of two `rocprofv3 --pmc FETCH_SIZE`
+and `--pmc WRITE_SIZE` runs of the same program.  Both counters read KiB per
+dispatch; each is calibrated by the largest `__amd_rocclr_copyBuffer`
+dispatch of the run, a plain device copy of --copy-bytes bytes (it fetches
+and writes exactly that many), and the table gives calibrated bytes per
+launch.
 """
 import argparse
+import collections
+import csv
 import sqlite3
 
 
@@ -24,12 +34,43 @@ def summarize(path, top=12):
     return "\n".join(out)
 
 
+def _counter_means(path):
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        agg[(name, int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}, {k: len(v) for k, v in agg.items()}
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_bytes, top=12):
+    f, nf = _counter_means(fetch_csv)
+    w, _ = _counter_means(write_csv)
+    copies = [k for k in f if k[0] == "__amd_rocclr_copyBuffer"]
+    cal = max(copies, key=lambda k: f[k])
+    kf = copy_bytes / (f[cal] * 1024.0)
+    kw = copy_bytes / (w[cal] * 1024.0)
+    out = ["Calibration: copy of %d bytes reads FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB -> factors %.4f (fetch), "
+           "%.4f (write)." % (copy_bytes, f[cal], w[cal], kf, kw), "",
+           "| kernel | grid (work-items) | launches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | read (bytes) | written (bytes) |",
+           "|:--|:--|--:|--:|--:|--:|--:|"]
+    for k in sorted(f, key=lambda k: -f[k] * nf[k])[:top]:
+        wk = w.get(k, float("nan"))
+        out.append("| `%s` | %d | %d | %.1f | %.1f | %.0f | %.0f |" % (k[0], k[1], nf[k], f[k], wk, f[k] * 1024 * kf,
+                                                                   wk * 1024 * kw))
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("db")
+    ap.add_argument("db", nargs="?")
     ap.add_argument("--top", type=int, default=12)
+    ap.add_argument("--pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--copy-bytes", type=int, default=256 << 20)
     a = ap.parse_args()
-    print(summarize(a.db, a.top))
+    if a.pmc:
+        print(summarize_pmc(a.pmc[0], a.pmc[1], a.copy_bytes, a.top))
+    else:
+        print(summarize(a.db, a.top))
 
 
 if __name__ == "__main__":
