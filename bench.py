@@ -260,6 +260,45 @@ def pmc_workload(U, torch, np, dev, ctx):
     print("pmc workload done", flush=True)
 
 
+BF16_MFMA_PEAK = 2.5e15     # MI355X dense BF16 MFMA, FLOP/s
+
+
+def gemm_roofline(U, torch, np, dev, ctx, batch=256):
+    """Training GEMMs of the warm-start net (8192 -> 256 -> 256 -> 256 -> 4096,
+    BF16 operands, FP32 accumulation) at batch 256: the four largest products
+    of one Adam step, each launched back to back between HIP events, priced
+    against the dense BF16 MFMA peak; plus the whole training step (forward,
+    loss, backward, Adam) timed over 20 steps."""
+    g = torch.Generator(device="cpu")
+    g.manual_seed(0)
+    rnd = lambda *s: U.bf16_bits(torch.randn(*s, generator=g).to(dev)).contiguous()
+    shapes = [("forward layer 1", False, True, batch, 256, 8192), ("backward dh layer 4", False, False, batch, 256, 4096),
+              ("backward dW layer 1", True, False, 256, 8192, batch), ("forward layer 4", False, True, batch, 4096, 256)]
+    out = {"bound": "mfma", "peak": BF16_MFMA_PEAK / 1e12, "unit": "TFLOP/s", "gemms": []}
+    for name, ta, tb, M, N, K in shapes:
+        A = rnd(K, M) if ta else rnd(M, K)
+        B = rnd(N, K) if tb else rnd(K, N)
+        ms = U.time_gemm_bf16(A, B, M, N, K, ta=ta, tb=tb, reps=20, ctx=ctx)
+        fl = 2.0 * M * N * K
+        out["gemms"].append({"name": name, "M": M, "N": N, "K": K, "ms": ms, "achieved": fl / (ms * 1e-3) / 1e12,
+                             "frac": fl / (ms * 1e-3) / BF16_MFMA_PEAK})
+    net = U.WarmStartNet(8192, 256, 4096, dev, seed=0)
+    x = torch.randn(batch, 8192, generator=g).to(dev)
+    t = torch.randn(batch, 4096, generator=g).to(dev) * 0.1
+    for _ in range(3):
+        net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) / 20 * 1e3
+    step_flops = 3 * 2.0 * batch * (8192 * 256 + 2 * 256 * 256 + 256 * 4096)
+    out["train_step"] = {"batch": batch, "ms": step_ms, "achieved": step_flops / (step_ms * 1e-3) / 1e12,
+                         "frac": step_flops / (step_ms * 1e-3) / BF16_MFMA_PEAK}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +309,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-warm-batched", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-gemm", action="store_true")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="only run the launches the HBM-traffic counters are read on")
     args = ap.parse_args()
@@ -347,6 +387,8 @@ def main():
     }
     if not args.no_dense:
         line["roofline_dense"] = dense_roofline(U, torch, np, dev, ctx)
+    if not args.no_gemm:
+        line["roofline_gemm"] = gemm_roofline(U, torch, np, dev, ctx)
     if not args.no_warm_batched:
         line["warm_batched_vs_plain"] = warm_batched(U, ctx, dev, np, torch)
     if not args.no_cpu_baseline:

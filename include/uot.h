@@ -361,6 +361,12 @@ int uot_time_fields_half_step(uot_ctx *ctx, const uot_problem *pb, int nb, doubl
                               const void *v, int reps, double *ms, int *n_kernels, void *ws,
                               size_t ws_bytes, int grid_kernel);
 
+/* Average device time in ms of uot_gemm_bf16 with these arguments over
+ * `reps` back-to-back launches on the library stream (HIP events). */
+int uot_time_gemm_bf16(uot_ctx *ctx, int ta, int tb, int M, int N, int K, const uint16_t *A,
+                       int64_t lda, const uint16_t *B, int64_t ldb, float *C, int64_t ldc,
+                       int reps, double *ms);
+
 /* Throughput probe of the current device: v_exp_f32 results per second and
  * v_add_f32 results per second, from 8 independent dependency chains per lane
  * on 64 waves per compute unit.  Allocates a small scratch buffer itself. */

@@ -11,6 +11,7 @@
 //   W1 [width x n_in], b1 [width], W2 [width x width], b2, W3 [width x width],
 //   b3, W4 [n_out x width], b4 [n_out].
 #include <hip/hip_runtime.h>
+#include <cstdlib>
 
 #include <cmath>
 #include <vector>
@@ -43,59 +44,94 @@ static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1
 //   TA = false: A[m][k] = A[m*lda + k];  TA = true: A[m][k] = A[k*lda + m]
 //   TB = false: B[k][n] = B[k*ldb + n];  TB = true: B[k][n] = B[n*ldb + k]
 // Block tile 64 x 64, K tile 32, 4 waves of 32 x 32 (2 x 2 MFMA 16x16x32).
+// Split K (blockIdx.z): each block sums the K range [z kc, (z + 1) kc) and
+// adds its partial into C with FP32 atomics (C cleared beforehand; split 0
+// adds the bias); used when there are too few output tiles to fill the chip.
+// Operands move as 16-byte vectors along their contiguous axis where the
+// leading dimension and the tile edge allow, element by element otherwise.
 // ---------------------------------------------------------------------------
 constexpr int TM = 64, TN = 64, TK = 32, LK = TK + 8;
+
+// 8 consecutive u16 from p (16-byte aligned), or element by element with
+// zeros past `avail` elements
+__device__ __forceinline__ void load8(const u16* __restrict__ p, int avail, bool vec, u16 (&v)[8]) {
+  if (vec && avail >= 8) {
+    const uint4 q = *reinterpret_cast<const uint4*>(p);
+    __builtin_memcpy(v, &q, sizeof(q));
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = j < avail ? p[j] : (u16)0;
+  }
+}
+
+// One 64 x 32 operand tile, as T[row][k] in LDS, moved in two steps so the
+// global loads of the next K tile overlap the MFMAs of the current one:
+// fetch_tile (global -> 8 registers per thread), store_tile (registers ->
+// LDS).  Row-major source (rows contiguous in k) when !TRANS, k-major source
+// (rows contiguous) when TRANS.
+template <bool TRANS>
+__device__ __forceinline__ void fetch_tile(u16 (&v)[8], const u16* __restrict__ X, int64_t ld, int r0, int R, int k0,
+                                           int kend, bool vec) {
+  const int tid = threadIdx.x;
+  if (!TRANS) {
+    const int r = tid >> 2, c = (tid & 3) * 8;
+    const int row = r0 + r, k = k0 + c;
+    const int avail = (row < R) ? (kend - k) : 0;
+    load8(X + (int64_t)(row < R ? row : 0) * ld + (k < kend ? k : 0), avail, vec, v);
+  } else {
+    const int kk = tid >> 3, c = (tid & 7) * 8;
+    const int k = k0 + kk, row = r0 + c;
+    const int avail = (k < kend) ? (R - row) : 0;
+    load8(X + (int64_t)(k < kend ? k : 0) * ld + (row < R ? row : 0), avail, vec, v);
+  }
+}
+
+template <bool TRANS>
+__device__ __forceinline__ void store_tile(u16 (*T)[LK], const u16 (&v)[8]) {
+  const int tid = threadIdx.x;
+  if (!TRANS) {
+    const int r = tid >> 2, c = (tid & 3) * 8;
+    uint4 q;
+    __builtin_memcpy(&q, v, sizeof(q));
+    *reinterpret_cast<uint4*>(&T[r][c]) = q;
+  } else {
+    const int kk = tid >> 3, c = (tid & 7) * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) T[c + j][kk] = v[j];
+  }
+}
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(kB) void k_gemm(const u16* __restrict__ A, int64_t lda, const u16* __restrict__ Bm,
                                               int64_t ldb, int M, int N, int K, float* __restrict__ C, int64_t ldc,
-                                              u16* __restrict__ Cb, const float* __restrict__ bias, int relu) {
+                                              u16* __restrict__ Cb, const float* __restrict__ bias, int relu, int kc,
+                                              int split) {
   __shared__ __align__(16) u16 As[TM][LK];
   __shared__ __align__(16) u16 Bs[TN][LK];
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int kb = blockIdx.z * kc;
+  const int ke = kb + kc < K ? kb + kc : K;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  // 16-byte loads need 8-element aligned rows (base pointers are 256-byte aligned)
+  const bool va = (lda % 8) == 0 && (reinterpret_cast<uintptr_t>(A) % 16) == 0;
+  const bool vb = (ldb % 8) == 0 && (reinterpret_cast<uintptr_t>(Bm) % 16) == 0;
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += TK) {
-    if (!TA) {
-      const int r = tid >> 2, c = (tid & 3) * 8;
-      const int m = m0 + r;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + c + j;
-        As[r][c + j] = (m < M && k < K) ? A[(int64_t)m * lda + k] : (u16)0;
-      }
-    } else {
-      const int kk = tid >> 3, c = (tid & 7) * 8;
-      const int k = k0 + kk;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int m = m0 + c + j;
-        As[c + j][kk] = (m < M && k < K) ? A[(int64_t)k * lda + m] : (u16)0;
-      }
-    }
-    if (TB) {
-      const int r = tid >> 2, c = (tid & 3) * 8;
-      const int n = n0 + r;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + c + j;
-        Bs[r][c + j] = (n < N && k < K) ? Bm[(int64_t)n * ldb + k] : (u16)0;
-      }
-    } else {
-      const int kk = tid >> 3, c = (tid & 7) * 8;
-      const int k = k0 + kk;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int n = n0 + c + j;
-        Bs[c + j][kk] = (n < N && k < K) ? Bm[(int64_t)k * ldb + n] : (u16)0;
-      }
-    }
+  u16 ra[8], rb[8];
+  fetch_tile<TA>(ra, A, lda, m0, M, kb, ke, va);
+  fetch_tile<!TB>(rb, Bm, ldb, n0, N, kb, ke, vb);
+  for (int k0 = kb; k0 < ke; k0 += TK) {
+    store_tile<TA>(As, ra);
+    store_tile<!TB>(Bs, rb);
     __syncthreads();
+    if (k0 + TK < ke) {
+      fetch_tile<TA>(ra, A, lda, m0, M, k0 + TK, ke, va);
+      fetch_tile<!TB>(rb, Bm, ldb, n0, N, k0 + TK, ke, vb);
+    }
     // operand layout of v_mfma_f32_16x16x32_bf16: lane l holds row (l % 16)
     // of A and column (l % 16) of B, k = 8 (l / 16) .. 8 (l / 16) + 7
 #pragma unroll
@@ -120,19 +156,50 @@ __global__ __launch_bounds__(kB) void k_gemm(const u16* __restrict__ A, int64_t 
         const int n = n0 + wn + j * 16 + (lane & 15);
         if (m < M && n < N) {
           float x = acc[i][j][r];
-          if (bias) x += bias[n];
-          if (relu) x = x > 0.f ? x : 0.f;
-          if (C) C[(int64_t)m * ldc + n] = x;
-          if (Cb) Cb[(int64_t)m * ldc + n] = f2bf(x);
+          if (bias && blockIdx.z == 0) x += bias[n];
+          if (split) {
+            atomicAdd(&C[(int64_t)m * ldc + n], x);
+          } else {
+            if (relu) x = x > 0.f ? x : 0.f;
+            if (C) C[(int64_t)m * ldc + n] = x;
+            if (Cb) Cb[(int64_t)m * ldc + n] = f2bf(x);
+          }
         }
       }
+}
+
+// C[m][n] = 0 for m < M, n < N
+__global__ void k_zero2d(float* __restrict__ C, int M, int N, int64_t ldc) {
+  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (t >= (int64_t)M * N) return;
+  C[(t / N) * ldc + t % N] = 0.f;
+}
+
+// K-splits for a product: enough blocks for the chip (>= 512) when the
+// output has few tiles and K is long; 1 when the result needs ReLU or BF16
+// (those are not additive), or when the caller asks for plain launches
+static int gemm_splits(int M, int N, int K, bool additive) {
+  static const int mode = [] {
+    const char* v = std::getenv("UOT_GEMM_SPLITK");
+    return v ? std::atoi(v) : 1;
+  }();
+  if (!additive || mode == 0) return 1;
+  const int64_t tiles = (int64_t)cdiv(M, TM) * cdiv(N, TN);
+  int s = 1;
+  while (tiles * s < 512 && K / (2 * s) >= 256) s *= 2;
+  return s;
 }
 
 template <bool TA, bool TB>
 static void gemm(const u16* A, int64_t lda, const u16* B, int64_t ldb, int M, int N, int K, float* C, int64_t ldc,
                  u16* Cb, const float* bias, int relu, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm<TA, TB>), dim3(cdiv(N, TN), cdiv(M, TM)), dim3(kB), 0, s, A, lda, B, ldb, M, N, K, C, ldc,
-                     Cb, bias, relu);
+  const int sp = gemm_splits(M, N, K, C != nullptr && Cb == nullptr && !relu);
+  const int kc = sp > 1 ? (int)(cdiv(cdiv(K, sp), TK) * TK) : K;
+  const int sz = sp > 1 ? (int)cdiv(K, kc) : 1;
+  if (sz > 1)
+    hipLaunchKernelGGL(k_zero2d, dim3(cdiv((int64_t)M * N, kB)), dim3(kB), 0, s, C, M, N, ldc);
+  hipLaunchKernelGGL((k_gemm<TA, TB>), dim3(cdiv(N, TN), cdiv(M, TM), sz), dim3(kB), 0, s, A, lda, B, ldb, M, N, K, C,
+                     ldc, Cb, bias, relu, kc, sz > 1 ? 1 : 0);
 }
 
 // y = bf16(scale * x + shift)
@@ -528,6 +595,35 @@ int uot_gemm_bf16(uot_ctx* ctx, int ta, int tb, int M, int N, int K, const uint1
   else if (!ta && tb) gemm<false, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
   else if (ta && !tb) gemm<true, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
   else gemm<true, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
+int uot_time_gemm_bf16(uot_ctx* ctx, int ta, int tb, int M, int N, int K, const uint16_t* A, int64_t lda,
+                       const uint16_t* B, int64_t ldb, float* C, int64_t ldc, int reps, double* ms) {
+  if (!ctx || !A || !B || !C || !ms || M < 1 || N < 1 || K < 1 || reps < 1) return fail(UOT_E_INVALID, "bad arguments");
+  int rc = begin(ctx);
+  if (rc) return rc;
+  hipStream_t s = ctx->work;
+  auto run = [&] {
+    if (!ta && !tb) gemm<false, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
+    else if (!ta && tb) gemm<false, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
+    else if (ta && !tb) gemm<true, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
+    else gemm<true, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
+  };
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  run();
+  HIP_TRY(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) run();
+  HIP_TRY(hipEventRecord(e1, s));
+  HIP_TRY(hipEventSynchronize(e1));
+  float t = 0.f;
+  HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+  *ms = double(t) / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   HIP_TRY(hipGetLastError());
   return finish(ctx);
 }

@@ -128,6 +128,8 @@ def lib():
         "uot_grid_upsample": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, c_vp]),
         "uot_bary_estimate": (c_i32, [c_vp, c_vp, c_i32, c_i64, P(c_dbl), c_dbl, P(UotDiv), c_vp]),
         "uot_gemm_bf16": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64]),
+        "uot_time_gemm_bf16": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,
+                                       c_i32, P(c_dbl)]),
         "uot_solve_batched": (c_i32, [c_vp, P(UotBatchProblem), P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t,
                                       P(UotBatchResult)]),
     }
@@ -595,6 +597,18 @@ def gemm_bf16(A_bits, B_bits, M, N, K, ta=False, tb=False, lda=None, ldb=None, c
     _check(lib().uot_gemm_bf16(ctx.handle, int(ta), int(tb), M, N, K, _ptr(A_bits), lda, _ptr(B_bits), ldb, _ptr(C),
                                N), "uot_gemm_bf16", False)
     return C
+
+
+def time_gemm_bf16(A_bits, B_bits, M, N, K, ta=False, tb=False, reps=20, ctx: Optional[Context] = None):
+    """Average ms of gemm_bf16 with these operands (HIP events, library stream)."""
+    ctx = ctx or default_context()
+    C = torch.empty(M, N, dtype=torch.float32, device=A_bits.device)
+    lda = M if ta else K
+    ldb = K if tb else N
+    ms = c_dbl()
+    _check(lib().uot_time_gemm_bf16(ctx.handle, int(ta), int(tb), M, N, K, _ptr(A_bits), lda, _ptr(B_bits), ldb,
+                                    _ptr(C), N, int(reps), ctypes.byref(ms)), "uot_time_gemm_bf16", False)
+    return ms.value
 
 
 class WarmStartNet:
