@@ -139,8 +139,14 @@ typedef struct uot_params {
   int64_t *kernel_launches; /* optional HOST array [4]: launches per class   */
   int32_t grid_kernel;   /* grids: 0 default (2 for FP32, 1 for FP64), 1 direct log-sum-exp
                             passes, 2 tile-factored FP32 MFMA passes (FP32
-                            problems, axes with a multiple of 16 cells; other
-                            axes use direct passes)                        */
+                            problems, axes with a multiple of 16 cells and
+                            h^2 log2(e) / eps <= 0.5 at the final eps; other
+                            axes use direct passes), 3 as 2 with FP16 MFMA
+                            operands where h^2 log2(e) / eps <= 0.125
+                            (results good to ~1e-3 relative; the residual
+                            levels off near 2e-5), 4 mixed precision: the
+                            passes of 3 until the residual reaches 1e-4, then
+                            those of 2 down to tol (FP32 accuracy)         */
   int32_t reserved;
 } uot_params;
 

@@ -125,6 +125,7 @@ struct Plan {
   int nparts_x = 0;      // residual partials written by the X epilogue
   int gk = 1;            // grid passes: 1 direct log-sum-exp, 2 tile-factored MFMA where allowed
   bool tf_axis[3] = {false, false, false};   // tile-factored pass used on this axis
+  bool tf16_axis[3] = {false, false, false}; // ... with FP16 operands
   // workspace offsets
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
       o_gcost, o_obj, o_scal, total;
@@ -138,6 +139,14 @@ bool use_tf(const Plan& P, int axis) { return P.tf_axis[axis]; }
 // far inside the FP32 range (c <= 0.5, i.e. |log2 Khat| <= 56.25) at the
 // smallest eps of the schedule, and only for FP32 axes of a multiple of 16 cells.
 constexpr double kTfMaxC = 0.5;
+// FP16 operands (grid_kernel 3): Khat must stay below the FP16 maximum, 2 c
+// 7.5^2 <= 15 (c <= 0.133); axes beyond that use the FP32 MFMA pass.
+constexpr double kTf16MaxC = 0.125;
+// Mixed precision (grid_kernel 4): FP16 operands until the residual reaches
+// this value (the FP16 passes level off near 2e-5), FP32 operands after.
+constexpr double kMixedSwitchTol = 1e-4;
+
+bool has_tf16(const Plan& P) { return P.tf16_axis[0] || P.tf16_axis[1] || P.tf16_axis[2]; }
 
 int grid_final_parts_for(const Plan& P, bool tf0) {
   const int64_t nb = P.nb;
@@ -167,7 +176,7 @@ void dense_config(Plan& P, int side) {
 
 int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_kernel = 0, double eps_min = 0.0) {
   if (dtype != UOT_F32 && dtype != UOT_F64) return fail(UOT_E_INVALID, "dtype must be UOT_F32 or UOT_F64");
-  if (grid_kernel < 0 || grid_kernel > 2) return fail(UOT_E_INVALID, "grid_kernel must be 0, 1 or 2");
+  if (grid_kernel < 0 || grid_kernel > 4) return fail(UOT_E_INVALID, "grid_kernel must be 0 .. 4");
   P.gk = grid_kernel == 0 ? (dtype == UOT_F32 ? 2 : 1) : grid_kernel;
   P.dtype = dtype;
   P.esz = dtype == UOT_F32 ? 4 : 8;
@@ -193,9 +202,11 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
     }
     if (g.dim == 3 && (int64_t)nb * g.n[0] > 65535) return fail(UOT_E_UNSUPPORTED, "fields x n[0] must be <= 65535");
     P.N = P.M = sz;
-    for (int k = 0; k < g.dim; ++k)
-      P.tf_axis[k] = P.gk == 2 && dtype == UOT_F32 && g.n[k] % 16 == 0 && eps_min > 0 &&
-                     g.h[k] * g.h[k] * kLog2e / eps_min <= kTfMaxC;
+    for (int k = 0; k < g.dim; ++k) {
+      const double c = eps_min > 0 ? g.h[k] * g.h[k] * kLog2e / eps_min : INFINITY;
+      P.tf_axis[k] = P.gk >= 2 && dtype == UOT_F32 && g.n[k] % 16 == 0 && c <= kTfMaxC;
+      P.tf16_axis[k] = P.tf_axis[k] && (P.gk == 3 || P.gk == 4) && c <= kTf16MaxC;
+    }
   } else {
     return fail(UOT_E_INVALID, "unknown geometry kind");
   }
@@ -318,7 +329,7 @@ void contig_pass(const Plan& P, int axis, const T* w, int64_t A, T* const* tabs,
                  const EpiArgs<T>& ep, hipStream_t s) {
   if constexpr (std::is_same<T, float>::value) {
     if (use_tf(P, axis)) {
-      timed(0, [&] { launch_grid_tf(w, A, (int)P.n[axis], 1, false, P.h[axis], side, c, ep, s); });
+      timed(0, [&] { launch_grid_tf(w, A, (int)P.n[axis], 1, false, P.tf16_axis[axis], P.h[axis], side, c, ep, s); });
       return;
     }
   }
@@ -330,7 +341,7 @@ void strided_pass(const Plan& P, int axis, const T* w, int64_t A, int64_t B, T* 
                   const EpiArgs<T>& ep, hipStream_t s) {
   if constexpr (std::is_same<T, float>::value) {
     if (use_tf(P, axis)) {
-      timed(1, [&] { launch_grid_tf(w, A, (int)P.n[axis], B, true, P.h[axis], side, c, ep, s); });
+      timed(1, [&] { launch_grid_tf(w, A, (int)P.n[axis], B, true, P.tf16_axis[axis], P.h[axis], side, c, ep, s); });
       return;
     }
   }
@@ -450,9 +461,12 @@ inline int even_chunk(int check_every) {
 }
 
 // drive iterations until the device sets stop; `iteration(par)` enqueues one
-// iteration of parity par
-template <typename F>
-int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot_result* res) {
+// iteration of parity par.  With a second phase (`iteration2`, non-null
+// `final_tol`), a stop with status 0 ends phase one (whose control block
+// tolerance was looser): the solve resumes at `final_tol` with iteration2.
+template <typename F, typename F2 = std::remove_reference_t<F>>
+int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot_result* res,
+             F2* iteration2 = nullptr, const double* final_tol = nullptr) {
   hipStream_t s = ctx->work;
   const int chunk = even_chunk(pr->check_every);
   hipGraphExec_t exec = nullptr;
@@ -464,20 +478,33 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
   struct Reset {
     ~Reset() { g_timer = nullptr; }
   } reset_timer;
-  if (pr->use_graph && !timing) {
+  auto capture = [&](auto& it) -> int {
+    if (!pr->use_graph || timing) return UOT_OK;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < chunk; ++k) iteration(k & 1);
+    for (int k = 0; k < chunk; ++k) it(k & 1);
     HIP_TRY(hipStreamEndCapture(s, &graph));
     HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  }
+    return UOT_OK;
+  };
+  auto release = [&] {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  };
+  int rc = capture(iteration);
+  if (rc) return rc;
+  bool second = false;
   auto t0 = std::chrono::steady_clock::now();
   int64_t launched = 0;
-  int rc = UOT_OK;
   while (true) {
     if (exec) {
       if (hipGraphLaunch(exec, s) != hipSuccess) { rc = fail(UOT_E_HIP, "hipGraphLaunch failed"); break; }
     } else {
-      for (int k = 0; k < chunk; ++k) iteration(k & 1);
+      for (int k = 0; k < chunk; ++k) {
+        if (second) (*iteration2)(k & 1);
+        else iteration(k & 1);
+      }
     }
     launched += chunk;
     if (hipMemcpyAsync(ctx->pinned, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -486,8 +513,17 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
       break;
     }
     if (timing) timer.collect();
-    if (ctx->pinned->stop) break;
-    if (launched > pr->max_iter + chunk) { rc = fail(UOT_E_HIP, "control block did not stop"); break; }
+    if (ctx->pinned->stop) {
+      if (iteration2 && !second && ctx->pinned->status == 0) {
+        second = true;
+        release();
+        launch_ctrl_resume(dctrl, *final_tol, s);
+        if ((rc = capture(*iteration2))) break;
+        continue;
+      }
+      break;
+    }
+    if (launched > pr->max_iter + 2 * chunk) { rc = fail(UOT_E_HIP, "control block did not stop"); break; }
   }
   if (timing) {
     for (int k = 0; k < 4; ++k) {
@@ -518,7 +554,12 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   hipStream_t s = ctx->work;
   if ((rc = begin(ctx))) return rc;
   Bufs<T> B = carve<T>(P, ws);
-  Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, pr->tol, pr->max_iter);
+  // mixed precision: FP16 passes down to kMixedSwitchTol, then FP32 passes
+  const bool mixed = P.gk == 4 && has_tf16(P) && pr->tol < kMixedSwitchTol;
+  Plan P2 = P;
+  for (int k = 0; k < 3; ++k) P2.tf16_axis[k] = false;
+  const double tol1 = mixed ? kMixedSwitchTol : pr->tol;
+  Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, tol1, pr->max_iter);
   launch_ctrl_init(B.ctrl, init, s);
   launch_log<T>(static_cast<const T*>(pb->p), B.logp, nb * P.N, 1, s);
   launch_log<T>(static_cast<const T*>(pb->q), B.logq, nb * P.M, 1, s);
@@ -540,12 +581,17 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
     host.nparts = P.nparts_x;
     host.hist = pr->res_hist;
   }
-  auto iteration = [&](int par) {
-    half_step<T>(P, *pb, 0 | par << 1, B, u, nullptr, true, s);
-    if (!hosted) timed(2, [&] { launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s, nfields, par); });
-    half_step<T>(P, *pb, 1 | par << 1, B, v, nullptr, false, s, hosted ? &host : nullptr);
+  auto iteration_with = [&](const Plan& PP) {
+    return [&, pp = &PP](int par) {
+      half_step<T>(*pp, *pb, 0 | par << 1, B, u, nullptr, true, s);
+      if (!hosted) timed(2, [&] { launch_control(B.ctrl, B.parts, pp->nparts_x, pr->res_hist, s, nfields, par); });
+      half_step<T>(*pp, *pb, 1 | par << 1, B, v, nullptr, false, s, hosted ? &host : nullptr);
+    };
   };
-  rc = run_loop(ctx, B.ctrl, pr, iteration, res);
+  auto iteration = iteration_with(P);
+  auto iteration2 = iteration_with(P2);
+  const double final_tol = pr->tol;
+  rc = run_loop(ctx, B.ctrl, pr, iteration, res, mixed ? &iteration2 : nullptr, &final_tol);
   if (rc) return rc;
   if ((rc = finish(ctx))) return rc;
   if (res->status == -3) return fail(UOT_E_NONFINITE, "non-finite residual");
@@ -702,7 +748,11 @@ int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u,
   if ((rc = begin(ctx))) return rc;
   Bufs<T> B = carve<T>(P, ws);
   const int64_t size = P.N, nb = pb->n;
-  Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, pr->tol, pr->max_iter);
+  const bool mixed = P.gk == 4 && has_tf16(P) && pr->tol < kMixedSwitchTol;
+  Plan P2 = P;
+  for (int k = 0; k < 3; ++k) P2.tf16_axis[k] = false;
+  Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, mixed ? kMixedSwitchTol : pr->tol,
+                        pr->max_iter);
   launch_ctrl_init(B.ctrl, init, s);
   launch_log<T>(static_cast<const T*>(pb->p), B.logp, nb * size, 1, s);
   launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, size, 0, s);
@@ -718,18 +768,23 @@ int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u,
     asum += pb->alpha[k];
   }
   const DivDev F2 = to_dev(pb->F2);
-  auto iteration = [&](int par) {
-    EpiArgs<T> ep = prox_epi<T>(u, B.wu, B.logp, B.logdx, nullptr, B.parts, size, pb->F1);
-    grid_chain<T>(P, B.wv, B.gtab, 0 | par << 1, B.ctrl, ep, B.t1, B.t2, s);
-    launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s, 0, par);
-    EpiArgs<T> raw{};
-    raw.mode = EPI_RAW;
-    raw.out = B.t3;
-    grid_chain<T>(P, B.wu, B.gtab, 1 | par << 1, B.ctrl, raw, B.t1, B.t2, s);
-    launch_bary_combine<T>(B.t3, pb->n, size, la, std::log(asum), F2, B.logdy, v, B.wv, logh, B.ctrl, 1 | par << 1,
-                           s);
+  auto iteration_with = [&](const Plan& PP) {
+    return [&, pp = &PP](int par) {
+      EpiArgs<T> ep = prox_epi<T>(u, B.wu, B.logp, B.logdx, nullptr, B.parts, size, pb->F1);
+      grid_chain<T>(*pp, B.wv, B.gtab, 0 | par << 1, B.ctrl, ep, B.t1, B.t2, s);
+      launch_control(B.ctrl, B.parts, pp->nparts_x, pr->res_hist, s, 0, par);
+      EpiArgs<T> raw{};
+      raw.mode = EPI_RAW;
+      raw.out = B.t3;
+      grid_chain<T>(*pp, B.wu, B.gtab, 1 | par << 1, B.ctrl, raw, B.t1, B.t2, s);
+      launch_bary_combine<T>(B.t3, pb->n, size, la, std::log(asum), F2, B.logdy, v, B.wv, logh, B.ctrl,
+                             1 | par << 1, s);
+    };
   };
-  rc = run_loop(ctx, B.ctrl, pr, iteration, res);
+  auto iteration = iteration_with(P);
+  auto iteration2 = iteration_with(P2);
+  const double final_tol = pr->tol;
+  rc = run_loop(ctx, B.ctrl, pr, iteration, res, mixed ? &iteration2 : nullptr, &final_tol);
   if (rc) return rc;
   if ((rc = finish(ctx))) return rc;
   if (res->status == -3) return fail(UOT_E_NONFINITE, "non-finite residual");

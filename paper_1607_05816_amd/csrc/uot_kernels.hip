@@ -565,6 +565,17 @@ __global__ void k_res_reduce(const ResPart* __restrict__ part, int nparts, doubl
   out[0] = num / den;
 }
 
+// continue a stopped solve with a new tolerance (the second phase of a
+// mixed-precision grid solve): clear the stop and skip flags, keep the
+// iteration count, residual history and eps slots
+__global__ void k_ctrl_resume(Ctrl* __restrict__ c, double tol) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  c->stop = 0;
+  c->status = 1;
+  c->skip[0] = c->skip[1] = 0;
+  c->tol = tol;
+}
+
 __global__ void k_ctrl_init(Ctrl* __restrict__ c, Ctrl init) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = init;
 }
@@ -858,6 +869,10 @@ void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipS
 
 void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_res_reduce, dim3(1), dim3(64), 0, s, part, nparts, out);
+}
+
+void launch_ctrl_resume(Ctrl* c, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctrl_resume, dim3(1), dim3(64), 0, s, c, tol);
 }
 
 void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s) {
@@ -1175,6 +1190,10 @@ template void launch_batch_lse<double>(int, int, int, const BItem*, int, int*, c
 // The J tiles of an output are combined by an online log-sum-exp.  Exact up
 // to FP32 rounding; exp2 count per output: 16/16 (E) + 2 per J tile instead of
 // 16 per J tile.  Requires n % 16 == 0.
+// HALF: Khat and E in FP16, one v_mfma_f32_16x16x16f16 per J tile (FP32
+// accumulation); lane (li, q) then holds taps 4 q .. 4 q + 3 of a tile.  The
+// inputs carry FP16 rounding (2^-11 relative), so results are good to ~1e-3;
+// Khat stays finite in FP16 while 2 c 7.5^2 <= 15.
 //   STRIDED = false: in[a][j], lines a (16 per group);  out[a][i]
 //   STRIDED = true : in[a][j][b], lines (a, b), 16 consecutive b per group
 // grid = (n/16 output tiles, line groups (y, z)), 4 waves split the J tiles.
@@ -1182,8 +1201,9 @@ template void launch_batch_lse<double>(int, int, int, const BItem*, int, int*, c
 namespace uot {
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
 
-template <bool STRIDED, int TPC, bool MULTI>
+template <bool STRIDED, int TPC, bool MULTI, bool HALF>
 __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in, int n, int64_t A, int64_t B,
                                                      int opb, double h, int side, const Ctrl* __restrict__ c,
                                                      EpiArgs<float> ep) {
@@ -1214,13 +1234,14 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
   // (4 TPC loads issued together).  The first chunk and the operands of the
   // first epilogue this wave finishes (outputs i = I0 + 4 q + wv of line li)
   // are loaded before the control block is read, so the latencies overlap.
-  // Tap (jt, s) of the lane's line is cell jt * 16 + 4 s + q; tiles past the
-  // end are read at the last tile (in bounds) and replaced by -inf.  Lanes of
+  // Tap (jt, s) of the lane's line is cell jt * 16 + f(q, s), f = 4 s + q
+  // (FP32 operand layout) or 4 q + s (FP16); tiles past the end are read at
+  // the last tile (in bounds) and replaced by -inf.  Lanes of
   // a line past the end read line 0 unconditionally: lines never mix (MFMA
   // columns and the max exchanges stay within a line) and their outputs are
   // dropped, while a masked load would serialise the loads.
-  const float* __restrict__ pl = in + base + (int64_t)q * tstride;
-  const int64_t st4 = 4 * tstride;
+  auto tapf = [&](int s) -> int { return HALF ? 4 * q + s : 4 * s + q; };
+  const float* __restrict__ pl = in + base;
   auto load_chunk = [&](float (&w)[TPC][4], int jc) {
 #pragma unroll
     for (int t = 0; t < TPC; ++t) {
@@ -1228,7 +1249,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
       const int jtc = jt < nt ? jt : nt - 1;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const float x = pl[(int64_t)(jtc * 4 + s) * st4];
+        const float x = pl[(int64_t)(jtc * 16 + tapf(s)) * tstride];
         w[t][s] = jt < nt ? x : -__builtin_inff();
       }
     }
@@ -1263,12 +1284,14 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
     return;
   }
   const float cc = float(h * h * kLog2e / eps_of(c, side));
-  // Khat as MFMA A operands: k-step s -> Khat[i = li][k = 4 s + q]
+  // Khat as MFMA A operands: entry s of the lane is Khat[i = li][k = f(q, s)]
   float kh[4];
+  f16x4_t kh16;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    const float e = float(li) - 7.5f, f = float(4 * s + q) - 7.5f;
+    const float e = float(li) - 7.5f, f = float(tapf(s)) - 7.5f;
     kh[s] = __builtin_amdgcn_exp2f(2.f * cc * e * f);
+    kh16[s] = (_Float16)kh[s];
   }
   // opb > 1 only when one chunk holds all of a wave's tap tiles (the host
   // picks opb so), so the taps stay in registers across the output tiles
@@ -1300,7 +1323,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
         mloc[t] = -__builtin_inff();
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          const float f = float(4 * s + q) - 7.5f;
+          const float f = float(tapf(s)) - 7.5f;
           beta[t][s] = wv4[t][s] - cc * (f * (f - 2.f * D[t]));
           mloc[t] = fmaxf(mloc[t], beta[t][s]);
         }
@@ -1317,10 +1340,21 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
 #pragma unroll
         for (int s = 0; s < 4; ++s) E[t][s] = __builtin_amdgcn_exp2f(beta[t][s] - msh);
       }
+      if (HALF) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+        for (int t = 0; t < TPC; ++t) {
+          f16x4_t e16;
 #pragma unroll
-        for (int t = 0; t < TPC; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(kh[s], E[t][s], acc[t], 0, 0, 0);
+          for (int s = 0; s < 4; ++s) e16[s] = (_Float16)E[t][s];
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16f16(kh16, e16, acc[t], 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int t = 0; t < TPC; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(kh[s], E[t][s], acc[t], 0, 0, 0);
+      }
       // acc[t][r] = sum_f Khat[e_i][f] E_f for output i = 4 q + r of line li;
       // one rescale of the running sum per chunk
 #pragma unroll
@@ -1390,27 +1424,38 @@ int grid_tf_parts(int n, int64_t A, int64_t B, bool strided) {
   return (int)((n / 16) / tf_opb(n, g) * g);
 }
 
-void launch_grid_tf(const float* in, int64_t A, int n, int64_t B, bool strided, double h, int side, const Ctrl* c,
-                    const EpiArgs<float>& ep, hipStream_t s) {
+template <bool ST, int TP, bool HF>
+static void launch_tf_t(unsigned blocks, int opb, const float* in, int64_t A, int n, int64_t B, double h, int side,
+                        const Ctrl* c, const EpiArgs<float>& ep, hipStream_t s) {
+  if (opb > 1)
+    hipLaunchKernelGGL((k_grid_tf<ST, TP, true, HF>), dim3(blocks), dim3(kBlock), 0, s, in, n, A, B, opb, h, side, c,
+                       ep);
+  else
+    hipLaunchKernelGGL((k_grid_tf<ST, TP, false, HF>), dim3(blocks), dim3(kBlock), 0, s, in, n, A, B, 1, h, side, c,
+                       ep);
+}
+
+template <bool ST, bool HF>
+static void launch_tf_tpc(int tpc, unsigned blocks, int opb, const float* in, int64_t A, int n, int64_t B, double h,
+                          int side, const Ctrl* c, const EpiArgs<float>& ep, hipStream_t s) {
+  if (tpc == 4) launch_tf_t<ST, 4, HF>(blocks, opb, in, A, n, B, h, side, c, ep, s);
+  else if (tpc == 2) launch_tf_t<ST, 2, HF>(blocks, opb, in, A, n, B, h, side, c, ep, s);
+  else launch_tf_t<ST, 1, HF>(blocks, opb, in, A, n, B, h, side, c, ep, s);
+}
+
+void launch_grid_tf(const float* in, int64_t A, int n, int64_t B, bool strided, bool half, double h, int side,
+                    const Ctrl* c, const EpiArgs<float>& ep, hipStream_t s) {
   const int64_t g = tf_groups(A, B, strided);
   const int opb = tf_opb(n, g);
   const unsigned blocks = (unsigned)((n / 16) / opb * g);
   const int tpc = tf_tpc(n);
-#define UOT_TF(ST, TP)                                                                                         \
-  do {                                                                                                         \
-    if (opb > 1)                                                                                               \
-      hipLaunchKernelGGL((k_grid_tf<ST, TP, true>), dim3(blocks), dim3(kBlock), 0, s, in, n, A, B, opb, h, side, \
-                         c, ep);                                                                               \
-    else                                                                                                       \
-      hipLaunchKernelGGL((k_grid_tf<ST, TP, false>), dim3(blocks), dim3(kBlock), 0, s, in, n, A, B, 1, h, side, \
-                         c, ep);                                                                               \
-  } while (0)
   if (strided) {
-    if (tpc == 4) UOT_TF(true, 4); else if (tpc == 2) UOT_TF(true, 2); else UOT_TF(true, 1);
+    if (half) launch_tf_tpc<true, true>(tpc, blocks, opb, in, A, n, B, h, side, c, ep, s);
+    else launch_tf_tpc<true, false>(tpc, blocks, opb, in, A, n, B, h, side, c, ep, s);
   } else {
-    if (tpc == 4) UOT_TF(false, 4); else if (tpc == 2) UOT_TF(false, 2); else UOT_TF(false, 1);
+    if (half) launch_tf_tpc<false, true>(tpc, blocks, opb, in, A, n, B, h, side, c, ep, s);
+    else launch_tf_tpc<false, false>(tpc, blocks, opb, in, A, n, B, h, side, c, ep, s);
   }
-#undef UOT_TF
 }
 
 }  // namespace uot

@@ -60,6 +60,7 @@ void launch_dense_epi(const T* pm, const T* ps, int nsplit, int64_t Nr, int side
 void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s, int nfields, int par);
 void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t s);
 void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s);
+void launch_ctrl_resume(Ctrl* c, double tol, hipStream_t s);
 constexpr int kMaxBary = 64;
 struct BaryW {
   double v[kMaxBary];   // log alpha_k
@@ -78,8 +79,8 @@ void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w
 
 void launch_probe(int which, float* out, int blocks, int iters, hipStream_t s);
 int grid_tf_parts(int n, int64_t A, int64_t B, bool strided);
-void launch_grid_tf(const float* in, int64_t A, int n, int64_t B, bool strided, double h, int side, const Ctrl* c,
-                    const EpiArgs<float>& ep, hipStream_t s);
+void launch_grid_tf(const float* in, int64_t A, int n, int64_t B, bool strided, bool half, double h, int side,
+                    const Ctrl* c, const EpiArgs<float>& ep, hipStream_t s);
 template <typename T>
 void launch_batch_lse(int dim, int R, int blocks, const BItem* items, int n_items, int* cursor, const int64_t* offR,
                       const int64_t* offC, const T* xr, int64_t totR, const T* yc, int64_t totC, const T* w,

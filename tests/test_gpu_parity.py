@@ -399,3 +399,103 @@ def test_grid_mfma_solve_256_matches_direct_and_oracle_residual():
     _, _, r = O.half_step_x(G, np.log(p), np.log(d), np.log(d), O.KL(0.1), 1e-3,
                             u2.cpu().numpy().astype(np.float64), v2.cpu().numpy().astype(np.float64))
     assert r < 5e-6, r
+
+
+# ---------------------------------------------------------------------------
+# tile-factored MFMA grid passes with FP16 operands (grid_kernel 3): FP16
+# rounding of Khat and of the column factors (2^-11 relative) bounds them at
+# 1e-3 relative on potentials, the tolerance of the half-precision paths
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(64,), (48, 32), (48, 29), (16, 32, 16)])
+def test_grid_mfma16_passes_fixed_iterations(shape):
+    rng = np.random.default_rng(191 + shape[0])
+    h, p, q, d = grid_case(rng, shape, torch.float32)
+    eps = 0.01
+    G = O.GridGeom(shape, h)
+    for F in (U.KL(0.5), U.TV(0.1)):
+        say("case grid mfma16", shape, F)
+        prob = U.grid_problem(shape, h, T(p, torch.float32), T(q, torch.float32), T(d, torch.float32),
+                              T(d, torch.float32), F, F)
+        u, v, info = U.solve(prob, eps, tol=0.0, max_iter=20, grid_kernel=U.GRID_MFMA16)
+        ref = O.solve(G, np.log(p), np.log(q), np.log(d), np.log(d), oracle_div(F), oracle_div(F), eps, tol=0.0,
+                      max_iter=20)
+        eu = pot_rel_err(u.cpu(), ref["u"], eps)
+        ev = pot_rel_err(v.cpu(), ref["v"], eps)
+        assert eu < 1e-3 and ev < 1e-3, (F, eu, ev)
+        # where an axis takes the FP16 pass, the error shows it (above the FP32
+        # paths' level, far below the tolerance)
+        if any(n % 16 == 0 and (1.0 / n) ** 2 * math.log2(math.e) / eps <= 0.125 for n in shape):
+            assert max(eu, ev) > 1e-7
+
+
+def test_grid_mfma16_solve_256_and_barycentre():
+    """The 256 x 256 workload (KL 0.1, eps 1e-1 -> 1e-3) and a 128 x 128
+    barycentre of 8 images with FP16 operands.  Rounding the operands to FP16
+    every iteration leaves a residual floor far above the FP32 paths' (the
+    map moves by single FP16 roundings between iterations), so these solves
+    run to residual 1e-4, and agree with the FP32 MFMA solves (residual 1e-6)
+    to 1e-3."""
+    pr = synth.blobs2d(0, n=256)
+    npd = np.float32
+    p, q = rounded(pr.p, npd), rounded(pr.q, npd)
+    d = rounded(np.full(pr.size, pr.h[0] * pr.h[1]), npd)
+    F = U.KL(0.1)
+    say("case grid mfma16 256")
+    prob = U.grid_problem(pr.shape, pr.h, T(p, torch.float32), T(q, torch.float32), T(d, torch.float32),
+                          T(d, torch.float32), F, F)
+    u1, v1, i1 = U.solve(prob, 1e-3, eps0=1e-1, tol=1e-6, max_iter=5000, grid_kernel=U.GRID_MFMA)
+    u2, v2, i2 = U.solve(prob, 1e-3, eps0=1e-1, tol=1e-4, max_iter=5000, grid_kernel=U.GRID_MFMA16, record=True)
+    hist = i2["res_hist"].numpy()
+    say("fp16 residual after %d iterations: %.2e (min of the last 200: %.2e)" % (i2["iters"], i2["residual"],
+                                                                                 hist[-200:].min()))
+    assert i1["converged"] and i2["converged"]
+    assert pot_rel_err(u2.cpu(), u1.cpu().numpy().astype(np.float64), 1e-3) < 1e-3
+    assert pot_rel_err(v2.cpu(), v1.cpu().numpy().astype(np.float64), 1e-3) < 1e-3
+    say("case barycentre mfma16 128")
+    bp = synth.bary_blobs(0, n_marg=8, n=128)
+    pb = T(bp.p, torch.float32)
+    hb = (1.0 / 128, 1.0 / 128)
+    db = torch.full((128 * 128,), hb[0] * hb[1], dtype=torch.float32, device=DEV)
+    Fb = U.KL(0.5)
+    _, vb1, lh1, ib1 = U.barycenter((128, 128), hb, pb, bp.alpha, db, db, Fb, Fb, 2e-3, eps0=1e-1, tol=1e-6,
+                                    max_iter=6000, grid_kernel=U.GRID_MFMA)
+    _, vb2, lh2, ib2 = U.barycenter((128, 128), hb, pb, bp.alpha, db, db, Fb, Fb, 2e-3, eps0=1e-1, tol=1e-4,
+                                    max_iter=6000, grid_kernel=U.GRID_MFMA16)
+    assert ib1["converged"] and ib2["converged"]
+    assert pot_rel_err(lh2.cpu(), lh1.cpu().numpy().astype(np.float64), 1.0) < 1e-3
+
+
+def test_grid_mixed_precision_reaches_fp32_accuracy():
+    """grid_kernel 4: FP16 passes down to residual 1e-4, FP32 passes after.
+    The solve reaches residual 1e-6 and lands on the FP32 fixed point (1e-5,
+    the FP32 tolerance), on the 256 x 256 workload and a 128 x 128
+    barycentre of 8 images; the residual history continues across the
+    switch."""
+    pr = synth.blobs2d(0, n=256)
+    npd = np.float32
+    p, q = rounded(pr.p, npd), rounded(pr.q, npd)
+    d = rounded(np.full(pr.size, pr.h[0] * pr.h[1]), npd)
+    for F in (U.KL(0.1), U.TV(0.05)):
+        say("case grid mixed 256", F)
+        prob = U.grid_problem(pr.shape, pr.h, T(p, torch.float32), T(q, torch.float32), T(d, torch.float32),
+                              T(d, torch.float32), F, F)
+        u1, v1, i1 = U.solve(prob, 1e-3, eps0=1e-1, tol=1e-6, max_iter=5000, grid_kernel=U.GRID_MFMA)
+        u2, v2, i2 = U.solve(prob, 1e-3, eps0=1e-1, tol=1e-6, max_iter=5000, grid_kernel=U.GRID_MIXED, record=True)
+        assert i1["converged"] and i2["converged"] and i2["residual"] <= 1e-6
+        assert abs(i1["iters"] - i2["iters"]) <= 50, (i1["iters"], i2["iters"])
+        hist = i2["res_hist"].numpy()
+        assert np.all(np.isfinite(hist)) and hist[-1] <= 1e-6
+        assert pot_rel_err(u2.cpu(), u1.cpu().numpy().astype(np.float64), 1e-3) < 1e-5
+        assert pot_rel_err(v2.cpu(), v1.cpu().numpy().astype(np.float64), 1e-3) < 1e-5
+    say("case barycentre mixed 128")
+    bp = synth.bary_blobs(0, n_marg=8, n=128)
+    pb = T(bp.p, torch.float32)
+    hb = (1.0 / 128, 1.0 / 128)
+    db = torch.full((128 * 128,), hb[0] * hb[1], dtype=torch.float32, device=DEV)
+    Fb = U.KL(0.5)
+    _, _, lh1, ib1 = U.barycenter((128, 128), hb, pb, bp.alpha, db, db, Fb, Fb, 2e-3, eps0=1e-1, tol=1e-6,
+                                  max_iter=6000, grid_kernel=U.GRID_MFMA)
+    _, _, lh2, ib2 = U.barycenter((128, 128), hb, pb, bp.alpha, db, db, Fb, Fb, 2e-3, eps0=1e-1, tol=1e-6,
+                                  max_iter=6000, grid_kernel=U.GRID_MIXED)
+    assert ib1["converged"] and ib2["converged"]
+    assert pot_rel_err(lh2.cpu(), lh1.cpu().numpy().astype(np.float64), 1.0) < 1e-5
