@@ -234,13 +234,27 @@ __global__ void k_relu_grad(const float* __restrict__ dh, const float* __restric
   if (i < n) g[i] = z[i] > 0.f ? f2bf(dh[i]) : (u16)0;
 }
 
-// out[n] = sum_b g[b][n]  (bias gradients)
-__global__ void k_colsum(const u16* __restrict__ g, int rows, int cols, float* __restrict__ out) {
-  const int n = blockIdx.x * kB + threadIdx.x;
-  if (n >= cols) return;
-  float s = 0.f;
-  for (int b = 0; b < rows; ++b) s += bf2f(g[(int64_t)b * cols + n]);
-  out[n] = s;
+// out[n] = sum_b g[b][n]  (bias gradients): 64 columns per block (one row
+// segment of 128 bytes per load), the 4 waves take every 4th row with 4
+// independent partial sums each, merged in LDS (fixed order)
+__global__ __launch_bounds__(kB) void k_colsum(const u16* __restrict__ g, int rows, int cols, float* __restrict__ out) {
+  __shared__ float part[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + lane;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  if (n < cols) {
+    int b = wv;
+    for (; b + 12 < rows; b += 16) {
+      s0 += bf2f(g[(int64_t)b * cols + n]);
+      s1 += bf2f(g[(int64_t)(b + 4) * cols + n]);
+      s2 += bf2f(g[(int64_t)(b + 8) * cols + n]);
+      s3 += bf2f(g[(int64_t)(b + 12) * cols + n]);
+    }
+    for (; b < rows; b += 4) s0 += bf2f(g[(int64_t)b * cols + n]);
+  }
+  part[wv][lane] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (wv == 0 && n < cols) out[n] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 // Adam with bias correction; refreshes the BF16 copy of the weights
@@ -425,7 +439,7 @@ void backward(const uot_net* n, const Layout& L, const Act& a, const float* t, i
     // dW_l [out x in] = g^T [out x batch] * inp [batch x in]
     gemm<true, false>(g, L.out[l], inp, L.in[l], L.out[l], L.in[l], (int)batch, a.grad + L.w[l], L.in[l], nullptr,
                       nullptr, 0, s);
-    hipLaunchKernelGGL(k_colsum, dim3(cdiv(L.out[l], kB)), dim3(kB), 0, s, g, (int)batch, L.out[l], a.grad + L.b[l]);
+    hipLaunchKernelGGL(k_colsum, dim3(cdiv(L.out[l], 64)), dim3(kB), 0, s, g, (int)batch, L.out[l], a.grad + L.b[l]);
     if (l == 0) break;
     // dh_{l-1} [batch x in] = g [batch x out] * W_l [out x in], then the ReLU mask
     gemm<false, false>(g, L.out[l], n->wbf16 + L.w[l], L.in[l], (int)batch, L.in[l], L.out[l], a.dh, L.in[l], nullptr,
