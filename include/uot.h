@@ -219,12 +219,14 @@ int uot_objective(uot_ctx *ctx, const uot_problem *pb, double eps,
  * Barycentres (Sec. 5.2): n densities p_k on one regular grid (X = Y), with
  * alpha_k-weighted entropy and K_k = exp(-alpha_k c/(alpha_k eps)) = K, F1 =
  * sum_k F1(. | p_k) (any uot_div kind, applied per coupling) and F2(s) =
- * min_h lambda sum_k alpha_k D(s_k | h) with D = KL (Table estimatebary (ii))
- * or equality (row (i)).  Per iteration: for every k an X half-step
- * u_k = eps log proxdiv_F1(e^{S_k}); then T_k = log K^T(a_k dx),
- *   log h = ((eps+lam)/eps) [LSE_k(log alpha_k + eps/(eps+lam) T_k) - log sum alpha]
- * and v_k = eps log proxdiv_{lam KL(.|h)}(e^{T_k}).  The residual is the
- * relative L1 X-marginal violation summed over all k.
+ * min_h lambda sum_k alpha_k D(s_k | h) with D any uot_div kind (Table
+ * estimatebary: (i) equality, (ii) KL, (iii) TV, (iv) RG with finite beta).
+ * Per iteration: for every k an X half-step u_k = eps log proxdiv_F1(e^{S_k});
+ * then T_k = log K^T(a_k dx) and, per cell, h from the table's row, e.g. (ii)
+ *   log h = ((eps+lam)/eps) [LSE_k(log alpha_k + eps/(eps+lam) T_k) - log sum alpha];
+ * (iii)/(iv) take the smallest root of their piecewise-linear equation in
+ * log h (exact, by its breakpoints); then v_k = eps log proxdiv_{D(.|h)}(e^{T_k}).
+ * The residual is the relative L1 X-marginal violation summed over all k.
  * ------------------------------------------------------------------------- */
 typedef struct uot_bary_problem {
   int32_t dtype;         /* UOT_F32 or UOT_F64                               */
@@ -235,7 +237,7 @@ typedef struct uot_bary_problem {
   const void *dx;        /* device, size                                     */
   const void *dy;        /* device, size                                     */
   uot_div F1;            /* per-coupling first-marginal penalty              */
-  uot_div F2;            /* kind UOT_DIV_KL (lambda) or UOT_DIV_EQ           */
+  uot_div F2;            /* any kind; RG needs a finite beta                 */
 } uot_bary_problem;
 
 int uot_bary_workspace_size(const uot_bary_problem *pb, size_t *bytes);

@@ -492,19 +492,87 @@ def scaling_algo2(C, p, q, dx, dy, F1, F2, eps, n_iter, tau, eps0=None, n_stages
 # barycentres: Sec. 5.2 (weighted KL, K_k = exp(-c_k/(alpha_k eps)) with
 # c_k = alpha_k c so that every K_k = K; Table estimatebary rows (i) and (ii))
 # ---------------------------------------------------------------------------
+def pwl_root_inf(f, breaks: np.ndarray) -> np.ndarray:
+    """Per column j: inf{x : f(x)[j] >= 0} for a function f, non-decreasing in
+    x and linear between consecutive finite entries of breaks[:, j], that is
+    negative left of the first breakpoint and >= 0 at the last one.  f takes
+    an array of shape (m, J) of evaluation points and returns the same shape.
+    The root is the linear interpolation on the segment where f first
+    becomes >= 0 (the first breakpoint itself when f is already >= 0 there)."""
+    b = np.sort(np.where(np.isfinite(breaks), breaks, np.inf), axis=0)
+    fb = f(b)
+    ok = np.isfinite(b) & (fb >= 0)
+    i = np.argmax(ok, axis=0)                     # first breakpoint with f >= 0
+    J = np.arange(b.shape[1])
+    x1, f1 = b[i, J], fb[i, J]
+    im = np.maximum(i - 1, 0)
+    x0, f0 = b[im, J], fb[im, J]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        x = x0 + (0.0 - f0) * (x1 - x0) / (f1 - f0)
+    return np.where(i == 0, x1, x)
+
+
 def bary_logh(T: np.ndarray, alpha: np.ndarray, eps: float, F2: Div) -> np.ndarray:
     """log h from Table estimatebary, given T_k = log s_k (shape (n, J)).
 
-      (i)  =     : h = (prod_k s_k^alpha_k)^(1/sum alpha)
-      (ii) lam KL: h = (sum_k alpha_k s_k^(eps/(eps+lam)) / sum alpha)^((eps+lam)/eps)
+      (i)   =       : h = (prod_k s_k^alpha_k)^(1/sum alpha)
+      (ii)  lam KL  : h = (sum_k alpha_k s_k^(eps/(eps+lam)) / sum alpha)^((eps+lam)/eps)
+      (iii) lam TV  : with I+ = {k : s_k > 0}, h = 0 if the weight off I+ is at
+                      least the weight on I+; otherwise log h is the root of
+                      sum_{k not in I+} alpha_k + sum_{k in I+} alpha_k
+                        clamp((eps/lam) log(h/s_k), -1, 1)
+      (iv)  RG[b1,b2]: h = 0 if some s_k = 0; otherwise log h is the root of
+                      sum_k alpha_k [b2 min(log(b2 h/s_k), 0) + b1 max(log(b1 h/s_k), 0)]
+    (iii) and (iv) are non-decreasing and piecewise linear in log h with
+    breakpoints log s_k -+ lam/eps (TV) and log s_k - log b_i (RG); where
+    their zero set is an interval the smallest root is taken (for (iv) that
+    interval is [max log s_k - log b2, min log s_k - log b1] when every s_k
+    fits one band, and its left end is returned exactly).
     """
     alpha = np.asarray(alpha, np.float64)
+    T = np.asarray(T, np.float64)
     A = alpha.sum()
     if F2.kind == "eq":
         return np.sum(alpha[:, None] * T, axis=0) / A
     if F2.kind == "kl":
         g = eps / (eps + F2.lam)
         return (lse(np.log(alpha)[:, None] + g * T, axis=0) - np.log(A)) / g
+    al = alpha[:, None, None]
+    if F2.kind == "tv":
+        pos = np.isfinite(T)
+        a0 = np.sum(np.where(pos, 0.0, alpha[:, None]), axis=0)
+        a1 = np.sum(np.where(pos, alpha[:, None], 0.0), axis=0)
+        d = F2.lam / eps
+        Tp = np.where(pos, T, np.nan)
+
+        def f(x):   # x: (m, J)
+            t = np.clip((x[None, :, :] - Tp[:, None, :]) / d, -1.0, 1.0)
+            return a0[None, :] + np.nansum(np.where(pos[:, None, :], al * t, 0.0), axis=0)
+        br = np.concatenate([np.where(pos, T - d, np.inf), np.where(pos, T + d, np.inf)], axis=0)
+        x = pwl_root_inf(f, br)
+        return np.where(a0 >= a1, -np.inf, x)
+    if F2.kind == "rg":
+        b1, b2 = F2.alpha, F2.beta
+        if not np.isfinite(b2):
+            raise ValueError("a range barycentre needs a finite upper bound")
+        zero = np.any(np.isneginf(T), axis=0)
+        Tz = np.where(np.isneginf(T), 0.0, T)
+        lb1 = np.log(b1) if b1 > 0 else -np.inf
+
+        def f(x):
+            y = x[None, :, :] - Tz[:, None, :]
+            lo = b1 * np.maximum(y + lb1, 0.0) if b1 > 0 else 0.0
+            return np.sum(al * (b2 * np.minimum(y + np.log(b2), 0.0) + lo), axis=0)
+        br = [Tz - np.log(b2)]
+        if b1 > 0:
+            br.append(Tz - lb1)
+        x = pwl_root_inf(f, np.concatenate(br, axis=0))
+        # every input within one band [b1 h, b2 h]: the function is zero on
+        # [max log s_k - log b2, min log s_k - log b1]; its left end is taken
+        # exactly (evaluated at a breakpoint, the sum may round to -0)
+        left = np.max(Tz, axis=0) - np.log(b2)
+        band = left <= (np.min(Tz, axis=0) - lb1 if b1 > 0 else np.inf)
+        return np.where(zero, -np.inf, np.where(band, left, x))
     raise ValueError("barycentre F2 kind %s is not supported" % F2.kind)
 
 

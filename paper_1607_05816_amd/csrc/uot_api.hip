@@ -1389,8 +1389,8 @@ int uot_barycenter(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* p
   int rc = check_div(pb->F1, "F1");
   if (rc) return rc;
   if ((rc = check_div(pb->F2, "F2"))) return rc;
-  if (pb->F2.kind != UOT_DIV_KL && pb->F2.kind != UOT_DIV_EQ)
-    return fail(UOT_E_UNSUPPORTED, "barycentre F2 must be KL or equality");
+  if (pb->F2.kind == UOT_DIV_RG && !std::isfinite(pb->F2.beta))
+    return fail(UOT_E_UNSUPPORTED, "a range barycentre needs a finite upper bound beta");
   if ((rc = validate_params(pr))) return rc;
   if (pb->dtype == UOT_F32)
     return bary_t<float>(ctx, pb, pr, static_cast<float*>(u), static_cast<float*>(v), static_cast<float*>(logh),

@@ -585,6 +585,98 @@ __global__ void k_ctrl_init(Ctrl* __restrict__ c, Ctrl init) {
 // Y Gibbs product: T2 (n x size, log2 units) ->  log h (natural), and
 //   v_k = eps log proxdiv_{F2(.|h)}(e^{T_k}),  w_k = (v_k/eps_next + log dy) log2(e)
 // ---------------------------------------------------------------------------
+// Table estimatebary (iii) lam TV / (iv) RG[b1, b2]: log h is a root of
+//   TV: A0 + sum_{k: s_k>0} alpha_k clamp((x - log s_k) eps/lam, -1, 1)   (A0: weight of s_k = 0)
+//   RG: sum_k alpha_k [b2 min(x + log b2 - log s_k, 0) + b1 max(x + log b1 - log s_k, 0)]
+// in x = log h; both are non-decreasing and linear between their breakpoints
+// (log s_k -+ lam/eps, log s_k - log b_i).  The smallest root is taken: the
+// first breakpoint where the function is >= 0, linear interpolation from the
+// breakpoint before it.  h = 0 (TV: A0 >= weight of the others; RG: some
+// s_k = 0).  t2: log2 s_k at stride `stride`.
+template <typename T>
+__device__ T bary_f(const T* __restrict__ t2, int64_t stride, int n, const double* lav, bool tv, T a0, T d, T lb1,
+                    T lb2, T b1, T b2, bool has_lo, T x) {
+  T acc = tv ? a0 : T(0);
+  for (int k = 0; k < n; ++k) {
+    const T t = t2[k * stride] * T(kLn2);
+    if (t == Num<T>::ninf()) continue;
+    const T al = T(::exp(lav[k]));
+    if (tv) {
+      const T y = (x - t) / d;
+      acc += al * (y < T(-1) ? T(-1) : (y > T(1) ? T(1) : y));
+    } else {
+      const T up = x + lb2 - t, dn = x + lb1 - t;
+      T term = b2 * (up < T(0) ? up : T(0));
+      if (has_lo) term += b1 * (dn > T(0) ? dn : T(0));
+      acc += al * term;
+    }
+  }
+  return acc;
+}
+
+// breakpoint w (0, 1) of input k, natural log t: TV t -+ d, RG t - log b2 / t - log b1
+template <typename T>
+__device__ __forceinline__ T bary_break(bool tv, T t, int w, T d, T lb1, T lb2) {
+  return tv ? (w == 0 ? t - d : t + d) : (w == 0 ? t - lb2 : t - lb1);
+}
+
+template <typename T>
+__device__ T bary_root(const T* __restrict__ t2, int64_t stride, int n, const BaryW& la, const DivDev& F, T eps) {
+  const bool tv = F.kind == 2;
+  T a0 = T(0), a1 = T(0);
+  for (int k = 0; k < n; ++k) {
+    const T al = T(::exp(la.v[k]));
+    if (t2[k * stride] == Num<T>::ninf()) a0 += al;
+    else a1 += al;
+  }
+  if (tv ? (a0 >= a1) : (a0 > T(0))) return Num<T>::ninf();
+  if (!tv) {
+    // every input within one band [b1 h, b2 h]: the function is zero on
+    // [max log s_k - log b2, min log s_k - log b1]; return its left end
+    // exactly (at a breakpoint the sum may round to -0)
+    T tmax = Num<T>::ninf(), tmin = Num<T>::pinf();
+    for (int k = 0; k < n; ++k) {
+      const T t = t2[k * stride] * T(kLn2);
+      tmax = t > tmax ? t : tmax;
+      tmin = t < tmin ? t : tmin;
+    }
+    const T left = tmax - T(F.log_beta);
+    if (!F.has_lo || left <= tmin - T(F.log_alpha)) return left;
+  }
+  const T d = tv ? T(F.lam) / eps : T(0);
+  const T lb1 = F.has_lo ? T(F.log_alpha) : T(0), lb2 = T(F.log_beta);
+  const T b1 = F.has_lo ? T(::exp(F.log_alpha)) : T(0), b2 = T(::exp(F.log_beta));
+  const bool lo = F.has_lo != 0;
+  const int per = tv ? 2 : (lo ? 2 : 1);
+  // first breakpoint (in value) where the function is >= 0 ...
+  T bhi = Num<T>::pinf(), fhi = T(0);
+  for (int q = 0; q < n * per; ++q) {
+    const int k = q / per, w = q % per;
+    const T t = t2[k * stride] * T(kLn2);
+    if (t == Num<T>::ninf()) continue;
+    const T b = bary_break<T>(tv, t, w, d, lb1, lb2);
+    if (b < bhi) {
+      const T fb = bary_f<T>(t2, stride, n, la.v, tv, a0, d, lb1, lb2, b1, b2, lo, b);
+      if (fb >= T(0)) {
+        bhi = b;
+        fhi = fb;
+      }
+    }
+  }
+  // ... and the breakpoint before it; the function is linear in between
+  T blo = Num<T>::ninf();
+  for (int q = 0; q < n * per; ++q) {
+    const int k = q / per, w = q % per;
+    const T t = t2[k * stride] * T(kLn2);
+    if (t == Num<T>::ninf()) continue;
+    const T b = bary_break<T>(tv, t, w, d, lb1, lb2);
+    if (b < bhi && b > blo) blo = b;
+  }
+  if (blo == Num<T>::ninf()) return bhi;
+  const T flo = bary_f<T>(t2, stride, n, la.v, tv, a0, d, lb1, lb2, b1, b2, lo, blo);
+  return blo + (T(0) - flo) * (bhi - blo) / (fhi - flo);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bary_combine(const T* __restrict__ T2, int nm, int64_t size,
                                                           BaryW log_alpha, double log_sum_alpha,
@@ -597,7 +689,9 @@ __global__ __launch_bounds__(kBlock) void k_bary_combine(const T* __restrict__ T
   const T eps = T(eps_of(c, side));
   const T eps_w = T(eps_next_of(c, side));
   T logh;
-  if (F2.kind == 0) {
+  if (F2.kind == 2 || F2.kind == 3) {
+    logh = bary_root<T>(T2 + j, size, nm, log_alpha, F2, eps);
+  } else if (F2.kind == 0) {
     double acc = 0.0, asum = 0.0;
     for (int k = 0; k < nm; ++k) {
       const double al = ::exp(log_alpha.v[k]);

@@ -297,7 +297,7 @@ def test_objective_parity(geom, F):
 # barycentres
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype,tolr", [(torch.float64, 1e-11), (torch.float32, 1e-5)])
-@pytest.mark.parametrize("F2", [U.KL(0.5), U.EQ()])
+@pytest.mark.parametrize("F2", [U.KL(0.5), U.EQ(), U.TV(0.1), U.RG(0.7, 1.3)])
 def test_barycenter_fixed_iterations(dtype, tolr, F2):
     npd = np.float32 if dtype == torch.float32 else np.float64
     rng = np.random.default_rng(55)

@@ -590,3 +590,97 @@ def test_barycenter_fixed_point_optimality():
     # sum_k alpha_k (1 - s~_k / h) = 0 (KL case of the appendix derivation)
     h = np.exp(out["logh"])
     np.testing.assert_allclose(np.sum(alpha[:, None] * (1 - pi2 / h[None, :]), axis=0), 0.0, atol=1e-9)
+
+
+def _bary_tv_rg_objective(h, s, alpha, eps, F):
+    """Value of the pointwise barycentre problem (Sec. 5.2, the minimisation
+    over (s~, h) that defines Table estimatebary) at a given h, with the
+    inner minimisation over s~ done in closed form:
+      TV : eps KLbar(s~|s) + lam |s~ - h| is minimised by s~ = h clamped to
+           [s e^{-lam/eps}, s e^{lam/eps}] (first-order condition);
+      RG : the indicator of s~ in [b1 h, b2 h] leaves s~ = s clamped there."""
+    if F.kind == "tv":
+        lo, hi = s * np.exp(-F.lam / eps), s * np.exp(F.lam / eps)
+        st = np.clip(h, lo, hi)
+        return float(np.sum(alpha * (eps * _kl_bar_vec(st, s) + F.lam * np.abs(st - h))))
+    st = np.clip(s, F.alpha * h, F.beta * h)
+    return float(np.sum(alpha * eps * _kl_bar_vec(st, s)))
+
+
+def _kl_bar_vec(a, b):
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(a > 0, a * np.log(a / b) - a + b, b)
+
+
+@pytest.mark.parametrize("F", [O.TV(0.3), O.TV(0.02), O.RG(0.7, 1.3), O.RG(0.0, 1.5)])
+def test_bary_h_tv_rg_minimises_the_pointwise_problem(F):
+    """Table estimatebary (iii)/(iv): the oracle's h attains the minimum of the
+    defining pointwise problem, found independently by a bounded scalar search
+    on log h, and no smaller h does as well (the smallest minimiser is taken
+    where the minimiser is an interval)."""
+    rng = np.random.default_rng(53)
+    for _ in range(12):
+        n = 5
+        s = np.exp(rng.uniform(-2, 2, n))
+        alpha = rng.uniform(0.2, 1.0, n)
+        eps = rng.uniform(0.01, 0.3)
+        logh = O.bary_logh(np.log(s)[:, None], alpha, eps, F)[0]
+        assert np.isfinite(logh)
+        val = _bary_tv_rg_objective(np.exp(logh), s, alpha, eps, F)
+        obj = lambda lh: _bary_tv_rg_objective(np.exp(lh), s, alpha, eps, F)
+        lo, hi = np.log(s).min() - 8, np.log(s).max() + 8
+        grid = np.linspace(lo, hi, 4001)
+        k = int(np.argmin([obj(x) for x in grid]))
+        r = optimize.minimize_scalar(obj, bounds=(grid[max(k - 2, 0)], grid[min(k + 2, 4000)]), method="bounded",
+                                     options=dict(xatol=1e-12))
+        best = min(r.fun, min(obj(x) for x in grid))
+        assert val <= best + 1e-10 * max(1.0, abs(best))
+        assert obj(logh - 1e-4) > val + 1e-14
+
+
+def test_bary_h_tv_rg_special_cases():
+    T = np.log(np.full((4, 1), 0.7))
+    alpha = np.array([0.1, 0.2, 0.3, 0.4])
+    # identical inputs: TV gives h = s; RG gives the smallest minimiser s / b2
+    assert O.bary_logh(T, alpha, 0.05, O.TV(0.3))[0] == pytest.approx(np.log(0.7), abs=1e-12)
+    assert O.bary_logh(T, alpha, 0.05, O.RG(0.6, 1.25))[0] == pytest.approx(np.log(0.7 / 1.25), abs=1e-12)
+    # TV with zeros: h = 0 iff the weight of the zero inputs is at least that of the others
+    s = np.array([[0.0], [0.0], [2.0], [1.0]])
+    with np.errstate(divide="ignore"):
+        L = np.log(s)
+    assert np.isneginf(O.bary_logh(L, np.array([0.3, 0.3, 0.2, 0.2]), 0.05, O.TV(0.3))[0])
+    assert np.isfinite(O.bary_logh(L, np.array([0.1, 0.1, 0.4, 0.4]), 0.05, O.TV(0.3))[0])
+    # RG: any zero input forces h = 0
+    assert np.isneginf(O.bary_logh(L, alpha, 0.05, O.RG(0.6, 1.25))[0])
+    # lam -> 0 for TV: the clamp saturates at once, h is the weighted median of s
+    s = np.array([[1.0], [2.0], [5.0]])
+    lh = O.bary_logh(np.log(s), np.array([0.2, 0.5, 0.3]), 1.0, O.TV(1e-9))[0]
+    assert lh == pytest.approx(np.log(2.0), abs=1e-6)
+
+
+@pytest.mark.parametrize("F2", [O.TV(0.05), O.RG(0.8, 1.25)])
+def test_barycenter_tv_rg_fixed_point(F2):
+    """Barycentres with TV / range penalties on the second marginals (Table
+    estimatebary (iii)/(iv)): the iteration converges, and at its fixed point
+    each coupling's Y marginal s~_k lies in the band the divergence allows
+    around h (TV: h e^{-lam/eps} .. h e^{lam/eps}; RG: b1 h .. b2 h), while h
+    solves the pointwise problem for the Y marginals (its objective, checked
+    as in the estimate pins, is not improved by a smaller h)."""
+    G = O.GridGeom((10, 9), (1 / 10, 1 / 9))
+    rng = np.random.default_rng(59)
+    ldx = np.full(G.N, np.log(1 / G.N))
+    eps = 0.02
+    p = rng.uniform(0.3, 1.5, (3, G.N))
+    alpha = np.array([0.2, 0.5, 0.3])
+    out = O.barycenter(G, np.log(p), alpha, ldx, ldx, O.KL(0.5), F2, eps, tol=1e-12, max_iter=20000)
+    assert out["res"][-1] <= 1e-12
+    T = np.stack([G.lse_y(out["u"][k] / eps + ldx, eps) for k in range(3)])
+    st = np.exp(out["v"] / eps + T)
+    h = np.exp(out["logh"])
+    if F2.kind == "tv":
+        lo, hi = h * np.exp(-F2.lam / eps), h * np.exp(F2.lam / eps)
+    else:
+        lo, hi = F2.alpha * h, F2.beta * h
+    assert np.all(st >= lo * (1 - 1e-9)) and np.all(st <= hi * (1 + 1e-9))
+    # h is the estimate of its own inputs: recomputing it from T changes nothing
+    np.testing.assert_allclose(O.bary_logh(T, alpha, eps, F2), out["logh"], rtol=0, atol=1e-12)
