@@ -199,6 +199,21 @@ int uot_fields_workspace_size(const uot_problem *pb, int nb, size_t *bytes);
 int uot_solve_fields(uot_ctx *ctx, const uot_problem *pb, int nb, const uot_params *pr,
                      void *u, void *v, void *ws, size_t ws_bytes, uot_result *res);
 
+/* Scaling iteration with a function of the total mass (Sec. 4.4, Algorithm
+ * 4): min F1(P^X R) + F2(P^Y R) + F3(total mass of R) + eps KL(R|K), with F3
+ * = D(. | mass) a divergence on the one-point space (reference measure 1):
+ * EQ fixes the mass (with F1 = F2 = RG[0, 1] this is partial transport), KL
+ * / TV penalise it, RG bounds it to [alpha mass, beta mass].  In log form,
+ * with zeta = log z: both half-steps apply their proxdiv to S + zeta; after
+ * the Y half-step, log m = LSE_j(T_j + v_j/eps + log dy_j) (the plan's mass
+ * without z) and zeta = log proxdiv_F3(m) (Table proximalexplicit, p = mass).
+ * The plan is R_ij = exp(zeta + (u_i + v_j - C_ij)/eps); *log_z (HOST)
+ * receives zeta.  Workspace: uot_workspace_size.  grid_kernel 4 is not
+ * supported here. */
+int uot_solve_mass(uot_ctx *ctx, const uot_problem *pb, const uot_div *F3, double mass,
+                   const uot_params *pr, void *u, void *v, double *log_z, void *ws,
+                   size_t ws_bytes, uot_result *res);
+
 /* One half-step of (S) from a given state, for checking a single step.
  * side 0 (X half-step): S = log K(e^{v/eps} dy) with v = pot_in (M);
  *   pot_io (N) holds u_old on entry and u' = eps log proxdiv_F1(e^S) on exit;

@@ -327,8 +327,10 @@ def solve(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, eps: float,
         S = log K(b (.) dy),  u <- eps log proxdiv_F1(e^S)
     followed by a Y half-step
         T = log K^T(a (.) dx), v <- eps log proxdiv_F2(e^T),
-    all in the log domain.  Stops after the first iteration whose residual
-    r <= tol at the final eps (annealing iterations count), or at max_iter.
+    all in the log domain.  Stops after the first iteration (from the second
+    on: the first residual compares with the arbitrary initial u) whose
+    residual r <= tol at the final eps (annealing iterations count), or at
+    max_iter.
 
     Returns dict(u, v, iters, res (list), S_last).
     """
@@ -359,7 +361,9 @@ def solve(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, eps: float,
             res.append(r)
             if record:
                 hist.append((u.copy(), v.copy()))
-            if final and r <= tol:
+            # the first residual compares with the arbitrary initial u and
+            # certifies nothing: it is recorded, not used to stop
+            if final and r <= tol and it >= 2:
                 return dict(u=u, v=v, iters=it, res=res, converged=True, hist=hist)
     raise AssertionError("unreachable")
 
@@ -492,6 +496,75 @@ def scaling_algo2(C, p, q, dx, dy, F1, F2, eps, n_iter, tau, eps0=None, n_stages
 # barycentres: Sec. 5.2 (weighted KL, K_k = exp(-c_k/(alpha_k eps)) with
 # c_k = alpha_k c so that every K_k = K; Table estimatebary rows (i) and (ii))
 # ---------------------------------------------------------------------------
+# ---------------------------------------------------------------------------
+# Algorithm 4 (Sec. 4.4, generalization to a function of the total mass):
+# min F1(P^X R) + F2(P^Y R) + F3(m R) + eps KL(R|K), with m R the total mass
+# of the plan and F3 a divergence on the one-point space (reference measure
+# 1, "density" m0): F3(sigma) = D(sigma | m0).  Its proxdiv is the row of
+# Table proximalexplicit with p = m0.
+# ---------------------------------------------------------------------------
+def mass_scaling_algo(C, p, q, dx, dy, F1, F2, F3, m0, eps, n_iter):
+    """Algorithm 4 in the scaling domain: b = 1, z = 1; repeat
+        a = proxdiv_F1(z K(b dy)),  b = proxdiv_F2(z K^T(a dx)),
+        z = proxdiv_F3(<a dx, K(b dy)>);
+    the plan is z a_i K_ij b_j.  Returns (eps log a, eps log b, log z) after
+    each iteration."""
+    K = np.exp(-np.asarray(C, np.float64) / eps)
+    b = np.ones(len(q))
+    z = 1.0
+    out = []
+    m0a = np.array([float(m0)])
+    for _ in range(n_iter):
+        a = proxdiv_scaling(F1, p, z * (K @ (b * dy)), 0.0, eps)
+        b = proxdiv_scaling(F2, q, z * (K.T @ (a * dx)), 0.0, eps)
+        z = float(proxdiv_scaling(F3, m0a, np.array([(a * dx) @ (K @ (b * dy))]), 0.0, eps)[0])
+        with np.errstate(divide="ignore"):
+            out.append((eps * np.log(a), eps * np.log(b), np.log(z)))
+    return out
+
+
+def solve_mass(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, F3: Div, log_m0: float, eps: float,
+               tol: float = 1e-6, max_iter: int = 10000, eps0: Optional[float] = None, n_stages: int = 10,
+               iters_per_stage: int = 100):
+    """Algorithm 4 in the log domain (zeta = log z, potentials u, v): per
+    iteration
+        S = log K(b dy);  u <- eps log proxdiv_F1(e^{S + zeta})   (residual r as in solve, on S + zeta)
+        T = log K^T(a dx); v <- eps log proxdiv_F2(e^{T + zeta})
+        log m = LSE_j(T_j + v_j/eps + log dy_j);  zeta <- log proxdiv_F3(e^{log m})  (p = m0)
+    with the eps schedule of solve.  Returns dict(u, v, zeta, iters, res)."""
+    N = len(logp)
+    M = len(logq)
+    v = np.zeros(M)
+    u = np.zeros(N)
+    zeta = 0.0
+    stages = eps_schedule(eps, eps0, n_stages, iters_per_stage)
+    res = []
+    it = 0
+    plan = [(e, n, False) for e, n in stages] + [(eps, None, True)]
+    lm0 = np.array([float(log_m0)])
+    for e, n_it, final in plan:
+        k = 0
+        while True:
+            if it >= max_iter:
+                return dict(u=u, v=v, zeta=zeta, iters=it, res=res, converged=False)
+            if n_it is not None and k >= n_it:
+                break
+            S = geom.lse_x(v / e + logdy, e) + zeta
+            u_new = e * proxdiv_log(F1, logp, S, 0.0, e)
+            r = marginal_residual(S, u, u_new, logdx, e)
+            u = u_new
+            T = geom.lse_y(u / e + logdx, e)
+            v = e * proxdiv_log(F2, logq, T + zeta, 0.0, e)
+            logm = float(lse(T + v / e + logdy, axis=0))
+            zeta = float(proxdiv_log(F3, lm0, np.array([logm]), 0.0, e)[0])
+            it += 1
+            k += 1
+            res.append(r)
+            if final and r <= tol and it >= 2:
+                return dict(u=u, v=v, zeta=zeta, iters=it, res=res, converged=True)
+    raise AssertionError("unreachable")
+
+
 def pwl_root_inf(f, breaks: np.ndarray) -> np.ndarray:
     """Per column j: inf{x : f(x)[j] >= 0} for a function f, non-decreasing in
     x and linear between consecutive finite entries of breaks[:, j], that is
@@ -608,7 +681,7 @@ def barycenter(geom, logp, alpha, logdx, logdy, F1: Div, F2: Div, eps: float,
         logh = bary_logh(T, alpha, eps, F2)
         v = eps * proxdiv_log(F2, np.broadcast_to(logh, T.shape), T, 0.0, eps)
         res.append(r)
-        if r <= tol:
+        if r <= tol and it >= 2:
             return dict(u=u, v=v, logh=logh, iters=it, res=res, converged=True)
     return dict(u=u, v=v, logh=logh, iters=max_iter, res=res, converged=False)
 

@@ -123,12 +123,13 @@ struct Plan {
   int splits[2] = {1, 1};
   int64_t cps[2] = {0, 0};
   int nparts_x = 0;      // residual partials written by the X epilogue
+  int nparts_y = 0;      // blocks of the Y epilogue (mass partials of Algorithm 4)
   int gk = 1;            // grid passes: 1 direct log-sum-exp, 2 tile-factored MFMA where allowed
   bool tf_axis[3] = {false, false, false};   // tile-factored pass used on this axis
   bool tf16_axis[3] = {false, false, false}; // ... with FP16 operands
   // workspace offsets
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
-      o_gcost, o_obj, o_scal, total;
+      o_gcost, o_obj, o_scal, o_mass, total;
   int64_t obj_doubles = 0;
 };
 
@@ -244,6 +245,8 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
                              ? std::max(grid_final_parts_for(P, false), P.n[0] % 16 == 0 ? grid_final_parts_for(P, true) : 0)
                              : P.nparts_x;
   P.o_parts = take(sizeof(ResPart) * std::max(parts_room, 1));
+  P.nparts_y = P.geom == UOT_GEOM_GRID ? P.nparts_x : (int)((P.M + 255) / 256);
+  P.o_mass = take(2 * e * std::max(std::max(parts_room, P.nparts_y), 1));
   for (int k = 0; k < 3; ++k) P.o_gtab[k] = take(P.geom == UOT_GEOM_GRID && k < P.dim ? e * (2 * P.n[k] - 1) * nst : 0);
   int64_t gmax = 1;
   for (int k = 0; k < P.dim; ++k) gmax = std::max(gmax, 2 * P.n[k] - 1);
@@ -298,6 +301,7 @@ template <typename T> struct Bufs {
   T* gcost;
   double* obj;
   double* scal;
+  T *mass_m, *mass_s;     // mass partials of Algorithm 4 (Y epilogue)
 };
 
 template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
@@ -319,6 +323,8 @@ template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
   b.gcost = at<T>(ws, P.o_gcost);
   b.obj = at<double>(ws, P.o_obj);
   b.scal = at<double>(ws, P.o_scal);
+  b.mass_m = at<T>(ws, P.o_mass);
+  b.mass_s = b.mass_m + std::max(std::max(P.nparts_x, P.nparts_y), 1);
   return b;
 }
 
@@ -423,13 +429,17 @@ EpiArgs<T> prox_epi(T* pot, T* wnext, const T* logp, const T* logd, T* lse_out, 
 // v / wv); bit 1 of side is the parity of the iteration
 template <typename T>
 void half_step(const Plan& P, const uot_problem& pb, int side, Bufs<T>& B, T* pot, T* lse_out, bool with_res,
-               hipStream_t s, const CtlHost* host = nullptr) {
+               hipStream_t s, const CtlHost* host = nullptr, bool mass = false) {
   if ((side & 1) == 0) {
     EpiArgs<T> ep = prox_epi<T>(pot, B.wu, B.logp, B.logdx, lse_out, with_res ? B.parts : nullptr, P.N, pb.F1);
     if (P.geom == UOT_GEOM_GRID) grid_chain<T>(P, B.wv, B.gtab, side, B.ctrl, ep, B.t1, B.t2, s);
     else dense_half<T>(P, pb.geom, side, B.wv, B, B.ctrl, ep, s);
   } else {
     EpiArgs<T> ep = prox_epi<T>(pot, B.wv, B.logq, B.logdy, lse_out, nullptr, P.M, pb.F2);
+    if (mass) {
+      ep.mass_m = B.mass_m;
+      ep.mass_s = B.mass_s;
+    }
     if (P.geom == UOT_GEOM_GRID) grid_chain<T>(P, B.wu, B.gtab, side, B.ctrl, ep, B.t1, B.t2, s, host);
     else dense_half<T>(P, pb.geom, side, B.wu, B, B.ctrl, ep, s);
   }
@@ -542,9 +552,15 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
   return UOT_OK;
 }
 
+// total-mass penalty of Algorithm 4: F3 on the one-point space, log m0
+struct MassOpt {
+  DivDev F3;
+  double log_m0;
+};
+
 template <typename T>
 int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* v, char* ws, size_t wsb,
-            uot_result* res, int nb = 1) {
+            uot_result* res, int nb = 1, const MassOpt* mass = nullptr, double* log_z = nullptr) {
   Plan P;
   const bool anneal = pr->eps0 > pr->eps && pr->eps_stages > 0 && pr->iters_per_stage > 0;
   int rc = make_plan(P, pb->dtype, pb->geom, nb, anneal ? pr->eps_stages + 1 : 1, pr->grid_kernel, pr->eps);
@@ -585,7 +601,9 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
     return [&, pp = &PP](int par) {
       half_step<T>(*pp, *pb, 0 | par << 1, B, u, nullptr, true, s);
       if (!hosted) timed(2, [&] { launch_control(B.ctrl, B.parts, pp->nparts_x, pr->res_hist, s, nfields, par); });
-      half_step<T>(*pp, *pb, 1 | par << 1, B, v, nullptr, false, s, hosted ? &host : nullptr);
+      half_step<T>(*pp, *pb, 1 | par << 1, B, v, nullptr, false, s, hosted ? &host : nullptr, mass != nullptr);
+      if (mass)
+        timed(2, [&] { launch_mass_update<T>(B.ctrl, B.mass_m, B.mass_s, pp->nparts_y, mass->F3, mass->log_m0, par, s); });
     };
   };
   auto iteration = iteration_with(P);
@@ -593,6 +611,7 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   const double final_tol = pr->tol;
   rc = run_loop(ctx, B.ctrl, pr, iteration, res, mixed ? &iteration2 : nullptr, &final_tol);
   if (rc) return rc;
+  if (log_z) *log_z = ctx->pinned->zeta;
   if ((rc = finish(ctx))) return rc;
   if (res->status == -3) return fail(UOT_E_NONFINITE, "non-finite residual");
   return res->status == 0 ? UOT_OK : UOT_NOT_CONVERGED;
@@ -1270,6 +1289,23 @@ int uot_solve_fields(uot_ctx* ctx, const uot_problem* pb, int nb, const uot_para
                           res, nb);
   return solve_t<double>(ctx, pb, pr, static_cast<double*>(u), static_cast<double*>(v), static_cast<char*>(ws), wsb,
                          res, nb);
+}
+
+int uot_solve_mass(uot_ctx* ctx, const uot_problem* pb, const uot_div* F3, double mass, const uot_params* pr,
+                   void* u, void* v, double* log_z, void* ws, size_t wsb, uot_result* res) {
+  if (!ctx || !res || !F3 || !log_z) return fail(UOT_E_INVALID, "ctx, F3, log_z and res are required");
+  int rc = validate_problem(pb);
+  if (rc) return rc;
+  if ((rc = check_div(*F3, "F3"))) return rc;
+  if (!(mass > 0 && std::isfinite(mass))) return fail(UOT_E_INVALID, "mass must be finite and > 0");
+  if ((rc = validate_params(pr))) return rc;
+  if (pr->grid_kernel == 4) return fail(UOT_E_UNSUPPORTED, "the mass penalty runs with grid_kernel 0 .. 3");
+  MassOpt m{to_dev(*F3), std::log(mass)};
+  if (pb->dtype == UOT_F32)
+    return solve_t<float>(ctx, pb, pr, static_cast<float*>(u), static_cast<float*>(v), static_cast<char*>(ws), wsb,
+                          res, 1, &m, log_z);
+  return solve_t<double>(ctx, pb, pr, static_cast<double*>(u), static_cast<double*>(v), static_cast<char*>(ws), wsb,
+                         res, 1, &m, log_z);
 }
 
 int uot_half_step(uot_ctx* ctx, const uot_problem* pb, double eps, int side, const void* pot_in, void* pot_io,

@@ -101,6 +101,7 @@ struct Ctrl {
   double res;        // residual of the last iteration
   double eps[2];     // eps of the iteration of parity p
   double eps_tab[kMaxStages + 1];
+  double zeta;       // log z of a total-mass penalty (Algorithm 4); 0 otherwise
   // ragged batches only
   int32_t active[2];  // problems still active after the last iteration (slot = iteration parity)
   uint64_t t0_clock;  // device wall clock at the start of the solve

@@ -105,7 +105,8 @@ __device__ __forceinline__ void epi_apply(int64_t e, T S2, const EpiIn<T>& x, co
   }
   const T eps = T(eps_of(c, side));
   const T eps_w = T(eps_next_of(c, side));   // w feeds the next half-step
-  const T S = S2 * T(kLn2);
+  const T Sraw = S2 * T(kLn2);
+  const T S = Sraw + T(c->zeta);              // z K(.): log z of a total-mass penalty, else 0
   const T ld = x.ld;
   const T uo = x.uo;
   const T un = proxdiv_pot<T>(ep.F, x.lp, S, eps);
@@ -119,6 +120,9 @@ __device__ __forceinline__ void epi_apply(int64_t e, T S2, const EpiIn<T>& x, co
       const T d = Num<T>::expm1((uo - un) / eps);
       ra.add((S + un / eps + ld) * T(kLog2e), T(1), Num<T>::fmax(d, -d));
     }
+  } else if (ep.mass_m) {
+    // mass of the plan without z: the (m, den) pair of ra carries it
+    ra.add((Sraw + un / eps + ld) * T(kLog2e), T(1), T(0));
   }
 }
 
@@ -128,9 +132,36 @@ __device__ __forceinline__ void epi_elem(int64_t e, T S2, const Ctrl* __restrict
   epi_apply<T>(e, S2, epi_load<T>(e, ep), c, side, ep, ra);
 }
 
+// log2-sum-exp (m, s) over a block in T precision (every thread calls it);
+// thread 0 writes the result
+template <typename T>
+__device__ __forceinline__ void block_lse_reduce(T m, T s, T* out_m, T* out_s) {
+  __shared__ T sm[kBlock], ss[kBlock];
+  sm[threadIdx.x] = m;
+  ss[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kBlock / 2; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      Lse2<T> a;
+      a.m = sm[threadIdx.x];
+      a.s = ss[threadIdx.x];
+      a.merge(sm[threadIdx.x + off], ss[threadIdx.x + off]);
+      sm[threadIdx.x] = a.m;
+      ss[threadIdx.x] = a.s;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *out_m = sm[0];
+    *out_s = ss[0];
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void epi_finish(const EpiArgs<T>& ep, const ResAcc<T>& ra, int part_index) {
-  if (ep.mode != EPI_RAW && ep.part) block_res_reduce<T>(ra.m, ra.den, ra.num, ep.part + part_index);
+  if (ep.mode == EPI_RAW) return;
+  if (ep.part) block_res_reduce<T>(ra.m, ra.den, ra.num, ep.part + part_index);
+  else if (ep.mass_m) block_lse_reduce<T>(ra.m, ra.den, ep.mass_m + part_index, ep.mass_s + part_index);
 }
 
 // ---------------------------------------------------------------------------
@@ -179,7 +210,8 @@ __device__ void control_finish(Ctrl* c, const CtrlSnap& s, double r, double* __r
   if (r != r) {
     stop = true;
     status = -3;
-  } else if (final_stage && r <= s.tol) {
+  } else if (final_stage && r <= s.tol && s.l >= 1) {
+    // (the first residual compares with the initial u and is not used to stop)
     stop = true;
     status = 0;
   } else if (s.l + 1 >= s.max_iter) {
@@ -576,6 +608,27 @@ __global__ void k_ctrl_resume(Ctrl* __restrict__ c, double tol) {
   c->tol = tol;
 }
 
+// total-mass step of Algorithm 4 (one block): log m from the mass partials of
+// the Y half-step, then log z = log proxdiv_F3(m) with p = m0 on the
+// one-point space, at the eps of the iteration
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mass_update(Ctrl* __restrict__ c, const T* __restrict__ mm,
+                                                         const T* __restrict__ ms, int nparts, DivDev F3,
+                                                         double log_m0, int par) {
+  if (c->skip[par]) return;
+  Lse2<T> a;
+  a.init();
+  for (int k = threadIdx.x; k < nparts; k += kBlock) a.merge(mm[k], ms[k]);
+  __shared__ T om, os;
+  block_lse_reduce<T>(a.m, a.s, &om, &os);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double logm = (double(om) + ::log2(double(os))) * kLn2;
+    const double eps = c->eps[par];
+    c->zeta = proxdiv_pot<double>(F3, log_m0, logm, eps) / eps;
+  }
+}
+
 __global__ void k_ctrl_init(Ctrl* __restrict__ c, Ctrl init) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = init;
 }
@@ -969,6 +1022,15 @@ void launch_ctrl_resume(Ctrl* c, double tol, hipStream_t s) {
   hipLaunchKernelGGL(k_ctrl_resume, dim3(1), dim3(64), 0, s, c, tol);
 }
 
+template <typename T>
+void launch_mass_update(Ctrl* c, const T* mass_m, const T* mass_s, int nparts, const DivDev& F3, double log_m0, int par,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_mass_update<T>, dim3(1), dim3(kBlock), 0, s, c, mass_m, mass_s, nparts, F3, log_m0, par);
+}
+template void launch_mass_update<float>(Ctrl*, const float*, const float*, int, const DivDev&, double, int, hipStream_t);
+template void launch_mass_update<double>(Ctrl*, const double*, const double*, int, const DivDev&, double, int,
+                                         hipStream_t);
+
 void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s) {
   hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, c, init);
 }
@@ -1190,7 +1252,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_control(Ctrl* __restrict__ c, 
   const bool final_stage = c->iters_per_stage <= 0 || l >= (int64_t)c->n_stages * c->iters_per_stage;
   int stop = 0;
   if (r != r) { stop = 1; bc->status[b] = -3; }
-  else if (final_stage && r <= c->tol) { stop = 1; bc->status[b] = 0; }
+  else if (final_stage && r <= c->tol && l >= 1) { stop = 1; bc->status[b] = 0; }
   else if (l + 1 >= c->max_iter) { stop = 1; bc->status[b] = 1; }
   if (stop) {
     bc->stop[b] = 1;

@@ -35,6 +35,10 @@ template <typename T> struct EpiArgs {
   double* host_hist;
   int host_nparts;
   int host_pad;
+  // total-mass penalty (Y side): per-block log2-sum-exp partials (m, s) of
+  // T + v/eps + log d, the log mass of the plan without the factor z
+  T* mass_m;
+  T* mass_s;
 };
 
 template <typename T> void launch_log(const T* src, T* dst, int64_t n, int zero_is_ninf, hipStream_t s);
@@ -61,6 +65,9 @@ void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipS
 void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t s);
 void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s);
 void launch_ctrl_resume(Ctrl* c, double tol, hipStream_t s);
+template <typename T>
+void launch_mass_update(Ctrl* c, const T* mass_m, const T* mass_s, int nparts, const DivDev& F3, double log_m0, int par,
+                        hipStream_t s);
 constexpr int kMaxBary = 64;
 struct BaryW {
   double v[kMaxBary];   // log alpha_k

@@ -116,6 +116,8 @@ def lib():
         "uot_fields_workspace_size": (c_i32, [P(UotProblem), c_i32, P(ctypes.c_size_t)]),
         "uot_solve_fields": (c_i32, [c_vp, P(UotProblem), c_i32, P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t,
                                      P(UotResult)]),
+        "uot_solve_mass": (c_i32, [c_vp, P(UotProblem), P(UotDiv), c_dbl, P(UotParams), c_vp, c_vp, P(c_dbl), c_vp,
+                                   ctypes.c_size_t, P(UotResult)]),
         "uot_batch_workspace_size": (c_i32, [P(UotBatchProblem), P(ctypes.c_size_t)]),
         "uot_net_param_count": (c_i32, [P(UotNet), P(c_i64)]),
         "uot_net_workspace_size": (c_i32, [P(UotNet), c_i64, P(ctypes.c_size_t)]),
@@ -381,6 +383,30 @@ def objective(prob: Problem, eps, u, v, ctx: Optional[Context] = None, marginals
     if marginals:
         d["pi1"], d["pi2"] = pi1, pi2
     return d
+
+
+def solve_mass(prob: Problem, F3: Div, mass, eps, ctx: Optional[Context] = None, record=False, **kw):
+    """Algorithm 4: the scaling iteration with F3 on the total mass of the plan
+    (reference value `mass`).  Returns (u, v, log_z, info)."""
+    ctx = ctx or default_context()
+    dev = prob.p.device
+    u = torch.empty(prob.N, dtype=prob.dtype, device=dev)
+    v = torch.empty(prob.M, dtype=prob.dtype, device=dev)
+    ws = prob.workspace()
+    max_iter = kw.get("max_iter", 10000)
+    hist = torch.full((max_iter,), float("nan"), dtype=torch.float64, device=dev) if record else None
+    pr = params(eps, res_hist=hist, **kw)
+    res = UotResult()
+    lz = c_dbl()
+    f3 = F3.c()
+    code = lib().uot_solve_mass(ctx.handle, ctypes.byref(prob.c), ctypes.byref(f3), float(mass), ctypes.byref(pr),
+                                _ptr(u), _ptr(v), ctypes.byref(lz), _ptr(ws), ws.numel(), ctypes.byref(res))
+    _check(code, "uot_solve_mass")
+    info = dict(iters=res.iters, residual=res.residual, status=res.status, elapsed_ms=res.elapsed_ms,
+                converged=(code == UOT_OK))
+    if record:
+        info["res_hist"] = hist[:res.iters].cpu()
+    return u, v, lz.value, info
 
 
 def barycenter(shape, h, p, alpha, dx, dy, F1: Div, F2: Div, eps, ctx: Optional[Context] = None, v0=None,

@@ -499,3 +499,69 @@ def test_grid_mixed_precision_reaches_fp32_accuracy():
                                   max_iter=6000, grid_kernel=U.GRID_MIXED)
     assert ib1["converged"] and ib2["converged"]
     assert pot_rel_err(lh2.cpu(), lh1.cpu().numpy().astype(np.float64), 1.0) < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 4: a function F3 of the total mass
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,tolr", [(torch.float64, 1e-11), (torch.float32, 1e-5)])
+@pytest.mark.parametrize("F3", [U.EQ(), U.KL(0.3), U.RG(0.5, 0.8)])
+def test_mass_penalty_fixed_iterations(dtype, tolr, F3):
+    rng = np.random.default_rng(81)
+    x, y, p, q, dx, dy = points_case(rng, 300, 260, 2, dtype)
+    eps, mass = 0.02, 0.6
+    F1, F2 = U.KL(0.5), U.TV(0.2)
+    say("case mass points", dtype, F3)
+    prob = gpu_points(x, y, p, q, dx, dy, F1, F2, dtype)
+    u, v, lz, info = U.solve_mass(prob, F3, mass, eps, tol=0.0, max_iter=25)
+    g = O.PointsGeom(x, y)
+    ref = O.solve_mass(g, O.safe_log(p), O.safe_log(q), np.log(dx), np.log(dy), oracle_div(F1), oracle_div(F2),
+                       oracle_div(F3), np.log(mass), eps, tol=0.0, max_iter=25)
+    assert pot_rel_err(u.cpu(), ref["u"], eps) < tolr
+    assert pot_rel_err(v.cpu(), ref["v"], eps) < tolr
+    assert lz == pytest.approx(ref["zeta"], rel=tolr * 10, abs=tolr)
+    # the same on a grid (separable passes; FP32 uses the MFMA passes)
+    rng = np.random.default_rng(83)
+    shape = (48, 32)
+    h, pg, qg, dg = grid_case(rng, shape, dtype)
+    say("case mass grid", dtype, F3)
+    pgp = U.grid_problem(shape, h, T(pg, dtype), T(qg, dtype), T(dg, dtype), T(dg, dtype), F1, F2)
+    u, v, lz, info = U.solve_mass(pgp, F3, mass, eps, tol=0.0, max_iter=25)
+    G = O.GridGeom(shape, h)
+    ref = O.solve_mass(G, np.log(pg), np.log(qg), np.log(dg), np.log(dg), oracle_div(F1), oracle_div(F2),
+                       oracle_div(F3), np.log(mass), eps, tol=0.0, max_iter=25)
+    assert pot_rel_err(u.cpu(), ref["u"], eps) < tolr
+    assert pot_rel_err(v.cpu(), ref["v"], eps) < tolr
+    assert lz == pytest.approx(ref["zeta"], rel=tolr * 10, abs=tolr)
+
+
+def test_mass_penalty_free_mass_and_partial_transport():
+    """F3 = 0 on the nonnegative reals leaves z = 1 (the plain solve); partial
+    transport (dominations RG[0, 1], total mass fixed) converges on the GPU
+    to the oracle's solution, with the mass and the dominations held."""
+    rng = np.random.default_rng(85)
+    x, y, p, q, dx, dy = points_case(rng, 200, 180, 2, torch.float64)
+    eps = 0.02
+    F = U.KL(0.4)
+    prob = gpu_points(x, y, p, q, dx, dy, F, F, torch.float64)
+    say("case mass free")
+    u1, v1, lz, i1 = U.solve_mass(prob, U.RG(0.0, math.inf), 1.0, eps, tol=1e-10, max_iter=20000)
+    u2, v2, i2 = U.solve(prob, eps, tol=1e-10, max_iter=20000)
+    assert lz == 0.0 and i1["iters"] == i2["iters"]
+    assert torch.equal(u1, u2) and torch.equal(v1, v2)
+    say("case partial transport")
+    dom = U.RG(0.0, 1.0)
+    pd = gpu_points(x, y, p, q, dx, dy, dom, dom, torch.float64)
+    m0 = 0.5 * min(float(np.sum(p * dx)), float(np.sum(q * dy)))
+    u, v, lz, info = U.solve_mass(pd, U.EQ(), m0, eps, tol=1e-10, max_iter=50000)
+    assert info["converged"]
+    g = O.PointsGeom(x, y)
+    ref = O.solve_mass(g, np.log(p), np.log(q), np.log(dx), np.log(dy), O.RG(0.0, 1.0), O.RG(0.0, 1.0), O.EQ,
+                       np.log(m0), eps, tol=1e-10, max_iter=50000)
+    assert info["iters"] == ref["iters"]
+    assert pot_rel_err(u.cpu(), ref["u"], eps) < 1e-9
+    assert lz == pytest.approx(ref["zeta"], rel=1e-9)
+    C = O.sq_dist(x, y)
+    R = np.exp((u.cpu().numpy()[:, None] + v.cpu().numpy()[None, :] - C) / eps + lz)
+    assert np.sum(R * dx[:, None] * dy[None, :]) == pytest.approx(m0, rel=1e-8)
+    assert np.all(R @ dy <= p * (1 + 1e-8)) and np.all(R.T @ dx <= q * (1 + 1e-8))

@@ -684,3 +684,79 @@ def test_barycenter_tv_rg_fixed_point(F2):
     assert np.all(st >= lo * (1 - 1e-9)) and np.all(st <= hi * (1 + 1e-9))
     # h is the estimate of its own inputs: recomputing it from T changes nothing
     np.testing.assert_allclose(O.bary_logh(T, alpha, eps, F2), out["logh"], rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 4: a function F3 of the total mass of the plan
+# ---------------------------------------------------------------------------
+def test_mass_algo_free_mass_is_algorithm_1():
+    """F3 = 0 on the nonnegative reals (RG with bounds 0, inf): z stays 1 and
+    Algorithm 4 is Algorithm 1."""
+    rng = np.random.default_rng(61)
+    x, y, p, q, dx, dy = _rand_problem(rng, 7, 6)
+    C = O.sq_dist(x, y)
+    eps = 0.05
+    a4 = O.mass_scaling_algo(C, p, q, dx, dy, O.KL(0.4), O.TV(0.2), O.RG(0.0, np.inf), 1.0, eps, 30)
+    a1 = O.scaling_algo(C, p, q, dx, dy, O.KL(0.4), O.TV(0.2), eps, 30)
+    for (u4, v4, lz), (u1, v1) in zip(a4, a1):
+        assert lz == 0.0
+        np.testing.assert_allclose(u4, u1, rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(v4, v1, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("F3", [O.EQ, O.KL(0.3), O.TV(0.1), O.RG(0.5, 0.8)])
+def test_mass_algo_log_domain_matches_scaling(F3):
+    """The log-domain form (potentials and zeta = log z) gives the iterates of
+    the scaling form of Algorithm 4."""
+    rng = np.random.default_rng(67)
+    x, y, p, q, dx, dy = _rand_problem(rng, 8, 9)
+    C = O.sq_dist(x, y)
+    eps, m0 = 0.05, 0.6
+    sc = O.mass_scaling_algo(C, p, q, dx, dy, O.KL(0.5), O.KL(0.5), F3, m0, eps, 25)
+    g = O.DenseGeom(C)
+    lg = (np.log(p), np.log(q), np.log(dx), np.log(dy))
+    for n in (1, 7, 25):
+        s = O.solve_mass(g, *lg, O.KL(0.5), O.KL(0.5), F3, np.log(m0), eps, tol=0.0, max_iter=n)
+        u, v, lz = sc[n - 1]
+        np.testing.assert_allclose(s["u"], u, rtol=1e-11, atol=1e-13)
+        np.testing.assert_allclose(s["v"], v, rtol=1e-11, atol=1e-13)
+        assert s["zeta"] == pytest.approx(lz, rel=1e-11, abs=1e-13)
+
+
+def test_partial_transport_lp_limit():
+    """Optimal partial transport (Sec. 4.4, Algorithm 4 with F1, F2 the
+    domination constraints RG[0, 1] and F3 the equality with m0): as eps -> 0
+    the plan's cost tends to the LP optimum of min <C, R> subject to
+    R dy <= p, R^T dx <= q, total mass m0, and the plan carries mass m0 and
+    respects the dominations."""
+    rng = np.random.default_rng(71)
+    x, y, p, q, dx, dy = _rand_problem(rng, 6, 7)
+    C = O.sq_dist(x, y)
+    N, M = C.shape
+    m0 = 0.6 * min(np.sum(p * dx), np.sum(q * dy))
+    W = (dx[:, None] * dy[None, :]).reshape(-1)
+    A_ub = np.zeros((N + M, N * M))
+    for i in range(N):
+        A_ub[i, i * M:(i + 1) * M] = dy
+    for j in range(M):
+        A_ub[N + j, j::M] = dx
+    lp = optimize.linprog(C.reshape(-1) * W, A_ub=A_ub, b_ub=np.r_[p, q], A_eq=W[None, :], b_eq=[m0],
+                          bounds=(0, None), method="highs")
+    assert lp.status == 0
+    g = O.DenseGeom(C)
+    lg = (np.log(p), np.log(q), np.log(dx), np.log(dy))
+    dom = O.RG(0.0, 1.0)
+    prev = None
+    for eps in (1e-2, 3e-3, 1e-3):
+        s = O.solve_mass(g, *lg, dom, dom, O.EQ, np.log(m0), eps, tol=1e-12, max_iter=400000)
+        assert s["converged"]
+        R = np.exp((s["u"][:, None] + s["v"][None, :] - C) / eps + s["zeta"])
+        pi1, pi2 = R @ dy, R.T @ dx
+        assert np.sum(R * W.reshape(N, M)) == pytest.approx(m0, rel=1e-9)
+        assert np.all(pi1 <= p * (1 + 1e-9)) and np.all(pi2 <= q * (1 + 1e-9))
+        cost = np.sum(C * R * W.reshape(N, M))
+        assert cost >= lp.fun - 1e-9
+        assert cost - lp.fun <= 3 * eps * np.log(N * M) + 1e-9
+        if prev is not None:
+            assert cost - lp.fun <= prev + 1e-12
+        prev = cost - lp.fun
