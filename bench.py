@@ -138,12 +138,12 @@ PASS_NAMES = ["k_grid_tf<false, 4>", "k_grid_tf<true, 4>"]
 # two passes at both launch shapes, from the two counter runs of
 # `bench.py --pmc-workload`; they hold for the kernel source they were taken
 # on (sha256 of csrc/uot_kernels.hip) and are reported as null otherwise.
-TRAFFIC_SOURCE_SHA256 = "755750aadbf4bf6b13c23a5d095dcf918c27f5d9ea817ffe54f50ece2ddc56a0"
+TRAFFIC_SOURCE_SHA256 = "79df1b1c79d2ec579d569ecec08f5c9f5db15d44348fd6c05d33d5c42cc3f3a2"
 TRAFFIC_BYTES = {
-    ("k_grid_tf<false, 4>", 1): (2259102, 259672),
-    ("k_grid_tf<true, 4>", 1): (3078355, 523333),
-    ("k_grid_tf<false, 4>", 256): (67295563, 67108864),
-    ("k_grid_tf<true, 4>", 256): (406304708, 134348800),
+    ("k_grid_tf<false, 4>", 1): (2275605, 259840),
+    ("k_grid_tf<true, 4>", 1): (3091183, 523671),
+    ("k_grid_tf<false, 4>", 256): (67297964, 67108864),
+    ("k_grid_tf<true, 4>", 256): (406600962, 134348800),
 }
 
 

@@ -90,8 +90,16 @@ def test_batch_converged_each_problem_stops_on_its_own():
         ref = O.solve(O.PointsGeom(x, y), np.log(p), np.log(q), np.log(dx), np.log(dy), O.KL(1.0), O.KL(1.0), eps,
                       tol=1e-6, max_iter=4000)
         assert abs(int(its[b]) - ref["iters"]) <= max(2, ref["iters"] // 50), (b, its[b], ref["iters"])
-        assert pot_rel_err(us[b], ref["u"], eps) < 1e-5
-        assert pot_rel_err(vs[b], ref["v"], eps) < 1e-5
+        # the two sides stop on their own residual (FP32 here, FP64 in the
+        # oracle), a few iterations apart: the element-wise comparison is with
+        # the oracle run for exactly the iterations this problem took; the
+        # converged oracle solution is only a few residuals away
+        same = O.solve(O.PointsGeom(x, y), np.log(p), np.log(q), np.log(dx), np.log(dy), O.KL(1.0), O.KL(1.0),
+                       eps, tol=0.0, max_iter=int(its[b]))
+        assert pot_rel_err(us[b], same["u"], eps) < 1e-5, (b, its[b])
+        assert pot_rel_err(vs[b], same["v"], eps) < 1e-5, (b, its[b])
+        assert pot_rel_err(us[b], ref["u"], eps) < 5e-5
+        assert pot_rel_err(vs[b], ref["v"], eps) < 5e-5
     # second call with the same signature reuses the tuned choice; graph and
     # direct launches give identical potentials
     u2, v2, info2 = U.solve_batched(bp, eps, tol=1e-6, max_iter=4000, check_every=32, use_graph=False)

@@ -180,8 +180,15 @@ def test_grid_eps_scaling_to_tolerance():
                   tol=1e-6, max_iter=4000, eps0=1e-1)
     assert info["converged"] and ref["converged"]
     assert abs(info["iters"] - ref["iters"]) <= max(3, ref["iters"] // 100)
-    assert pot_rel_err(u.cpu(), ref["u"], 1e-3) < 1e-5
-    assert pot_rel_err(v.cpu(), ref["v"], 1e-3) < 1e-5
+    # each side stops on its own residual: element-wise parity is with the
+    # oracle run for the iterations the GPU took, the converged oracle is a
+    # few residuals away
+    same = O.solve(O.GridGeom(shape, h), np.log(p), np.log(q), np.log(d), np.log(d), O.KL(0.1), O.KL(0.1), 1e-3,
+                   tol=0.0, max_iter=int(info["iters"]), eps0=1e-1)
+    assert pot_rel_err(u.cpu(), same["u"], 1e-3) < 1e-5
+    assert pot_rel_err(v.cpu(), same["v"], 1e-3) < 1e-5
+    assert pot_rel_err(u.cpu(), ref["u"], 1e-3) < 5e-5
+    assert pot_rel_err(v.cpu(), ref["v"], 1e-3) < 5e-5
 
 
 def test_grid_half_step_full_size_256():
@@ -256,8 +263,11 @@ def test_dense_eps_scaling_solve_fp32():
     ref = oracle_points_run(x, y, p, q, dx, dy, F, F, 1e-2, 6000, tol=1e-6, eps0=1.0)
     assert info["converged"] and ref["converged"]
     assert abs(info["iters"] - ref["iters"]) <= max(3, ref["iters"] // 100)
-    assert pot_rel_err(u.cpu(), ref["u"], 1e-2) < 1e-5
-    assert pot_rel_err(v.cpu(), ref["v"], 1e-2) < 1e-5
+    same = oracle_points_run(x, y, p, q, dx, dy, F, F, 1e-2, int(info["iters"]), tol=0.0, eps0=1.0)
+    assert pot_rel_err(u.cpu(), same["u"], 1e-2) < 1e-5
+    assert pot_rel_err(v.cpu(), same["v"], 1e-2) < 1e-5
+    assert pot_rel_err(u.cpu(), ref["u"], 1e-2) < 5e-5
+    assert pot_rel_err(v.cpu(), ref["v"], 1e-2) < 5e-5
 
 
 # ---------------------------------------------------------------------------
