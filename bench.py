@@ -132,6 +132,49 @@ def warm_batched(U, ctx, dev, np, torch):
     return out
 
 
+def extensions(U, pr, ctx, dev, np, torch):
+    """Solves beyond the KL/TV pair, timed to tol 1e-6 (FP32, device-resident):
+    (a) barycentres of 8 blob images at 128 x 128 with TV 0.1 and RG [0.7, 1.3]
+        penalties on the barycentre side (Table estimatebary iii/iv), KL 0.5 on
+        the input side, eps 1e-1 -> 2e-3;
+    (b) Algorithm 4 on the 256 x 256 workload: optimal partial transport
+        (dominations RG[0, 1] on both marginals, total mass fixed to 0.7 of the
+        smaller marginal's mass), eps 1e-1 -> 1e-2."""
+    from paper_1607_05816_amd import synth
+    out = {}
+    bb = synth.bary_blobs(0, n_marg=8, n=128)
+    p = torch.tensor(bb.p, dtype=torch.float32, device=dev)
+    d = torch.full((128 * 128,), bb.h[0] * bb.h[1], dtype=torch.float32, device=dev)
+    for name, F2 in (("TV0.1", U.TV(0.1)), ("RG0.7-1.3", U.RG(0.7, 1.3))):
+        for rep in range(2):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            _, _, _, bi = U.barycenter(bb.shape, bb.h, p, bb.alpha, d, d, U.KL(0.5), F2, 2e-3, eps0=1e-1, tol=1e-6,
+                                       max_iter=20000, check_every=50, ctx=ctx)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - a) * 1e3
+        out["barycenter_8x128_" + name] = {"iters": int(bi["iters"]), "ms": ms, "converged": bool(bi["converged"]),
+                                           "iters_per_s": bi["iters"] / (ms * 1e-3)}
+    t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+    cw = pr.h[0] * pr.h[1]
+    dd = np.full(pr.size, cw)
+    m0 = 0.7 * min(pr.p.sum(), pr.q.sum()) * cw
+    F = U.RG(0.0, 1.0)
+    pb = U.grid_problem(pr.shape, pr.h, t(pr.p), t(pr.q), t(dd), t(dd), F, F)
+    pb.workspace()
+    for rep in range(2):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        u, v, lz, info = U.solve_mass(pb, U.EQ(), m0, 1e-2, eps0=1e-1, tol=1e-6, max_iter=20000, check_every=50,
+                                      ctx=ctx)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - a) * 1e3
+    out["partial_transport_256x256"] = {"iters": int(info["iters"]), "ms": ms, "converged": bool(info["converged"]),
+                                        "iters_per_s": info["iters"] / (ms * 1e-3), "log_z": lz,
+                                        "mass_target": float(m0)}
+    return out
+
+
 PASS_NAMES = ["k_grid_tf<false, 4>", "k_grid_tf<true, 4>"]
 
 # HBM bytes per launch (calibrated FETCH_SIZE read + WRITE_SIZE written) of the
@@ -343,6 +386,7 @@ def main():
     ap.add_argument("--no-warm-batched", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-gemm", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="only run the launches the HBM-traffic counters are read on")
     args = ap.parse_args()
@@ -424,6 +468,8 @@ def main():
         line["roofline_dense"] = dense_roofline(U, torch, np, dev, ctx)
     if not args.no_gemm:
         line["roofline_gemm"] = gemm_roofline(U, torch, np, dev, ctx)
+    if not args.no_extensions:
+        line["extensions"] = extensions(U, pr, ctx, dev, np, torch)
     if not args.no_warm_batched:
         line["warm_batched_vs_plain"] = warm_batched(U, ctx, dev, np, torch)
     if not args.no_cpu_baseline:

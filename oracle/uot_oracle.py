@@ -58,7 +58,10 @@ class Div:
     "divergencefunctions"), scaled by `lam` for KL and TV.
 
     kind: "eq" (equality constraint), "kl" (lam * KL), "tv" (lam * TV),
-    "rg" (range constraint RG[alpha, beta], 0 <= alpha <= beta <= inf).
+    "rg" (range constraint RG[alpha, beta], 0 <= alpha <= beta <= inf),
+    "growth" (the growth functional of the WF gradient flow example of Sec.
+    5.3: F(s) = inf_r KL(s|r) - lam r + iota_{r <= p}, lam = 2 tau alpha in
+    [0, 1); p is the density cap, 1 in the paper's example).
     """
     kind: str
     lam: float = 1.0
@@ -81,6 +84,11 @@ def RG(alpha, beta):
     return Div("rg", alpha=float(alpha), beta=float(beta))
 
 
+def GROWTH(lam):
+    """Growth functional with incentive lam = 2 tau alpha (0 <= lam < 1)."""
+    return Div("growth", lam=float(lam))
+
+
 # ---------------------------------------------------------------------------
 # proxdiv: Table "proximalexplicit" (Sec. 5.1), stabilized form of eq.
 # (proxdiv) in Sec. 4.3.  proxdiv_F(s, u, eps) = prox^KL_{F/eps}(e^{-u/eps} s) / s
@@ -94,12 +102,16 @@ def proxdiv_log(F: Div, logp: np.ndarray, logs: np.ndarray, ubar, eps: float) ->
       lam KL : lam/(lam+eps) (log p - log s) - ubar/(lam+eps)
       lam TV : clamp(log p - log s, -(lam+ubar)/eps, (lam-ubar)/eps)
       RG     : min(log beta + log p - log s, max(log alpha + log p - log s, -ubar/eps))
+      growth : min(-(ubar + log kappa)/eps, (log p - log s - ubar)/(1 + eps)),
+               kappa = 1 - lam (the two branches of the tumour-growth example,
+               Sec. 5.3, with the cap p; they meet where the paper switches)
     """
     logp = np.asarray(logp, dtype=np.float64)
     logs = np.asarray(logs, dtype=np.float64)
     ubar = np.broadcast_to(np.asarray(ubar, dtype=np.float64), logp.shape)
     with np.errstate(invalid="ignore"):
-        d = logp - logs
+        # p = 0 gives ratio 0 even where s = 0 (0/0 = 0); s = 0 < p gives +inf
+        d = np.where(np.isneginf(logp), -np.inf, logp - logs)
     if F.kind == "eq":
         return d
     if F.kind == "kl":
@@ -115,6 +127,9 @@ def proxdiv_log(F: Div, logp: np.ndarray, logs: np.ndarray, ubar, eps: float) ->
         if np.isinf(F.beta):
             return inner
         return np.minimum(np.log(F.beta) + d, inner)
+    if F.kind == "growth":
+        lk = np.log1p(-F.lam)
+        return np.minimum(-(ubar + lk) / eps, (d - ubar) / (1.0 + eps))
     raise ValueError(F.kind)
 
 
@@ -138,6 +153,14 @@ def proxdiv_scaling(F: Div, p: np.ndarray, s: np.ndarray, ubar, eps: float) -> n
         if np.isinf(F.beta):
             return inner
         return np.minimum(F.beta * ratio, inner)
+    if F.kind == "growth":
+        # first branch while s <= e^{u/eps} kappa^{(1+eps)/eps} p, else the second
+        kap = 1.0 - F.lam
+        with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+            low = s <= np.exp(ubar / eps) * kap ** ((1.0 + eps) / eps) * p
+            first = (np.exp(ubar) * kap) ** (-1.0 / eps) * np.ones_like(s)
+            second = np.where(p > 0, (p / (s * np.exp(ubar))) ** (1.0 / (1.0 + eps)), 0.0)
+        return np.where(p > 0, np.where(low, first, second), 0.0)
     raise ValueError(F.kind)
 
 
@@ -162,7 +185,23 @@ def F_value(F: Div, s: np.ndarray, p: np.ndarray, dx: np.ndarray) -> float:
     if F.kind == "rg":
         ok = np.all(s >= F.alpha * p * (1 - 1e-9)) and np.all(s <= F.beta * p * (1 + 1e-9))
         return 0.0 if ok else np.inf
+    if F.kind == "growth":
+        return float(np.sum(dx * growth_value(s, p, F.lam)))
     raise ValueError(F.kind)
+
+
+def growth_value(s, p, lam):
+    """Pointwise inf_{0 <= r <= p} [KL(s|r) - lam r] in closed form: the inner
+    minimiser is r = min(s / kappa, p) (kappa = 1 - lam), giving s log kappa
+    while s <= kappa p and s log(s/p) - s + kappa p beyond."""
+    s = np.asarray(s, np.float64)
+    p = np.asarray(p, np.float64)
+    kap = 1.0 - lam
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lo = s * np.log(kap)
+        hi = np.where(s > 0, s * np.log(s / p), 0.0) - s + kap * p
+    out = np.where(s <= kap * p, lo, hi)
+    return np.where((p == 0) & (s > 0), np.inf, out)
 
 
 def F_conj(F: Div, w: np.ndarray, p: np.ndarray, dx: np.ndarray) -> float:
@@ -189,6 +228,11 @@ def F_conj(F: Div, w: np.ndarray, p: np.ndarray, dx: np.ndarray) -> float:
         with np.errstate(invalid="ignore"):
             t = np.where(p > 0, p * hi, 0.0)
         return float(np.sum(dx * t))
+    if F.kind == "growth":
+        # the pointwise F is C^1 with F' = log max(kappa, s/p): F*(w) = 0 for
+        # w <= log kappa, p (e^w - kappa) beyond
+        with np.errstate(over="ignore"):
+            return float(np.sum(dx * p * np.maximum(np.exp(w) - (1.0 - F.lam), 0.0)))
     raise ValueError(F.kind)
 
 
@@ -204,15 +248,21 @@ class DenseGeom:
         self.N, self.M = self.C.shape
 
     def lse_x(self, w, eps):
-        return lse(-self.C / eps + np.asarray(w)[None, :], axis=1)
+        with np.errstate(invalid="ignore"):
+            a = np.where(np.isinf(self.C), -np.inf, -self.C / eps + np.asarray(w)[None, :])
+        return lse(a, axis=1)
 
     def lse_y(self, w, eps):
-        return lse(-self.C / eps + np.asarray(w)[:, None], axis=0)
+        with np.errstate(invalid="ignore"):
+            a = np.where(np.isinf(self.C), -np.inf, -self.C / eps + np.asarray(w)[:, None])
+        return lse(a, axis=0)
 
     def cost_moment_log(self, wx, wy, eps):
-        """log sum_ij C_ij exp(wx_i + wy_j - C_ij/eps)."""
-        with np.errstate(divide="ignore"):
-            L = np.log(self.C) - self.C / eps + np.asarray(wx)[:, None] + np.asarray(wy)[None, :]
+        """log sum_ij C_ij exp(wx_i + wy_j - C_ij/eps); pairs with C = inf
+        (beyond a cut locus) carry no mass and contribute nothing."""
+        with np.errstate(divide="ignore", invalid="ignore"):
+            L = np.where(np.isfinite(self.C), np.log(self.C) - self.C / eps, -np.inf) \
+                + np.asarray(wx)[:, None] + np.asarray(wy)[None, :]
         return float(lse(L.reshape(-1), axis=0))
 
 
@@ -230,11 +280,32 @@ def sq_dist(x: np.ndarray, y: np.ndarray) -> np.ndarray:
     return C
 
 
-class PointsGeom(DenseGeom):
-    """Point clouds with the squared Euclidean cost (Sec. 2.3 GHK cost |x-y|^2)."""
+def wf_cost(d2: np.ndarray, cut: float) -> np.ndarray:
+    """Cost of the Wasserstein-Fisher-Rao distance (Definition WF, eq.
+    "logcost"): c = -log cos_+^2(theta), cos_+(z) = cos(min(z, pi/2)), with the
+    distance rescaled so that theta = (pi/2) |x - y| / cut; c is +inf from
+    |x - y| = cut on (the cut locus).  d2 holds squared distances."""
+    d = np.sqrt(np.asarray(d2, np.float64))
+    theta = 0.5 * np.pi * d / cut
+    with np.errstate(divide="ignore"):
+        c = -2.0 * np.log(np.cos(np.minimum(theta, 0.5 * np.pi)))
+    return np.where(theta < 0.5 * np.pi, c, np.inf)
 
-    def __init__(self, x, y):
-        super().__init__(sq_dist(x, y))
+
+def make_cost(d2, cost: str, cut: Optional[float]):
+    if cost == "sqeuclid":
+        return np.asarray(d2, np.float64)
+    if cost == "wf":
+        return wf_cost(d2, cut)
+    raise ValueError(cost)
+
+
+class PointsGeom(DenseGeom):
+    """Point clouds with the squared Euclidean cost (Sec. 2.3 GHK cost |x-y|^2)
+    or, with cost="wf", the WF cost of eq. "logcost" with cut locus `cut`."""
+
+    def __init__(self, x, y, cost: str = "sqeuclid", cut: Optional[float] = None):
+        super().__init__(make_cost(sq_dist(x, y), cost, cut))
 
 
 class GridGeom:
@@ -244,11 +315,16 @@ class GridGeom:
     kernel).  Each 1-D pass is evaluated as a log-sum-exp, which is the same
     sum as the paper's convolution written in the log domain."""
 
-    def __init__(self, shape: Sequence[int], h: Sequence[float]):
+    def __init__(self, shape: Sequence[int], h: Sequence[float], cost: str = "sqeuclid",
+                 cut: Optional[float] = None):
         self.shape = tuple(int(n) for n in shape)
         self.h = tuple(float(v) for v in h)
+        self.cost, self.cut = cost, cut
+        if cost != "sqeuclid" and len(self.shape) != 1:
+            # -log cos^2 of a Euclidean distance is not a sum over axes
+            raise ValueError("the WF cost is separable only on a 1-D grid")
         self.N = self.M = int(np.prod(self.shape))
-        self.C1 = [((np.arange(n)[:, None] - np.arange(n)[None, :]) * hh) ** 2
+        self.C1 = [make_cost(((np.arange(n)[:, None] - np.arange(n)[None, :]) * hh) ** 2, cost, cut)
                    for n, hh in zip(self.shape, self.h)]
 
     def _sep(self, w, logkers):
@@ -273,8 +349,8 @@ class GridGeom:
             kers = []
             for b, C in enumerate(self.C1):
                 if a == b:
-                    with np.errstate(divide="ignore"):
-                        kers.append(np.log(C) - C / eps)
+                    with np.errstate(divide="ignore", invalid="ignore"):
+                        kers.append(np.where(np.isfinite(C), np.log(C) - C / eps, -np.inf))
                 else:
                     kers.append(-C / eps)
             terms.append(lse(np.asarray(wx) + self._sep(wy, kers), axis=0))
@@ -284,19 +360,37 @@ class GridGeom:
         axes = [(np.arange(n) + 0.5) * hh for n, hh in zip(self.shape, self.h)]
         mesh = np.meshgrid(*axes, indexing="ij")
         pts = np.stack([m.reshape(-1) for m in mesh], axis=1)
-        return PointsGeom(pts, pts)
+        return PointsGeom(pts, pts, self.cost, self.cut)
 
 
 # ---------------------------------------------------------------------------
 # residual: relative L1 violation of the X marginal against its prox target
 # (stopping criterion, which the paper leaves unspecified in Alg. 1 / 2)
 # ---------------------------------------------------------------------------
+def expo(pot, prev, logd, eps):
+    """Exponent pot/eps + log d with which a potential enters the next Gibbs
+    product.  Where the product it was computed from vanished (prev = -inf:
+    K b = 0 at that point, which exact zeros of K beyond a cut locus allow),
+    the row of the plan is zero whatever the potential, and every b_j that
+    a_i K_ij could reach is already 0 (q_j = 0), so the point is left out
+    (-inf) instead of carrying an infinite potential into the sum."""
+    pot = np.asarray(pot, np.float64)
+    with np.errstate(invalid="ignore"):
+        w = pot / eps + logd
+    if prev is None:
+        return w
+    return np.where(np.isneginf(prev), -np.inf, w)
+
+
 def marginal_residual(S, u_old, u_new, logdx, eps) -> float:
     """r = sum_i dx_i |e^{S_i + u_old_i/eps} - e^{S_i + u_new_i/eps}|
-           / sum_i dx_i e^{S_i + u_new_i/eps}."""
-    la = S + u_old / eps + logdx
-    lb = S + u_new / eps + logdx
+           / sum_i dx_i e^{S_i + u_new_i/eps}  (terms with S_i = -inf are 0)."""
+    la = S + expo(u_old, S, logdx, eps)
+    lb = S + expo(u_new, S, logdx, eps)
     m = np.max(lb)
+    if m == -np.inf:
+        # the marginal vanishes: 0/0 = 0 if the old one did too
+        return 0.0 if np.all(np.isneginf(la)) else np.inf
     with np.errstate(over="ignore", invalid="ignore"):
         ea = np.exp(la - m)
         eb = np.exp(lb - m)
@@ -332,7 +426,7 @@ def solve(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, eps: float,
     residual r <= tol at the final eps (annealing iterations count), or at
     max_iter.
 
-    Returns dict(u, v, iters, res (list), S_last).
+    Returns dict(u, v, iters, res (list), converged, hist, S) with S the last X product.
     """
     N = len(logp)
     M = len(logq)
@@ -343,18 +437,19 @@ def solve(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, eps: float,
     hist = []
     it = 0
     plan = [(e, n, False) for e, n in stages] + [(eps, None, True)]
+    T = S = None
     for e, n_it, final in plan:
         k = 0
         while True:
             if it >= max_iter:
-                return dict(u=u, v=v, iters=it, res=res, converged=False, hist=hist)
+                return dict(u=u, v=v, iters=it, res=res, converged=False, hist=hist, S=S)
             if n_it is not None and k >= n_it:
                 break
-            S = geom.lse_x(v / e + logdy, e)
+            S = geom.lse_x(expo(v, T, logdy, e), e)
             u_new = e * proxdiv_log(F1, logp, S, 0.0, e)
             r = marginal_residual(S, u, u_new, logdx, e)
             u = u_new
-            T = geom.lse_y(u / e + logdx, e)
+            T = geom.lse_y(expo(u, S, logdx, e), e)
             v = e * proxdiv_log(F2, logq, T, 0.0, e)
             it += 1
             k += 1
@@ -364,7 +459,7 @@ def solve(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, eps: float,
             # the first residual compares with the arbitrary initial u and
             # certifies nothing: it is recorded, not used to stop
             if final and r <= tol and it >= 2:
-                return dict(u=u, v=v, iters=it, res=res, converged=True, hist=hist)
+                return dict(u=u, v=v, iters=it, res=res, converged=True, hist=hist, S=S)
     raise AssertionError("unreachable")
 
 
@@ -401,8 +496,8 @@ def objective(geom, p, q, dx, dy, F1: Div, F2: Div, eps, u, v) -> dict:
     S = geom.lse_x(v / eps + logdy, eps)
     T = geom.lse_y(u / eps + logdx, eps)
     with np.errstate(invalid="ignore"):
-        pi1 = np.exp(u / eps + S)
-        pi2 = np.exp(v / eps + T)
+        pi1 = np.exp(S + expo(u, S, 0.0, eps))
+        pi2 = np.exp(T + expo(v, T, 0.0, eps))
     pi1 = np.nan_to_num(pi1, nan=0.0)
     pi2 = np.nan_to_num(pi2, nan=0.0)
     m1 = float(np.sum(dx * pi1))
@@ -419,8 +514,8 @@ def objective(geom, p, q, dx, dy, F1: Div, F2: Div, eps, u, v) -> dict:
     dual = -c1 - c2 - eps * m1 + eps * mK
     gap = (f1 + c1 + up) + (f2 + c2 + vp)
     with np.errstate(invalid="ignore"):
-        wx = np.where(np.isneginf(u), -np.inf, u / eps + logdx)
-        wy = np.where(np.isneginf(v), -np.inf, v / eps + logdy)
+        wx = np.where(np.isneginf(u), -np.inf, expo(u, S, logdx, eps))
+        wy = np.where(np.isneginf(v), -np.inf, expo(v, T, logdy, eps))
     cost = float(np.exp(geom.cost_moment_log(wx, wy, eps)))
     return dict(primal=primal, dual=dual, gap=gap, transport_cost=cost,
                 mass=m1, mass2=m2, pi1=pi1, pi2=pi2, mK=mK)
@@ -542,6 +637,7 @@ def solve_mass(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, F3: Div, log_m0
     it = 0
     plan = [(e, n, False) for e, n in stages] + [(eps, None, True)]
     lm0 = np.array([float(log_m0)])
+    T = None
     for e, n_it, final in plan:
         k = 0
         while True:
@@ -549,13 +645,13 @@ def solve_mass(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, F3: Div, log_m0
                 return dict(u=u, v=v, zeta=zeta, iters=it, res=res, converged=False)
             if n_it is not None and k >= n_it:
                 break
-            S = geom.lse_x(v / e + logdy, e) + zeta
+            S = geom.lse_x(expo(v, T, logdy, e), e) + zeta
             u_new = e * proxdiv_log(F1, logp, S, 0.0, e)
             r = marginal_residual(S, u, u_new, logdx, e)
             u = u_new
-            T = geom.lse_y(u / e + logdx, e)
+            T = geom.lse_y(expo(u, S, logdx, e), e)
             v = e * proxdiv_log(F2, logq, T + zeta, 0.0, e)
-            logm = float(lse(T + v / e + logdy, axis=0))
+            logm = float(lse(T + expo(v, T, logdy, e), axis=0))
             zeta = float(proxdiv_log(F3, lm0, np.array([logm]), 0.0, e)[0])
             it += 1
             k += 1
@@ -664,26 +760,141 @@ def barycenter(geom, logp, alpha, logdx, logdy, F1: Div, F2: Div, eps: float,
     u = np.zeros((n, N))
     res = []
     logh = None
+    T = None
     for it in range(1, max_iter + 1):
-        num = 0.0
-        den = 0.0
-        S = np.stack([geom.lse_x(v[k] / eps + logdy, eps) for k in range(n)])
+        S = np.stack([geom.lse_x(expo(v[k], None if T is None else T[k], logdy, eps), eps) for k in range(n)])
         u_new = eps * proxdiv_log(F1, logp, S, 0.0, eps)
-        la = S + u / eps + logdx
-        lb = S + u_new / eps + logdx
-        m = np.max(lb)
-        with np.errstate(over="ignore", invalid="ignore"):
-            num = np.sum(np.where(np.isneginf(la) & np.isneginf(lb), 0.0, np.abs(np.exp(la - m) - np.exp(lb - m))))
-        den = np.sum(np.exp(lb - m))
-        r = float(num / den)
+        # aggregated over every coupling
+        r = marginal_residual(S, u, u_new, logdx, eps)
         u = u_new
-        T = np.stack([geom.lse_y(u[k] / eps + logdx, eps) for k in range(n)])
+        T = np.stack([geom.lse_y(expo(u[k], S[k], logdx, eps), eps) for k in range(n)])
         logh = bary_logh(T, alpha, eps, F2)
         v = eps * proxdiv_log(F2, np.broadcast_to(logh, T.shape), T, 0.0, eps)
         res.append(r)
         if r <= tol and it >= 2:
             return dict(u=u, v=v, logh=logh, iters=it, res=res, converged=True)
     return dict(u=u, v=v, logh=logh, iters=max_iter, res=res, converged=False)
+
+
+# ---------------------------------------------------------------------------
+# gradient flows (Sec. 5.3): each time step is one problem of the generic
+# form, solved by the scaling iteration; the next density is read off the
+# optimal coupling
+# ---------------------------------------------------------------------------
+def second_marginal_log(geom, u, v, logdx, eps, S=None):
+    """log pi2 = log(R^T dx) = v/eps + T(u), the density of P^2_# R w.r.t. dy
+    (S: the product u was computed from, for the vanishing-product rule)."""
+    T = geom.lse_y(expo(u, S, logdx, eps), eps)
+    return T + expo(v, T, 0.0, eps)
+
+
+def growth_joint_pot(T, logq, lam, eps):
+    """Y update of the multi-species growth step (Sec. 5.3, several species).
+    The paper's joint proxdiv is e^{-u_k/eps} / beta(sum_k s_k e^{-u_k/eps})
+    with beta(Z) = max(Z^{1/(1+eps)}, kappa^{1/eps}), kappa = 1 - lam, for the
+    cap 1; with a cap q, Z is replaced by Z/q.  In potentials (u = 0 form):
+    v = -eps log beta, the same for every species.  T: (S, M), T_k = log s_k."""
+    T = np.atleast_2d(np.asarray(T, np.float64))
+    logq = np.asarray(logq, np.float64)
+    L = lse(T, axis=0)
+    lk = np.log1p(-lam)
+    with np.errstate(invalid="ignore"):
+        logbeta = np.maximum((L - logq) / (1.0 + eps), lk / eps)
+    v = np.where(np.isneginf(logq), -np.inf, -eps * logbeta)
+    return np.broadcast_to(v, T.shape).copy()
+
+
+def growth_next_log(logy, logq, lam):
+    """Next densities of the growth flow from the second marginals y_k of the
+    optimal couplings: the minimiser r_k of sum_k KL(y_k|r_k) - lam sum_k r_k
+    under sum_k r_k <= q, i.e. r_k = y_k / max(kappa, sum_k y_k / q) (for one
+    species min(y / kappa, q), as Sec. 5.3 states)."""
+    logy = np.atleast_2d(np.asarray(logy, np.float64))
+    logq = np.asarray(logq, np.float64)
+    L = lse(logy, axis=0)
+    with np.errstate(invalid="ignore"):
+        den = np.maximum(np.log1p(-lam), L - logq)
+    out = logy - den
+    return np.where(np.isneginf(logq) | np.isneginf(logy), -np.inf, out)
+
+
+def solve_species(geom, logp, logq, logdx, logdy, lam, eps, tol=1e-6, max_iter=10000, v0=None,
+                  F1: Optional[Div] = None):
+    """Scaling iterations of one step of the multi-species WF growth flow
+    (Sec. 5.3; the several-couplings iteration of Sec. 4.4): S couplings R_k,
+    F1 = KL(.|p_k) (lambda 1 unless given) on each first marginal and the joint
+    growth functional of incentive lam and cap q on the sum of the second
+    marginals.  Per iteration: S_k = log K(b_k dy), u_k = eps log
+    proxdiv_F1(p_k)(e^{S_k}) for every k; then T_k = log K^T(a_k dx) and the
+    joint v (growth_joint_pot).  The residual aggregates the X-marginal
+    violations of all couplings; the first one never stops the loop.
+    Returns dict(u, v, iters, res, converged)."""
+    F1 = KL(1.0) if F1 is None else F1
+    logp = np.atleast_2d(np.asarray(logp, np.float64))
+    n, N = logp.shape
+    M = len(logdy)
+    v = np.zeros((n, M)) if v0 is None else np.array(np.broadcast_to(v0, (n, M)), np.float64)
+    u = np.zeros((n, N))
+    res = []
+    T = None
+    for it in range(1, max_iter + 1):
+        S = np.stack([geom.lse_x(expo(v[k], None if T is None else T[k], logdy, eps), eps) for k in range(n)])
+        u_new = eps * proxdiv_log(F1, logp, S, 0.0, eps)
+        # aggregated over every coupling
+        r = marginal_residual(S, u, u_new, logdx, eps)
+        u = u_new
+        T = np.stack([geom.lse_y(expo(u[k], S[k], logdx, eps), eps) for k in range(n)])
+        v = growth_joint_pot(T, logq, lam, eps)
+        res.append(r)
+        if r <= tol and it >= 2:
+            return dict(u=u, v=v, iters=it, res=res, converged=True, S=S)
+    return dict(u=u, v=v, iters=max_iter, res=res, converged=False, S=S)
+
+
+def flow(geom, kind: str, p0, q, dx, tau: float, eps: float, n_steps: int, iters: int,
+         alpha: float = 0.0, tol: float = 0.0):
+    """A time-discretised gradient flow (Sec. 5.3): n_steps steps, each solved
+    by the scaling iteration (`iters` iterations, or to tol), warm-started with
+    the previous step's v.  X = Y, dx = dy.
+      "heat"  : F1 = iota_=(. | p_k), F2 = 2 tau KL(. | q): Wasserstein flow of
+                KL(. | q dx); next density = pi2
+      "crowd" : F1 = iota_=(. | p_k), F2 = iota_{<= q}: the projection step of
+                the congested crowd model (its free evolution is another
+                algorithm and not part of this); next density = pi2
+      "growth": WF flow of -alpha mu(X) + iota_{<= q}: per species F1 = KL(. |
+                p_k), the joint growth functional with lam = 2 tau alpha on the
+                second marginals; next densities from growth_next_log
+    p0: (S, N) initial densities (S = 1 unless kind is "growth").
+    Returns (list of n_steps + 1 arrays (S, N), list of per-step info dicts)."""
+    p = np.atleast_2d(np.asarray(p0, np.float64))
+    q = np.asarray(q, np.float64)
+    dx = np.asarray(dx, np.float64)
+    logdx = np.log(dx)
+    logq = safe_log(q)
+    n = p.shape[0]
+    if kind != "growth" and n != 1:
+        raise ValueError("several species only for the growth flow")
+    out = [p.copy()]
+    infos = []
+    v = None
+    for _ in range(n_steps):
+        logp = safe_log(p)
+        if kind == "growth":
+            lam = 2.0 * tau * alpha
+            r = solve_species(geom, logp, logq, logdx, logdx, lam, eps, tol=tol, max_iter=iters, v0=v)
+            logy = np.stack([second_marginal_log(geom, r["u"][k], r["v"][k], logdx, eps, r["S"][k])
+                             for k in range(n)])
+            p = np.exp(growth_next_log(logy, logq, lam))
+            v = r["v"]
+        else:
+            F2 = KL(2.0 * tau) if kind == "heat" else RG(0.0, 1.0)
+            r = solve(geom, logp[0], logq, logdx, logdx, EQ, F2, eps, tol=tol, max_iter=iters,
+                      v0=None if v is None else v[0])
+            p = np.exp(second_marginal_log(geom, r["u"], r["v"], logdx, eps, r["S"]))[None, :]
+            v = r["v"][None, :]
+        out.append(p.copy())
+        infos.append(dict(iters=r["iters"], res=r["res"], converged=r["converged"]))
+    return out, infos
 
 
 # ---------------------------------------------------------------------------
