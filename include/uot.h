@@ -62,12 +62,28 @@ enum uot_status_code {
  *   UOT_DIV_KL : lambda KL,           proxdiv = (p/s)^(lambda/(lambda+eps))
  *   UOT_DIV_TV : lambda TV,           proxdiv = min(e^(lambda/eps), max(e^(-lambda/eps), p/s))
  *   UOT_DIV_RG : range [alpha, beta], proxdiv = min(beta p/s, max(alpha p/s, 1))
- * beta = +inf (and alpha = 0) are allowed for RG. */
-enum uot_div_kind { UOT_DIV_EQ = 0, UOT_DIV_KL = 1, UOT_DIV_TV = 2, UOT_DIV_RG = 3 };
+ * beta = +inf (and alpha = 0) are allowed for RG.
+ *   UOT_DIV_GROWTH: the growth functional of the WF gradient-flow example
+ *                (Sec. 5.3, tumour growth), F(s) = inf_r KL(s|r) - lambda r
+ *                over 0 <= r <= p, lambda = 2 tau alpha in [0, 1), p the
+ *                density cap (1 in the paper);
+ *                proxdiv = min(kappa^{-1/eps}, (p/s)^{1/(1+eps)}),
+ *                kappa = 1 - lambda: the example's two branches.  Not
+ *                accepted on the barycentre side. */
+enum uot_div_kind { UOT_DIV_EQ = 0, UOT_DIV_KL = 1, UOT_DIV_TV = 2, UOT_DIV_RG = 3, UOT_DIV_GROWTH = 4 };
 
 enum uot_dtype { UOT_F64 = 0, UOT_F32 = 1 };
 
-/* Geometry of the cost C_ij = |x_i - y_j|^2 (squared Euclidean, Sec. 2.3).
+/* Geometry of the cost: C_ij = |x_i - y_j|^2 (squared Euclidean, Sec. 2.3;
+ * cost = UOT_COST_SQEUCLID) or the Wasserstein-Fisher-Rao cost of Definition
+ * WF, eq. "logcost", C_ij = -log cos^2((pi/2) |x_i - y_j| / cut) for
+ * |x_i - y_j| < cut and +inf beyond (cost = UOT_COST_WF; the distance is
+ * rescaled so that the cut locus pi/2 sits at `cut`).  K then has exact zeros:
+ * the dense product skips column tiles whose bounding box lies beyond the cut
+ * from the rows' box (pays when points are stored in a spatially coherent
+ * order), 1-D grid passes read only the taps within the cut.  The WF cost is
+ * not separable over axes: on grids it needs dim = 1.  Ragged batches take
+ * the squared Euclidean cost only.
  *   UOT_GEOM_POINTS: point clouds; x is dim x N, y is dim x M, coordinate-major
  *                    (x[k*N + i] = k-th coordinate of x_i); 1 <= dim <= 3.
  *                    The Gibbs product is a dense log-sum-exp that recomputes
@@ -80,6 +96,7 @@ enum uot_dtype { UOT_F64 = 0, UOT_F32 = 1 };
  *                    separable kernel), each 1-D pass evaluated as a
  *                    log-sum-exp.  N = M = prod(n). */
 enum uot_geom_kind { UOT_GEOM_POINTS = 0, UOT_GEOM_GRID = 1 };
+enum uot_cost_kind { UOT_COST_SQEUCLID = 0, UOT_COST_WF = 1 };
 
 typedef struct uot_div {
   int32_t kind;      /* enum uot_div_kind                              */
@@ -97,6 +114,9 @@ typedef struct uot_geom {
   const void *y;     /* POINTS: device, dim x M                        */
   int64_t n[3];      /* GRID: cells per axis                           */
   double h[3];       /* GRID: spacing per axis                         */
+  int32_t cost;      /* enum uot_cost_kind (0: squared Euclidean)      */
+  int32_t reserved;
+  double cut;        /* UOT_COST_WF: cut-locus distance, > 0           */
 } uot_geom;
 
 typedef struct uot_problem {
@@ -261,6 +281,59 @@ int uot_bary_workspace_size(const uot_bary_problem *pb, size_t *bytes);
 int uot_barycenter(uot_ctx *ctx, const uot_bary_problem *pb, const uot_params *pr,
                    void *u, void *v, void *logh, void *ws, size_t ws_bytes,
                    uot_result *res);
+
+/* ---------------------------------------------------------------------------
+ * Gradient flows (Sec. 5.3): n_steps time steps of size tau, each one problem
+ * of the generic form on X = Y solved by the scaling iteration (to pr->tol or
+ * pr->max_iter iterations per step, pr->eps with optional eps-scaling per
+ * step), warm-started with the previous step's v; the next density is read
+ * off the optimal coupling on the device.  With p_k the density of step k:
+ *   UOT_FLOW_HEAT  : F1 = iota_=(. | p_k), F2 = 2 tau KL(. | q) (Wasserstein
+ *                    flow of KL(. | q dx); q = 1 gives the heat flow);
+ *                    p_{k+1} = pi2, the density of the coupling's second
+ *                    marginal w.r.t. dx.
+ *   UOT_FLOW_CROWD : F1 = iota_=(. | p_k), F2 = iota_{<= q} (the projection
+ *                    step of the congested crowd model, proxdiv min(q/s, 1);
+ *                    its free evolution is another algorithm and is left to
+ *                    the caller); p_{k+1} = pi2.
+ *   UOT_FLOW_GROWTH: WF flow of -alpha mu(X) + iota_{<= q}: per species
+ *                    F1 = KL(. | p_k) and, on the second marginals, the growth
+ *                    functional (UOT_DIV_GROWTH, lambda = 2 tau alpha) of
+ *                    their sum with cap q; the joint proxdiv gives every
+ *                    species the potential -eps log max((Z/q)^{1/(1+eps)},
+ *                    kappa^{1/eps}), Z = sum_k s_k, kappa = 1 - 2 tau alpha.
+ *                    p_{k+1} = pi2_k / max(kappa, sum_k pi2_k / q), the
+ *                    inner minimiser of the growth functional (one species:
+ *                    min(pi2 / kappa, q), as the paper states).  The paper
+ *                    uses the WF cost (geom.cost = UOT_COST_WF) and q = 1.
+ * Several species need a grid; X = Y means a grid, or points with x == y.
+ * ------------------------------------------------------------------------- */
+enum uot_flow_kind { UOT_FLOW_HEAT = 0, UOT_FLOW_CROWD = 1, UOT_FLOW_GROWTH = 2 };
+
+typedef struct uot_flow_problem {
+  int32_t dtype;         /* UOT_F32 or UOT_F64                               */
+  int32_t kind;          /* enum uot_flow_kind                               */
+  int32_t species;       /* densities moved together, >= 1 (> 1: growth, grid) */
+  int32_t reserved;
+  uot_geom geom;         /* X = Y (grid, or points with x == y, N == M)      */
+  const void *p0;        /* device, species x N: initial densities w.r.t. dx */
+  const void *q;         /* device, N: reference (HEAT) / cap (CROWD, GROWTH) */
+  const void *dx;        /* device, N: reference weights (dy = dx), > 0      */
+  double tau;            /* time step, > 0                                    */
+  double alpha;          /* GROWTH: growth rate >= 0, 2 tau alpha < 1         */
+} uot_flow_problem;
+
+int uot_flow_workspace_size(const uot_flow_problem *fp, size_t *bytes);
+/* dens: device, (n_steps + 1) x species x N output; dens[0] = p0 and
+ * dens[k] is the density after step k.  v: device, species x N output, the
+ * last step's v (pr->v0, if set, warm-starts the first step).  steps: optional
+ * HOST array of n_steps results (iterations, last residual, status, time of
+ * each step).  pr->res_hist, if set, holds the last step's residuals.
+ * grid_kernel 4 is not available.  Returns UOT_NOT_CONVERGED when a step
+ * ended at max_iter (always so with tol = 0, the fixed-iteration steps of the
+ * paper's experiments). */
+int uot_flow(uot_ctx *ctx, const uot_flow_problem *fp, const uot_params *pr, int32_t n_steps,
+             void *dens, void *v, void *ws, size_t ws_bytes, uot_result *steps);
 
 /* ---------------------------------------------------------------------------
  * Ragged batches: B independent point-cloud problems of uneven sizes, solved

@@ -93,11 +93,14 @@ DivDev to_dev(const uot_div& d) {
   r.has_hi = (d.kind == UOT_DIV_RG && std::isfinite(d.beta)) ? 1 : 0;
   r.log_alpha = r.has_lo ? std::log(d.alpha) : 0.0;
   r.log_beta = r.has_hi ? std::log(d.beta) : 0.0;
+  if (d.kind == UOT_DIV_GROWTH) r.log_alpha = std::log1p(-d.lambda);
   return r;
 }
 
 int check_div(const uot_div& d, const char* name) {
-  if (d.kind < 0 || d.kind > 3) return fail(UOT_E_INVALID, std::string(name) + ": unknown divergence kind");
+  if (d.kind < 0 || d.kind > 4) return fail(UOT_E_INVALID, std::string(name) + ": unknown divergence kind");
+  if (d.kind == UOT_DIV_GROWTH && !(d.lambda >= 0 && d.lambda < 1))
+    return fail(UOT_E_INVALID, std::string(name) + ": growth needs 0 <= lambda (= 2 tau alpha) < 1");
   if ((d.kind == UOT_DIV_KL || d.kind == UOT_DIV_TV) && !(d.lambda > 0 && std::isfinite(d.lambda)))
     return fail(UOT_E_INVALID, std::string(name) + ": lambda must be finite and > 0");
   if (d.kind == UOT_DIV_RG && !(d.alpha >= 0 && d.beta >= d.alpha && d.beta > 0))
@@ -127,6 +130,8 @@ struct Plan {
   int gk = 1;            // grid passes: 1 direct log-sum-exp, 2 tile-factored MFMA where allowed
   bool tf_axis[3] = {false, false, false};   // tile-factored pass used on this axis
   bool tf16_axis[3] = {false, false, false}; // ... with FP16 operands
+  CostArgs cost{0, 0, 0.0};                  // squared Euclidean or WF with a cut locus
+  int band[3] = {0, 0, 0};                   // grid axes: taps |i - j| < band can be non-zero
   // workspace offsets
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
       o_gcost, o_obj, o_scal, o_mass, total;
@@ -186,6 +191,14 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
   P.nb = nb;
   P.nst = nst;
   if (g.dim < 1 || g.dim > 3) return fail(UOT_E_UNSUPPORTED, "dim must be 1, 2 or 3");
+  if (g.cost != UOT_COST_SQEUCLID && g.cost != UOT_COST_WF) return fail(UOT_E_INVALID, "unknown cost kind");
+  if (g.cost == UOT_COST_WF) {
+    if (!(g.cut > 0 && std::isfinite(g.cut))) return fail(UOT_E_INVALID, "the WF cost needs a finite cut > 0");
+    if (g.kind == UOT_GEOM_GRID && g.dim != 1)
+      return fail(UOT_E_UNSUPPORTED, "the WF cost is not separable: grids need dim = 1");
+  }
+  P.cost.kind = g.cost;
+  P.cost.cut = g.cost == UOT_COST_WF ? g.cut : 0.0;
   if (g.kind == UOT_GEOM_POINTS) {
     if (g.N < 1 || g.M < 1) return fail(UOT_E_INVALID, "N and M must be >= 1");
     if (!g.x || !g.y) return fail(UOT_E_INVALID, "point coordinates x and y are required");
@@ -205,8 +218,11 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
     P.N = P.M = sz;
     for (int k = 0; k < g.dim; ++k) {
       const double c = eps_min > 0 ? g.h[k] * g.h[k] * kLog2e / eps_min : INFINITY;
-      P.tf_axis[k] = P.gk >= 2 && dtype == UOT_F32 && g.n[k] % 16 == 0 && c <= kTfMaxC;
+      // the tile factorization is that of the Gaussian kernel
+      P.tf_axis[k] = P.gk >= 2 && dtype == UOT_F32 && g.n[k] % 16 == 0 && c <= kTfMaxC && g.cost == UOT_COST_SQEUCLID;
       P.tf16_axis[k] = P.tf_axis[k] && (P.gk == 3 || P.gk == 4) && c <= kTf16MaxC;
+      P.band[k] = (int)g.n[k];
+      if (g.cost == UOT_COST_WF) P.band[k] = (int)std::min<double>((double)g.n[k], std::ceil(g.cut / g.h[k]));
     }
   } else {
     return fail(UOT_E_INVALID, "unknown geometry kind");
@@ -339,7 +355,7 @@ void contig_pass(const Plan& P, int axis, const T* w, int64_t A, T* const* tabs,
       return;
     }
   }
-  timed(0, [&] { launch_grid_contig<T>(w, A, (int)P.n[axis], tabs[axis], side, c, ep, s); });
+  timed(0, [&] { launch_grid_contig<T>(w, A, (int)P.n[axis], tabs[axis], side, c, ep, P.band[axis], s); });
 }
 
 template <typename T>
@@ -404,7 +420,7 @@ void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Buf
   const int64_t Mc = half == 0 ? P.M : P.N;
   timed(0, [&] {
     launch_dense_lse<T>(P.dim, P.R[half], rows, Nr, cols, w_cols, Mc, P.splits[half], P.cps[half], B.pm, B.ps, side,
-                        c, s);
+                        c, P.cost, s);
   });
   timed(1, [&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[half], Nr, side, c, ep, s); });
 }
@@ -470,13 +486,24 @@ inline int even_chunk(int check_every) {
   return c + (c & 1);
 }
 
+// a captured chunk kept across solves whose launches are the same (the steps
+// of a gradient flow): captured by the first solve, replayed by the others
+struct GraphCache {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~GraphCache() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
 // drive iterations until the device sets stop; `iteration(par)` enqueues one
 // iteration of parity par.  With a second phase (`iteration2`, non-null
 // `final_tol`), a stop with status 0 ends phase one (whose control block
 // tolerance was looser): the solve resumes at `final_tol` with iteration2.
 template <typename F, typename F2 = std::remove_reference_t<F>>
 int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot_result* res,
-             F2* iteration2 = nullptr, const double* final_tol = nullptr) {
+             F2* iteration2 = nullptr, const double* final_tol = nullptr, GraphCache* cache = nullptr) {
   hipStream_t s = ctx->work;
   const int chunk = even_chunk(pr->check_every);
   hipGraphExec_t exec = nullptr;
@@ -502,8 +529,14 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
     exec = nullptr;
     graph = nullptr;
   };
-  int rc = capture(iteration);
-  if (rc) return rc;
+  int rc = UOT_OK;
+  if (cache && cache->exec && pr->use_graph && !timing) {
+    exec = cache->exec;
+    graph = cache->graph;
+  } else {
+    rc = capture(iteration);
+    if (rc) return rc;
+  }
   bool second = false;
   auto t0 = std::chrono::steady_clock::now();
   int64_t launched = 0;
@@ -542,8 +575,14 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
     }
   }
   auto t1 = std::chrono::steady_clock::now();
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
+  if (cache && !second) {
+    // keep the phase-one graph for the next solve
+    cache->exec = exec;
+    cache->graph = graph;
+  } else {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
   if (rc) return rc;
   res->iters = ctx->pinned->iter;
   res->residual = ctx->pinned->res;
@@ -582,7 +621,7 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, P.N, 0, s);
   launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
   if (P.geom == UOT_GEOM_GRID)
-    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, P.nst, s);
+    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, P.nst, P.cost, s);
   launch_init_pot<T>(nullptr, B.logdx, u, nullptr, nb * P.N, P.N, B.ctrl, 0, s);
   launch_init_pot<T>(static_cast<const T*>(pr->v0), B.logdy, v, B.wv, nb * P.M, P.M, B.ctrl, 0, s);
   HIP_TRY(hipGetLastError());
@@ -636,7 +675,7 @@ int half_step_t(uot_ctx* ctx, const uot_problem* pb, double eps, int side, const
   launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, P.N, 0, s);
   launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
   if (P.geom == UOT_GEOM_GRID)
-    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, 1, s);
+    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, 1, P.cost, s);
   if (side == 0) {
     launch_init_pot<T>(pot_in, B.logdy, nullptr, B.wv, P.M, P.M, B.ctrl, 0, s);
     half_step<T>(P, *pb, 0, B, pot_io, lse_out, true, s);
@@ -673,7 +712,7 @@ int objective_t(uot_ctx* ctx, const uot_problem* pb, double eps, const T* u, con
   launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, P.N, 0, s);
   launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
   if (P.geom == UOT_GEOM_GRID)
-    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, 1, s);
+    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, 1, P.cost, s);
   // w fields of u and v, and of the zero potential (for m(K))
   launch_init_pot<T>(v, B.logdy, nullptr, B.wv, P.M, P.M, B.ctrl, 0, s);
   launch_init_pot<T>(u, B.logdx, nullptr, B.wu, P.N, P.N, B.ctrl, 0, s);
@@ -715,7 +754,7 @@ int objective_t(uot_ctx* ctx, const uot_problem* pb, double eps, const T* u, con
   int ncost = 0;
   if (P.geom == UOT_GEOM_GRID) {
     for (int a = 0; a < P.dim; ++a) {
-      launch_gtab_cost<T>(B.gcost, (int)P.n[a], P.h[a], eps, s);
+      launch_gtab_cost<T>(B.gcost, (int)P.n[a], P.h[a], eps, P.cost, s);
       T* tabs[3] = {B.gtab[0], B.gtab[1], B.gtab[2]};
       tabs[a] = B.gcost;
       product(0, B.wv, B.t1, tabs);
@@ -724,7 +763,7 @@ int objective_t(uot_ctx* ctx, const uot_problem* pb, double eps, const T* u, con
     }
   } else {
     launch_dense_cost<T>(P.dim, static_cast<const T*>(pb->geom.x), P.N, static_cast<const T*>(pb->geom.y), B.wv, P.M,
-                         eps, B.t1, s);
+                         eps, B.t1, P.cost, s);
     launch_sum_exp2<T>(B.wu, B.t1, P.N, part3, s);
     ncost = 1;
   }
@@ -747,8 +786,8 @@ int objective_t(uot_ctx* ctx, const uot_problem* pb, double eps, const T* u, con
   out->transport_cost = cost;
   out->primal = sx[2] + sy[2] + sx[1] + sy[1] - eps * sx[0] + eps * mK;
   out->dual = -sx[3] - sy[3] - eps * sx[0] + eps * mK;
-  const bool finite_gap = (pb->F1.kind == UOT_DIV_KL || pb->F1.kind == UOT_DIV_TV) &&
-                          (pb->F2.kind == UOT_DIV_KL || pb->F2.kind == UOT_DIV_TV);
+  auto finite_valued = [](int k) { return k == UOT_DIV_KL || k == UOT_DIV_TV || k == UOT_DIV_GROWTH; };
+  const bool finite_gap = finite_valued(pb->F1.kind) && finite_valued(pb->F2.kind);
   out->gap = finite_gap ? (sx[2] + sx[3] + sx[1]) + (sy[2] + sy[3] + sy[1]) : NAN;
   if (!finite_gap) out->primal = NAN;
   return finish(ctx);
@@ -776,7 +815,7 @@ int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u,
   launch_log<T>(static_cast<const T*>(pb->p), B.logp, nb * size, 1, s);
   launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, size, 0, s);
   launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, size, 0, s);
-  for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, P.nst, s);
+  for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, P.nst, P.cost, s);
   launch_init_pot<T>(nullptr, B.logdx, u, nullptr, nb * size, size, B.ctrl, 0, s);
   launch_init_pot<T>(static_cast<const T*>(pr->v0), B.logdy, v, B.wv, nb * size, size, B.ctrl, 0, s);
   HIP_TRY(hipGetLastError());
@@ -810,6 +849,129 @@ int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u,
   return res->status == 0 ? UOT_OK : UOT_NOT_CONVERGED;
 }
 
+// ---------------------------------------------------------------------------
+// gradient flows (Sec. 5.3): a sequence of steps, each one problem of the
+// generic form solved by the scaling iteration, warm-started with the previous
+// step's v; the next density is read off the optimal coupling on the device
+// ---------------------------------------------------------------------------
+struct FlowDivs {
+  uot_div F1, F2;
+};
+
+int validate_flow(const uot_flow_problem* fp, FlowDivs& d) {
+  if (!fp) return fail(UOT_E_INVALID, "flow problem is NULL");
+  if (!fp->p0 || !fp->q || !fp->dx) return fail(UOT_E_INVALID, "p0, q and dx are required");
+  if (fp->kind < UOT_FLOW_HEAT || fp->kind > UOT_FLOW_GROWTH) return fail(UOT_E_INVALID, "unknown flow kind");
+  if (!(fp->tau > 0 && std::isfinite(fp->tau))) return fail(UOT_E_INVALID, "tau must be finite and > 0");
+  if (fp->species < 1 || fp->species > kMaxBary) return fail(UOT_E_UNSUPPORTED, "1 <= species <= 64");
+  if (fp->species > 1 && fp->kind != UOT_FLOW_GROWTH)
+    return fail(UOT_E_UNSUPPORTED, "several species only for the growth flow");
+  if (fp->species > 1 && fp->geom.kind != UOT_GEOM_GRID)
+    return fail(UOT_E_UNSUPPORTED, "several species need a grid geometry");
+  if (fp->geom.kind == UOT_GEOM_POINTS && (fp->geom.x != fp->geom.y || fp->geom.N != fp->geom.M))
+    return fail(UOT_E_INVALID, "a flow moves densities on one space: x and y must be the same points");
+  const double lam = 2.0 * fp->tau * fp->alpha;
+  if (fp->kind == UOT_FLOW_GROWTH && !(fp->alpha >= 0 && lam < 1))
+    return fail(UOT_E_INVALID, "growth flow: alpha >= 0 and 2 tau alpha < 1");
+  d.F1 = uot_div{fp->kind == UOT_FLOW_GROWTH ? UOT_DIV_KL : UOT_DIV_EQ, 0, 1.0, 0.0, INFINITY};
+  if (fp->kind == UOT_FLOW_HEAT) d.F2 = uot_div{UOT_DIV_KL, 0, 2.0 * fp->tau, 0.0, INFINITY};
+  else if (fp->kind == UOT_FLOW_CROWD) d.F2 = uot_div{UOT_DIV_RG, 0, 1.0, 0.0, 1.0};
+  else d.F2 = uot_div{UOT_DIV_GROWTH, 0, lam, 0.0, INFINITY};
+  return UOT_OK;
+}
+
+int flow_plan(Plan& P, const uot_flow_problem* fp, int nst, int grid_kernel, double eps_min, size_t& o_u) {
+  int rc = make_plan(P, fp->dtype, fp->geom, fp->species, nst, grid_kernel, eps_min);
+  if (rc) return rc;
+  o_u = align_up(P.total);
+  P.total = align_up(o_u + P.esz * (size_t)fp->species * P.N);
+  return UOT_OK;
+}
+
+template <typename T>
+int flow_t(uot_ctx* ctx, const uot_flow_problem* fp, const FlowDivs& fd, const uot_params* pr, int n_steps, T* dens,
+           T* v, char* ws, size_t wsb, uot_result* steps) {
+  Plan P;
+  size_t o_u = 0;
+  const bool anneal = pr->eps0 > pr->eps && pr->eps_stages > 0 && pr->iters_per_stage > 0;
+  int rc = flow_plan(P, fp, anneal ? pr->eps_stages + 1 : 1, pr->grid_kernel, pr->eps, o_u);
+  if (rc) return rc;
+  if ((rc = check_ws(P, ws, wsb))) return rc;
+  if (!dens || !v) return fail(UOT_E_INVALID, "dens and v output buffers are required");
+  hipStream_t s = ctx->work;
+  if ((rc = begin(ctx))) return rc;
+  Bufs<T> B = carve<T>(P, ws);
+  T* u = at<T>(ws, o_u);
+  const int S = fp->species;
+  const int64_t N = P.N, SN = (int64_t)S * N;
+  const Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, pr->tol, pr->max_iter);
+  launch_ctrl_init(B.ctrl, init, s);
+  launch_log<T>(static_cast<const T*>(fp->dx), B.logdx, N, 0, s);
+  launch_log<T>(static_cast<const T*>(fp->dx), B.logdy, N, 0, s);
+  launch_log<T>(static_cast<const T*>(fp->q), B.logq, N, 1, s);
+  if (P.geom == UOT_GEOM_GRID)
+    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, P.nst, P.cost, s);
+  HIP_TRY(hipMemcpyAsync(dens, fp->p0, sizeof(T) * SN, hipMemcpyDeviceToDevice, s));
+  if (pr->v0) HIP_TRY(hipMemcpyAsync(v, pr->v0, sizeof(T) * SN, hipMemcpyDeviceToDevice, s));
+  else launch_init_pot<T>(nullptr, B.logdy, v, nullptr, SN, N, B.ctrl, 0, s);
+  uot_problem pb{};
+  pb.dtype = fp->dtype;
+  pb.geom = fp->geom;
+  pb.F1 = fd.F1;
+  pb.F2 = fd.F2;
+  const DivDev Fg = to_dev(fd.F2);
+  const bool growth = fp->kind == UOT_FLOW_GROWTH;
+  auto iteration = [&](int par) {
+    if (S == 1) {
+      half_step<T>(P, pb, 0 | par << 1, B, u, nullptr, true, s);
+      timed(2, [&] { launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s, 0, par); });
+      half_step<T>(P, pb, 1 | par << 1, B, v, nullptr, false, s);
+    } else {
+      // several species: KL(. | p_k) on each first marginal, the joint growth
+      // proxdiv on the sum of the second marginals
+      EpiArgs<T> ep = prox_epi<T>(u, B.wu, B.logp, B.logdx, nullptr, B.parts, N, fd.F1);
+      grid_chain<T>(P, B.wv, B.gtab, 0 | par << 1, B.ctrl, ep, B.t1, B.t2, s);
+      timed(2, [&] { launch_control(B.ctrl, B.parts, P.nparts_x, pr->res_hist, s, 0, par); });
+      EpiArgs<T> raw{};
+      raw.mode = EPI_RAW;
+      raw.out = B.t3;
+      grid_chain<T>(P, B.wu, B.gtab, 1 | par << 1, B.ctrl, raw, B.t1, B.t2, s);
+      launch_growth_combine<T>(B.t3, S, N, Fg, B.logq, B.logdy, v, B.wv, B.ctrl, 1 | par << 1, s);
+    }
+  };
+  GraphCache cache;
+  int worst = UOT_OK;
+  for (int k = 0; k < n_steps; ++k) {
+    T* pk = dens + (int64_t)k * SN;
+    T* pn = pk + SN;
+    launch_ctrl_init(B.ctrl, init, s);
+    launch_log<T>(pk, B.logp, SN, 1, s);
+    launch_init_pot<T>(nullptr, B.logdx, u, nullptr, SN, N, B.ctrl, 0, s);
+    launch_init_pot<T>(v, B.logdy, v, B.wv, SN, N, B.ctrl, 0, s);   // warm start: last step's v
+    HIP_TRY(hipGetLastError());
+    uot_result r{};
+    rc = run_loop(ctx, B.ctrl, pr, iteration, &r, static_cast<decltype(iteration)*>(nullptr), nullptr, &cache);
+    if (rc) return rc;
+    if (steps) steps[k] = r;
+    if (r.status == -3) return fail(UOT_E_NONFINITE, "non-finite residual in flow step " + std::to_string(k));
+    if (r.status != 0) worst = UOT_NOT_CONVERGED;
+    // the second marginals of the final plans: one more Y product at the last eps
+    launch_ctrl_post(B.ctrl, s);
+    launch_init_pot<T>(u, B.logdx, nullptr, B.wu, SN, N, B.ctrl, 0, s);
+    EpiArgs<T> raw{};
+    raw.mode = EPI_RAW;
+    raw.out = B.t3;
+    if (P.geom == UOT_GEOM_GRID) grid_chain<T>(P, B.wu, B.gtab, 1, B.ctrl, raw, B.t1, B.t2, s);
+    else dense_half<T>(P, fp->geom, 1, B.wu, B, B.ctrl, raw, s);
+    launch_flow_next<T>(B.t3, v, B.logq, S, N, growth ? 1 : 0, std::log1p(-2.0 * fp->tau * fp->alpha), B.ctrl, pn,
+                        s);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if ((rc = finish(ctx))) return rc;
+  return worst;
+}
+
 // average device time of each Gibbs-product kernel of one X half-step over nb
 // fields (grids; points: nb = 1), with HIP events around `reps` back-to-back
 // launches of that kernel alone
@@ -831,7 +993,7 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
   launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, P.N, 0, s);
   launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
   if (P.geom == UOT_GEOM_GRID)
-    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, 1, s);
+    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, 1, P.cost, s);
   launch_init_pot<T>(v, B.logdy, nullptr, B.wv, nb * P.M, P.M, B.ctrl, 0, s);
   launch_init_pot<T>(nullptr, B.logdx, B.t3, nullptr, nb * P.N, P.N, B.ctrl, 0, s);   // u = 0 in t3
   EpiArgs<T> ep = prox_epi<T>(B.t3, B.wu, B.logp, B.logdx, nullptr, B.parts, P.N, pb->F1);
@@ -858,7 +1020,8 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
     const T* rows = static_cast<const T*>(pb->geom.x);
     const T* cols = static_cast<const T*>(pb->geom.y);
     ks.push_back([&] {
-      launch_dense_lse<T>(P.dim, P.R[0], rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps, 0, B.ctrl, s);
+      launch_dense_lse<T>(P.dim, P.R[0], rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps, 0, B.ctrl,
+                          P.cost, s);
     });
     ks.push_back([&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[0], P.N, 0, B.ctrl, ep, s); });
   }
@@ -1308,6 +1471,36 @@ int uot_solve_mass(uot_ctx* ctx, const uot_problem* pb, const uot_div* F3, doubl
                          res, 1, &m, log_z);
 }
 
+int uot_flow_workspace_size(const uot_flow_problem* fp, size_t* bytes) {
+  if (!bytes) return fail(UOT_E_INVALID, "NULL argument");
+  FlowDivs d;
+  int rc = validate_flow(fp, d);
+  if (rc) return rc;
+  Plan P;
+  size_t o_u = 0;
+  if ((rc = flow_plan(P, fp, kMaxStages + 1, 0, 0.0, o_u))) return rc;
+  *bytes = P.total;
+  return UOT_OK;
+}
+
+int uot_flow(uot_ctx* ctx, const uot_flow_problem* fp, const uot_params* pr, int32_t n_steps, void* dens, void* v,
+             void* ws, size_t wsb, uot_result* steps) {
+  if (!ctx) return fail(UOT_E_INVALID, "ctx is required");
+  FlowDivs d;
+  int rc = validate_flow(fp, d);
+  if (rc) return rc;
+  if ((rc = validate_params(pr))) return rc;
+  if (n_steps < 0) return fail(UOT_E_INVALID, "n_steps must be >= 0");
+  if (pr->grid_kernel == 4) return fail(UOT_E_UNSUPPORTED, "flows run with grid_kernel 0 .. 3");
+  if (fp->dtype == UOT_F32)
+    return flow_t<float>(ctx, fp, d, pr, n_steps, static_cast<float*>(dens), static_cast<float*>(v),
+                         static_cast<char*>(ws), wsb, steps);
+  if (fp->dtype == UOT_F64)
+    return flow_t<double>(ctx, fp, d, pr, n_steps, static_cast<double*>(dens), static_cast<double*>(v),
+                          static_cast<char*>(ws), wsb, steps);
+  return fail(UOT_E_INVALID, "dtype must be UOT_F32 or UOT_F64");
+}
+
 int uot_half_step(uot_ctx* ctx, const uot_problem* pb, double eps, int side, const void* pot_in, void* pot_io,
                   void* lse_out, double* residual, void* ws, size_t wsb) {
   if (!ctx) return fail(UOT_E_INVALID, "ctx is required");
@@ -1427,6 +1620,8 @@ int uot_barycenter(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* p
   if ((rc = check_div(pb->F2, "F2"))) return rc;
   if (pb->F2.kind == UOT_DIV_RG && !std::isfinite(pb->F2.beta))
     return fail(UOT_E_UNSUPPORTED, "a range barycentre needs a finite upper bound beta");
+  if (pb->F2.kind == UOT_DIV_GROWTH)
+    return fail(UOT_E_UNSUPPORTED, "the barycentre side takes =, KL, TV or RG (Table estimatebary)");
   if ((rc = validate_params(pr))) return rc;
   if (pb->dtype == UOT_F32)
     return bary_t<float>(ctx, pb, pr, static_cast<float*>(u), static_cast<float*>(v), static_cast<float*>(logh),

@@ -47,6 +47,48 @@ template <> struct Num<double> {
 };
 
 // ---------------------------------------------------------------------------
+// cos(sqrt(z)) on 0 <= z <= (pi/2)^2 from the Taylor series of cos in
+// z = theta^2, sum_k (-z)^k / (2k)!, in Horner form.  FP32 stops after z^6
+// (remainder z^7/14! < 6.5e-9 at the end of the range), FP64 after z^10
+// (remainder z^11/22! < 1.9e-17).  The WF cost -log cos^2(theta) only needs
+// theta^2, so no square root and no range reduction are taken.
+// ---------------------------------------------------------------------------
+template <typename T> struct CosSqrt;
+template <> struct CosSqrt<float> {
+  static __device__ __forceinline__ float eval(float z) {
+    float r = 1.0f / 479001600.0f;                 // 1/12!
+    r = __builtin_fmaf(r, -z, 1.0f / 3628800.0f);  // 1/10!
+    r = __builtin_fmaf(r, -z, 1.0f / 40320.0f);
+    r = __builtin_fmaf(r, -z, 1.0f / 720.0f);
+    r = __builtin_fmaf(r, -z, 1.0f / 24.0f);
+    r = __builtin_fmaf(r, -z, 0.5f);
+    return __builtin_fmaf(r, -z, 1.0f);
+  }
+};
+template <> struct CosSqrt<double> {
+  static __device__ __forceinline__ double eval(double z) {
+    // 1/(2k)! for k = 10 .. 1
+    constexpr double c[10] = {1.0 / 2432902008176640000.0, 1.0 / 6402373705728000.0, 1.0 / 20922789888000.0,
+                              1.0 / 87178291200.0,         1.0 / 479001600.0,        1.0 / 3628800.0,
+                              1.0 / 40320.0,               1.0 / 720.0,              1.0 / 24.0,
+                              0.5};
+    double r = c[0];
+#pragma unroll
+    for (int k = 1; k < 10; ++k) r = __builtin_fma(r, -z, c[k]);
+    return __builtin_fma(r, -z, 1.0);
+  }
+};
+
+// log2 of the WF kernel entry cos_+^{2/eps}(theta), theta = (pi/2) d / cut:
+// ewf log2 cos(theta) with z = theta^2 = a2 d^2 (a2 = (pi / (2 cut))^2) while
+// d^2 < cut^2; -inf from the cut locus on (the entry is exactly zero)
+template <typename T>
+__device__ __forceinline__ T wf_log2k(T d2, T a2, T cut2, T ewf) {
+  const T cv = CosSqrt<T>::eval(d2 * a2);
+  return (d2 < cut2 && cv > T(0)) ? ewf * Num<T>::log2(cv) : Num<T>::ninf();
+}
+
+// ---------------------------------------------------------------------------
 // running log2-sum-exp2 with a chunked online maximum: the value is
 // m + log2(s).  add<C>() folds C terms with one rescale, so the per-term
 // cost is one max, one subtract, one exp2 and one add.
@@ -146,15 +188,16 @@ struct ResPart {
 // potential eps*log(a) from S = log K(b dy) (natural log), zero absorbed offset.
 // ---------------------------------------------------------------------------
 struct DivDev {
-  int kind;          // 0 =, 1 KL, 2 TV, 3 RG
+  int kind;          // 0 =, 1 KL, 2 TV, 3 RG, 4 growth
   int has_lo, has_hi;
   int pad;
-  double lam, log_alpha, log_beta;
+  double lam, log_alpha, log_beta;   // growth: log_alpha = log(1 - lam)
 };
 
 template <typename T>
 __device__ __forceinline__ T proxdiv_pot(const DivDev& F, T logp, T S, T eps) {
-  const T d = logp - S;                 // -inf where p = 0
+  // log(p/s): -inf where p = 0 (also where s = 0: 0/0 = 0), +inf where only s = 0
+  const T d = (logp == Num<T>::ninf()) ? Num<T>::ninf() : logp - S;
   switch (F.kind) {
     case 0:
       return eps * d;
@@ -166,12 +209,24 @@ __device__ __forceinline__ T proxdiv_pot(const DivDev& F, T logp, T S, T eps) {
       const T lam = T(F.lam);
       return Num<T>::fmin(Num<T>::fmax(eps * d, -lam), lam);
     }
-    default: {
+    case 3: {
       const T lo = F.has_lo ? eps * (T(F.log_alpha) + d) : Num<T>::ninf();
       const T hi = F.has_hi ? eps * (T(F.log_beta) + d) : Num<T>::pinf();
       return Num<T>::fmin(hi, Num<T>::fmax(lo, T(0)));
     }
+    default: {
+      // growth functional (tumour example of the WF gradient flows): the
+      // constant branch -log kappa below the switch, the KL(1)-like branch
+      // eps (log p - log s) / (1 + eps) above it; p is the density cap
+      return Num<T>::fmin(-T(F.log_alpha), (eps / (T(1) + eps)) * d);
+    }
   }
+}
+
+// relative residual num / den with 0/0 = 0 (a marginal that vanishes before
+// and after the update) and +inf for mass that vanished
+__device__ __forceinline__ double res_ratio(double num, double den) {
+  return den > 0.0 ? num / den : (num > 0.0 ? __builtin_inf() : 0.0);
 }
 
 // ---------------------------------------------------------------------------

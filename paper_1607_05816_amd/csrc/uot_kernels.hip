@@ -39,7 +39,8 @@ __global__ void k_log(const T* __restrict__ src, T* __restrict__ dst, int64_t n,
   dst[i] = (s > T(0)) ? Num<T>::log(s) : (zero_is_ninf ? Num<T>::ninf() : Num<T>::log(s));
 }
 
-// pot = v0 (or 0), w = (pot/eps + logd) * log2(e)
+// pot = v0 (or 0), w = (pot/eps + logd) * log2(e); a potential of +inf (left by
+// a vanishing product: that point's row of the plan is zero) gives w = -inf
 template <typename T>
 __global__ void k_init_pot(const T* __restrict__ v0, const T* __restrict__ logd, T* __restrict__ pot,
                            T* __restrict__ w, int64_t n, int64_t size, const Ctrl* __restrict__ c,
@@ -49,18 +50,27 @@ __global__ void k_init_pot(const T* __restrict__ v0, const T* __restrict__ logd,
   const T eps = T(c->eps[which_eps & 1]);
   T p = v0 ? v0[i] : T(0);
   if (pot) pot[i] = p;
-  if (w) w[i] = (p / eps + logd[i % size]) * T(kLog2e);
+  if (w) w[i] = (p == Num<T>::pinf()) ? Num<T>::ninf() : (p / eps + logd[i % size]) * T(kLog2e);
 }
 
-// g tables of one grid axis for every eps stage: tab[s][k] = -((k-(n-1)) h)^2 / eps_s * log2(e)
+// g tables of one grid axis for every eps stage, tab[s][k] = log2 of the 1-D
+// kernel at offset d = (k - (n-1)) h:  -d^2 / eps_s log2(e) (squared
+// Euclidean cost), or (2 / eps_s) log2 cos((pi/2) |d| / cut) for |d| < cut and
+// -inf beyond (WF cost, 1-D grids)
 template <typename T>
-__global__ void k_gtab(T* __restrict__ tab, int n, double h, const Ctrl* __restrict__ c, int nst) {
+__global__ void k_gtab(T* __restrict__ tab, int n, double h, const Ctrl* __restrict__ c, int nst, CostArgs cost) {
   const int len = 2 * n - 1;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)len * nst) return;
   const int s = (int)(t / len), k = (int)(t % len);
   const double d = double(k - (n - 1)) * h;
-  tab[t] = T(-(d * d) / c->eps_tab[s] * kLog2e);
+  if (cost.kind == 1) {
+    const double ad = ::fabs(d);
+    tab[t] = ad < cost.cut ? T(2.0 / c->eps_tab[s] * ::log2(::cos(0.5 * M_PI * ad / cost.cut)))
+                           : Num<T>::ninf();
+  } else {
+    tab[t] = T(-(d * d) / c->eps_tab[s] * kLog2e);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -110,9 +120,14 @@ __device__ __forceinline__ void epi_apply(int64_t e, T S2, const EpiIn<T>& x, co
   const T ld = x.ld;
   const T uo = x.uo;
   const T un = proxdiv_pot<T>(ep.F, x.lp, S, eps);
+  // a vanishing product (K b = 0 here, possible with exact zeros of K): the
+  // row of the plan is zero whatever the potential, so the point carries no
+  // marginal mass and enters the next product as -inf
+  const bool vanish = Sraw == Num<T>::ninf();
   ep.pot[e] = un;
-  if (ep.wnext) ep.wnext[e] = (un / eps_w + ld) * T(kLog2e);
+  if (ep.wnext) ep.wnext[e] = vanish ? Num<T>::ninf() : (un / eps_w + ld) * T(kLog2e);
   if (ep.lse_out) ep.lse_out[e] = S;
+  if (vanish) return;
   if (ep.part) {
     if (un == Num<T>::ninf()) {
       if (uo != Num<T>::ninf()) ra.add((S + uo / eps + ld) * T(kLog2e), T(0), T(1));
@@ -243,7 +258,7 @@ __device__ __forceinline__ void ctl_reduce_finish(Ctrl* c, const CtrlSnap& snap,
   __syncthreads();   // the block's own reductions before this one are complete
   block_res_reduce<float>(m, den, num, &tot);
   __syncthreads();
-  if (threadIdx.x == 0) control_finish(c, snap, double(tot.num) / double(tot.den), hist, par);
+  if (threadIdx.x == 0) control_finish(c, snap, res_ratio(double(tot.num), double(tot.den)), hist, par);
 }
 
 // merge the per-wave partial LSEs of a block (4 waves split the taps); the
@@ -351,10 +366,13 @@ __global__ __launch_bounds__(kBlock) void k_grid_strided(const T* __restrict__ i
 // the stage's table; the 4 waves split the taps j.
 // grid = (ceil(n / (64 RI)), A_lo, A_hi) with a = blockIdx.z * gridDim.y + blockIdx.y
 // ---------------------------------------------------------------------------
+// taps j with |i - j| >= band are exact zeros of the kernel (a cut locus; band
+// = n otherwise) and are skipped: a block reads only the taps within band of
+// its outputs
 template <typename T, int RI>
 __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in, int n, int64_t A,
                                                          const T* __restrict__ gtab, int side,
-                                                         const Ctrl* __restrict__ c, EpiArgs<T> ep) {
+                                                         const Ctrl* __restrict__ c, EpiArgs<T> ep, int band) {
   // block 0 of a launch that hosts the control step: partials loaded first
   const bool hosting = ep.host_ctl != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0;
   const int par = par_of(side);
@@ -384,9 +402,13 @@ __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in
     const int i = (blockIdx.x * RI + r) * 64 + lane;
     ii[r] = (i < n ? i : n - 1) + (n - 1);          // index of g[i - 0] in the LDS table
   }
-  const int jq = (n + 3) >> 2;
-  const int j0 = wv * jq;
-  const int j1 = (j0 + jq < n) ? j0 + jq : n;
+  const int o0 = blockIdx.x * RI * 64;
+  const int o1 = (o0 + RI * 64 < n) ? o0 + RI * 64 : n;
+  const int ta = (o0 - band + 1 > 0) ? o0 - band + 1 : 0;
+  const int tb = (o1 - 1 + band < n) ? o1 - 1 + band : n;
+  const int jq = (tb - ta + 3) >> 2;
+  const int j0 = ta + wv * jq;
+  const int j1 = (j0 + jq < tb) ? j0 + jq : tb;
   Lse2<T> acc[RI];
 #pragma unroll
   for (int r = 0; r < RI; ++r) acc[r].init();
@@ -439,20 +461,64 @@ __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in
 
 // ---------------------------------------------------------------------------
 // dense point-cloud product: partial LSE over one column split.
-//   part[split][i] = (m, s) with  m + log2 s = LSE2_{j in split}( w_j - sc |x_i - y_j|^2 )
+//   part[split][i] = (m, s) with  m + log2 s = LSE2_{j in split}( w_j + log2 K_ij )
 // rows: xr (DIM x Nr), columns: yc (DIM x Mc) and w (Mc, log2 units).
+// COST 0: log2 K = -|x_i - y_j|^2 log2(e) / eps.
+// COST 1: the WF cost with cut locus, log2 K = (2/eps) log2 cos((pi/2) d / cut)
+//         for d < cut and -inf beyond (wf_log2k).  K then has exact zeros:
+//         each block bounds its rows and every 256-column chunk by boxes and
+//         skips a chunk whose box lies at distance >= cut from the rows' box
+//         (every entry of that tile is zero; the skip is block-uniform).
 // grid = (ceil(Nr / (256 R)), splits)
 // ---------------------------------------------------------------------------
-template <typename T, int DIM, int R>
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = Num<T>::fmin(v, __shfl_xor(v, o));
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = Num<T>::fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// bounding box of the points a block's threads hold (invalid ones pass
+// lo = +inf, hi = -inf); every thread receives it.  Uses bx[4][2 DIM].
+template <typename T, int DIM>
+__device__ __forceinline__ void block_box(const T (&lo)[3], const T (&hi)[3], T (*bx)[6], T (&blo)[3],
+                                          T (&bhi)[3]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const T a = wave_min<T>(lo[d]), b = wave_max<T>(hi[d]);
+    if (lane == 0) {
+      bx[wv][2 * d] = a;
+      bx[wv][2 * d + 1] = b;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    blo[d] = Num<T>::fmin(Num<T>::fmin(bx[0][2 * d], bx[1][2 * d]), Num<T>::fmin(bx[2][2 * d], bx[3][2 * d]));
+    bhi[d] = Num<T>::fmax(Num<T>::fmax(bx[0][2 * d + 1], bx[1][2 * d + 1]),
+                          Num<T>::fmax(bx[2][2 * d + 1], bx[3][2 * d + 1]));
+  }
+}
+
+template <typename T, int DIM, int R, int COST>
 __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, int64_t Nr,
                                                        const T* __restrict__ yc, const T* __restrict__ w,
                                                        int64_t Mc, int64_t cols_per_split,
                                                        T* __restrict__ pm, T* __restrict__ ps, int side,
-                                                       const Ctrl* __restrict__ c) {
+                                                       const Ctrl* __restrict__ c, T a2, T cut2) {
   if (skip_side(c, side)) return;
   using V4 = typename Vec4<T>::type;
   __shared__ V4 tile[kBlock];
+  __shared__ T rbx[4][6], cbx[4][6];
   const T sc = T(kLog2e / eps_of(c, side));
+  const T ewf = T(2.0 / eps_of(c, side));
   T xi[R][DIM];
   int64_t rows[R];
 #pragma unroll
@@ -461,6 +527,22 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
     const int64_t rr = rows[r] < Nr ? rows[r] : 0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) xi[r][d] = xr[d * Nr + rr];
+  }
+  T rlo[3], rhi[3];
+  if (COST == 1) {
+    T lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      lo[d] = Num<T>::pinf();
+      hi[d] = Num<T>::ninf();
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (rows[r] < Nr) {
+          lo[d] = Num<T>::fmin(lo[d], xi[r][d]);
+          hi[d] = Num<T>::fmax(hi[d], xi[r][d]);
+        }
+    }
+    block_box<T, DIM>(lo, hi, rbx, rlo, rhi);
   }
   Lse2<T> acc[R];
 #pragma unroll
@@ -481,7 +563,29 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
     }
     __syncthreads();
     tile[threadIdx.x] = rec;
-    __syncthreads();
+    if (COST == 1) {
+      // box of the chunk's columns that carry mass
+      const bool live = rec.w != Num<T>::ninf();
+      const T cx[3] = {rec.x, rec.y, rec.z};
+      T lo[3], hi[3], clo[3], chi[3];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        lo[d] = live ? cx[d] : Num<T>::pinf();
+        hi[d] = live ? cx[d] : Num<T>::ninf();
+      }
+      block_box<T, DIM>(lo, hi, cbx, clo, chi);   // includes the barrier that publishes the tile
+      T gap2 = T(0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const T g = Num<T>::fmax(Num<T>::fmax(clo[d] - rhi[d], rlo[d] - chi[d]), T(0));
+        gap2 = Num<T>::fma(g, g, gap2);
+      }
+      // every entry of the tile is beyond the cut (an empty chunk gives nan
+      // or +inf here and is skipped as well)
+      if (!(gap2 < cut2)) continue;
+    } else {
+      __syncthreads();
+    }
     const int64_t rem = ce - c0;
     const int cnt = rem < kBlock ? (int)rem : kBlock;
     for (int jj = 0; jj < cnt; jj += kChunk) {
@@ -497,7 +601,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
           T cst = d0 * d0;
           if (DIM > 1) { T d1 = xi[r][1] - q[k].y; cst = Num<T>::fma(d1, d1, cst); }
           if (DIM > 2) { T d2 = xi[r][2] - q[k].z; cst = Num<T>::fma(d2, d2, cst); }
-          t[k] = Num<T>::fma(-sc, cst, q[k].w);
+          if (COST == 1) t[k] = q[k].w + wf_log2k<T>(cst, a2, cut2, ewf);
+          else t[k] = Num<T>::fma(-sc, cst, q[k].w);
         }
         acc[r].template add<kChunk>(t);
       }
@@ -550,7 +655,7 @@ __device__ void control_step(Ctrl* __restrict__ c, const ResPart* __restrict__ p
   for (int f = threadIdx.x; f < nfields; f += kBlock) {
     float m = -__builtin_inff(), den = 0.f, num = 0.f;
     for (int k = f * per; k < (f + 1) * per; ++k) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
-    const float rf = num / den;
+    const float rf = float(res_ratio(double(num), double(den)));
     rmax = (rf != rf || rmax != rmax) ? rf : (rf > rmax ? rf : rmax);
   }
   smax[threadIdx.x] = rmax;
@@ -594,12 +699,24 @@ __global__ void k_res_reduce(const ResPart* __restrict__ part, int nparts, doubl
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double m = -__builtin_inf(), den = 0.0, num = 0.0;
   for (int k = 0; k < nparts; ++k) res_merge<double>(m, den, num, part[k].m, part[k].den, part[k].num);
-  out[0] = num / den;
+  out[0] = res_ratio(num, den);
 }
 
 // continue a stopped solve with a new tolerance (the second phase of a
 // mixed-precision grid solve): clear the stop and skip flags, keep the
 // iteration count, residual history and eps slots
+// after a stopped solve, slot 0 is made valid again for one more product at
+// the eps of the last iteration (a stopped solve marks its slots skipped)
+__global__ void k_ctrl_post(Ctrl* __restrict__ c) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t l = c->iter > 0 ? c->iter - 1 : 0;
+  int64_t sn = c->iters_per_stage > 0 ? l / c->iters_per_stage : c->n_stages;
+  if (sn > c->n_stages) sn = c->n_stages;
+  c->stage[0] = (int)sn;
+  c->eps[0] = c->eps_tab[sn];
+  c->skip[0] = 0;
+}
+
 __global__ void k_ctrl_resume(Ctrl* __restrict__ c, double tol) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   c->stop = 0;
@@ -768,8 +885,71 @@ __global__ __launch_bounds__(kBlock) void k_bary_combine(const T* __restrict__ T
     const T S = T2[k * size + j] * T(kLn2);
     const T vn = proxdiv_pot<T>(F2, logh, S, eps);
     v[k * size + j] = vn;
-    w[k * size + j] = (vn / eps_w + ld) * T(kLog2e);
+    w[k * size + j] = (S == Num<T>::ninf()) ? Num<T>::ninf() : (vn / eps_w + ld) * T(kLog2e);
   }
+}
+
+// ---------------------------------------------------------------------------
+// gradient flows (Sec. 5.3)
+// ---------------------------------------------------------------------------
+// Y update of the multi-species growth step: the joint proxdiv of the growth
+// functional (F, kind 4, cap q) at the sum of the species' products,
+// L = log sum_k e^{T_k}; the potential v is the same for every species.
+// T2: nm x size in log2 units.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_growth_combine(const T* __restrict__ T2, int nm, int64_t size,
+                                                            DivDev F, const T* __restrict__ logq,
+                                                            const T* __restrict__ logdy, T* __restrict__ v,
+                                                            T* __restrict__ w, const Ctrl* __restrict__ c, int side) {
+  if (skip_side(c, side)) return;
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= size) return;
+  const T eps = T(eps_of(c, side));
+  const T eps_w = T(eps_next_of(c, side));
+  Lse2<T> a;
+  a.init();
+  for (int k = 0; k < nm; ++k) {
+    T t[1] = {T2[k * size + j]};
+    a.template add<1>(t);
+  }
+  const T vn = proxdiv_pot<T>(F, logq[j], a.result() * T(kLn2), eps);
+  const T wn = (vn / eps_w + logdy[j]) * T(kLog2e);
+  for (int k = 0; k < nm; ++k) {
+    v[k * size + j] = vn;
+    w[k * size + j] = (T2[k * size + j] == Num<T>::ninf()) ? Num<T>::ninf() : wn;
+  }
+}
+
+// next densities of a gradient-flow step from the final potentials: the
+// second marginals y_k = e^{T_k + v_k/eps} of the couplings (T2: log2 of
+// K^T(a_k dx)), as they are (heat, crowd) or, for growth, the inner
+// minimiser of the growth functional, y_k / max(kappa, sum_k y_k / q)
+template <typename T>
+__device__ __forceinline__ T flow_logy(const T* __restrict__ T2, const T* __restrict__ v, int64_t e, T eps) {
+  const T t = T2[e];
+  return t == Num<T>::ninf() ? Num<T>::ninf() : t * T(kLn2) + v[e] / eps;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_flow_next(const T* __restrict__ T2, const T* __restrict__ v,
+                                                       const T* __restrict__ logq, int nm, int64_t size, int growth,
+                                                       double log_kappa, const Ctrl* __restrict__ c,
+                                                       T* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= size) return;
+  const T eps = T(c->eps[0]);
+  T den = T(0);
+  if (growth) {
+    T m = Num<T>::ninf();
+    for (int k = 0; k < nm; ++k) m = Num<T>::fmax(m, flow_logy<T>(T2, v, k * size + j, eps));
+    T sum = T(0);
+    if (m != Num<T>::ninf())
+      for (int k = 0; k < nm; ++k) sum += Num<T>::exp(flow_logy<T>(T2, v, k * size + j, eps) - m);
+    const T L = m == Num<T>::ninf() ? m : m + Num<T>::log(sum);
+    const T lq = logq[j];
+    den = lq == Num<T>::ninf() ? Num<T>::pinf() : Num<T>::fmax(T(log_kappa), L - lq);
+  }
+  for (int k = 0; k < nm; ++k) out[k * size + j] = Num<T>::exp(flow_logy<T>(T2, v, k * size + j, eps) - den);
 }
 
 // ---------------------------------------------------------------------------
@@ -792,7 +972,8 @@ __global__ __launch_bounds__(kBlock) void k_obj_side(const T* __restrict__ pot, 
     const double s = double(S[i]) * kLn2;   // S arrives in log2 units
     const double pp = double(p[i]);
     const double dd = double(d[i]);
-    const double pi = (u == -__builtin_inf()) ? 0.0 : ::exp(u / eps + s);
+    // no mass where the potential or the product vanishes (0 times any potential)
+    const double pi = (u == -__builtin_inf() || s == -__builtin_inf()) ? 0.0 : ::exp(u / eps + s);
     if (pi_out) pi_out[i] = T(pi);
     a0 = dd * pi;
     a1 = (pi > 0) ? dd * u * pi : 0.0;
@@ -808,6 +989,13 @@ __global__ __launch_bounds__(kBlock) void k_obj_side(const T* __restrict__ pot, 
         a2 = dd * lam * ::fabs(pi - pp);
         a3 = (w > lam * (1 + 1e-6)) ? __builtin_inf() : dd * pp * ::fmax(w, -lam);
         break;
+      case 4: {  // growth, cap pp: F = s log kappa below kappa pp, s log(s/pp) - s + kappa pp above
+        const double kap = 1.0 - lam;
+        if (pp == 0.0) a2 = pi > 0 ? __builtin_inf() : 0.0;
+        else a2 = dd * (pi <= kap * pp ? pi * ::log(kap) : pi * ::log(pi / pp) - pi + kap * pp);
+        a3 = dd * pp * ::fmax(::exp(w) - kap, 0.0);
+        break;
+      }
       default:  // = / RG: indicator terms are not finite-valued; gap reported as NaN by the host
         a2 = 0.0;
         a3 = 0.0;
@@ -859,7 +1047,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_exp2(const T* __restrict__ a, co
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_dense_cost(const T* __restrict__ xr, int64_t Nr,
                                                         const T* __restrict__ yc, const T* __restrict__ w,
-                                                        int64_t Mc, double eps, T* __restrict__ out) {
+                                                        int64_t Mc, double eps, T* __restrict__ out, CostArgs cost) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= Nr) return;
   const double sc = kLog2e / eps;
@@ -871,6 +1059,11 @@ __global__ __launch_bounds__(kBlock) void k_dense_cost(const T* __restrict__ xr,
     for (int d = 0; d < DIM; ++d) {
       const double dd = xi[d] - double(yc[d * Mc + j]);
       cst += dd * dd;
+    }
+    if (cost.kind == 1) {
+      // WF: c = -2 log cos((pi/2) d / cut); no mass beyond the cut
+      if (cst >= cost.cut * cost.cut) continue;
+      cst = -2.0 * ::log(::cos(0.5 * M_PI * ::sqrt(cst) / cost.cut));
     }
     const double t = double(w[j]) - sc * cst;
     if (t == -__builtin_inf() || cst == 0.0) continue;
@@ -887,13 +1080,17 @@ __global__ __launch_bounds__(kBlock) void k_dense_cost(const T* __restrict__ xr,
 
 // grid cost table: tab[k] = g_s[k] + log2(C1(k)) at the current X stage (-inf at 0 offset)
 template <typename T>
-__global__ void k_gtab_cost(T* __restrict__ tab, int n, double h, double eps) {
+__global__ void k_gtab_cost(T* __restrict__ tab, int n, double h, double eps, CostArgs cost) {
   const int len = 2 * n - 1;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= len) return;
   const double d = double(k - (n - 1)) * h;
-  const double cst = d * d;
-  tab[k] = (cst == 0.0) ? T(-__builtin_inf()) : T(-cst / eps * kLog2e + ::log2(cst));
+  double cst = d * d;
+  if (cost.kind == 1) {
+    const double ad = ::fabs(d);
+    cst = ad < cost.cut ? -2.0 * ::log(::cos(0.5 * M_PI * ad / cost.cut)) : __builtin_inf();
+  }
+  tab[k] = (cst == 0.0 || cst == __builtin_inf()) ? T(-__builtin_inf()) : T(-cst / eps * kLog2e + ::log2(cst));
 }
 
 // ---------------------------------------------------------------------------
@@ -915,14 +1112,14 @@ void launch_init_pot(const T* v0, const T* logd, T* pot, T* w, int64_t n, int64_
 }
 
 template <typename T>
-void launch_gtab(T* tab, int n, double h, const Ctrl* c, int nst, hipStream_t s) {
+void launch_gtab(T* tab, int n, double h, const Ctrl* c, int nst, const CostArgs& cost, hipStream_t s) {
   const int64_t tot = (int64_t)(2 * n - 1) * nst;
-  hipLaunchKernelGGL(k_gtab<T>, dim3(ceil_div(tot, kBlock)), dim3(kBlock), 0, s, tab, n, h, c, nst);
+  hipLaunchKernelGGL(k_gtab<T>, dim3(ceil_div(tot, kBlock)), dim3(kBlock), 0, s, tab, n, h, c, nst, cost);
 }
 
 template <typename T>
-void launch_gtab_cost(T* tab, int n, double h, double eps, hipStream_t s) {
-  hipLaunchKernelGGL(k_gtab_cost<T>, dim3(ceil_div(2 * n - 1, kBlock)), dim3(kBlock), 0, s, tab, n, h, eps);
+void launch_gtab_cost(T* tab, int n, double h, double eps, const CostArgs& cost, hipStream_t s) {
+  hipLaunchKernelGGL(k_gtab_cost<T>, dim3(ceil_div(2 * n - 1, kBlock)), dim3(kBlock), 0, s, tab, n, h, eps, cost);
 }
 
 // outputs per lane: 2 when one output per lane would already give more than
@@ -974,26 +1171,37 @@ void launch_grid_strided(const T* in, int64_t A, int n, int64_t B, const T* gtab
 
 template <typename T>
 void launch_grid_contig(const T* in, int64_t A, int n, const T* gtab, int side, const Ctrl* c,
-                        const EpiArgs<T>& ep, hipStream_t s) {
+                        const EpiArgs<T>& ep, int band, hipStream_t s) {
   const int ri = contig_ri(n, A);
   unsigned gx, gy, gz;
   contig_grid(n, A, ri, gx, gy, gz);
   const size_t lds = (size_t)(2 * n - 1) * sizeof(T);
-  if (ri == 2) hipLaunchKernelGGL((k_grid_contig<T, 2>), dim3(gx, gy, gz), dim3(kBlock), lds, s, in, n, A, gtab, side, c, ep);
-  else hipLaunchKernelGGL((k_grid_contig<T, 1>), dim3(gx, gy, gz), dim3(kBlock), lds, s, in, n, A, gtab, side, c, ep);
+  const int bd = (band < 1 || band > n) ? n : band;
+  if (ri == 2)
+    hipLaunchKernelGGL((k_grid_contig<T, 2>), dim3(gx, gy, gz), dim3(kBlock), lds, s, in, n, A, gtab, side, c, ep, bd);
+  else
+    hipLaunchKernelGGL((k_grid_contig<T, 1>), dim3(gx, gy, gz), dim3(kBlock), lds, s, in, n, A, gtab, side, c, ep, bd);
 }
 
 template <typename T, int DIM, int R>
 static void launch_dense_lse_t(const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, int nsplit,
-                               int64_t cps, T* pm, T* ps, int side, const Ctrl* c, hipStream_t s) {
+                               int64_t cps, T* pm, T* ps, int side, const Ctrl* c, const CostArgs& cost,
+                               hipStream_t s) {
   dim3 grid(ceil_div(Nr, kBlock * R), (unsigned)nsplit);
-  hipLaunchKernelGGL((k_dense_lse<T, DIM, R>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side, c);
+  if (cost.kind == 1) {
+    const T a2 = T(0.25 * M_PI * M_PI / (cost.cut * cost.cut)), cut2 = T(cost.cut * cost.cut);
+    hipLaunchKernelGGL((k_dense_lse<T, DIM, R, 1>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side,
+                       c, a2, cut2);
+  } else {
+    hipLaunchKernelGGL((k_dense_lse<T, DIM, R, 0>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side,
+                       c, T(0), T(0));
+  }
 }
 
 template <typename T>
 void launch_dense_lse(int dim, int R, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, int nsplit,
-                      int64_t cps, T* pm, T* ps, int side, const Ctrl* c, hipStream_t s) {
-#define UOT_DL(D, RR) launch_dense_lse_t<T, D, RR>(xr, Nr, yc, w, Mc, nsplit, cps, pm, ps, side, c, s)
+                      int64_t cps, T* pm, T* ps, int side, const Ctrl* c, const CostArgs& cost, hipStream_t s) {
+#define UOT_DL(D, RR) launch_dense_lse_t<T, D, RR>(xr, Nr, yc, w, Mc, nsplit, cps, pm, ps, side, c, cost, s)
   if (R == 1) {
     if (dim == 1) UOT_DL(1, 1); else if (dim == 2) UOT_DL(2, 1); else UOT_DL(3, 1);
   } else if (R == 2) {
@@ -1021,6 +1229,30 @@ void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t
 void launch_ctrl_resume(Ctrl* c, double tol, hipStream_t s) {
   hipLaunchKernelGGL(k_ctrl_resume, dim3(1), dim3(64), 0, s, c, tol);
 }
+
+void launch_ctrl_post(Ctrl* c, hipStream_t s) { hipLaunchKernelGGL(k_ctrl_post, dim3(1), dim3(64), 0, s, c); }
+
+template <typename T>
+void launch_growth_combine(const T* T2, int nm, int64_t size, const DivDev& F, const T* logq, const T* logdy, T* v,
+                           T* w, const Ctrl* c, int side, hipStream_t s) {
+  hipLaunchKernelGGL(k_growth_combine<T>, dim3(ceil_div(size, kBlock)), dim3(kBlock), 0, s, T2, nm, size, F, logq,
+                     logdy, v, w, c, side);
+}
+template void launch_growth_combine<float>(const float*, int, int64_t, const DivDev&, const float*, const float*,
+                                           float*, float*, const Ctrl*, int, hipStream_t);
+template void launch_growth_combine<double>(const double*, int, int64_t, const DivDev&, const double*,
+                                            const double*, double*, double*, const Ctrl*, int, hipStream_t);
+
+template <typename T>
+void launch_flow_next(const T* T2, const T* v, const T* logq, int nm, int64_t size, int growth, double log_kappa,
+                      const Ctrl* c, T* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_flow_next<T>, dim3(ceil_div(size, kBlock)), dim3(kBlock), 0, s, T2, v, logq, nm, size, growth,
+                     log_kappa, c, out);
+}
+template void launch_flow_next<float>(const float*, const float*, const float*, int, int64_t, int, double,
+                                      const Ctrl*, float*, hipStream_t);
+template void launch_flow_next<double>(const double*, const double*, const double*, int, int64_t, int, double,
+                                       const Ctrl*, double*, hipStream_t);
 
 template <typename T>
 void launch_mass_update(Ctrl* c, const T* mass_m, const T* mass_s, int nparts, const DivDev& F3, double log_m0, int par,
@@ -1060,26 +1292,27 @@ int launch_sum_exp2(const T* a, const T* b, int64_t n, double* part, hipStream_t
 
 template <typename T>
 void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, double eps, T* out,
-                       hipStream_t s) {
+                       const CostArgs& cost, hipStream_t s) {
   dim3 grid(ceil_div(Nr, kBlock));
-  if (dim == 1) hipLaunchKernelGGL((k_dense_cost<T, 1>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, eps, out);
-  else if (dim == 2) hipLaunchKernelGGL((k_dense_cost<T, 2>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, eps, out);
-  else hipLaunchKernelGGL((k_dense_cost<T, 3>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, eps, out);
+  if (dim == 1) hipLaunchKernelGGL((k_dense_cost<T, 1>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, eps, out, cost);
+  else if (dim == 2)
+    hipLaunchKernelGGL((k_dense_cost<T, 2>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, eps, out, cost);
+  else hipLaunchKernelGGL((k_dense_cost<T, 3>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, eps, out, cost);
 }
 
 #define UOT_INSTANTIATE(T)                                                                                         \
   template void launch_log<T>(const T*, T*, int64_t, int, hipStream_t);                                           \
   template void launch_init_pot<T>(const T*, const T*, T*, T*, int64_t, int64_t, const Ctrl*, int, hipStream_t);  \
-  template void launch_gtab<T>(T*, int, double, const Ctrl*, int, hipStream_t);                                   \
-  template void launch_gtab_cost<T>(T*, int, double, double, hipStream_t);                                        \
+  template void launch_gtab<T>(T*, int, double, const Ctrl*, int, const CostArgs&, hipStream_t);                  \
+  template void launch_gtab_cost<T>(T*, int, double, double, const CostArgs&, hipStream_t);                       \
   template int grid_strided_parts<T>(int, int64_t, int64_t);                                                      \
   template int grid_contig_parts<T>(int, int64_t);                                                                \
   template void launch_grid_strided<T>(const T*, int64_t, int, int64_t, const T*, int, const Ctrl*,              \
                                        const EpiArgs<T>&, hipStream_t);                                          \
   template void launch_grid_contig<T>(const T*, int64_t, int, const T*, int, const Ctrl*, const EpiArgs<T>&,     \
-                                      hipStream_t);                                                               \
+                                      int, hipStream_t);                                                          \
   template void launch_dense_lse<T>(int, int, const T*, int64_t, const T*, const T*, int64_t, int, int64_t, T*,  \
-                                    T*, int, const Ctrl*, hipStream_t);                                           \
+                                    T*, int, const Ctrl*, const CostArgs&, hipStream_t);                          \
   template void launch_dense_epi<T>(const T*, const T*, int, int64_t, int, const Ctrl*, const EpiArgs<T>&,       \
                                     hipStream_t);                                                                 \
   template void launch_bary_combine<T>(const T*, int, int64_t, const BaryW&, double, const DivDev&, const T*,    \
@@ -1087,7 +1320,8 @@ void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w
   template int launch_obj_side<T>(const T*, const T*, const T*, const T*, int64_t, double, const DivDev&, T*,    \
                                   double*, hipStream_t);                                                          \
   template int launch_sum_exp2<T>(const T*, const T*, int64_t, double*, hipStream_t);                            \
-  template void launch_dense_cost<T>(int, const T*, int64_t, const T*, const T*, int64_t, double, T*, hipStream_t);
+  template void launch_dense_cost<T>(int, const T*, int64_t, const T*, const T*, int64_t, double, T*,             \
+                                     const CostArgs&, hipStream_t);
 
 UOT_INSTANTIATE(float)
 UOT_INSTANTIATE(double)
@@ -1245,7 +1479,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_control(Ctrl* __restrict__ c, 
   bc->yskip[b] = 0;
   float m = -__builtin_inff(), den = 0.f, num = 0.f;
   for (int k = pstart[b]; k < pstart[b + 1]; ++k) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
-  const double r = double(num) / double(den);
+  const double r = res_ratio(double(num), double(den));
   const int64_t l = bc->iters[b];
   bc->res[b] = r;
   bc->iters[b] = l + 1;

@@ -10,6 +10,13 @@ namespace uot {
 
 enum EpiMode { EPI_RAW = 0, EPI_PROX = 1 };
 
+// cost of a geometry: kind 0 squared Euclidean, 1 WF with cut locus `cut`
+struct CostArgs {
+  int kind;
+  int pad;
+  double cut;
+};
+
 // What the last pass of a Gibbs product does with S2 = log2 of the product.
 //  EPI_RAW : out[e] = S2
 //  EPI_PROX: pot[e] = eps log proxdiv_F(e^S) (old value read first), wnext[e] =
@@ -45,8 +52,9 @@ template <typename T> void launch_log(const T* src, T* dst, int64_t n, int zero_
 template <typename T>
 void launch_init_pot(const T* v0, const T* logd, T* pot, T* w, int64_t n, int64_t size, const Ctrl* c, int which,
                      hipStream_t s);
-template <typename T> void launch_gtab(T* tab, int n, double h, const Ctrl* c, int nst, hipStream_t s);
-template <typename T> void launch_gtab_cost(T* tab, int n, double h, double eps, hipStream_t s);
+template <typename T>
+void launch_gtab(T* tab, int n, double h, const Ctrl* c, int nst, const CostArgs& cost, hipStream_t s);
+template <typename T> void launch_gtab_cost(T* tab, int n, double h, double eps, const CostArgs& cost, hipStream_t s);
 template <typename T> int grid_strided_parts(int n, int64_t A, int64_t B);
 template <typename T> int grid_contig_parts(int n, int64_t A);
 template <typename T>
@@ -54,10 +62,10 @@ void launch_grid_strided(const T* in, int64_t A, int n, int64_t B, const T* gtab
                          const EpiArgs<T>& ep, hipStream_t s);
 template <typename T>
 void launch_grid_contig(const T* in, int64_t A, int n, const T* gtab, int side, const Ctrl* c,
-                        const EpiArgs<T>& ep, hipStream_t s);
+                        const EpiArgs<T>& ep, int band, hipStream_t s);
 template <typename T>
 void launch_dense_lse(int dim, int R, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, int nsplit,
-                      int64_t cps, T* pm, T* ps, int side, const Ctrl* c, hipStream_t s);
+                      int64_t cps, T* pm, T* ps, int side, const Ctrl* c, const CostArgs& cost, hipStream_t s);
 template <typename T>
 void launch_dense_epi(const T* pm, const T* ps, int nsplit, int64_t Nr, int side, const Ctrl* c,
                       const EpiArgs<T>& ep, hipStream_t s);
@@ -65,6 +73,14 @@ void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipS
 void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t s);
 void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s);
 void launch_ctrl_resume(Ctrl* c, double tol, hipStream_t s);
+// slot 0 valid again after a stopped solve (one more product at the last eps)
+void launch_ctrl_post(Ctrl* c, hipStream_t s);
+template <typename T>
+void launch_growth_combine(const T* T2, int nm, int64_t size, const DivDev& F, const T* logq, const T* logdy, T* v,
+                           T* w, const Ctrl* c, int side, hipStream_t s);
+template <typename T>
+void launch_flow_next(const T* T2, const T* v, const T* logq, int nm, int64_t size, int growth, double log_kappa,
+                      const Ctrl* c, T* out, hipStream_t s);
 template <typename T>
 void launch_mass_update(Ctrl* c, const T* mass_m, const T* mass_s, int nparts, const DivDev& F3, double log_m0, int par,
                         hipStream_t s);
@@ -82,7 +98,7 @@ int launch_obj_side(const T* pot, const T* S, const T* p, const T* d, int64_t n,
 template <typename T> int launch_sum_exp2(const T* a, const T* b, int64_t n, double* part, hipStream_t s);
 template <typename T>
 void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, double eps, T* out,
-                       hipStream_t s);
+                       const CostArgs& cost, hipStream_t s);
 
 void launch_probe(int which, float* out, int blocks, int iters, hipStream_t s);
 int grid_tf_parts(int n, int64_t A, int64_t B, bool strided);

@@ -201,3 +201,65 @@ def bary_blobs(seed: int, n_marg: int = 8, n: int = 128, n_blobs: int = 5,
 def pair_blobs(seed: int, n: int = 64) -> GridProblem:
     """One training pair for the warm-start network: two n x n blob images."""
     return blobs2d(seed, n=n)
+
+
+# ---------------------------------------------------------------------------
+# spatially coherent point order (for kernels with exact zeros beyond a cut
+# locus, whose tiles can only be skipped when nearby points sit together)
+# ---------------------------------------------------------------------------
+def morton_order(x: np.ndarray, bits: int = 10) -> np.ndarray:
+    """Indices sorting points x (N, d) of [0, 1]^d along a Z-order (Morton)
+    curve: coordinates quantised to 2^bits levels, bits interleaved."""
+    x = np.atleast_2d(np.asarray(x, np.float64))
+    N, d = x.shape
+    q = np.clip((x * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+    code = np.zeros(N, np.int64)
+    for b in range(bits):
+        for k in range(d):
+            code |= ((q[:, k] >> b) & 1) << (b * d + k)
+    return np.argsort(code, kind="stable")
+
+
+def clusters_sorted(seed: int, N: int = 20000, M: int = 20000, d: int = 2, n_comp: int = 12,
+                    sig_lo: float = 0.03, sig_hi: float = 0.12) -> CloudProblem:
+    """Two clouds of Gaussian clusters in [0, 1]^d (clipped), each stored in
+    Morton order; uniform reference weights 1/N, 1/M and densities
+    U[0.5, 1.5] times the masses 1 and 1.3."""
+    rng = np.random.default_rng(seed)
+
+    def cloud(n):
+        c = rng.uniform(0.15, 0.85, (n_comp, d))
+        s = rng.uniform(sig_lo, sig_hi, n_comp)
+        lab = rng.integers(0, n_comp, n)
+        pts = np.clip(c[lab] + s[lab, None] * rng.standard_normal((n, d)), 0.0, 1.0)
+        return pts[morton_order(pts)]
+
+    x, y = cloud(N), cloud(M)
+    dx, dy = np.full(N, 1.0 / N), np.full(M, 1.0 / M)
+    p = rng.uniform(0.5, 1.5, N)
+    q = rng.uniform(0.5, 1.5, M) * 1.3
+    return CloudProblem(x, y, p, q, dx, dy)
+
+
+# ---------------------------------------------------------------------------
+# gradient flows on [0, 1] (Sec. 5.3 experiments: n uniform cells)
+# ---------------------------------------------------------------------------
+def growth_profile_1d(seed: int, n: int = 3000, species: int = 1, floor: float = 1e-3) -> np.ndarray:
+    """Initial densities (species, n) for the growth flows, w.r.t. the cell
+    width 1/n: a plateau at the cap 1 with smooth shoulders and a few smaller
+    bumps (the shape of the tumour example's initial profile), at least
+    `floor`.  Several species split the profile with smooth random weights
+    (their sum keeps the shape)."""
+    rng = np.random.default_rng(seed)
+    t = (np.arange(n) + 0.5) / n
+    a, b = np.sort(rng.uniform(0.25, 0.55, 2))
+    w = rng.uniform(0.02, 0.05)
+    plateau = 0.5 * (np.tanh((t - a) / w) - np.tanh((t - b - 0.1) / w))
+    bumps = sum(rng.uniform(0.2, 0.6) * np.exp(-0.5 * ((t - rng.uniform(0.1, 0.9)) / rng.uniform(0.02, 0.06)) ** 2)
+                for _ in range(3))
+    prof = np.clip(np.maximum(plateau, bumps), floor, 1.0)
+    if species == 1:
+        return prof[None, :]
+    raw = np.stack([1.0 + 0.8 * np.sin(2 * np.pi * (rng.uniform(0.5, 2.0) * t + rng.uniform())) for _ in range(species)])
+    wts = raw / raw.sum(axis=0)
+    return np.maximum(prof[None, :] * wts, floor / species)

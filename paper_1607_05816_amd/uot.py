@@ -19,9 +19,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libuot.so")
 
 UOT_OK, UOT_NOT_CONVERGED = 0, 1
-UOT_DIV_EQ, UOT_DIV_KL, UOT_DIV_TV, UOT_DIV_RG = 0, 1, 2, 3
+UOT_DIV_EQ, UOT_DIV_KL, UOT_DIV_TV, UOT_DIV_RG, UOT_DIV_GROWTH = 0, 1, 2, 3, 4
 UOT_F64, UOT_F32 = 0, 1
 UOT_GEOM_POINTS, UOT_GEOM_GRID = 0, 1
+UOT_COST_SQEUCLID, UOT_COST_WF = 0, 1
 
 c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
@@ -32,7 +33,7 @@ class UotDiv(ctypes.Structure):
 
 class UotGeom(ctypes.Structure):
     _fields_ = [("kind", c_i32), ("dim", c_i32), ("N", c_i64), ("M", c_i64), ("x", c_vp), ("y", c_vp),
-                ("n", c_i64 * 3), ("h", c_dbl * 3)]
+                ("n", c_i64 * 3), ("h", c_dbl * 3), ("cost", c_i32), ("reserved", c_i32), ("cut", c_dbl)]
 
 
 class UotProblem(ctypes.Structure):
@@ -73,6 +74,11 @@ class UotBatchResult(ctypes.Structure):
                 ("latency_ms", ctypes.POINTER(c_dbl)), ("status", ctypes.POINTER(c_i32)), ("iters_max", c_i64),
                 ("n_converged", c_i64), ("elapsed_ms", c_dbl), ("tile_rows", c_i32), ("blocks_per_cu", c_i32),
                 ("tune_ms", c_dbl)]
+
+
+class UotFlowProblem(ctypes.Structure):
+    _fields_ = [("dtype", c_i32), ("kind", c_i32), ("species", c_i32), ("reserved", c_i32), ("geom", UotGeom),
+                ("p0", c_vp), ("q", c_vp), ("dx", c_vp), ("tau", c_dbl), ("alpha", c_dbl)]
 
 
 class UotNet(ctypes.Structure):
@@ -134,6 +140,9 @@ def lib():
                                        c_i32, P(c_dbl)]),
         "uot_solve_batched": (c_i32, [c_vp, P(UotBatchProblem), P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t,
                                       P(UotBatchResult)]),
+        "uot_flow_workspace_size": (c_i32, [P(UotFlowProblem), P(ctypes.c_size_t)]),
+        "uot_flow": (c_i32, [c_vp, P(UotFlowProblem), P(UotParams), c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t,
+                             P(UotResult)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -185,6 +194,36 @@ def TV(lam):
 
 def RG(alpha, beta):
     return Div(UOT_DIV_RG, alpha=float(alpha), beta=float(beta))
+
+
+def GROWTH(lam):
+    """Growth functional of the WF gradient flow (lam = 2 tau alpha in [0, 1));
+    the marginal's density is the cap."""
+    return Div(UOT_DIV_GROWTH, lam=float(lam))
+
+
+# ---------------------------------------------------------------------------
+# costs: squared Euclidean, or WF (-log cos^2 with the cut locus at `cut`)
+# ---------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Cost:
+    kind: int = UOT_COST_SQEUCLID
+    cut: float = 0.0
+
+
+SQEUCLID = Cost()
+
+
+def WF(cut):
+    return Cost(UOT_COST_WF, float(cut))
+
+
+def _grid_geom(shape, h, cost: Cost) -> UotGeom:
+    size = int(math.prod(shape))
+    n = list(shape) + [1] * (3 - len(shape))
+    hh = list(h) + [0.0] * (3 - len(h))
+    return UotGeom(UOT_GEOM_GRID, len(shape), size, size, c_vp(), c_vp(), (c_i64 * 3)(*n), (c_dbl * 3)(*hh),
+                   cost.kind, 0, cost.cut)
 
 
 # ---------------------------------------------------------------------------
@@ -276,7 +315,7 @@ class Problem:
         return self._ws
 
 
-def points_problem(x, y, p, q, dx, dy, F1: Div, F2: Div) -> Problem:
+def points_problem(x, y, p, q, dx, dy, F1: Div, F2: Div, cost: Cost = SQEUCLID) -> Problem:
     """x: (N, d) or (d, N) coordinate tensors are accepted as (N, d); stored
     coordinate-major for the kernels."""
     dtype = p.dtype
@@ -296,19 +335,18 @@ def points_problem(x, y, p, q, dx, dy, F1: Div, F2: Div) -> Problem:
         raise ValueError("x and y must have the same dimension")
     for t, n, nm in ((p, N, "p"), (q, M, "q"), (dx, N, "dx"), (dy, M, "dy")):
         _dev(t, dtype, n, nm)
-    g = UotGeom(UOT_GEOM_POINTS, d, N, M, _ptr(xs), _ptr(ys), (c_i64 * 3)(0, 0, 0), (c_dbl * 3)(0, 0, 0))
+    g = UotGeom(UOT_GEOM_POINTS, d, N, M, _ptr(xs), _ptr(ys), (c_i64 * 3)(0, 0, 0), (c_dbl * 3)(0, 0, 0),
+                cost.kind, 0, cost.cut)
     return Problem(g, dtype, p, q, dx, dy, F1, F2, keep=(xs, ys))
 
 
-def grid_problem(shape: Sequence[int], h: Sequence[float], p, q, dx, dy, F1: Div, F2: Div) -> Problem:
+def grid_problem(shape: Sequence[int], h: Sequence[float], p, q, dx, dy, F1: Div, F2: Div,
+                 cost: Cost = SQEUCLID) -> Problem:
     dtype = p.dtype
     size = int(math.prod(shape))
     for t, nm in ((p, "p"), (q, "q"), (dx, "dx"), (dy, "dy")):
         _dev(t, dtype, size, nm)
-    n = list(shape) + [1] * (3 - len(shape))
-    hh = list(h) + [0.0] * (3 - len(h))
-    g = UotGeom(UOT_GEOM_GRID, len(shape), size, size, c_vp(), c_vp(), (c_i64 * 3)(*n), (c_dbl * 3)(*hh))
-    return Problem(g, dtype, p, q, dx, dy, F1, F2)
+    return Problem(_grid_geom(shape, h, cost), dtype, p, q, dx, dy, F1, F2)
 
 
 GRID_AUTO, GRID_DIRECT, GRID_MFMA, GRID_MFMA16, GRID_MIXED = 0, 1, 2, 3, 4
@@ -410,7 +448,7 @@ def solve_mass(prob: Problem, F3: Div, mass, eps, ctx: Optional[Context] = None,
 
 
 def barycenter(shape, h, p, alpha, dx, dy, F1: Div, F2: Div, eps, ctx: Optional[Context] = None, v0=None,
-               record=False, **kw):
+               record=False, cost: Cost = SQEUCLID, **kw):
     """Unbalanced barycentre of n densities p (n x size) on a grid.
     Returns (u, v, logh, info)."""
     ctx = ctx or default_context()
@@ -420,9 +458,7 @@ def barycenter(shape, h, p, alpha, dx, dy, F1: Div, F2: Div, eps, ctx: Optional[
     _dev(p, dtype, nm * size, "p")
     _dev(dx, dtype, size, "dx")
     _dev(dy, dtype, size, "dy")
-    n = list(shape) + [1] * (3 - len(shape))
-    hh = list(h) + [0.0] * (3 - len(h))
-    g = UotGeom(UOT_GEOM_GRID, len(shape), size, size, c_vp(), c_vp(), (c_i64 * 3)(*n), (c_dbl * 3)(*hh))
+    g = _grid_geom(shape, h, cost)
     al = (c_dbl * nm)(*[float(a) for a in alpha])
     bp = UotBaryProblem(_dt(p), nm, g, _ptr(p), ctypes.cast(al, ctypes.POINTER(c_dbl)), _ptr(dx), _ptr(dy),
                         F1.c(), F2.c())
@@ -460,7 +496,7 @@ def time_half_step(prob: Problem, eps, v, reps=50, ctx: Optional[Context] = None
 
 
 def time_fields_half_step(shape, h, p, dx, dy, F1: Div, eps, v, reps=20, ctx: Optional[Context] = None,
-                          grid_kernel=0):
+                          grid_kernel=0, cost: Cost = SQEUCLID):
     """time_half_step over nb fields on one grid (p, v: nb x size); every
     timed launch processes all fields."""
     ctx = ctx or default_context()
@@ -471,9 +507,7 @@ def time_fields_half_step(shape, h, p, dx, dy, F1: Div, eps, v, reps=20, ctx: Op
     _dev(v, dtype, nb * size, "v")
     _dev(dx, dtype, size, "dx")
     _dev(dy, dtype, size, "dy")
-    n = list(shape) + [1] * (3 - len(shape))
-    hh = list(h) + [0.0] * (3 - len(h))
-    g = UotGeom(UOT_GEOM_GRID, len(shape), size, size, c_vp(), c_vp(), (c_i64 * 3)(*n), (c_dbl * 3)(*hh))
+    g = _grid_geom(shape, h, cost)
     pb = UotProblem(_dt(p), 0, g, _ptr(p), _ptr(p), _ptr(dx), _ptr(dy), F1.c(), F1.c())
     nbytes = ctypes.c_size_t()
     _check(lib().uot_fields_workspace_size(ctypes.byref(pb), nb, ctypes.byref(nbytes)), "uot_fields_workspace_size",
@@ -570,7 +604,7 @@ def solve_batched(bp: BatchProblem, eps, ctx: Optional[Context] = None, v0=None,
 
 
 def solve_fields(shape, h, p, q, dx, dy, F1: Div, F2: Div, eps, ctx: Optional[Context] = None, v0=None,
-                 record=False, **kw):
+                 record=False, cost: Cost = SQEUCLID, **kw):
     """nb independent UOT problems on one grid (p, q: nb x size).  Returns
     (u, v, info) with u, v of shape (nb, size)."""
     ctx = ctx or default_context()
@@ -581,9 +615,7 @@ def solve_fields(shape, h, p, q, dx, dy, F1: Div, F2: Div, eps, ctx: Optional[Co
     _dev(q, dtype, nb * size, "q")
     _dev(dx, dtype, size, "dx")
     _dev(dy, dtype, size, "dy")
-    n = list(shape) + [1] * (3 - len(shape))
-    hh = list(h) + [0.0] * (3 - len(h))
-    g = UotGeom(UOT_GEOM_GRID, len(shape), size, size, c_vp(), c_vp(), (c_i64 * 3)(*n), (c_dbl * 3)(*hh))
+    g = _grid_geom(shape, h, cost)
     pb = UotProblem(_dt(p), 0, g, _ptr(p), _ptr(q), _ptr(dx), _ptr(dy), F1.c(), F2.c())
     nbytes = ctypes.c_size_t()
     _check(lib().uot_fields_workspace_size(ctypes.byref(pb), nb, ctypes.byref(nbytes)), "uot_fields_workspace_size",
@@ -737,3 +769,62 @@ def bary_estimate(p, alpha, eps, F2: Div, ctx: Optional[Context] = None):
     _check(lib().uot_bary_estimate(ctx.handle, _ptr(p), n, size, al, float(eps), ctypes.byref(f), _ptr(h)),
            "uot_bary_estimate", False)
     return h
+
+
+# ---------------------------------------------------------------------------
+# gradient flows (uot_flow)
+# ---------------------------------------------------------------------------
+FLOW_HEAT, FLOW_CROWD, FLOW_GROWTH = 0, 1, 2
+_FLOW_KINDS = {"heat": FLOW_HEAT, "crowd": FLOW_CROWD, "growth": FLOW_GROWTH}
+
+
+def flow(kind, p0, q, dx, tau, eps, n_steps, shape=None, h=None, x=None, alpha=0.0, cost: Cost = SQEUCLID,
+         ctx: Optional[Context] = None, v0=None, record=False, **kw):
+    """A gradient flow of n_steps steps (uot_flow): kind "heat", "crowd" or
+    "growth" on a grid (shape, h) or on one point cloud x (N x d, X = Y).
+    p0: (species, N) or (N,) initial densities w.r.t. dx; q: (N,) reference
+    (heat) or cap (crowd, growth).  Per-step solver settings (tol, max_iter,
+    eps0, check_every, grid_kernel ...) come through **kw.
+    Returns (dens (n_steps+1, species, N), v (species, N), steps, info) with
+    steps a list of per-step dicts (iters, residual, status, elapsed_ms)."""
+    ctx = ctx or default_context()
+    k = _FLOW_KINDS[kind] if isinstance(kind, str) else int(kind)
+    dtype = q.dtype
+    p0 = p0.reshape(-1, q.numel()) if p0.dim() == 1 else p0
+    S, N = p0.shape
+    _dev(p0, dtype, S * N, "p0")
+    _dev(q, dtype, N, "q")
+    _dev(dx, dtype, N, "dx")
+    keep = ()
+    if shape is not None:
+        g = _grid_geom(shape, h, cost)
+    else:
+        xs = x if x.dim() == 2 else x[:, None]
+        if xs.shape[0] == N and xs.shape[1] != N:
+            xs = xs.t()
+        xs = _dev(xs.contiguous(), dtype, name="x")
+        g = UotGeom(UOT_GEOM_POINTS, xs.shape[0], N, N, _ptr(xs), _ptr(xs), (c_i64 * 3)(0, 0, 0),
+                    (c_dbl * 3)(0, 0, 0), cost.kind, 0, cost.cut)
+        keep = (xs,)
+    fp = UotFlowProblem(_dt(q), k, S, 0, g, _ptr(p0), _ptr(q), _ptr(dx), float(tau), float(alpha))
+    nbytes = ctypes.c_size_t()
+    _check(lib().uot_flow_workspace_size(ctypes.byref(fp), ctypes.byref(nbytes)), "uot_flow_workspace_size", False)
+    ws = workspace(nbytes.value, q.device)
+    dens = torch.empty(n_steps + 1, S, N, dtype=dtype, device=q.device)
+    v = torch.empty(S, N, dtype=dtype, device=q.device)
+    if v0 is not None:
+        _dev(v0, dtype, S * N, "v0")
+    max_iter = kw.get("max_iter", 10000)
+    hist = torch.full((max_iter,), float("nan"), dtype=torch.float64, device=q.device) if record else None
+    pr = params(eps, v0=v0, res_hist=hist, **kw)
+    steps = (UotResult * max(n_steps, 1))()
+    code = lib().uot_flow(ctx.handle, ctypes.byref(fp), ctypes.byref(pr), int(n_steps), _ptr(dens), _ptr(v),
+                          _ptr(ws), ws.numel(), steps)
+    _check(code, "uot_flow")
+    del keep
+    out = [dict(iters=steps[i].iters, residual=steps[i].residual, status=steps[i].status,
+                elapsed_ms=steps[i].elapsed_ms) for i in range(n_steps)]
+    info = dict(converged=(code == UOT_OK), elapsed_ms=sum(o["elapsed_ms"] for o in out))
+    if record:
+        info["res_hist"] = hist.cpu()
+    return dens, v, out, info

@@ -27,6 +27,8 @@ def oracle_div(F):
         return O.KL(F.lam)
     if F.kind == U.UOT_DIV_TV:
         return O.TV(F.lam)
+    if F.kind == U.UOT_DIV_GROWTH:
+        return O.GROWTH(F.lam)
     return O.RG(F.alpha, F.beta)
 
 

@@ -47,7 +47,9 @@ _PROBE = r"""
 #define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
   S(uot_div) S(uot_geom) S(uot_problem) S(uot_params) S(uot_result) S(uot_objective_values) S(uot_bary_problem)
-  S(uot_batch_problem) S(uot_batch_result)
+  S(uot_batch_problem) S(uot_batch_result) S(uot_flow_problem)
+  O(uot_geom, cost) O(uot_geom, cut) O(uot_flow_problem, geom) O(uot_flow_problem, p0) O(uot_flow_problem, tau)
+  O(uot_flow_problem, alpha)
   O(uot_batch_problem, F2) O(uot_batch_problem, dy) O(uot_batch_result, tune_ms) O(uot_batch_result, tile_rows)
   O(uot_geom, n) O(uot_geom, h) O(uot_problem, geom) O(uot_problem, F1) O(uot_problem, F2)
   O(uot_params, v0) O(uot_params, res_hist) O(uot_params, check_every) O(uot_params, kernel_ms) O(uot_params, kernel_launches) O(uot_params, grid_kernel)
@@ -71,7 +73,8 @@ def test_ctypes_layout_matches_c_header():
     py = {"uot_div": uot.UotDiv, "uot_geom": uot.UotGeom, "uot_problem": uot.UotProblem,
           "uot_params": uot.UotParams, "uot_result": uot.UotResult,
           "uot_objective_values": uot.UotObjectiveValues, "uot_bary_problem": uot.UotBaryProblem,
-          "uot_batch_problem": uot.UotBatchProblem, "uot_batch_result": uot.UotBatchResult}
+          "uot_batch_problem": uot.UotBatchProblem, "uot_batch_result": uot.UotBatchResult,
+          "uot_flow_problem": uot.UotFlowProblem}
     for k, T in py.items():
         assert ctypes.sizeof(T) == c[k], k
     pyname = {"F1": "F1", "F2": "F2"}
@@ -156,3 +159,60 @@ def test_batch_workspace_and_validation():
     bp.offN = bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     assert L.uot_batch_workspace_size(ctypes.byref(bp), ctypes.byref(n)) == -1
     assert b"N, M >= 1" in L.uot_last_error()
+
+
+def test_wf_cost_and_flow_validation_on_host():
+    """WF cost and gradient-flow arguments are checked on the host."""
+    L = uot.lib()
+    n = ctypes.c_size_t()
+    # WF cost: a cut > 0 is needed, and grids must be 1-D (not separable)
+    pg = uot.UotProblem()
+    pg.dtype = uot.UOT_F32
+    pg.geom.kind, pg.geom.dim = uot.UOT_GEOM_GRID, 1
+    pg.geom.n[0], pg.geom.h[0] = 300, 1 / 300
+    pg.geom.cost, pg.geom.cut = uot.UOT_COST_WF, 0.2
+    assert L.uot_workspace_size(ctypes.byref(pg), ctypes.byref(n)) == 0
+    pg.geom.cut = 0.0
+    assert L.uot_workspace_size(ctypes.byref(pg), ctypes.byref(n)) == -1
+    pg.geom.cut = 0.2
+    pg.geom.dim = 2
+    pg.geom.n[1], pg.geom.h[1] = 64, 1 / 64
+    assert L.uot_workspace_size(ctypes.byref(pg), ctypes.byref(n)) == -2
+    assert b"separable" in L.uot_last_error()
+    pg.geom.cost = 5
+    assert L.uot_workspace_size(ctypes.byref(pg), ctypes.byref(n)) == -1
+    # flows
+    fp = uot.UotFlowProblem()
+    fp.dtype, fp.kind, fp.species = uot.UOT_F32, uot.FLOW_GROWTH, 1
+    fp.geom.kind, fp.geom.dim = uot.UOT_GEOM_GRID, 1
+    fp.geom.n[0], fp.geom.h[0] = 3000, 1 / 3000
+    fp.geom.cost, fp.geom.cut = uot.UOT_COST_WF, 1.5707963267948966
+    fp.p0 = fp.q = fp.dx = ctypes.c_void_p(0x1000)
+    fp.tau, fp.alpha = 0.006, 1.0
+    assert L.uot_flow_workspace_size(ctypes.byref(fp), ctypes.byref(n)) == 0
+    assert n.value > 4 * 3000 * 4
+    fp.species = 2
+    assert L.uot_flow_workspace_size(ctypes.byref(fp), ctypes.byref(n)) == 0
+    fp.alpha = 100.0                                  # 2 tau alpha >= 1
+    assert L.uot_flow_workspace_size(ctypes.byref(fp), ctypes.byref(n)) == -1
+    fp.alpha = 1.0
+    fp.kind = uot.FLOW_HEAT                           # several species: growth only
+    assert L.uot_flow_workspace_size(ctypes.byref(fp), ctypes.byref(n)) == -2
+    fp.kind, fp.species = uot.FLOW_CROWD, 1
+    fp.geom.kind, fp.geom.dim, fp.geom.N, fp.geom.M = uot.UOT_GEOM_POINTS, 2, 100, 100
+    fp.geom.x, fp.geom.y = ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    assert L.uot_flow_workspace_size(ctypes.byref(fp), ctypes.byref(n)) == -1    # X != Y
+    assert b"same points" in L.uot_last_error()
+    fp.geom.y = fp.geom.x
+    assert L.uot_flow_workspace_size(ctypes.byref(fp), ctypes.byref(n)) == 0
+    pr = uot.UotParams()
+    assert L.uot_flow(None, ctypes.byref(fp), ctypes.byref(pr), 1, None, None, None, 0, None) == -1
+    # the growth divergence: 0 <= lambda < 1
+    # (the problem check fails before the context or the zeroed params are used)
+    pb = uot.UotProblem()
+    pb.p = pb.q = pb.dx = pb.dy = ctypes.c_void_p(0x1000)
+    pb.F1 = uot.KL(1.0).c()
+    pb.F2 = uot.GROWTH(1.2).c()
+    assert L.uot_solve(ctypes.c_void_p(1), ctypes.byref(pb), ctypes.byref(pr), None, None, None, 0,
+                       ctypes.byref(uot.UotResult())) == -1
+    assert b"growth" in L.uot_last_error()
