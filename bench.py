@@ -16,6 +16,7 @@ of every timed step); ms_per_step = time to residual 1e-6 for the KL + TV pair.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -180,23 +181,31 @@ PASS_NAMES = ["k_grid_tf<false, 4>", "k_grid_tf<true, 4>"]
 # HBM bytes per launch (calibrated FETCH_SIZE read + WRITE_SIZE written) of the
 # two passes at both launch shapes, from the two counter runs of
 # `bench.py --pmc-workload`; they hold for the kernel source they were taken
-# on (sha256 of csrc/uot_kernels.hip) and are reported as null otherwise.
-TRAFFIC_SOURCE_SHA256 = "79df1b1c79d2ec579d569ecec08f5c9f5db15d44348fd6c05d33d5c42cc3f3a2"
+# on (sha256 of the pass's file and the headers it includes) and are reported
+# as null otherwise.
+TRAFFIC_SOURCES = ["uot_grid_tf.hip", "uot_epilogue.h", "uot_device.h", "uot_launch.h"]
+TRAFFIC_SOURCE_SHA256 = "4cd731ce5e2c22dee5c34b90edef8a574bc0f6cf76d9d9ccedead19d74c1ade9"
 TRAFFIC_BYTES = {
-    ("k_grid_tf<false, 4>", 1): (2275605, 259840),
-    ("k_grid_tf<true, 4>", 1): (3091183, 523671),
-    ("k_grid_tf<false, 4>", 256): (67297964, 67108864),
-    ("k_grid_tf<true, 4>", 256): (406600962, 134348800),
+    ('k_grid_tf<false, 4>', 1): (2273385, 259840),
+    ('k_grid_tf<false, 4>', 256): (67286754, 67108864),
+    ('k_grid_tf<true, 4>', 1): (3096766, 523671),
+    ('k_grid_tf<true, 4>', 256): (406300680, 134348800),
 }
 
 
-def traffic(kernel, fields):
-    """(bytes read, bytes written) per launch, or None once the kernels changed."""
+def tf_source_sha256():
     import hashlib
-    src = os.path.join(ROOT, "paper_1607_05816_amd", "csrc", "uot_kernels.hip")
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC_SOURCE_SHA256:
-            return None
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1607_05816_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic(kernel, fields):
+    """(bytes read, bytes written) per launch, or None once the kernel changed."""
+    if tf_source_sha256() != TRAFFIC_SOURCE_SHA256:
+        return None
     return TRAFFIC_BYTES.get((kernel, fields))
 
 
@@ -281,6 +290,70 @@ def dense_roofline(U, torch, np, dev, ctx, n=20000, eps=1e-3):
             "achieved": pairs / (ms[0] * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "Texp/s",
             "frac": pairs / (ms[0] * 1e-3) / peak, "work_per_launch": pairs, "work_unit": "exp (one per pair)",
             "epilogue_ms": ms[1], "workload": "clouds3d N=M=%d eps=%g FP32" % (n, eps)}
+
+
+def wf_dense_roofline(U, torch, np, dev, ctx, n=20000, cut=0.1, eps=1e-3):
+    """Dense product with the WF cost and cut locus 0.1 (2-D clustered clouds,
+    N = M = 20000, FP32): the same launch timed on Morton-ordered clouds (tiles
+    beyond the cut skipped), on the same clouds shuffled (nothing skippable),
+    and with the squared Euclidean cost.  Algorithmic work: the pairs within
+    the cut (the non-zero kernel entries), each one exp and one log, priced at
+    half the transcendental issue peak."""
+    from paper_1607_05816_amd import synth
+    cp = synth.clusters_sorted(0, N=n, M=n, d=2)
+    T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
+    rng = np.random.default_rng(0)
+    # pairs within the cut: exact count by rows in chunks
+    inside = 0
+    for a in range(0, n, 2000):
+        d2 = ((cp.x[a:a + 2000, None, :] - cp.y[None, :, :]) ** 2).sum(-1)
+        inside += int((d2 < cut * cut).sum())
+    F = U.KL(1.0)
+    v = torch.zeros(n, dtype=torch.float32, device=dev)
+    out = {}
+    perm = rng.permutation(n)
+    for name, x, y, cost in (("sorted", cp.x, cp.y, U.WF(cut)), ("shuffled", cp.x[perm], cp.y[perm], U.WF(cut)),
+                             ("sqeuclid", cp.x, cp.y, U.SQEUCLID)):
+        pb = U.points_problem(T(x), T(y), T(cp.p), T(cp.q), T(cp.dx), T(cp.dy), F, F, cost=cost)
+        pb.workspace()
+        out[name + "_ms"] = U.time_half_step(pb, eps, v, reps=20, ctx=ctx)[0]
+    peak = exp_peak() / 2
+    ms = out["sorted_ms"]
+    out.update({"bound": "alu", "kernel": "k_dense_lse<float, 2, 2, 1>", "kernel_avg_ms": ms,
+                "achieved": inside / (ms * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "Tpairs/s",
+                "frac": inside / (ms * 1e-3) / peak, "work_per_launch": float(inside),
+                "work_unit": "pair within the cut (one exp + one log)", "pairs_within_cut_frac": inside / float(n) ** 2,
+                "dense_pairs_per_s_equivalent": float(n) ** 2 / (ms * 1e-3),
+                "workload": "clusters_sorted 2-D N=M=%d, WF cut %g, eps %g, FP32" % (n, cut, eps)})
+    return out
+
+
+def flows_bench(U, torch, np, dev, ctx, steps=10):
+    """The gradient-flow experiments' shapes (Sec. 5.3): [0, 1] in 3000 cells,
+    WF cost (cut pi/2 beyond the segment), 500 iterations per step, FP64
+    (eps 1e-8 / 1e-7 puts potentials / eps near 1e8): the tumour growth flow
+    (tau 0.006, alpha 1, eps 1e-8) and two species (tau 0.004, alpha 1,
+    eps 1e-7), `steps` steps each, densities kept on the device."""
+    from paper_1607_05816_amd import synth
+    n = 3000
+    out = {}
+    for name, species, tau, eps in (("growth_1species", 1, 0.006, 1e-8), ("growth_2species", 2, 0.004, 1e-7)):
+        p0 = torch.tensor(synth.growth_profile_1d(0, n, species=species), dtype=torch.float64, device=dev)
+        q = torch.ones(n, dtype=torch.float64, device=dev)
+        dx = torch.full((n,), 1.0 / n, dtype=torch.float64, device=dev)
+        U.flow("growth", p0, q, dx, tau, eps, 1, shape=(n,), h=(1.0 / n,), alpha=1.0, cost=U.WF(math.pi / 2),
+               tol=0.0, max_iter=500, check_every=50, ctx=ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dens, v, st, info = U.flow("growth", p0, q, dx, tau, eps, steps, shape=(n,), h=(1.0 / n,), alpha=1.0,
+                                   cost=U.WF(math.pi / 2), tol=0.0, max_iter=500, check_every=50, ctx=ctx)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        mass = (dens.sum(dim=(1, 2)) / n).cpu().numpy()
+        out[name] = {"steps": steps, "iters_per_step": 500, "ms_per_step": dt / steps * 1e3,
+                     "iters_per_s": steps * 500 / dt, "mass_first_last": [float(mass[0]), float(mass[-1])],
+                     "max_density_last": float(dens[-1].sum(0).max()), "dtype": "f64"}
+    return out
 
 
 def pmc_workload(U, torch, np, dev, ctx):
@@ -470,6 +543,8 @@ def main():
         line["roofline_gemm"] = gemm_roofline(U, torch, np, dev, ctx)
     if not args.no_extensions:
         line["extensions"] = extensions(U, pr, ctx, dev, np, torch)
+        line["extensions"]["roofline_wf_dense"] = wf_dense_roofline(U, torch, np, dev, ctx)
+        line["extensions"]["gradient_flows"] = flows_bench(U, torch, np, dev, ctx)
     if not args.no_warm_batched:
         line["warm_batched_vs_plain"] = warm_batched(U, ctx, dev, np, torch)
     if not args.no_cpu_baseline:

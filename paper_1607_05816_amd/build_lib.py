@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libuot.so")
-SOURCES = ["uot_kernels.hip", "uot_api.hip", "uot_net.hip"]
+SOURCES = ["uot_kernels.hip", "uot_grid_tf.hip", "uot_api.hip", "uot_net.hip"]
 ARCH = os.environ.get("UOT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -132,6 +132,9 @@ struct Plan {
   bool tf16_axis[3] = {false, false, false}; // ... with FP16 operands
   CostArgs cost{0, 0, 0.0};                  // squared Euclidean or WF with a cut locus
   int band[3] = {0, 0, 0};                   // grid axes: taps |i - j| < band can be non-zero
+  int split1d = 1;                           // 1-D grids: tap slices of the (direct) pass
+  mutable void* split_pm = nullptr;          // ... their partial LSEs (set by carve)
+  mutable void* split_ps = nullptr;
   // workspace offsets
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
       o_gcost, o_obj, o_scal, o_mass, total;
@@ -156,6 +159,7 @@ bool has_tf16(const Plan& P) { return P.tf16_axis[0] || P.tf16_axis[1] || P.tf16
 
 int grid_final_parts_for(const Plan& P, bool tf0) {
   const int64_t nb = P.nb;
+  if (P.dim == 1 && !tf0 && P.split1d > 1) return (int)((nb * P.n[0] + 255) / 256);   // merge blocks
   if (P.dim == 1) return tf0 ? grid_tf_parts((int)P.n[0], nb, 1, false) : grid_contig_parts<float>((int)P.n[0], nb);
   const int64_t B = P.dim == 2 ? P.n[1] : P.n[1] * P.n[2];
   return tf0 ? grid_tf_parts((int)P.n[0], nb, B, true) : grid_strided_parts<float>((int)P.n[0], nb, B);
@@ -224,6 +228,7 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
       P.band[k] = (int)g.n[k];
       if (g.cost == UOT_COST_WF) P.band[k] = (int)std::min<double>((double)g.n[k], std::ceil(g.cut / g.h[k]));
     }
+    if (g.dim == 1) P.split1d = grid_contig_splits((int)g.n[0], nb, P.band[0]);
   } else {
     return fail(UOT_E_INVALID, "unknown geometry kind");
   }
@@ -253,7 +258,9 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
     P.o_ps = take(e * np);
     P.nparts_x = (int)((P.N + 255) / 256);
   } else {
-    P.o_pm = P.o_ps = take(0);
+    const size_t np = P.dim == 1 && P.split1d > 1 ? (size_t)P.split1d * nb * P.N : 0;
+    P.o_pm = take(e * np);
+    P.o_ps = take(e * np);
     P.nparts_x = grid_final_parts(P);
   }
   // room for either pass kind, so a size query without eps fits every solve
@@ -341,6 +348,8 @@ template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
   b.scal = at<double>(ws, P.o_scal);
   b.mass_m = at<T>(ws, P.o_mass);
   b.mass_s = b.mass_m + std::max(std::max(P.nparts_x, P.nparts_y), 1);
+  P.split_pm = b.pm;
+  P.split_ps = b.ps;
   return b;
 }
 
@@ -354,6 +363,16 @@ void contig_pass(const Plan& P, int axis, const T* w, int64_t A, T* const* tabs,
       timed(0, [&] { launch_grid_tf(w, A, (int)P.n[axis], 1, false, P.tf16_axis[axis], P.h[axis], side, c, ep, s); });
       return;
     }
+  }
+  if (P.dim == 1 && P.split1d > 1) {
+    // few long lines: tap slices, then the merge with the epilogue
+    T* pm = static_cast<T*>(P.split_pm);
+    T* ps = static_cast<T*>(P.split_ps);
+    timed(0, [&] {
+      launch_grid_contig_split<T>(w, A, (int)P.n[axis], tabs[axis], side, c, P.band[axis], P.split1d, pm, ps, s);
+    });
+    timed(1, [&] { launch_dense_epi<T>(pm, ps, P.split1d, A * P.n[axis], side, c, ep, s); });
+    return;
   }
   timed(0, [&] { launch_grid_contig<T>(w, A, (int)P.n[axis], tabs[axis], side, c, ep, P.band[axis], s); });
 }

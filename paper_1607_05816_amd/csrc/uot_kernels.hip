@@ -13,14 +13,15 @@
 //     recomputed from coordinates staged in LDS (Sec. 4.4, "Computing the
 //     matrix multiplications"); columns are split across blocks and the
 //     per-split (max, sum) pairs merged by the epilogue kernel.
+#include <algorithm>
 #include <cstdlib>
 
 #include "uot_device.h"
+#include "uot_epilogue.h"
 #include "uot_launch.h"
 
 namespace uot {
 
-constexpr int kBlock = 256;
 constexpr int kChunk = 8;       // terms per online-max rescale
 constexpr int kMaxLine = 4096;  // longest grid axis (LDS table of the contiguous pass)
 
@@ -71,194 +72,6 @@ __global__ void k_gtab(T* __restrict__ tab, int n, double h, const Ctrl* __restr
   } else {
     tab[t] = T(-(d * d) / c->eps_tab[s] * kLog2e);
   }
-}
-
-// ---------------------------------------------------------------------------
-// epilogue shared by every Gibbs product.  epi_elem handles one element with
-// S2 = log2 of the product; epi_finish reduces the residual partials of the
-// block (every thread of the block must call it).
-// ---------------------------------------------------------------------------
-template <typename T> struct ResAcc {
-  T m, den, num;
-  __device__ __forceinline__ void init() {
-    m = Num<T>::ninf();
-    den = T(0);
-    num = T(0);
-  }
-  __device__ __forceinline__ void add(T m2, T d2, T n2) { res_merge<T>(m, den, num, m2, d2, n2); }
-};
-
-// operands of one element's epilogue, loadable ahead of the product
-template <typename T> struct EpiIn {
-  T ld, uo, lp;
-};
-
-template <typename T>
-__device__ __forceinline__ EpiIn<T> epi_load(int64_t e, const EpiArgs<T>& ep) {
-  EpiIn<T> x;
-  if (ep.mode == EPI_RAW) {
-    x.ld = x.uo = x.lp = T(0);
-    return x;
-  }
-  x.ld = ep.logd[e < ep.size ? e : e % ep.size];
-  x.uo = ep.pot[e];
-  x.lp = ep.logp[e];
-  return x;
-}
-
-template <typename T>
-__device__ __forceinline__ void epi_apply(int64_t e, T S2, const EpiIn<T>& x, const Ctrl* __restrict__ c, int side,
-                                          const EpiArgs<T>& ep, ResAcc<T>& ra) {
-  if (ep.mode == EPI_RAW) {
-    ep.out[e] = S2;
-    return;
-  }
-  const T eps = T(eps_of(c, side));
-  const T eps_w = T(eps_next_of(c, side));   // w feeds the next half-step
-  const T Sraw = S2 * T(kLn2);
-  const T S = Sraw + T(c->zeta);              // z K(.): log z of a total-mass penalty, else 0
-  const T ld = x.ld;
-  const T uo = x.uo;
-  const T un = proxdiv_pot<T>(ep.F, x.lp, S, eps);
-  // a vanishing product (K b = 0 here, possible with exact zeros of K): the
-  // row of the plan is zero whatever the potential, so the point carries no
-  // marginal mass and enters the next product as -inf
-  const bool vanish = Sraw == Num<T>::ninf();
-  ep.pot[e] = un;
-  if (ep.wnext) ep.wnext[e] = vanish ? Num<T>::ninf() : (un / eps_w + ld) * T(kLog2e);
-  if (ep.lse_out) ep.lse_out[e] = S;
-  if (vanish) return;
-  if (ep.part) {
-    if (un == Num<T>::ninf()) {
-      if (uo != Num<T>::ninf()) ra.add((S + uo / eps + ld) * T(kLog2e), T(0), T(1));
-    } else {
-      const T d = Num<T>::expm1((uo - un) / eps);
-      ra.add((S + un / eps + ld) * T(kLog2e), T(1), Num<T>::fmax(d, -d));
-    }
-  } else if (ep.mass_m) {
-    // mass of the plan without z: the (m, den) pair of ra carries it
-    ra.add((Sraw + un / eps + ld) * T(kLog2e), T(1), T(0));
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void epi_elem(int64_t e, T S2, const Ctrl* __restrict__ c, int side,
-                                         const EpiArgs<T>& ep, ResAcc<T>& ra) {
-  epi_apply<T>(e, S2, epi_load<T>(e, ep), c, side, ep, ra);
-}
-
-// log2-sum-exp (m, s) over a block in T precision (every thread calls it);
-// thread 0 writes the result
-template <typename T>
-__device__ __forceinline__ void block_lse_reduce(T m, T s, T* out_m, T* out_s) {
-  __shared__ T sm[kBlock], ss[kBlock];
-  sm[threadIdx.x] = m;
-  ss[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = kBlock / 2; off >= 1; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      Lse2<T> a;
-      a.m = sm[threadIdx.x];
-      a.s = ss[threadIdx.x];
-      a.merge(sm[threadIdx.x + off], ss[threadIdx.x + off]);
-      sm[threadIdx.x] = a.m;
-      ss[threadIdx.x] = a.s;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    *out_m = sm[0];
-    *out_s = ss[0];
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void epi_finish(const EpiArgs<T>& ep, const ResAcc<T>& ra, int part_index) {
-  if (ep.mode == EPI_RAW) return;
-  if (ep.part) block_res_reduce<T>(ra.m, ra.den, ra.num, ep.part + part_index);
-  else if (ep.mass_m) block_lse_reduce<T>(ra.m, ra.den, ep.mass_m + part_index, ep.mass_s + part_index);
-}
-
-// ---------------------------------------------------------------------------
-// control step of an iteration: reduce the residual partials of the X
-// half-step, count the iteration, pick the next eps, stop when done.  It runs
-// as its own launch (k_control) or in block 0 of the first pass of the Y
-// half-step (grid solves of one problem: that pass only reads the slot of
-// the current iteration, the step writes the slot of the next).
-// ---------------------------------------------------------------------------
-// what the control step of an iteration of parity par reads of the control
-// block, loaded before the residual reduction so those loads overlap the
-// loads of the partials
-struct CtrlSnap {
-  int64_t l, max_iter;
-  int stage, n_stages, sn;
-  double tol, eps_next;
-};
-
-__device__ __forceinline__ CtrlSnap ctrl_snap(const Ctrl* c, int par) {
-  CtrlSnap s;
-  s.l = c->iter;
-  s.max_iter = c->max_iter;
-  s.stage = c->stage[par];
-  s.n_stages = c->n_stages;
-  s.tol = c->tol;
-  int64_t sn = c->iters_per_stage > 0 ? (s.l + 1) / c->iters_per_stage : s.n_stages;
-  if (sn > s.n_stages) sn = s.n_stages;
-  s.sn = (int)sn;
-  s.eps_next = c->eps_tab[sn];
-  return s;
-}
-
-// one thread: record r, count the iteration, fill the slot of the next
-// iteration (parity par ^ 1) with its eps stage, stop when done.  A stopped
-// solve skips the next iteration; the control step of a skipped iteration
-// passes the skip on (control_skip), so every later iteration skips too.
-__device__ void control_finish(Ctrl* c, const CtrlSnap& s, double r, double* __restrict__ hist, int par) {
-  if (hist) hist[s.l] = r;
-  c->res = r;
-  c->iter = s.l + 1;
-  c->stage[par ^ 1] = s.sn;
-  c->eps[par ^ 1] = s.eps_next;
-  const bool final_stage = s.stage >= s.n_stages;
-  int status = 0;
-  bool stop = false;
-  if (r != r) {
-    stop = true;
-    status = -3;
-  } else if (final_stage && r <= s.tol && s.l >= 1) {
-    // (the first residual compares with the initial u and is not used to stop)
-    stop = true;
-    status = 0;
-  } else if (s.l + 1 >= s.max_iter) {
-    stop = true;
-    status = 1;
-  }
-  if (stop) {
-    c->status = status;
-    c->stop = 1;
-    c->skip[par ^ 1] = 1;
-  }
-}
-
-__device__ __forceinline__ void control_skip(Ctrl* c, int par) { c->skip[par ^ 1] = 1; }
-
-// this thread's share of the residual partials of one problem
-__device__ __forceinline__ void ctl_load(const ResPart* __restrict__ part, int nparts, float& m, float& den,
-                                         float& num) {
-  m = -__builtin_inff();
-  den = num = 0.f;
-  for (int k = threadIdx.x; k < nparts; k += kBlock) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
-}
-
-// block reduction of the shares and the control step (every thread of the
-// block calls it)
-__device__ __forceinline__ void ctl_reduce_finish(Ctrl* c, const CtrlSnap& snap, float m, float den, float num,
-                                                  double* __restrict__ hist, int par) {
-  __shared__ ResPart tot;
-  __syncthreads();   // the block's own reductions before this one are complete
-  block_res_reduce<float>(m, den, num, &tot);
-  __syncthreads();
-  if (threadIdx.x == 0) control_finish(c, snap, res_ratio(double(tot.num), double(tot.den)), hist, par);
 }
 
 // merge the per-wave partial LSEs of a block (4 waves split the taps); the
@@ -368,13 +181,18 @@ __global__ __launch_bounds__(kBlock) void k_grid_strided(const T* __restrict__ i
 // ---------------------------------------------------------------------------
 // taps j with |i - j| >= band are exact zeros of the kernel (a cut locus; band
 // = n otherwise) and are skipped: a block reads only the taps within band of
-// its outputs
-template <typename T, int RI>
+// its outputs, and only the part of the g table they need.
+// SPLIT: few long lines (1-D grids): blockIdx.z takes one of nsplit slices of
+// the tap range and the block writes its partial LSE (m, s) per output to
+// pm / ps[(z A + a) n + i]; k_dense_epi merges the slices and runs the
+// epilogue.  grid = (ceil(n / 64 RI), A, nsplit) then, else (.., lines in y, z).
+template <typename T, int RI, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in, int n, int64_t A,
                                                          const T* __restrict__ gtab, int side,
-                                                         const Ctrl* __restrict__ c, EpiArgs<T> ep, int band) {
+                                                         const Ctrl* __restrict__ c, EpiArgs<T> ep, int band,
+                                                         T* __restrict__ pm, T* __restrict__ ps, int nsplit) {
   // block 0 of a launch that hosts the control step: partials loaded first
-  const bool hosting = ep.host_ctl != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0;
+  const bool hosting = !SPLIT && ep.host_ctl != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0;
   const int par = par_of(side);
   CtrlSnap hsnap{};
   float hm = -__builtin_inff(), hden = 0.f, hnum = 0.f;
@@ -386,26 +204,37 @@ __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in
     if (hosting && threadIdx.x == 0) control_skip(ep.host_ctl, par);
     return;
   }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t a = SPLIT ? (int64_t)blockIdx.y : (int64_t)blockIdx.z * gridDim.y + blockIdx.y;
+  const bool valid_a = a < A;
+  const T* __restrict__ line = in + (valid_a ? a : 0) * (int64_t)n;
+  // outputs [o0, o1) of the block, taps [ta, tb) within the band (one slice
+  // of it when SPLIT)
+  const int o0 = blockIdx.x * RI * 64;
+  const int o1 = (o0 + RI * 64 < n) ? o0 + RI * 64 : n;
+  int ta = (o0 - band + 1 > 0) ? o0 - band + 1 : 0;
+  int tb = (o1 - 1 + band < n) ? o1 - 1 + band : n;
+  if (SPLIT) {
+    const int sl = (tb - ta + nsplit - 1) / nsplit;
+    const int s0 = ta + (int)blockIdx.z * sl;
+    ta = s0 < tb ? s0 : tb;
+    tb = (s0 + sl < tb) ? s0 + sl : tb;
+  }
+  // the g entries the block reads: offsets i - j in [o0 - tb + 1, o1 - 1 - ta]
   extern __shared__ __align__(16) unsigned char gl_raw[];
   T* gl = reinterpret_cast<T*>(gl_raw);
   const int stage = stage_of(c, side);
   const T* __restrict__ g = gtab + (int64_t)stage * (2 * n - 1);
-  for (int k = threadIdx.x; k < 2 * n - 1; k += kBlock) gl[k] = g[k];
+  const int wlo = o0 - tb + 1 + (n - 1);
+  const int wlen = (tb > ta) ? (o1 - o0) + (tb - ta) - 1 : 0;
+  for (int k = threadIdx.x; k < wlen; k += kBlock) gl[k] = g[wlo + k];
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t a = (int64_t)blockIdx.z * gridDim.y + blockIdx.y;
-  const bool valid_a = a < A;
-  const T* __restrict__ line = in + (valid_a ? a : 0) * (int64_t)n;
   int ii[RI];
 #pragma unroll
   for (int r = 0; r < RI; ++r) {
     const int i = (blockIdx.x * RI + r) * 64 + lane;
-    ii[r] = (i < n ? i : n - 1) + (n - 1);          // index of g[i - 0] in the LDS table
+    ii[r] = (i < n ? i : o1 - 1) + (n - 1) - wlo;   // window index of g[i - 0]
   }
-  const int o0 = blockIdx.x * RI * 64;
-  const int o1 = (o0 + RI * 64 < n) ? o0 + RI * 64 : n;
-  const int ta = (o0 - band + 1 > 0) ? o0 - band + 1 : 0;
-  const int tb = (o1 - 1 + band < n) ? o1 - 1 + band : n;
   const int jq = (tb - ta + 3) >> 2;
   const int j0 = ta + wv * jq;
   const int j1 = (j0 + jq < tb) ? j0 + jq : tb;
@@ -446,6 +275,20 @@ __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in
     }
   }
   merge_waves<T, RI>(acc);
+  if (SPLIT) {
+    if (wv == 0 && valid_a) {
+#pragma unroll
+      for (int r = 0; r < RI; ++r) {
+        const int i = (blockIdx.x * RI + r) * 64 + lane;
+        if (i < n) {
+          const int64_t e = ((int64_t)blockIdx.z * A + a) * n + i;
+          pm[e] = acc[r].m;
+          ps[e] = acc[r].s;
+        }
+      }
+    }
+    return;
+  }
   ResAcc<T> ra;
   ra.init();
   if (wv == 0 && valid_a) {
@@ -466,45 +309,24 @@ __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in
 // COST 0: log2 K = -|x_i - y_j|^2 log2(e) / eps.
 // COST 1: the WF cost with cut locus, log2 K = (2/eps) log2 cos((pi/2) d / cut)
 //         for d < cut and -inf beyond (wf_log2k).  K then has exact zeros:
-//         each block bounds its rows and every 256-column chunk by boxes and
-//         skips a chunk whose box lies at distance >= cut from the rows' box
-//         (every entry of that tile is zero; the skip is block-uniform).
+//         each wave holds 64 R consecutive rows and bounds them by a box,
+//         every 256-column chunk is bounded by 8 boxes of 32 columns, and a
+//         wave skips the column groups whose box lies at distance >= cut from
+//         its rows' box (every entry there is zero).  This pays when the
+//         points are stored in a spatially coherent order.
 // grid = (ceil(Nr / (256 R)), splits)
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T wave_min(T v) {
+__device__ __forceinline__ T lanes_min(T v, int from) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = Num<T>::fmin(v, __shfl_xor(v, o));
+  for (int o = from; o >= 1; o >>= 1) v = Num<T>::fmin(v, __shfl_xor(v, o));
   return v;
 }
 template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
+__device__ __forceinline__ T lanes_max(T v, int from) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = Num<T>::fmax(v, __shfl_xor(v, o));
+  for (int o = from; o >= 1; o >>= 1) v = Num<T>::fmax(v, __shfl_xor(v, o));
   return v;
-}
-
-// bounding box of the points a block's threads hold (invalid ones pass
-// lo = +inf, hi = -inf); every thread receives it.  Uses bx[4][2 DIM].
-template <typename T, int DIM>
-__device__ __forceinline__ void block_box(const T (&lo)[3], const T (&hi)[3], T (*bx)[6], T (&blo)[3],
-                                          T (&bhi)[3]) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    const T a = wave_min<T>(lo[d]), b = wave_max<T>(hi[d]);
-    if (lane == 0) {
-      bx[wv][2 * d] = a;
-      bx[wv][2 * d + 1] = b;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    blo[d] = Num<T>::fmin(Num<T>::fmin(bx[0][2 * d], bx[1][2 * d]), Num<T>::fmin(bx[2][2 * d], bx[3][2 * d]));
-    bhi[d] = Num<T>::fmax(Num<T>::fmax(bx[0][2 * d + 1], bx[1][2 * d + 1]),
-                          Num<T>::fmax(bx[2][2 * d + 1], bx[3][2 * d + 1]));
-  }
 }
 
 template <typename T, int DIM, int R, int COST>
@@ -516,95 +338,134 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
   if (skip_side(c, side)) return;
   using V4 = typename Vec4<T>::type;
   __shared__ V4 tile[kBlock];
-  __shared__ T rbx[4][6], cbx[4][6];
   const T sc = T(kLog2e / eps_of(c, side));
   const T ewf = T(2.0 / eps_of(c, side));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   T xi[R][DIM];
   int64_t rows[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    rows[r] = (int64_t)blockIdx.x * (kBlock * R) + r * kBlock + threadIdx.x;
+    // WF: the rows of a wave are consecutive, so its box is tight
+    rows[r] = (int64_t)blockIdx.x * (kBlock * R) +
+              (COST == 1 ? wv * (64 * R) + r * 64 + lane : r * kBlock + threadIdx.x);
     const int64_t rr = rows[r] < Nr ? rows[r] : 0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) xi[r][d] = xr[d * Nr + rr];
-  }
-  T rlo[3], rhi[3];
-  if (COST == 1) {
-    T lo[3], hi[3];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      lo[d] = Num<T>::pinf();
-      hi[d] = Num<T>::ninf();
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (rows[r] < Nr) {
-          lo[d] = Num<T>::fmin(lo[d], xi[r][d]);
-          hi[d] = Num<T>::fmax(hi[d], xi[r][d]);
-        }
-    }
-    block_box<T, DIM>(lo, hi, rbx, rlo, rhi);
   }
   Lse2<T> acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r].init();
   const int64_t cb = (int64_t)blockIdx.y * cols_per_split;
   const int64_t ce = (cb + cols_per_split < Mc) ? cb + cols_per_split : Mc;
-  for (int64_t c0 = cb; c0 < ce; c0 += kBlock) {
-    const int64_t cc = c0 + threadIdx.x;
-    V4 rec;
-    rec.x = rec.y = rec.z = T(0);
-    if (cc < ce) {
-      rec.x = yc[cc];
-      if (DIM > 1) rec.y = yc[Mc + cc];
-      if (DIM > 2) rec.z = yc[2 * Mc + cc];
-      rec.w = w[cc];
-    } else {
-      rec.w = Num<T>::ninf();
+  if constexpr (COST == 0) {
+    for (int64_t c0 = cb; c0 < ce; c0 += kBlock) {
+      const int64_t cc = c0 + threadIdx.x;
+      V4 rec;
+      rec.x = rec.y = rec.z = T(0);
+      if (cc < ce) {
+        rec.x = yc[cc];
+        if (DIM > 1) rec.y = yc[Mc + cc];
+        if (DIM > 2) rec.z = yc[2 * Mc + cc];
+        rec.w = w[cc];
+      } else {
+        rec.w = Num<T>::ninf();
+      }
+      __syncthreads();
+      tile[threadIdx.x] = rec;
+      __syncthreads();
+      const int64_t rem = ce - c0;
+      const int cnt = rem < kBlock ? (int)rem : kBlock;
+      for (int jj = 0; jj < cnt; jj += kChunk) {
+        V4 q[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) q[k] = tile[jj + k];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          T t[kChunk];
+#pragma unroll
+          for (int k = 0; k < kChunk; ++k) {
+            T d0 = xi[r][0] - q[k].x;
+            T cst = d0 * d0;
+            if (DIM > 1) { T d1 = xi[r][1] - q[k].y; cst = Num<T>::fma(d1, d1, cst); }
+            if (DIM > 2) { T d2 = xi[r][2] - q[k].z; cst = Num<T>::fma(d2, d2, cst); }
+            t[k] = Num<T>::fma(-sc, cst, q[k].w);
+          }
+          acc[r].template add<kChunk>(t);
+        }
+      }
     }
-    __syncthreads();
-    tile[threadIdx.x] = rec;
-    if (COST == 1) {
-      // box of the chunk's columns that carry mass
+  } else {
+    __shared__ T gbx[8][6];   // boxes of the 8 groups of 32 columns of a chunk
+    T rlo[3], rhi[3];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      T lo = Num<T>::pinf(), hi = Num<T>::ninf();
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (rows[r] < Nr) {
+          lo = Num<T>::fmin(lo, xi[r][d]);
+          hi = Num<T>::fmax(hi, xi[r][d]);
+        }
+      rlo[d] = lanes_min<T>(lo, 32);
+      rhi[d] = lanes_max<T>(hi, 32);
+    }
+    for (int64_t c0 = cb; c0 < ce; c0 += kBlock) {
+      const int64_t cc = c0 + threadIdx.x;
+      V4 rec;
+      rec.x = rec.y = rec.z = T(0);
+      if (cc < ce) {
+        rec.x = yc[cc];
+        if (DIM > 1) rec.y = yc[Mc + cc];
+        if (DIM > 2) rec.z = yc[2 * Mc + cc];
+        rec.w = w[cc];
+      } else {
+        rec.w = Num<T>::ninf();
+      }
+      __syncthreads();
+      tile[threadIdx.x] = rec;
+      // box of each group of 32 columns, over the columns that carry mass
       const bool live = rec.w != Num<T>::ninf();
       const T cx[3] = {rec.x, rec.y, rec.z};
-      T lo[3], hi[3], clo[3], chi[3];
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        lo[d] = live ? cx[d] : Num<T>::pinf();
-        hi[d] = live ? cx[d] : Num<T>::ninf();
-      }
-      block_box<T, DIM>(lo, hi, cbx, clo, chi);   // includes the barrier that publishes the tile
-      T gap2 = T(0);
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const T g = Num<T>::fmax(Num<T>::fmax(clo[d] - rhi[d], rlo[d] - chi[d]), T(0));
-        gap2 = Num<T>::fma(g, g, gap2);
-      }
-      // every entry of the tile is beyond the cut (an empty chunk gives nan
-      // or +inf here and is skipped as well)
-      if (!(gap2 < cut2)) continue;
-    } else {
-      __syncthreads();
-    }
-    const int64_t rem = ce - c0;
-    const int cnt = rem < kBlock ? (int)rem : kBlock;
-    for (int jj = 0; jj < cnt; jj += kChunk) {
-      V4 q[kChunk];
-#pragma unroll
-      for (int k = 0; k < kChunk; ++k) q[k] = tile[jj + k];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        T t[kChunk];
-#pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
-          T d0 = xi[r][0] - q[k].x;
-          T cst = d0 * d0;
-          if (DIM > 1) { T d1 = xi[r][1] - q[k].y; cst = Num<T>::fma(d1, d1, cst); }
-          if (DIM > 2) { T d2 = xi[r][2] - q[k].z; cst = Num<T>::fma(d2, d2, cst); }
-          if (COST == 1) t[k] = q[k].w + wf_log2k<T>(cst, a2, cut2, ewf);
-          else t[k] = Num<T>::fma(-sc, cst, q[k].w);
+        const T lo = lanes_min<T>(live ? cx[d] : Num<T>::pinf(), 16);
+        const T hi = lanes_max<T>(live ? cx[d] : Num<T>::ninf(), 16);
+        if ((lane & 31) == 0) {
+          gbx[wv * 2 + (lane >> 5)][2 * d] = lo;
+          gbx[wv * 2 + (lane >> 5)][2 * d + 1] = hi;
         }
-        acc[r].template add<kChunk>(t);
+      }
+      __syncthreads();
+      const int64_t rem = ce - c0;
+      const int cnt = rem < kBlock ? (int)rem : kBlock;
+      for (int gi = 0; gi < 8 && gi * 32 < cnt; ++gi) {
+        T gap2 = T(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const T g = Num<T>::fmax(Num<T>::fmax(gbx[gi][2 * d] - rhi[d], rlo[d] - gbx[gi][2 * d + 1]), T(0));
+          gap2 = Num<T>::fma(g, g, gap2);
+        }
+        // every entry of the group is beyond the cut (an empty box gives +inf)
+        if (!(gap2 < cut2)) continue;
+        const int je = (gi * 32 + 32 < cnt) ? gi * 32 + 32 : cnt;
+        for (int jj = gi * 32; jj < je; jj += kChunk) {
+          V4 q[kChunk];
+#pragma unroll
+          for (int k = 0; k < kChunk; ++k) q[k] = tile[jj + k];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            T t[kChunk];
+#pragma unroll
+            for (int k = 0; k < kChunk; ++k) {
+              T d0 = xi[r][0] - q[k].x;
+              T cst = d0 * d0;
+              if (DIM > 1) { T d1 = xi[r][1] - q[k].y; cst = Num<T>::fma(d1, d1, cst); }
+              if (DIM > 2) { T d2 = xi[r][2] - q[k].z; cst = Num<T>::fma(d2, d2, cst); }
+              t[k] = q[k].w + wf_log2k<T>(cst, a2, cut2, ewf);
+            }
+            acc[r].template add<kChunk>(t);
+          }
+        }
       }
     }
   }
@@ -1178,9 +1039,33 @@ void launch_grid_contig(const T* in, int64_t A, int n, const T* gtab, int side, 
   const size_t lds = (size_t)(2 * n - 1) * sizeof(T);
   const int bd = (band < 1 || band > n) ? n : band;
   if (ri == 2)
-    hipLaunchKernelGGL((k_grid_contig<T, 2>), dim3(gx, gy, gz), dim3(kBlock), lds, s, in, n, A, gtab, side, c, ep, bd);
+    hipLaunchKernelGGL((k_grid_contig<T, 2, false>), dim3(gx, gy, gz), dim3(kBlock), lds, s, in, n, A, gtab, side, c,
+                       ep, bd, (T*)nullptr, (T*)nullptr, 1);
   else
-    hipLaunchKernelGGL((k_grid_contig<T, 1>), dim3(gx, gy, gz), dim3(kBlock), lds, s, in, n, A, gtab, side, c, ep, bd);
+    hipLaunchKernelGGL((k_grid_contig<T, 1, false>), dim3(gx, gy, gz), dim3(kBlock), lds, s, in, n, A, gtab, side, c,
+                       ep, bd, (T*)nullptr, (T*)nullptr, 1);
+}
+
+// tap slices for few long lines (A x ceil(n/64) blocks well below the chip's
+// width): enough slices for ~2048 blocks, each slice at least 256 taps
+int grid_contig_splits(int n, int64_t A, int band) {
+  const int bd = (band < 1 || band > n) ? n : band;
+  const int64_t blocks1 = (int64_t)ceil_div(n, 64) * A;
+  if (blocks1 >= 1024 || A > 65535) return 1;
+  const int taps = std::min(n, 2 * bd - 1);
+  int64_t sp = (2048 + blocks1 - 1) / blocks1;
+  const int64_t maxsp = std::max(1, taps / 256);
+  return (int)std::max<int64_t>(1, std::min(sp, maxsp));
+}
+
+template <typename T>
+void launch_grid_contig_split(const T* in, int64_t A, int n, const T* gtab, int side, const Ctrl* c, int band,
+                              int nsplit, T* pm, T* ps, hipStream_t s) {
+  const int bd = (band < 1 || band > n) ? n : band;
+  const size_t lds = (size_t)(2 * n - 1) * sizeof(T);
+  EpiArgs<T> none{};
+  hipLaunchKernelGGL((k_grid_contig<T, 1, true>), dim3(ceil_div(n, 64), (unsigned)A, (unsigned)nsplit), dim3(kBlock),
+                     lds, s, in, n, A, gtab, side, c, none, bd, pm, ps, nsplit);
 }
 
 template <typename T, int DIM, int R>
@@ -1311,6 +1196,8 @@ void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w
                                        const EpiArgs<T>&, hipStream_t);                                          \
   template void launch_grid_contig<T>(const T*, int64_t, int, const T*, int, const Ctrl*, const EpiArgs<T>&,     \
                                       int, hipStream_t);                                                          \
+  template void launch_grid_contig_split<T>(const T*, int64_t, int, const T*, int, const Ctrl*, int, int, T*, T*, \
+                                            hipStream_t);                                                         \
   template void launch_dense_lse<T>(int, int, const T*, int64_t, const T*, const T*, int64_t, int, int64_t, T*,  \
                                     T*, int, const Ctrl*, const CostArgs&, hipStream_t);                          \
   template void launch_dense_epi<T>(const T*, const T*, int, int64_t, int, const Ctrl*, const EpiArgs<T>&,       \
@@ -1564,288 +1451,5 @@ template void launch_batch_lse<float>(int, int, int, const BItem*, int, int*, co
 template void launch_batch_lse<double>(int, int, int, const BItem*, int, int*, const int64_t*, const int64_t*,
                                        const double*, int64_t, const double*, int64_t, const double*, const BCtrl*,
                                        const Ctrl*, int, const EpiArgs<double>&, hipStream_t);
-
-}  // namespace uot
-
-// ---------------------------------------------------------------------------
-// Tile-factored separable pass on FP32 MFMA.  For output tile I and tap tile J
-// of 16 cells each (centres cI, cJ, offsets e = i - cI, f = j - cJ, D = cI -
-// cJ, all in cells) the 1-D kernel g(i - j) = -c (i - j)^2 (c = h^2 log2(e) /
-// eps) splits exactly as
-//   g = [-c e (e + 2D)] + [-c f (f - 2D)] - c D^2 + 2 c e f,
-// so  sum_j 2^{g + w_j} = 2^{-c e (e+2D) - c D^2 + m} * sum_j Khat[e][f] E_j,
-//   Khat[e][f] = 2^{2 c e f}  (one 16 x 16 matrix, |2 c e f| <= 2 c 7.5^2),
-//   E_j = 2^{w_j - c f (f - 2D) - m},  m = max_j (w_j - c f (f - 2D)),
-// and the inner sums of 16 lines at once are one 16x16x16 FP32 MFMA product.
-// The J tiles of an output are combined by an online log-sum-exp.  Exact up
-// to FP32 rounding; exp2 count per output: 16/16 (E) + 2 per J tile instead of
-// 16 per J tile.  Requires n % 16 == 0.
-// HALF: Khat and E in FP16, one v_mfma_f32_16x16x16f16 per J tile (FP32
-// accumulation); lane (li, q) then holds taps 4 q .. 4 q + 3 of a tile.  The
-// inputs carry FP16 rounding (2^-11 relative), so results are good to ~1e-3;
-// Khat stays finite in FP16 while 2 c 7.5^2 <= 15.
-//   STRIDED = false: in[a][j], lines a (16 per group);  out[a][i]
-//   STRIDED = true : in[a][j][b], lines (a, b), 16 consecutive b per group
-// grid = (n/16 output tiles, line groups (y, z)), 4 waves split the J tiles.
-// ---------------------------------------------------------------------------
-namespace uot {
-
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
-typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
-
-template <bool STRIDED, int TPC, bool MULTI, bool HALF>
-__global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in, int n, int64_t A, int64_t B,
-                                                     int opb, double h, int side, const Ctrl* __restrict__ c,
-                                                     EpiArgs<float> ep) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int q = lane >> 4, li = lane & 15;
-  const int nt = n / 16;
-  // logical block -> (block of opb output tiles, line group of 16 lines)
-  const int64_t lid = blockIdx.x;
-  const int nob = MULTI ? opb : 1;         // output tiles of this block
-  const int tpb = nt / nob;                // output-tile blocks per line group
-  const int64_t grp = lid / tpb;
-  const int ob = (int)(lid % tpb);
-  int64_t a, bb;
-  bool valid;
-  if (STRIDED) {
-    const int64_t gpa = (B + 15) / 16;     // groups per a
-    a = grp / gpa;
-    bb = (grp % gpa) * 16 + li;
-    valid = (a < A) && (bb < B);
-  } else {
-    a = grp * 16 + li;
-    bb = 0;
-    valid = a < A;
-  }
-  const int64_t base = valid ? (STRIDED ? a * (int64_t)n * B + bb : a * (int64_t)n) : 0;
-  const int64_t tstride = STRIDED ? B : 1;
-  // The wave's tap tiles jt = wv, wv + 4, ... are taken in chunks of TPC
-  // (4 TPC loads issued together).  The first chunk and the operands of the
-  // first epilogue this wave finishes (outputs i = I0 + 4 q + wv of line li)
-  // are loaded before the control block is read, so the latencies overlap.
-  // Tap (jt, s) of the lane's line is cell jt * 16 + f(q, s), f = 4 s + q
-  // (FP32 operand layout) or 4 q + s (FP16); tiles past the end are read at
-  // the last tile (in bounds) and replaced by -inf.  Lanes of
-  // a line past the end read line 0 unconditionally: lines never mix (MFMA
-  // columns and the max exchanges stay within a line) and their outputs are
-  // dropped, while a masked load would serialise the loads.
-  auto tapf = [&](int s) -> int { return HALF ? 4 * q + s : 4 * s + q; };
-  const float* __restrict__ pl = in + base;
-  auto load_chunk = [&](float (&w)[TPC][4], int jc) {
-#pragma unroll
-    for (int t = 0; t < TPC; ++t) {
-      const int jt = jc + 4 * t;
-      const int jtc = jt < nt ? jt : nt - 1;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const float x = pl[(int64_t)(jtc * 16 + tapf(s)) * tstride];
-        w[t][s] = jt < nt ? x : -__builtin_inff();
-      }
-    }
-  };
-  // output element of lane (li, q) in output tile o of the block, row wv
-  auto out_elem = [&](int o) -> int64_t {
-    const int ie = (ob * nob + o) * 16 + 4 * q + wv;
-    return valid ? (STRIDED ? (a * (int64_t)n + ie) * B + bb : a * (int64_t)n + ie) : 0;
-  };
-  float wv4[TPC][4];
-  load_chunk(wv4, wv);
-  int64_t eo = out_elem(0);
-  EpiIn<float> xin = epi_load<float>(eo, ep);
-  // block 0 of a launch that hosts the control step loads the residual
-  // partials and control fields now, and finishes the step at the end
-  const bool hosting = ep.host_ctl != nullptr && blockIdx.x == 0;
-  const int par = par_of(side);
-  CtrlSnap hsnap{};
-  float hm = -__builtin_inff(), hden = 0.f, hnum = 0.f;
-  if (hosting) {
-    hsnap = ctrl_snap(ep.host_ctl, par);
-    ctl_load(ep.host_parts, ep.host_nparts, hm, hden, hnum);
-  }
-  // keep those loads ahead of the branch (otherwise they may be moved past it)
-#pragma unroll
-  for (int t = 0; t < TPC; ++t)
-#pragma unroll
-    for (int s = 0; s < 4; ++s) asm volatile("" ::"v"(wv4[t][s]));
-  asm volatile("" ::"v"(xin.ld), "v"(xin.uo), "v"(xin.lp));
-  if (skip_side(c, side)) {
-    if (hosting && threadIdx.x == 0) control_skip(ep.host_ctl, par);
-    return;
-  }
-  const float cc = float(h * h * kLog2e / eps_of(c, side));
-  // Khat as MFMA A operands: entry s of the lane is Khat[i = li][k = f(q, s)]
-  float kh[4];
-  f16x4_t kh16;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const float e = float(li) - 7.5f, f = float(tapf(s)) - 7.5f;
-    kh[s] = __builtin_amdgcn_exp2f(2.f * cc * e * f);
-    kh16[s] = (_Float16)kh[s];
-  }
-  // opb > 1 only when one chunk holds all of a wave's tap tiles (the host
-  // picks opb so), so the taps stay in registers across the output tiles
-  __shared__ float smM[2][4][4][64], smS[2][4][4][64];
-  ResAcc<float> ra;
-  ra.init();
-  for (int o = 0; o < nob; ++o) {
-    const int I0 = (ob * nob + o) * 16;
-    // epilogue operands of the next output tile, in flight during this one
-    const bool more = MULTI && o + 1 < nob;
-    const int64_t eo_next = more ? out_elem(o + 1) : eo;
-    const EpiIn<float> xin_next = more ? epi_load<float>(eo_next, ep) : xin;
-    // running LSE of the 4 outputs i = 4q + r of this lane's line li (D layout)
-    float M[4], S[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      M[r] = -__builtin_inff();
-      S[r] = 0.f;
-    }
-    for (int jc = wv; jc < nt; jc += 4 * TPC) {
-      if (jc != wv) load_chunk(wv4, jc);
-      // the TPC tiles of a chunk are independent until the final merge:
-      // column factors and their line maxima first, then the products, so
-      // the exchanges and the MFMA chains of different tiles overlap
-      float D[TPC], mloc[TPC], beta[TPC][4];
-#pragma unroll
-      for (int t = 0; t < TPC; ++t) {
-        D[t] = float(I0 - (jc + 4 * t) * 16);
-        mloc[t] = -__builtin_inff();
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const float f = float(tapf(s)) - 7.5f;
-          beta[t][s] = wv4[t][s] - cc * (f * (f - 2.f * D[t]));
-          mloc[t] = fmaxf(mloc[t], beta[t][s]);
-        }
-      }
-      // max over the 16 taps of the line: the four lane rows q share a line
-#pragma unroll
-      for (int t = 0; t < TPC; ++t) mloc[t] = max_over_rows(mloc[t]);
-      f32x4_t acc[TPC];
-      float E[TPC][4];
-#pragma unroll
-      for (int t = 0; t < TPC; ++t) {
-        acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-        const float msh = (mloc[t] == -__builtin_inff()) ? 0.f : mloc[t];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) E[t][s] = __builtin_amdgcn_exp2f(beta[t][s] - msh);
-      }
-      if (HALF) {
-#pragma unroll
-        for (int t = 0; t < TPC; ++t) {
-          f16x4_t e16;
-#pragma unroll
-          for (int s = 0; s < 4; ++s) e16[s] = (_Float16)E[t][s];
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16f16(kh16, e16, acc[t], 0, 0, 0);
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int t = 0; t < TPC; ++t)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(kh[s], E[t][s], acc[t], 0, 0, 0);
-      }
-      // acc[t][r] = sum_f Khat[e_i][f] E_f for output i = 4 q + r of line li;
-      // one rescale of the running sum per chunk
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float e = float(4 * q + r) - 7.5f;
-        float al[TPC];
-        float mn = M[r];
-#pragma unroll
-        for (int t = 0; t < TPC; ++t) {
-          al[t] = (mloc[t] == -__builtin_inff()) ? -__builtin_inff()
-                                                 : (mloc[t] - cc * (e * (e + 2.f * D[t])) - cc * D[t] * D[t]);
-          mn = fmaxf(mn, al[t]);
-        }
-        const float sh = (mn == -__builtin_inff()) ? 0.f : mn;
-        float sum = S[r] * __builtin_amdgcn_exp2f(M[r] - sh);
-#pragma unroll
-        for (int t = 0; t < TPC; ++t) sum += acc[t][r] * __builtin_amdgcn_exp2f(al[t] - sh);
-        S[r] = sum;
-        M[r] = mn;
-      }
-    }
-    // merge the four waves (each saw a quarter of the J tiles); wave w then
-    // finishes output row r = w of every lane.  Two LDS buffers alternate
-    // over the output tiles, so one barrier per tile suffices.
-    const int pb = o & 1;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      smM[pb][wv][r][lane] = M[r];
-      smS[pb][wv][r][lane] = S[r];
-    }
-    __syncthreads();
-    Lse2<float> tot;
-    tot.m = smM[pb][0][wv][lane];
-    tot.s = smS[pb][0][wv][lane];
-#pragma unroll
-    for (int k = 1; k < 4; ++k) tot.merge(smM[pb][k][wv][lane], smS[pb][k][wv][lane]);
-    if (valid) epi_apply<float>(eo, tot.result(), xin, c, side, ep, ra);
-    eo = eo_next;
-    xin = xin_next;
-  }
-  epi_finish<float>(ep, ra, (int)lid);
-  if (hosting) ctl_reduce_finish(ep.host_ctl, hsnap, hm, hden, hnum, ep.host_hist, par);
-}
-
-// output tiles per block: 1 unless there are enough line groups to fill the
-// chip with fewer, longer blocks, and only while one chunk of tap tiles
-// holds all of a wave's tiles (so the taps are loaded once per block)
-static inline int tf_tpc(int n) {
-  const int per_wave = (n / 16 + 3) / 4;
-  return per_wave >= 4 ? 4 : (per_wave >= 2 ? 2 : 1);
-}
-
-static inline int tf_opb(int n, int64_t groups) {
-  const int nt = n / 16;
-  if (nt > 4 * tf_tpc(n)) return 1;
-  int opb = 1;
-  while (nt % (opb * 2) == 0 && (int64_t)(nt / (opb * 2)) * groups >= 2048) opb *= 2;
-  return opb;
-}
-
-static inline int64_t tf_groups(int64_t A, int64_t B, bool strided) {
-  return strided ? A * ((B + 15) / 16) : (A + 15) / 16;
-}
-
-int grid_tf_parts(int n, int64_t A, int64_t B, bool strided) {
-  const int64_t g = tf_groups(A, B, strided);
-  return (int)((n / 16) / tf_opb(n, g) * g);
-}
-
-template <bool ST, int TP, bool HF>
-static void launch_tf_t(unsigned blocks, int opb, const float* in, int64_t A, int n, int64_t B, double h, int side,
-                        const Ctrl* c, const EpiArgs<float>& ep, hipStream_t s) {
-  if (opb > 1)
-    hipLaunchKernelGGL((k_grid_tf<ST, TP, true, HF>), dim3(blocks), dim3(kBlock), 0, s, in, n, A, B, opb, h, side, c,
-                       ep);
-  else
-    hipLaunchKernelGGL((k_grid_tf<ST, TP, false, HF>), dim3(blocks), dim3(kBlock), 0, s, in, n, A, B, 1, h, side, c,
-                       ep);
-}
-
-template <bool ST, bool HF>
-static void launch_tf_tpc(int tpc, unsigned blocks, int opb, const float* in, int64_t A, int n, int64_t B, double h,
-                          int side, const Ctrl* c, const EpiArgs<float>& ep, hipStream_t s) {
-  if (tpc == 4) launch_tf_t<ST, 4, HF>(blocks, opb, in, A, n, B, h, side, c, ep, s);
-  else if (tpc == 2) launch_tf_t<ST, 2, HF>(blocks, opb, in, A, n, B, h, side, c, ep, s);
-  else launch_tf_t<ST, 1, HF>(blocks, opb, in, A, n, B, h, side, c, ep, s);
-}
-
-void launch_grid_tf(const float* in, int64_t A, int n, int64_t B, bool strided, bool half, double h, int side,
-                    const Ctrl* c, const EpiArgs<float>& ep, hipStream_t s) {
-  const int64_t g = tf_groups(A, B, strided);
-  const int opb = tf_opb(n, g);
-  const unsigned blocks = (unsigned)((n / 16) / opb * g);
-  const int tpc = tf_tpc(n);
-  if (strided) {
-    if (half) launch_tf_tpc<true, true>(tpc, blocks, opb, in, A, n, B, h, side, c, ep, s);
-    else launch_tf_tpc<true, false>(tpc, blocks, opb, in, A, n, B, h, side, c, ep, s);
-  } else {
-    if (half) launch_tf_tpc<false, true>(tpc, blocks, opb, in, A, n, B, h, side, c, ep, s);
-    else launch_tf_tpc<false, false>(tpc, blocks, opb, in, A, n, B, h, side, c, ep, s);
-  }
-}
 
 }  // namespace uot

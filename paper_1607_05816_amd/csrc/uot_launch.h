@@ -63,6 +63,12 @@ void launch_grid_strided(const T* in, int64_t A, int n, int64_t B, const T* gtab
 template <typename T>
 void launch_grid_contig(const T* in, int64_t A, int n, const T* gtab, int side, const Ctrl* c,
                         const EpiArgs<T>& ep, int band, hipStream_t s);
+// few long lines: tap slices (grid_contig_splits) with partial LSEs in pm / ps
+// (nsplit x A x n each), merged by launch_dense_epi over A n outputs
+int grid_contig_splits(int n, int64_t A, int band);
+template <typename T>
+void launch_grid_contig_split(const T* in, int64_t A, int n, const T* gtab, int side, const Ctrl* c, int band,
+                              int nsplit, T* pm, T* ps, hipStream_t s);
 template <typename T>
 void launch_dense_lse(int dim, int R, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, int nsplit,
                       int64_t cps, T* pm, T* ps, int side, const Ctrl* c, const CostArgs& cost, hipStream_t s);
