@@ -898,6 +898,46 @@ def flow(geom, kind: str, p0, q, dx, tau: float, eps: float, n_steps: int, iters
 
 
 # ---------------------------------------------------------------------------
+# barycentric projection (colour transfer, Sec. 5.1): the approximate
+# transport map T_i = sum_j R_ij dy_j y_j / sum_j R_ij dy_j
+# ---------------------------------------------------------------------------
+def barycentric_map_dense(C, Y, v, logdy, eps, rows=None):
+    """T (len(rows) x d) straight from the plan's definition: row i of the plan
+    w.r.t. dx is R_ij dy_j = exp((u_i + v_j - C_ij)/eps + log dy_j) and u_i
+    cancels in the ratio.  C: cost rows (len(rows) x M) or the full matrix;
+    Y: (M, d) coordinates of the points of Y.  A row with no mass gives NaN."""
+    C = np.atleast_2d(np.asarray(C, np.float64))
+    Y = np.asarray(Y, np.float64).reshape(C.shape[1], -1)
+    with np.errstate(invalid="ignore"):
+        L = np.where(np.isinf(C), -np.inf, (np.asarray(v)[None, :] - C) / eps + np.asarray(logdy)[None, :])
+    m = np.max(L, axis=1, keepdims=True)
+    with np.errstate(invalid="ignore"):
+        W = np.exp(L - np.where(np.isfinite(m), m, 0.0))
+        den = W.sum(axis=1, keepdims=True)
+        return (W @ Y) / den
+
+
+def grid_points(shape, h):
+    """Cell centres (i + 1/2) h of a grid, (size, ndim), row-major."""
+    axes = [(np.arange(n) + 0.5) * hh for n, hh in zip(shape, h)]
+    mesh = np.meshgrid(*axes, indexing="ij")
+    return np.stack([m.reshape(-1) for m in mesh], axis=1)
+
+
+def barycentric_map_rows(geom, v, logdy, eps, rows):
+    """T for the given rows of X on a grid or point geometry, one cost row at a
+    time (no N x M matrix): the definition above, for large problems."""
+    if isinstance(geom, GridGeom):
+        P = grid_points(geom.shape, geom.h)
+        Y = P
+        d2 = ((P[rows][:, None, :] - P[None, :, :]) ** 2).sum(-1)
+        C = make_cost(d2, geom.cost, geom.cut)
+    else:
+        raise TypeError("use barycentric_map_dense with the cost matrix")
+    return barycentric_map_dense(C, Y, v, logdy, eps)
+
+
+# ---------------------------------------------------------------------------
 # batches: independent problems, one after the other
 # ---------------------------------------------------------------------------
 def solve_batch(problems, F1, F2, eps, tol, max_iter, **kw):

@@ -263,3 +263,31 @@ def growth_profile_1d(seed: int, n: int = 3000, species: int = 1, floor: float =
     raw = np.stack([1.0 + 0.8 * np.sin(2 * np.pi * (rng.uniform(0.5, 2.0) * t + rng.uniform())) for _ in range(species)])
     wts = raw / raw.sum(axis=0)
     return np.maximum(prof[None, :] * wts, floor / species)
+
+
+# ---------------------------------------------------------------------------
+# colour histograms (colour-transfer experiment, Sec. 5.1): the colours of an
+# image in a cube X = [0, 1]^3 (luminance, two chrominances), binned on a
+# 64 x 32 x 32 grid with unit reference mass per bin
+# ---------------------------------------------------------------------------
+def colour_histograms(seed: int, shape=(64, 32, 32), n_pixels: int = 512 * 512, n_modes: int = 6) -> GridProblem:
+    """Two synthetic images' colour histograms.  Each image's pixel colours
+    come from a mixture of n_modes anisotropic Gaussians (luminance spread
+    widely, chrominance tightly, as in natural images), clipped to the cube
+    and binned; p, q = bin counts / n_pixels (mass 1 each) w.r.t. dx = dy = 1.
+    Most bins are empty, as in real colour histograms."""
+    rng = np.random.default_rng(seed)
+    shape = tuple(int(s) for s in shape)
+    h = tuple(1.0 / s for s in shape)
+
+    def hist():
+        w = rng.dirichlet(np.full(n_modes, 2.0))
+        lab = rng.choice(n_modes, n_pixels, p=w)
+        mu = np.column_stack([rng.uniform(0.15, 0.85, n_modes), rng.uniform(0.3, 0.7, (n_modes, 2))])
+        sd = np.column_stack([rng.uniform(0.05, 0.15, n_modes), rng.uniform(0.01, 0.04, (n_modes, 2))])
+        c = np.clip(mu[lab] + sd[lab] * rng.standard_normal((n_pixels, 3)), 0.0, 1.0 - 1e-9)
+        idx = [np.minimum((c[:, k] * shape[k]).astype(np.int64), shape[k] - 1) for k in range(3)]
+        flat = np.ravel_multi_index(idx, shape)
+        return np.bincount(flat, minlength=int(np.prod(shape))).astype(np.float64) / n_pixels
+
+    return GridProblem(shape, h, hist(), hist())

@@ -362,3 +362,63 @@ def test_flow_invariants():
     tot = [a.sum(axis=0) for a in d2]
     assert all(t.max() <= 1.0 + 1e-12 for t in tot)
     assert all(np.all(a > 0) for a in d2)
+
+
+# ---------------------------------------------------------------------------
+# barycentric projection (colour transfer)
+# ---------------------------------------------------------------------------
+def _gauss_corr(s1, s2, eps):
+    """Correlation of the entropic plan between N(0, s1^2) and N(0, s2^2) for
+    the cost |x - y|^2 and entropy weight eps: stationarity of
+    -2 c s1 s2 - (eps/2) log(1 - c^2), i.e. eps c / (1 - c^2) = 2 s1 s2."""
+    a = 2 * s1 * s2
+    return (-eps + np.sqrt(eps * eps + 4 * a * a)) / (2 * a)
+
+
+@pytest.mark.parametrize("s1,s2", [(0.05, 0.05), (0.04, 0.06)])
+def test_barycentric_map_of_gaussians(s1, s2):
+    """Balanced entropic OT between two Gaussians well inside [0, 1] (600
+    cells): the plan is Gaussian and T(x) = E[Y | X = x] = 0.5 + c (s2/s1)
+    (x - 0.5) with c from the Gaussian optimality condition."""
+    n = 600
+    h = 1.0 / n
+    xs = (np.arange(n) + 0.5) * h
+    p = np.exp(-0.5 * ((xs - 0.5) / s1) ** 2)
+    q = np.exp(-0.5 * ((xs - 0.5) / s2) ** 2)
+    p /= p.sum() * h
+    q /= q.sum() * h
+    eps = 1e-3
+    g = O.GridGeom((n,), (h,))
+    d = np.full(n, h)
+    r = O.solve(g, np.log(p), np.log(q), np.log(d), np.log(d), O.EQ, O.EQ, eps, tol=1e-13, max_iter=20000)
+    assert r["converged"]
+    rows = np.where(np.abs(xs - 0.5) < 3 * s1)[0]
+    T = O.barycentric_map_rows(g, r["v"], np.log(d), eps, rows)[:, 0]
+    c = _gauss_corr(s1, s2, eps)
+    np.testing.assert_allclose(T, 0.5 + c * (s2 / s1) * (xs[rows] - 0.5), atol=1e-8)
+
+
+def test_barycentric_map_mean_identity_and_translation():
+    """sum_i dx_i pi1_i T_i = sum_j dy_j pi2_j y_j (the definition summed over
+    the plan); every T_i lies in the hull of Y; shifting both clouds shifts T."""
+    rng = np.random.default_rng(12)
+    x, y = rng.uniform(0, 1, (40, 2)), rng.uniform(0, 1, (30, 2)) + 0.2
+    p, q = rng.uniform(0.5, 1.5, 40), rng.uniform(0.5, 1.5, 30)
+    dx, dy = np.full(40, 1 / 40), np.full(30, 1 / 30)
+    F, eps = O.KL(0.3), 0.02
+    g = O.PointsGeom(x, y)
+    r = O.solve(g, np.log(p), np.log(q), np.log(dx), np.log(dy), F, F, eps, tol=1e-12, max_iter=20000)
+    T = O.barycentric_map_dense(g.C, y, r["v"], np.log(dy), eps)
+    o = O.objective(g, p, q, dx, dy, F, F, eps, r["u"], r["v"])
+    np.testing.assert_allclose((dx * o["pi1"]) @ T, (dy * o["pi2"]) @ y, rtol=1e-9)
+    assert np.all(T >= y.min(0) - 1e-12) and np.all(T <= y.max(0) + 1e-12)
+    t = np.array([-0.7, 0.3])
+    g2 = O.PointsGeom(x + t, y + t)
+    r2 = O.solve(g2, np.log(p), np.log(q), np.log(dx), np.log(dy), F, F, eps, tol=1e-12, max_iter=20000)
+    T2 = O.barycentric_map_dense(g2.C, y + t, r2["v"], np.log(dy), eps)
+    np.testing.assert_allclose(T2, T + t, atol=1e-9)
+    # rows computed one at a time on a grid equal the dense form
+    gg = O.GridGeom((6, 5, 4), (1 / 6, 1 / 5, 1 / 4))
+    v = rng.normal(0, 0.01, 120)
+    Td = O.barycentric_map_dense(gg.dense().C, O.grid_points(gg.shape, gg.h), v, np.zeros(120), 0.05)
+    np.testing.assert_allclose(O.barycentric_map_rows(gg, v, np.zeros(120), 0.05, np.arange(120)), Td, rtol=1e-12)
