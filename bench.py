@@ -356,6 +356,37 @@ def flows_bench(U, torch, np, dev, ctx, steps=10):
     return out
 
 
+def colour_transfer_bench(U, torch, np, dev, ctx):
+    """The colour-transfer experiment's configuration (Sec. 5.1): 64 x 32 x 32
+    colour bins of [0, 1]^3 with unit reference mass, synthetic image
+    histograms, F1 = equality and F2 = 0.03 KL / RG[0, 5] / 0.2 TV, eps = 2e-3,
+    2000 iterations (as in the paper, no tolerance), FP32, then the barycentric
+    projection map; times include the device synchronisation."""
+    from paper_1607_05816_amd import synth
+    shape, h = (64, 32, 32), (1 / 64, 1 / 32, 1 / 32)
+    cp = synth.colour_histograms(0, shape=shape)
+    t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+    one = t(np.ones(cp.p.size))
+    out = {}
+    for name, F2 in (("KL0.03", U.KL(0.03)), ("RG0-5", U.RG(0.0, 5.0)), ("TV0.2", U.TV(0.2))):
+        pb = U.grid_problem(shape, h, t(cp.p), t(cp.q), one, one, U.EQ(), F2)
+        pb.workspace()
+        for rep in range(2):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            u, v, info = U.solve(pb, 2e-3, tol=0.0, max_iter=2000, check_every=100, ctx=ctx)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - a) * 1e3
+            a = time.perf_counter()
+            T = U.barycentric_map(pb, 2e-3, v, ctx=ctx)
+            torch.cuda.synchronize()
+            ms_map = (time.perf_counter() - a) * 1e3
+        out[name] = {"iters": int(info["iters"]), "ms": ms, "ms_per_iter": ms / info["iters"], "map_ms": ms_map,
+                     "map_finite": bool(torch.isfinite(T).all().item())}
+    out["workload"] = "64x32x32 colour bins, dx = dy = 1, F1 = equality, eps 2e-3, 2000 iterations, FP32"
+    return out
+
+
 def pmc_workload(U, torch, np, dev, ctx):
     """The launches the HBM-traffic counters are read on (rocprofv3 --pmc
     FETCH_SIZE, then WRITE_SIZE): a plain device copy of 256 MiB (the
@@ -545,6 +576,7 @@ def main():
         line["extensions"] = extensions(U, pr, ctx, dev, np, torch)
         line["extensions"]["roofline_wf_dense"] = wf_dense_roofline(U, torch, np, dev, ctx)
         line["extensions"]["gradient_flows"] = flows_bench(U, torch, np, dev, ctx)
+        line["extensions"]["colour_transfer"] = colour_transfer_bench(U, torch, np, dev, ctx)
     if not args.no_warm_batched:
         line["warm_batched_vs_plain"] = warm_batched(U, ctx, dev, np, torch)
     if not args.no_cpu_baseline:

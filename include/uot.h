@@ -282,6 +282,19 @@ int uot_barycenter(uot_ctx *ctx, const uot_bary_problem *pb, const uot_params *p
                    void *u, void *v, void *logh, void *ws, size_t ws_bytes,
                    uot_result *res);
 
+/* Barycentric projection (colour transfer, Sec. 5.1): the approximate
+ * transport map of a solved problem,
+ *   T_i = sum_j R_ij dy_j y_j / sum_j R_ij dy_j,   R_ij = e^{(u_i + v_j - C_ij)/eps},
+ * computed from v alone (u cancels) as Gibbs products of the X side: one for
+ * the denominator and one per coordinate with y^(k) folded into the input
+ * (two per coordinate for point clouds: positive and negative parts).  Grid
+ * coordinates are the cell centres (i + 1/2) h[k].  T: device output, dim x N,
+ * coordinate-major like x.  Since u cancels, a row with a_i = 0 still gets the
+ * projection of its row of K(b dy); T is NaN only where K(b dy) vanishes.  The
+ * workspace is that of uot_workspace_size(pb); eps is the eps v belongs to. */
+int uot_barycentric_map(uot_ctx *ctx, const uot_problem *pb, double eps, const void *v, void *T,
+                        void *ws, size_t ws_bytes);
+
 /* ---------------------------------------------------------------------------
  * Gradient flows (Sec. 5.3): n_steps time steps of size tau, each one problem
  * of the generic form on X = Y solved by the scaling iteration (to pr->tol or

@@ -869,6 +869,57 @@ int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u,
 }
 
 // ---------------------------------------------------------------------------
+// barycentric projection (colour transfer, Sec. 5.1): T = R (y dy) / R dy
+// from v alone (u cancels), as dim + 1 Gibbs products of the X side (2 dim + 1
+// for points: positive and negative parts of each coordinate)
+// ---------------------------------------------------------------------------
+template <typename T>
+int map_t(uot_ctx* ctx, const uot_problem* pb, double eps, const T* v, T* Tout, char* ws, size_t wsb) {
+  Plan P;
+  int rc = make_plan(P, pb->dtype, pb->geom, 1, 1, 0, eps);
+  if (rc) return rc;
+  if ((rc = check_ws(P, ws, wsb))) return rc;
+  if (!v || !Tout) return fail(UOT_E_INVALID, "v and T are required");
+  if (!(eps > 0 && std::isfinite(eps))) return fail(UOT_E_INVALID, "eps must be finite and > 0");
+  hipStream_t s = ctx->work;
+  if ((rc = begin(ctx))) return rc;
+  Bufs<T> B = carve<T>(P, ws);
+  const Ctrl init = make_ctrl(eps, 0, 0, 0, 0, 1);
+  launch_ctrl_init(B.ctrl, init, s);
+  launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
+  if (P.geom == UOT_GEOM_GRID)
+    for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, 1, P.cost, s);
+  launch_init_pot<T>(v, B.logdy, nullptr, B.wv, P.M, P.M, B.ctrl, 0, s);
+  EpiArgs<T> raw{};
+  raw.mode = EPI_RAW;
+  auto product = [&](const T* w, T* out) {
+    raw.out = out;
+    if (P.geom == UOT_GEOM_GRID) grid_chain<T>(P, w, B.gtab, 0, B.ctrl, raw, B.t1, B.t2, s);
+    else dense_half<T>(P, pb->geom, 0, w, B, B.ctrl, raw, s);
+  };
+  product(B.wv, B.t3);   // log2 of sum_j R_ij dy_j (up to the factor a_i)
+  int64_t stride = 1;
+  for (int k = P.dim - 1; k >= 0; --k) {
+    T* num = Tout + (int64_t)k * P.N;
+    if (P.geom == UOT_GEOM_GRID) {
+      launch_coord_weight<T>(B.wv, B.logq, P.M, stride, P.n[k], P.h[k], nullptr, 1, s);
+      product(B.logq, num);
+      launch_map_finish<T>(num, B.t3, nullptr, P.N, s);
+      stride *= P.n[k];
+    } else {
+      const T* yk = static_cast<const T*>(pb->geom.y) + (int64_t)k * P.M;
+      launch_coord_weight<T>(B.wv, B.logq, P.M, 1, 1, 0.0, yk, 1, s);
+      product(B.logq, num);
+      launch_coord_weight<T>(B.wv, B.logq, P.M, 1, 1, 0.0, yk, -1, s);
+      product(B.logq, B.wu);
+      launch_map_finish<T>(num, B.t3, B.wu, P.N, s);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
+// ---------------------------------------------------------------------------
 // gradient flows (Sec. 5.3): a sequence of steps, each one problem of the
 // generic form solved by the scaling iteration, warm-started with the previous
 // step's v; the next density is read off the optimal coupling on the device
@@ -1488,6 +1539,18 @@ int uot_solve_mass(uot_ctx* ctx, const uot_problem* pb, const uot_div* F3, doubl
                           res, 1, &m, log_z);
   return solve_t<double>(ctx, pb, pr, static_cast<double*>(u), static_cast<double*>(v), static_cast<char*>(ws), wsb,
                          res, 1, &m, log_z);
+}
+
+int uot_barycentric_map(uot_ctx* ctx, const uot_problem* pb, double eps, const void* v, void* T, void* ws,
+                        size_t wsb) {
+  if (!ctx || !pb) return fail(UOT_E_INVALID, "ctx and problem are required");
+  if (!pb->dy) return fail(UOT_E_INVALID, "dy is required");
+  if (pb->dtype == UOT_F32)
+    return map_t<float>(ctx, pb, eps, static_cast<const float*>(v), static_cast<float*>(T), static_cast<char*>(ws), wsb);
+  if (pb->dtype == UOT_F64)
+    return map_t<double>(ctx, pb, eps, static_cast<const double*>(v), static_cast<double*>(T), static_cast<char*>(ws),
+                         wsb);
+  return fail(UOT_E_INVALID, "dtype must be UOT_F32 or UOT_F64");
 }
 
 int uot_flow_workspace_size(const uot_flow_problem* fp, size_t* bytes) {

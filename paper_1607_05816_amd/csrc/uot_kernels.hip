@@ -23,6 +23,7 @@
 namespace uot {
 
 constexpr int kChunk = 8;       // terms per online-max rescale
+static inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 constexpr int kMaxLine = 4096;  // longest grid axis (LDS table of the contiguous pass)
 
 template <typename T> struct Vec4;
@@ -566,6 +567,64 @@ __global__ void k_res_reduce(const ResPart* __restrict__ part, int nparts, doubl
 // continue a stopped solve with a new tolerance (the second phase of a
 // mixed-precision grid solve): clear the stop and skip flags, keep the
 // iteration count, residual history and eps slots
+// ---------------------------------------------------------------------------
+// barycentric projection (colour transfer): T_i = sum_j R_ij dy_j y_j /
+// sum_j R_ij dy_j as a ratio of two Gibbs products of the same row, the
+// numerator's input weighted by one coordinate of y_j (log domain: its log2
+// added to w).  Grid coordinates (cell centres) are positive; point
+// coordinates are split into positive and negative parts.
+// ---------------------------------------------------------------------------
+// out[j] = w[j] + log2 y_j^(k): grid cell centre (j_k + 1/2) h_k with
+// j_k = (j / stride) % nk, or, for points (yk != null), log2 max(sign yk[j], 0)
+template <typename T>
+__global__ void k_coord_weight(const T* __restrict__ w, T* __restrict__ out, int64_t M, int64_t stride, int64_t nk,
+                               double hk, const T* __restrict__ yk, int sign) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  T lc;
+  if (yk) {
+    const T y = T(sign) * yk[j];
+    lc = y > T(0) ? Num<T>::log2(y) : Num<T>::ninf();
+  } else {
+    const int64_t jk = (j / stride) % nk;
+    lc = T(::log2((double(jk) + 0.5) * hk));
+  }
+  out[j] = w[j] + lc;
+}
+
+// T[i] = 2^{num[i] - den[i]} (- 2^{neg[i] - den[i]}); NaN where the row of
+// the plan vanishes (den = -inf)
+template <typename T>
+__global__ void k_map_finish(T* __restrict__ num, const T* __restrict__ den, const T* __restrict__ neg, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const T d = den[i];
+  if (d == Num<T>::ninf()) {
+    num[i] = T(__builtin_nan(""));
+    return;
+  }
+  T t = Num<T>::exp2(num[i] - d);
+  if (neg) t -= Num<T>::exp2(neg[i] - d);
+  num[i] = t;
+}
+
+template <typename T>
+void launch_coord_weight(const T* w, T* out, int64_t M, int64_t stride, int64_t nk, double hk, const T* yk, int sign,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_coord_weight<T>, dim3(ceil_div(M, kBlock)), dim3(kBlock), 0, s, w, out, M, stride, nk, hk, yk,
+                     sign);
+}
+template <typename T>
+void launch_map_finish(T* num, const T* den, const T* neg, int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_map_finish<T>, dim3(ceil_div(N, kBlock)), dim3(kBlock), 0, s, num, den, neg, N);
+}
+template void launch_coord_weight<float>(const float*, float*, int64_t, int64_t, int64_t, double, const float*, int,
+                                         hipStream_t);
+template void launch_coord_weight<double>(const double*, double*, int64_t, int64_t, int64_t, double, const double*, int,
+                                          hipStream_t);
+template void launch_map_finish<float>(float*, const float*, const float*, int64_t, hipStream_t);
+template void launch_map_finish<double>(double*, const double*, const double*, int64_t, hipStream_t);
+
 // after a stopped solve, slot 0 is made valid again for one more product at
 // the eps of the last iteration (a stopped solve marks its slots skipped)
 __global__ void k_ctrl_post(Ctrl* __restrict__ c) {
@@ -957,7 +1016,6 @@ __global__ void k_gtab_cost(T* __restrict__ tab, int n, double h, double eps, Co
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 template <typename T>
 void launch_log(const T* src, T* dst, int64_t n, int zero_is_ninf, hipStream_t s) {

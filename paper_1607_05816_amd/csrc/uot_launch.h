@@ -80,6 +80,10 @@ void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t
 void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s);
 void launch_ctrl_resume(Ctrl* c, double tol, hipStream_t s);
 // slot 0 valid again after a stopped solve (one more product at the last eps)
+template <typename T>
+void launch_coord_weight(const T* w, T* out, int64_t M, int64_t stride, int64_t nk, double hk, const T* yk, int sign,
+                         hipStream_t s);
+template <typename T> void launch_map_finish(T* num, const T* den, const T* neg, int64_t N, hipStream_t s);
 void launch_ctrl_post(Ctrl* c, hipStream_t s);
 template <typename T>
 void launch_growth_combine(const T* T2, int nm, int64_t size, const DivDev& F, const T* logq, const T* logdy, T* v,

@@ -141,6 +141,7 @@ def lib():
         "uot_solve_batched": (c_i32, [c_vp, P(UotBatchProblem), P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t,
                                       P(UotBatchResult)]),
         "uot_flow_workspace_size": (c_i32, [P(UotFlowProblem), P(ctypes.c_size_t)]),
+        "uot_barycentric_map": (c_i32, [c_vp, P(UotProblem), c_dbl, c_vp, c_vp, c_vp, ctypes.c_size_t]),
         "uot_flow": (c_i32, [c_vp, P(UotFlowProblem), P(UotParams), c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t,
                              P(UotResult)]),
     }
@@ -421,6 +422,18 @@ def objective(prob: Problem, eps, u, v, ctx: Optional[Context] = None, marginals
     if marginals:
         d["pi1"], d["pi2"] = pi1, pi2
     return d
+
+
+def barycentric_map(prob: Problem, eps, v, ctx: Optional[Context] = None):
+    """Barycentric projection T (dim x N) of the plan of (u, v) (u cancels):
+    T_i = sum_j R_ij dy_j y_j / sum_j R_ij dy_j; NaN only where K(b dy) vanishes."""
+    ctx = ctx or default_context()
+    _dev(v, prob.dtype, prob.M, "v")
+    T = torch.empty(prob.c.geom.dim, prob.N, dtype=prob.dtype, device=v.device)
+    ws = prob.workspace()
+    _check(lib().uot_barycentric_map(ctx.handle, ctypes.byref(prob.c), float(eps), _ptr(v), _ptr(T), _ptr(ws),
+                                     ws.numel()), "uot_barycentric_map", False)
+    return T
 
 
 def solve_mass(prob: Problem, F3: Div, mass, eps, ctx: Optional[Context] = None, record=False, **kw):
