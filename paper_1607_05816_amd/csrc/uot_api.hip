@@ -842,6 +842,7 @@ int bary_t(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* pr, T* u,
   double asum = 0;
   for (int k = 0; k < pb->n; ++k) {
     la.v[k] = std::log(pb->alpha[k]);
+    la.a[k] = pb->alpha[k];
     asum += pb->alpha[k];
   }
   const DivDev F2 = to_dev(pb->F2);

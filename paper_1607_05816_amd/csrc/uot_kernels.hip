@@ -683,14 +683,27 @@ __global__ void k_ctrl_init(Ctrl* __restrict__ c, Ctrl init) {
 // first breakpoint where the function is >= 0, linear interpolation from the
 // breakpoint before it.  h = 0 (TV: A0 >= weight of the others; RG: some
 // s_k = 0).  t2: log2 s_k at stride `stride`.
+
+// breakpoint w (0, 1) of input k, natural log t: TV t -+ d, RG t - log b2 / t - log b1
 template <typename T>
-__device__ T bary_f(const T* __restrict__ t2, int64_t stride, int n, const double* lav, bool tv, T a0, T d, T lb1,
-                    T lb2, T b1, T b2, bool has_lo, T x) {
+__device__ __forceinline__ T bary_break(bool tv, T t, int w, T d, T lb1, T lb2) {
+  return tv ? (w == 0 ? t - d : t + d) : (w == 0 ? t - lb2 : t - lb1);
+}
+
+// TV / RG barycentre combine with L lanes per cell (L a power of two, 2..64):
+// each lane evaluates f at its share of the cell's breakpoints, segmented
+// shuffle reductions over the L lanes find the smallest breakpoint with
+// f >= 0 and the largest one below it, and f is linear in between.  Spreading
+// the breakpoints over lanes replaces one long dependent loop per cell, which
+// left a launch of a few blocks waiting on memory.
+template <typename T>
+__device__ __forceinline__ T bary_fa(const T* __restrict__ t2, int64_t stride, int n, const BaryW& la, bool tv, T a0,
+                                     T d, T lb1, T lb2, T b1, T b2, bool has_lo, T x) {
   T acc = tv ? a0 : T(0);
   for (int k = 0; k < n; ++k) {
     const T t = t2[k * stride] * T(kLn2);
     if (t == Num<T>::ninf()) continue;
-    const T al = T(::exp(lav[k]));
+    const T al = T(la.a[k]);
     if (tv) {
       const T y = (x - t) / d;
       acc += al * (y < T(-1) ? T(-1) : (y > T(1) ? T(1) : y));
@@ -704,67 +717,103 @@ __device__ T bary_f(const T* __restrict__ t2, int64_t stride, int n, const doubl
   return acc;
 }
 
-// breakpoint w (0, 1) of input k, natural log t: TV t -+ d, RG t - log b2 / t - log b1
-template <typename T>
-__device__ __forceinline__ T bary_break(bool tv, T t, int w, T d, T lb1, T lb2) {
-  return tv ? (w == 0 ? t - d : t + d) : (w == 0 ? t - lb2 : t - lb1);
-}
-
-template <typename T>
-__device__ T bary_root(const T* __restrict__ t2, int64_t stride, int n, const BaryW& la, const DivDev& F, T eps) {
-  const bool tv = F.kind == 2;
-  T a0 = T(0), a1 = T(0);
-  for (int k = 0; k < n; ++k) {
-    const T al = T(::exp(la.v[k]));
-    if (t2[k * stride] == Num<T>::ninf()) a0 += al;
-    else a1 += al;
-  }
-  if (tv ? (a0 >= a1) : (a0 > T(0))) return Num<T>::ninf();
-  if (!tv) {
-    // every input within one band [b1 h, b2 h]: the function is zero on
-    // [max log s_k - log b2, min log s_k - log b1]; return its left end
-    // exactly (at a breakpoint the sum may round to -0)
-    T tmax = Num<T>::ninf(), tmin = Num<T>::pinf();
-    for (int k = 0; k < n; ++k) {
-      const T t = t2[k * stride] * T(kLn2);
+template <typename T, int L>
+__global__ __launch_bounds__(kBlock) void k_bary_root(const T* __restrict__ T2, int nm, int64_t size, BaryW la,
+                                                       DivDev F2, const T* __restrict__ logdy, T* __restrict__ v,
+                                                       T* __restrict__ w, T* __restrict__ logh_out,
+                                                       const Ctrl* __restrict__ c, int side) {
+  if (skip_side(c, side)) return;
+  const int sub = threadIdx.x & (L - 1);
+  const int64_t j = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / L;
+  const bool valid = j < size;
+  const T* __restrict__ t2 = T2 + (valid ? j : size - 1);   // every lane takes part in the shuffles
+  const T eps = T(eps_of(c, side));
+  const T eps_w = T(eps_next_of(c, side));
+  const bool tv = F2.kind == 2;
+  const bool lo = F2.has_lo != 0;
+  T a0 = T(0), a1 = T(0), tmax = Num<T>::ninf(), tmin = Num<T>::pinf();
+  for (int k = 0; k < nm; ++k) {
+    const T t = t2[k * size] * T(kLn2);
+    const T al = T(la.a[k]);
+    if (t == Num<T>::ninf()) {
+      a0 += al;
+    } else {
+      a1 += al;
       tmax = t > tmax ? t : tmax;
       tmin = t < tmin ? t : tmin;
     }
-    const T left = tmax - T(F.log_beta);
-    if (!F.has_lo || left <= tmin - T(F.log_alpha)) return left;
   }
-  const T d = tv ? T(F.lam) / eps : T(0);
-  const T lb1 = F.has_lo ? T(F.log_alpha) : T(0), lb2 = T(F.log_beta);
-  const T b1 = F.has_lo ? T(::exp(F.log_alpha)) : T(0), b2 = T(::exp(F.log_beta));
-  const bool lo = F.has_lo != 0;
-  const int per = tv ? 2 : (lo ? 2 : 1);
-  // first breakpoint (in value) where the function is >= 0 ...
-  T bhi = Num<T>::pinf(), fhi = T(0);
-  for (int q = 0; q < n * per; ++q) {
-    const int k = q / per, w = q % per;
-    const T t = t2[k * stride] * T(kLn2);
-    if (t == Num<T>::ninf()) continue;
-    const T b = bary_break<T>(tv, t, w, d, lb1, lb2);
-    if (b < bhi) {
-      const T fb = bary_f<T>(t2, stride, n, la.v, tv, a0, d, lb1, lb2, b1, b2, lo, b);
-      if (fb >= T(0)) {
-        bhi = b;
-        fhi = fb;
-      }
+  // the cases with a closed answer: no mass (-inf), or RG with every input in
+  // one band (the left end of the zero interval, exactly)
+  bool closed = false;
+  T logh = T(0);
+  if (tv ? (a0 >= a1) : (a0 > T(0))) {
+    closed = true;
+    logh = Num<T>::ninf();
+  } else if (!tv) {
+    const T left = tmax - T(F2.log_beta);
+    if (!lo || left <= tmin - T(F2.log_alpha)) {
+      closed = true;
+      logh = left;
     }
   }
-  // ... and the breakpoint before it; the function is linear in between
-  T blo = Num<T>::ninf();
-  for (int q = 0; q < n * per; ++q) {
-    const int k = q / per, w = q % per;
-    const T t = t2[k * stride] * T(kLn2);
+  const T d = tv ? T(F2.lam) / eps : T(0);
+  const T lb1 = lo ? T(F2.log_alpha) : T(0), lb2 = T(F2.log_beta);
+  const T b1 = lo ? T(::exp(F2.log_alpha)) : T(0), b2 = T(::exp(F2.log_beta));
+  const int per = tv ? 2 : (lo ? 2 : 1);
+  const int nbp = nm * per;
+  // smallest breakpoint with f >= 0 (and f there)
+  T bhi = Num<T>::pinf(), fhi = T(0);
+  for (int q = sub; q < nbp; q += L) {
+    const int k = q / per, wq = q % per;
+    const T t = t2[k * size] * T(kLn2);
     if (t == Num<T>::ninf()) continue;
-    const T b = bary_break<T>(tv, t, w, d, lb1, lb2);
+    const T b = bary_break<T>(tv, t, wq, d, lb1, lb2);
+    const T fb = bary_fa<T>(t2, size, nm, la, tv, a0, d, lb1, lb2, b1, b2, lo, b);
+    if (fb >= T(0) && b < bhi) {
+      bhi = b;
+      fhi = fb;
+    }
+  }
+#pragma unroll
+  for (int o = L / 2; o >= 1; o >>= 1) {
+    const T ob = __shfl_xor(bhi, o), of = __shfl_xor(fhi, o);
+    if (ob < bhi || (ob == bhi && of < fhi)) {
+      bhi = ob;
+      fhi = of;
+    }
+  }
+  // largest breakpoint below it
+  T blo = Num<T>::ninf();
+  for (int q = sub; q < nbp; q += L) {
+    const int k = q / per, wq = q % per;
+    const T t = t2[k * size] * T(kLn2);
+    if (t == Num<T>::ninf()) continue;
+    const T b = bary_break<T>(tv, t, wq, d, lb1, lb2);
     if (b < bhi && b > blo) blo = b;
   }
-  if (blo == Num<T>::ninf()) return bhi;
-  const T flo = bary_f<T>(t2, stride, n, la.v, tv, a0, d, lb1, lb2, b1, b2, lo, blo);
-  return blo + (T(0) - flo) * (bhi - blo) / (fhi - flo);
+#pragma unroll
+  for (int o = L / 2; o >= 1; o >>= 1) {
+    const T ob = __shfl_xor(blo, o);
+    blo = ob > blo ? ob : blo;
+  }
+  if (!closed) {
+    if (blo == Num<T>::ninf()) {
+      logh = bhi;
+    } else {
+      const T flo = bary_fa<T>(t2, size, nm, la, tv, a0, d, lb1, lb2, b1, b2, lo, blo);
+      logh = blo + (T(0) - flo) * (bhi - blo) / (fhi - flo);
+    }
+  }
+  if (!valid) return;
+  if (sub == 0 && logh_out) logh_out[j] = logh;
+  const T ld = logdy[j];
+  for (int k = sub; k < nm; k += L) {
+    const T S = T2[k * size + j] * T(kLn2);
+    const T vn = proxdiv_pot<T>(F2, logh, S, eps);
+    v[k * size + j] = vn;
+    w[k * size + j] = (S == Num<T>::ninf()) ? Num<T>::ninf() : (vn / eps_w + ld) * T(kLog2e);
+  }
 }
 
 template <typename T>
@@ -778,10 +827,8 @@ __global__ __launch_bounds__(kBlock) void k_bary_combine(const T* __restrict__ T
   if (j >= size) return;
   const T eps = T(eps_of(c, side));
   const T eps_w = T(eps_next_of(c, side));
-  T logh;
-  if (F2.kind == 2 || F2.kind == 3) {
-    logh = bary_root<T>(T2 + j, size, nm, log_alpha, F2, eps);
-  } else if (F2.kind == 0) {
+  T logh;   // (TV and RG barycentres run in k_bary_root)
+  if (F2.kind == 0) {
     double acc = 0.0, asum = 0.0;
     for (int k = 0; k < nm; ++k) {
       const double al = ::exp(log_alpha.v[k]);
@@ -1214,6 +1261,25 @@ template <typename T>
 void launch_bary_combine(const T* T2, int nm, int64_t size, const BaryW& log_alpha, double log_sum_alpha,
                          const DivDev& F2, const T* logdy, T* v, T* w, T* logh, const Ctrl* c, int side,
                          hipStream_t s) {
+  if (F2.kind == 2 || F2.kind == 3) {
+    const int nbp = nm * ((F2.kind == 2 || F2.has_lo) ? 2 : 1);
+    int L = 2;
+    while (L < nbp && L < 64) L *= 2;
+    const unsigned blocks = ceil_div(size * L, kBlock);
+#define UOT_BR(LL)                                                                                               \
+  hipLaunchKernelGGL((k_bary_root<T, LL>), dim3(blocks), dim3(kBlock), 0, s, T2, nm, size, log_alpha, F2, logdy, v, w, \
+                     logh, c, side)
+    switch (L) {
+      case 2: UOT_BR(2); break;
+      case 4: UOT_BR(4); break;
+      case 8: UOT_BR(8); break;
+      case 16: UOT_BR(16); break;
+      case 32: UOT_BR(32); break;
+      default: UOT_BR(64); break;
+    }
+#undef UOT_BR
+    return;
+  }
   hipLaunchKernelGGL(k_bary_combine<T>, dim3(ceil_div(size, kBlock)), dim3(kBlock), 0, s, T2, nm, size, log_alpha,
                      log_sum_alpha, F2, logdy, v, w, logh, c, side);
 }

@@ -97,6 +97,7 @@ void launch_mass_update(Ctrl* c, const T* mass_m, const T* mass_s, int nparts, c
 constexpr int kMaxBary = 64;
 struct BaryW {
   double v[kMaxBary];   // log alpha_k
+  double a[kMaxBary];   // alpha_k
 };
 template <typename T>
 void launch_bary_combine(const T* T2, int nm, int64_t size, const BaryW& log_alpha, double log_sum_alpha,

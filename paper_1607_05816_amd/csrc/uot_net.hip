@@ -589,6 +589,7 @@ int uot_bary_estimate(uot_ctx* ctx, const float* p, int n, int64_t size, const d
   for (int k = 0; k < n; ++k) {
     if (!(alpha[k] > 0)) return fail(UOT_E_INVALID, "alpha_k must be > 0");
     la.v[k] = std::log(alpha[k]);
+    la.a[k] = alpha[k];
     asum += alpha[k];
   }
   int rc = begin(ctx);
