@@ -167,7 +167,14 @@ typedef struct uot_params {
                             levels off near 2e-5), 4 mixed precision: the
                             passes of 3 until the residual reaches 1e-4, then
                             those of 2 down to tol (FP32 accuracy)         */
-  int32_t reserved;
+  int32_t dense_kernel;  /* point clouds: 0 default (1), 1 direct log-sum-exp
+                            product, 2 tile-factored product (FP32, squared
+                            Euclidean cost): both clouds are put in Morton
+                            order on the device once per solve, tile pairs
+                            factor exactly (w_j - c|x_i - y_j|^2 = beta_jI +
+                            alpha_iJ + 2c e_i.f_j) and wide tile pairs are
+                            summed directly; results come back in the
+                            caller's order                                  */
 } uot_params;
 
 typedef struct uot_result {

@@ -135,9 +135,10 @@ struct Plan {
   int split1d = 1;                           // 1-D grids: tap slices of the (direct) pass
   mutable void* split_pm = nullptr;          // ... their partial LSEs (set by carve)
   mutable void* split_ps = nullptr;
+  bool dense_tf = false;                     // points: tile-factored product on Morton-ordered copies
   // workspace offsets
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
-      o_gcost, o_obj, o_scal, o_mass, total;
+      o_gcost, o_obj, o_scal, o_mass, o_xs, o_ys, o_permx, o_permy, o_code, o_box, o_us, o_vs, total;
   int64_t obj_doubles = 0;
 };
 
@@ -172,7 +173,14 @@ void dense_config(Plan& P, int side) {
   const int64_t Mc = side == 0 ? P.M : P.N;
   const int R = (P.dtype == UOT_F32) ? 2 : 1;
   const int64_t rt = (Nr + 256 * R - 1) / (256 * R);
-  int64_t sp = (2048 + rt - 1) / rt;
+  // blocks to aim for: 2048 (8 resident per compute unit); the tile-factored
+  // kernel holds more registers and balances better over more, smaller blocks
+  static const int tf_blocks = [] {
+    const char* e = getenv("UOT_DENSE_TF_BLOCKS");
+    return e ? atoi(e) : 2048;
+  }();
+  const int64_t target = P.dense_tf && tf_blocks > 0 ? tf_blocks : 2048;
+  int64_t sp = (target + rt - 1) / rt;
   const int64_t maxsp = (Mc + 31) / 32;
   if (sp > maxsp) sp = maxsp;
   if (sp < 1) sp = 1;
@@ -184,8 +192,10 @@ void dense_config(Plan& P, int side) {
   P.cps[side] = cps;
 }
 
-int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_kernel = 0, double eps_min = 0.0) {
+int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_kernel = 0, double eps_min = 0.0,
+              int dense_kernel = 1) {
   if (dtype != UOT_F32 && dtype != UOT_F64) return fail(UOT_E_INVALID, "dtype must be UOT_F32 or UOT_F64");
+  if (dense_kernel < 0 || dense_kernel > 2) return fail(UOT_E_INVALID, "dense_kernel must be 0 .. 2");
   if (grid_kernel < 0 || grid_kernel > 4) return fail(UOT_E_INVALID, "grid_kernel must be 0 .. 4");
   P.gk = grid_kernel == 0 ? (dtype == UOT_F32 ? 2 : 1) : grid_kernel;
   P.dtype = dtype;
@@ -209,6 +219,9 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
     if (nb != 1) return fail(UOT_E_UNSUPPORTED, "several fields need a grid geometry");
     P.N = g.N;
     P.M = g.M;
+    P.dense_tf = dense_kernel == 2;
+    if (P.dense_tf && (dtype != UOT_F32 || g.cost != UOT_COST_SQEUCLID))
+      return fail(UOT_E_UNSUPPORTED, "the tile-factored dense product takes FP32 and the squared Euclidean cost");
   } else if (g.kind == UOT_GEOM_GRID) {
     int64_t sz = 1;
     for (int k = 0; k < g.dim; ++k) {
@@ -251,9 +264,16 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
   P.o_t2 = take(e * F);
   P.o_t3 = take(e * F);
   if (P.geom == UOT_GEOM_POINTS) {
-    dense_config(P, 0);
-    dense_config(P, 1);
-    const int64_t np = std::max((int64_t)P.splits[0] * P.N, (int64_t)P.splits[1] * P.M);
+    // partials sized for both product kernels, so one workspace size query
+    // covers every dense_kernel choice
+    int64_t np = 0;
+    const bool tf = P.dense_tf;
+    for (int pass = 0; pass < 2; ++pass) {
+      P.dense_tf = pass == 0 ? !tf : tf;
+      dense_config(P, 0);
+      dense_config(P, 1);
+      np = std::max(np, std::max((int64_t)P.splits[0] * P.N, (int64_t)P.splits[1] * P.M));
+    }
     P.o_pm = take(e * np);
     P.o_ps = take(e * np);
     P.nparts_x = (int)((P.N + 255) / 256);
@@ -277,6 +297,16 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
   P.obj_doubles = 4 * ((std::max(P.N, P.M) + 255) / 256) * 2 + 8 * ((std::max(P.N, P.M) + 255) / 256);
   P.o_obj = take(sizeof(double) * P.obj_doubles);
   P.o_scal = take(sizeof(double) * 8);
+  // Morton-ordered copies of point clouds (tile-factored product)
+  const bool pts = P.geom == UOT_GEOM_POINTS;
+  P.o_xs = take(pts ? e * P.dim * P.N : 0);
+  P.o_ys = take(pts ? e * P.dim * P.M : 0);
+  P.o_permx = take(pts ? sizeof(int32_t) * P.N : 0);
+  P.o_permy = take(pts ? sizeof(int32_t) * P.M : 0);
+  P.o_code = take(pts ? sizeof(uint32_t) * std::max(P.N, P.M) : 0);
+  P.o_box = take(pts ? e * 6 : 0);
+  P.o_us = take(pts ? e * P.N : 0);
+  P.o_vs = take(pts ? e * P.M : 0);
   P.total = o;
   return UOT_OK;
 }
@@ -438,6 +468,12 @@ void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Buf
   const int64_t Nr = half == 0 ? P.N : P.M;
   const int64_t Mc = half == 0 ? P.M : P.N;
   timed(0, [&] {
+    if constexpr (std::is_same<T, float>::value) {
+      if (P.dense_tf) {
+        launch_dense_tf(P.dim, rows, Nr, cols, w_cols, Mc, P.splits[half], P.cps[half], B.pm, B.ps, side, c, s);
+        return;
+      }
+    }
     launch_dense_lse<T>(P.dim, P.R[half], rows, Nr, cols, w_cols, Mc, P.splits[half], P.cps[half], B.pm, B.ps, side,
                         c, P.cost, s);
   });
@@ -610,6 +646,40 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
   return UOT_OK;
 }
 
+// Morton-ordered copies of both clouds for the tile-factored dense product:
+// coordinates gathered into the workspace (permutations kept there), the
+// problem returned points at the copies
+template <typename T>
+uot_problem sorted_points(const Plan& P, const uot_problem& pb, char* ws, hipStream_t s) {
+  T* xs = at<T>(ws, P.o_xs);
+  T* ys = at<T>(ws, P.o_ys);
+  int32_t* px = at<int32_t>(ws, P.o_permx);
+  int32_t* py = at<int32_t>(ws, P.o_permy);
+  uint32_t* code = at<uint32_t>(ws, P.o_code);
+  T* box = at<T>(ws, P.o_box);
+  const T* x = static_cast<const T*>(pb.geom.x);
+  const T* y = static_cast<const T*>(pb.geom.y);
+  launch_spatial_order<T>(x, P.N, P.dim, box, code, px, s);
+  launch_spatial_order<T>(y, P.M, P.dim, box, code, py, s);
+  launch_gather<T>(x, px, P.N, P.dim, xs, s);
+  launch_gather<T>(y, py, P.M, P.dim, ys, s);
+  uot_problem q = pb;
+  q.geom.x = xs;
+  q.geom.y = ys;
+  return q;
+}
+
+// log of a caller array, in the caller's order or gathered by perm
+template <typename T>
+void log_into(const void* src, T* dst, int64_t n, int zero_is_ninf, const int32_t* perm, T* tmp, hipStream_t s) {
+  if (!perm) {
+    launch_log<T>(static_cast<const T*>(src), dst, n, zero_is_ninf, s);
+    return;
+  }
+  launch_log<T>(static_cast<const T*>(src), tmp, n, zero_is_ninf, s);
+  launch_gather<T>(tmp, perm, n, 1, dst, s);
+}
+
 // total-mass penalty of Algorithm 4: F3 on the one-point space, log m0
 struct MassOpt {
   DivDev F3;
@@ -621,13 +691,28 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
             uot_result* res, int nb = 1, const MassOpt* mass = nullptr, double* log_z = nullptr) {
   Plan P;
   const bool anneal = pr->eps0 > pr->eps && pr->eps_stages > 0 && pr->iters_per_stage > 0;
-  int rc = make_plan(P, pb->dtype, pb->geom, nb, anneal ? pr->eps_stages + 1 : 1, pr->grid_kernel, pr->eps);
+  int rc = make_plan(P, pb->dtype, pb->geom, nb, anneal ? pr->eps_stages + 1 : 1, pr->grid_kernel, pr->eps,
+                     pr->dense_kernel == 0 ? 1 : pr->dense_kernel);
   if (rc) return rc;
   if ((rc = check_ws(P, ws, wsb))) return rc;
   if (!u || !v) return fail(UOT_E_INVALID, "u and v output buffers are required");
   hipStream_t s = ctx->work;
   if ((rc = begin(ctx))) return rc;
   Bufs<T> B = carve<T>(P, ws);
+  // the iteration runs on pbs into uo / vo: the caller's problem and outputs,
+  // or Morton-ordered copies whose potentials are scattered back at the end
+  uot_problem pbs = *pb;
+  T* uo = u;
+  T* vo = v;
+  const int32_t* px = nullptr;
+  const int32_t* py = nullptr;
+  if (P.dense_tf) {
+    pbs = sorted_points<T>(P, *pb, ws, s);
+    px = at<int32_t>(ws, P.o_permx);
+    py = at<int32_t>(ws, P.o_permy);
+    uo = at<T>(ws, P.o_us);
+    vo = at<T>(ws, P.o_vs);
+  }
   // mixed precision: FP16 passes down to kMixedSwitchTol, then FP32 passes
   const bool mixed = P.gk == 4 && has_tf16(P) && pr->tol < kMixedSwitchTol;
   Plan P2 = P;
@@ -635,14 +720,19 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   const double tol1 = mixed ? kMixedSwitchTol : pr->tol;
   Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, tol1, pr->max_iter);
   launch_ctrl_init(B.ctrl, init, s);
-  launch_log<T>(static_cast<const T*>(pb->p), B.logp, nb * P.N, 1, s);
-  launch_log<T>(static_cast<const T*>(pb->q), B.logq, nb * P.M, 1, s);
-  launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, P.N, 0, s);
-  launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
+  log_into<T>(pb->p, B.logp, nb * P.N, 1, px, B.t1, s);
+  log_into<T>(pb->q, B.logq, nb * P.M, 1, py, B.t1, s);
+  log_into<T>(pb->dx, B.logdx, P.N, 0, px, B.t1, s);
+  log_into<T>(pb->dy, B.logdy, P.M, 0, py, B.t1, s);
   if (P.geom == UOT_GEOM_GRID)
     for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, P.nst, P.cost, s);
-  launch_init_pot<T>(nullptr, B.logdx, u, nullptr, nb * P.N, P.N, B.ctrl, 0, s);
-  launch_init_pot<T>(static_cast<const T*>(pr->v0), B.logdy, v, B.wv, nb * P.M, P.M, B.ctrl, 0, s);
+  launch_init_pot<T>(nullptr, B.logdx, uo, nullptr, nb * P.N, P.N, B.ctrl, 0, s);
+  const T* v0 = static_cast<const T*>(pr->v0);
+  if (v0 && py) {
+    launch_gather<T>(v0, py, P.M, 1, vo, s);
+    v0 = vo;
+  }
+  launch_init_pot<T>(v0, B.logdy, vo, B.wv, nb * P.M, P.M, B.ctrl, 0, s);
   HIP_TRY(hipGetLastError());
   const int nfields = nb > 1 ? nb : 0;
   // a single problem on a grid of 2 or 3 axes: the first Y pass (no
@@ -657,9 +747,9 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   }
   auto iteration_with = [&](const Plan& PP) {
     return [&, pp = &PP](int par) {
-      half_step<T>(*pp, *pb, 0 | par << 1, B, u, nullptr, true, s);
+      half_step<T>(*pp, pbs, 0 | par << 1, B, uo, nullptr, true, s);
       if (!hosted) timed(2, [&] { launch_control(B.ctrl, B.parts, pp->nparts_x, pr->res_hist, s, nfields, par); });
-      half_step<T>(*pp, *pb, 1 | par << 1, B, v, nullptr, false, s, hosted ? &host : nullptr, mass != nullptr);
+      half_step<T>(*pp, pbs, 1 | par << 1, B, vo, nullptr, false, s, hosted ? &host : nullptr, mass != nullptr);
       if (mass)
         timed(2, [&] { launch_mass_update<T>(B.ctrl, B.mass_m, B.mass_s, pp->nparts_y, mass->F3, mass->log_m0, par, s); });
     };
@@ -669,6 +759,11 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   const double final_tol = pr->tol;
   rc = run_loop(ctx, B.ctrl, pr, iteration, res, mixed ? &iteration2 : nullptr, &final_tol);
   if (rc) return rc;
+  if (P.dense_tf) {
+    launch_scatter<T>(uo, px, P.N, u, s);
+    launch_scatter<T>(vo, py, P.M, v, s);
+    HIP_TRY(hipGetLastError());
+  }
   if (log_z) *log_z = ctx->pinned->zeta;
   if ((rc = finish(ctx))) return rc;
   if (res->status == -3) return fail(UOT_E_NONFINITE, "non-finite residual");
@@ -1051,7 +1146,9 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
                      int* nk, char* ws, size_t wsb, int grid_kernel) {
   Plan P;
   if (nb < 1) return fail(UOT_E_INVALID, "nb must be >= 1");
-  int rc = make_plan(P, pb->dtype, pb->geom, nb, 1, grid_kernel, eps);
+  // point clouds: kernel 2 times the tile-factored product on Morton-ordered copies
+  const int dk = (pb->geom.kind == UOT_GEOM_POINTS && grid_kernel == 2) ? 2 : 1;
+  int rc = make_plan(P, pb->dtype, pb->geom, nb, 1, pb->geom.kind == UOT_GEOM_GRID ? grid_kernel : 0, eps, dk);
   if (rc) return rc;
   if ((rc = check_ws(P, ws, wsb))) return rc;
   if (!v || !ms || !nk || reps < 1) return fail(UOT_E_INVALID, "v, ms, n_kernels and reps >= 1 are required");
@@ -1060,12 +1157,25 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
   Bufs<T> B = carve<T>(P, ws);
   Ctrl init = make_ctrl(eps, 0, 0, 0, 0, 1);
   launch_ctrl_init(B.ctrl, init, s);
-  launch_log<T>(static_cast<const T*>(pb->p), B.logp, nb * P.N, 1, s);
-  launch_log<T>(static_cast<const T*>(pb->dx), B.logdx, P.N, 0, s);
-  launch_log<T>(static_cast<const T*>(pb->dy), B.logdy, P.M, 0, s);
+  uot_problem pbs = *pb;
+  const int32_t* px = nullptr;
+  const int32_t* py = nullptr;
+  if (P.dense_tf) {
+    pbs = sorted_points<T>(P, *pb, ws, s);
+    px = at<int32_t>(ws, P.o_permx);
+    py = at<int32_t>(ws, P.o_permy);
+  }
+  log_into<T>(pb->p, B.logp, nb * P.N, 1, px, B.t1, s);
+  log_into<T>(pb->dx, B.logdx, P.N, 0, px, B.t1, s);
+  log_into<T>(pb->dy, B.logdy, P.M, 0, py, B.t1, s);
   if (P.geom == UOT_GEOM_GRID)
     for (int k = 0; k < P.dim; ++k) launch_gtab<T>(B.gtab[k], (int)P.n[k], P.h[k], B.ctrl, 1, P.cost, s);
-  launch_init_pot<T>(v, B.logdy, nullptr, B.wv, nb * P.M, P.M, B.ctrl, 0, s);
+  const T* vin = v;
+  if (py) {
+    launch_gather<T>(v, py, P.M, 1, B.t2, s);
+    vin = B.t2;
+  }
+  launch_init_pot<T>(vin, B.logdy, nullptr, B.wv, nb * P.M, P.M, B.ctrl, 0, s);
   launch_init_pot<T>(nullptr, B.logdx, B.t3, nullptr, nb * P.N, P.N, B.ctrl, 0, s);   // u = 0 in t3
   EpiArgs<T> ep = prox_epi<T>(B.t3, B.wu, B.logp, B.logdx, nullptr, B.parts, P.N, pb->F1);
   EpiArgs<T> raw{};
@@ -1088,9 +1198,15 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
       ks.push_back([&] { strided_pass<T>(P, 0, B.t2, nbf, P.n[1] * P.n[2], B.gtab, 0, B.ctrl, ep, s); });
     }
   } else {
-    const T* rows = static_cast<const T*>(pb->geom.x);
-    const T* cols = static_cast<const T*>(pb->geom.y);
+    const T* rows = static_cast<const T*>(pbs.geom.x);
+    const T* cols = static_cast<const T*>(pbs.geom.y);
     ks.push_back([&] {
+      if constexpr (std::is_same<T, float>::value) {
+        if (P.dense_tf) {
+          launch_dense_tf(P.dim, rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps, 0, B.ctrl, s);
+          return;
+        }
+      }
       launch_dense_lse<T>(P.dim, P.R[0], rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps, 0, B.ctrl,
                           P.cost, s);
     });

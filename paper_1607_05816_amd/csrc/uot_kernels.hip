@@ -479,6 +479,340 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// dense point-cloud product, tile-factored (FP32, squared Euclidean cost).
+// Row tile I = the 64 R consecutive rows of a wave (centre xbar_I, radius
+// r_I), column tile J = 16 consecutive columns of a staged chunk (ybar_J, r_J),
+// e_i = x_i - xbar_I, f_j = y_j - ybar_J.  With c = log2(e) / eps,
+//   w_j - c |x_i - y_j|^2 = beta_jI + alpha_iJ + 2 c e_i . f_j,
+//   beta_jI  = w_j - c |y_j - xbar_I|^2,
+//   alpha_iJ = -c |x_i - ybar_J|^2 + c |xbar_I - ybar_J|^2
+// (exact), so the tile's share of row i is
+//   2^{alpha_iJ + m_IJ} sum_j 2^{2c e_i.f_j + l_jI},  l_jI = beta_jI - m_IJ <= 0,
+// m_IJ = max_j beta_jI: per pair DIM FMAs (the chain starts at l_jI), one exp2
+// and one add, and no running maximum.  The exponent is summed before the
+// exp2: 2^{l_jI} alone can fall below the FP32 normal range while the product
+// with 2^{2c e.f} still matters.  The tile's largest term is at least 2^{-B},
+// B = 2c r_I r_J, so terms that underflow are negligible.  Tile pairs where B
+// exceeds kDenseTfBound (wide tiles: points not in a spatially coherent order)
+// are summed directly instead, so the result never depends on the order.
+// grid = (ceil(Nr / (256 R)), splits); partials as in k_dense_lse.
+// ---------------------------------------------------------------------------
+constexpr float kDenseTfBound = 64.f;
+
+template <int DIM, int R>
+__global__ __launch_bounds__(kBlock) void k_dense_tf(const float* __restrict__ xr, int64_t Nr,
+                                                      const float* __restrict__ yc, const float* __restrict__ w,
+                                                      int64_t Mc, int64_t cols_per_split,
+                                                      float* __restrict__ pm, float* __restrict__ ps, int side,
+                                                      const Ctrl* __restrict__ c) {
+  if (skip_side(c, side)) return;
+  __shared__ float4 tile[kBlock];        // (y, w) of the chunk, for directly summed tile pairs
+  __shared__ float4 fe[4][kBlock];       // (f_j, l_jI) for the row tile I of each wave
+  __shared__ float toff[4][16];          // m_IJ + c |xbar_I - ybar_J|^2  (-inf: no mass in J)
+  __shared__ int tfac[4][16];            // tile pair factored (1) or summed directly (0)
+  __shared__ float tyb[16][3];           // ybar_J
+  __shared__ float xbs[4][3], xrs[4];    // xbar_I and r_I^2 of the 4 waves
+  const float cc = float(kLog2e / eps_of(c, side));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float xi[R][3];
+  int64_t rows[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    rows[r] = (int64_t)blockIdx.x * (kBlock * R) + wv * (64 * R) + r * 64 + lane;
+    const int64_t rr = rows[r] < Nr ? rows[r] : 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xi[r][d] = d < DIM ? xr[d * Nr + rr] : 0.f;
+  }
+  // the wave's row tile: box centre and radius over its valid rows
+  float xb[3], e2[R][3];
+  float rad2 = 0.f;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    float lo = __builtin_inff(), hi = -__builtin_inff();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (d < DIM && rows[r] < Nr) {
+        lo = fminf(lo, xi[r][d]);
+        hi = fmaxf(hi, xi[r][d]);
+      }
+    lo = lanes_min<float>(lo, 32);
+    hi = lanes_max<float>(hi, 32);
+    xb[d] = lo <= hi ? 0.5f * (lo + hi) : 0.f;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    float q = 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float e = xi[r][d] - xb[d];
+      e2[r][d] = 2.f * cc * e;
+      q = __builtin_fmaf(e, e, q);
+    }
+    if (rows[r] < Nr) rad2 = fmaxf(rad2, q);
+  }
+  rad2 = lanes_max<float>(rad2, 32);
+  if (lane == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xbs[wv][d] = xb[d];
+    xrs[wv] = rad2;
+  }
+  __syncthreads();
+  Lse2<float> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r].init();
+  const int64_t cb = (int64_t)blockIdx.y * cols_per_split;
+  const int64_t ce = (cb + cols_per_split < Mc) ? cb + cols_per_split : Mc;
+  const int J = threadIdx.x >> 4;        // this thread's column tile within the chunk
+  for (int64_t c0 = cb; c0 < ce; c0 += kBlock) {
+    const int64_t col = c0 + threadIdx.x;
+    float4 rec;
+    rec.x = rec.y = rec.z = 0.f;
+    if (col < ce) {
+      rec.x = yc[col];
+      if (DIM > 1) rec.y = yc[Mc + col];
+      if (DIM > 2) rec.z = yc[2 * Mc + col];
+      rec.w = w[col];
+    } else {
+      rec.w = -__builtin_inff();
+    }
+    __syncthreads();                     // the previous chunk's reads are done
+    tile[threadIdx.x] = rec;
+    // column tile: box centre and radius over its columns that carry mass
+    const bool live = rec.w != -__builtin_inff();
+    const float y[3] = {rec.x, rec.y, rec.z};
+    float yb[3], f[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float lo = lanes_min<float>(live && d < DIM ? y[d] : __builtin_inff(), 8);
+      const float hi = lanes_max<float>(live && d < DIM ? y[d] : -__builtin_inff(), 8);
+      yb[d] = lo <= hi ? 0.5f * (lo + hi) : 0.f;
+      // columns without mass (padding, zero density) lie outside the box: f = 0
+      // keeps 2c e.f bounded there, and their l is -inf
+      f[d] = live ? y[d] - yb[d] : 0.f;
+    }
+    const float fr2 = lanes_max<float>(live ? __builtin_fmaf(f[0], f[0], __builtin_fmaf(f[1], f[1], f[2] * f[2])) : 0.f, 8);
+    if ((threadIdx.x & 15) == 0) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) tyb[J][d] = yb[d];
+    }
+#pragma unroll
+    for (int I = 0; I < 4; ++I) {
+      float dy2 = 0.f, dxy2 = 0.f;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float a = y[d] - xbs[I][d], b = xbs[I][d] - yb[d];
+        dy2 = __builtin_fmaf(a, a, dy2);
+        dxy2 = __builtin_fmaf(b, b, dxy2);
+      }
+      const float beta = live ? __builtin_fmaf(-cc, dy2, rec.w) : -__builtin_inff();
+      const float m = lanes_max<float>(beta, 8);
+      fe[I][threadIdx.x] = make_float4(f[0], f[1], f[2], beta - m);   // -inf for columns without mass
+      if ((threadIdx.x & 15) == 0) {
+        toff[I][J] = m == -__builtin_inff() ? m : __builtin_fmaf(cc, dxy2, m);
+        tfac[I][J] = 2.f * cc * __builtin_sqrtf(xrs[I] * fr2) <= kDenseTfBound;
+      }
+    }
+    __syncthreads();
+    const int64_t rem = ce - c0;
+    const int cnt = rem < kBlock ? (int)rem : kBlock;
+    const int ntl = (cnt + 15) >> 4;
+    // tile metadata for this wave's row tile in lanes 0..15, read per tile
+    // into scalars (no LDS round trip inside the tile loop)
+    const int li = lane & 15;
+    const float moff = toff[wv][li];
+    const int mfac = tfac[wv][li];
+    const float myb0 = tyb[li][0], myb1 = tyb[li][1], myb2 = tyb[li][2];
+    for (int jt = 0; jt < ntl; ++jt) {
+      const float off = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(moff), jt));
+      if (off == -__builtin_inff()) continue;     // no mass in this column tile
+      if (__builtin_amdgcn_readlane(mfac, jt)) {
+        // each staged column feeds the R rows of the thread
+        float sm[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) sm[r] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const float4 q = fe[wv][jt * 16 + k];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            float t = __builtin_fmaf(e2[r][0], q.x, q.w);
+            if (DIM > 1) t = __builtin_fmaf(e2[r][1], q.y, t);
+            if (DIM > 2) t = __builtin_fmaf(e2[r][2], q.z, t);
+            sm[r] += __builtin_amdgcn_exp2f(t);
+          }
+        }
+        const float ybj[3] = {__int_as_float(__builtin_amdgcn_readlane(__float_as_int(myb0), jt)),
+                              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(myb1), jt)),
+                              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(myb2), jt))};
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          float a = off;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            const float dd = xi[r][d] - ybj[d];
+            a = __builtin_fmaf(-cc * dd, dd, a);
+          }
+          // branch-free merge of (a, sm[r]) into the running (m, s)
+          const float mn = fmaxf(acc[r].m, a);
+          const float sh = mn == -__builtin_inff() ? 0.f : mn;
+          acc[r].s = acc[r].s * __builtin_amdgcn_exp2f(acc[r].m - sh) + sm[r] * __builtin_amdgcn_exp2f(a - sh);
+          acc[r].m = mn;
+        }
+      } else {
+        const float sc = cc;
+        for (int jj = jt * 16; jj < jt * 16 + 16; jj += kChunk) {
+          float4 q[kChunk];
+#pragma unroll
+          for (int k = 0; k < kChunk; ++k) q[k] = tile[jj + k];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            float t[kChunk];
+#pragma unroll
+            for (int k = 0; k < kChunk; ++k) {
+              float d0 = xi[r][0] - q[k].x;
+              float cst = d0 * d0;
+              if (DIM > 1) { float d1 = xi[r][1] - q[k].y; cst = __builtin_fmaf(d1, d1, cst); }
+              if (DIM > 2) { float d2 = xi[r][2] - q[k].z; cst = __builtin_fmaf(d2, d2, cst); }
+              t[k] = __builtin_fmaf(-sc, cst, q[k].w);
+            }
+            acc[r].template add<kChunk>(t);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (rows[r] < Nr) {
+      pm[blockIdx.y * Nr + rows[r]] = acc[r].m;
+      ps[blockIdx.y * Nr + rows[r]] = acc[r].s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// spatial order of a point cloud (Z-order / Morton), for the tile-factored
+// dense product: box, codes, then the permutation by counting ranks
+// ---------------------------------------------------------------------------
+// bx[d] = min, bx[3 + d] = max of coordinate d (one block)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_point_box(const T* __restrict__ x, int64_t n, int dim, T* __restrict__ bx) {
+  __shared__ T smin[kBlock], smax[kBlock];
+  for (int d = 0; d < dim; ++d) {
+    T lo = Num<T>::pinf(), hi = Num<T>::ninf();
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+      const T v = x[d * n + i];
+      lo = Num<T>::fmin(lo, v);
+      hi = Num<T>::fmax(hi, v);
+    }
+    smin[threadIdx.x] = lo;
+    smax[threadIdx.x] = hi;
+    __syncthreads();
+    for (int o = kBlock / 2; o >= 1; o >>= 1) {
+      if ((int)threadIdx.x < o) {
+        smin[threadIdx.x] = Num<T>::fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+        smax[threadIdx.x] = Num<T>::fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      bx[d] = smin[0];
+      bx[3 + d] = smax[0];
+    }
+    __syncthreads();
+  }
+}
+
+// Morton code: coordinates quantised over the box to 2^bits levels
+// (bits = 30 / dim), their bits interleaved
+template <typename T>
+__global__ void k_morton(const T* __restrict__ x, int64_t n, int dim, const T* __restrict__ bx,
+                         uint32_t* __restrict__ code) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int bits = 30 / dim;
+  const uint32_t top = (1u << bits) - 1u;
+  uint32_t out = 0;
+  for (int d = 0; d < dim; ++d) {
+    const double lo = double(bx[d]), ext = double(bx[3 + d]) - lo;
+    double t = ext > 0 ? (double(x[d * n + i]) - lo) / ext : 0.0;
+    uint32_t q = (uint32_t)(t * double(top) + 0.5);
+    q = q > top ? top : q;
+    for (int b = 0; b < bits; ++b) out |= ((q >> b) & 1u) << (b * dim + d);
+  }
+  code[i] = out;
+}
+
+// perm[rank_i] = i with rank_i = #{j : code_j < code_i, or code_j = code_i and j < i}
+// (a stable order; O(n^2) comparisons, once per solve, through LDS tiles)
+__global__ __launch_bounds__(kBlock) void k_rank(const uint32_t* __restrict__ code, int64_t n,
+                                                  int32_t* __restrict__ perm) {
+  __shared__ uint32_t sc[kBlock];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t ci = i < n ? code[i] : 0u;
+  int64_t rank = 0;
+  for (int64_t j0 = 0; j0 < n; j0 += kBlock) {
+    __syncthreads();
+    sc[threadIdx.x] = (j0 + threadIdx.x < n) ? code[j0 + threadIdx.x] : 0xffffffffu;
+    __syncthreads();
+    const int cnt = (n - j0 < kBlock) ? (int)(n - j0) : kBlock;
+    for (int k = 0; k < cnt; ++k) {
+      const uint32_t cj = sc[k];
+      rank += (cj < ci || (cj == ci && j0 + k < i)) ? 1 : 0;
+    }
+  }
+  if (i < n) perm[rank] = (int32_t)i;
+}
+
+// out[r][k] = in[r][perm[k]] for rows r < nrow of length n
+template <typename T>
+__global__ void k_gather(const T* __restrict__ in, const int32_t* __restrict__ perm, int64_t n, int nrow,
+                         T* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t src = perm[k];
+  for (int r = 0; r < nrow; ++r) out[r * n + k] = in[r * n + src];
+}
+
+// out[perm[k]] = in[k]
+template <typename T>
+__global__ void k_scatter(const T* __restrict__ in, const int32_t* __restrict__ perm, int64_t n, T* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  out[perm[k]] = in[k];
+}
+
+template <typename T>
+void launch_spatial_order(const T* x, int64_t n, int dim, T* box, uint32_t* code, int32_t* perm, hipStream_t s) {
+  hipLaunchKernelGGL(k_point_box<T>, dim3(1), dim3(kBlock), 0, s, x, n, dim, box);
+  hipLaunchKernelGGL(k_morton<T>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, x, n, dim, box, code);
+  hipLaunchKernelGGL(k_rank, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, code, n, perm);
+}
+template <typename T>
+void launch_gather(const T* in, const int32_t* perm, int64_t n, int nrow, T* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather<T>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, in, perm, n, nrow, out);
+}
+template <typename T>
+void launch_scatter(const T* in, const int32_t* perm, int64_t n, T* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter<T>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, in, perm, n, out);
+}
+template void launch_spatial_order<float>(const float*, int64_t, int, float*, uint32_t*, int32_t*, hipStream_t);
+template void launch_spatial_order<double>(const double*, int64_t, int, double*, uint32_t*, int32_t*, hipStream_t);
+template void launch_gather<float>(const float*, const int32_t*, int64_t, int, float*, hipStream_t);
+template void launch_gather<double>(const double*, const int32_t*, int64_t, int, double*, hipStream_t);
+template void launch_scatter<float>(const float*, const int32_t*, int64_t, float*, hipStream_t);
+template void launch_scatter<double>(const double*, const int32_t*, int64_t, double*, hipStream_t);
+
+void launch_dense_tf(int dim, const float* xr, int64_t Nr, const float* yc, const float* w, int64_t Mc, int nsplit,
+                     int64_t cps, float* pm, float* ps, int side, const Ctrl* c, hipStream_t s) {
+  dim3 grid(ceil_div(Nr, kBlock * 2), (unsigned)nsplit);
+  if (dim == 1) hipLaunchKernelGGL((k_dense_tf<1, 2>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side, c);
+  else if (dim == 2)
+    hipLaunchKernelGGL((k_dense_tf<2, 2>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side, c);
+  else hipLaunchKernelGGL((k_dense_tf<3, 2>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side, c);
+}
+
 // merge the column splits of k_dense_lse, then the epilogue; grid = ceil(Nr/256)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, const T* __restrict__ ps,

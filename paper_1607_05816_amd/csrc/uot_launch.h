@@ -80,6 +80,15 @@ void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t
 void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s);
 void launch_ctrl_resume(Ctrl* c, double tol, hipStream_t s);
 // slot 0 valid again after a stopped solve (one more product at the last eps)
+// spatial (Morton) order of n points (dim x n, coordinate-major): box (6),
+// codes (n) and the permutation perm (n, sorted position -> original index)
+template <typename T>
+void launch_spatial_order(const T* x, int64_t n, int dim, T* box, uint32_t* code, int32_t* perm, hipStream_t s);
+template <typename T> void launch_gather(const T* in, const int32_t* perm, int64_t n, int nrow, T* out, hipStream_t s);
+template <typename T> void launch_scatter(const T* in, const int32_t* perm, int64_t n, T* out, hipStream_t s);
+// tile-factored dense product (FP32, R = 2), partials as launch_dense_lse
+void launch_dense_tf(int dim, const float* xr, int64_t Nr, const float* yc, const float* w, int64_t Mc, int nsplit,
+                     int64_t cps, float* pm, float* ps, int side, const Ctrl* c, hipStream_t s);
 template <typename T>
 void launch_coord_weight(const T* w, T* out, int64_t M, int64_t stride, int64_t nk, double hk, const T* yk, int sign,
                          hipStream_t s);
