@@ -167,14 +167,23 @@ typedef struct uot_params {
                             levels off near 2e-5), 4 mixed precision: the
                             passes of 3 until the residual reaches 1e-4, then
                             those of 2 down to tol (FP32 accuracy)         */
-  int32_t dense_kernel;  /* point clouds: 0 default (1), 1 direct log-sum-exp
+  int32_t dense_kernel;  /* point clouds: 0 default (4 for FP32 data with the
+                            squared Euclidean cost, else 1), 1 direct log-sum-exp
                             product, 2 tile-factored product (FP32, squared
                             Euclidean cost): both clouds are put in Morton
                             order on the device once per solve, tile pairs
                             factor exactly (w_j - c|x_i - y_j|^2 = beta_jI +
                             alpha_iJ + 2c e_i.f_j) and wide tile pairs are
                             summed directly; results come back in the
-                            caller's order                                  */
+                            caller's order; 3 and 4 matrix-core products
+                            (FP32 data, squared Euclidean cost; Morton-ordered
+                            copies as for 2): around a centre per block of
+                            rows, w_j - c|x_i - y_j|^2 = R_i + G_j + e_i.B_j,
+                            the exponents of 16 x 16 pairs as one MFMA product:
+                            3 with FP32 operands (16x16x4 FP32 MFMA), 4 with
+                            each operand split into three bf16 parts (24
+                            bits; one 16x16x32 BF16 MFMA, FP32 accumulation),
+                            which runs beside the exp2 on the vector units  */
 } uot_params;
 
 typedef struct uot_result {
@@ -469,7 +478,10 @@ int uot_gemm_bf16(uot_ctx *ctx, int ta, int tb, int M, int N, int K, const uint1
  * *n_kernels receives the number of entries written (<= 3). */
 int uot_time_half_step(uot_ctx *ctx, const uot_problem *pb, double eps, const void *v,
                        int reps, double *ms, int *n_kernels, void *ws, size_t ws_bytes,
-                       int grid_kernel);   /* as uot_params.grid_kernel */
+                       int grid_kernel);   /* as uot_params.grid_kernel; point
+                                              clouds: 2, 3 or 4 time that
+                                              dense_kernel, otherwise the
+                                              direct one */
 /* The same over nb fields on one grid (the layout of uot_solve_fields: pb->p
  * is nb x size, v is nb x size, workspace from uot_fields_workspace_size);
  * every launch processes all nb fields.  nb = 1 is uot_time_half_step. */

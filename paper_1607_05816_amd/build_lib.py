@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libuot.so")
-SOURCES = ["uot_kernels.hip", "uot_grid_tf.hip", "uot_api.hip", "uot_net.hip"]
+SOURCES = ["uot_kernels.hip", "uot_grid_tf.hip", "uot_dense_mf.hip", "uot_api.hip", "uot_net.hip"]
 ARCH = os.environ.get("UOT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -19,6 +19,11 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
+# per-source additions: the matrix-core dense product keeps its MFMA operands
+# and results in VGPRs, so the exp2 reads them without AGPR copies, and runs
+# with the IEEE mode bit off (its maxima then need no NaN quieting; no NaN
+# reaches them)
+EXTRA = {"uot_dense_mf.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form", "-mno-amdgpu-ieee", "-fno-honor-nans"]}
 
 
 def build(verbose: bool = False, jobs: int = 3) -> str:
@@ -28,7 +33,7 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT), src))

@@ -135,7 +135,14 @@ struct Plan {
   int split1d = 1;                           // 1-D grids: tap slices of the (direct) pass
   mutable void* split_pm = nullptr;          // ... their partial LSEs (set by carve)
   mutable void* split_ps = nullptr;
-  bool dense_tf = false;                     // points: tile-factored product on Morton-ordered copies
+  bool dense_tf = false;                     // points: tile-factored product
+  bool dense_mf = false;                     // points: product on the matrix cores
+  bool mf_split = false;                     // ... with BF16 x 3 operands (else FP32)
+  int mf_groups = 4;                         // its row groups of 16 per wave (4 or 8)
+  // the factored products run on Morton-ordered copies of the clouds (rows
+  // of a wave or block lie close together, so the factored exponents keep
+  // small magnitudes); results are scattered back to the caller's order
+  bool sorted() const { return dense_tf || dense_mf; }
   // workspace offsets
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
       o_gcost, o_obj, o_scal, o_mass, o_xs, o_ys, o_permx, o_permy, o_code, o_box, o_us, o_vs, total;
@@ -171,15 +178,20 @@ int grid_final_parts(const Plan& P) { return grid_final_parts_for(P, use_tf(P, 0
 void dense_config(Plan& P, int side) {
   const int64_t Nr = side == 0 ? P.N : P.M;
   const int64_t Mc = side == 0 ? P.M : P.N;
-  const int R = (P.dtype == UOT_F32) ? 2 : 1;
+  // rows per thread (the matrix-core kernel: mf_groups / 4, with mf_groups
+  // row groups of 16 per wave)
+  const int R = P.dense_mf ? P.mf_groups / 4 : (P.dtype == UOT_F32) ? 2 : 1;
   const int64_t rt = (Nr + 256 * R - 1) / (256 * R);
-  // blocks to aim for: 2048 (8 resident per compute unit); the tile-factored
-  // kernel holds more registers and balances better over more, smaller blocks
-  static const int tf_blocks = [] {
-    const char* e = getenv("UOT_DENSE_TF_BLOCKS");
-    return e ? atoi(e) : 2048;
+  // blocks to aim for: 2048 (8 resident per compute unit), 1024 for the
+  // matrix-core product (its column chunks after the first cost one pass,
+  // so longer column ranges per block pay); UOT_DENSE_BLOCKS overrides the
+  // target of the factored kernels
+  static const int fac_blocks = [] {
+    const char* e = getenv("UOT_DENSE_BLOCKS");
+    return e ? atoi(e) : 0;
   }();
-  const int64_t target = P.dense_tf && tf_blocks > 0 ? tf_blocks : 2048;
+  int64_t target = P.dense_mf ? 1024 : 2048;   // the matrix-core product: fewer splits to merge
+  if ((P.dense_tf || P.dense_mf) && fac_blocks > 0) target = fac_blocks;
   int64_t sp = (target + rt - 1) / rt;
   const int64_t maxsp = (Mc + 31) / 32;
   if (sp > maxsp) sp = maxsp;
@@ -195,7 +207,7 @@ void dense_config(Plan& P, int side) {
 int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_kernel = 0, double eps_min = 0.0,
               int dense_kernel = 1) {
   if (dtype != UOT_F32 && dtype != UOT_F64) return fail(UOT_E_INVALID, "dtype must be UOT_F32 or UOT_F64");
-  if (dense_kernel < 0 || dense_kernel > 2) return fail(UOT_E_INVALID, "dense_kernel must be 0 .. 2");
+  if (dense_kernel < 0 || dense_kernel > 4) return fail(UOT_E_INVALID, "dense_kernel must be 0 .. 4");
   if (grid_kernel < 0 || grid_kernel > 4) return fail(UOT_E_INVALID, "grid_kernel must be 0 .. 4");
   P.gk = grid_kernel == 0 ? (dtype == UOT_F32 ? 2 : 1) : grid_kernel;
   P.dtype = dtype;
@@ -219,9 +231,19 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
     if (nb != 1) return fail(UOT_E_UNSUPPORTED, "several fields need a grid geometry");
     P.N = g.N;
     P.M = g.M;
+    // default: the BF16 x 3 matrix-core product where it applies (FP32, squared
+    // Euclidean cost), the direct product otherwise
+    if (dense_kernel == 0) dense_kernel = dtype == UOT_F32 && g.cost == UOT_COST_SQEUCLID ? 4 : 1;
     P.dense_tf = dense_kernel == 2;
-    if (P.dense_tf && (dtype != UOT_F32 || g.cost != UOT_COST_SQEUCLID))
-      return fail(UOT_E_UNSUPPORTED, "the tile-factored dense product takes FP32 and the squared Euclidean cost");
+    P.dense_mf = dense_kernel == 3 || dense_kernel == 4;
+    P.mf_split = dense_kernel == 4;
+    static const int mf_groups = [] {
+      const char* e = getenv("UOT_DENSE_MF_GROUPS");
+      return e && atoi(e) == 8 ? 8 : 4;
+    }();
+    P.mf_groups = mf_groups;
+    if ((P.dense_tf || P.dense_mf) && (dtype != UOT_F32 || g.cost != UOT_COST_SQEUCLID))
+      return fail(UOT_E_UNSUPPORTED, "the factored dense products take FP32 and the squared Euclidean cost");
   } else if (g.kind == UOT_GEOM_GRID) {
     int64_t sz = 1;
     for (int k = 0; k < g.dim; ++k) {
@@ -264,12 +286,15 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
   P.o_t2 = take(e * F);
   P.o_t3 = take(e * F);
   if (P.geom == UOT_GEOM_POINTS) {
-    // partials sized for both product kernels, so one workspace size query
-    // covers every dense_kernel choice
+    // partials sized for every product kernel, so one workspace size query
+    // covers every dense_kernel choice; the plan's own kernel is set last
     int64_t np = 0;
-    const bool tf = P.dense_tf;
-    for (int pass = 0; pass < 2; ++pass) {
-      P.dense_tf = pass == 0 ? !tf : tf;
+    const Plan keep = P;
+    for (int pass = 0; pass < 5; ++pass) {
+      P.dense_tf = pass == 1;
+      P.dense_mf = pass >= 2;
+      P.mf_groups = pass == 2 ? 8 : 4;
+      if (pass == 4) P = keep;
       dense_config(P, 0);
       dense_config(P, 1);
       np = std::max(np, std::max((int64_t)P.splits[0] * P.N, (int64_t)P.splits[1] * P.M));
@@ -471,6 +496,11 @@ void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Buf
     if constexpr (std::is_same<T, float>::value) {
       if (P.dense_tf) {
         launch_dense_tf(P.dim, rows, Nr, cols, w_cols, Mc, P.splits[half], P.cps[half], B.pm, B.ps, side, c, s);
+        return;
+      }
+      if (P.dense_mf) {
+        launch_dense_mf(P.dim, P.mf_groups, P.mf_split, rows, Nr, cols, w_cols, Mc, P.splits[half], P.cps[half], B.pm, B.ps,
+                        side, c, s);
         return;
       }
     }
@@ -692,7 +722,7 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   Plan P;
   const bool anneal = pr->eps0 > pr->eps && pr->eps_stages > 0 && pr->iters_per_stage > 0;
   int rc = make_plan(P, pb->dtype, pb->geom, nb, anneal ? pr->eps_stages + 1 : 1, pr->grid_kernel, pr->eps,
-                     pr->dense_kernel == 0 ? 1 : pr->dense_kernel);
+                     pr->dense_kernel);
   if (rc) return rc;
   if ((rc = check_ws(P, ws, wsb))) return rc;
   if (!u || !v) return fail(UOT_E_INVALID, "u and v output buffers are required");
@@ -706,7 +736,7 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   T* vo = v;
   const int32_t* px = nullptr;
   const int32_t* py = nullptr;
-  if (P.dense_tf) {
+  if (P.sorted()) {
     pbs = sorted_points<T>(P, *pb, ws, s);
     px = at<int32_t>(ws, P.o_permx);
     py = at<int32_t>(ws, P.o_permy);
@@ -759,7 +789,7 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   const double final_tol = pr->tol;
   rc = run_loop(ctx, B.ctrl, pr, iteration, res, mixed ? &iteration2 : nullptr, &final_tol);
   if (rc) return rc;
-  if (P.dense_tf) {
+  if (P.sorted()) {
     launch_scatter<T>(uo, px, P.N, u, s);
     launch_scatter<T>(vo, py, P.M, v, s);
     HIP_TRY(hipGetLastError());
@@ -1146,8 +1176,9 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
                      int* nk, char* ws, size_t wsb, int grid_kernel) {
   Plan P;
   if (nb < 1) return fail(UOT_E_INVALID, "nb must be >= 1");
-  // point clouds: kernel 2 times the tile-factored product on Morton-ordered copies
-  const int dk = (pb->geom.kind == UOT_GEOM_POINTS && grid_kernel == 2) ? 2 : 1;
+  // point clouds: kernel 2 times the tile-factored product on Morton-ordered
+  // copies, kernels 3 and 4 the matrix-core products
+  const int dk = (pb->geom.kind == UOT_GEOM_POINTS && grid_kernel >= 2 && grid_kernel <= 4) ? grid_kernel : 1;
   int rc = make_plan(P, pb->dtype, pb->geom, nb, 1, pb->geom.kind == UOT_GEOM_GRID ? grid_kernel : 0, eps, dk);
   if (rc) return rc;
   if ((rc = check_ws(P, ws, wsb))) return rc;
@@ -1160,7 +1191,7 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
   uot_problem pbs = *pb;
   const int32_t* px = nullptr;
   const int32_t* py = nullptr;
-  if (P.dense_tf) {
+  if (P.sorted()) {
     pbs = sorted_points<T>(P, *pb, ws, s);
     px = at<int32_t>(ws, P.o_permx);
     py = at<int32_t>(ws, P.o_permy);
@@ -1204,6 +1235,11 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
       if constexpr (std::is_same<T, float>::value) {
         if (P.dense_tf) {
           launch_dense_tf(P.dim, rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps, 0, B.ctrl, s);
+          return;
+        }
+        if (P.dense_mf) {
+          launch_dense_mf(P.dim, P.mf_groups, P.mf_split, rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps, 0,
+                          B.ctrl, s);
           return;
         }
       }

@@ -1,0 +1,420 @@
+// Dense point-cloud product of libuot with the squared Euclidean cost on the
+// gfx950 matrix cores, with its launcher.
+#include "uot_device.h"
+#include "uot_epilogue.h"
+#include "uot_launch.h"
+
+// ---------------------------------------------------------------------------
+// Row i of a half-step needs log2 sum_j 2^{w_j - c |x_i - y_j|^2} (c =
+// log2(e) / eps, w_j the column's log2 weight).  Around a centre xbar shared
+// by the rows of a block, with e_i = x_i - xbar,
+//   w_j - c |x_i - y_j|^2 = R_i + G_j + e_i . B_j,
+//   R_i = -c |e_i|^2,  G_j = w_j - c |y_j - xbar|^2,  B_j = 2 c (y_j - xbar),
+// exactly (the host passes Morton-ordered clouds, so the rows of a block lie
+// close together and |e_i . B_j| stays small for the columns that matter).
+// The exponents of 16 columns x 16 rows are then the product of a
+// 16 x K matrix (column operands) with a K x 16 matrix (row operands), one
+// MFMA, which leaves one exp2 and one add per pair to the vector units.  Two
+// operand forms:
+//   FP32 (SPLIT = false): K = 4, column (B_j, G_j), row (e_i, 1), one
+//     v_mfma_f32_16x16x4f32.  FP32 matrix instructions run on the vector
+//     ALUs: they do not overlap the exp2.
+//   BF16 x 3 (SPLIT = true): every FP32 operand a is split into three bf16
+//     parts a = a1 + a2 + a3 (each the bf16 rounding of what the previous
+//     parts leave; 24 significant bits together), and e.B is summed from the
+//     six part products e_r B_s with r + s <= 4 per coordinate, G from its
+//     three parts against 1: 21 of the 32 slots of one
+//     v_mfma_f32_16x16x32_bf16 (products exact, FP32 accumulation; dropped
+//     part products are below 2^-24 of |e_d B_d|).  These run on the matrix
+//     cores, next to the exp2 of other groups.
+// The column operands of a chunk of 256 columns are built once in LDS.
+// Layout of the 16 x 16 MFMAs (64 lanes, q = lane / 16, l = lane % 16): a
+// lane supplies A[l][k in slots of q] and B[k in slots of q][l] (the same K
+// slots for both), and gets D[4 q + r][l], r = 0..3.  Here A holds the
+// columns and B the rows (row 16 g + l of the wave), so lane (q, l) gets the
+// exponents of row 16 g + l against columns 4 q .. 4 q + 3 of the tile:
+// every lane keeps one running sum per row group, and a row is spread over
+// the 4 lanes l + 16 q.
+// Shift: the sum pass feeds minus the running maximum m of each row in as
+// the accumulator input.  Where m is not yet finite (the first chunk), a
+// maximum pass over the chunk (lane maxima, then over the 4 lanes of the
+// row) sets it first, so every exp2 argument is <= 0.  Later chunks run the
+// sum pass alone against the running m: a term above m stays finite up to
+// 2^127, and the chunk is redone with both passes when a row total is not
+// below 2^100 (which includes an overflow); otherwise whole powers of two of
+// the total move into m.  Terms that underflow lie more than 2^126 below a
+// term already summed, so they do not change the result.
+// Columns without mass (and padding) carry G = -inf, so their terms are 0.
+// G row groups of 16 per wave (64 G rows per block);
+// grid = (ceil(Nr / (64 G)), splits); partials (m, s) per split as the
+// direct kernel: log2 sum = m + log2 s.
+// ---------------------------------------------------------------------------
+namespace uot {
+
+typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mf_bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+// sum over the four lanes l % 16 + {0, 16, 32, 48}
+__device__ __forceinline__ float sum_over_rows(float x) {
+  const LanePair p = lane_xor16(x);
+  const float y = p.a + p.b;
+  const LanePair r = lane_xor32(y);
+  return r.a + r.b;
+}
+
+// a = p[0] + p[1] + p[2] to 24 significant bits; -inf -> (-inf, 0, 0)
+__device__ __forceinline__ void split3(float a, __bf16 (&p)[3]) {
+  if (!(a > -__builtin_inff())) {
+    p[0] = (__bf16)a;
+    p[1] = p[2] = (__bf16)0.f;
+    return;
+  }
+  p[0] = (__bf16)a;
+  const float r1 = a - (float)p[0];
+  p[1] = (__bf16)r1;
+  p[2] = (__bf16)(r1 - (float)p[1]);
+}
+
+// slot k of the K = 32 operands: k < 18 is part product u = k % 6 of
+// coordinate k / 6, with (row part, column part) = (1,1) (1,2) (2,1) (1,3)
+// (2,2) (3,1); k = 18, 19, 20 carry G's parts against 1; the rest are 0
+template <int K>
+__device__ __forceinline__ __bf16 row_slot(const __bf16 (&e)[3][3]) {
+  if constexpr (K < 18) {
+    constexpr int u = K % 6;
+    return e[K / 6][(u == 2 || u == 4) ? 1 : (u == 5 ? 2 : 0)];
+  } else if constexpr (K < 21) {
+    return (__bf16)1.f;
+  } else {
+    return (__bf16)0.f;
+  }
+}
+template <int K>
+__device__ __forceinline__ __bf16 col_slot(const __bf16 (&b)[3][3], const __bf16 (&g)[3]) {
+  if constexpr (K < 18) {
+    constexpr int u = K % 6;
+    return b[K / 6][(u == 1 || u == 4) ? 1 : (u == 3 ? 2 : 0)];
+  } else if constexpr (K < 21) {
+    return g[K - 18];
+  } else {
+    return (__bf16)0.f;
+  }
+}
+template <int Q>
+__device__ __forceinline__ mf_bf16x8 row_chunk(const __bf16 (&e)[3][3]) {
+  return mf_bf16x8{row_slot<8 * Q>(e),     row_slot<8 * Q + 1>(e), row_slot<8 * Q + 2>(e), row_slot<8 * Q + 3>(e),
+                   row_slot<8 * Q + 4>(e), row_slot<8 * Q + 5>(e), row_slot<8 * Q + 6>(e), row_slot<8 * Q + 7>(e)};
+}
+template <int Q>
+__device__ __forceinline__ mf_bf16x8 col_chunk(const __bf16 (&b)[3][3], const __bf16 (&g)[3]) {
+  return mf_bf16x8{col_slot<8 * Q>(b, g),     col_slot<8 * Q + 1>(b, g), col_slot<8 * Q + 2>(b, g),
+                   col_slot<8 * Q + 3>(b, g), col_slot<8 * Q + 4>(b, g), col_slot<8 * Q + 5>(b, g),
+                   col_slot<8 * Q + 6>(b, g), col_slot<8 * Q + 7>(b, g)};
+}
+
+// operand forms: the lane's column operand of tile t (16 columns) from its
+// LDS base, and the product
+template <bool SPLIT>
+struct MfOps;
+template <>
+struct MfOps<false> {
+  using Op = float;                   // staged as [k][column]: base = &st[q][l]
+  static __device__ __forceinline__ Op col(const Op* base, int t) { return base[t * 16]; }
+  static __device__ __forceinline__ mf_f32x4 mma(Op a, Op b, mf_f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MfOps<true> {
+  using Op = mf_bf16x8;               // staged as [column][q]: base = &st[l][q]
+  static __device__ __forceinline__ Op col(const Op* base, int t) { return base[t * 64]; }
+  static __device__ __forceinline__ mf_f32x4 mma(Op a, Op b, mf_f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// The two product passes over the ntl tiles of a staged chunk.  Both are
+// software-pipelined by one row group: the products of group g are issued
+// before the vector work on group g - 1 (the last group's follower is group 0
+// of the next tile; the final followers read the two padding tiles after the
+// chunk and are discarded), so the exp2 of one group never waits on its own
+// product.
+// maximum pass: mx[g] = this lane's maximum exponent of row 16 g + l
+template <bool SPLIT, int G>
+__device__ __forceinline__ void mf_max_pass(const typename MfOps<SPLIT>::Op* base,
+                                            const typename MfOps<SPLIT>::Op (&E)[G], int ntl, float (&mx)[G]) {
+  using O = MfOps<SPLIT>;
+  const mf_f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int g = 0; g < G; ++g) mx[g] = -__builtin_inff();
+  mf_f32x4 c0 = O::mma(O::col(base, 0), E[0], zero);
+  mf_f32x4 c1 = O::mma(O::col(base, 1), E[0], zero);
+  for (int jt = 0; jt < ntl; jt += 2) {
+    const auto b0 = O::col(base, jt), b1 = O::col(base, jt + 1);
+    const auto n0 = O::col(base, jt + 2), n1 = O::col(base, jt + 3);   // padding past the chunk
+#pragma unroll
+    for (int g = 1; g <= G; ++g) {
+      const mf_f32x4 e0 = O::mma(g < G ? b0 : n0, E[g % G], zero);
+      const mf_f32x4 e1 = O::mma(g < G ? b1 : n1, E[g % G], zero);
+      __builtin_amdgcn_sched_barrier(0);   // the products go out first
+      float t = fmaxf(fmaxf(mx[g - 1], c0[0]), c0[1]);
+      t = fmaxf(fmaxf(t, c0[2]), c0[3]);
+      t = fmaxf(fmaxf(t, c1[0]), c1[1]);
+      mx[g - 1] = fmaxf(fmaxf(t, c1[2]), c1[3]);
+      c0 = e0;
+      c1 = e1;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+// sum pass: s[g] += sum of 2^{exponent - max} (nm = minus the row maxima)
+template <bool SPLIT, int G>
+__device__ __forceinline__ void mf_sum_pass(const typename MfOps<SPLIT>::Op* base,
+                                            const typename MfOps<SPLIT>::Op (&E)[G], const mf_f32x4 (&nm)[G],
+                                            int ntl, float (&s)[G]) {
+  using O = MfOps<SPLIT>;
+  mf_f32x4 dc = O::mma(O::col(base, 0), E[0], nm[0]);
+  for (int jt = 0; jt < ntl; ++jt) {
+    const auto b = O::col(base, jt);
+    const auto bn = O::col(base, jt + 1);   // padding past the chunk
+#pragma unroll
+    for (int g = 1; g <= G; ++g) {
+      const mf_f32x4 dn = O::mma(g < G ? b : bn, E[g % G], nm[g % G]);
+      __builtin_amdgcn_sched_barrier(0);
+      s[g - 1] += (__builtin_amdgcn_exp2f(dc[0]) + __builtin_amdgcn_exp2f(dc[1])) +
+                  (__builtin_amdgcn_exp2f(dc[2]) + __builtin_amdgcn_exp2f(dc[3]));
+      dc = dn;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+template <int DIM, int G, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ xr, int64_t Nr,
+                                                      const float* __restrict__ yc, const float* __restrict__ w,
+                                                      int64_t Mc, int64_t cols_per_split,
+                                                      float* __restrict__ pm, float* __restrict__ ps, int side,
+                                                      const Ctrl* __restrict__ c) {
+  static_assert(G % 4 == 0, "a block's rows are loaded 256 at a time");
+  using O = MfOps<SPLIT>;
+  using Op = typename O::Op;
+  if (skip_side(c, side)) return;
+  // column operands of the chunk and two padding tiles (read by the
+  // discarded final products of the passes): FP32 [k][column], BF16 x 3
+  // [column][q]
+  constexpr int kCols = kBlock + 32;
+  __shared__ Op st[4 * kCols];
+  __shared__ float sbox[4][6];
+  const float cc = float(kLog2e / eps_of(c, side));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, q = lane >> 4;
+  const int64_t bbase = (int64_t)blockIdx.x * (64 * G);
+  const int64_t wbase = bbase + wv * (16 * G);
+  // the block centre: middle of the box of its valid rows
+  float xb[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    float lo = __builtin_inff(), hi = -__builtin_inff();
+#pragma unroll
+    for (int t = 0; t < G / 4; ++t) {
+      const int64_t row = bbase + t * kBlock + threadIdx.x;
+      if (row < Nr) {
+        const float v = xr[d * Nr + row];
+        lo = fminf(lo, v);
+        hi = fmaxf(hi, v);
+      }
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (lane == 0) {
+      sbox[wv][2 * d] = lo;
+      sbox[wv][2 * d + 1] = hi;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const float lo = fminf(fminf(sbox[0][2 * d], sbox[1][2 * d]), fminf(sbox[2][2 * d], sbox[3][2 * d]));
+    const float hi =
+        fmaxf(fmaxf(sbox[0][2 * d + 1], sbox[1][2 * d + 1]), fmaxf(sbox[2][2 * d + 1], sbox[3][2 * d + 1]));
+    xb[d] = lo <= hi ? 0.5f * (lo + hi) : 0.f;
+  }
+  // row operands of rows 16 g + l; rows past the end give e = 0
+  Op E[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int64_t row = wbase + g * 16 + li;
+    float e[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) e[d] = (d < DIM && row < Nr) ? xr[d * Nr + row] - xb[d] : 0.f;
+    if constexpr (SPLIT) {
+      __bf16 p[3][3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) split3(e[d], p[d]);
+      const mf_bf16x8 r0 = row_chunk<0>(p), r1 = row_chunk<1>(p), r2 = row_chunk<2>(p), r3 = row_chunk<3>(p);
+      E[g] = q == 0 ? r0 : (q == 1 ? r1 : (q == 2 ? r2 : r3));
+    } else {
+      E[g] = q == 3 ? 1.f : (q == 0 ? e[0] : (q == 1 ? e[1] : e[2]));
+    }
+  }
+  // running (m, s) of row 16 g + l: m is the same in the 4 lanes of the row,
+  // s is this lane's share (its columns)
+  float m[G], s[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    m[g] = -__builtin_inff();
+    s[g] = 0.f;
+  }
+  const Op* base = SPLIT ? &st[li * 4 + q] : &st[q * kCols + li];
+  const int64_t cb = (int64_t)blockIdx.y * cols_per_split;
+  const int64_t ce = (cb + cols_per_split < Mc) ? cb + cols_per_split : Mc;
+  for (int64_t c0 = cb; c0 < ce; c0 += kBlock) {
+    const int64_t col = c0 + threadIdx.x;
+    float y[3] = {0.f, 0.f, 0.f};
+    float wj = -__builtin_inff();
+    if (col < ce) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) y[d] = yc[d * Mc + col];
+      wj = w[col];
+    }
+    float bd[3], d2 = 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float a = d < DIM ? y[d] - xb[d] : 0.f;
+      bd[d] = 2.f * cc * a;
+      d2 = __builtin_fmaf(a, a, d2);
+    }
+    const float gj = wj == -__builtin_inff() ? wj : __builtin_fmaf(-cc, d2, wj);
+    __syncthreads();                     // the previous chunk's reads are done
+    if constexpr (SPLIT) {
+      __bf16 b[3][3], gp[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) split3(bd[d], b[d]);
+      split3(gj, gp);
+      st[threadIdx.x * 4 + 0] = col_chunk<0>(b, gp);
+      st[threadIdx.x * 4 + 1] = col_chunk<1>(b, gp);
+      st[threadIdx.x * 4 + 2] = col_chunk<2>(b, gp);
+      st[threadIdx.x * 4 + 3] = col_chunk<3>(b, gp);
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) st[d * kCols + threadIdx.x] = bd[d];
+      st[3 * kCols + threadIdx.x] = gj;
+    }
+    __syncthreads();
+    const int64_t rem = ce - c0;
+    const int cnt = rem < kBlock ? (int)rem : kBlock;
+    // an even tile count (the staged padding is -inf), uniform
+    const int ntl = __builtin_amdgcn_readfirstlane(((cnt + 31) >> 5) << 1);
+    // a chunk with a row that has no finite running maximum yet (the first
+    // chunk) takes the maximum pass first; others run the sum pass against
+    // the running maxima and take the two passes only when a row's sum leaves
+    // [0, 2^100) (a new maximum far above the old one)
+    bool two = false;
+#pragma unroll
+    for (int g = 0; g < G; ++g) two = two || m[g] == -__builtin_inff();
+    two = __any(two);
+    if (!two) {
+      float s0[G];
+      mf_f32x4 nm[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        s0[g] = s[g];
+        nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
+      }
+      mf_sum_pass<SPLIT, G>(base, E, nm, ntl, s);
+      float tot[G];
+      bool bad = false;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        tot[g] = sum_over_rows(s[g]);
+        bad = bad || !(tot[g] < 0x1p100f);
+      }
+      if (__any(bad)) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) s[g] = s0[g];
+        two = true;
+      } else {
+        // keep the sums near 1: move whole powers of two into the maxima (the
+        // same in the 4 lanes of a row, whose totals are equal)
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          if (tot[g] > 0x1p32f) {
+            const int k = __builtin_amdgcn_frexp_expf(tot[g]);
+            m[g] += float(k);
+            s[g] = __builtin_amdgcn_ldexpf(s[g], -k);
+          }
+      }
+    }
+    if (two) {
+      float mx[G];
+      mf_max_pass<SPLIT, G>(base, E, ntl, mx);
+      // new running maxima; rescale the sums; accumulator input -max
+      mf_f32x4 nm[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const float mn = fmaxf(m[g], max_over_rows(mx[g]));
+        const float sh = mn == -__builtin_inff() ? 0.f : mn;
+        s[g] *= __builtin_amdgcn_exp2f(m[g] - sh);
+        m[g] = mn;
+        nm[g] = mf_f32x4{-sh, -sh, -sh, -sh};
+      }
+      mf_sum_pass<SPLIT, G>(base, E, nm, ntl, s);
+    }
+  }
+  // totals of each row over its 4 lanes; lanes q = 0 write row 16 g + l,
+  // adding R_i
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const float sr = sum_over_rows(s[g]);
+    const int64_t row = wbase + g * 16 + li;
+    if (q == 0 && row < Nr) {
+      float e2 = 0.f;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const float e = xr[d * Nr + row] - xb[d];
+        e2 = __builtin_fmaf(e, e, e2);
+      }
+      pm[blockIdx.y * Nr + row] = m[g] == -__builtin_inff() ? m[g] : __builtin_fmaf(-cc, e2, m[g]);
+      ps[blockIdx.y * Nr + row] = sr;
+    }
+  }
+}
+
+void launch_dense_mf(int dim, int groups, bool split, const float* xr, int64_t Nr, const float* yc, const float* w,
+                     int64_t Mc, int nsplit, int64_t cps, float* pm, float* ps, int side, const Ctrl* c,
+                     hipStream_t s) {
+#define UOT_MF(D, G, S)                                                                                        \
+  hipLaunchKernelGGL((k_dense_mf<D, G, S>), dim3((unsigned)((Nr + 64 * G - 1) / (64 * G)), (unsigned)nsplit), \
+                     dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side, c)
+#define UOT_MF_DIM(G, S)              \
+  if (dim == 1) UOT_MF(1, G, S);      \
+  else if (dim == 2) UOT_MF(2, G, S); \
+  else UOT_MF(3, G, S);
+  if (split) {
+    if (groups == 8) {
+      UOT_MF_DIM(8, true)
+    } else {
+      UOT_MF_DIM(4, true)
+    }
+  } else {
+    if (groups == 8) {
+      UOT_MF_DIM(8, false)
+    } else {
+      UOT_MF_DIM(4, false)
+    }
+  }
+#undef UOT_MF_DIM
+#undef UOT_MF
+}
+
+}  // namespace uot

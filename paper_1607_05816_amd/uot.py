@@ -351,7 +351,7 @@ def grid_problem(shape: Sequence[int], h: Sequence[float], p, q, dx, dy, F1: Div
 
 
 GRID_AUTO, GRID_DIRECT, GRID_MFMA, GRID_MFMA16, GRID_MIXED = 0, 1, 2, 3, 4
-DENSE_AUTO, DENSE_DIRECT, DENSE_TF = 0, 1, 2
+DENSE_AUTO, DENSE_DIRECT, DENSE_TF, DENSE_MF, DENSE_MF3 = 0, 1, 2, 3, 4
 
 
 def params(eps, tol=1e-6, max_iter=10000, eps0=None, eps_stages=10, iters_per_stage=100, check_every=50,

@@ -1,8 +1,10 @@
-"""The tile-factored dense product (dense_kernel 2: Morton-ordered copies,
-tile pairs factored exactly, wide pairs summed directly) against the FP64
-oracle and against the direct product, FP32.  Inputs are given in random
-order: the library orders them itself and returns potentials in the caller's
-order.  Tolerance 1e-5 relative on potentials (FP32)."""
+"""The factored dense products against the FP64 oracle and against the direct
+product, FP32: dense_kernel 2 (Morton-ordered copies, tile pairs factored
+exactly, wide pairs summed directly; inputs are given in random order, the
+library orders them itself and returns potentials in the caller's order) and
+dense_kernels 3 and 4 (exponents of 16 x 16 pairs as one MFMA product around
+a centre per block of rows: FP32 operands, or operands split into three bf16
+parts).  Tolerance 1e-5 relative on potentials (FP32)."""
 import sys
 
 import numpy as np
@@ -39,33 +41,39 @@ def mixture(seed, N, M, d):
             rounded(pr.dx, np.float32), rounded(pr.dy, np.float32))
 
 
+KERNELS = [pytest.param(U.DENSE_TF, id="tf"), pytest.param(U.DENSE_MF, id="mfma"),
+           pytest.param(U.DENSE_MF3, id="mfma_bf16x3")]
+
+
+@pytest.mark.parametrize("kern", KERNELS)
 @pytest.mark.parametrize("d", [1, 2, 3])
 @pytest.mark.parametrize("eps", [1e-2, 1e-4])
-def test_dense_tf_fixed_iterations(d, eps):
+def test_dense_tf_fixed_iterations(d, eps, kern):
     """N = 3000, M = 2500 (ragged tails), KL 1; at eps = 1e-4 many tile pairs
-    are too wide to factor and are summed directly."""
+    are too wide to factor and are summed directly (kernel 2)."""
     x, y, p, q, dx, dy = mixture(d, 3000, 2500, d)
     F = U.KL(1.0)
-    say("case dense tf", d, eps)
+    say("case dense factored", kern, d, eps)
     prob = U.points_problem(T(x), T(y), T(p), T(q), T(dx), T(dy), F, F)
-    u, v, info = U.solve(prob, eps, tol=0.0, max_iter=20, dense_kernel=U.DENSE_TF)
+    u, v, info = U.solve(prob, eps, tol=0.0, max_iter=20, dense_kernel=kern)
     ref = O.solve(O.PointsGeom(x, y), np.log(p), np.log(q), np.log(dx), np.log(dy), O.KL(1.0), O.KL(1.0), eps,
                   tol=0.0, max_iter=20)
     assert pot_rel_err(u.cpu(), ref["u"], eps) < 1e-5
     assert pot_rel_err(v.cpu(), ref["v"], eps) < 1e-5
 
 
-def test_dense_tf_eps_scaling_and_residuals():
+@pytest.mark.parametrize("kern", KERNELS)
+def test_dense_tf_eps_scaling_and_residuals(kern):
     """eps-scaling 1e-1 -> 1e-3 with a warm start and the residual history:
-    the tile-factored run follows the oracle's iterates."""
+    the factored run follows the oracle's iterates."""
     x, y, p, q, dx, dy = mixture(7, 1500, 1800, 3)
     F = U.TV(0.2)
     rng = np.random.default_rng(3)
     v0 = rounded(0.01 * rng.standard_normal(1800), np.float32)
-    say("case dense tf eps-scaling")
+    say("case dense factored eps-scaling", kern)
     prob = U.points_problem(T(x), T(y), T(p), T(q), T(dx), T(dy), F, F)
     u, v, info = U.solve(prob, 1e-3, eps0=1e-1, iters_per_stage=10, tol=0.0, max_iter=120, v0=T(v0),
-                         dense_kernel=U.DENSE_TF, record=True)
+                         dense_kernel=kern, record=True)
     ref = O.solve(O.PointsGeom(x, y), np.log(p), np.log(q), np.log(dx), np.log(dy), O.TV(0.2), O.TV(0.2), 1e-3,
                   tol=0.0, max_iter=120, eps0=1e-1, iters_per_stage=10, v0=v0)
     assert pot_rel_err(u.cpu(), ref["u"], 1e-3) < 1e-5
@@ -73,14 +81,76 @@ def test_dense_tf_eps_scaling_and_residuals():
     np.testing.assert_allclose(info["res_hist"].numpy()[1:], ref["res"][1:], rtol=1e-3, atol=1e-7)
 
 
-def test_dense_tf_matches_direct_full_size():
+@pytest.mark.parametrize("kern", KERNELS)
+def test_dense_tf_matches_direct_full_size(kern):
     """N = M = 20000 3-D mixture clouds, eps = 1e-3, 40 iterations: the
-    tile-factored and the direct product give the same potentials."""
+    factored and the direct product give the same potentials."""
     pr = synth.clouds3d(0, N=20000, M=20000)
     F = U.KL(1.0)
-    say("case dense tf full size")
+    say("case dense factored full size", kern)
     prob = U.points_problem(T(pr.x), T(pr.y), T(pr.p), T(pr.q), T(pr.dx), T(pr.dy), F, F)
     u1, v1, _ = U.solve(prob, 1e-3, tol=0.0, max_iter=40, dense_kernel=U.DENSE_DIRECT)
-    u2, v2, _ = U.solve(prob, 1e-3, tol=0.0, max_iter=40, dense_kernel=U.DENSE_TF)
+    u2, v2, _ = U.solve(prob, 1e-3, tol=0.0, max_iter=40, dense_kernel=kern)
     assert pot_rel_err(u2.cpu(), u1.cpu().numpy(), 1e-3) < 1e-5
     assert pot_rel_err(v2.cpu(), v1.cpu().numpy(), 1e-3) < 1e-5
+
+
+@pytest.mark.parametrize("kern", KERNELS)
+@pytest.mark.parametrize("N,M", [(1, 1), (1, 37), (53, 1), (700, 513)])
+def test_dense_factored_small_and_vanishing(N, M, kern):
+    """Degenerate sizes (one row, one column, tails shorter than a tile) and
+    zero densities on both sides (the vanishing-product rule: -inf potentials
+    where the density is zero), KL 0.5, eps = 1e-2."""
+    rng = np.random.default_rng(N * 1000 + M)
+    x = rounded(rng.random((N, 2)), np.float32)
+    y = rounded(rng.random((M, 2)), np.float32)
+    p = rng.random(N) + 0.1
+    q = rng.random(M) + 0.1
+    if N > 1:
+        p[::5] = 0.0
+    if M > 1:
+        q[1::4] = 0.0
+    p, q = rounded(p, np.float32), rounded(q, np.float32)
+    dx = rounded(np.full(N, 1.0 / N), np.float32)
+    dy = rounded(np.full(M, 1.0 / M), np.float32)
+    F = U.KL(0.5)
+    say("case dense factored small", kern, N, M)
+    prob = U.points_problem(T(x), T(y), T(p), T(q), T(dx), T(dy), F, F)
+    u, v, info = U.solve(prob, 1e-2, tol=0.0, max_iter=15, dense_kernel=kern)
+    ref = O.solve(O.PointsGeom(x, y), np.log(p), np.log(q), np.log(dx), np.log(dy), O.KL(0.5), O.KL(0.5), 1e-2,
+                  tol=0.0, max_iter=15)
+    assert pot_rel_err(u.cpu(), ref["u"], 1e-2) < 1e-5
+    assert pot_rel_err(v.cpu(), ref["v"], 1e-2) < 1e-5
+
+
+@pytest.mark.parametrize("kern", [pytest.param(U.DENSE_MF, id="mfma"), pytest.param(U.DENSE_MF3, id="mfma_bf16x3")])
+@pytest.mark.parametrize("far_first", [True, False])
+def test_dense_mf_running_max_jumps(far_first, kern):
+    """Kernels 3 and 4 carry a running row maximum from chunk to chunk of 256
+    columns.  N = 3000, M = 100000 on a line: each column split holds 320
+    columns, the first 256 (or the last 64) of them at distance >= 0.4 from
+    every row, so at eps = 1e-3 the next chunk's exponents jump more than 2^127
+    above the running maximum (the chunk is redone with a maximum pass) or fall
+    as far below it.  Compared with the direct product, which the oracle
+    parity tests pin, after 2 iterations, relative to the larger of the two
+    potentials' norms (u alone is small here)."""
+    N, M = 3000, 100000
+    rng = np.random.default_rng(11 if far_first else 12)
+    x = rounded(0.1 * rng.random((N, 1)), np.float32)
+    j = np.arange(M)
+    far = (j % 320) < 256 if far_first else (j % 320) >= 256
+    y = np.where(far, 0.5 + 0.1 * rng.random(M), 0.1 * rng.random(M))[:, None]
+    y = rounded(y, np.float32)
+    p = rounded(rng.random(N) + 0.5, np.float32)
+    q = rounded(rng.random(M) + 0.5, np.float32)
+    dx = rounded(np.full(N, 1.0 / N), np.float32)
+    dy = rounded(np.full(M, 1.0 / M), np.float32)
+    F = U.KL(1.0)
+    say("case dense mf running max", far_first, kern)
+    prob = U.points_problem(T(x), T(y), T(p), T(q), T(dx), T(dy), F, F)
+    u1, v1, _ = U.solve(prob, 1e-3, tol=0.0, max_iter=2, dense_kernel=U.DENSE_DIRECT)
+    u2, v2, _ = U.solve(prob, 1e-3, tol=0.0, max_iter=2, dense_kernel=kern)
+    u1, v1, u2, v2 = (t.cpu().numpy().astype(np.float64) for t in (u1, v1, u2, v2))
+    scale = max(np.abs(u1).max(), np.abs(v1).max())
+    assert np.abs(u2 - u1).max() / scale < 1e-5
+    assert np.abs(v2 - v1).max() / scale < 1e-5
