@@ -271,11 +271,18 @@ def grid_roofline(U, probs, last, ctx, torch, np, nb_fields=256):
     return out
 
 
+DENSE_KERNELS = ((1, "direct", "k_dense_lse<float, 3, 2, 0>"), (2, "tile_factored", "k_dense_tf<3, 2>"),
+                 (3, "mfma_fp32", "k_dense_mf<3, 4, false>"), (4, "mfma_bf16x3", "k_dense_mf<3, 4, true>"))
+
+
 def dense_roofline(U, torch, np, dev, ctx, n=20000, eps=1e-3):
     """Dense point-cloud product (3-D clouds, N = M = 20000, 8-component
-    mixtures, FP32): the column-split log-sum-exp kernel of one X half-step,
-    launched back to back between HIP events.  Algorithmic work: one exp per
-    pair (N M per launch), priced against the v_exp_f32 issue peak."""
+    mixtures, FP32 data): the column-split log-sum-exp kernel of one X
+    half-step, launched back to back between HIP events, for each product
+    kernel (the default is the BF16 x 3 matrix-core one).  Algorithmic work:
+    one exp per pair (N M per launch), priced against the v_exp_f32 issue
+    peak; with one add per pair beside it the vector units cap a kernel at
+    2/3 of that peak."""
     from paper_1607_05816_amd import synth
     pr = synth.clouds3d(0, N=n, M=n)
     T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
@@ -283,13 +290,50 @@ def dense_roofline(U, torch, np, dev, ctx, n=20000, eps=1e-3):
     pb = U.points_problem(T(pr.x), T(pr.y), T(pr.p), T(pr.q), T(pr.dx), T(pr.dy), F, F)
     pb.workspace()
     v = torch.zeros(n, dtype=torch.float32, device=dev)
-    ms = U.time_half_step(pb, eps, v, reps=20, ctx=ctx)
     pairs = float(n) * n
     peak = exp_peak()
-    return {"bound": "alu", "kernel": "k_dense_lse<float, 3, 2>", "kernel_avg_ms": ms[0],
-            "achieved": pairs / (ms[0] * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "Texp/s",
-            "frac": pairs / (ms[0] * 1e-3) / peak, "work_per_launch": pairs, "work_unit": "exp (one per pair)",
-            "epilogue_ms": ms[1], "workload": "clouds3d N=M=%d eps=%g FP32" % (n, eps)}
+    by = {}
+    for k, name, kern in DENSE_KERNELS:
+        ms = U.time_half_step(pb, eps, v, reps=20, ctx=ctx, grid_kernel=k)
+        by[name] = {"kernel": kern, "kernel_avg_ms": ms[0], "merge_epilogue_ms": ms[1],
+                    "frac": pairs / (ms[0] * 1e-3) / peak}
+    d = by["mfma_bf16x3"]
+    return {"bound": "alu", "kernel": d["kernel"], "kernel_avg_ms": d["kernel_avg_ms"],
+            "achieved": pairs / (d["kernel_avg_ms"] * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "Texp/s",
+            "frac": d["frac"], "work_per_launch": pairs, "work_unit": "exp (one per pair)",
+            "epilogue_ms": d["merge_epilogue_ms"], "by_kernel": by,
+            "workload": "clouds3d N=M=%d eps=%g FP32, v = 0" % (n, eps)}
+
+
+def dense_solve(U, torch, np, dev, ctx, n=20000):
+    """The dense configuration end to end: N = M = 20000 3-D mixture clouds,
+    KL 1, eps 1e-1 -> 1e-3 (10 stages of 100 iterations, then to residual
+    1e-6), FP32 data, with the default (matrix-core) product and with the
+    direct one; potentials of the two compared."""
+    from paper_1607_05816_amd import synth
+    pr = synth.clouds3d(0, N=n, M=n)
+    T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
+    F = U.KL(1.0)
+    pb = U.points_problem(T(pr.x), T(pr.y), T(pr.p), T(pr.q), T(pr.dx), T(pr.dy), F, F)
+    pb.workspace()
+    out = {"workload": "clouds3d N=M=%d KL1 eps 1e-1->1e-3 10x100 tol 1e-6 FP32" % n}
+    pots = {}
+    for k, name in ((0, "default_mfma_bf16x3"), (1, "direct")):
+        U.solve(pb, 1e-3, eps0=1e-1, tol=1e-6, max_iter=3000, check_every=50, ctx=ctx, dense_kernel=k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, v, info = U.solve(pb, 1e-3, eps0=1e-1, tol=1e-6, max_iter=3000, check_every=50, ctx=ctx,
+                             dense_kernel=k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        pots[name] = (u.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64))
+        out[name] = {"seconds": dt, "iters": int(info["iters"]), "iters_per_s": info["iters"] / dt,
+                     "converged": bool(info["converged"]), "residual": float(info["residual"])}
+    (u1, v1), (u2, v2) = pots["default_mfma_bf16x3"], pots["direct"]
+    sc = max(np.abs(u2).max(), np.abs(v2).max())
+    out["max_potential_diff_rel"] = float(max(np.abs(u1 - u2).max(), np.abs(v1 - v2).max()) / sc)
+    out["speedup_vs_direct"] = out["direct"]["seconds"] / out["default_mfma_bf16x3"]["seconds"]
+    return out
 
 
 def wf_dense_roofline(U, torch, np, dev, ctx, n=20000, cut=0.1, eps=1e-3):
@@ -570,6 +614,7 @@ def main():
     }
     if not args.no_dense:
         line["roofline_dense"] = dense_roofline(U, torch, np, dev, ctx)
+        line["dense_solve"] = dense_solve(U, torch, np, dev, ctx)
     if not args.no_gemm:
         line["roofline_gemm"] = gemm_roofline(U, torch, np, dev, ctx)
     if not args.no_extensions:

@@ -145,8 +145,9 @@ struct Plan {
   bool sorted() const { return dense_tf || dense_mf; }
   // workspace offsets
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
-      o_gcost, o_obj, o_scal, o_mass, o_xs, o_ys, o_permx, o_permy, o_code, o_box, o_us, o_vs, total;
+      o_gcost, o_obj, o_scal, o_mass, o_xs, o_ys, o_permx, o_permy, o_code, o_box, o_us, o_vs, o_pw, total;
   int64_t obj_doubles = 0;
+  int64_t np_pw = 0;                         // points: row maxima per side (matrix-core product)
 };
 
 bool use_tf(const Plan& P, int axis) { return P.tf_axis[axis]; }
@@ -301,6 +302,7 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
     }
     P.o_pm = take(e * np);
     P.o_ps = take(e * np);
+    P.np_pw = np;
     P.nparts_x = (int)((P.N + 255) / 256);
   } else {
     const size_t np = P.dim == 1 && P.split1d > 1 ? (size_t)P.split1d * nb * P.N : 0;
@@ -332,6 +334,9 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
   P.o_box = take(pts ? e * 6 : 0);
   P.o_us = take(pts ? e * P.N : 0);
   P.o_vs = take(pts ? e * P.M : 0);
+  // row maxima the matrix-core product leaves for the next product of the
+  // same side (two sides)
+  P.o_pw = take(pts ? sizeof(float) * 2 * P.np_pw : 0);
   P.total = o;
   return UOT_OK;
 }
@@ -380,6 +385,7 @@ template <typename T> struct Bufs {
   double* obj;
   double* scal;
   T *mass_m, *mass_s;     // mass partials of Algorithm 4 (Y epilogue)
+  float* pw;              // points: row maxima of the two sides' products
 };
 
 template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
@@ -396,6 +402,7 @@ template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
   b.t3 = at<T>(ws, P.o_t3);
   b.pm = at<T>(ws, P.o_pm);
   b.ps = at<T>(ws, P.o_ps);
+  b.pw = at<float>(ws, P.o_pw);
   b.parts = at<ResPart>(ws, P.o_parts);
   for (int k = 0; k < 3; ++k) b.gtab[k] = at<T>(ws, P.o_gtab[k]);
   b.gcost = at<T>(ws, P.o_gcost);
@@ -500,7 +507,7 @@ void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Buf
       }
       if (P.dense_mf) {
         launch_dense_mf(P.dim, P.mf_groups, P.mf_split, rows, Nr, cols, w_cols, Mc, P.splits[half], P.cps[half], B.pm, B.ps,
-                        side, c, s);
+                        B.pw + half * P.np_pw, side, c, s);
         return;
       }
     }
@@ -1238,8 +1245,8 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
           return;
         }
         if (P.dense_mf) {
-          launch_dense_mf(P.dim, P.mf_groups, P.mf_split, rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps, 0,
-                          B.ctrl, s);
+          launch_dense_mf(P.dim, P.mf_groups, P.mf_split, rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps,
+                          B.pw, 0, B.ctrl, s);
           return;
         }
       }

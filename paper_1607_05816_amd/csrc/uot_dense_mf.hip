@@ -35,15 +35,19 @@
 // exponents of row 16 g + l against columns 4 q .. 4 q + 3 of the tile:
 // every lane keeps one running sum per row group, and a row is spread over
 // the 4 lanes l + 16 q.
-// Shift: the sum pass feeds minus the running maximum m of each row in as
-// the accumulator input.  Where m is not yet finite (the first chunk), a
-// maximum pass over the chunk (lane maxima, then over the 4 lanes of the
-// row) sets it first, so every exp2 argument is <= 0.  Later chunks run the
-// sum pass alone against the running m: a term above m stays finite up to
-// 2^127, and the chunk is redone with both passes when a row total is not
-// below 2^100 (which includes an overflow); otherwise whole powers of two of
-// the total move into m.  Terms that underflow lie more than 2^126 below a
-// term already summed, so they do not change the result.
+// Shift: the sum pass feeds minus a running maximum m of each row in as the
+// accumulator input.  m starts from the row's maximum over the same column
+// split in the previous product of this side (pw; the potentials move little
+// between iterations), or is not finite.  A chunk where some row has no
+// finite m takes a maximum pass first (lane maxima, then over the 4 lanes of
+// the row), so every exp2 argument is <= 0.  Otherwise the sum pass runs
+// alone against m: a term above m stays finite up to 2^127, and the chunk is
+// redone with both passes when a row total is not below 2^100 (which
+// includes an overflow); otherwise whole powers of two of the total move into
+// m.  A row whose final total is below 2^-60 started from an m too high: the
+// block then sums its split again from no maximum.  So every accepted total
+// has a term within 2^60 of m, and the terms that underflow (more than
+// 2^126 below m) do not change it.
 // Columns without mass (and padding) carry G = -inf, so their terms are 0.
 // G row groups of 16 per wave (64 G rows per block);
 // grid = (ceil(Nr / (64 G)), splits); partials (m, s) per split as the
@@ -203,8 +207,8 @@ template <int DIM, int G, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ xr, int64_t Nr,
                                                       const float* __restrict__ yc, const float* __restrict__ w,
                                                       int64_t Mc, int64_t cols_per_split,
-                                                      float* __restrict__ pm, float* __restrict__ ps, int side,
-                                                      const Ctrl* __restrict__ c) {
+                                                      float* __restrict__ pm, float* __restrict__ ps,
+                                                      float* __restrict__ pw, int side, const Ctrl* __restrict__ c) {
   static_assert(G % 4 == 0, "a block's rows are loaded 256 at a time");
   using O = MfOps<SPLIT>;
   using Op = typename O::Op;
@@ -269,113 +273,131 @@ __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ x
   }
   // running (m, s) of row 16 g + l: m is the same in the 4 lanes of the row,
   // s is this lane's share (its columns)
-  float m[G], s[G];
+  float m[G], s[G], wm[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    m[g] = -__builtin_inff();
-    s[g] = 0.f;
+    const int64_t row = wbase + g * 16 + li;
+    const float v = row < Nr ? pw[blockIdx.y * Nr + row] : -__builtin_inff();
+    wm[g] = __builtin_isfinite(v) ? v : -__builtin_inff();
   }
   const Op* base = SPLIT ? &st[li * 4 + q] : &st[q * kCols + li];
   const int64_t cb = (int64_t)blockIdx.y * cols_per_split;
   const int64_t ce = (cb + cols_per_split < Mc) ? cb + cols_per_split : Mc;
-  for (int64_t c0 = cb; c0 < ce; c0 += kBlock) {
-    const int64_t col = c0 + threadIdx.x;
-    float y[3] = {0.f, 0.f, 0.f};
-    float wj = -__builtin_inff();
-    if (col < ce) {
+  float tot[G];
+  for (int attempt = 0;; ++attempt) {
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) y[d] = yc[d * Mc + col];
-      wj = w[col];
+    for (int g = 0; g < G; ++g) {
+      m[g] = attempt == 0 ? wm[g] : -__builtin_inff();
+      s[g] = 0.f;
     }
-    float bd[3], d2 = 0.f;
+    for (int64_t c0 = cb; c0 < ce; c0 += kBlock) {
+      const int64_t col = c0 + threadIdx.x;
+      float y[3] = {0.f, 0.f, 0.f};
+      float wj = -__builtin_inff();
+      if (col < ce) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const float a = d < DIM ? y[d] - xb[d] : 0.f;
-      bd[d] = 2.f * cc * a;
-      d2 = __builtin_fmaf(a, a, d2);
-    }
-    const float gj = wj == -__builtin_inff() ? wj : __builtin_fmaf(-cc, d2, wj);
-    __syncthreads();                     // the previous chunk's reads are done
-    if constexpr (SPLIT) {
-      __bf16 b[3][3], gp[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) split3(bd[d], b[d]);
-      split3(gj, gp);
-      st[threadIdx.x * 4 + 0] = col_chunk<0>(b, gp);
-      st[threadIdx.x * 4 + 1] = col_chunk<1>(b, gp);
-      st[threadIdx.x * 4 + 2] = col_chunk<2>(b, gp);
-      st[threadIdx.x * 4 + 3] = col_chunk<3>(b, gp);
-    } else {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) st[d * kCols + threadIdx.x] = bd[d];
-      st[3 * kCols + threadIdx.x] = gj;
-    }
-    __syncthreads();
-    const int64_t rem = ce - c0;
-    const int cnt = rem < kBlock ? (int)rem : kBlock;
-    // an even tile count (the staged padding is -inf), uniform
-    const int ntl = __builtin_amdgcn_readfirstlane(((cnt + 31) >> 5) << 1);
-    // a chunk with a row that has no finite running maximum yet (the first
-    // chunk) takes the maximum pass first; others run the sum pass against
-    // the running maxima and take the two passes only when a row's sum leaves
-    // [0, 2^100) (a new maximum far above the old one)
-    bool two = false;
-#pragma unroll
-    for (int g = 0; g < G; ++g) two = two || m[g] == -__builtin_inff();
-    two = __any(two);
-    if (!two) {
-      float s0[G];
-      mf_f32x4 nm[G];
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        s0[g] = s[g];
-        nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
+        for (int d = 0; d < DIM; ++d) y[d] = yc[d * Mc + col];
+        wj = w[col];
       }
-      mf_sum_pass<SPLIT, G>(base, E, nm, ntl, s);
-      float tot[G];
-      bool bad = false;
+      float bd[3], d2 = 0.f;
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        tot[g] = sum_over_rows(s[g]);
-        bad = bad || !(tot[g] < 0x1p100f);
+      for (int d = 0; d < 3; ++d) {
+        const float a = d < DIM ? y[d] - xb[d] : 0.f;
+        bd[d] = 2.f * cc * a;
+        d2 = __builtin_fmaf(a, a, d2);
       }
-      if (__any(bad)) {
+      const float gj = wj == -__builtin_inff() ? wj : __builtin_fmaf(-cc, d2, wj);
+      __syncthreads();                     // the previous chunk's reads are done
+      if constexpr (SPLIT) {
+        __bf16 b[3][3], gp[3];
 #pragma unroll
-        for (int g = 0; g < G; ++g) s[g] = s0[g];
-        two = true;
+        for (int d = 0; d < 3; ++d) split3(bd[d], b[d]);
+        split3(gj, gp);
+        st[threadIdx.x * 4 + 0] = col_chunk<0>(b, gp);
+        st[threadIdx.x * 4 + 1] = col_chunk<1>(b, gp);
+        st[threadIdx.x * 4 + 2] = col_chunk<2>(b, gp);
+        st[threadIdx.x * 4 + 3] = col_chunk<3>(b, gp);
       } else {
-        // keep the sums near 1: move whole powers of two into the maxima (the
-        // same in the 4 lanes of a row, whose totals are equal)
 #pragma unroll
-        for (int g = 0; g < G; ++g)
-          if (tot[g] > 0x1p32f) {
-            const int k = __builtin_amdgcn_frexp_expf(tot[g]);
-            m[g] += float(k);
-            s[g] = __builtin_amdgcn_ldexpf(s[g], -k);
-          }
+        for (int d = 0; d < 3; ++d) st[d * kCols + threadIdx.x] = bd[d];
+        st[3 * kCols + threadIdx.x] = gj;
+      }
+      __syncthreads();
+      const int64_t rem = ce - c0;
+      const int cnt = rem < kBlock ? (int)rem : kBlock;
+      // an even tile count (the staged padding is -inf), uniform
+      const int ntl = __builtin_amdgcn_readfirstlane(((cnt + 31) >> 5) << 1);
+      // a chunk with a row that has no finite running maximum yet (the first
+      // chunk) takes the maximum pass first; others run the sum pass against
+      // the running maxima and take the two passes only when a row's sum leaves
+      // [0, 2^100) (a new maximum far above the old one)
+      bool two = false;
+#pragma unroll
+      for (int g = 0; g < G; ++g) two = two || m[g] == -__builtin_inff();
+      two = __any(two);
+      if (!two) {
+        float s0[G];
+        mf_f32x4 nm[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          s0[g] = s[g];
+          nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
+        }
+        mf_sum_pass<SPLIT, G>(base, E, nm, ntl, s);
+        bool bad = false;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          tot[g] = sum_over_rows(s[g]);
+          bad = bad || !(tot[g] < 0x1p100f);
+        }
+        if (__any(bad)) {
+#pragma unroll
+          for (int g = 0; g < G; ++g) s[g] = s0[g];
+          two = true;
+        } else {
+          // keep the sums near 1: move whole powers of two into the maxima (the
+          // same in the 4 lanes of a row, whose totals are equal)
+#pragma unroll
+          for (int g = 0; g < G; ++g)
+            if (tot[g] > 0x1p32f) {
+              const int k = __builtin_amdgcn_frexp_expf(tot[g]);
+              m[g] += float(k);
+              s[g] = __builtin_amdgcn_ldexpf(s[g], -k);
+            }
+        }
+      }
+      if (two) {
+        float mx[G];
+        mf_max_pass<SPLIT, G>(base, E, ntl, mx);
+        // new running maxima; rescale the sums; accumulator input -max
+        mf_f32x4 nm[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const float mn = fmaxf(m[g], max_over_rows(mx[g]));
+          const float sh = mn == -__builtin_inff() ? 0.f : mn;
+          s[g] *= __builtin_amdgcn_exp2f(m[g] - sh);
+          m[g] = mn;
+          nm[g] = mf_f32x4{-sh, -sh, -sh, -sh};
+        }
+        mf_sum_pass<SPLIT, G>(base, E, nm, ntl, s);
       }
     }
-    if (two) {
-      float mx[G];
-      mf_max_pass<SPLIT, G>(base, E, ntl, mx);
-      // new running maxima; rescale the sums; accumulator input -max
-      mf_f32x4 nm[G];
+    // totals of each row over its 4 lanes; a total below 2^-60 under a finite
+    // maximum came from a starting maximum too high: sum the split again from
+    // none (the whole block, as the chunk loop holds barriers)
+    bool low = false;
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const float mn = fmaxf(m[g], max_over_rows(mx[g]));
-        const float sh = mn == -__builtin_inff() ? 0.f : mn;
-        s[g] *= __builtin_amdgcn_exp2f(m[g] - sh);
-        m[g] = mn;
-        nm[g] = mf_f32x4{-sh, -sh, -sh, -sh};
-      }
-      mf_sum_pass<SPLIT, G>(base, E, nm, ntl, s);
+    for (int g = 0; g < G; ++g) {
+      tot[g] = sum_over_rows(s[g]);
+      low = low || (m[g] != -__builtin_inff() && !(tot[g] >= 0x1p-60f));
     }
+    if (attempt > 0 || !__syncthreads_or(low)) break;
   }
-  // totals of each row over its 4 lanes; lanes q = 0 write row 16 g + l,
-  // adding R_i
+  // lanes q = 0 write row 16 g + l: (m + R_i, total), and m for the next
+  // product of this side
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    const float sr = sum_over_rows(s[g]);
+    const float sr = tot[g];
     const int64_t row = wbase + g * 16 + li;
     if (q == 0 && row < Nr) {
       float e2 = 0.f;
@@ -386,16 +408,17 @@ __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ x
       }
       pm[blockIdx.y * Nr + row] = m[g] == -__builtin_inff() ? m[g] : __builtin_fmaf(-cc, e2, m[g]);
       ps[blockIdx.y * Nr + row] = sr;
+      pw[blockIdx.y * Nr + row] = m[g];
     }
   }
 }
 
 void launch_dense_mf(int dim, int groups, bool split, const float* xr, int64_t Nr, const float* yc, const float* w,
-                     int64_t Mc, int nsplit, int64_t cps, float* pm, float* ps, int side, const Ctrl* c,
+                     int64_t Mc, int nsplit, int64_t cps, float* pm, float* ps, float* pw, int side, const Ctrl* c,
                      hipStream_t s) {
 #define UOT_MF(D, G, S)                                                                                        \
   hipLaunchKernelGGL((k_dense_mf<D, G, S>), dim3((unsigned)((Nr + 64 * G - 1) / (64 * G)), (unsigned)nsplit), \
-                     dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side, c)
+                     dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, pw, side, c)
 #define UOT_MF_DIM(G, S)              \
   if (dim == 1) UOT_MF(1, G, S);      \
   else if (dim == 2) UOT_MF(2, G, S); \

@@ -91,9 +91,11 @@ void launch_dense_tf(int dim, const float* xr, int64_t Nr, const float* yc, cons
                      int64_t cps, float* pm, float* ps, int side, const Ctrl* c, hipStream_t s);
 // dense product on the matrix cores (FP32 data, squared Euclidean): groups =
 // 4 or 8 row groups of 16 per wave; split: BF16 x 3 operands on
-// v_mfma_f32_16x16x32_bf16, else FP32 operands on v_mfma_f32_16x16x4f32
+// v_mfma_f32_16x16x32_bf16, else FP32 operands on v_mfma_f32_16x16x4f32;
+// pw (nsplit x Nr, kept between the products of one side): the row maxima
+// the product starts from and leaves for the next one
 void launch_dense_mf(int dim, int groups, bool split, const float* xr, int64_t Nr, const float* yc, const float* w,
-                     int64_t Mc, int nsplit, int64_t cps, float* pm, float* ps, int side, const Ctrl* c,
+                     int64_t Mc, int nsplit, int64_t cps, float* pm, float* ps, float* pw, int side, const Ctrl* c,
                      hipStream_t s);
 template <typename T>
 void launch_coord_weight(const T* w, T* out, int64_t M, int64_t stride, int64_t nk, double hk, const T* yk, int sign,

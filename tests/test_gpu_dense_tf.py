@@ -154,3 +154,27 @@ def test_dense_mf_running_max_jumps(far_first, kern):
     scale = max(np.abs(u1).max(), np.abs(v1).max())
     assert np.abs(u2 - u1).max() / scale < 1e-5
     assert np.abs(v2 - v1).max() / scale < 1e-5
+
+
+@pytest.mark.parametrize("fill", ["random_bytes", "large_finite"])
+def test_dense_mf_warm_maxima_any_workspace(fill):
+    """Kernel 4 starts each product from the row maxima the previous product
+    of the same side left in the workspace.  Whatever that memory holds
+    (random bytes: NaN, inf, denormals; or finite values far above the true
+    maxima), the result is that of the oracle: a start too low is caught by
+    the overflow redo, one too high by the final-total check.  3-D mixture,
+    N = 2000, M = 2300, KL 1, eps 1e-1 -> 1e-3, 30 iterations."""
+    x, y, p, q, dx, dy = mixture(5, 2000, 2300, 3)
+    F = U.KL(1.0)
+    say("case dense mf warm maxima", fill)
+    prob = U.points_problem(T(x), T(y), T(p), T(q), T(dx), T(dy), F, F)
+    ws = prob.workspace()
+    if fill == "random_bytes":
+        ws.random_(0, 256)
+    else:
+        ws.view(torch.float32)[:] = 3.0e4
+    u, v, _ = U.solve(prob, 1e-3, eps0=1e-1, iters_per_stage=5, tol=0.0, max_iter=30, dense_kernel=U.DENSE_MF3)
+    ref = O.solve(O.PointsGeom(x, y), np.log(p), np.log(q), np.log(dx), np.log(dy), O.KL(1.0), O.KL(1.0), 1e-3,
+                  tol=0.0, max_iter=30, eps0=1e-1, iters_per_stage=5)
+    assert pot_rel_err(u.cpu(), ref["u"], 1e-3) < 1e-5
+    assert pot_rel_err(v.cpu(), ref["v"], 1e-3) < 1e-5
