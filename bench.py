@@ -184,12 +184,12 @@ PASS_NAMES = ["k_grid_tf<false, 4>", "k_grid_tf<true, 4>"]
 # on (sha256 of the pass's file and the headers it includes) and are reported
 # as null otherwise.
 TRAFFIC_SOURCES = ["uot_grid_tf.hip", "uot_epilogue.h", "uot_device.h", "uot_launch.h"]
-TRAFFIC_SOURCE_SHA256 = "4cd731ce5e2c22dee5c34b90edef8a574bc0f6cf76d9d9ccedead19d74c1ade9"
+TRAFFIC_SOURCE_SHA256 = "55325a65ab7f69201a6ea4b644beef692ad909cbd68b0fb23041b7dbefa3c151"
 TRAFFIC_BYTES = {
-    ('k_grid_tf<false, 4>', 1): (2273385, 259840),
-    ('k_grid_tf<false, 4>', 256): (67286754, 67108864),
-    ('k_grid_tf<true, 4>', 1): (3096766, 523671),
-    ('k_grid_tf<true, 4>', 256): (406300680, 134348800),
+    ('k_grid_tf<false, 4>', 1): (2273395, 259840),
+    ('k_grid_tf<false, 4>', 256): (67286989, 67108864),
+    ('k_grid_tf<true, 4>', 1): (3096780, 523671),
+    ('k_grid_tf<true, 4>', 256): (406575356, 134348800),
 }
 
 
