@@ -168,7 +168,8 @@ typedef struct uot_params {
                             passes of 3 until the residual reaches 1e-4, then
                             those of 2 down to tol (FP32 accuracy)         */
   int32_t dense_kernel;  /* point clouds: 0 default (4 for FP32 data with the
-                            squared Euclidean cost, else 1), 1 direct log-sum-exp
+                            squared Euclidean cost and N, M >= 2048, else 1),
+                            1 direct log-sum-exp
                             product, 2 tile-factored product (FP32, squared
                             Euclidean cost): both clouds are put in Morton
                             order on the device once per solve, tile pairs

@@ -233,8 +233,10 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
     P.N = g.N;
     P.M = g.M;
     // default: the BF16 x 3 matrix-core product where it applies (FP32, squared
-    // Euclidean cost), the direct product otherwise
-    if (dense_kernel == 0) dense_kernel = dtype == UOT_F32 && g.cost == UOT_COST_SQEUCLID ? 4 : 1;
+    // Euclidean cost) and both clouds have 2048 points or more (below that
+    // its per-block set-up outweighs the pairs), the direct product otherwise
+    if (dense_kernel == 0)
+      dense_kernel = dtype == UOT_F32 && g.cost == UOT_COST_SQEUCLID && std::min(g.N, g.M) >= 2048 ? 4 : 1;
     P.dense_tf = dense_kernel == 2;
     P.dense_mf = dense_kernel == 3 || dense_kernel == 4;
     P.mf_split = dense_kernel == 4;

@@ -824,10 +824,19 @@ __global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, 
   ResAcc<T> ra;
   ra.init();
   if (valid) {
-    Lse2<T> acc;
-    acc.init();
-    for (int s = 0; s < nsplit; ++s) acc.merge(pm[s * Nr + i], ps[s * Nr + i]);
-    epi_elem<T>(i, acc.result(), c, side, ep, ra);
+    // two passes over the splits with independent loads: the largest
+    // maximum, then the sum of the partial sums scaled to it
+    T mx = Num<T>::ninf();
+#pragma unroll 8
+    for (int s = 0; s < nsplit; ++s) mx = Num<T>::fmax(mx, pm[s * Nr + i]);
+    T lse = mx;
+    if (mx != Num<T>::ninf()) {
+      T sum = T(0);
+#pragma unroll 8
+      for (int s = 0; s < nsplit; ++s) sum += ps[s * Nr + i] * Num<T>::exp2(pm[s * Nr + i] - mx);
+      lse = mx + Num<T>::log2(sum);
+    }
+    epi_elem<T>(i, lse, c, side, ep, ra);
   }
   epi_finish<T>(ep, ra, blockIdx.x);
 }
