@@ -363,7 +363,7 @@ def wf_dense_roofline(U, torch, np, dev, ctx, n=20000, cut=0.1, eps=1e-3):
         out[name + "_ms"] = U.time_half_step(pb, eps, v, reps=20, ctx=ctx)[0]
     peak = exp_peak() / 2
     ms = out["sorted_ms"]
-    out.update({"bound": "alu", "kernel": "k_dense_lse<float, 2, 2, 1>", "kernel_avg_ms": ms,
+    out.update({"bound": "alu", "kernel": "k_dense_lse<float, 2, 1, 1>", "kernel_avg_ms": ms,
                 "achieved": inside / (ms * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "Tpairs/s",
                 "frac": inside / (ms * 1e-3) / peak, "work_per_launch": float(inside),
                 "work_unit": "pair within the cut (one exp + one log)", "pairs_within_cut_frac": inside / float(n) ** 2,

@@ -181,7 +181,8 @@ void dense_config(Plan& P, int side) {
   const int64_t Mc = side == 0 ? P.M : P.N;
   // rows per thread (the matrix-core kernel: mf_groups / 4, with mf_groups
   // row groups of 16 per wave)
-  const int R = P.dense_mf ? P.mf_groups / 4 : (P.dtype == UOT_F32) ? 2 : 1;
+  // (the WF cost: one row per thread, so a wave's box is that of 64 rows)
+  const int R = P.dense_mf ? P.mf_groups / 4 : (P.dtype == UOT_F32 && P.cost.kind != UOT_COST_WF) ? 2 : 1;
   const int64_t rt = (Nr + 256 * R - 1) / (256 * R);
   // blocks to aim for: 2048 (8 resident per compute unit), 1024 for the
   // matrix-core product (its column chunks after the first cost one pass,

@@ -310,8 +310,9 @@ __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in
 // COST 0: log2 K = -|x_i - y_j|^2 log2(e) / eps.
 // COST 1: the WF cost with cut locus, log2 K = (2/eps) log2 cos((pi/2) d / cut)
 //         for d < cut and -inf beyond (wf_log2k).  K then has exact zeros:
-//         each wave holds 64 R consecutive rows and bounds them by a box,
-//         every 256-column chunk is bounded by 8 boxes of 32 columns, and a
+//         each wave holds 64 R consecutive rows (R = 1 for this cost) and
+//         bounds them by a box, every 256-column chunk is bounded by 16 boxes
+//         of 16 columns, and a
 //         wave skips the column groups whose box lies at distance >= cut from
 //         its rows' box (every entry there is zero).  This pays when the
 //         points are stored in a spatially coherent order.
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
       }
     }
   } else {
-    __shared__ T gbx[8][6];   // boxes of the 8 groups of 32 columns of a chunk
+    __shared__ T gbx[16][6];  // boxes of the 16 groups of 16 columns of a chunk
     T rlo[3], rhi[3];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -424,22 +425,22 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
       }
       __syncthreads();
       tile[threadIdx.x] = rec;
-      // box of each group of 32 columns, over the columns that carry mass
+      // box of each group of 16 columns, over the columns that carry mass
       const bool live = rec.w != Num<T>::ninf();
       const T cx[3] = {rec.x, rec.y, rec.z};
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        const T lo = lanes_min<T>(live ? cx[d] : Num<T>::pinf(), 16);
-        const T hi = lanes_max<T>(live ? cx[d] : Num<T>::ninf(), 16);
-        if ((lane & 31) == 0) {
-          gbx[wv * 2 + (lane >> 5)][2 * d] = lo;
-          gbx[wv * 2 + (lane >> 5)][2 * d + 1] = hi;
+        const T lo = lanes_min<T>(live ? cx[d] : Num<T>::pinf(), 8);
+        const T hi = lanes_max<T>(live ? cx[d] : Num<T>::ninf(), 8);
+        if ((lane & 15) == 0) {
+          gbx[wv * 4 + (lane >> 4)][2 * d] = lo;
+          gbx[wv * 4 + (lane >> 4)][2 * d + 1] = hi;
         }
       }
       __syncthreads();
       const int64_t rem = ce - c0;
       const int cnt = rem < kBlock ? (int)rem : kBlock;
-      for (int gi = 0; gi < 8 && gi * 32 < cnt; ++gi) {
+      for (int gi = 0; gi < 16 && gi * 16 < cnt; ++gi) {
         T gap2 = T(0);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
@@ -448,8 +449,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
         }
         // every entry of the group is beyond the cut (an empty box gives +inf)
         if (!(gap2 < cut2)) continue;
-        const int je = (gi * 32 + 32 < cnt) ? gi * 32 + 32 : cnt;
-        for (int jj = gi * 32; jj < je; jj += kChunk) {
+        const int je = (gi * 16 + 16 < cnt) ? gi * 16 + 16 : cnt;
+        for (int jj = gi * 16; jj < je; jj += kChunk) {
           V4 q[kChunk];
 #pragma unroll
           for (int k = 0; k < kChunk; ++k) q[k] = tile[jj + k];
