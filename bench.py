@@ -110,6 +110,7 @@ def warm_batched(U, ctx, dev, np, torch):
         "latency_ms_p50": float(np.percentile(info["latency_ms"], 50)),
         "latency_ms_p99": float(np.percentile(info["latency_ms"], 99)),
         "tile_rows": info["tile_rows"], "blocks_per_cu": info["blocks_per_cu"],
+        "product": {1: "direct", 4: "mfma_bf16x3"}.get(int(info["product"]), str(info["product"])),
         "plain_ms_per_problem_sample16": plain_per * 1e3,
         "speedup_vs_plain": plain_per * len(probs) / bs}
     net = load_weights(os.path.join(ROOT, "paper_1607_05816_amd", "data", "warmstart_mlp64.npz"), dev)

@@ -405,6 +405,12 @@ typedef struct uot_batch_result {
   int32_t tile_rows;     /* autotuned rows per work item                    */
   int32_t blocks_per_cu; /* autotuned persistent blocks per compute unit    */
   double tune_ms;        /* time spent tuning (0 if the cached choice was used) */
+  int32_t product;       /* autotuned product: 1 direct log-sum-exp, 4 matrix
+                            core (FP32 data; both clouds of every problem in
+                            Morton order on the device, potentials returned
+                            in the caller's order).  uot_params.dense_kernel
+                            restricts the tuner: 0 both, 1 or 4 that one    */
+  int32_t reserved;
 } uot_batch_result;
 
 int uot_batch_workspace_size(const uot_batch_problem *pb, size_t *bytes);

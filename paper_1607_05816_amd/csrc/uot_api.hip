@@ -753,6 +753,9 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
     uo = at<T>(ws, P.o_us);
     vo = at<T>(ws, P.o_vs);
   }
+  // the matrix-core product starts this solve with no row maxima (all bits
+  // set: not finite), so a solve does not depend on what the workspace held
+  if (P.dense_mf) HIP_TRY(hipMemsetAsync(B.pw, 0xFF, sizeof(float) * 2 * P.np_pw, s));
   // mixed precision: FP16 passes down to kMixedSwitchTol, then FP32 passes
   const bool mixed = P.gk == 4 && has_tf16(P) && pr->tol < kMixedSwitchTol;
   Plan P2 = P;
@@ -1287,8 +1290,11 @@ struct BatchPlan {
   size_t esz = 0;
   int64_t B = 0, totN = 0, totM = 0;
   int64_t max_items = 0;       // items per side at R = 1 (upper bound for any R)
+  int64_t nmaxN = 0, nmaxM = 0;   // largest problem per side
+  bool mf = false;                // FP32: the matrix-core product is among the tuner's choices
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_stop, o_yskip, o_status, o_iters, o_res, o_clock,
-      o_itx, o_ity, o_pstart, o_parts, o_curs, o_offN, o_offM, total;
+      o_itx, o_ity, o_pstart, o_parts, o_curs, o_offN, o_offM, o_xs, o_ys, o_permx, o_permy, o_code, o_box, o_us,
+      o_vs, o_pw, total;
 };
 
 int make_batch_plan(BatchPlan& P, const uot_batch_problem* pb) {
@@ -1308,6 +1314,8 @@ int make_batch_plan(BatchPlan& P, const uot_batch_problem* pb) {
     if (n > (1 << 30) || m > (1 << 30)) return fail(UOT_E_UNSUPPORTED, "problem too large for a batch");
     items += (n + 255) / 256;
     itemsy += (m + 255) / 256;
+    P.nmaxN = std::max(P.nmaxN, n);
+    P.nmaxM = std::max(P.nmaxM, m);
   }
   P.totN = pb->offN[pb->B];
   P.totM = pb->offM[pb->B];
@@ -1339,6 +1347,19 @@ int make_batch_plan(BatchPlan& P, const uot_batch_problem* pb) {
   P.o_curs = take(4 * 2);
   P.o_offN = take(8 * (P.B + 1));
   P.o_offM = take(8 * (P.B + 1));
+  // FP32: Morton-ordered copies per problem for the matrix-core product
+  // (coordinates, permutations, codes, boxes, potentials) and its row maxima
+  P.mf = P.dtype == UOT_F32;
+  const bool mf = P.mf;
+  P.o_xs = take(mf ? 4 * P.dim * P.totN : 0);
+  P.o_ys = take(mf ? 4 * P.dim * P.totM : 0);
+  P.o_permx = take(mf ? 4 * P.totN : 0);
+  P.o_permy = take(mf ? 4 * P.totM : 0);
+  P.o_code = take(mf ? 4 * std::max(P.totN, P.totM) : 0);
+  P.o_box = take(mf ? 4 * 6 * P.B : 0);
+  P.o_us = take(mf ? 4 * P.totN : 0);
+  P.o_vs = take(mf ? 4 * P.totM : 0);
+  P.o_pw = take(mf ? 4 * (P.totN + P.totM) : 0);
   P.total = o;
   return UOT_OK;
 }
@@ -1415,6 +1436,37 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
   HIP_TRY(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, ctx->device));
   const uot_geom dummy{};
   (void)dummy;
+  // FP32: both sides in Morton order per problem; the iteration runs on the
+  // ordered copies and the potentials are scattered back at the end
+  const T* xo = static_cast<const T*>(pb->x);
+  const T* yo = static_cast<const T*>(pb->y);
+  T* uo = u;
+  T* vo = v;
+  const int32_t* px = nullptr;
+  const int32_t* py = nullptr;
+  float* pw = nullptr;
+  if constexpr (std::is_same<T, float>::value) {
+    if (P.mf) {
+      float* xs = at<float>(ws, P.o_xs);
+      float* ys = at<float>(ws, P.o_ys);
+      int32_t* pxw = at<int32_t>(ws, P.o_permx);
+      int32_t* pyw = at<int32_t>(ws, P.o_permy);
+      uint32_t* code = at<uint32_t>(ws, P.o_code);
+      float* box = at<float>(ws, P.o_box);
+      launch_spatial_order_batch<float>(xo, P.totN, offN_d, P.B, P.nmaxN, P.dim, box, code, pxw, s);
+      launch_spatial_order_batch<float>(yo, P.totM, offM_d, P.B, P.nmaxM, P.dim, box, code, pyw, s);
+      launch_gather<float>(xo, pxw, P.totN, P.dim, xs, s);
+      launch_gather<float>(yo, pyw, P.totM, P.dim, ys, s);
+      HIP_TRY(hipGetLastError());
+      xo = xs;
+      yo = ys;
+      px = pxw;
+      py = pyw;
+      uo = at<float>(ws, P.o_us);
+      vo = at<float>(ws, P.o_vs);
+      pw = at<float>(ws, P.o_pw);
+    }
+  }
 
   std::vector<BItem> hx, hy;
   std::vector<int32_t> pst;
@@ -1431,34 +1483,54 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
     launch_ctrl_init(ctrl, init, s);
     launch_batch_init(bc_dev, (int)P.B, ctrl, s);
     launch_set_int(curs, 2, 0, s);
-    launch_log<T>(static_cast<const T*>(pb->p), logp, P.totN, 1, s);
-    launch_log<T>(static_cast<const T*>(pb->q), logq, P.totM, 1, s);
-    launch_log<T>(static_cast<const T*>(pb->dx), logdx, P.totN, 0, s);
-    launch_log<T>(static_cast<const T*>(pb->dy), logdy, P.totM, 0, s);
-    launch_init_pot<T>(nullptr, logdx, u, nullptr, P.totN, P.totN, ctrl, 0, s);
-    launch_init_pot<T>(static_cast<const T*>(pr->v0), logdy, v, wv, P.totM, P.totM, ctrl, 0, s);
+    log_into<T>(pb->p, logp, P.totN, 1, px, uo, s);
+    log_into<T>(pb->q, logq, P.totM, 1, py, vo, s);
+    log_into<T>(pb->dx, logdx, P.totN, 0, px, uo, s);
+    log_into<T>(pb->dy, logdy, P.totM, 0, py, vo, s);
+    launch_init_pot<T>(nullptr, logdx, uo, nullptr, P.totN, P.totN, ctrl, 0, s);
+    const T* v0 = static_cast<const T*>(pr->v0);
+    if (v0 && py) {
+      launch_gather<T>(v0, py, P.totM, 1, vo, s);
+      v0 = vo;
+    }
+    launch_init_pot<T>(v0, logdy, vo, wv, P.totM, P.totM, ctrl, 0, s);
+    // the matrix-core product starts with no row maxima (all bits set: not
+    // finite), so the run does not depend on what the workspace held
+    if (pw) (void)hipMemsetAsync(pw, 0xFF, sizeof(float) * (P.totN + P.totM), s);
   };
   int R = 1, bpc = 8;
+  bool mfk = false;   // the matrix-core product (rows per item 256 R, R = 1 or 2)
   auto iteration = [&](int par) {
-    EpiArgs<T> epx = prox_epi<T>(u, wu, logp, logdx, nullptr, parts, P.totN, pb->F1);
-    EpiArgs<T> epy = prox_epi<T>(v, wv, logq, logdy, nullptr, nullptr, P.totM, pb->F2);
-    timed(0, [&] {
-      launch_batch_lse<T>(P.dim, R, ncu * bpc, itx, (int)hx.size(), curs + 0, offN_d, offM_d,
-                          static_cast<const T*>(pb->x), P.totN, static_cast<const T*>(pb->y), P.totM, wv, bc_dev,
-                          ctrl, 0 | par << 1, epx, s);
-    });
+    EpiArgs<T> epx = prox_epi<T>(uo, wu, logp, logdx, nullptr, parts, P.totN, pb->F1);
+    EpiArgs<T> epy = prox_epi<T>(vo, wv, logq, logdy, nullptr, nullptr, P.totM, pb->F2);
+    auto product = [&](int half, const BItem* items, int n_items, int* cur, const int64_t* offR,
+                       const int64_t* offC, const T* xr, int64_t totR, const T* yc, int64_t totC, const T* w,
+                       float* pwr, const EpiArgs<T>& ep) {
+      if constexpr (std::is_same<T, float>::value) {
+        if (mfk) {
+          launch_batch_mf(P.dim, 4 * R, ncu * bpc, items, n_items, cur, offR, offC, xr, totR, yc, totC, w, pwr,
+                          bc_dev, ctrl, half | par << 1, ep, s);
+          return;
+        }
+      }
+      launch_batch_lse<T>(P.dim, R, ncu * bpc, items, n_items, cur, offR, offC, xr, totR, yc, totC, w, bc_dev, ctrl,
+                          half | par << 1, ep, s);
+    };
+    timed(0, [&] { product(0, itx, (int)hx.size(), curs + 0, offN_d, offM_d, xo, P.totN, yo, P.totM, wv, pw, epx); });
     timed(2, [&] { launch_batch_control(ctrl, bc_dev, (int)P.B, parts, pstart_d, curs, par, s); });
     timed(1, [&] {
-      launch_batch_lse<T>(P.dim, R, ncu * bpc, ity, (int)hy.size(), curs + 1, offM_d, offN_d,
-                          static_cast<const T*>(pb->y), P.totM, static_cast<const T*>(pb->x), P.totN, wu, bc_dev,
-                          ctrl, 1 | par << 1, epy, s);
+      product(1, ity, (int)hy.size(), curs + 1, offM_d, offN_d, yo, P.totM, xo, P.totN, wu,
+              pw ? pw + P.totN : nullptr, epy);
     });
   };
 
   // autotuner: rows per item (256 R) and persistent blocks per CU, measured on
   // two iterations from the initial state; cached per batch signature
+  if (pr->dense_kernel != 0 && pr->dense_kernel != 1 && pr->dense_kernel != 4)
+    return fail(UOT_E_INVALID, "batches take dense_kernel 0 (tuned), 1 (direct) or 4 (matrix core)");
+  if (pr->dense_kernel == 4 && !P.mf) return fail(UOT_E_UNSUPPORTED, "the matrix-core product takes FP32 data");
   std::string key = std::to_string(P.dtype) + ":" + std::to_string(P.dim) + ":" + std::to_string(P.B) + ":" +
-                    std::to_string(P.totN) + ":" + std::to_string(P.totM);
+                    std::to_string(P.totN) + ":" + std::to_string(P.totM) + ":" + std::to_string(pr->dense_kernel);
   {
     uint64_t hsh = 1469598103934665603ull;
     for (int64_t b = 0; b <= P.B; ++b) hsh = (hsh ^ (uint64_t)(pb->offN[b] * 31 + pb->offM[b])) * 1099511628211ull;
@@ -1467,7 +1539,8 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
   double tune_ms = 0.0;
   auto found = ctx->batch_tuned.find(key);
   if (found != ctx->batch_tuned.end()) {
-    R = found->second.first;
+    R = found->second.first & 15;
+    mfk = (found->second.first & 16) != 0;
     bpc = found->second.second;
   } else {
     auto t0 = std::chrono::steady_clock::now();
@@ -1476,12 +1549,18 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
     HIP_TRY(hipEventCreate(&e1));
     float best = 1e30f;
     int bestR = 1, bestB = 8;
-    const int Rs[3] = {1, 2, 4};
+    bool bestMf = false;
+    // products: direct with 256 R rows per item (R = 1, 2, 4), and on FP32
+    // data the matrix-core one (R = 1, 2: 4 or 8 row groups per wave)
+    const int Rs[5] = {1, 2, 4, 1, 2};
     const int Bs[3] = {4, 8, 16};
-    for (int ri = 0; ri < 3; ++ri) {
+    const int r_lo = pr->dense_kernel == 4 ? 3 : 0;
+    const int r_hi = pr->dense_kernel == 1 || !P.mf ? 3 : 5;
+    for (int ri = r_lo; ri < r_hi; ++ri) {
       if ((rc = upload_items(Rs[ri]))) return rc;
       for (int bi = 0; bi < 3; ++bi) {
         R = Rs[ri];
+        mfk = ri >= 3;
         bpc = Bs[bi];
         init_state();
         iteration(0);   // first iteration: caches and code warm
@@ -1496,6 +1575,7 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
           best = t;
           bestR = R;
           bestB = bpc;
+          bestMf = mfk;
         }
       }
     }
@@ -1503,7 +1583,8 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
     (void)hipEventDestroy(e1);
     R = bestR;
     bpc = bestB;
-    ctx->batch_tuned[key] = {R, bpc};
+    mfk = bestMf;
+    ctx->batch_tuned[key] = {R | (mfk ? 16 : 0), bpc};
     tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   if ((rc = upload_items(R))) return rc;
@@ -1551,6 +1632,11 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (rc) return rc;
+  if (px) {
+    launch_scatter<T>(uo, px, P.totN, u, s);
+    launch_scatter<T>(vo, py, P.totM, v, s);
+    HIP_TRY(hipGetLastError());
+  }
   if (timing) {
     for (int k = 0; k < 4; ++k) {
       pr->kernel_ms[k] = timer.ms[k];
@@ -1583,6 +1669,7 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
   res->tile_rows = 256 * R;
   res->blocks_per_cu = bpc;
   res->tune_ms = tune_ms;
+  res->product = mfk ? 4 : 1;
   if ((rc = finish(ctx))) return rc;
   if (nonfinite) return fail(UOT_E_NONFINITE, "non-finite residual in a batch problem");
   return nconv == P.B ? UOT_OK : UOT_NOT_CONVERGED;

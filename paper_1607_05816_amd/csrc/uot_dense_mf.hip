@@ -57,6 +57,8 @@ namespace uot {
 
 typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mf_bf16x8 __attribute__((ext_vector_type(8)));
+// LDS columns per chunk: 256 staged plus two padding tiles of 16
+constexpr int kMfCols = kBlock + 32;
 
 __device__ __forceinline__ float wave_min(float v) {
 #pragma unroll
@@ -203,27 +205,24 @@ __device__ __forceinline__ void mf_sum_pass(const typename MfOps<SPLIT>::Op* bas
   }
 }
 
+// The product of one block's rows (xr: first row, coordinate stride xs, nrow
+// of its 64 G rows valid) with ncol columns (yc: first column, stride ys; w
+// their log2 weights): for row 16 g + l of this wave, m[g] (the shift; -inf
+// if no term is finite), tot[g] (the total over the row's 4 lanes, relative
+// to 2^m) and rc[g] = R_i.  pw holds the rows' starting maxima on entry and
+// is not written.  st, sbox: the block's LDS.
 template <int DIM, int G, bool SPLIT>
-__global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ xr, int64_t Nr,
-                                                      const float* __restrict__ yc, const float* __restrict__ w,
-                                                      int64_t Mc, int64_t cols_per_split,
-                                                      float* __restrict__ pm, float* __restrict__ ps,
-                                                      float* __restrict__ pw, int side, const Ctrl* __restrict__ c) {
+__device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs, int nrow,
+                                        const float* __restrict__ yc, int64_t ys, const float* __restrict__ w,
+                                        int64_t ncol, float cc, const float* __restrict__ pw,
+                                        typename MfOps<SPLIT>::Op* st, float (*sbox)[6], float (&m)[G],
+                                        float (&tot)[G], float (&rc)[G]) {
   static_assert(G % 4 == 0, "a block's rows are loaded 256 at a time");
-  using O = MfOps<SPLIT>;
-  using Op = typename O::Op;
-  if (skip_side(c, side)) return;
-  // column operands of the chunk and two padding tiles (read by the
-  // discarded final products of the passes): FP32 [k][column], BF16 x 3
-  // [column][q]
-  constexpr int kCols = kBlock + 32;
-  __shared__ Op st[4 * kCols];
-  __shared__ float sbox[4][6];
-  const float cc = float(kLog2e / eps_of(c, side));
+  using Op = typename MfOps<SPLIT>::Op;
+  constexpr int kCols = kMfCols;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, q = lane >> 4;
-  const int64_t bbase = (int64_t)blockIdx.x * (64 * G);
-  const int64_t wbase = bbase + wv * (16 * G);
+  const int wbase = wv * (16 * G);
   // the block centre: middle of the box of its valid rows
   float xb[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -231,9 +230,9 @@ __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ x
     float lo = __builtin_inff(), hi = -__builtin_inff();
 #pragma unroll
     for (int t = 0; t < G / 4; ++t) {
-      const int64_t row = bbase + t * kBlock + threadIdx.x;
-      if (row < Nr) {
-        const float v = xr[d * Nr + row];
+      const int row = t * kBlock + threadIdx.x;
+      if (row < nrow) {
+        const float v = xr[d * xs + row];
         lo = fminf(lo, v);
         hi = fmaxf(hi, v);
       }
@@ -257,10 +256,10 @@ __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ x
   Op E[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    const int64_t row = wbase + g * 16 + li;
+    const int row = wbase + g * 16 + li;
     float e[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) e[d] = (d < DIM && row < Nr) ? xr[d * Nr + row] - xb[d] : 0.f;
+    for (int d = 0; d < 3; ++d) e[d] = (d < DIM && row < nrow) ? xr[d * xs + row] - xb[d] : 0.f;
     if constexpr (SPLIT) {
       __bf16 p[3][3];
 #pragma unroll
@@ -273,30 +272,27 @@ __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ x
   }
   // running (m, s) of row 16 g + l: m is the same in the 4 lanes of the row,
   // s is this lane's share (its columns)
-  float m[G], s[G], wm[G];
+  float s[G], wm[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    const int64_t row = wbase + g * 16 + li;
-    const float v = row < Nr ? pw[blockIdx.y * Nr + row] : -__builtin_inff();
+    const int row = wbase + g * 16 + li;
+    const float v = row < nrow ? pw[row] : -__builtin_inff();
     wm[g] = __builtin_isfinite(v) ? v : -__builtin_inff();
   }
   const Op* base = SPLIT ? &st[li * 4 + q] : &st[q * kCols + li];
-  const int64_t cb = (int64_t)blockIdx.y * cols_per_split;
-  const int64_t ce = (cb + cols_per_split < Mc) ? cb + cols_per_split : Mc;
-  float tot[G];
   for (int attempt = 0;; ++attempt) {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       m[g] = attempt == 0 ? wm[g] : -__builtin_inff();
       s[g] = 0.f;
     }
-    for (int64_t c0 = cb; c0 < ce; c0 += kBlock) {
+    for (int64_t c0 = 0; c0 < ncol; c0 += kBlock) {
       const int64_t col = c0 + threadIdx.x;
       float y[3] = {0.f, 0.f, 0.f};
       float wj = -__builtin_inff();
-      if (col < ce) {
+      if (col < ncol) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) y[d] = yc[d * Mc + col];
+        for (int d = 0; d < DIM; ++d) y[d] = yc[d * ys + col];
         wj = w[col];
       }
       float bd[3], d2 = 0.f;
@@ -323,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ x
         st[3 * kCols + threadIdx.x] = gj;
       }
       __syncthreads();
-      const int64_t rem = ce - c0;
+      const int64_t rem = ncol - c0;
       const int cnt = rem < kBlock ? (int)rem : kBlock;
       // an even tile count (the staged padding is -inf), uniform
       const int ntl = __builtin_amdgcn_readfirstlane(((cnt + 31) >> 5) << 1);
@@ -393,23 +389,102 @@ __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ x
     }
     if (attempt > 0 || !__syncthreads_or(low)) break;
   }
+  // row constants R_i = -c |e_i|^2
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int row = wbase + g * 16 + li;
+    float e2 = 0.f;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const float e = row < nrow ? xr[d * xs + row] - xb[d] : 0.f;
+      e2 = __builtin_fmaf(e, e, e2);
+    }
+    rc[g] = -cc * e2;
+  }
+}
+
+template <int DIM, int G, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ xr, int64_t Nr,
+                                                      const float* __restrict__ yc, const float* __restrict__ w,
+                                                      int64_t Mc, int64_t cols_per_split,
+                                                      float* __restrict__ pm, float* __restrict__ ps,
+                                                      float* __restrict__ pw, int side, const Ctrl* __restrict__ c) {
+  using Op = typename MfOps<SPLIT>::Op;
+  if (skip_side(c, side)) return;
+  // column operands of the chunk and two padding tiles (read by the
+  // discarded final products of the passes): FP32 [k][column], BF16 x 3
+  // [column][q]
+  __shared__ Op st[4 * kMfCols];
+  __shared__ float sbox[4][6];
+  const float cc = float(kLog2e / eps_of(c, side));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, q = lane >> 4;
+  const int64_t bbase = (int64_t)blockIdx.x * (64 * G);
+  const int64_t cb = (int64_t)blockIdx.y * cols_per_split;
+  const int64_t ce = (cb + cols_per_split < Mc) ? cb + cols_per_split : Mc;
+  const int nrow = (int)(Nr - bbase < 64 * G ? Nr - bbase : 64 * G);
+  float* pws = pw + blockIdx.y * Nr + bbase;
+  float m[G], tot[G], rc[G];
+  mf_tile<DIM, G, SPLIT>(xr + bbase, Nr, nrow, yc + cb, Mc, w + cb, ce - cb, cc, pws, st, sbox, m, tot, rc);
   // lanes q = 0 write row 16 g + l: (m + R_i, total), and m for the next
   // product of this side
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    const float sr = tot[g];
-    const int64_t row = wbase + g * 16 + li;
-    if (q == 0 && row < Nr) {
-      float e2 = 0.f;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const float e = xr[d * Nr + row] - xb[d];
-        e2 = __builtin_fmaf(e, e, e2);
-      }
-      pm[blockIdx.y * Nr + row] = m[g] == -__builtin_inff() ? m[g] : __builtin_fmaf(-cc, e2, m[g]);
-      ps[blockIdx.y * Nr + row] = sr;
-      pw[blockIdx.y * Nr + row] = m[g];
+    const int row = wv * (16 * G) + g * 16 + li;
+    if (q == 0 && row < nrow) {
+      pm[blockIdx.y * Nr + bbase + row] = m[g] == -__builtin_inff() ? m[g] : m[g] + rc[g];
+      ps[blockIdx.y * Nr + bbase + row] = tot[g];
+      pws[row] = m[g];
     }
+  }
+}
+
+// Ragged batch on the matrix cores: persistent blocks pull (problem, 64 G
+// rows) items from an atomic cursor as k_batch_lse does, take the product of
+// the item's rows with all columns of the problem (the clouds in Morton
+// order per problem) and apply the proxdiv epilogue; pw: starting maxima per
+// row, left for the next iteration.
+template <int DIM, int G, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_batch_mf(const BItem* __restrict__ items, int n_items,
+                                                      int* __restrict__ cursor, const int64_t* __restrict__ offR,
+                                                      const int64_t* __restrict__ offC, const float* __restrict__ xr,
+                                                      int64_t totR, const float* __restrict__ yc, int64_t totC,
+                                                      const float* __restrict__ w, float* __restrict__ pw,
+                                                      const BCtrl* __restrict__ bc, const Ctrl* __restrict__ c,
+                                                      int side, EpiArgs<float> ep) {
+  using Op = typename MfOps<SPLIT>::Op;
+  __shared__ Op st[4 * kMfCols];
+  __shared__ float sbox[4][6];
+  __shared__ int item_sh;
+  const float cc = float(kLog2e / eps_of(c, side));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, q = lane >> 4;
+  const int32_t* __restrict__ skip = half_of(side) == 0 ? bc->stop : bc->yskip;
+  while (true) {
+    __syncthreads();
+    if (threadIdx.x == 0) item_sh = atomicAdd(cursor, 1);
+    __syncthreads();
+    const int it = item_sh;
+    if (it >= n_items) break;
+    const BItem I = items[it];
+    if (skip[I.prob]) continue;
+    const int64_t rb = offR[I.prob] + I.row0;
+    const int64_t cb = offC[I.prob], ce = offC[I.prob + 1];
+    float m[G], tot[G], rc[G];
+    mf_tile<DIM, G, SPLIT>(xr + rb, totR, I.nrows, yc + cb, totC, w + cb, ce - cb, cc, pw + rb, st, sbox, m, tot,
+                           rc);
+    ResAcc<float> ra;
+    ra.init();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int row = wv * (16 * G) + g * 16 + li;
+      if (q == 0 && row < I.nrows) {
+        const float lse = m[g] == -__builtin_inff() ? m[g] : m[g] + rc[g] + __builtin_log2f(tot[g]);
+        epi_elem<float>(rb + row, lse, c, side, ep, ra);
+        pw[rb + row] = m[g];
+      }
+    }
+    epi_finish<float>(ep, ra, I.part);
   }
 }
 
@@ -438,6 +513,29 @@ void launch_dense_mf(int dim, int groups, bool split, const float* xr, int64_t N
   }
 #undef UOT_MF_DIM
 #undef UOT_MF
+}
+
+}  // namespace uot
+
+namespace uot {
+
+void launch_batch_mf(int dim, int groups, int blocks, const BItem* items, int n_items, int* cursor,
+                     const int64_t* offR, const int64_t* offC, const float* xr, int64_t totR, const float* yc,
+                     int64_t totC, const float* w, float* pw, const BCtrl* bc, const Ctrl* c, int side,
+                     const EpiArgs<float>& ep, hipStream_t s) {
+#define UOT_BMF(D, G)                                                                                         \
+  hipLaunchKernelGGL((k_batch_mf<D, G, true>), dim3(blocks), dim3(kBlock), 0, s, items, n_items, cursor, offR, \
+                     offC, xr, totR, yc, totC, w, pw, bc, c, side, ep)
+  if (groups == 8) {
+    if (dim == 1) UOT_BMF(1, 8);
+    else if (dim == 2) UOT_BMF(2, 8);
+    else UOT_BMF(3, 8);
+  } else {
+    if (dim == 1) UOT_BMF(1, 4);
+    else if (dim == 2) UOT_BMF(2, 4);
+    else UOT_BMF(3, 4);
+  }
+#undef UOT_BMF
 }
 
 }  // namespace uot

@@ -726,23 +726,29 @@ __global__ __launch_bounds__(kBlock) void k_point_box(const T* __restrict__ x, i
 }
 
 // Morton code: coordinates quantised over the box to 2^bits levels
-// (bits = 30 / dim), their bits interleaved
+// (bits = 30 / dim), their bits interleaved; xp: the point's first
+// coordinate, stride: between coordinates
 template <typename T>
-__global__ void k_morton(const T* __restrict__ x, int64_t n, int dim, const T* __restrict__ bx,
-                         uint32_t* __restrict__ code) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ uint32_t morton_code(const T* __restrict__ xp, int64_t stride, int dim,
+                                                const T* __restrict__ bx) {
   const int bits = 30 / dim;
   const uint32_t top = (1u << bits) - 1u;
   uint32_t out = 0;
   for (int d = 0; d < dim; ++d) {
     const double lo = double(bx[d]), ext = double(bx[3 + d]) - lo;
-    double t = ext > 0 ? (double(x[d * n + i]) - lo) / ext : 0.0;
+    double t = ext > 0 ? (double(xp[d * stride]) - lo) / ext : 0.0;
     uint32_t q = (uint32_t)(t * double(top) + 0.5);
     q = q > top ? top : q;
     for (int b = 0; b < bits; ++b) out |= ((q >> b) & 1u) << (b * dim + d);
   }
-  code[i] = out;
+  return out;
+}
+template <typename T>
+__global__ void k_morton(const T* __restrict__ x, int64_t n, int dim, const T* __restrict__ bx,
+                         uint32_t* __restrict__ code) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  code[i] = morton_code<T>(x + i, n, dim, bx);
 }
 
 // perm[rank_i] = i with rank_i = #{j : code_j < code_i, or code_j = code_i and j < i}
@@ -783,6 +789,81 @@ __global__ void k_scatter(const T* __restrict__ in, const int32_t* __restrict__ 
   if (k >= n) return;
   out[perm[k]] = in[k];
 }
+
+// The same per problem of a batch: problem b holds the points off[b] ..
+// off[b + 1] - 1 of x (coordinate stride tot); its box goes to bx[6 b ..],
+// and perm maps within the problem's range (perm[off[b] + rank] = off[b] + i).
+// grid: blockIdx.x = problem (box: one block each; codes and ranks: blocks
+// (b, t) step over the problem's tiles of 256 points by gridDim.y)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_point_box_batch(const T* __restrict__ x, int64_t tot,
+                                                             const int64_t* __restrict__ off, int dim,
+                                                             T* __restrict__ bx) {
+  __shared__ T smin[kBlock], smax[kBlock];
+  const int64_t o = off[blockIdx.x], n = off[blockIdx.x + 1] - o;
+  for (int d = 0; d < dim; ++d) {
+    T lo = Num<T>::pinf(), hi = Num<T>::ninf();
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+      const T v = x[d * tot + o + i];
+      lo = Num<T>::fmin(lo, v);
+      hi = Num<T>::fmax(hi, v);
+    }
+    smin[threadIdx.x] = lo;
+    smax[threadIdx.x] = hi;
+    __syncthreads();
+    for (int h = kBlock / 2; h >= 1; h >>= 1) {
+      if ((int)threadIdx.x < h) {
+        smin[threadIdx.x] = Num<T>::fmin(smin[threadIdx.x], smin[threadIdx.x + h]);
+        smax[threadIdx.x] = Num<T>::fmax(smax[threadIdx.x], smax[threadIdx.x + h]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      bx[6 * blockIdx.x + d] = smin[0];
+      bx[6 * blockIdx.x + 3 + d] = smax[0];
+    }
+    __syncthreads();
+  }
+}
+template <typename T>
+__global__ void k_morton_batch(const T* __restrict__ x, int64_t tot, const int64_t* __restrict__ off, int dim,
+                               const T* __restrict__ bx, uint32_t* __restrict__ code) {
+  const int64_t o = off[blockIdx.x], n = off[blockIdx.x + 1] - o;
+  for (int64_t i = (int64_t)blockIdx.y * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.y * kBlock)
+    code[o + i] = morton_code<T>(x + o + i, tot, dim, bx + 6 * blockIdx.x);
+}
+__global__ __launch_bounds__(kBlock) void k_rank_batch(const uint32_t* __restrict__ code,
+                                                        const int64_t* __restrict__ off, int32_t* __restrict__ perm) {
+  __shared__ uint32_t sc[kBlock];
+  const int64_t o = off[blockIdx.x], n = off[blockIdx.x + 1] - o;
+  for (int64_t t0 = (int64_t)blockIdx.y * kBlock; t0 < n; t0 += (int64_t)gridDim.y * kBlock) {
+    const int64_t i = t0 + threadIdx.x;
+    const uint32_t ci = i < n ? code[o + i] : 0u;
+    int64_t rank = 0;
+    for (int64_t j0 = 0; j0 < n; j0 += kBlock) {
+      __syncthreads();
+      sc[threadIdx.x] = (j0 + threadIdx.x < n) ? code[o + j0 + threadIdx.x] : 0xffffffffu;
+      __syncthreads();
+      const int cnt = (n - j0 < kBlock) ? (int)(n - j0) : kBlock;
+      for (int k = 0; k < cnt; ++k) {
+        const uint32_t cj = sc[k];
+        rank += (cj < ci || (cj == ci && j0 + k < i)) ? 1 : 0;
+      }
+    }
+    if (i < n) perm[o + rank] = (int32_t)(o + i);
+  }
+}
+
+template <typename T>
+void launch_spatial_order_batch(const T* x, int64_t tot, const int64_t* off, int64_t B, int64_t nmax, int dim,
+                                T* box, uint32_t* code, int32_t* perm, hipStream_t s) {
+  const unsigned ty = (unsigned)std::min<int64_t>(ceil_div(nmax, kBlock), 1024);
+  hipLaunchKernelGGL(k_point_box_batch<T>, dim3((unsigned)B), dim3(kBlock), 0, s, x, tot, off, dim, box);
+  hipLaunchKernelGGL(k_morton_batch<T>, dim3((unsigned)B, ty), dim3(kBlock), 0, s, x, tot, off, dim, box, code);
+  hipLaunchKernelGGL(k_rank_batch, dim3((unsigned)B, ty), dim3(kBlock), 0, s, code, off, perm);
+}
+template void launch_spatial_order_batch<float>(const float*, int64_t, const int64_t*, int64_t, int64_t, int, float*,
+                                                uint32_t*, int32_t*, hipStream_t);
 
 template <typename T>
 void launch_spatial_order(const T* x, int64_t n, int dim, T* box, uint32_t* code, int32_t* perm, hipStream_t s) {

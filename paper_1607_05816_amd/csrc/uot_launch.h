@@ -89,6 +89,19 @@ template <typename T> void launch_scatter(const T* in, const int32_t* perm, int6
 // tile-factored dense product (FP32, R = 2), partials as launch_dense_lse
 void launch_dense_tf(int dim, const float* xr, int64_t Nr, const float* yc, const float* w, int64_t Mc, int nsplit,
                      int64_t cps, float* pm, float* ps, int side, const Ctrl* c, hipStream_t s);
+// Morton order of each problem of a batch (problem b: points off[b] ..
+// off[b + 1] - 1, coordinate stride tot; nmax: the largest problem; box: 6
+// per problem); perm maps within each problem's range
+template <typename T>
+void launch_spatial_order_batch(const T* x, int64_t tot, const int64_t* off, int64_t B, int64_t nmax, int dim,
+                                T* box, uint32_t* code, int32_t* perm, hipStream_t s);
+// the ragged batch on the matrix cores (BF16 x 3 operands, FP32 data, squared
+// Euclidean): groups = 4 or 8 row groups of 16 per wave (items of 64 groups
+// rows); pw: starting row maxima (totR), kept between iterations
+void launch_batch_mf(int dim, int groups, int blocks, const BItem* items, int n_items, int* cursor,
+                     const int64_t* offR, const int64_t* offC, const float* xr, int64_t totR, const float* yc,
+                     int64_t totC, const float* w, float* pw, const BCtrl* bc, const Ctrl* c, int side,
+                     const EpiArgs<float>& ep, hipStream_t s);
 // dense product on the matrix cores (FP32 data, squared Euclidean): groups =
 // 4 or 8 row groups of 16 per wave; split: BF16 x 3 operands on
 // v_mfma_f32_16x16x32_bf16, else FP32 operands on v_mfma_f32_16x16x4f32;

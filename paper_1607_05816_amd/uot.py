@@ -73,7 +73,7 @@ class UotBatchResult(ctypes.Structure):
     _fields_ = [("iters", ctypes.POINTER(c_i64)), ("residual", ctypes.POINTER(c_dbl)),
                 ("latency_ms", ctypes.POINTER(c_dbl)), ("status", ctypes.POINTER(c_i32)), ("iters_max", c_i64),
                 ("n_converged", c_i64), ("elapsed_ms", c_dbl), ("tile_rows", c_i32), ("blocks_per_cu", c_i32),
-                ("tune_ms", c_dbl)]
+                ("tune_ms", c_dbl), ("product", c_i32), ("reserved", c_i32)]
 
 
 class UotFlowProblem(ctypes.Structure):
@@ -610,7 +610,8 @@ def solve_batched(bp: BatchProblem, eps, ctx: Optional[Context] = None, v0=None,
     _check(code, "uot_solve_batched")
     info = dict(iters=it, residual=rs, latency_ms=lat, status=st, iters_max=res.iters_max,
                 n_converged=res.n_converged, elapsed_ms=res.elapsed_ms, tile_rows=res.tile_rows,
-                blocks_per_cu=res.blocks_per_cu, tune_ms=res.tune_ms, converged=(code == UOT_OK))
+                blocks_per_cu=res.blocks_per_cu, tune_ms=res.tune_ms, product=res.product,
+                converged=(code == UOT_OK))
     if time_kernels:
         info["kernel_ms"] = [kms[k] for k in range(4)]
         info["kernel_launches"] = [kcnt[k] for k in range(4)]

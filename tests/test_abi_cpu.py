@@ -50,7 +50,7 @@ int main(void) {
   S(uot_batch_problem) S(uot_batch_result) S(uot_flow_problem)
   O(uot_geom, cost) O(uot_geom, cut) O(uot_flow_problem, geom) O(uot_flow_problem, p0) O(uot_flow_problem, tau)
   O(uot_flow_problem, alpha)
-  O(uot_batch_problem, F2) O(uot_batch_problem, dy) O(uot_batch_result, tune_ms) O(uot_batch_result, tile_rows)
+  O(uot_batch_problem, F2) O(uot_batch_problem, dy) O(uot_batch_result, tune_ms) O(uot_batch_result, tile_rows) O(uot_batch_result, product)
   O(uot_geom, n) O(uot_geom, h) O(uot_problem, geom) O(uot_problem, F1) O(uot_problem, F2)
   O(uot_params, v0) O(uot_params, res_hist) O(uot_params, check_every) O(uot_params, kernel_ms) O(uot_params, kernel_launches) O(uot_params, grid_kernel)
   O(uot_bary_problem, alpha) O(uot_bary_problem, F2) O(uot_result, elapsed_ms)

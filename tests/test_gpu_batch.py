@@ -51,16 +51,21 @@ def split(t, off):
     return [a[off[b]:off[b + 1]] for b in range(len(off) - 1)]
 
 
-@pytest.mark.parametrize("dtype,tolr", [(torch.float32, 1e-5), (torch.float64, 1e-11)])
-def test_batch_fixed_iterations_every_problem(dtype, tolr):
+@pytest.mark.parametrize("dtype,tolr,kern", [(torch.float32, 1e-5, 1), (torch.float32, 1e-5, 4),
+                                             (torch.float64, 1e-11, 0)])
+def test_batch_fixed_iterations_every_problem(dtype, tolr, kern):
+    """dense_kernel 1 / 4 pins the batch tuner to the direct or the
+    matrix-core product (problems in Morton order on the device)."""
     npd = np.float32 if dtype == torch.float32 else np.float64
     Ns, Ms, probs = make_batch(3, 29, 20, 700, 2, npd, extra=[(1, 1), (1, 300), (513, 2)])
     F = U.KL(1.0)
     bp = to_gpu(Ns, Ms, probs, F, F, dtype)
     eps = 0.05
-    say("case batch fixed", dtype, "B", bp.B)
-    u, v, info = U.solve_batched(bp, eps, tol=0.0, max_iter=30)
+    say("case batch fixed", dtype, "B", bp.B, "kernel", kern)
+    u, v, info = U.solve_batched(bp, eps, tol=0.0, max_iter=30, dense_kernel=kern)
     assert (info["iters"] == 30).all()
+    if kern:
+        assert info["product"] == kern
     us, vs = split(u, bp.offN), split(v, bp.offM)
     for b, (x, y, p, q, dx, dy) in enumerate(probs):
         ref = O.solve(O.PointsGeom(x, y), np.log(p), np.log(q), np.log(dx), np.log(dy), O.KL(1.0), O.KL(1.0), eps,
@@ -69,14 +74,15 @@ def test_batch_fixed_iterations_every_problem(dtype, tolr):
         assert pot_rel_err(vs[b], ref["v"], eps) < tolr, (b, Ns[b], Ms[b])
 
 
-def test_batch_converged_each_problem_stops_on_its_own():
+@pytest.mark.parametrize("kern", [0, 4])
+def test_batch_converged_each_problem_stops_on_its_own(kern):
     npd = np.float32
     Ns, Ms, probs = make_batch(5, 24, 40, 900, 2, npd)
     F = U.KL(1.0)
     bp = to_gpu(Ns, Ms, probs, F, F, torch.float32)
     eps = 0.02
-    say("case batch converged")
-    u, v, info = U.solve_batched(bp, eps, tol=1e-6, max_iter=4000, check_every=32)
+    say("case batch converged", kern)
+    u, v, info = U.solve_batched(bp, eps, tol=1e-6, max_iter=4000, check_every=32, dense_kernel=kern)
     assert info["converged"] and info["n_converged"] == bp.B
     assert info["tile_rows"] in (256, 512, 1024) and info["blocks_per_cu"] in (4, 8, 16)
     us, vs = split(u, bp.offN), split(v, bp.offM)
@@ -102,7 +108,8 @@ def test_batch_converged_each_problem_stops_on_its_own():
         assert pot_rel_err(vs[b], ref["v"], eps) < 5e-5
     # second call with the same signature reuses the tuned choice; graph and
     # direct launches give identical potentials
-    u2, v2, info2 = U.solve_batched(bp, eps, tol=1e-6, max_iter=4000, check_every=32, use_graph=False)
+    u2, v2, info2 = U.solve_batched(bp, eps, tol=1e-6, max_iter=4000, check_every=32, use_graph=False,
+                                    dense_kernel=kern)
     assert info2["tune_ms"] == 0.0
     assert torch.equal(u, u2) and torch.equal(v, v2)
     assert np.array_equal(info2["iters"], its)
