@@ -854,13 +854,55 @@ __global__ __launch_bounds__(kBlock) void k_rank_batch(const uint32_t* __restric
   }
 }
 
+// the same permutation for problems of at most kSortLds points: a bitonic
+// sort of (code, index) pairs in LDS, one block per problem (the index
+// breaks ties, so the order is the stable one of k_rank_batch)
+constexpr int kSortLds = 4096;
+__global__ __launch_bounds__(kBlock) void k_sort_batch(const uint32_t* __restrict__ code,
+                                                        const int64_t* __restrict__ off, int32_t* __restrict__ perm) {
+  __shared__ uint32_t sk[kSortLds];
+  __shared__ int32_t si[kSortLds];
+  const int64_t o = off[blockIdx.x];
+  const int n = (int)(off[blockIdx.x + 1] - o);
+  int P = 1;
+  while (P < n) P <<= 1;
+  for (int i = threadIdx.x; i < P; i += kBlock) {
+    sk[i] = i < n ? code[o + i] : 0xffffffffu;
+    si[i] = i;   // padding sorts last: largest code, then largest index
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < P / 2; t += kBlock) {
+        // pair (a, b = a + j) of the j-step: a has bit j clear
+        const int a = ((t / j) * 2 * j) + (t % j), b = a + j;
+        const bool up = (a & k) == 0;
+        const uint32_t ka = sk[a], kb = sk[b];
+        const int32_t ia = si[a], ib = si[b];
+        const bool gt = ka > kb || (ka == kb && ia > ib);
+        if (gt == up) {
+          sk[a] = kb;
+          sk[b] = ka;
+          si[a] = ib;
+          si[b] = ia;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += kBlock) perm[o + i] = (int32_t)(o + si[i]);
+}
+
 template <typename T>
 void launch_spatial_order_batch(const T* x, int64_t tot, const int64_t* off, int64_t B, int64_t nmax, int dim,
                                 T* box, uint32_t* code, int32_t* perm, hipStream_t s) {
   const unsigned ty = (unsigned)std::min<int64_t>(ceil_div(nmax, kBlock), 1024);
   hipLaunchKernelGGL(k_point_box_batch<T>, dim3((unsigned)B), dim3(kBlock), 0, s, x, tot, off, dim, box);
   hipLaunchKernelGGL(k_morton_batch<T>, dim3((unsigned)B, ty), dim3(kBlock), 0, s, x, tot, off, dim, box, code);
-  hipLaunchKernelGGL(k_rank_batch, dim3((unsigned)B, ty), dim3(kBlock), 0, s, code, off, perm);
+  if (nmax <= kSortLds)
+    hipLaunchKernelGGL(k_sort_batch, dim3((unsigned)B), dim3(kBlock), 0, s, code, off, perm);
+  else
+    hipLaunchKernelGGL(k_rank_batch, dim3((unsigned)B, ty), dim3(kBlock), 0, s, code, off, perm);
 }
 template void launch_spatial_order_batch<float>(const float*, int64_t, const int64_t*, int64_t, int64_t, int, float*,
                                                 uint32_t*, int32_t*, hipStream_t);

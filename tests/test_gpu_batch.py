@@ -113,3 +113,22 @@ def test_batch_converged_each_problem_stops_on_its_own(kern):
     assert info2["tune_ms"] == 0.0
     assert torch.equal(u, u2) and torch.equal(v, v2)
     assert np.array_equal(info2["iters"], its)
+
+
+def test_batch_matrix_core_large_problem_order():
+    """A batch holding a problem above 4096 points (Morton order by counting
+    ranks instead of the in-LDS sort) next to small ones: the matrix-core
+    product (dense_kernel 4) against the direct one (1), whose parity with
+    the oracle the tests above pin."""
+    npd = np.float32
+    Ns, Ms, probs = make_batch(9, 6, 30, 600, 2, npd, extra=[(5000, 4500)])
+    F = U.KL(1.0)
+    bp = to_gpu(Ns, Ms, probs, F, F, torch.float32)
+    eps = 0.05
+    say("case batch large problem order")
+    u1, v1, _ = U.solve_batched(bp, eps, tol=0.0, max_iter=20, dense_kernel=1)
+    u4, v4, info = U.solve_batched(bp, eps, tol=0.0, max_iter=20, dense_kernel=4)
+    assert info["product"] == 4
+    for a, b, off in ((u4, u1, bp.offN), (v4, v1, bp.offM)):
+        for x, y in zip(split(a, off), split(b, off)):
+            assert pot_rel_err(x, y, eps) < 1e-5
