@@ -308,32 +308,39 @@ def dense_roofline(U, torch, np, dev, ctx, n=20000, eps=1e-3):
 
 def dense_solve(U, torch, np, dev, ctx, n=20000):
     """The dense configuration end to end: N = M = 20000 3-D mixture clouds,
-    KL 1, eps 1e-1 -> 1e-3 (10 stages of 100 iterations, then to residual
-    1e-6), FP32 data, with the default (matrix-core) product and with the
-    direct one; potentials of the two compared."""
+    KL 1, eps 1e-1 -> 1e-3 (10 stages of 100 iterations, then on), FP32 data.
+    The default (matrix-core) product runs to residual 1e-6 (time to
+    residual); both it and the direct product run a fixed 3000 iterations
+    (iterations/s), and their potentials are compared."""
     from paper_1607_05816_amd import synth
     pr = synth.clouds3d(0, N=n, M=n)
     T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
     F = U.KL(1.0)
     pb = U.points_problem(T(pr.x), T(pr.y), T(pr.p), T(pr.q), T(pr.dx), T(pr.dy), F, F)
     pb.workspace()
-    out = {"workload": "clouds3d N=M=%d KL1 eps 1e-1->1e-3 10x100 tol 1e-6 FP32" % n}
+    out = {"workload": "clouds3d N=M=%d KL1 eps 1e-1->1e-3 10x100 FP32" % n}
     pots = {}
     for k, name in ((0, "default_mfma_bf16x3"), (1, "direct")):
-        U.solve(pb, 1e-3, eps0=1e-1, tol=1e-6, max_iter=3000, check_every=50, ctx=ctx, dense_kernel=k)
+        U.solve(pb, 1e-3, eps0=1e-1, tol=0.0, max_iter=300, check_every=50, ctx=ctx, dense_kernel=k)   # warm
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        u, v, info = U.solve(pb, 1e-3, eps0=1e-1, tol=1e-6, max_iter=3000, check_every=50, ctx=ctx,
+        u, v, info = U.solve(pb, 1e-3, eps0=1e-1, tol=0.0, max_iter=3000, check_every=50, ctx=ctx,
                              dense_kernel=k)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         pots[name] = (u.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64))
         out[name] = {"seconds": dt, "iters": int(info["iters"]), "iters_per_s": info["iters"] / dt,
-                     "converged": bool(info["converged"]), "residual": float(info["residual"])}
+                     "residual": float(info["residual"])}
     (u1, v1), (u2, v2) = pots["default_mfma_bf16x3"], pots["direct"]
     sc = max(np.abs(u2).max(), np.abs(v2).max())
     out["max_potential_diff_rel"] = float(max(np.abs(u1 - u2).max(), np.abs(v1 - v2).max()) / sc)
     out["speedup_vs_direct"] = out["direct"]["seconds"] / out["default_mfma_bf16x3"]["seconds"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, info = U.solve(pb, 1e-3, eps0=1e-1, tol=1e-6, max_iter=40000, check_every=50, ctx=ctx)
+    torch.cuda.synchronize()
+    out["time_to_residual_1e-6"] = {"seconds": time.perf_counter() - t0, "iters": int(info["iters"]),
+                                    "converged": bool(info["converged"]), "residual": float(info["residual"])}
     return out
 
 
