@@ -192,8 +192,11 @@ void dense_config(Plan& P, int side) {
     const char* e = getenv("UOT_DENSE_BLOCKS");
     return e ? atoi(e) : 0;
   }();
-  int64_t target = P.dense_mf ? 1024 : 2048;   // the matrix-core product: fewer splits to merge
-  if ((P.dense_tf || P.dense_mf) && fac_blocks > 0) target = fac_blocks;
+  // the matrix-core product: fewer splits to merge; the WF cost: more, as
+  // the pairs within the cut concentrate in few (row block, split) pairs and
+  // smaller splits spread them over more compute units
+  int64_t target = P.dense_mf ? 1024 : (P.cost.kind == UOT_COST_WF ? 8192 : 2048);
+  if ((P.dense_tf || P.dense_mf || P.cost.kind == UOT_COST_WF) && fac_blocks > 0) target = fac_blocks;
   int64_t sp = (target + rt - 1) / rt;
   const int64_t maxsp = (Mc + 31) / 32;
   if (sp > maxsp) sp = maxsp;
