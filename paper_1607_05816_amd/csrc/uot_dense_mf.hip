@@ -36,9 +36,10 @@
 // every lane keeps one running sum per row group, and a row is spread over
 // the 4 lanes l + 16 q.
 // Shift: the sum pass feeds minus a running maximum m of each row in as the
-// accumulator input.  m starts from the row's maximum over the same column
-// split in the previous product of this side (pw; the potentials move little
-// between iterations), or is not finite.  A chunk where some row has no
+// accumulator input.  m starts from the row's maximum over the same columns
+// (the block's column split; all columns of a batch problem) in the previous
+// product of this side (pw; the potentials move little between iterations),
+// or is not finite (the first product of a solve).  A chunk where some row has no
 // finite m takes a maximum pass first (lane maxima, then over the 4 lanes of
 // the row), so every exp2 argument is <= 0.  Otherwise the sum pass runs
 // alone against m: a term above m stays finite up to 2^127, and the chunk is
