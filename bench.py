@@ -466,6 +466,22 @@ def pmc_workload(U, torch, np, dev, ctx):
     print("pmc workload done", flush=True)
 
 
+def pmc_workload_dense(U, torch, np, dev, ctx, n=20000):
+    """The launches the dense products' instruction counters are read on:
+    three back-to-back launches of each product kernel on one X half-step of
+    the 20000^2 3-D mixture clouds (eps 1e-3, v = 0), as in roofline_dense."""
+    from paper_1607_05816_amd import synth
+    pr = synth.clouds3d(0, N=n, M=n)
+    T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
+    F = U.KL(1.0)
+    pb = U.points_problem(T(pr.x), T(pr.y), T(pr.p), T(pr.q), T(pr.dx), T(pr.dy), F, F)
+    v = torch.zeros(n, dtype=torch.float32, device=dev)
+    for k, _, _ in DENSE_KERNELS:
+        U.time_half_step(pb, 1e-3, v, reps=3, ctx=ctx, grid_kernel=k)
+    torch.cuda.synchronize()
+    print("pmc dense workload done", flush=True)
+
+
 BF16_MFMA_PEAK = 2.5e15     # MI355X dense BF16 MFMA, FLOP/s
 
 
@@ -543,8 +559,9 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-gemm", action="store_true")
     ap.add_argument("--no-extensions", action="store_true")
-    ap.add_argument("--pmc-workload", action="store_true",
-                    help="only run the launches the HBM-traffic counters are read on")
+    ap.add_argument("--pmc-workload", nargs="?", const="grid", choices=("grid", "dense"),
+                    help="only run the launches counters are read on: the grid passes (HBM traffic) or "
+                         "the dense products at 20000^2 (instruction counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -560,8 +577,11 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
-    if args.pmc_workload:
+    if args.pmc_workload == "grid":
         pmc_workload(U, torch, np, dev, U.default_context())
+        return
+    if args.pmc_workload == "dense":
+        pmc_workload_dense(U, torch, np, dev, U.default_context())
         return
     pr = synth.blobs2d(args.seed, n=N_GRID)
     t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)

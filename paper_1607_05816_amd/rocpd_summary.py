@@ -2,11 +2,16 @@
 
     python -m paper_1607_05816_amd.rocpd_summary <run_results.db> [--top N]
     python -m paper_1607_05816_amd.rocpd_summary --pmc <fetch.csv> <write.csv> [--copy-bytes B]
+    python -m paper_1607_05816_amd.rocpd_summary --counters <a.csv> [<b.csv> ...] [--match S]
 
 rocprofv3's own --stats table averages every launch of a kernel symbol; the
 same symbol runs here at several launch shapes (one field vs a batch of
 fields), so this groups the dispatches by (kernel, grid size) and prints a
 markdown table of calls and durations in ns.
+
+--counters: counter_collection.csv files of `rocprofv3 --pmc` runs (any
+counters); per kernel (and launch size) the mean of each counter over the
+dispatches, one column per counter; --match keeps kernels whose name holds S.
 
 --pmc: the counter_collection.csv files of two `rocprofv3 --pmc FETCH_SIZE`
 and `--pmc WRITE_SIZE` runs of the same program.  Both counters read KiB per
@@ -60,14 +65,38 @@ def summarize_pmc(fetch_csv, write_csv, copy_bytes, top=12):
     return "\n".join(out)
 
 
+def summarize_counters(paths, match=None):
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    names = []
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            if match and match not in name:
+                continue
+            c = r["Counter_Name"]
+            if c not in names:
+                names.append(c)
+            agg[(name, int(r["Grid_Size"]))][c].append(float(r["Counter_Value"]))
+    out = ["| kernel | grid (work-items) | " + " | ".join(names) + " |",
+           "|:--|--:|" + "--:|" * len(names)]
+    for k in sorted(agg):
+        vals = [("%.4g" % (sum(agg[k][c]) / len(agg[k][c]))) if agg[k][c] else "" for c in names]
+        out.append("| `%s` | %d | %s |" % (k[0], k[1], " | ".join(vals)))
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("db", nargs="?")
     ap.add_argument("--top", type=int, default=12)
     ap.add_argument("--pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--copy-bytes", type=int, default=256 << 20)
+    ap.add_argument("--counters", nargs="+")
+    ap.add_argument("--match")
     a = ap.parse_args()
-    if a.pmc:
+    if a.counters:
+        print(summarize_counters(a.counters, a.match))
+    elif a.pmc:
         print(summarize_pmc(a.pmc[0], a.pmc[1], a.copy_bytes, a.top))
     else:
         print(summarize(a.db, a.top))
