@@ -27,7 +27,8 @@
 //     v_mfma_f32_16x16x32_bf16 (products exact, FP32 accumulation; dropped
 //     part products are below 2^-24 of |e_d B_d|).  These run on the matrix
 //     cores, next to the exp2 of other groups.
-// The column operands of a chunk of 256 columns are built once in LDS.
+// The column operands of a chunk of columns (512 in the dense kernel, 256 in
+// the batch one) are built once in LDS.
 // Layout of the 16 x 16 MFMAs (64 lanes, q = lane / 16, l = lane % 16): a
 // lane supplies A[l][k in slots of q] and B[k in slots of q][l] (the same K
 // slots for both), and gets D[4 q + r][l], r = 0..3.  Here A holds the
@@ -58,8 +59,8 @@ namespace uot {
 
 typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mf_bf16x8 __attribute__((ext_vector_type(8)));
-// LDS columns per chunk: 256 staged plus two padding tiles of 16
-constexpr int kMfCols = kBlock + 32;
+// LDS columns for chunks of C columns: C staged plus two padding tiles of 16
+constexpr int mf_cols(int C) { return C + 32; }
 
 __device__ __forceinline__ float wave_min(float v) {
 #pragma unroll
@@ -212,7 +213,7 @@ __device__ __forceinline__ void mf_sum_pass(const typename MfOps<SPLIT>::Op* bas
 // if no term is finite), tot[g] (the total over the row's 4 lanes, relative
 // to 2^m) and rc[g] = R_i.  pw holds the rows' starting maxima on entry and
 // is not written.  st, sbox: the block's LDS.
-template <int DIM, int G, bool SPLIT>
+template <int DIM, int G, bool SPLIT, int CHUNK>
 __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs, int nrow,
                                         const float* __restrict__ yc, int64_t ys, const float* __restrict__ w,
                                         int64_t ncol, float cc, const float* __restrict__ pw,
@@ -220,7 +221,8 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
                                         float (&tot)[G], float (&rc)[G]) {
   static_assert(G % 4 == 0, "a block's rows are loaded 256 at a time");
   using Op = typename MfOps<SPLIT>::Op;
-  constexpr int kCols = kMfCols;
+  static_assert(CHUNK % kBlock == 0 && CHUNK / 16 <= 32, "chunks of 256 or 512 columns");
+  constexpr int kCols = mf_cols(CHUNK);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, q = lane >> 4;
   const int wbase = wv * (16 * G);
@@ -287,41 +289,51 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
       m[g] = attempt == 0 ? wm[g] : -__builtin_inff();
       s[g] = 0.f;
     }
-    for (int64_t c0 = 0; c0 < ncol; c0 += kBlock) {
-      const int64_t col = c0 + threadIdx.x;
-      float y[3] = {0.f, 0.f, 0.f};
-      float wj = -__builtin_inff();
-      if (col < ncol) {
+    for (int64_t c0 = 0; c0 < ncol; c0 += CHUNK) {
+      // this thread's columns h kBlock + t of the chunk
+      constexpr int H = CHUNK / kBlock;
+      float y[H][3], wj[H];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) y[d] = yc[d * ys + col];
-        wj = w[col];
-      }
-      float bd[3], d2 = 0.f;
+      for (int h = 0; h < H; ++h) {
+        const int64_t col = c0 + h * kBlock + threadIdx.x;
+        y[h][0] = y[h][1] = y[h][2] = 0.f;
+        wj[h] = -__builtin_inff();
+        if (col < ncol) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const float a = d < DIM ? y[d] - xb[d] : 0.f;
-        bd[d] = 2.f * cc * a;
-        d2 = __builtin_fmaf(a, a, d2);
+          for (int d = 0; d < DIM; ++d) y[h][d] = yc[d * ys + col];
+          wj[h] = w[col];
+        }
       }
-      const float gj = wj == -__builtin_inff() ? wj : __builtin_fmaf(-cc, d2, wj);
       __syncthreads();                     // the previous chunk's reads are done
-      if constexpr (SPLIT) {
-        __bf16 b[3][3], gp[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) split3(bd[d], b[d]);
-        split3(gj, gp);
-        st[threadIdx.x * 4 + 0] = col_chunk<0>(b, gp);
-        st[threadIdx.x * 4 + 1] = col_chunk<1>(b, gp);
-        st[threadIdx.x * 4 + 2] = col_chunk<2>(b, gp);
-        st[threadIdx.x * 4 + 3] = col_chunk<3>(b, gp);
-      } else {
+      for (int h = 0; h < H; ++h) {
+        const int lc = h * kBlock + threadIdx.x;
+        float bd[3], d2 = 0.f;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) st[d * kCols + threadIdx.x] = bd[d];
-        st[3 * kCols + threadIdx.x] = gj;
+        for (int d = 0; d < 3; ++d) {
+          const float a = d < DIM ? y[h][d] - xb[d] : 0.f;
+          bd[d] = 2.f * cc * a;
+          d2 = __builtin_fmaf(a, a, d2);
+        }
+        const float gj = wj[h] == -__builtin_inff() ? wj[h] : __builtin_fmaf(-cc, d2, wj[h]);
+        if constexpr (SPLIT) {
+          __bf16 b[3][3], gp[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) split3(bd[d], b[d]);
+          split3(gj, gp);
+          st[lc * 4 + 0] = col_chunk<0>(b, gp);
+          st[lc * 4 + 1] = col_chunk<1>(b, gp);
+          st[lc * 4 + 2] = col_chunk<2>(b, gp);
+          st[lc * 4 + 3] = col_chunk<3>(b, gp);
+        } else {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) st[d * kCols + lc] = bd[d];
+          st[3 * kCols + lc] = gj;
+        }
       }
       __syncthreads();
       const int64_t rem = ncol - c0;
-      const int cnt = rem < kBlock ? (int)rem : kBlock;
+      const int cnt = rem < CHUNK ? (int)rem : CHUNK;
       // an even tile count (the staged padding is -inf), uniform
       const int ntl = __builtin_amdgcn_readfirstlane(((cnt + 31) >> 5) << 1);
       // a chunk with a row that has no finite running maximum yet (the first
@@ -412,10 +424,10 @@ __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ x
                                                       float* __restrict__ pw, int side, const Ctrl* __restrict__ c) {
   using Op = typename MfOps<SPLIT>::Op;
   if (skip_side(c, side)) return;
-  // column operands of the chunk and two padding tiles (read by the
-  // discarded final products of the passes): FP32 [k][column], BF16 x 3
-  // [column][q]
-  __shared__ Op st[4 * kMfCols];
+  // column operands of a chunk of 512 columns and two padding tiles (read
+  // by the discarded final products of the passes): FP32 [k][column], BF16
+  // x 3 [column][q]
+  __shared__ Op st[4 * mf_cols(512)];
   __shared__ float sbox[4][6];
   const float cc = float(kLog2e / eps_of(c, side));
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -426,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ x
   const int nrow = (int)(Nr - bbase < 64 * G ? Nr - bbase : 64 * G);
   float* pws = pw + blockIdx.y * Nr + bbase;
   float m[G], tot[G], rc[G];
-  mf_tile<DIM, G, SPLIT>(xr + bbase, Nr, nrow, yc + cb, Mc, w + cb, ce - cb, cc, pws, st, sbox, m, tot, rc);
+  mf_tile<DIM, G, SPLIT, 512>(xr + bbase, Nr, nrow, yc + cb, Mc, w + cb, ce - cb, cc, pws, st, sbox, m, tot, rc);
   // lanes q = 0 write row 16 g + l: (m + R_i, total), and m for the next
   // product of this side
 #pragma unroll
@@ -454,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_mf(const BItem* __restrict__ i
                                                       const BCtrl* __restrict__ bc, const Ctrl* __restrict__ c,
                                                       int side, EpiArgs<float> ep) {
   using Op = typename MfOps<SPLIT>::Op;
-  __shared__ Op st[4 * kMfCols];
+  __shared__ Op st[4 * mf_cols(256)];   // chunks of 256 columns: batch problems are small
   __shared__ float sbox[4][6];
   __shared__ int item_sh;
   const float cc = float(kLog2e / eps_of(c, side));
@@ -472,8 +484,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_mf(const BItem* __restrict__ i
     const int64_t rb = offR[I.prob] + I.row0;
     const int64_t cb = offC[I.prob], ce = offC[I.prob + 1];
     float m[G], tot[G], rc[G];
-    mf_tile<DIM, G, SPLIT>(xr + rb, totR, I.nrows, yc + cb, totC, w + cb, ce - cb, cc, pw + rb, st, sbox, m, tot,
-                           rc);
+    mf_tile<DIM, G, SPLIT, 256>(xr + rb, totR, I.nrows, yc + cb, totC, w + cb, ce - cb, cc, pw + rb, st, sbox, m,
+                                tot, rc);
     ResAcc<float> ra;
     ra.init();
 #pragma unroll
