@@ -184,7 +184,13 @@ typedef struct uot_params {
                             3 with FP32 operands (16x16x4 FP32 MFMA), 4 with
                             each operand split into three bf16 parts (24
                             bits; one 16x16x32 BF16 MFMA, FP32 accumulation),
-                            which runs beside the exp2 on the vector units  */
+                            which runs beside the exp2 on the vector units.
+                            Kernels 2-4 pass the exponent through FP32 terms
+                            of size c r^2 (r: half-diagonal of a row block's
+                            box), so their potentials err by a few 2^-24 r^2
+                            in cost units, the direct product's by a few
+                            2^-24 |u|: choose 1 where the potentials are far
+                            below r^2 (local transport at tiny eps)        */
 } uot_params;
 
 typedef struct uot_result {

@@ -132,3 +132,87 @@ def test_batch_matrix_core_large_problem_order():
     for a, b, off in ((u4, u1, bp.offN), (v4, v1, bp.offM)):
         for x, y in zip(split(a, off), split(b, off)):
             assert pot_rel_err(x, y, eps) < 1e-5
+
+
+
+def line_problem(rng, N, M, f32=np.float32):
+    """1-D rows in [0.45, 0.55], columns uniform on [0, 1]."""
+    x = rounded((0.45 + 0.1 * rng.random(N))[:, None], f32)
+    y = rounded(rng.random((M, 1)), f32)
+    return (x, y, rounded(rng.random(N) + 0.5, f32), rounded(rng.random(M) + 0.5, f32),
+            rounded(np.full(N, 1.0 / N), f32), rounded(np.full(M, 1.0 / M), f32))
+
+
+def joint_errs(bp, pots1, pots2):
+    """Per problem: largest potential difference, and the larger of the two
+    reference potentials' magnitudes."""
+    (u1, v1), (u2, v2) = pots1, pots2
+    U1, V1, U2, V2 = (split(t, off) for t, off in ((u1, bp.offN), (v1, bp.offM), (u2, bp.offN), (v2, bp.offM)))
+    return [(max(np.abs(U2[b] - U1[b]).max(), np.abs(V2[b] - V1[b]).max()),
+             max(np.abs(U1[b]).max(), np.abs(V1[b]).max())) for b in range(bp.B)]
+
+
+def test_batch_matrix_core_running_max_jumps():
+    """The batched matrix-core product carries a running row maximum from
+    chunk to chunk of 256 columns, starting cold in a solve's first product:
+    rows in [0.45, 0.55], columns uniform on [0, 1], eps = 1e-5, so left of
+    the rows every chunk's exponents exceed the running maximum by hundreds
+    of powers of two and right of them fall as far below it (3000 x 20000,
+    next to 200 x 1500 and 50 x 700).  Against the direct product after 2
+    iterations, relative to the larger of the two potentials' magnitudes
+    (after the first iteration far pairs' terms are differences of numbers
+    of order 1/eps, so u is small against the rounding of those terms)."""
+    rng = np.random.default_rng(21)
+    Ns, Ms = [200, 3000, 50], [1500, 20000, 700]
+    probs = [line_problem(rng, n, m) for n, m in zip(Ns, Ms)]
+    F = U.KL(1.0)
+    bp = to_gpu(Ns, Ms, probs, F, F, torch.float32)
+    say("case batch running max jumps")
+    u1, v1, _ = U.solve_batched(bp, 1e-5, tol=0.0, max_iter=2, dense_kernel=1)
+    u4, v4, info = U.solve_batched(bp, 1e-5, tol=0.0, max_iter=2, dense_kernel=4)
+    assert info["product"] == 4
+    for b, (err, scale) in enumerate(joint_errs(bp, (u1, v1), (u4, v4))):
+        assert err / scale < 1e-5, (b, err / scale)
+
+
+def test_batch_matrix_core_error_model():
+    """The matrix-core product's exponent passes through FP32 intermediates
+    of size c r^2 (r: the half-diagonal of the rows' bounding box around the
+    block centre, c = 1 / (eps ln 2)), so its potentials carry an absolute
+    error of a few 2^-24 r^2 whatever eps and the potentials' size, where the
+    direct product's error scales with the potentials.  Uniform 1-D problems
+    (one item spans a whole problem: r = 1/2) at eps = 1e-5, where the
+    potentials (~1e-4) are far below r^2: the difference from the direct
+    product stays within 8 * 2^-24 * r^2 after 2 iterations."""
+    npd = np.float32
+    Ns, Ms, probs = make_batch(4, 6, 40, 300, 1, npd)
+    F = U.KL(1.0)
+    bp = to_gpu(Ns, Ms, probs, F, F, torch.float32)
+    say("case batch matrix-core error model")
+    u1, v1, _ = U.solve_batched(bp, 1e-5, tol=0.0, max_iter=2, dense_kernel=1)
+    u4, v4, _ = U.solve_batched(bp, 1e-5, tol=0.0, max_iter=2, dense_kernel=4)
+    for b, (err, scale) in enumerate(joint_errs(bp, (u1, v1), (u4, v4))):
+        x = probs[b][0]
+        r2 = float(((x.max(0) - x.min(0)) / 2).astype(np.float64) @ ((x.max(0) - x.min(0)) / 2))
+        assert err <= 8 * 2.0 ** -24 * r2, (b, err, r2)
+
+
+def test_batch_matrix_core_converged_bench_eps():
+    """The batch benchmark's setting (2-D uniform points, KL 1, eps 5e-3,
+    tol 1e-6) with the matrix-core product: each problem converged, compared
+    with the oracle run for the iterations it took (FP32 bar 1e-5)."""
+    npd = np.float32
+    Ns, Ms, probs = make_batch(6, 8, 64, 400, 2, npd)
+    F = U.KL(1.0)
+    bp = to_gpu(Ns, Ms, probs, F, F, torch.float32)
+    eps = 5e-3
+    say("case batch converged bench eps")
+    u, v, info = U.solve_batched(bp, eps, tol=1e-6, max_iter=4000, check_every=32, dense_kernel=4)
+    assert info["converged"] and info["product"] == 4
+    us, vs = split(u, bp.offN), split(v, bp.offM)
+    its = info["iters"]
+    for b, (x, y, p, q, dx, dy) in enumerate(probs):
+        same = O.solve(O.PointsGeom(x, y), np.log(p), np.log(q), np.log(dx), np.log(dy), O.KL(1.0), O.KL(1.0),
+                       eps, tol=0.0, max_iter=int(its[b]))
+        assert pot_rel_err(us[b], same["u"], eps) < 1e-5, (b, its[b])
+        assert pot_rel_err(vs[b], same["v"], eps) < 1e-5, (b, its[b])

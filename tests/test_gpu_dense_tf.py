@@ -123,37 +123,59 @@ def test_dense_factored_small_and_vanishing(N, M, kern):
     assert pot_rel_err(v.cpu(), ref["v"], 1e-2) < 1e-5
 
 
-@pytest.mark.parametrize("kern", [pytest.param(U.DENSE_MF, id="mfma"), pytest.param(U.DENSE_MF3, id="mfma_bf16x3")])
-@pytest.mark.parametrize("far_first", [True, False])
-def test_dense_mf_running_max_jumps(far_first, kern):
-    """Kernels 3 and 4 carry a running row maximum from chunk to chunk of 256
-    columns.  N = 3000, M = 100000 on a line: each column split holds 320
-    columns, the first 256 (or the last 64) of them at distance >= 0.4 from
-    every row, so at eps = 1e-3 the next chunk's exponents jump more than 2^127
-    above the running maximum (the chunk is redone with a maximum pass) or fall
-    as far below it.  Compared with the direct product, which the oracle
-    parity tests pin, after 2 iterations, relative to the larger of the two
-    potentials' norms (u alone is small here)."""
-    N, M = 3000, 100000
-    rng = np.random.default_rng(11 if far_first else 12)
-    x = rounded(0.1 * rng.random((N, 1)), np.float32)
-    j = np.arange(M)
-    far = (j % 320) < 256 if far_first else (j % 320) >= 256
-    y = np.where(far, 0.5 + 0.1 * rng.random(M), 0.1 * rng.random(M))[:, None]
-    y = rounded(y, np.float32)
+def line_jumps(pattern, N, M, seed):
+    """1-D clouds whose exponents, in the Morton (here: coordinate) order the
+    matrix-core products sort the columns into, jump from chunk to chunk.
+    'distance': rows in [0.45, 0.55], columns uniform on [0, 1], eps = 1e-5;
+    one column step moves a far column's exponent by about a nat, so left of
+    the rows each chunk's exponents exceed the running maximum by hundreds of
+    powers of two (the lazy sum overflows and the chunk is redone with a
+    maximum pass), right of them they fall as far below it.  'density':
+    eps = 0.1, columns in alternating bands of width 0.02 (about 2000 sorted
+    columns) with densities 1e-36 and O(1), so entering a dense band lifts
+    the exponents by about 2^120: a finite lazy total above 2^100, which
+    also triggers the redo.  Returns the problem arrays and eps."""
+    rng = np.random.default_rng(seed)
+    y = rng.random(M)
+    if pattern == "distance":
+        x, eps, q = 0.45 + 0.1 * rng.random(N), 1e-5, rng.random(M) + 0.5
+    else:
+        x, eps = rng.random(N), 1e-1
+        q = np.where(np.floor(y * 50) % 2 == 0, 1e-36, rng.random(M) + 0.5)
+    x, y = rounded(x[:, None], np.float32), rounded(y[:, None], np.float32)
     p = rounded(rng.random(N) + 0.5, np.float32)
-    q = rounded(rng.random(M) + 0.5, np.float32)
+    q = rounded(q, np.float32)
     dx = rounded(np.full(N, 1.0 / N), np.float32)
     dy = rounded(np.full(M, 1.0 / M), np.float32)
-    F = U.KL(1.0)
-    say("case dense mf running max", far_first, kern)
-    prob = U.points_problem(T(x), T(y), T(p), T(q), T(dx), T(dy), F, F)
-    u1, v1, _ = U.solve(prob, 1e-3, tol=0.0, max_iter=2, dense_kernel=U.DENSE_DIRECT)
-    u2, v2, _ = U.solve(prob, 1e-3, tol=0.0, max_iter=2, dense_kernel=kern)
+    return (x, y, p, q, dx, dy), eps
+
+
+def joint_rel_err(u2, v2, u1, v1):
+    """Largest difference relative to the larger of the two reference
+    potentials' magnitudes: after the first iteration the terms of far pairs
+    are differences of two numbers of order 1/eps, so each FP32 product errs
+    by about 2^-24 of the larger potential, however small the other is."""
     u1, v1, u2, v2 = (t.cpu().numpy().astype(np.float64) for t in (u1, v1, u2, v2))
     scale = max(np.abs(u1).max(), np.abs(v1).max())
-    assert np.abs(u2 - u1).max() / scale < 1e-5
-    assert np.abs(v2 - v1).max() / scale < 1e-5
+    return max(np.abs(u2 - u1).max(), np.abs(v2 - v1).max()) / scale
+
+
+@pytest.mark.parametrize("kern", [pytest.param(U.DENSE_MF, id="mfma"), pytest.param(U.DENSE_MF3, id="mfma_bf16x3")])
+@pytest.mark.parametrize("pattern", ["distance", "density"])
+def test_dense_mf_running_max_jumps(pattern, kern):
+    """Kernels 3 and 4 carry a running row maximum from chunk to chunk of 512
+    columns, starting cold in a solve's first product.  N = 3000,
+    M = 100000: a column split holds about 1200 columns, so splits that open
+    with a chunk of low exponents and then meet high ones are many (the
+    patterns are those of line_jumps).  Compared with the direct product,
+    which the oracle parity tests pin, after 2 iterations."""
+    (x, y, p, q, dx, dy), eps = line_jumps(pattern, 3000, 100000, 11)
+    F = U.KL(1.0)
+    say("case dense mf running max", pattern, kern)
+    prob = U.points_problem(T(x), T(y), T(p), T(q), T(dx), T(dy), F, F)
+    u1, v1, _ = U.solve(prob, eps, tol=0.0, max_iter=2, dense_kernel=U.DENSE_DIRECT)
+    u2, v2, _ = U.solve(prob, eps, tol=0.0, max_iter=2, dense_kernel=kern)
+    assert joint_rel_err(u2, v2, u1, v1) < 1e-5
 
 
 @pytest.mark.parametrize("fill", ["random_bytes", "large_finite"])
