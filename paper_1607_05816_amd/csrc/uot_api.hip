@@ -139,6 +139,7 @@ struct Plan {
   bool dense_mf = false;                     // points: product on the matrix cores
   bool mf_split = false;                     // ... with BF16 x 3 operands (else FP32)
   int mf_groups = 4;                         // its row groups of 16 per wave (4 or 8)
+  int mf_target[2] = {0, 0};                 // its block target per side (0: 1024)
   // the factored products run on Morton-ordered copies of the clouds (rows
   // of a wave or block lie close together, so the factored exponents keep
   // small magnitudes); results are scattered back to the caller's order
@@ -176,6 +177,21 @@ int grid_final_parts_for(const Plan& P, bool tf0) {
 
 int grid_final_parts(const Plan& P) { return grid_final_parts_for(P, use_tf(P, 0)); }
 
+int dense_blocks_env() {
+  static const int v = [] {
+    const char* e = getenv("UOT_DENSE_BLOCKS");
+    return e ? atoi(e) : 0;
+  }();
+  return v;
+}
+
+// block targets the matrix-core product's tuner times (the first is the
+// untuned default): 4 blocks of 256 rows are resident per compute unit, so
+// 1024 fill the chip once; where the last column chunk of a split or the last
+// round of blocks falls depends on the sizes
+constexpr int kMfTargets[] = {1024, 1280, 1536, 2048};
+constexpr int kMfNTargets = 4;
+
 void dense_config(Plan& P, int side) {
   const int64_t Nr = side == 0 ? P.N : P.M;
   const int64_t Mc = side == 0 ? P.M : P.N;
@@ -186,16 +202,14 @@ void dense_config(Plan& P, int side) {
   const int64_t rt = (Nr + 256 * R - 1) / (256 * R);
   // blocks to aim for: 2048 (8 resident per compute unit), 1024 for the
   // matrix-core product (its column chunks after the first cost one pass,
-  // so longer column ranges per block pay); UOT_DENSE_BLOCKS overrides the
-  // target of the factored kernels
-  static const int fac_blocks = [] {
-    const char* e = getenv("UOT_DENSE_BLOCKS");
-    return e ? atoi(e) : 0;
-  }();
+  // so longer column ranges per block pay; the tuner may pick up to 2048);
+  // UOT_DENSE_BLOCKS overrides the target of the factored kernels
+  const int fac_blocks = dense_blocks_env();
   // the matrix-core product: fewer splits to merge; the WF cost: more, as
   // the pairs within the cut concentrate in few (row block, split) pairs and
   // smaller splits spread them over more compute units
-  int64_t target = P.dense_mf ? 1024 : (P.cost.kind == UOT_COST_WF ? 8192 : 2048);
+  int64_t target = P.dense_mf ? (P.mf_target[side] > 0 ? P.mf_target[side] : kMfTargets[0])
+                              : (P.cost.kind == UOT_COST_WF ? 8192 : 2048);
   if ((P.dense_tf || P.dense_mf || P.cost.kind == UOT_COST_WF) && fac_blocks > 0) target = fac_blocks;
   int64_t sp = (target + rt - 1) / rt;
   const int64_t maxsp = (Mc + 31) / 32;
@@ -302,10 +316,17 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
       P.dense_mf = pass >= 2;
       P.mf_groups = pass == 2 ? 8 : 4;
       if (pass == 4) P = keep;
-      dense_config(P, 0);
-      dense_config(P, 1);
-      np = std::max(np, std::max((int64_t)P.splits[0] * P.N, (int64_t)P.splits[1] * P.M));
+      // every block target the matrix-core tuner may pick
+      for (int k = 0; k < (P.dense_mf ? kMfNTargets : 1); ++k) {
+        P.mf_target[0] = P.mf_target[1] = P.dense_mf ? kMfTargets[k] : 0;
+        dense_config(P, 0);
+        dense_config(P, 1);
+        np = std::max(np, std::max((int64_t)P.splits[0] * P.N, (int64_t)P.splits[1] * P.M));
+      }
     }
+    P.mf_target[0] = P.mf_target[1] = 0;
+    dense_config(P, 0);
+    dense_config(P, 1);
     P.o_pm = take(e * np);
     P.o_ps = take(e * np);
     P.np_pw = np;
@@ -729,6 +750,70 @@ struct MassOpt {
   double log_m0;
 };
 
+// The matrix-core product's column splits, per side: each block target of
+// kMfTargets is timed once per context and product shape (a cold launch, then
+// the mean of 3 warm ones; rows, columns and column weights log dy / log dx of
+// the solve, whose values do not change the work), and the fastest is kept.
+// Leaves the row maxima of the side's workspace to be reset by the caller.
+template <typename T>
+int tune_dense_mf(uot_ctx* ctx, Plan& P, const uot_geom& g, Bufs<T>& B, hipStream_t s) {
+  if constexpr (!std::is_same<T, float>::value) {
+    return UOT_OK;
+  } else {
+    if (!P.dense_mf || dense_blocks_env() > 0) return UOT_OK;
+    for (int half = 0; half < 2; ++half) {
+      const int64_t Nr = half == 0 ? P.N : P.M;
+      const int64_t Mc = half == 0 ? P.M : P.N;
+      const std::string key = std::to_string(P.dim) + ":" + std::to_string(Nr) + ":" + std::to_string(Mc) + ":" +
+                              std::to_string(P.mf_groups) + ":" + std::to_string((int)P.mf_split);
+      const auto found = ctx->dense_tuned.find(key);
+      if (found != ctx->dense_tuned.end()) {
+        P.mf_target[half] = found->second;
+        dense_config(P, half);
+        continue;
+      }
+      const float* rows = static_cast<const float*>(half == 0 ? g.x : g.y);
+      const float* cols = static_cast<const float*>(half == 0 ? g.y : g.x);
+      const float* wc = half == 0 ? B.logdy : B.logdx;
+      float* pw = B.pw + half * P.np_pw;
+      hipEvent_t e0, e1;
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      int best = kMfTargets[0], last_sp = -1;
+      float best_t = 0.f;
+      for (int k = 0; k < kMfNTargets; ++k) {
+        P.mf_target[half] = kMfTargets[k];
+        dense_config(P, half);
+        if (P.splits[half] == last_sp) continue;
+        last_sp = P.splits[half];
+        auto launch = [&] {
+          launch_dense_mf(P.dim, P.mf_groups, P.mf_split, rows, Nr, cols, wc, Mc, P.splits[half], P.cps[half], B.pm,
+                          B.ps, pw, half, B.ctrl, s);
+        };
+        HIP_TRY(hipMemsetAsync(pw, 0xFF, sizeof(float) * P.np_pw, s));
+        launch();
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r) launch();
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        if (k == 0 || t < best_t) {
+          best_t = t;
+          best = kMfTargets[k];
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      HIP_TRY(hipGetLastError());
+      P.mf_target[half] = best;
+      dense_config(P, half);
+      ctx->dense_tuned[key] = best;
+    }
+    return UOT_OK;
+  }
+}
+
 template <typename T>
 int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* v, char* ws, size_t wsb,
             uot_result* res, int nb = 1, const MassOpt* mass = nullptr, double* log_z = nullptr) {
@@ -756,13 +841,8 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
     uo = at<T>(ws, P.o_us);
     vo = at<T>(ws, P.o_vs);
   }
-  // the matrix-core product starts this solve with no row maxima (all bits
-  // set: not finite), so a solve does not depend on what the workspace held
-  if (P.dense_mf) HIP_TRY(hipMemsetAsync(B.pw, 0xFF, sizeof(float) * 2 * P.np_pw, s));
   // mixed precision: FP16 passes down to kMixedSwitchTol, then FP32 passes
   const bool mixed = P.gk == 4 && has_tf16(P) && pr->tol < kMixedSwitchTol;
-  Plan P2 = P;
-  for (int k = 0; k < 3; ++k) P2.tf16_axis[k] = false;
   const double tol1 = mixed ? kMixedSwitchTol : pr->tol;
   Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, tol1, pr->max_iter);
   launch_ctrl_init(B.ctrl, init, s);
@@ -780,6 +860,14 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   }
   launch_init_pot<T>(v0, B.logdy, vo, B.wv, nb * P.M, P.M, B.ctrl, 0, s);
   HIP_TRY(hipGetLastError());
+  if (P.dense_mf) {
+    if ((rc = tune_dense_mf<T>(ctx, P, pbs.geom, B, s))) return rc;
+    // the matrix-core product starts this solve with no row maxima (all bits
+    // set: not finite), so a solve does not depend on what the workspace held
+    HIP_TRY(hipMemsetAsync(B.pw, 0xFF, sizeof(float) * 2 * P.np_pw, s));
+  }
+  Plan P2 = P;
+  for (int k = 0; k < 3; ++k) P2.tf16_axis[k] = false;
   const int nfields = nb > 1 ? nb : 0;
   // a single problem on a grid of 2 or 3 axes: the first Y pass (no
   // epilogue) hosts the control step; otherwise it is its own launch
@@ -1224,6 +1312,11 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
   }
   launch_init_pot<T>(vin, B.logdy, nullptr, B.wv, nb * P.M, P.M, B.ctrl, 0, s);
   launch_init_pot<T>(nullptr, B.logdx, B.t3, nullptr, nb * P.N, P.N, B.ctrl, 0, s);   // u = 0 in t3
+  if (P.dense_mf) {
+    int rc2 = tune_dense_mf<T>(ctx, P, pbs.geom, B, s);
+    if (rc2) return rc2;
+    HIP_TRY(hipMemsetAsync(B.pw, 0xFF, sizeof(float) * 2 * P.np_pw, s));
+  }
   EpiArgs<T> ep = prox_epi<T>(B.t3, B.wu, B.logp, B.logdx, nullptr, B.parts, P.N, pb->F1);
   EpiArgs<T> raw{};
   raw.mode = EPI_RAW;

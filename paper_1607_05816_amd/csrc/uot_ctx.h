@@ -17,6 +17,7 @@ struct uot_ctx {
   uot::Ctrl* pinned = nullptr;  // host mirror of the control block
   int device = 0;
   std::map<std::string, std::pair<int, int>> batch_tuned;   // batch signature -> (R, blocks per CU)
+  std::map<std::string, int> dense_tuned;                    // matrix-core product shape -> block target
 };
 
 namespace uot {
