@@ -40,16 +40,19 @@
 // accumulator input.  m starts from the row's maximum over the same columns
 // (the block's column split; all columns of a batch problem) in the previous
 // product of this side (pw; the potentials move little between iterations),
-// or is not finite (the first product of a solve).  A chunk where some row has no
-// finite m takes a maximum pass first (lane maxima, then over the 4 lanes of
-// the row), so every exp2 argument is <= 0.  Otherwise the sum pass runs
-// alone against m: a term above m stays finite up to 2^127, and the chunk is
-// redone with both passes when a row total is not below 2^100 (which
-// includes an overflow); otherwise whole powers of two of the total move into
-// m.  A row whose final total is below 2^-60 started from an m too high: the
-// block then sums its split again from no maximum.  So every accepted total
-// has a term within 2^60 of m, and the terms that underflow (more than
-// 2^126 below m) do not change it.
+// or is not finite (the first product of a solve).  A wave whose rows all
+// start from a finite m runs the sum pass alone over every chunk and checks
+// the row totals at the end of the split.  Otherwise a chunk where some row
+// has no finite m takes a maximum pass first (lane maxima, then over the 4
+// lanes of the row), so every exp2 argument is <= 0, and later chunks run the
+// sum pass against m, redone with both passes when a row total is not below
+// 2^100 (a term above m stays finite up to 2^127, and an overflow fails the
+// test too); accepted chunks move whole powers of two of the total into m.
+// A row whose final total is below 2^-60 (under a finite m) started from an
+// m too high, one not below 2^100 (unchecked chunks) from one too low: the
+// block then sums its split again from no maximum, checking every chunk.  So
+// every accepted total has a term within 2^60 of m, and the terms that
+// underflow (more than 2^126 below m) do not change it.
 // Columns without mass (and padding) carry G = -inf, so their terms are 0.
 // G row groups of 16 per wave (64 G rows per block);
 // grid = (ceil(Nr / (64 G)), splits); partials (m, s) per split as the
@@ -283,7 +286,15 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
     wm[g] = __builtin_isfinite(v) ? v : -__builtin_inff();
   }
   const Op* base = SPLIT ? &st[li * 4 + q] : &st[q * kCols + li];
+  // a wave whose rows all start from a finite maximum sums every chunk
+  // against it and checks its totals once, at the end of the split; a failed
+  // check sums the split again from no maximum, checking every chunk
+  bool cold = false;
+#pragma unroll
+  for (int g = 0; g < G; ++g) cold = cold || wm[g] == -__builtin_inff();
+  const bool warm_wave = !__any(cold);
   for (int attempt = 0;; ++attempt) {
+    const bool unchecked = attempt == 0 && warm_wave;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       m[g] = attempt == 0 ? wm[g] : -__builtin_inff();
@@ -344,7 +355,12 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
 #pragma unroll
       for (int g = 0; g < G; ++g) two = two || m[g] == -__builtin_inff();
       two = __any(two);
-      if (!two) {
+      if (!two && unchecked) {
+        mf_f32x4 nm[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
+        mf_sum_pass<SPLIT, G>(base, E, nm, ntl, s);
+      } else if (!two) {
         float s0[G];
         mf_f32x4 nm[G];
 #pragma unroll
@@ -392,15 +408,16 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
       }
     }
     // totals of each row over its 4 lanes; a total below 2^-60 under a finite
-    // maximum came from a starting maximum too high: sum the split again from
-    // none (the whole block, as the chunk loop holds barriers)
-    bool low = false;
+    // maximum came from a starting maximum too high, one not below 2^100
+    // (unchecked chunks) from one too low: sum the split again from none (the
+    // whole block, as the chunk loop holds barriers)
+    bool redo = false;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       tot[g] = sum_over_rows(s[g]);
-      low = low || (m[g] != -__builtin_inff() && !(tot[g] >= 0x1p-60f));
+      redo = redo || (m[g] != -__builtin_inff() && !(tot[g] >= 0x1p-60f)) || !(tot[g] < 0x1p100f);
     }
-    if (attempt > 0 || !__syncthreads_or(low)) break;
+    if (attempt > 0 || !__syncthreads_or(redo)) break;
   }
   // row constants R_i = -c |e_i|^2
 #pragma unroll
