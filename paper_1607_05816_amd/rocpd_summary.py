@@ -2,7 +2,7 @@
 
     python -m paper_1607_05816_amd.rocpd_summary <run_results.db> [--top N]
     python -m paper_1607_05816_amd.rocpd_summary --pmc <fetch.csv> <write.csv> [--copy-bytes B]
-    python -m paper_1607_05816_amd.rocpd_summary --counters <a.csv> [<b.csv> ...] [--match S]
+    python -m paper_1607_05816_amd.rocpd_summary --counters <a.csv> [<b.csv> ...] [--match S] [--last N]
 
 rocprofv3's own --stats table averages every launch of a kernel symbol; the
 same symbol runs here at several launch shapes (one field vs a batch of
@@ -11,7 +11,8 @@ markdown table of calls and durations in ns.
 
 --counters: counter_collection.csv files of `rocprofv3 --pmc` runs (any
 counters); per kernel (and launch size) the mean of each counter over the
-dispatches, one column per counter; --match keeps kernels whose name holds S.
+dispatches, one column per counter (--last N: over the last N dispatches of
+each, in dispatch order); --match keeps kernels whose name holds S.
 
 --pmc: the counter_collection.csv files of two `rocprofv3 --pmc FETCH_SIZE`
 and `--pmc WRITE_SIZE` runs of the same program.  Both counters read KiB per
@@ -65,11 +66,13 @@ def summarize_pmc(fetch_csv, write_csv, copy_bytes, top=12):
     return "\n".join(out)
 
 
-def summarize_counters(paths, match=None):
+def summarize_counters(paths, match=None, last=0):
     agg = collections.defaultdict(lambda: collections.defaultdict(list))
     names = []
     for path in paths:
-        for r in csv.DictReader(open(path)):
+        rows = list(csv.DictReader(open(path)))
+        rows.sort(key=lambda r: int(r.get("Dispatch_Id") or 0))
+        for r in rows:
             name = r["Kernel_Name"].split("(")[0].replace("void ", "")
             if match and match not in name:
                 continue
@@ -80,7 +83,8 @@ def summarize_counters(paths, match=None):
     out = ["| kernel | grid (work-items) | " + " | ".join(names) + " |",
            "|:--|--:|" + "--:|" * len(names)]
     for k in sorted(agg):
-        vals = [("%.4g" % (sum(agg[k][c]) / len(agg[k][c]))) if agg[k][c] else "" for c in names]
+        sel = {c: agg[k][c][-last:] if last > 0 else agg[k][c] for c in names}
+        vals = [("%.4g" % (sum(sel[c]) / len(sel[c]))) if sel[c] else "" for c in names]
         out.append("| `%s` | %d | %s |" % (k[0], k[1], " | ".join(vals)))
     return "\n".join(out)
 
@@ -93,9 +97,10 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=256 << 20)
     ap.add_argument("--counters", nargs="+")
     ap.add_argument("--match")
+    ap.add_argument("--last", type=int, default=0)
     a = ap.parse_args()
     if a.counters:
-        print(summarize_counters(a.counters, a.match))
+        print(summarize_counters(a.counters, a.match, a.last))
     elif a.pmc:
         print(summarize_pmc(a.pmc[0], a.pmc[1], a.copy_bytes, a.top))
     else:

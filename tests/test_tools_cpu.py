@@ -51,3 +51,18 @@ def test_counter_means_per_kernel(tmp_path):
     assert out[0] == "| kernel | grid (work-items) | SQ_WAVES | SQ_INSTS_MFMA |"
     assert out[2] == "| `uot::k_x<3>` | 1024 | 24 | 5 |"
     assert len(out) == 3
+
+
+def test_counter_means_over_last_dispatches(tmp_path):
+    a = tmp_path / "a.csv"
+    fields = ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"]
+    rows = [(3, "uot::k_y()", 512, "SQ_WAVES", 30), (1, "uot::k_y()", 512, "SQ_WAVES", 1000),
+            (4, "uot::k_y()", 512, "SQ_WAVES", 50), (2, "uot::k_y()", 512, "SQ_WAVES", 10)]
+    with open(a, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(fields, r)))
+    # the last two in dispatch order are 30 and 50; all four average 272.5
+    assert R.summarize_counters([str(a)], last=2).splitlines()[2] == "| `uot::k_y` | 512 | 40 |"
+    assert R.summarize_counters([str(a)]).splitlines()[2] == "| `uot::k_y` | 512 | 272.5 |"
