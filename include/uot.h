@@ -190,7 +190,11 @@ typedef struct uot_params {
                             box), so their potentials err by a few 2^-24 r^2
                             in cost units, the direct product's by a few
                             2^-24 |u|: choose 1 where the potentials are far
-                            below r^2 (local transport at tiny eps)        */
+                            below r^2 (local transport at tiny eps).
+                            Kernels 3 and 4 time their column splits at
+                            the first solve of a shape (4 candidates, a few
+                            ms; kept in the context; UOT_DENSE_BLOCKS in
+                            the environment fixes the block target)       */
 } uot_params;
 
 typedef struct uot_result {
