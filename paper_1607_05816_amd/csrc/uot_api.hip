@@ -776,9 +776,17 @@ int tune_dense_mf(uot_ctx* ctx, Plan& P, const uot_geom& g, Bufs<T>& B, hipStrea
       const float* cols = static_cast<const float*>(half == 0 ? g.y : g.x);
       const float* wc = half == 0 ? B.logdy : B.logdx;
       float* pw = B.pw + half * P.np_pw;
-      hipEvent_t e0, e1;
-      HIP_TRY(hipEventCreate(&e0));
-      HIP_TRY(hipEventCreate(&e1));
+      // the two timing events, released on every return
+      struct Events {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+          for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+        }
+      } ev;
+      HIP_TRY(hipEventCreate(&ev.e[0]));
+      HIP_TRY(hipEventCreate(&ev.e[1]));
+      hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
       int best = kMfTargets[0], last_sp = -1;
       float best_t = 0.f;
       for (int k = 0; k < kMfNTargets; ++k) {
@@ -803,8 +811,6 @@ int tune_dense_mf(uot_ctx* ctx, Plan& P, const uot_geom& g, Bufs<T>& B, hipStrea
           best = kMfTargets[k];
         }
       }
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
       HIP_TRY(hipGetLastError());
       P.mf_target[half] = best;
       dense_config(P, half);
