@@ -146,9 +146,11 @@ struct Plan {
   bool sorted() const { return dense_tf || dense_mf; }
   // workspace offsets
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
-      o_gcost, o_obj, o_scal, o_mass, o_xs, o_ys, o_permx, o_permy, o_code, o_box, o_us, o_vs, o_pw, total;
+      o_gcost, o_obj, o_scal, o_mass, o_xs, o_ys, o_permx, o_permy, o_code, o_box, o_us, o_vs, o_pw, o_wfbox,
+      total;
   int64_t obj_doubles = 0;
   int64_t np_pw = 0;                         // points: row maxima per side (matrix-core product)
+  bool wfb = false;                          // WF points: block / split boxes computed for this call
 };
 
 bool use_tf(const Plan& P, int axis) { return P.tf_axis[axis]; }
@@ -364,6 +366,11 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
   // row maxima the matrix-core product leaves for the next product of the
   // same side (two sides)
   P.o_pw = take(pts ? sizeof(float) * 2 * P.np_pw : 0);
+  // WF points: boxes of the 256-row blocks and of the column splits, both
+  // sides (row blocks of x, splits of y, row blocks of y, splits of x)
+  P.o_wfbox = take(pts && P.cost.kind == UOT_COST_WF
+                       ? e * 6 * ((P.N + 255) / 256 + (P.M + 255) / 256 + P.splits[0] + P.splits[1])
+                       : 0);
   P.total = o;
   return UOT_OK;
 }
@@ -413,6 +420,7 @@ template <typename T> struct Bufs {
   double* scal;
   T *mass_m, *mass_s;     // mass partials of Algorithm 4 (Y epilogue)
   float* pw;              // points: row maxima of the two sides' products
+  T* wfbox;               // WF points: block and split boxes (Plan::o_wfbox)
 };
 
 template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
@@ -430,6 +438,7 @@ template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
   b.pm = at<T>(ws, P.o_pm);
   b.ps = at<T>(ws, P.o_ps);
   b.pw = at<float>(ws, P.o_pw);
+  b.wfbox = at<T>(ws, P.o_wfbox);
   b.parts = at<ResPart>(ws, P.o_parts);
   for (int k = 0; k < 3; ++k) b.gtab[k] = at<T>(ws, P.o_gtab[k]);
   b.gcost = at<T>(ws, P.o_gcost);
@@ -517,6 +526,35 @@ void grid_chain(const Plan& P, const T* w, T* const* tabs, int side, Ctrl* c, co
   }
 }
 
+// WF point clouds: the boxes the product's blocks test before their columns
+// (rows in blocks of 256, R = 1 for the WF cost; columns by split), once per
+// call; P.wfb tells the products of this call to use them
+template <typename T>
+void wf_boxes(Plan& P, const uot_geom& g, Bufs<T>& B, hipStream_t s) {
+  if (P.geom != UOT_GEOM_POINTS || P.cost.kind != UOT_COST_WF) return;
+  const T* x = static_cast<const T*>(g.x);
+  const T* y = static_cast<const T*>(g.y);
+  const int64_t rN = (P.N + 255) / 256, rM = (P.M + 255) / 256;
+  T* b = B.wfbox;
+  launch_chunk_boxes<T>(x, P.N, 256, P.dim, b, s);
+  launch_chunk_boxes<T>(y, P.M, P.cps[0], P.dim, b + 6 * rN, s);
+  launch_chunk_boxes<T>(y, P.M, 256, P.dim, b + 6 * (rN + P.splits[0]), s);
+  launch_chunk_boxes<T>(x, P.N, P.cps[1], P.dim, b + 6 * (rN + P.splits[0] + rM), s);
+  P.wfb = true;
+}
+
+template <typename T>
+CostArgs wf_cost(const Plan& P, const Bufs<T>& B, int half) {
+  CostArgs ca = P.cost;
+  if (P.wfb && P.R[half] == 1) {
+    const int64_t rN = (P.N + 255) / 256, rM = (P.M + 255) / 256;
+    const T* b = B.wfbox;
+    ca.rbox = half == 0 ? b : b + 6 * (rN + P.splits[0]);
+    ca.cbox = half == 0 ? b + 6 * rN : b + 6 * (rN + P.splits[0] + rM);
+  }
+  return ca;
+}
+
 // dense point-cloud product for one side; returns the residual partial count
 template <typename T>
 void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Bufs<T>& B, Ctrl* c,
@@ -539,7 +577,7 @@ void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Buf
       }
     }
     launch_dense_lse<T>(P.dim, P.R[half], rows, Nr, cols, w_cols, Mc, P.splits[half], P.cps[half], B.pm, B.ps, side,
-                        c, P.cost, s);
+                        c, wf_cost<T>(P, B, half), s);
   });
   timed(1, [&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[half], Nr, side, c, ep, s); });
 }
@@ -872,6 +910,7 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
     // set: not finite), so a solve does not depend on what the workspace held
     HIP_TRY(hipMemsetAsync(B.pw, 0xFF, sizeof(float) * 2 * P.np_pw, s));
   }
+  wf_boxes<T>(P, pbs.geom, B, s);
   Plan P2 = P;
   for (int k = 0; k < 3; ++k) P2.tf16_axis[k] = false;
   const int nfields = nb > 1 ? nb : 0;
@@ -1323,6 +1362,7 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
     if (rc2) return rc2;
     HIP_TRY(hipMemsetAsync(B.pw, 0xFF, sizeof(float) * 2 * P.np_pw, s));
   }
+  wf_boxes<T>(P, pbs.geom, B, s);
   EpiArgs<T> ep = prox_epi<T>(B.t3, B.wu, B.logp, B.logdx, nullptr, B.parts, P.N, pb->F1);
   EpiArgs<T> raw{};
   raw.mode = EPI_RAW;
@@ -1359,7 +1399,7 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
         }
       }
       launch_dense_lse<T>(P.dim, P.R[0], rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps, 0, B.ctrl,
-                          P.cost, s);
+                          wf_cost<T>(P, B, 0), s);
     });
     ks.push_back([&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[0], P.N, 0, B.ctrl, ep, s); });
   }

@@ -336,8 +336,35 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
                                                        const T* __restrict__ yc, const T* __restrict__ w,
                                                        int64_t Mc, int64_t cols_per_split,
                                                        T* __restrict__ pm, T* __restrict__ ps, int side,
-                                                       const Ctrl* __restrict__ c, T a2, T cut2) {
+                                                       const Ctrl* __restrict__ c, T a2, T cut2,
+                                                       const T* __restrict__ rbox, const T* __restrict__ cbox) {
   if (skip_side(c, side)) return;
+  if constexpr (COST == 1) {
+    // the block's rows against its column split as boxes: when every pair is
+    // beyond the cut, every entry is exactly zero and the partial is empty
+    if (rbox != nullptr) {
+      const T* rb = rbox + 6 * (int64_t)blockIdx.x;
+      const T* cb = cbox + 6 * (int64_t)blockIdx.y;
+      T gap2 = T(0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const T g = Num<T>::fmax(Num<T>::fmax(cb[2 * d] - rb[2 * d + 1], rb[2 * d] - cb[2 * d + 1]), T(0));
+        gap2 = Num<T>::fma(g, g, gap2);
+      }
+      if (!(gap2 < cut2)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int64_t row = (int64_t)blockIdx.x * (kBlock * R) + (threadIdx.x >> 6) * (64 * R) + r * 64 +
+                              (threadIdx.x & 63);
+          if (row < Nr) {
+            pm[blockIdx.y * Nr + row] = Num<T>::ninf();
+            ps[blockIdx.y * Nr + row] = T(0);
+          }
+        }
+        return;
+      }
+    }
+  }
   using V4 = typename Vec4<T>::type;
   __shared__ V4 tile[kBlock];
   const T sc = T(kLog2e / eps_of(c, side));
@@ -1648,11 +1675,47 @@ static void launch_dense_lse_t(const T* xr, int64_t Nr, const T* yc, const T* w,
   if (cost.kind == 1) {
     const T a2 = T(0.25 * M_PI * M_PI / (cost.cut * cost.cut)), cut2 = T(cost.cut * cost.cut);
     hipLaunchKernelGGL((k_dense_lse<T, DIM, R, 1>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side,
-                       c, a2, cut2);
+                       c, a2, cut2, static_cast<const T*>(cost.rbox), static_cast<const T*>(cost.cbox));
   } else {
     hipLaunchKernelGGL((k_dense_lse<T, DIM, R, 0>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side,
-                       c, T(0), T(0));
+                       c, T(0), T(0), static_cast<const T*>(nullptr), static_cast<const T*>(nullptr));
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_chunk_boxes(const T* __restrict__ pts, int64_t n, int64_t per, int dim,
+                                                         T* __restrict__ out) {
+  __shared__ T red[2][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = b0 + per < n ? b0 + per : n;
+  for (int d = 0; d < 3; ++d) {
+    T lo = Num<T>::pinf(), hi = Num<T>::ninf();
+    if (d < dim)
+      for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
+        lo = Num<T>::fmin(lo, pts[d * n + i]);
+        hi = Num<T>::fmax(hi, pts[d * n + i]);
+      }
+    lo = lanes_min<T>(lo, 32);
+    hi = lanes_max<T>(hi, 32);
+    __syncthreads();                       // the previous coordinate's reads are done
+    if (lane == 0) {
+      red[0][wv] = lo;
+      red[1][wv] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      lo = Num<T>::fmin(Num<T>::fmin(red[0][0], red[0][1]), Num<T>::fmin(red[0][2], red[0][3]));
+      hi = Num<T>::fmax(Num<T>::fmax(red[1][0], red[1][1]), Num<T>::fmax(red[1][2], red[1][3]));
+      out[6 * (int64_t)blockIdx.x + 2 * d] = d < dim ? lo : T(0);
+      out[6 * (int64_t)blockIdx.x + 2 * d + 1] = d < dim ? hi : T(0);
+    }
+  }
+}
+
+template <typename T>
+void launch_chunk_boxes(const T* pts, int64_t n, int64_t per, int dim, T* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_chunk_boxes<T>, dim3(ceil_div(n, per)), dim3(kBlock), 0, s, pts, n, per, dim, out);
 }
 
 template <typename T>
@@ -1791,6 +1854,7 @@ void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w
                                             hipStream_t);                                                         \
   template void launch_dense_lse<T>(int, int, const T*, int64_t, const T*, const T*, int64_t, int, int64_t, T*,  \
                                     T*, int, const Ctrl*, const CostArgs&, hipStream_t);                          \
+  template void launch_chunk_boxes<T>(const T*, int64_t, int64_t, int, T*, hipStream_t);                        \
   template void launch_dense_epi<T>(const T*, const T*, int, int64_t, int, const Ctrl*, const EpiArgs<T>&,       \
                                     hipStream_t);                                                                 \
   template void launch_bary_combine<T>(const T*, int, int64_t, const BaryW&, double, const DivDev&, const T*,    \

@@ -15,6 +15,10 @@ struct CostArgs {
   int kind;
   int pad;
   double cut;
+  // WF dense products: boxes (lo, hi per coordinate: 6 values) of the rows'
+  // blocks of 256 and of the columns' splits, or null (no block-level test)
+  const void* rbox = nullptr;
+  const void* cbox = nullptr;
 };
 
 // What the last pass of a Gibbs product does with S2 = log2 of the product.
@@ -72,6 +76,10 @@ void launch_grid_contig_split(const T* in, int64_t A, int n, const T* gtab, int 
 template <typename T>
 void launch_dense_lse(int dim, int R, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, int nsplit,
                       int64_t cps, T* pm, T* ps, int side, const Ctrl* c, const CostArgs& cost, hipStream_t s);
+// boxes of consecutive chunks of `per` points (SoA, n points, dim <= 3):
+// out[6 b + 2 d], out[6 b + 2 d + 1] = min, max of coordinate d over chunk b
+template <typename T>
+void launch_chunk_boxes(const T* pts, int64_t n, int64_t per, int dim, T* out, hipStream_t s);
 template <typename T>
 void launch_dense_epi(const T* pm, const T* ps, int nsplit, int64_t Nr, int side, const Ctrl* c,
                       const EpiArgs<T>& ep, hipStream_t s);
