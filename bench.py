@@ -185,12 +185,12 @@ PASS_NAMES = ["k_grid_tf<false, 4>", "k_grid_tf<true, 4>"]
 # on (sha256 of the pass's file and the headers it includes) and are reported
 # as null otherwise.
 TRAFFIC_SOURCES = ["uot_grid_tf.hip", "uot_epilogue.h", "uot_device.h", "uot_launch.h"]
-TRAFFIC_SOURCE_SHA256 = "88636795026a0843a98b9d557af51f0f3929ebbcd353dbb45bb7d64b7dbbed46"
+TRAFFIC_SOURCE_SHA256 = "38bc0ed204173d6a9cc25effd79c3265698ce3347e6b5fafe54186552afeb729"
 TRAFFIC_BYTES = {
     ('k_grid_tf<false, 4>', 1): (2273408, 259840),
-    ('k_grid_tf<false, 4>', 256): (67287321, 67108864),
+    ('k_grid_tf<false, 4>', 256): (67287172, 67108864),
     ('k_grid_tf<true, 4>', 1): (3096797, 523671),
-    ('k_grid_tf<true, 4>', 256): (406622285, 134348800),
+    ('k_grid_tf<true, 4>', 256): (406346152, 134348800),
 }
 
 

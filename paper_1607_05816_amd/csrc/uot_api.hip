@@ -147,7 +147,7 @@ struct Plan {
   // workspace offsets
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
       o_gcost, o_obj, o_scal, o_mass, o_xs, o_ys, o_permx, o_permy, o_code, o_box, o_us, o_vs, o_pw, o_wfbox,
-      total;
+      o_wfact, total;
   int64_t obj_doubles = 0;
   int64_t np_pw = 0;                         // points: row maxima per side (matrix-core product)
   bool wfb = false;                          // WF points: block / split boxes computed for this call
@@ -209,9 +209,10 @@ void dense_config(Plan& P, int side) {
   const int fac_blocks = dense_blocks_env();
   // the matrix-core product: fewer splits to merge; the WF cost: more, as
   // the pairs within the cut concentrate in few (row block, split) pairs and
-  // smaller splits spread them over more compute units
+  // smaller splits spread them over more compute units (blocks and merges
+  // skip the pairs whose boxes are beyond the cut)
   int64_t target = P.dense_mf ? (P.mf_target[side] > 0 ? P.mf_target[side] : kMfTargets[0])
-                              : (P.cost.kind == UOT_COST_WF ? 8192 : 2048);
+                              : (P.cost.kind == UOT_COST_WF ? 16384 : 2048);
   if ((P.dense_tf || P.dense_mf || P.cost.kind == UOT_COST_WF) && fac_blocks > 0) target = fac_blocks;
   int64_t sp = (target + rt - 1) / rt;
   const int64_t maxsp = (Mc + 31) / 32;
@@ -371,6 +372,10 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
   P.o_wfbox = take(pts && P.cost.kind == UOT_COST_WF
                        ? e * 6 * ((P.N + 255) / 256 + (P.M + 255) / 256 + P.splits[0] + P.splits[1])
                        : 0);
+  // ... and the activity flag of every (row block, column split) pair
+  P.o_wfact = take(pts && P.cost.kind == UOT_COST_WF
+                       ? (size_t)((P.N + 255) / 256 * P.splits[0] + (P.M + 255) / 256 * P.splits[1])
+                       : 0);
   P.total = o;
   return UOT_OK;
 }
@@ -421,6 +426,7 @@ template <typename T> struct Bufs {
   T *mass_m, *mass_s;     // mass partials of Algorithm 4 (Y epilogue)
   float* pw;              // points: row maxima of the two sides' products
   T* wfbox;               // WF points: block and split boxes (Plan::o_wfbox)
+  uint8_t* wfact;         // WF points: activity of (row block, split) pairs, side 0 then side 1
 };
 
 template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
@@ -439,6 +445,7 @@ template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
   b.ps = at<T>(ws, P.o_ps);
   b.pw = at<float>(ws, P.o_pw);
   b.wfbox = at<T>(ws, P.o_wfbox);
+  b.wfact = at<uint8_t>(ws, P.o_wfact);
   b.parts = at<ResPart>(ws, P.o_parts);
   for (int k = 0; k < 3; ++k) b.gtab[k] = at<T>(ws, P.o_gtab[k]);
   b.gcost = at<T>(ws, P.o_gcost);
@@ -526,32 +533,40 @@ void grid_chain(const Plan& P, const T* w, T* const* tabs, int side, Ctrl* c, co
   }
 }
 
-// WF point clouds: the boxes the product's blocks test before their columns
-// (rows in blocks of 256, R = 1 for the WF cost; columns by split), once per
-// call; P.wfb tells the products of this call to use them
+// WF point clouds: which (block of 256 rows, column split) pairs of each
+// side have a pair within the cut, from the boxes of the row blocks (R = 1
+// for the WF cost) and of the splits; once per call (the geometry is fixed),
+// and P.wfb tells the products and merges of this call to use the flags
 template <typename T>
 void wf_boxes(Plan& P, const uot_geom& g, Bufs<T>& B, hipStream_t s) {
-  if (P.geom != UOT_GEOM_POINTS || P.cost.kind != UOT_COST_WF) return;
+  if (P.geom != UOT_GEOM_POINTS || P.cost.kind != UOT_COST_WF || P.R[0] != 1 || P.R[1] != 1) return;
   const T* x = static_cast<const T*>(g.x);
   const T* y = static_cast<const T*>(g.y);
   const int64_t rN = (P.N + 255) / 256, rM = (P.M + 255) / 256;
-  T* b = B.wfbox;
-  launch_chunk_boxes<T>(x, P.N, 256, P.dim, b, s);
-  launch_chunk_boxes<T>(y, P.M, P.cps[0], P.dim, b + 6 * rN, s);
-  launch_chunk_boxes<T>(y, P.M, 256, P.dim, b + 6 * (rN + P.splits[0]), s);
-  launch_chunk_boxes<T>(x, P.N, P.cps[1], P.dim, b + 6 * (rN + P.splits[0] + rM), s);
+  T* bxr = B.wfbox;                               // x by 256
+  T* byc = bxr + 6 * rN;                          // y by side 0's splits
+  T* byr = byc + 6 * P.splits[0];                 // y by 256
+  T* bxc = byr + 6 * rM;                          // x by side 1's splits
+  launch_chunk_boxes<T>(x, P.N, 256, P.dim, bxr, s);
+  launch_chunk_boxes<T>(y, P.M, P.cps[0], P.dim, byc, s);
+  launch_chunk_boxes<T>(y, P.M, 256, P.dim, byr, s);
+  launch_chunk_boxes<T>(x, P.N, P.cps[1], P.dim, bxc, s);
+  const double cut2 = P.cost.cut * P.cost.cut;
+  launch_box_pairs<T>(bxr, rN, byc, P.splits[0], P.dim, cut2, B.wfact, s);
+  launch_box_pairs<T>(byr, rM, bxc, P.splits[1], P.dim, cut2, B.wfact + rN * P.splits[0], s);
   P.wfb = true;
+}
+
+template <typename T>
+const uint8_t* wf_act(const Plan& P, const Bufs<T>& B, int half) {
+  if (!P.wfb) return nullptr;
+  return half == 0 ? B.wfact : B.wfact + (P.N + 255) / 256 * P.splits[0];
 }
 
 template <typename T>
 CostArgs wf_cost(const Plan& P, const Bufs<T>& B, int half) {
   CostArgs ca = P.cost;
-  if (P.wfb && P.R[half] == 1) {
-    const int64_t rN = (P.N + 255) / 256, rM = (P.M + 255) / 256;
-    const T* b = B.wfbox;
-    ca.rbox = half == 0 ? b : b + 6 * (rN + P.splits[0]);
-    ca.cbox = half == 0 ? b + 6 * rN : b + 6 * (rN + P.splits[0] + rM);
-  }
+  ca.act = wf_act<T>(P, B, half);
   return ca;
 }
 
@@ -579,7 +594,7 @@ void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Buf
     launch_dense_lse<T>(P.dim, P.R[half], rows, Nr, cols, w_cols, Mc, P.splits[half], P.cps[half], B.pm, B.ps, side,
                         c, wf_cost<T>(P, B, half), s);
   });
-  timed(1, [&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[half], Nr, side, c, ep, s); });
+  timed(1, [&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[half], Nr, side, c, ep, s, wf_act<T>(P, B, half)); });
 }
 
 template <typename T>
@@ -1401,7 +1416,7 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
       launch_dense_lse<T>(P.dim, P.R[0], rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps, 0, B.ctrl,
                           wf_cost<T>(P, B, 0), s);
     });
-    ks.push_back([&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[0], P.N, 0, B.ctrl, ep, s); });
+    ks.push_back([&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[0], P.N, 0, B.ctrl, ep, s, wf_act<T>(P, B, 0)); });
   }
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));

@@ -337,34 +337,11 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
                                                        int64_t Mc, int64_t cols_per_split,
                                                        T* __restrict__ pm, T* __restrict__ ps, int side,
                                                        const Ctrl* __restrict__ c, T a2, T cut2,
-                                                       const T* __restrict__ rbox, const T* __restrict__ cbox) {
+                                                       const uint8_t* __restrict__ act) {
   if (skip_side(c, side)) return;
-  if constexpr (COST == 1) {
-    // the block's rows against its column split as boxes: when every pair is
-    // beyond the cut, every entry is exactly zero and the partial is empty
-    if (rbox != nullptr) {
-      const T* rb = rbox + 6 * (int64_t)blockIdx.x;
-      const T* cb = cbox + 6 * (int64_t)blockIdx.y;
-      T gap2 = T(0);
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const T g = Num<T>::fmax(Num<T>::fmax(cb[2 * d] - rb[2 * d + 1], rb[2 * d] - cb[2 * d + 1]), T(0));
-        gap2 = Num<T>::fma(g, g, gap2);
-      }
-      if (!(gap2 < cut2)) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int64_t row = (int64_t)blockIdx.x * (kBlock * R) + (threadIdx.x >> 6) * (64 * R) + r * 64 +
-                              (threadIdx.x & 63);
-          if (row < Nr) {
-            pm[blockIdx.y * Nr + row] = Num<T>::ninf();
-            ps[blockIdx.y * Nr + row] = T(0);
-          }
-        }
-        return;
-      }
-    }
-  }
+  // WF: a block whose rows and column split are beyond the cut as boxes has
+  // only exact zeros; its partial is neither written nor merged
+  if (COST == 1 && act != nullptr && !act[(int64_t)blockIdx.x * gridDim.y + blockIdx.y]) return;
   using V4 = typename Vec4<T>::type;
   __shared__ V4 tile[kBlock];
   const T sc = T(kLog2e / eps_of(c, side));
@@ -968,13 +945,65 @@ void launch_dense_tf(int dim, const float* xr, int64_t Nr, const float* yc, cons
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, const T* __restrict__ ps,
                                                        int nsplit, int64_t Nr, int side,
-                                                       const Ctrl* __restrict__ c, EpiArgs<T> ep) {
+                                                       const Ctrl* __restrict__ c, EpiArgs<T> ep,
+                                                       const uint8_t* __restrict__ act) {
   if (skip_side(c, side)) return;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool valid = i < Nr;
   ResAcc<T> ra;
   ra.init();
-  if (valid) {
+  // WF: only the partials of active (row block, split) pairs exist; the
+  // block's 256 rows are one row block of the product, so the flags are the
+  // same for every thread.  Up to kEpiList splits, the active ones are listed
+  // in LDS in split order (ballots per wave), so the loads below stay
+  // independent; beyond, each split's flag is tested in the loop.
+  constexpr int kEpiList = 1024;
+  __shared__ int lst[kEpiList];
+  __shared__ int wcnt[kBlock / 64];
+  int nact = -1;
+  if (act != nullptr && nsplit <= kEpiList) {
+    const uint8_t* a = act + (int64_t)blockIdx.x * nsplit;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    nact = 0;
+    for (int c0 = 0; c0 < nsplit; c0 += kBlock) {
+      const int sp = c0 + threadIdx.x;
+      const bool f = sp < nsplit && a[sp] != 0;
+      const uint64_t m = __ballot(f);
+      if (lane == 0) wcnt[wv] = __popcll(m);
+      __syncthreads();
+      int off = nact;
+      for (int k = 0; k < wv; ++k) off += wcnt[k];
+      if (f) lst[off + __popcll(m & ((uint64_t(1) << lane) - 1))] = sp;
+      for (int k = 0; k < kBlock / 64; ++k) nact += wcnt[k];
+      __syncthreads();
+    }
+  }
+  if (valid && nact >= 0) {
+    T mx = Num<T>::ninf();
+#pragma unroll 8
+    for (int k = 0; k < nact; ++k) mx = Num<T>::fmax(mx, pm[lst[k] * Nr + i]);
+    T lse = mx;
+    if (mx != Num<T>::ninf()) {
+      T sum = T(0);
+#pragma unroll 8
+      for (int k = 0; k < nact; ++k) sum += ps[lst[k] * Nr + i] * Num<T>::exp2(pm[lst[k] * Nr + i] - mx);
+      lse = mx + Num<T>::log2(sum);
+    }
+    epi_elem<T>(i, lse, c, side, ep, ra);
+  } else if (valid && act != nullptr) {
+    const uint8_t* a = act + (int64_t)blockIdx.x * nsplit;
+    T mx = Num<T>::ninf();
+    for (int s = 0; s < nsplit; ++s)
+      if (a[s]) mx = Num<T>::fmax(mx, pm[s * Nr + i]);
+    T lse = mx;
+    if (mx != Num<T>::ninf()) {
+      T sum = T(0);
+      for (int s = 0; s < nsplit; ++s)
+        if (a[s]) sum += ps[s * Nr + i] * Num<T>::exp2(pm[s * Nr + i] - mx);
+      lse = mx + Num<T>::log2(sum);
+    }
+    epi_elem<T>(i, lse, c, side, ep, ra);
+  } else if (valid) {
     // two passes over the splits with independent loads: the largest
     // maximum, then the sum of the partial sums scaled to it
     T mx = Num<T>::ninf();
@@ -1675,11 +1704,34 @@ static void launch_dense_lse_t(const T* xr, int64_t Nr, const T* yc, const T* w,
   if (cost.kind == 1) {
     const T a2 = T(0.25 * M_PI * M_PI / (cost.cut * cost.cut)), cut2 = T(cost.cut * cost.cut);
     hipLaunchKernelGGL((k_dense_lse<T, DIM, R, 1>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side,
-                       c, a2, cut2, static_cast<const T*>(cost.rbox), static_cast<const T*>(cost.cbox));
+                       c, a2, cut2, cost.act);
   } else {
     hipLaunchKernelGGL((k_dense_lse<T, DIM, R, 0>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side,
-                       c, T(0), T(0), static_cast<const T*>(nullptr), static_cast<const T*>(nullptr));
+                       c, T(0), T(0), static_cast<const uint8_t*>(nullptr));
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_box_pairs(const T* __restrict__ rbox, int64_t nrb,
+                                                       const T* __restrict__ cbox, int nsp, int dim, T cut2,
+                                                       uint8_t* __restrict__ act) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= nrb * nsp) return;
+  const T* rb = rbox + 6 * (k / nsp);
+  const T* cb = cbox + 6 * (k % nsp);
+  T gap2 = T(0);
+  for (int d = 0; d < dim; ++d) {
+    const T g = Num<T>::fmax(Num<T>::fmax(cb[2 * d] - rb[2 * d + 1], rb[2 * d] - cb[2 * d + 1]), T(0));
+    gap2 = Num<T>::fma(g, g, gap2);
+  }
+  act[k] = gap2 < cut2 ? 1 : 0;
+}
+
+template <typename T>
+void launch_box_pairs(const T* rbox, int64_t nrb, const T* cbox, int nsp, int dim, double cut2, uint8_t* act,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_box_pairs<T>, dim3(ceil_div(nrb * nsp, kBlock)), dim3(kBlock), 0, s, rbox, nrb, cbox, nsp,
+                     dim, T(cut2), act);
 }
 
 template <typename T>
@@ -1734,8 +1786,9 @@ void launch_dense_lse(int dim, int R, const T* xr, int64_t Nr, const T* yc, cons
 
 template <typename T>
 void launch_dense_epi(const T* pm, const T* ps, int nsplit, int64_t Nr, int side, const Ctrl* c,
-                      const EpiArgs<T>& ep, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_epi<T>, dim3(ceil_div(Nr, kBlock)), dim3(kBlock), 0, s, pm, ps, nsplit, Nr, side, c, ep);
+                      const EpiArgs<T>& ep, hipStream_t s, const uint8_t* act) {
+  hipLaunchKernelGGL(k_dense_epi<T>, dim3(ceil_div(Nr, kBlock)), dim3(kBlock), 0, s, pm, ps, nsplit, Nr, side, c, ep,
+                     act);
 }
 
 void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s, int nfields, int par) {
@@ -1855,8 +1908,9 @@ void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w
   template void launch_dense_lse<T>(int, int, const T*, int64_t, const T*, const T*, int64_t, int, int64_t, T*,  \
                                     T*, int, const Ctrl*, const CostArgs&, hipStream_t);                          \
   template void launch_chunk_boxes<T>(const T*, int64_t, int64_t, int, T*, hipStream_t);                        \
+  template void launch_box_pairs<T>(const T*, int64_t, const T*, int, int, double, uint8_t*, hipStream_t);       \
   template void launch_dense_epi<T>(const T*, const T*, int, int64_t, int, const Ctrl*, const EpiArgs<T>&,       \
-                                    hipStream_t);                                                                 \
+                                    hipStream_t, const uint8_t*);                                                 \
   template void launch_bary_combine<T>(const T*, int, int64_t, const BaryW&, double, const DivDev&, const T*,    \
                                        T*, T*, T*, const Ctrl*, int, hipStream_t);                               \
   template int launch_obj_side<T>(const T*, const T*, const T*, const T*, int64_t, double, const DivDev&, T*,    \

@@ -15,10 +15,11 @@ struct CostArgs {
   int kind;
   int pad;
   double cut;
-  // WF dense products: boxes (lo, hi per coordinate: 6 values) of the rows'
-  // blocks of 256 and of the columns' splits, or null (no block-level test)
-  const void* rbox = nullptr;
-  const void* cbox = nullptr;
+  // WF dense products: per (block of 256 rows, column split), 1 when some
+  // pair of the two boxes lies within the cut, 0 when every entry is exactly
+  // zero (the product skips the block, the split merge the partial); null:
+  // every block active
+  const uint8_t* act = nullptr;
 };
 
 // What the last pass of a Gibbs product does with S2 = log2 of the product.
@@ -80,9 +81,14 @@ void launch_dense_lse(int dim, int R, const T* xr, int64_t Nr, const T* yc, cons
 // out[6 b + 2 d], out[6 b + 2 d + 1] = min, max of coordinate d over chunk b
 template <typename T>
 void launch_chunk_boxes(const T* pts, int64_t n, int64_t per, int dim, T* out, hipStream_t s);
+// act[b * nsp + s] = 1 when box b of rbox and box s of cbox are closer than
+// cut (squared distance of the boxes below cut2), else 0
+template <typename T>
+void launch_box_pairs(const T* rbox, int64_t nrb, const T* cbox, int nsp, int dim, double cut2, uint8_t* act,
+                      hipStream_t s);
 template <typename T>
 void launch_dense_epi(const T* pm, const T* ps, int nsplit, int64_t Nr, int side, const Ctrl* c,
-                      const EpiArgs<T>& ep, hipStream_t s);
+                      const EpiArgs<T>& ep, hipStream_t s, const uint8_t* act = nullptr);
 void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s, int nfields, int par);
 void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t s);
 void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s);
