@@ -942,6 +942,41 @@ void launch_dense_tf(int dim, const float* xr, int64_t Nr, const float* yc, cons
 }
 
 // merge the column splits of k_dense_lse, then the epilogue; grid = ceil(Nr/256)
+// log2 of the sum of n split partials (m, s) of row i (2^m s each; split
+// idx(k) for k < n): chunks of 16 splits are loaded together (one memory
+// round trip per chunk; lanes past n read split idx(0)'s partial of the row,
+// in bounds, and drop it), the chunk's maximum taken, and the running sum
+// rescaled once per chunk
+template <typename T, typename Idx>
+__device__ __forceinline__ T merge_splits(const T* __restrict__ pm, const T* __restrict__ ps, int64_t Nr, int64_t i,
+                                          int n, Idx idx) {
+  constexpr int C = 16;
+  T m = Num<T>::ninf(), acc = T(0);
+  for (int k0 = 0; k0 < n; k0 += C) {
+    T a[C], b[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const bool ok = k0 + k < n;
+      const int64_t off = (int64_t)idx(ok ? k0 + k : 0) * Nr + i;
+      const T pa = pm[off], pb = ps[off];
+      a[k] = ok ? pa : Num<T>::ninf();
+      b[k] = ok ? pb : T(0);
+    }
+    T cm = a[0];
+#pragma unroll
+    for (int k = 1; k < C; ++k) cm = Num<T>::fmax(cm, a[k]);
+    const T mn = Num<T>::fmax(m, cm);
+    if (mn != Num<T>::ninf()) {
+      T sum = acc * Num<T>::exp2(m - mn);
+#pragma unroll
+      for (int k = 0; k < C; ++k) sum += b[k] * Num<T>::exp2(a[k] - mn);
+      acc = sum;
+      m = mn;
+    }
+  }
+  return m == Num<T>::ninf() ? m : m + Num<T>::log2(acc);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, const T* __restrict__ ps,
                                                        int nsplit, int64_t Nr, int side,
@@ -979,17 +1014,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, 
     }
   }
   if (valid && nact >= 0) {
-    T mx = Num<T>::ninf();
-#pragma unroll 8
-    for (int k = 0; k < nact; ++k) mx = Num<T>::fmax(mx, pm[lst[k] * Nr + i]);
-    T lse = mx;
-    if (mx != Num<T>::ninf()) {
-      T sum = T(0);
-#pragma unroll 8
-      for (int k = 0; k < nact; ++k) sum += ps[lst[k] * Nr + i] * Num<T>::exp2(pm[lst[k] * Nr + i] - mx);
-      lse = mx + Num<T>::log2(sum);
-    }
-    epi_elem<T>(i, lse, c, side, ep, ra);
+    epi_elem<T>(i, merge_splits<T>(pm, ps, Nr, i, nact, [&](int k) { return lst[k]; }), c, side, ep, ra);
   } else if (valid && act != nullptr) {
     const uint8_t* a = act + (int64_t)blockIdx.x * nsplit;
     T mx = Num<T>::ninf();
@@ -1004,19 +1029,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, 
     }
     epi_elem<T>(i, lse, c, side, ep, ra);
   } else if (valid) {
-    // two passes over the splits with independent loads: the largest
-    // maximum, then the sum of the partial sums scaled to it
-    T mx = Num<T>::ninf();
-#pragma unroll 8
-    for (int s = 0; s < nsplit; ++s) mx = Num<T>::fmax(mx, pm[s * Nr + i]);
-    T lse = mx;
-    if (mx != Num<T>::ninf()) {
-      T sum = T(0);
-#pragma unroll 8
-      for (int s = 0; s < nsplit; ++s) sum += ps[s * Nr + i] * Num<T>::exp2(pm[s * Nr + i] - mx);
-      lse = mx + Num<T>::log2(sum);
-    }
-    epi_elem<T>(i, lse, c, side, ep, ra);
+    epi_elem<T>(i, merge_splits<T>(pm, ps, Nr, i, nsplit, [](int k) { return k; }), c, side, ep, ra);
   }
   epi_finish<T>(ep, ra, blockIdx.x);
 }
