@@ -115,6 +115,36 @@ def test_wf_points_order_and_isolated_points(dtype, tolr):
 
 
 @pytest.mark.parametrize("dtype,tolr", [(torch.float64, 1e-11), (torch.float32, 1e-5)])
+def test_wf_points_block_flags_many_splits(dtype, tolr):
+    """The (row block, column split) flags: 600 clustered rows in [0, 0.6]^2
+    plus 300 rows in [0.9, 1]^2 beyond the cut (0.3) of every column (the
+    last block of 256 rows has no partner at all: +inf potentials), against
+    40000 clustered columns in [0, 0.6]^2.  The X products run 1250 splits
+    of 32 columns, past the merge's LDS list (its per-split flag loop), the
+    Y products 29 splits (the list)."""
+    npd = npd_of(dtype)
+    rng = np.random.default_rng(17)
+    cx = synth.clusters_sorted(8, N=600, M=40000, d=2)
+    far = 0.9 + 0.1 * rng.random((300, 2))
+    x = rounded(np.vstack([0.6 * cx.x, far]), npd)
+    y = rounded(0.6 * cx.y, npd)
+    p = rounded(np.r_[cx.p, 0.5 + rng.random(300)], npd)
+    q = rounded(cx.q, npd)
+    dx, dy = rounded(np.full(900, 1.0 / 900), npd), rounded(np.full(40000, 1.0 / 40000), npd)
+    cut, eps = 0.3, 0.02
+    F = U.KL(1.0)
+    say("case wf block flags", dtype)
+    prob = U.points_problem(T(x, dtype), T(y, dtype), T(p, dtype), T(q, dtype), T(dx, dtype), T(dy, dtype), F, F,
+                            cost=U.WF(cut))
+    u, v, _ = U.solve(prob, eps, tol=0.0, max_iter=6)
+    g = O.PointsGeom(x, y, "wf", cut)
+    ref = O.solve(g, np.log(p), np.log(q), np.log(dx), np.log(dy), O.KL(1.0), O.KL(1.0), eps, tol=0.0, max_iter=6)
+    assert np.isposinf(ref["u"][768:]).all()
+    assert pot_rel_err(*split_inf(u.cpu(), ref["u"]), eps) < tolr
+    assert pot_rel_err(*split_inf(v.cpu(), ref["v"]), eps) < tolr
+
+
+@pytest.mark.parametrize("dtype,tolr", [(torch.float64, 1e-11), (torch.float32, 1e-5)])
 @pytest.mark.parametrize("n,cut", [(700, 0.05), (700, math.pi / 2), (300, 0.3)])
 def test_wf_grid_1d(dtype, tolr, n, cut):
     """1-D grid passes with the WF cost: band of ceil(cut / h) cells (the
