@@ -6,7 +6,8 @@ every matrix product (weights and activations) are rounded to BF16 (round to
 nearest even) exactly where the GPU network rounds them, and the backward
 pass treats the rounding as the identity (straight-through), which is what
 the GPU gradient computes.  Parameter layout: W1 [width x n_in], b1, W2, b2,
-W3, b3, W4 [n_out x width], b4.
+W3, b3, W4 [n_out x width], b4.  The optimiser is Adam (`adam_step`), in
+FP64.
 """
 import numpy as np
 
@@ -72,3 +73,17 @@ def loss_and_grad(theta, x, t, n_in, width, n_out, in_scale=1.0, in_shift=0.0, b
         flat.append(gW[l].reshape(-1))
         flat.append(gb[l])
     return loss, np.concatenate(flat)
+
+
+def adam_step(w, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One step of Adam (Kingma & Ba, "Adam: a method for stochastic
+    optimization", ICLR 2015, Algorithm 1), in FP64: the moment estimates
+    m <- beta1 m + (1 - beta1) g and v <- beta2 v + (1 - beta2) g^2, their
+    bias corrections m / (1 - beta1^t), v / (1 - beta2^t) at step t >= 1, and
+    w <- w - lr mhat / (sqrt(vhat) + eps).  Returns (w, m, v) as new arrays."""
+    w, g, m, v = (np.asarray(a, np.float64) for a in (w, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return w - lr * mhat / (np.sqrt(vhat) + eps), m, v

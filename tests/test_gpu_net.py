@@ -10,6 +10,7 @@ import torch
 
 from oracle import net_oracle as NO
 from oracle import uot_oracle as O
+from tests import net_cases
 from tests.helpers import pot_rel_err, rounded
 
 pytestmark = pytest.mark.gpu
@@ -43,30 +44,77 @@ def test_gemm_bf16_layouts(ta, tb, M, N, K):
     assert err < 2e-6, err
 
 
-def test_net_gradient_matches_reference():
-    rng = np.random.default_rng(4)
-    n_in, width, n_out, batch = 64, 32, 48, 20
-    net = U.WarmStartNet(n_in, width, n_out, DEV, seed=3, in_scale=0.5, in_shift=0.1)
-    x = rng.standard_normal((batch, n_in)).astype(np.float32)
-    t = rng.standard_normal((batch, n_out)).astype(np.float32) * 0.3
-    say("case net grad")
-    g, loss = net.grad(torch.tensor(x, device=DEV), torch.tensor(t, device=DEV))
-    theta = net.master.cpu().numpy().astype(np.float64)
-    lref, gref = NO.loss_and_grad(theta, x, t, n_in, width, n_out, 0.5, 0.1, bf16=True)
-    assert loss == pytest.approx(lref, rel=1e-4)
-    g = g.cpu().numpy()
-    # per parameter block: relative error in norm (BF16 rounding of gradients
-    # that differ in the last FP32 bits can flip)
-    sizes = [n_in * width, width, width * width, width, width * width, width, width * n_out, n_out]
-    o = 0
-    for s in sizes:
-        a, b = g[o:o + s], gref[o:o + s]
-        assert np.linalg.norm(a - b) <= 2e-2 * np.linalg.norm(b) + 1e-7, (o, s)
-        o += s
-    # inference agrees with the reference forward
-    y = net.infer(torch.tensor(x, device=DEV)).cpu().numpy()
-    yref, _ = NO.forward(theta, x, n_in, width, n_out, 0.5, 0.1, bf16=True)
-    assert np.max(np.abs(y - yref)) < 1e-3 * np.max(np.abs(yref))
+PROD = (8192, 256, 4096, 256)   # n_in, width, n_out, batch of the warm-start network
+
+
+@pytest.mark.parametrize("ta,tb,M,N,K", [
+    (False, True, 256, 256, 8192),    # forward layer 1 (split K)
+    (False, True, 256, 4096, 256),    # forward layer 4
+    (True, False, 256, 8192, 256),    # weight gradient of layer 1
+    (True, False, 4096, 256, 256),    # weight gradient of layer 4
+    (False, False, 256, 256, 4096),   # input gradient of layer 4 (split K)
+])
+def test_gemm_bf16_production_products(ta, tb, M, N, K):
+    """The network's five product shapes on generic data, element by element
+    against the FP64 product of the same BF16 values.  BF16 x BF16 products
+    are exact in FP32, so the only error is FP32 summation of K terms, which
+    in any order is at most K 2^-24 sum_k |a_mk b_kn| (plus second order)."""
+    say("case gemm production", ta, tb, M, N, K)
+    rng = np.random.default_rng(M + 3 * N + 7 * K)
+    A = rng.standard_normal((K, M) if ta else (M, K)).astype(np.float32)
+    B = rng.standard_normal((N, K) if tb else (K, N)).astype(np.float32)
+    C = U.gemm_bf16(U.bf16_bits(torch.tensor(A, device=DEV)).contiguous(),
+                    U.bf16_bits(torch.tensor(B, device=DEV)).contiguous(), M, N, K, ta=ta, tb=tb).cpu().numpy()
+    Aq, Bq = NO.bf16_round(A), NO.bf16_round(B)
+    Aq, Bq = (Aq.T if ta else Aq), (Bq.T if tb else Bq)
+    ref = Aq @ Bq
+    bound = 1.01 * K * 2.0 ** -24 * (np.abs(Aq) @ np.abs(Bq))
+    assert np.all(np.abs(C - ref) <= bound)
+
+
+def test_net_production_shape_bit_exact_and_adam():
+    """The warm-start network at its production shape (8192 -> 256 -> 256 ->
+    256 -> 4096, batch 256; layer 1 and the layer-4 input gradient run split
+    K with FP32 atomics) on integer-valued sparse weights, integer inputs and
+    targets one to three units off the output (tests/net_cases.py).  Every
+    sum is then exact in FP32 in any order and every BF16 rounding acts on
+    exact values, so the forward output, the loss and the whole gradient must
+    equal the FP64 reference bit for bit.  One Adam step (the same batch)
+    must then match the reference Adam step element by element: FP32
+    evaluation of the update formula, with the kernel's FP32 constants, within
+    a few units in the last place."""
+    n_in, width, n_out, batch = PROD
+    theta, x, t = net_cases.dyadic_net(11, n_in, width, n_out, batch)
+    fwd, bwd = net_cases.exact_margins(theta, x, t, n_in, width, n_out)
+    assert fwd < 2 ** 24 and bwd < 2 ** 24
+    net = U.WarmStartNet(n_in, width, n_out, DEV, params=theta.astype(np.float32), in_scale=1.0, in_shift=0.0)
+    xt = torch.tensor(x, dtype=torch.float32, device=DEV)
+    tt = torch.tensor(t, dtype=torch.float32, device=DEV)
+    say("case net production forward")
+    y = net.infer(xt).cpu().numpy().astype(np.float64)
+    yref, _ = NO.forward(theta, x, n_in, width, n_out, bf16=True)
+    assert np.array_equal(y, yref), np.max(np.abs(y - yref))
+    say("case net production gradient")
+    g, loss = net.grad(xt, tt)
+    lref, gref = NO.loss_and_grad(theta, x, t, n_in, width, n_out, bf16=True)
+    g = g.cpu().numpy().astype(np.float64)
+    assert loss == lref
+    bad = np.flatnonzero(g != gref)
+    assert bad.size == 0, (bad.size, bad[:10])
+    say("case net production adam")
+    lr = 1e-3
+    net.train_step(xt, tt, lr)
+    f = lambda c: float(np.float32(c))
+    wref, mref, vref = NO.adam_step(theta, gref, np.zeros_like(theta), np.zeros_like(theta), 1, f(lr),
+                                    beta1=f(0.9), beta2=f(0.999), eps=f(1e-8))
+    w = net.master.cpu().numpy().astype(np.float64)
+    step = np.abs(wref - theta)
+    assert np.all(np.abs(w - wref) <= 2.0 ** -24 * np.abs(wref) + 2.0 ** -21 * step)
+    assert np.array_equal(w == theta, gref == 0)
+    np.testing.assert_allclose(net.m.cpu().numpy(), mref, rtol=2.0 ** -21, atol=0)
+    np.testing.assert_allclose(net.v.cpu().numpy(), vref, rtol=2.0 ** -20, atol=0)
+    wb = NO.bf16_round(w.astype(np.float32)).astype(np.float32).view(np.uint32) >> 16
+    assert np.array_equal(net.wbf16.cpu().numpy().view(np.uint16), wb.astype(np.uint16)), "BF16 copy of the weights"
 
 
 def test_net_training_reduces_loss():
