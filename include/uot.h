@@ -274,6 +274,23 @@ int uot_half_step(uot_ctx *ctx, const uot_problem *pb, double eps, int side,
                   const void *pot_in, void *pot_io, void *lse_out,
                   double *residual, void *ws, size_t ws_bytes);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): uot_half_step with
+ * the library's own scratch memory in place of the caller's workspace.
+ * Arguments, layouts and results are those of uot_half_step; the caller still
+ * passes pot_in, pot_io and lse_out.  The call allocates nothing: the scratch
+ * is one static array of UOT_SCRATCH_BYTES per GPU, held from the library's
+ * load until the process ends, and its address is looked up once per device
+ * by uot_create.  A problem whose half-step workspace (at most
+ * uot_workspace_size) exceeds UOT_SCRATCH_BYTES returns UOT_E_WORKSPACE before
+ * anything is launched.  Every call on a GPU shares that GPU's array, which
+ * keeps the last call's contents; no call reads a scratch byte it has not
+ * written, so nothing needs clearing, but calls that overlap on one GPU
+ * (several contexts or streams at once) race: the caller serialises them. */
+#define UOT_SCRATCH_BYTES (32u << 20)
+int uot_half_step_noalloc(uot_ctx *ctx, const uot_problem *pb, double eps, int side,
+                          const void *pot_in, void *pot_io, void *lse_out, double *residual);
+
 /* Objective values, marginals (pi1: N, pi2: M, optional) at (u, v). */
 int uot_objective(uot_ctx *ctx, const uot_problem *pb, double eps,
                   const void *u, const void *v, void *pi1, void *pi2,

@@ -11,6 +11,7 @@
 #include <type_traits>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -30,9 +31,38 @@ int fail(int code, const std::string& msg) {
 }
 }  // namespace uot
 
+// Scratch memory of uot_half_step_noalloc: one zero-initialised array in the
+// code object, so each GPU the library runs on holds its own copy from module
+// load until the process ends, and that entry point allocates nothing.  On the
+// host `scratch` is only a stand-in for the symbol: kernels receive the device
+// address that hipGetSymbolAddress returns for the current device, looked up
+// once per device by uot_create.
+static __device__ __align__(256) char scratch[UOT_SCRATCH_BYTES];
+
 namespace {
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on `dev` (the current device), looked up on the
+// first call for that device and kept
+hipError_t scratch_address(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 // Per-launch HIP-event timing of the kernels of a solve (when requested): every
 // launch enqueued through timed() is bracketed by two events on the library
@@ -1862,6 +1892,9 @@ int uot_create(uot_ctx** out, void* stream) {
   if (!c) return fail(UOT_E_INVALID, "out of host memory");
   c->user = static_cast<hipStream_t>(stream);
   hipError_t e = hipGetDevice(&c->device);
+  // the no-allocation entry point's scratch on this device; a failure here
+  // only disables that entry point, which reports it
+  if (e == hipSuccess) c->scratch_err = scratch_address(c->device, &c->scratch);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
@@ -2001,6 +2034,23 @@ int uot_half_step(uot_ctx* ctx, const uot_problem* pb, double eps, int side, con
                               static_cast<float*>(lse_out), residual, static_cast<char*>(ws), wsb);
   return half_step_t<double>(ctx, pb, eps, side, static_cast<const double*>(pot_in), static_cast<double*>(pot_io),
                              static_cast<double*>(lse_out), residual, static_cast<char*>(ws), wsb);
+}
+
+int uot_half_step_noalloc(uot_ctx* ctx, const uot_problem* pb, double eps, int side, const void* pot_in,
+                          void* pot_io, void* lse_out, double* residual) {
+  if (!ctx) return fail(UOT_E_INVALID, "ctx is required");
+  int rc = validate_problem(pb);
+  if (rc) return rc;
+  if (!ctx->scratch)
+    return fail(UOT_E_HIP, std::string("no scratch address on this device: ") + hipGetErrorString(ctx->scratch_err));
+  // the plan uot_half_step makes for this problem; its workspace must fit
+  Plan P;
+  if ((rc = make_plan(P, pb->dtype, pb->geom, 1, 1, 0, eps))) return rc;
+  if (P.total > (size_t)UOT_SCRATCH_BYTES)
+    return fail(UOT_E_WORKSPACE, "this half-step needs " + std::to_string(P.total) +
+                                     " bytes of scratch, more than the UOT_SCRATCH_BYTES = " +
+                                     std::to_string((size_t)UOT_SCRATCH_BYTES) + " the library holds per GPU");
+  return uot_half_step(ctx, pb, eps, side, pot_in, pot_io, lse_out, residual, ctx->scratch, UOT_SCRATCH_BYTES);
 }
 
 int uot_objective(uot_ctx* ctx, const uot_problem* pb, double eps, const void* u, const void* v, void* pi1, void* pi2,

@@ -16,6 +16,8 @@ struct uot_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   uot::Ctrl* pinned = nullptr;  // host mirror of the control block
   int device = 0;
+  void* scratch = nullptr;                 // device address of the library's scratch array on `device`
+  hipError_t scratch_err = hipSuccess;     // why it is missing, if it is
   std::map<std::string, std::pair<int, int>> batch_tuned;   // batch signature -> (R, blocks per CU)
   std::map<std::string, int> dense_tuned;                    // matrix-core product shape -> block target
 };

@@ -109,6 +109,7 @@ def lib():
         "uot_solve": (c_i32, [c_vp, P(UotProblem), P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t, P(UotResult)]),
         "uot_half_step": (c_i32, [c_vp, P(UotProblem), c_dbl, c_i32, c_vp, c_vp, c_vp, P(c_dbl), c_vp,
                                   ctypes.c_size_t]),
+        "uot_half_step_noalloc": (c_i32, [c_vp, P(UotProblem), c_dbl, c_i32, c_vp, c_vp, c_vp, P(c_dbl)]),
         "uot_objective": (c_i32, [c_vp, P(UotProblem), c_dbl, c_vp, c_vp, c_vp, c_vp, P(UotObjectiveValues), c_vp,
                                   ctypes.c_size_t]),
         "uot_bary_workspace_size": (c_i32, [P(UotBaryProblem), P(ctypes.c_size_t)]),
@@ -405,6 +406,21 @@ def half_step(prob: Problem, eps, side, pot_in, pot_old, ctx: Optional[Context] 
     ws = prob.workspace()
     _check(lib().uot_half_step(ctx.handle, ctypes.byref(prob.c), float(eps), int(side), _ptr(pot_in), _ptr(out),
                                _ptr(lse), ctypes.byref(r), _ptr(ws), ws.numel()), "uot_half_step", False)
+    return out, lse, r.value
+
+
+def half_step_noalloc(prob: Problem, eps, side, pot_in, pot_old, ctx: Optional[Context] = None):
+    """half_step on the library's static scratch memory (uot_half_step_noalloc):
+    no workspace is allocated.  Same arguments and results as half_step."""
+    ctx = ctx or default_context()
+    n_out = prob.N if side == 0 else prob.M
+    n_in = prob.M if side == 0 else prob.N
+    _dev(pot_in, prob.dtype, n_in, "pot_in")
+    out = _dev(pot_old, prob.dtype, n_out, "pot_old").clone()
+    lse = torch.empty(n_out, dtype=prob.dtype, device=out.device)
+    r = c_dbl()
+    _check(lib().uot_half_step_noalloc(ctx.handle, ctypes.byref(prob.c), float(eps), int(side), _ptr(pot_in),
+                                       _ptr(out), _ptr(lse), ctypes.byref(r)), "uot_half_step_noalloc", False)
     return out, lse, r.value
 
 
