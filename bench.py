@@ -1,18 +1,25 @@
 #!/usr/bin/env python
 """Benchmark: Sinkhorn iterations per second and time to residual 1e-6 of the
-generalized scaling iteration on one MI355X.
+generalized scaling iteration on one MI355X, warm+batched against plain.
 
-Workload (one "step" = one pass of the whole hot path over one input pair):
-  2-D grid unbalanced OT between two 256 x 256 densities on [0,1]^2, each a
-  sum of 5 random Gaussian blobs plus a 1e-6 floor, masses U[0.5, 2]
-  (seeded synthetic stand-ins for the paper's 2-D experiment images);
-  separable Gaussian kernel applied as log-domain 1-D passes; eps annealed
-  1e-1 -> 1e-3 in 10 stages of 100 iterations, then iterated to residual
-  1e-6; solved once with KL (lambda = 0.1) and once with TV (lambda = 0.05)
-  penalties, each followed by the FP64 objective / gap reduction.  FP32.
+Headline workload (one "step" = one pass of the whole hot path over one
+batch): 4096 independent unbalanced OT problems between point clouds of
+uneven size (N, M log-uniform on [64, 4096], uniform points in [0,1]^2,
+densities U[0.1, 1] w.r.t. dx = 1/N, squared Euclidean cost, KL lambda = 1
+on both marginals, eps = 5e-3, FP32; seeded synthetic inputs).  A step is
+the learned warm start of every problem (features from batched Gibbs
+products, the network, v^(0)) followed by one batched solve of all 4096
+problems to residual 1e-6 (persistent launches over an atomic work cursor,
+captured in hipGraph chunks).  Plain = the cold single-problem solver, one
+problem after another (a stratified sample, extrapolated).
 
-Prints ONE JSON line.  value = total iterations / timed seconds (both solves
-of every timed step); ms_per_step = time to residual 1e-6 for the KL + TV pair.
+Prints ONE JSON line.  value = problems brought to residual 1e-6 per second
+by the warm+batched form (whole job); ms_per_step = its time to residual 1e-6
+for the whole batch.  Beside it: Sinkhorn iterations per second, the plain
+and cold-batched times and speedups, the roofline of the dominant kernel
+(the batched matrix-core product), the oracle's CPU baseline on the same
+workload, and the other workloads (the 2-D grid, dense clouds, the
+barycentre warm start, training GEMMs, extensions).
 """
 import argparse
 import json
@@ -38,102 +45,237 @@ def exp_peak():
     return N_CU * 64 * PEAK_CLOCK_HZ / 2.0
 
 
-def cpu_baseline(prob_np, budget_s=15.0):
-    """The FP64 oracle as it stands, on the same workload (KL solve from a cold
-    start at the first eps stage), for a bounded number of iterations."""
+RAGGED_B, RAGGED_EPS = 4096, 5e-3
+
+
+def _oracle_iter_seconds(prob, eps, iters):
+    """Seconds per iteration of the FP64 oracle on one problem (cold start)."""
     import numpy as np
     from oracle import uot_oracle as O
-    G = O.GridGeom(prob_np.shape, prob_np.h)
-    d = np.full(prob_np.size, prob_np.h[0] * prob_np.h[1])
-    lp, lq, ld = np.log(prob_np.p), np.log(prob_np.q), np.log(d)
-    F = O.KL(PENALTIES[0][1])
-    O.solve(G, lp, lq, ld, ld, F, F, EPS0, tol=0.0, max_iter=1)      # warm caches
-    it = 0
+    g = O.PointsGeom(prob.x, prob.y)
+    F = O.KL(1.0)
+    args = (g, np.log(prob.p), np.log(prob.q), np.log(prob.dx), np.log(prob.dy), F, F, eps)
+    t = time.perf_counter()
+    O.solve(*args, tol=0.0, max_iter=iters)
+    return (time.perf_counter() - t) / iters
+
+
+_CPU_PROBS = None      # the sampled problems, inherited by the forked workers
+
+
+def _oracle_worker(job):
+    idxs, eps, iters = job
+    return [(k, _oracle_iter_seconds(_CPU_PROBS[k], eps, iters)) for k in idxs]
+
+
+def cpu_sample(seed=0, n_sample=64, iters=20):
+    """The FP64 oracle as it stands on a stratified sample of the ragged
+    workload: every (B / n_sample)-th problem in order of N M, `iters`
+    iterations each, timed on one thread and then on every core the process
+    may run on (os.sched_getaffinity; one worker process per core, the
+    problems split between them).  Runs before the GPU is touched (the worker
+    processes are forked).  Returns per-problem seconds per iteration and the
+    wall times."""
+    import multiprocessing as mp
+    import numpy as np
+    from paper_1607_05816_amd import synth
+    sizes = synth.ragged_sizes(seed, B=RAGGED_B)
+    order = np.argsort(np.asarray(sizes[0], float) * np.asarray(sizes[1], float), kind="stable")
+    step = len(order) // n_sample
+    idx = [int(order[step // 2 + k * step]) for k in range(n_sample)]
+    global _CPU_PROBS
+    probs = synth.ragged_batch(seed, B=RAGGED_B)
+    _CPU_PROBS = {k: probs[k] for k in idx}
+    _oracle_iter_seconds(probs[idx[0]], RAGGED_EPS, 2)                      # warm caches
+    t = time.perf_counter()
+    one = {k: _oracle_iter_seconds(probs[k], RAGGED_EPS, iters) for k in idx}
+    wall1 = time.perf_counter() - t
+    cores = len(os.sched_getaffinity(0))
+    workers = max(1, min(cores, n_sample))
+    # one job per problem, largest first, handed out as workers free up
+    jobs = [([k], RAGGED_EPS, iters) for k in sorted(idx, key=lambda k: -one[k])]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_worker, [([idx[0]], RAGGED_EPS, 1)] * workers)   # start-up
+        t = time.perf_counter()
+        par = dict(kv for part in pool.imap_unordered(_oracle_worker, jobs, chunksize=1) for kv in part)
+        wallN = time.perf_counter() - t
+    return dict(idx=idx, order=order, step=step, one=one, par=par, wall1=wall1, wallN=wallN, cores=cores,
+                workers=workers, iters=iters)
+
+
+def cpu_baseline_ragged(cs, iters_cold, Ns, Ms):
+    """Extrapolate the oracle's sample to the whole workload: every problem
+    takes the per-iteration time of the sampled problem of its size stratum
+    (the same stratum of N M order), times its own iteration count to
+    residual 1e-6 (the GPU's count for the same cold iteration).  One thread:
+    the sum of those times; all cores: that sum scaled by the sample's
+    measured parallel speed-up."""
+    import numpy as np
+    order, step = cs["order"], cs["step"]
+    strat = {}
+    for rank, b in enumerate(order):
+        strat[int(b)] = cs["idx"][min(rank // step, len(cs["idx"]) - 1)]
+    t1 = sum(cs["one"][strat[b]] * float(iters_cold[b]) for b in range(len(order)))
+    sample_work = sum(cs["one"][k] * cs["iters"] for k in cs["idx"])
+    speedup = sample_work / cs["wallN"]
+    tN = t1 / speedup
+    return {"value": len(order) / tN, "unit": "problems/s to residual 1e-6", "cores": cs["workers"], "kind": "oracle",
+            "sample": "FP64 numpy oracle, %d problems of the 4096 (one per N*M stratum, every %d-th in size order), "
+                      "%d iterations each, %.1f s on one thread and %.1f s on %d worker processes (affinity %d "
+                      "cores); extrapolated by the GPU's cold iteration count of every problem"
+                      % (len(cs["idx"]), step, cs["iters"], cs["wall1"], cs["wallN"], cs["workers"], cs["cores"]),
+            "one_thread": {"value": len(order) / t1, "seconds_to_residual": t1},
+            "seconds_to_residual": tN, "parallel_speedup_of_sample": speedup}
+
+
+def ragged_headline(U, ctx, dev, np, torch, steps, warmup):
+    """The headline: warm start + batched solve of the 4096-problem ragged
+    workload to residual 1e-6, against the cold batched solve and the plain
+    cold single-problem solver."""
+    from paper_1607_05816_amd import cloud_warmstart as CW
+    if not os.path.exists(CW.WEIGHTS):
+        raise RuntimeError("the trained cloud warm start is missing: %s" % CW.WEIGHTS)
+    cw = CW.CloudWarmStart.load(CW.WEIGHTS, dev)
+    probs = CW.ragged(0, B=RAGGED_B)
+    Ns = np.array([p.x.shape[0] for p in probs], float)
+    Ms = np.array([p.y.shape[0] for p in probs], float)
+    pairs = Ns * Ms
+    bp = CW.batch_problem(probs, dev)
+    bp.workspace()
+
+    def step():
+        v0 = cw.v0(bp, ctx=ctx)
+        return CW.solve(bp, v0=v0, ctx=ctx)[2]
+
+    CW.solve(bp, ctx=ctx)                # the batch signature's one-time product tuning
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    v = None
-    while time.perf_counter() - t0 < budget_s or it < 3:
-        s = O.solve(G, lp, lq, ld, ld, F, F, EPS0, tol=0.0, max_iter=1, v0=v)
-        v = s["v"]
-        it += 1
+    infos = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dict(value=it / dt, unit="iters/s", cores=1, kind="oracle",
-                sample="%d iterations of the KL solve on the 256x256 workload at eps=1e-1 "
-                       "(numpy FP64, one thread), %.1f s" % (it, dt))
-
-
-def warm_batched(U, ctx, dev, np, torch):
-    """Warm+batched forms against the plain cold single-problem iteration:
-    (a) ragged batch of 4096 point-cloud problems (N, M log-uniform on
-        [64, 4096], uniform points in [0,1]^2, KL 1, eps 5e-3, tol 1e-6) in
-        one persistent launch per half-step vs plain solves of a 16-problem
-        sample (extrapolated);
-    (b) unbalanced barycentre of 8 blob images at 128 x 128 (KL 0.5, eps 2e-3,
-        tol 1e-6): plain = cold start with eps-scaling, warm = v^(0) from the
-        trained network (no annealing)."""
-    from paper_1607_05816_amd import synth, warmstart as W
-    from paper_1607_05816_amd.train_warmstart import load_weights
-    out = {}
-    probs = synth.ragged_batch(0, B=4096)
-    Ns = [p.x.shape[0] for p in probs]
-    Ms = [p.y.shape[0] for p in probs]
-    cat = lambda f: torch.tensor(np.concatenate([f(p) for p in probs]).astype(np.float32), device=dev)
-    F = U.KL(1.0)
-    bp = U.BatchProblem(Ns, Ms, cat(lambda p: p.x), cat(lambda p: p.y), cat(lambda p: p.p), cat(lambda p: p.q),
-                        cat(lambda p: p.dx), cat(lambda p: p.dy), F, F)
-    U.solve_batched(bp, 5e-3, tol=1e-6, max_iter=20000, check_every=50, ctx=ctx)       # tunes, warms
+    warm = infos[-1]
+    it_warm = warm["iters"].astype(float)
+    # warm start alone (features, network, v0)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, _, info = U.solve_batched(bp, 5e-3, tol=1e-6, max_iter=20000, check_every=50, ctx=ctx)
+    t = time.perf_counter()
+    for _ in range(3):
+        cw.v0(bp, ctx=ctx)
     torch.cuda.synchronize()
-    bs = time.perf_counter() - t0
-    it = info["iters"]
-    pairs = np.array(Ns, float) * np.array(Ms, float)
-    rng = np.random.default_rng(1)
-    idx = rng.choice(len(probs), 16, replace=False)
-    plain = 0.0
+    ws_ms = (time.perf_counter() - t) / 3 * 1e3
+    # cold batched
+    cold_s = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, cold = CW.solve(bp, ctx=ctx)
+        torch.cuda.synchronize()
+        cold_s.append(time.perf_counter() - t)
+    it_cold = cold["iters"].astype(float)
+    # plain: cold single-problem solves of a stratified sample (one per
+    # N*M stratum), each after an untimed first solve of its shape (the
+    # product tuning, kept out as the batch's tuning is)
+    order = np.argsort(pairs, kind="stable")
+    n_plain = 64
+    stp = len(order) // n_plain
+    sample = [int(order[stp // 2 + k * stp]) for k in range(n_plain)]
     T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
-    for k in idx:
+    F = U.KL(1.0)
+    plain = []
+    for k in sample:
         p = probs[k]
-        pb = U.points_problem(T(p.x), T(p.y), T(p.p), T(p.q), T(p.dx), T(p.dy), F, F)
+        pb = U.points_problem(T(p.x), T(p.y), T(p.p), T(p.q), T(p.dx), T(p.dy), F, F, layout="nd")
         pb.workspace()
-        # untimed first solve: a shape's one-time product tuning stays out of
-        # the plain time, as the batch's tuning stays out of the batched one
-        U.solve(pb, 5e-3, tol=1e-6, max_iter=20000, check_every=50, ctx=ctx)
+        U.solve(pb, RAGGED_EPS, tol=1e-6, max_iter=20000, check_every=50, ctx=ctx)
         torch.cuda.synchronize()
         a = time.perf_counter()
-        U.solve(pb, 5e-3, tol=1e-6, max_iter=20000, check_every=50, ctx=ctx)
+        _, _, pi = U.solve(pb, RAGGED_EPS, tol=1e-6, max_iter=20000, check_every=50, ctx=ctx)
         torch.cuda.synchronize()
-        plain += time.perf_counter() - a
-    plain_per = plain / len(idx)
-    out["ragged_batch_4096"] = {
-        "converged": int(info["n_converged"]), "problems": len(probs), "seconds": bs,
-        "problems_per_s": len(probs) / bs, "problem_iters_per_s": float(it.sum()) / bs,
-        "pair_evals_per_s": float((pairs * it).sum()) * 2 / bs,
-        "pair_evals_frac_of_exp_peak": float((pairs * it).sum()) * 2 / bs / exp_peak(),
-        "latency_ms_p50": float(np.percentile(info["latency_ms"], 50)),
-        "latency_ms_p99": float(np.percentile(info["latency_ms"], 99)),
-        "tile_rows": info["tile_rows"], "blocks_per_cu": info["blocks_per_cu"],
-        "product": {1: "direct", 4: "mfma_bf16x3"}.get(int(info["product"]), str(info["product"])),
-        "plain_ms_per_problem_sample16": plain_per * 1e3,
-        "speedup_vs_plain": plain_per * len(probs) / bs}
+        plain.append(time.perf_counter() - a)
+    plain_s = float(np.mean(plain)) * len(probs)
+    # roofline of the batched product: one warm solve with every launch
+    # between HIP events on the library stream (no graphs)
+    v0 = cw.v0(bp, ctx=ctx)
+    _, _, tk = CW.solve(bp, v0=v0, ctx=ctx, time_kernels=True)
+    it_tk = tk["iters"].astype(float)
+    launches = tk["kernel_launches"][0] + tk["kernel_launches"][1]
+    kms = tk["kernel_ms"][0] + tk["kernel_ms"][1]
+    work = 2.0 * float((pairs * it_tk).sum())          # pair evaluations, both half-steps
+    avg_ms = kms / launches
+    peak = exp_peak()
+    kname = {1: "k_batch_lse", 4: "k_batch_mf"}.get(int(tk["product"]), str(tk["product"]))
+    roof = {"bound": "alu", "kernel": kname, "kernel_avg_ms": avg_ms, "launches": int(launches),
+            "work_per_launch": work / launches, "work_unit": "exp (one per pair; both half-steps)",
+            "achieved": work / launches / (avg_ms * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "Texp/s",
+            "frac": work / launches / (avg_ms * 1e-3) / peak, "traffic": None,
+            "product_ms_total": kms, "control_ms_total": tk["kernel_ms"][2],
+            "note": "average over every product launch of a warm solve (converged problems' items exit at once)"}
+    tr = batch_traffic(kname, int(tk["tile_rows"]))
+    if tr is not None:
+        roof["traffic"] = float(sum(tr))
+        roof["traffic_read_written"] = list(tr)
+    return {
+        "value": len(probs) * steps / dt,
+        "ms_per_step": dt / steps * 1e3,
+        "warm": {"seconds": dt / steps, "iters_mean": float(it_warm.mean()), "iters_total": int(it_warm.sum()),
+                 "converged": int(warm["n_converged"]), "warm_start_ms": ws_ms,
+                 "problem_iters_per_s": float(it_warm.sum()) / (dt / steps),
+                 "pair_evals_per_s": 2.0 * float((pairs * it_warm).sum()) / (dt / steps),
+                 "latency_ms_p50": float(np.percentile(warm["latency_ms"], 50)),
+                 "latency_ms_p99": float(np.percentile(warm["latency_ms"], 99)),
+                 "product": kname, "tile_rows": int(warm["tile_rows"]), "blocks_per_cu": int(warm["blocks_per_cu"])},
+        "cold_batched": {"seconds": min(cold_s), "iters_mean": float(it_cold.mean()),
+                         "iters_total": int(it_cold.sum()), "converged": int(cold["n_converged"]),
+                         "problem_iters_per_s": float(it_cold.sum()) / min(cold_s)},
+        "plain": {"seconds_extrapolated": plain_s, "sample": n_plain, "ms_per_problem_mean": float(np.mean(plain)) * 1e3,
+                  "kind": "cold single-problem solves, one after another"},
+        "speedup_vs_plain": plain_s / (dt / steps),
+        "speedup_batched_cold_vs_plain": plain_s / min(cold_s),
+        "speedup_warm_vs_cold_batched": min(cold_s) / (dt / steps),
+        "iters_ratio_cold_over_warm": float(it_cold.sum() / it_warm.sum()),
+        "roofline": roof,
+        "iters_cold": it_cold,
+    }
+
+
+def warm_bary(U, ctx, dev, np, torch, seeds=(0, 1)):
+    """The barycentre configuration: 8 blob images at 128 x 128, KL 0.5 on
+    both sides, eps 2e-3, residual 1e-6.  Starts compared on the same
+    schedule where they can be: cold with the paper's eps-scaling, cold
+    without annealing (v^(0) = 0), the local estimate (no network, no
+    annealing) and the network (no annealing); iterations and time to
+    residual 1e-6 per seed, best of two runs."""
+    from paper_1607_05816_amd import synth, warmstart as W
+    from paper_1607_05816_amd.train_warmstart import load_weights
     net = load_weights(os.path.join(ROOT, "paper_1607_05816_amd", "data", "warmstart_mlp64.npz"), dev)
-    pr = synth.bary_blobs(0, n_marg=8, n=128)
-    p = torch.tensor(pr.p, dtype=torch.float32, device=dev)
-    res = {}
-    for name in ("plain_cold_eps_scaling", "warm"):
-        for rep in range(2):
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            if name == "warm":
-                v0 = W.barycenter_v0(net, p, pr.alpha, 128, ctx=ctx)
-                _, _, _, bi = W.barycenter_solve(p, pr.alpha, 128, v0=v0.contiguous(), ctx=ctx)
-            else:
-                _, _, _, bi = W.barycenter_solve(p, pr.alpha, 128, eps0=W.EPS0, ctx=ctx)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - a) * 1e3
-        res[name] = {"iters": int(bi["iters"]), "ms": ms, "converged": bool(bi["converged"])}
-    res["speedup"] = res["plain_cold_eps_scaling"]["ms"] / res["warm"]["ms"]
-    out["barycenter_8x128"] = res
+    out = {"workload": "barycentre of 8 blob images 128x128, KL 0.5, eps 2e-3, tol 1e-6, FP32"}
+    for seed in seeds:
+        pr = synth.bary_blobs(seed, n_marg=8, n=128)
+        p = torch.tensor(pr.p, dtype=torch.float32, device=dev)
+        res = {}
+        for name in ("cold_eps_scaling", "cold", "local", "net"):
+            best = None
+            for rep in range(2):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                if name == "net":
+                    v0 = W.barycenter_v0(net, p, pr.alpha, 128, ctx=ctx)
+                elif name == "local":
+                    v0 = W.barycenter_local_v0(p, pr.alpha, 128, ctx=ctx)
+                else:
+                    v0 = None
+                _, _, _, bi = W.barycenter_solve(p, pr.alpha, 128, v0=v0, ctx=ctx,
+                                                 eps0=W.EPS0 if name == "cold_eps_scaling" else None)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - a) * 1e3
+                if best is None or ms < best["ms"]:
+                    best = {"iters": int(bi["iters"]), "ms": ms, "converged": bool(bi["converged"])}
+            res[name] = best
+        base = min(res["cold"]["iters"], res["local"]["iters"])
+        res["net_iters_gain_vs_best_non_net"] = base / res["net"]["iters"]
+        out["seed%d" % seed] = res
     return out
 
 
@@ -195,6 +337,32 @@ TRAFFIC_BYTES = {
     ('k_grid_tf<true, 4>', 1): (3096797, 523671),
     ('k_grid_tf<true, 4>', 256): (406346152, 134348800),
 }
+
+
+# HBM bytes per launch (calibrated FETCH_SIZE read + WRITE_SIZE written) of
+# the batched matrix-core product on the ragged workload, from the counter
+# runs of `bench.py --pmc-workload batch`; valid for the source they were
+# taken on (sha256 of the product's file and the headers it includes).
+BATCH_TRAFFIC_SOURCES = ["uot_dense_mf.hip", "uot_epilogue.h", "uot_device.h", "uot_launch.h"]
+BATCH_TRAFFIC_SHA256 = None
+BATCH_TRAFFIC_BYTES = {}
+
+
+def _sha256(names):
+    import hashlib
+    h = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_1607_05816_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def batch_traffic(kernel, tile_rows):
+    """(bytes read, bytes written) per launch of the batched product, or None
+    once its source changed."""
+    if BATCH_TRAFFIC_SHA256 is None or _sha256(BATCH_TRAFFIC_SOURCES) != BATCH_TRAFFIC_SHA256:
+        return None
+    return BATCH_TRAFFIC_BYTES.get((kernel, tile_rows))
 
 
 def tf_source_sha256():
@@ -485,6 +653,28 @@ def pmc_workload_dense(U, torch, np, dev, ctx, n=20000):
     print("pmc dense workload done", flush=True)
 
 
+def pmc_workload_batch(U, torch, np, dev, ctx, iters=10):
+    """The launches the batched product's counters are read on: a 256 MiB
+    device copy (the calibration kernel of known size), then one batched
+    solve of the 4096-problem ragged workload for a fixed `iters` iterations
+    from the warm start (no tolerance, so every launch holds every problem),
+    after the batch signature's tuning solve."""
+    from paper_1607_05816_amd import cloud_warmstart as CW
+    src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    cw = CW.CloudWarmStart.load(CW.WEIGHTS, dev)
+    bp = CW.batch_problem(CW.ragged(0, B=RAGGED_B), dev)
+    CW.solve(bp, ctx=ctx, tol=0.0, max_iter=4)
+    v0 = cw.v0(bp, ctx=ctx)
+    _, _, info = CW.solve(bp, v0=v0, ctx=ctx, tol=0.0, max_iter=iters, check_every=iters)
+    torch.cuda.synchronize()
+    print("pmc batch workload done: %d iterations, product %s, rows per item %d" % (
+        int(info["iters"].max()), info["product"], int(info["tile_rows"])), flush=True)
+
+
 BF16_MFMA_PEAK = 2.5e15     # MI355X dense BF16 MFMA, FLOP/s
 
 
@@ -550,30 +740,87 @@ def mixed_precision(U, probs, last, ctx, torch, reps=3):
     return out
 
 
+def grid2d_bench(U, ctx, dev, np, torch, steps=5, warmup=1, seed=0):
+    """The 2-D grid workload: 256 x 256 blob densities, separable kernel in
+    log-domain 1-D passes, eps 1e-1 -> 1e-3 (10 stages of 100 iterations) to
+    residual 1e-6, solved once with KL 0.1 and once with TV 0.05, each
+    followed by the FP64 objective; iterations/s over `steps` steps, the
+    roofline of its dominant pass (one field and 256 fields) and the mixed
+    FP16/FP32 form."""
+    from paper_1607_05816_amd import synth
+    pr = synth.blobs2d(seed, n=N_GRID)
+    t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+    d = np.full(pr.size, pr.h[0] * pr.h[1])
+    probs = []
+    for name, lam in PENALTIES:
+        F = U.KL(lam) if name == "KL" else U.TV(lam)
+        probs.append((name, U.grid_problem(pr.shape, pr.h, t(pr.p), t(pr.q), t(d), t(d), F, F)))
+    for _, pb in probs:
+        pb.workspace()
+
+    def step():
+        out = []
+        for name, pb in probs:
+            u, v, info = U.solve(pb, EPS, eps0=EPS0, tol=TOL, max_iter=MAX_ITER, check_every=50, ctx=ctx)
+            obj = U.objective(pb, EPS, u, v, ctx=ctx)
+            out.append((name, info, obj, v))
+        return out
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    last = None
+    for _ in range(steps):
+        last = step()
+        iters += sum(o[1]["iters"] for o in last)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {
+        "workload": "grid2d-256x256-blobs5-KL0.1+TV0.05-eps1e-1to1e-3-10x100-tol1e-6 FP32",
+        "iters_per_s": iters / dt, "ms_per_step": dt / steps * 1e3, "steps": steps,
+        "time_to_residual_ms": {o[0]: o[1]["elapsed_ms"] for o in last},
+        "iters_per_solve": {o[0]: o[1]["iters"] for o in last},
+        "converged": all(o[1]["converged"] for o in last),
+        "gap": {o[0]: o[2]["gap"] for o in last},
+        "roofline": grid_roofline(U, probs, last, ctx, torch, np),
+        "mixed_fp16_fp32": mixed_precision(U, probs, last, ctx, torch),
+    }, pr
+
+
+METRIC = "Sinkhorn iters/s and time-to-residual 1e-6, warm+batched vs plain, 1 MI355X"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-warm-batched", action="store_true")
+    ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--no-warm-bary", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-gemm", action="store_true")
     ap.add_argument("--no-extensions", action="store_true")
-    ap.add_argument("--pmc-workload", nargs="?", const="grid", choices=("grid", "dense"),
-                    help="only run the launches counters are read on: the grid passes (HBM traffic) or "
-                         "the dense products at 20000^2 (instruction counters)")
+    ap.add_argument("--pmc-workload", nargs="?", const="grid", choices=("grid", "dense", "batch"),
+                    help="only run the launches counters are read on: the grid passes (HBM traffic), "
+                         "the dense products at 20000^2 or the batched product of the ragged workload")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    # the oracle's CPU sample runs first, before anything touches the GPU
+    # (its worker processes are forked)
+    cs = None
+    if not args.no_cpu_baseline and args.pmc_workload is None:
+        cs = cpu_sample()
+
     import numpy as np
     import torch
-    from paper_1607_05816_amd import synth
     from paper_1607_05816_amd import uot as U
 
     if not torch.cuda.is_available():
@@ -586,77 +833,53 @@ def main():
     if args.pmc_workload == "dense":
         pmc_workload_dense(U, torch, np, dev, U.default_context())
         return
-    pr = synth.blobs2d(args.seed, n=N_GRID)
-    t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
-    d = np.full(pr.size, pr.h[0] * pr.h[1])
-    probs = []
-    for name, lam in PENALTIES:
-        F = U.KL(lam) if name == "KL" else U.TV(lam)
-        probs.append((name, U.grid_problem(pr.shape, pr.h, t(pr.p), t(pr.q), t(d), t(d), F, F)))
+    if args.pmc_workload == "batch":
+        pmc_workload_batch(U, torch, np, dev, U.default_context())
+        return
     ctx = U.default_context()
-    for _, pb in probs:
-        pb.workspace()
-
-    def step():
-        out = []
-        for name, pb in probs:
-            u, v, info = U.solve(pb, EPS, eps0=EPS0, tol=TOL, max_iter=MAX_ITER, check_every=50, ctx=ctx)
-            obj = U.objective(pb, EPS, u, v, ctx=ctx)
-            out.append((name, info, obj, v))
-        return out
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = 0
-    last = None
-    for _ in range(args.steps):
-        last = step()
-        iters += sum(o[1]["iters"] for o in last)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    converged = all(o[1]["converged"] for o in last)
-
-    roofline = grid_roofline(U, probs, last, ctx, torch, np)
-    mixed = mixed_precision(U, probs, last, ctx, torch)
+    head = ragged_headline(U, ctx, dev, np, torch, args.steps, args.warmup)
+    iters_cold = head.pop("iters_cold")
     line = {
-        "metric": "Sinkhorn iters/s and time-to-residual 1e-6 (2-D grid 256x256, KL+TV, eps 1e-1->1e-3)",
-        "value": iters / dt,
-        "unit": "iters/s",
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "problems/s to residual 1e-6",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded Gaussian-blob densities)",
-        "config": {"workload": "grid2d-256x256-blobs5-KL0.1+TV0.05-eps1e-1to1e-3-10x100-tol1e-6",
-                   "grid": [N_GRID, N_GRID], "eps": EPS, "eps0": EPS0, "tol": TOL, "seed": args.seed,
-                   "parallelism": "single-gpu"},
-        "time_to_residual_ms": {o[0]: o[1]["elapsed_ms"] for o in last},
-        "iters_per_solve": {o[0]: o[1]["iters"] for o in last},
-        "converged": converged,
-        "gap": {o[0]: o[2]["gap"] for o in last},
-        "roofline": roofline,
-        "mixed_fp16_fp32": mixed,
+        "data": "synthetic (seeded ragged uniform point clouds)",
+        "config": {"workload": "ragged-4096-clouds2d-NM-loguniform-64-4096-uniform-points-KL1-eps5e-3-tol1e-6",
+                   "problems": RAGGED_B, "eps": RAGGED_EPS, "tol": TOL, "lambda": 1.0, "seed": 0,
+                   "warm_start": "cloud MLP 16-64-64-64-1 (data/warmstart_cloud.npz)", "parallelism": "single-gpu"},
+        "time_to_residual_1e-6_s": {"warm_batched": head["warm"]["seconds"],
+                                    "cold_batched": head["cold_batched"]["seconds"],
+                                    "plain_extrapolated": head["plain"]["seconds_extrapolated"]},
+        "speedup_vs_plain": head["speedup_vs_plain"],
+        "iters_per_s": head["warm"]["problem_iters_per_s"],
+        "roofline": head["roofline"],
+        "ragged": {k: v for k, v in head.items() if k not in ("value", "ms_per_step", "roofline")},
     }
+    if not args.no_grid:
+        line["grid2d_256"], pr = grid2d_bench(U, ctx, dev, np, torch, seed=args.seed)
+    if not args.no_warm_bary:
+        line["barycenter_warm_start"] = warm_bary(U, ctx, dev, np, torch)
     if not args.no_dense:
         line["roofline_dense"] = dense_roofline(U, torch, np, dev, ctx)
         line["dense_solve"] = dense_solve(U, torch, np, dev, ctx)
     if not args.no_gemm:
         line["roofline_gemm"] = gemm_roofline(U, torch, np, dev, ctx)
     if not args.no_extensions:
-        line["extensions"] = extensions(U, pr, ctx, dev, np, torch)
+        from paper_1607_05816_amd import synth
+        line["extensions"] = extensions(U, synth.blobs2d(args.seed, n=N_GRID), ctx, dev, np, torch)
         line["extensions"]["roofline_wf_dense"] = wf_dense_roofline(U, torch, np, dev, ctx)
         line["extensions"]["gradient_flows"] = flows_bench(U, torch, np, dev, ctx)
         line["extensions"]["colour_transfer"] = colour_transfer_bench(U, torch, np, dev, ctx)
-    if not args.no_warm_batched:
-        line["warm_batched_vs_plain"] = warm_batched(U, ctx, dev, np, torch)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(pr, args.cpu_budget)
+    if cs is not None:
+        line["cpu_baseline"] = cpu_baseline_ragged(cs, iters_cold, None, None)
     print(json.dumps(line), flush=True)
 
 

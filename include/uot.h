@@ -447,6 +447,18 @@ int uot_batch_workspace_size(const uot_batch_problem *pb, size_t *bytes);
 int uot_solve_batched(uot_ctx *ctx, const uot_batch_problem *pb, const uot_params *pr,
                       void *u, void *v, void *ws, size_t ws_bytes, uot_batch_result *res);
 
+/* Gibbs kernel products of a ragged batch without proxdiv (the product
+ * K(b dy) of Sec. 4 written as a log-sum-exp, at one eps): for every problem
+ * and every point r of its `rows` cloud (0: X, 1: Y),
+ *   out_r = log sum_c exp(w_c - |row_r - col_c|^2 / eps)
+ * over the points c of its `cols` cloud (0: X, 1: Y) of the same problem.
+ * w: device, concatenated over the problems on the cols side (natural log,
+ * -inf allowed); out: device, concatenated on the rows side (natural log;
+ * -inf where every term is -inf).  Problem dtype; direct product.
+ * Workspace: uot_batch_workspace_size.  F1, F2, p, q, dx, dy are not read. */
+int uot_batch_gibbs(uot_ctx *ctx, const uot_batch_problem *pb, double eps, int rows, int cols,
+                    const void *w, void *out, void *ws, size_t ws_bytes);
+
 /* ---------------------------------------------------------------------------
  * Warm-start network.  By Prop. "alternating" only v^(0) enters the iterates
  * (the first X half-step overwrites u), so predicting v from the two input
@@ -458,7 +470,7 @@ int uot_solve_batched(uot_ctx *ctx, const uot_batch_problem *pb, const uot_param
  * beta2 0.999, eps 1e-8, bias-corrected).  Loss: mean squared error over the
  * batch x n_out outputs.  Parameter layout of every parameter-sized array:
  * W1 [width x n_in], b1, W2 [width x width], b2, W3, b3, W4 [n_out x width], b4.
- * Sizes must be multiples of 8.  x: batch x n_in FP32 (normalised inside as
+ * n_in and width must be multiples of 8, n_out >= 1.  x: batch x n_in FP32 (normalised inside as
  * in_scale * x + in_shift), targets/outputs batch x n_out FP32.
  * ------------------------------------------------------------------------- */
 typedef struct uot_net {
@@ -489,6 +501,42 @@ int uot_warmstart_train_step(uot_ctx *ctx, uot_net *net, const float *x, const f
  * (R a multiple of r) and write x[b] = [log p_r, log q_r] (nb x 2 r^2) */
 int uot_warmstart_features(uot_ctx *ctx, const float *p, const float *q, int64_t nb,
                            int R, int r, float *x);
+/* Warm start of a ragged FP32 batch of point-cloud problems (the v side):
+ * per point y_j of every problem b, UOT_CLOUD_FEATURES = 16 features
+ *   c_0 = eps log q_j;
+ *   c_1..c_4   = eps G_a(log p + log dx over X),  a = 1/2, 1, 2, 4;
+ *   c_5..c_8   = eps G_a(log q + log dy over Y),  a = 1/2, 1, 2, 4;
+ *   c_9..c_11  = eps G_a(log dx over X),          a = 1/2, 1, 2;
+ *   c_12       = eps G_1(log dy over Y);
+ *   c_13, c_14 = eps log sum_i p_i dx_i, eps log sum_j q_j dy_j;
+ *   c_15 = eps log(N_b / M_b),
+ * with G_a(w) = log sum_c exp(w_c - |y_j - c|^2 / (a eps)) the Gibbs product
+ * at eps scaled by a (uot_batch_gibbs): the masses of the two measures and of
+ * the two reference measures near y_j at several kernel widths, and the
+ * problem's two total masses.  x (device,
+ * totM x 16, row per point) receives (c_k - shift_k) * scale_k with shift and
+ * scale HOST arrays of 16 (the network's input normalisation).  Workspace:
+ * uot_cloud_features_workspace_size. */
+#define UOT_CLOUD_FEATURES 16
+int uot_cloud_features_workspace_size(const uot_batch_problem *pb, size_t *bytes);
+int uot_cloud_features(uot_ctx *ctx, const uot_batch_problem *pb, double eps, const float *shift,
+                       const float *scale, float *x, void *ws, size_t ws_bytes);
+/* v0_j = zeps log q_j + out_scale y_j + out_shift for n points (device, FP32):
+ * y is the network's prediction of the smooth part of v (one output per
+ * point); with KL(lambda) on the second marginal zeps = eps lambda /
+ * (lambda + eps) makes the first term the exact pointwise part of v at the
+ * fixed point (Table proximalexplicit, KL row, in the log domain). */
+int uot_cloud_v0(uot_ctx *ctx, const float *q, int64_t n, double zeps, const float *y,
+                 double out_scale, double out_shift, float *v0);
+/* local (no transport) warm start of a KL(lam) barycentre on a 2-D grid
+ * n1 x n2 with cell sides h1, h2: with the Gibbs kernel replaced by its row
+ * mass kappa at each cell, every coupling reduces to the one-point problem
+ * between p_k and h0 there (the closed form of the KL/KL one-point problem,
+ * from the primal of Sec. 3), log r = (lam log p_k + lam log h0 + eps log
+ * kappa) / (2 lam + eps), and v0_k = -lam (log r - log h0).  p, v0: device
+ * n x n1 n2; h0: device n1 n2 (e.g. uot_bary_estimate); FP32. */
+int uot_bary_local_v0(uot_ctx *ctx, const float *p, const float *h0, int n, int n1, int n2,
+                      double h1, double h2, double lam, double eps, float *v0);
 /* first barycentre estimate for warm starts: Table estimatebary (ii) (KL,
  * lambda = F2->lambda) or (i) (equality) applied pointwise to the input
  * densities p (n x size, FP32) with weights alpha (HOST, n); h: size */

@@ -761,6 +761,12 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
     if (ctx->pinned->stop) {
       if (iteration2 && !second && ctx->pinned->status == 0) {
         second = true;
+        // a phase-one graph taken from the cache is destroyed here: the cache
+        // must not keep its handles
+        if (cache && cache->exec == exec) {
+          cache->exec = nullptr;
+          cache->graph = nullptr;
+        }
         release();
         launch_ctrl_resume(dctrl, *final_tol, s);
         if ((rc = capture(*iteration2))) break;
@@ -1579,6 +1585,176 @@ void build_items(const int64_t* offR, const int64_t* offC, int64_t B, int R, std
   });
 }
 
+// Workspace views and one-time set-up shared by the plain Gibbs products of a
+// batch (uot_batch_gibbs, the cloud warm-start features): offsets and the
+// per-problem flags on the device, every problem active.
+struct BatchGibbs {
+  Ctrl* ctrl;
+  BCtrl* bc_dev;
+  int64_t *offN_d, *offM_d;
+  BItem *items[2];     // rows X, rows Y (columns of the other side or the same side, see gibbs_items)
+  int n_items[2];
+  int* curs;
+  int ncu;
+};
+
+template <typename T>
+int batch_gibbs_setup(uot_ctx* ctx, const BatchPlan& P, const uot_batch_problem* pb, char* ws, BatchGibbs& G) {
+  hipStream_t s = ctx->work;
+  G.ctrl = at<Ctrl>(ws, P.o_ctrl);
+  BCtrl bc;
+  bc.stop = at<int32_t>(ws, P.o_stop);
+  bc.yskip = at<int32_t>(ws, P.o_yskip);
+  bc.status = at<int32_t>(ws, P.o_status);
+  bc.iters = at<int64_t>(ws, P.o_iters);
+  bc.res = at<double>(ws, P.o_res);
+  bc.clock = at<uint64_t>(ws, P.o_clock);
+  G.bc_dev = reinterpret_cast<BCtrl*>(reinterpret_cast<char*>(G.ctrl) + align_up(sizeof(Ctrl), 64));
+  G.offN_d = at<int64_t>(ws, P.o_offN);
+  G.offM_d = at<int64_t>(ws, P.o_offM);
+  G.items[0] = at<BItem>(ws, P.o_itx);
+  G.items[1] = at<BItem>(ws, P.o_ity);
+  G.curs = at<int>(ws, P.o_curs);
+  HIP_TRY(hipDeviceGetAttribute(&G.ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  // the synchronous copies below overwrite workspace earlier work on the stream may still read
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(G.offN_d, pb->offN, 8 * (P.B + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(G.offM_d, pb->offM, 8 * (P.B + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(G.bc_dev, &bc, sizeof(BCtrl), hipMemcpyHostToDevice));
+  return UOT_OK;
+}
+
+// items of rows of side `rows` (0: X, 1: Y) against the columns of side
+// `cols`, uploaded into the items slot of the rows side
+int gibbs_items(const BatchPlan& P, const uot_batch_problem* pb, int rows, int cols, BatchGibbs& G) {
+  std::vector<BItem> it;
+  build_items(rows ? pb->offM : pb->offN, cols ? pb->offM : pb->offN, P.B, 1, it, nullptr);
+  HIP_TRY(hipMemcpy(G.items[rows], it.data(), sizeof(BItem) * it.size(), hipMemcpyHostToDevice));
+  G.n_items[rows] = (int)it.size();
+  return UOT_OK;
+}
+
+// out_r = log sum_c exp(w_c - |row_r - col_c|^2 / eps) for every problem
+// (natural log), direct product; w2 is workspace for the log2 input
+template <typename T>
+void gibbs_launch(const BatchPlan& P, const uot_batch_problem* pb, const BatchGibbs& G, double eps, int rows, int cols,
+                  const T* w, T* w2, T* out, hipStream_t s) {
+  launch_ctrl_init(G.ctrl, make_ctrl(eps, 0, 0, 0, 0, 1), s);
+  launch_batch_init(G.bc_dev, (int)P.B, G.ctrl, s);
+  launch_set_int(G.curs, 2, 0, s);
+  const int64_t totR = rows ? P.totM : P.totN, totC = cols ? P.totM : P.totN;
+  launch_init_pot<T>(nullptr, w, nullptr, w2, totC, totC, G.ctrl, 0, s);   // w2 = w log2(e)
+  EpiArgs<T> ep{};
+  ep.mode = EPI_RAW;
+  ep.out = out;
+  launch_batch_lse<T>(P.dim, 1, G.ncu * 8, G.items[rows], G.n_items[rows], G.curs, rows ? G.offM_d : G.offN_d,
+                      cols ? G.offM_d : G.offN_d, static_cast<const T*>(rows ? pb->y : pb->x), totR,
+                      static_cast<const T*>(cols ? pb->y : pb->x), totC, w2, G.bc_dev, G.ctrl, 0, ep, s);
+  launch_scale<T>(out, totR, kLn2, s);
+}
+
+int check_batch_ws(const BatchPlan& P, const void* ws, size_t wsb, size_t need) {
+  if (!ws) return fail(UOT_E_WORKSPACE, "workspace pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(UOT_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (wsb < need) return fail(UOT_E_WORKSPACE, "workspace too small: need " + std::to_string(need));
+  (void)P;
+  return UOT_OK;
+}
+
+template <typename T>
+int batch_gibbs_t(uot_ctx* ctx, const uot_batch_problem* pb, double eps, int rows, int cols, const T* w, T* out,
+                  char* ws, size_t wsb) {
+  BatchPlan P;
+  int rc = make_batch_plan(P, pb);
+  if (rc) return rc;
+  if ((rc = check_batch_ws(P, ws, wsb, P.total))) return rc;
+  if (!pb->x || !pb->y || !w || !out) return fail(UOT_E_INVALID, "x, y, w and out are required");
+  if (!(eps > 0) || !std::isfinite(eps)) return fail(UOT_E_INVALID, "eps must be > 0");
+  if ((rows != 0 && rows != 1) || (cols != 0 && cols != 1)) return fail(UOT_E_INVALID, "rows and cols are 0 or 1");
+  if ((rc = begin(ctx))) return rc;
+  BatchGibbs G;
+  if ((rc = batch_gibbs_setup<T>(ctx, P, pb, ws, G))) return rc;
+  if ((rc = gibbs_items(P, pb, rows, cols, G))) return rc;
+  gibbs_launch<T>(P, pb, G, eps, rows, cols, w, at<T>(ws, cols ? P.o_wv : P.o_wu), out, ctx->work);
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
+static_assert(kCloudFeatures == UOT_CLOUD_FEATURES, "feature count of the C header");
+
+// the Gibbs products behind the cloud features (rows Y): columns, input and
+// scale factor of eps per product, in feature order after eps log q
+struct CloudProd {
+  int cols;      // 0: X, 1: Y
+  int input;     // 0: log p + log dx, 1: log q + log dy, 2: log dx, 3: log dy
+  double a;      // product at eps a (kCloudWhole: the total over the problem)
+};
+constexpr double kCloudWhole = 1e30;   // the kernel is 1 to FP32 precision: log of the total mass
+constexpr CloudProd kCloudProds[kCloudFeatures - 2] = {
+    {0, 0, 0.5}, {0, 0, 1.0}, {0, 0, 2.0}, {0, 0, 4.0},   // mass of the first measure near y_j
+    {1, 1, 0.5}, {1, 1, 1.0}, {1, 1, 2.0}, {1, 1, 4.0},   // mass of the second measure near y_j
+    {0, 2, 0.5}, {0, 2, 1.0}, {0, 2, 2.0},                // reference mass of the first cloud near y_j
+    {1, 3, 1.0},                                          // reference mass of the second cloud near y_j
+    {0, 0, kCloudWhole}, {1, 1, kCloudWhole}};            // total masses of the two measures
+
+size_t cloud_extra_bytes(const BatchPlan& P) {
+  return align_up(4 * (size_t)(kCloudFeatures - 2) * P.totM) + 2 * align_up(4 * (size_t)P.totN) +
+         3 * align_up(4 * (size_t)P.totM);
+}
+
+int cloud_features_t(uot_ctx* ctx, const uot_batch_problem* pb, double eps, const float* shift, const float* scale,
+                     float* x, char* ws, size_t wsb) {
+  BatchPlan P;
+  int rc = make_batch_plan(P, pb);
+  if (rc) return rc;
+  if (P.dtype != UOT_F32) return fail(UOT_E_UNSUPPORTED, "the cloud warm start takes FP32 batches");
+  if ((rc = check_batch_ws(P, ws, wsb, P.total + cloud_extra_bytes(P)))) return rc;
+  if (!pb->x || !pb->y || !pb->p || !pb->q || !pb->dx || !pb->dy || !shift || !scale || !x)
+    return fail(UOT_E_INVALID, "x, y, p, q, dx, dy, shift, scale and x_out are required");
+  if (!(eps > 0) || !std::isfinite(eps)) return fail(UOT_E_INVALID, "eps must be > 0");
+  hipStream_t s = ctx->work;
+  if ((rc = begin(ctx))) return rc;
+  BatchGibbs G;
+  if ((rc = batch_gibbs_setup<float>(ctx, P, pb, ws, G))) return rc;
+  // rows Y against columns X go to the X items slot, rows Y against columns Y to the Y slot
+  std::vector<BItem> it;
+  build_items(pb->offM, pb->offN, P.B, 1, it, nullptr);
+  HIP_TRY(hipMemcpy(G.items[0], it.data(), sizeof(BItem) * it.size(), hipMemcpyHostToDevice));
+  G.n_items[0] = (int)it.size();
+  if ((rc = gibbs_items(P, pb, 1, 1, G))) return rc;
+  char* ex = ws + P.total;
+  float* prod = reinterpret_cast<float*>(ex);
+  ex += align_up(4 * (size_t)(kCloudFeatures - 2) * P.totM);
+  float* in_x[2];
+  float* in_y[3];
+  for (auto& p : in_x) { p = reinterpret_cast<float*>(ex); ex += align_up(4 * (size_t)P.totN); }
+  for (auto& p : in_y) { p = reinterpret_cast<float*>(ex); ex += align_up(4 * (size_t)P.totM); }
+  const float* px = static_cast<const float*>(pb->p);
+  const float* qy = static_cast<const float*>(pb->q);
+  const float* dxp = static_cast<const float*>(pb->dx);
+  const float* dyp = static_cast<const float*>(pb->dy);
+  launch_log_sum(px, dxp, in_x[0], P.totN, s);                 // log p + log dx
+  launch_log<float>(dxp, in_x[1], P.totN, 0, s);               // log dx
+  launch_log_sum(qy, dyp, in_y[0], P.totM, s);                 // log q + log dy
+  launch_log<float>(dyp, in_y[1], P.totM, 0, s);               // log dy
+  launch_log<float>(qy, in_y[2], P.totM, 1, s);                // log q
+  const float* inputs[4] = {in_x[0], in_y[0], in_x[1], in_y[1]};
+  for (int k = 0; k < kCloudFeatures - 2; ++k) {
+    const CloudProd& c = kCloudProds[k];
+    // rows Y; the items slot of the columns' side holds the matching list
+    BatchGibbs Gk = G;
+    Gk.items[1] = G.items[c.cols];
+    Gk.n_items[1] = G.n_items[c.cols];
+    gibbs_launch<float>(P, pb, Gk, c.a == kCloudWhole ? c.a : c.a * eps, 1, c.cols, inputs[c.input],
+                        at<float>(ws, c.cols ? P.o_wv : P.o_wu),
+                        prod + (int64_t)k * P.totM, s);
+  }
+  launch_cloud_assemble(prod, kCloudFeatures - 2, in_y[2], G.offN_d, G.offM_d, P.B, P.totM, (float)eps, shift, scale,
+                        x, s);
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
 template <typename T>
 int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* u, T* v, char* ws, size_t wsb,
             uot_batch_result* res) {
@@ -2120,6 +2296,41 @@ int uot_batch_workspace_size(const uot_batch_problem* pb, size_t* bytes) {
   if (rc) return rc;
   *bytes = P.total;
   return UOT_OK;
+}
+
+int uot_batch_gibbs(uot_ctx* ctx, const uot_batch_problem* pb, double eps, int rows, int cols, const void* w,
+                    void* out, void* ws, size_t wsb) {
+  if (!ctx || !pb) return fail(UOT_E_INVALID, "ctx and problem are required");
+  if (pb->dtype == UOT_F32)
+    return batch_gibbs_t<float>(ctx, pb, eps, rows, cols, static_cast<const float*>(w), static_cast<float*>(out),
+                                static_cast<char*>(ws), wsb);
+  return batch_gibbs_t<double>(ctx, pb, eps, rows, cols, static_cast<const double*>(w), static_cast<double*>(out),
+                               static_cast<char*>(ws), wsb);
+}
+
+int uot_cloud_features_workspace_size(const uot_batch_problem* pb, size_t* bytes) {
+  if (!pb || !bytes) return fail(UOT_E_INVALID, "NULL argument");
+  BatchPlan P;
+  int rc = make_batch_plan(P, pb);
+  if (rc) return rc;
+  *bytes = P.total + cloud_extra_bytes(P);
+  return UOT_OK;
+}
+
+int uot_cloud_features(uot_ctx* ctx, const uot_batch_problem* pb, double eps, const float* shift, const float* scale,
+                       float* x, void* ws, size_t wsb) {
+  if (!ctx || !pb) return fail(UOT_E_INVALID, "ctx and problem are required");
+  return cloud_features_t(ctx, pb, eps, shift, scale, x, static_cast<char*>(ws), wsb);
+}
+
+int uot_cloud_v0(uot_ctx* ctx, const float* q, int64_t n, double zeps, const float* y, double out_scale,
+                 double out_shift, float* v0) {
+  if (!ctx || !q || !y || !v0 || n < 1) return fail(UOT_E_INVALID, "q, y, v0 and n >= 1 are required");
+  int rc = begin(ctx);
+  if (rc) return rc;
+  launch_cloud_v0(y, q, n, (float)zeps, (float)out_scale, (float)out_shift, v0, ctx->work);
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
 }
 
 int uot_solve_batched(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, void* u, void* v, void* ws,

@@ -2167,6 +2167,19 @@ void launch_set_int(int* p, int n, int v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_int, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, p, n, v);
 }
 
+template <typename T>
+__global__ void k_scale(T* __restrict__ a, int64_t n, T f) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) a[i] *= f;
+}
+
+template <typename T> void launch_scale(T* a, int64_t n, double f, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scale<T>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, a, n, T(f));
+}
+template void launch_scale<float>(float*, int64_t, double, hipStream_t);
+template void launch_scale<double>(double*, int64_t, double, hipStream_t);
+
 template void launch_batch_lse<float>(int, int, int, const BItem*, int, int*, const int64_t*, const int64_t*,
                                       const float*, int64_t, const float*, int64_t, const float*, const BCtrl*,
                                       const Ctrl*, int, const EpiArgs<float>&, hipStream_t);

@@ -167,5 +167,15 @@ void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const 
                           int par, hipStream_t s);
 void launch_batch_init(BCtrl* bc, int B, Ctrl* c, hipStream_t s);
 void launch_set_int(int* p, int n, int v, hipStream_t s);
+template <typename T> void launch_scale(T* a, int64_t n, double f, hipStream_t s);
+
+// warm start of ragged point-cloud batches (uot_net.hip)
+constexpr int kCloudFeatures = 16;   // UOT_CLOUD_FEATURES of the C header
+void launch_log_sum(const float* a, const float* b, float* out, int64_t n, hipStream_t s);
+void launch_cloud_assemble(const float* prod, int n_prod, const float* logq, const int64_t* offN, const int64_t* offM,
+                           int64_t B, int64_t totM, float eps, const float* shift, const float* scale, float* x,
+                           hipStream_t s);
+void launch_cloud_v0(const float* y, const float* q, int64_t n, float zeps, float out_scale, float out_shift,
+                     float* v0, hipStream_t s);
 
 }  // namespace uot

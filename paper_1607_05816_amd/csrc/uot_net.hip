@@ -344,6 +344,79 @@ __global__ void k_bary_estimate(const float* __restrict__ p, int n, int64_t size
   h[j] = expf(logh);
 }
 
+// local (no transport) estimate of the barycentre potentials on a 2-D grid:
+// with K replaced by its row mass kappa_i = sum_j dy_j exp(-|x_i - y_j|^2/eps)
+// at each cell, the KL(lam) coupling between p_k and h reduces to the
+// one-point problem at that cell, whose plan density is
+//   log r = (lam log p_k + lam log h + eps log kappa) / (2 lam + eps)
+// and whose second potential is v = -lam log(r / h).  kappa is the product of
+// the two 1-D kernel masses of the cell.
+__global__ void k_bary_local_v0(const float* __restrict__ p, const float* __restrict__ h0, int n, int n1, int n2,
+                                float h1, float h2, float lam, float eps, float* __restrict__ v0) {
+  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+  const int64_t size = (int64_t)n1 * n2;
+  if (t >= (int64_t)n * size) return;
+  const int64_t cell = t % size;
+  const int i1 = (int)(cell / n2), i2 = (int)(cell % n2);
+  float k1 = 0.f, k2 = 0.f;
+  for (int j = 0; j < n1; ++j) {
+    const float d = h1 * float(i1 - j);
+    k1 += h1 * expf(-d * d / eps);
+  }
+  for (int j = 0; j < n2; ++j) {
+    const float d = h2 * float(i2 - j);
+    k2 += h2 * expf(-d * d / eps);
+  }
+  const float lh = logf(h0[cell]);
+  const float logr = (lam * logf(p[t]) + lam * lh + eps * (logf(k1) + logf(k2))) / (2.f * lam + eps);
+  v0[t] = -lam * (logr - lh);
+}
+
+// ---------------------------------------------------------------------------
+// warm start of ragged point-cloud batches: per-point features of the
+// second cloud (the side v lives on) and the composition of v^(0)
+// ---------------------------------------------------------------------------
+__global__ void k_log_sum(const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ out,
+                          int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i < n) out[i] = logf(a[i]) + logf(b[i]);
+}
+
+struct FeatNorm {
+  float shift[kCloudFeatures], scale[kCloudFeatures];
+};
+
+// x[j][k] = (c_k(j) - shift_k) scale_k with c_0 = eps log q_j, c_1..c_np the
+// Gibbs products prod[k-1][j] (natural log) times eps, and the last column
+// eps log(N_b / M_b) of the problem b that point j belongs to
+__global__ void k_cloud_assemble(const float* __restrict__ prod, int n_prod, const float* __restrict__ logq,
+                                 const int64_t* __restrict__ offN, const int64_t* __restrict__ offM, int64_t B,
+                                 int64_t totM, float eps, FeatNorm nm, float* __restrict__ x) {
+  const int64_t j = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (j >= totM) return;
+  int64_t lo = 0, hi = B;   // offM[lo] <= j < offM[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) / 2;
+    if (offM[mid] <= j) lo = mid;
+    else hi = mid;
+  }
+  float c[kCloudFeatures];
+  c[0] = eps * logq[j];
+  for (int k = 0; k < kCloudFeatures - 2; ++k) c[k + 1] = k < n_prod ? eps * prod[(int64_t)k * totM + j] : 0.f;
+  c[kCloudFeatures - 1] = eps * logf(float(offN[lo + 1] - offN[lo]) / float(offM[lo + 1] - offM[lo]));
+  float* xo = x + j * kCloudFeatures;
+#pragma unroll
+  for (int k = 0; k < kCloudFeatures; ++k) xo[k] = (c[k] - nm.shift[k]) * nm.scale[k];
+}
+
+// v0_j = z eps log q_j + out_scale y_j + out_shift (the network predicts the
+// smooth part of v, the pointwise part z eps log q_j is exact)
+__global__ void k_cloud_v0(const float* __restrict__ y, const float* __restrict__ q, int64_t n, float zeps,
+                           float out_scale, float out_shift, float* __restrict__ v0) {
+  const int64_t j = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (j < n) v0[j] = zeps * logf(q[j]) + out_scale * y[j] + out_shift;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -409,7 +482,7 @@ Act carve(const uot_net* n, int64_t batch, char* ws) {
 int check_net(const uot_net* n) {
   if (!n) return fail(UOT_E_INVALID, "net is NULL");
   if (n->n_in < 1 || n->width < 1 || n->n_out < 1) return fail(UOT_E_INVALID, "net sizes must be >= 1");
-  if (n->width % 8 || n->n_in % 8 || n->n_out % 8) return fail(UOT_E_UNSUPPORTED, "net sizes must be multiples of 8");
+  if (n->width % 8 || n->n_in % 8) return fail(UOT_E_UNSUPPORTED, "n_in and width must be multiples of 8");
   return UOT_OK;
 }
 
@@ -464,6 +537,31 @@ double loss_from_parts(const Act& a, int64_t ny, hipStream_t s, int* rc) {
 }
 
 }  // namespace net
+
+void launch_log_sum(const float* a, const float* b, float* out, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(net::k_log_sum, dim3(net::cdiv(n, net::kB)), dim3(net::kB), 0, s, a, b, out, n);
+}
+
+void launch_cloud_assemble(const float* prod, int n_prod, const float* logq, const int64_t* offN, const int64_t* offM,
+                           int64_t B, int64_t totM, float eps, const float* shift, const float* scale, float* x,
+                           hipStream_t s) {
+  net::FeatNorm nm;
+  for (int k = 0; k < kCloudFeatures; ++k) {
+    nm.shift[k] = shift[k];
+    nm.scale[k] = scale[k];
+  }
+  if (totM > 0)
+    hipLaunchKernelGGL(net::k_cloud_assemble, dim3(net::cdiv(totM, net::kB)), dim3(net::kB), 0, s, prod, n_prod, logq,
+                       offN, offM, B, totM, eps, nm, x);
+}
+
+void launch_cloud_v0(const float* y, const float* q, int64_t n, float zeps, float out_scale, float out_shift,
+                     float* v0, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(net::k_cloud_v0, dim3(net::cdiv(n, net::kB)), dim3(net::kB), 0, s, y, q, n, zeps, out_scale,
+                       out_shift, v0);
+}
+
 }  // namespace uot
 
 using namespace uot;
@@ -596,6 +694,19 @@ int uot_bary_estimate(uot_ctx* ctx, const float* p, int n, int64_t size, const d
   if (rc) return rc;
   hipLaunchKernelGGL(k_bary_estimate, dim3(cdiv(size, kB)), dim3(kB), 0, ctx->work, p, n, size, la, std::log(asum),
                      (float)eps, (float)F2->lambda, F2->kind == UOT_DIV_KL ? 1 : 0, h);
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
+int uot_bary_local_v0(uot_ctx* ctx, const float* p, const float* h0, int n, int n1, int n2, double h1, double h2,
+                      double lam, double eps, float* v0) {
+  if (!ctx || !p || !h0 || !v0 || n < 1 || n1 < 1 || n2 < 1 || !(h1 > 0) || !(h2 > 0) || !(lam > 0) || !(eps > 0))
+    return fail(UOT_E_INVALID, "bad arguments");
+  int rc = begin(ctx);
+  if (rc) return rc;
+  const int64_t tot = (int64_t)n * n1 * n2;
+  hipLaunchKernelGGL(k_bary_local_v0, dim3(cdiv(tot, kB)), dim3(kB), 0, ctx->work, p, h0, n, n1, n2, (float)h1,
+                     (float)h2, (float)lam, (float)eps, v0);
   HIP_TRY(hipGetLastError());
   return finish(ctx);
 }

@@ -28,14 +28,15 @@ from . import warmstart as W
 WIDTH = 256
 
 
-def save_weights(net: U.WarmStartNet, path):
-    """Weights as their BF16 values (what the GEMMs use) plus FP32 biases."""
+def save_weights(net: U.WarmStartNet, path, extra=None):
+    """Weights as their BF16 values (what the GEMMs use) plus FP32 biases;
+    `extra` (name -> array) is stored beside them."""
     theta = net.master.cpu().numpy()
     wb = net.wbf16.cpu().numpy().view(np.uint16)
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     np.savez_compressed(path, wbf16=wb, theta_fp32_bias_mask=_bias_mask(net), biases=theta[_bias_mask(net)],
                         n_in=net.c.n_in, width=net.c.width, n_out=net.c.n_out, in_scale=net.c.in_scale,
-                        in_shift=net.c.in_shift)
+                        in_shift=net.c.in_shift, **(extra or {}))
 
 
 def _bias_mask(net):

@@ -139,6 +139,12 @@ def lib():
         "uot_gemm_bf16": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64]),
         "uot_time_gemm_bf16": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,
                                        c_i32, P(c_dbl)]),
+        "uot_bary_local_v0": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_dbl, c_dbl, c_dbl, c_dbl, c_vp]),
+        "uot_batch_gibbs": (c_i32, [c_vp, P(UotBatchProblem), c_dbl, c_i32, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t]),
+        "uot_cloud_features_workspace_size": (c_i32, [P(UotBatchProblem), P(ctypes.c_size_t)]),
+        "uot_cloud_features": (c_i32, [c_vp, P(UotBatchProblem), c_dbl, P(ctypes.c_float), P(ctypes.c_float), c_vp,
+                                       c_vp, ctypes.c_size_t]),
+        "uot_cloud_v0": (c_i32, [c_vp, c_vp, c_i64, c_dbl, c_vp, c_dbl, c_dbl, c_vp]),
         "uot_solve_batched": (c_i32, [c_vp, P(UotBatchProblem), P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t,
                                       P(UotBatchResult)]),
         "uot_flow_workspace_size": (c_i32, [P(UotFlowProblem), P(ctypes.c_size_t)]),
@@ -317,19 +323,35 @@ class Problem:
         return self._ws
 
 
-def points_problem(x, y, p, q, dx, dy, F1: Div, F2: Div, cost: Cost = SQEUCLID) -> Problem:
-    """x: (N, d) or (d, N) coordinate tensors are accepted as (N, d); stored
-    coordinate-major for the kernels."""
+def _coord_major(x, n, layout, name):
+    """(d, n) view of point coordinates given as (n, d) ("nd") or (d, n)
+    ("dn"); with layout None the shape decides, and a square shape above
+    1 x 1, which fits both readings, is an error."""
+    if x.dim() == 1:
+        return x[None, :] if layout == "dn" else x[:, None].t()
+    if layout is None:
+        if x.shape[0] == x.shape[1] and x.shape[0] > 1:
+            raise ValueError("%s is %d x %d: pass layout='nd' (points in rows) or 'dn' (coordinate-major)"
+                             % (name, x.shape[0], x.shape[1]))
+        layout = "nd" if x.shape[0] == n else "dn"
+    if layout not in ("nd", "dn"):
+        raise ValueError("layout must be 'nd' or 'dn'")
+    xs = x.t() if layout == "nd" else x
+    if xs.shape[1] != n:
+        raise ValueError("%s has shape %s, which does not hold %d points in layout %r" % (name, tuple(x.shape), n,
+                                                                                         layout))
+    return xs
+
+
+def points_problem(x, y, p, q, dx, dy, F1: Div, F2: Div, cost: Cost = SQEUCLID, layout: Optional[str] = None) -> Problem:
+    """Point clouds x (N points) and y (M points), given as (N, d) tensors
+    (layout "nd", points in rows) or coordinate-major (d, N) ("dn"); stored
+    coordinate-major for the kernels.  Without a layout the shape decides,
+    and a square shape (N = d) raises ValueError."""
     dtype = p.dtype
     N, M = p.numel(), q.numel()
-    if x.dim() == 1:
-        x = x[:, None]
-    if y.dim() == 1:
-        y = y[:, None]
-    if x.shape[0] == N and x.shape[1] != N:
-        x = x.t()
-    if y.shape[0] == M and y.shape[1] != M:
-        y = y.t()
+    x = _coord_major(x, N, layout, "x")
+    y = _coord_major(y, M, layout, "y")
     xs = _dev(x.contiguous(), dtype, name="x")
     ys = _dev(y.contiguous(), dtype, name="y")
     d = xs.shape[0]
@@ -565,7 +587,7 @@ class BatchProblem:
     xs, ys: lists of (N_b, d) / (M_b, d) tensors (or one concatenated tensor
     each with sizes Ns / Ms); p, q, dx, dy likewise concatenated."""
 
-    def __init__(self, Ns, Ms, x, y, p, q, dx, dy, F1: Div, F2: Div):
+    def __init__(self, Ns, Ms, x, y, p, q, dx, dy, F1: Div, F2: Div, layout: Optional[str] = None):
         import numpy as np
         dtype = p.dtype
         self.B = len(Ns)
@@ -574,10 +596,8 @@ class BatchProblem:
         self.offN[1:] = np.cumsum(np.asarray(Ns, dtype=np.int64))
         self.offM[1:] = np.cumsum(np.asarray(Ms, dtype=np.int64))
         totN, totM = int(self.offN[-1]), int(self.offM[-1])
-        if x.shape[0] == totN:
-            x = x.t()
-        if y.shape[0] == totM:
-            y = y.t()
+        x = _coord_major(x, totN, layout, "x")
+        y = _coord_major(y, totM, layout, "y")
         self.x = _dev(x.contiguous(), dtype, name="x")
         self.y = _dev(y.contiguous(), dtype, name="y")
         d = self.x.shape[0]
@@ -632,6 +652,51 @@ def solve_batched(bp: BatchProblem, eps, ctx: Optional[Context] = None, v0=None,
         info["kernel_ms"] = [kms[k] for k in range(4)]
         info["kernel_launches"] = [kcnt[k] for k in range(4)]
     return u, v, info
+
+
+def batch_gibbs(bp: BatchProblem, eps, rows, cols, w, ctx: Optional[Context] = None):
+    """out_r = log sum_c exp(w_c - |row_r - col_c|^2 / eps) per problem
+    (uot_batch_gibbs); rows, cols: 0 for X, 1 for Y."""
+    ctx = ctx or default_context()
+    _dev(w, bp.dtype, bp.totM if cols else bp.totN, "w")
+    out = torch.empty(bp.totM if rows else bp.totN, dtype=bp.dtype, device=w.device)
+    ws = bp.workspace()
+    _check(lib().uot_batch_gibbs(ctx.handle, ctypes.byref(bp.c), float(eps), int(rows), int(cols), _ptr(w), _ptr(out),
+                                 _ptr(ws), ws.numel()), "uot_batch_gibbs", False)
+    return out
+
+
+CLOUD_FEATURES = 16
+
+
+def cloud_features(bp: BatchProblem, eps, shift, scale, ctx: Optional[Context] = None):
+    """Warm-start features of every point of the Y clouds (uot_cloud_features):
+    (totM x 16) FP32, normalised as (c - shift) * scale."""
+    import numpy as np
+    ctx = ctx or default_context()
+    sh = np.ascontiguousarray(np.asarray(shift, dtype=np.float32).reshape(CLOUD_FEATURES))
+    sc = np.ascontiguousarray(np.asarray(scale, dtype=np.float32).reshape(CLOUD_FEATURES))
+    n = ctypes.c_size_t()
+    _check(lib().uot_cloud_features_workspace_size(ctypes.byref(bp.c), ctypes.byref(n)),
+           "uot_cloud_features_workspace_size", False)
+    ws = workspace(n.value, bp.p.device)
+    x = torch.empty(bp.totM, CLOUD_FEATURES, dtype=torch.float32, device=bp.p.device)
+    fp = ctypes.POINTER(ctypes.c_float)
+    _check(lib().uot_cloud_features(ctx.handle, ctypes.byref(bp.c), float(eps), sh.ctypes.data_as(fp),
+                                    sc.ctypes.data_as(fp), _ptr(x), _ptr(ws), ws.numel()), "uot_cloud_features", False)
+    return x
+
+
+def cloud_v0(q, zeps, y, out_scale, out_shift, ctx: Optional[Context] = None):
+    """v0 = zeps log q + out_scale y + out_shift (uot_cloud_v0), FP32."""
+    ctx = ctx or default_context()
+    n = q.numel()
+    _dev(q, torch.float32, n, "q")
+    _dev(y, torch.float32, n, "y")
+    v0 = torch.empty(n, dtype=torch.float32, device=q.device)
+    _check(lib().uot_cloud_v0(ctx.handle, _ptr(q), n, float(zeps), _ptr(y), float(out_scale), float(out_shift),
+                              _ptr(v0)), "uot_cloud_v0", False)
+    return v0
 
 
 def solve_fields(shape, h, p, q, dx, dy, F1: Div, F2: Div, eps, ctx: Optional[Context] = None, v0=None,
@@ -788,6 +853,20 @@ def grid_upsample(y, r, R, ctx: Optional[Context] = None):
     out = torch.empty(nb, R * R, dtype=torch.float32, device=y.device)
     _check(lib().uot_grid_upsample(ctx.handle, _ptr(y), nb, r, R, _ptr(out)), "uot_grid_upsample", False)
     return out
+
+
+def bary_local_v0(p, h0, shape, h, lam, eps, ctx: Optional[Context] = None):
+    """Local (no transport) warm start of a KL(lam) barycentre on a 2-D grid
+    (uot_bary_local_v0): p (n x size), h0 (size) -> v0 (n x size), FP32."""
+    ctx = ctx or default_context()
+    n = p.shape[0]
+    n1, n2 = shape
+    _dev(p, torch.float32, n * n1 * n2, "p")
+    _dev(h0, torch.float32, n1 * n2, "h0")
+    v0 = torch.empty(n, n1 * n2, dtype=torch.float32, device=p.device)
+    _check(lib().uot_bary_local_v0(ctx.handle, _ptr(p), _ptr(h0), n, n1, n2, float(h[0]), float(h[1]), float(lam),
+                                   float(eps), _ptr(v0)), "uot_bary_local_v0", False)
+    return v0
 
 
 def bary_estimate(p, alpha, eps, F2: Div, ctx: Optional[Context] = None):

@@ -136,6 +136,14 @@ def barycenter_v0(net: U.WarmStartNet, p, alpha, R, ctx=None):
     return U.grid_upsample(y, RES, R, ctx=ctx)
 
 
+def barycenter_local_v0(p, alpha, R, ctx=None):
+    """The local estimate without a network: v^(0)_k of the one-point problem
+    between p_k and h0 (Table estimatebary applied to the inputs) at every
+    cell, with the kernel's row mass (uot_bary_local_v0)."""
+    h0 = U.bary_estimate(p, alpha, EPS, U.KL(LAM), ctx=ctx)
+    return U.bary_local_v0(p, h0, (R, R), (1.0 / R, 1.0 / R), LAM, EPS, ctx=ctx)
+
+
 def barycenter_solve(p, alpha, R, v0=None, eps0=None, ctx=None, max_iter=20000, check_every=50):
     h = (1.0 / R, 1.0 / R)
     d = torch.full((R * R,), h[0] * h[1], dtype=torch.float32, device=p.device)

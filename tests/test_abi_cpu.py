@@ -216,3 +216,21 @@ def test_wf_cost_and_flow_validation_on_host():
     assert L.uot_solve(ctypes.c_void_p(1), ctypes.byref(pb), ctypes.byref(pr), None, None, None, 0,
                        ctypes.byref(uot.UotResult())) == -1
     assert b"growth" in L.uot_last_error()
+
+
+def test_point_layout_is_explicit_when_the_shape_is_square():
+    """Coordinates may come as (N, d) or (d, N); a square array fits both and
+    must name its layout instead of being guessed."""
+    import torch
+    from paper_1607_05816_amd.uot import _coord_major
+    a = torch.arange(6.0).reshape(3, 2)                   # 3 points in R^2
+    assert torch.equal(_coord_major(a, 3, None, "x"), a.t())
+    assert torch.equal(_coord_major(a.t(), 3, None, "x"), a.t())
+    sq = torch.arange(4.0).reshape(2, 2)                  # 2 points in R^2
+    with pytest.raises(ValueError, match="layout"):
+        _coord_major(sq, 2, None, "x")
+    assert torch.equal(_coord_major(sq, 2, "nd", "x"), sq.t())
+    assert torch.equal(_coord_major(sq, 2, "dn", "x"), sq)
+    assert _coord_major(torch.arange(5.0), 5, None, "x").shape == (1, 5)
+    with pytest.raises(ValueError):
+        _coord_major(a, 4, None, "x")
