@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define UOT_ABI_VERSION 1
+#define UOT_ABI_VERSION 2
 
 enum uot_status_code {
   UOT_OK = 0,
@@ -205,6 +205,11 @@ typedef struct uot_result {
   int32_t status;        /* UOT_OK / UOT_NOT_CONVERGED / UOT_E_NONFINITE      */
   int32_t reserved;
   double elapsed_ms;     /* host wall time of the iteration loop              */
+  double du_inf;         /* max_i |u_i - u_i^prev| of the last iteration (the
+                            change of the X potentials, ABI version 2): eps
+                            times the Thompson distance of the scalings that
+                            Thm. "convergenceKL" contracts; +inf when a
+                            potential changed to or from -inf              */
 } uot_result;
 
 /* Values at the plan R = exp((u + v - C)/eps) (Thm. "duality"):

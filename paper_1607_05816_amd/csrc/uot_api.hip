@@ -794,6 +794,7 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
   if (rc) return rc;
   res->iters = ctx->pinned->iter;
   res->residual = ctx->pinned->res;
+  res->du_inf = ctx->pinned->du;
   res->status = ctx->pinned->status;
   res->elapsed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   return UOT_OK;

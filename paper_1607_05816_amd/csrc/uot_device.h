@@ -141,6 +141,7 @@ struct Ctrl {
   int64_t max_iter;
   double tol;
   double res;        // residual of the last iteration
+  double du;         // max |u_new - u_old| of the last iteration (potential units)
   double eps[2];     // eps of the iteration of parity p
   double eps_tab[kMaxStages + 1];
   double zeta;       // log z of a total-mass penalty (Algorithm 4); 0 otherwise
@@ -178,9 +179,10 @@ struct BItem {
   int32_t prob, row0, nrows, part;
 };
 
-// residual partial (per block): value = 2^m * {den, num} (m in log2 units)
+// residual partial (per block): value = 2^m * {den, num} (m in log2 units);
+// du: the block's largest |u_new - u_old| (potential units)
 struct ResPart {
-  float m, den, num, pad;
+  float m, den, num, du;
 };
 
 // ---------------------------------------------------------------------------
@@ -281,11 +283,12 @@ __device__ __forceinline__ float max_over_rows(float x) {
 
 // Reduce (m, den, num) over a wave with res_merge; every lane ends with the
 // wave total (up to rounding order).
-__device__ __forceinline__ void wave_res_reduce(float& m, float& den, float& num) {
-#define UOT_RES_STEP(MOVE)                                  \
-  {                                                         \
-    const float m2 = MOVE(m), d2 = MOVE(den), n2 = MOVE(num); \
-    res_merge<float>(m, den, num, m2, d2, n2);              \
+__device__ __forceinline__ void wave_res_reduce(float& m, float& den, float& num, float& du) {
+#define UOT_RES_STEP(MOVE)                                               \
+  {                                                                      \
+    const float m2 = MOVE(m), d2 = MOVE(den), n2 = MOVE(num), u2 = MOVE(du); \
+    res_merge<float>(m, den, num, m2, d2, n2);                           \
+    du = fmaxf(du, u2);                                                  \
   }
   UOT_RES_STEP(dpp_mov<kDppXor1>)
   UOT_RES_STEP(dpp_mov<kDppXor2>)
@@ -293,43 +296,51 @@ __device__ __forceinline__ void wave_res_reduce(float& m, float& den, float& num
   UOT_RES_STEP(dpp_mov<kDppMirror>)
 #undef UOT_RES_STEP
   {
-    const LanePair pm = lane_xor16(m), pd = lane_xor16(den), pn = lane_xor16(num);
+    const LanePair pm = lane_xor16(m), pd = lane_xor16(den), pn = lane_xor16(num), pu = lane_xor16(du);
     m = pm.a;
     den = pd.a;
     num = pn.a;
     res_merge<float>(m, den, num, pm.b, pd.b, pn.b);
+    du = fmaxf(pu.a, pu.b);
   }
   {
-    const LanePair pm = lane_xor32(m), pd = lane_xor32(den), pn = lane_xor32(num);
+    const LanePair pm = lane_xor32(m), pd = lane_xor32(den), pn = lane_xor32(num), pu = lane_xor32(du);
     m = pm.a;
     den = pd.a;
     num = pn.a;
     res_merge<float>(m, den, num, pm.b, pd.b, pn.b);
+    du = fmaxf(pu.a, pu.b);
   }
 }
 
-// Reduce (m, den, num) over a block of 256 threads (m in log2 units); thread
-// 0 writes the result.  Every thread of the block must call this.  The
-// partials only feed the stopping test, so FP32 with the hardware exp2 is
-// enough (relative error ~1e-7 on r).
+// Reduce (m, den, num) and the largest |du| over a block of 256 threads (m in
+// log2 units); thread 0 writes the result.  Every thread of the block must
+// call this.  The partials only feed the stopping test and the reported
+// sup-norm, so FP32 with the hardware exp2 is enough (relative error ~1e-7
+// on r; du is rounded once to FP32).
 template <typename T>
-__device__ __forceinline__ void block_res_reduce(T m_in, T den_in, T num_in, ResPart* out) {
-  __shared__ float sm[4][3];
-  float m = float(m_in), den = float(den_in), num = float(num_in);
-  wave_res_reduce(m, den, num);
+__device__ __forceinline__ void block_res_reduce(T m_in, T den_in, T num_in, T du_in, ResPart* out) {
+  __shared__ float sm[4][4];
+  float m = float(m_in), den = float(den_in), num = float(num_in), du = float(du_in);
+  wave_res_reduce(m, den, num, du);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     sm[w][0] = m;
     sm[w][1] = den;
     sm[w][2] = num;
+    sm[w][3] = du;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    float M = sm[0][0], D = sm[0][1], U = sm[0][2];
-    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) res_merge<float>(M, D, U, sm[k][0], sm[k][1], sm[k][2]);
+    float M = sm[0][0], D = sm[0][1], U = sm[0][2], X = sm[0][3];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+      res_merge<float>(M, D, U, sm[k][0], sm[k][1], sm[k][2]);
+      X = fmaxf(X, sm[k][3]);
+    }
     out->m = M;
     out->den = D;
     out->num = U;
+    out->du = X;
   }
 }
 

@@ -19,11 +19,12 @@ constexpr int kBlock = 256;
 // block (every thread of the block must call it).
 // ---------------------------------------------------------------------------
 template <typename T> struct ResAcc {
-  T m, den, num;
+  T m, den, num, du;   // du: largest |u_new - u_old| seen
   __device__ __forceinline__ void init() {
     m = Num<T>::ninf();
     den = T(0);
     num = T(0);
+    du = T(0);
   }
   __device__ __forceinline__ void add(T m2, T d2, T n2) { res_merge<T>(m, den, num, m2, d2, n2); }
 };
@@ -70,10 +71,15 @@ __device__ __forceinline__ void epi_apply(int64_t e, T S2, const EpiIn<T>& x, co
   if (vanish) return;
   if (ep.part) {
     if (un == Num<T>::ninf()) {
-      if (uo != Num<T>::ninf()) ra.add((S + uo / eps + ld) * T(kLog2e), T(0), T(1));
+      if (uo != Num<T>::ninf()) {
+        ra.add((S + uo / eps + ld) * T(kLog2e), T(0), T(1));
+        ra.du = Num<T>::pinf();           // a potential that jumped to -inf
+      }
     } else {
       const T d = Num<T>::expm1((uo - un) / eps);
       ra.add((S + un / eps + ld) * T(kLog2e), T(1), Num<T>::fmax(d, -d));
+      const T a = uo - un;
+      ra.du = Num<T>::fmax(ra.du, uo == Num<T>::ninf() ? Num<T>::pinf() : Num<T>::fmax(a, -a));
     }
   } else if (ep.mass_m) {
     // mass of the plan without z: the (m, den) pair of ra carries it
@@ -115,7 +121,7 @@ __device__ __forceinline__ void block_lse_reduce(T m, T s, T* out_m, T* out_s) {
 template <typename T>
 __device__ __forceinline__ void epi_finish(const EpiArgs<T>& ep, const ResAcc<T>& ra, int part_index) {
   if (ep.mode == EPI_RAW) return;
-  if (ep.part) block_res_reduce<T>(ra.m, ra.den, ra.num, ep.part + part_index);
+  if (ep.part) block_res_reduce<T>(ra.m, ra.den, ra.num, ra.du, ep.part + part_index);
   else if (ep.mass_m) block_lse_reduce<T>(ra.m, ra.den, ep.mass_m + part_index, ep.mass_s + part_index);
 }
 
@@ -153,9 +159,11 @@ __device__ __forceinline__ CtrlSnap ctrl_snap(const Ctrl* c, int par) {
 // iteration (parity par ^ 1) with its eps stage, stop when done.  A stopped
 // solve skips the next iteration; the control step of a skipped iteration
 // passes the skip on (control_skip), so every later iteration skips too.
-static __device__ void control_finish(Ctrl* c, const CtrlSnap& s, double r, double* __restrict__ hist, int par) {
+static __device__ void control_finish(Ctrl* c, const CtrlSnap& s, double r, double du, double* __restrict__ hist,
+                                      int par) {
   if (hist) hist[s.l] = r;
   c->res = r;
+  c->du = du;
   c->iter = s.l + 1;
   c->stage[par ^ 1] = s.sn;
   c->eps[par ^ 1] = s.eps_next;
@@ -184,21 +192,25 @@ __device__ __forceinline__ void control_skip(Ctrl* c, int par) { c->skip[par ^ 1
 
 // this thread's share of the residual partials of one problem
 __device__ __forceinline__ void ctl_load(const ResPart* __restrict__ part, int nparts, float& m, float& den,
-                                         float& num) {
+                                         float& num, float& du) {
   m = -__builtin_inff();
-  den = num = 0.f;
-  for (int k = threadIdx.x; k < nparts; k += kBlock) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
+  den = num = du = 0.f;
+  for (int k = threadIdx.x; k < nparts; k += kBlock) {
+    res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
+    du = fmaxf(du, part[k].du);
+  }
 }
 
 // block reduction of the shares and the control step (every thread of the
 // block calls it)
 __device__ __forceinline__ void ctl_reduce_finish(Ctrl* c, const CtrlSnap& snap, float m, float den, float num,
-                                                  double* __restrict__ hist, int par) {
+                                                  float du, double* __restrict__ hist, int par) {
   __shared__ ResPart tot;
   __syncthreads();   // the block's own reductions before this one are complete
-  block_res_reduce<float>(m, den, num, &tot);
+  block_res_reduce<float>(m, den, num, du, &tot);
   __syncthreads();
-  if (threadIdx.x == 0) control_finish(c, snap, res_ratio(double(tot.num), double(tot.den)), hist, par);
+  if (threadIdx.x == 0)
+    control_finish(c, snap, res_ratio(double(tot.num), double(tot.den)), double(tot.du), hist, par);
 }
 
 }  // namespace uot

@@ -98,10 +98,10 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
   const bool hosting = ep.host_ctl != nullptr && blockIdx.x == 0;
   const int par = par_of(side);
   CtrlSnap hsnap{};
-  float hm = -__builtin_inff(), hden = 0.f, hnum = 0.f;
+  float hm = -__builtin_inff(), hden = 0.f, hnum = 0.f, hdu = 0.f;
   if (hosting) {
     hsnap = ctrl_snap(ep.host_ctl, par);
-    ctl_load(ep.host_parts, ep.host_nparts, hm, hden, hnum);
+    ctl_load(ep.host_parts, ep.host_nparts, hm, hden, hnum, hdu);
   }
   // keep those loads ahead of the branch (otherwise they may be moved past it)
 #pragma unroll
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_tf(const float* __restrict__ in
     xin = xin_next;
   }
   epi_finish<float>(ep, ra, (int)lid);
-  if (hosting) ctl_reduce_finish(ep.host_ctl, hsnap, hm, hden, hnum, ep.host_hist, par);
+  if (hosting) ctl_reduce_finish(ep.host_ctl, hsnap, hm, hden, hnum, hdu, ep.host_hist, par);
 }
 
 // output tiles per block: 1 unless there are enough line groups to fill the

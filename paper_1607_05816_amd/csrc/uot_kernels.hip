@@ -196,10 +196,10 @@ __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in
   const bool hosting = !SPLIT && ep.host_ctl != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0;
   const int par = par_of(side);
   CtrlSnap hsnap{};
-  float hm = -__builtin_inff(), hden = 0.f, hnum = 0.f;
+  float hm = -__builtin_inff(), hden = 0.f, hnum = 0.f, hdu = 0.f;
   if (hosting) {
     hsnap = ctrl_snap(ep.host_ctl, par);
-    ctl_load(ep.host_parts, ep.host_nparts, hm, hden, hnum);
+    ctl_load(ep.host_parts, ep.host_nparts, hm, hden, hnum, hdu);
   }
   if (skip_side(c, side)) {
     if (hosting && threadIdx.x == 0) control_skip(ep.host_ctl, par);
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_contig(const T* __restrict__ in
     }
   }
   epi_finish<T>(ep, ra, (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
-  if (hosting) ctl_reduce_finish(ep.host_ctl, hsnap, hm, hden, hnum, ep.host_hist, par);
+  if (hosting) ctl_reduce_finish(ep.host_ctl, hsnap, hm, hden, hnum, hdu, ep.host_hist, par);
 }
 
 // ---------------------------------------------------------------------------
@@ -1046,26 +1046,31 @@ __device__ void control_step(Ctrl* __restrict__ c, const ResPart* __restrict__ p
                              double* __restrict__ hist, int nfields, int par) {
   // nfields > 0: the partials form nfields equal contiguous ranges (one per
   // field) and r is the largest per-field residual
-  __shared__ float smax[kBlock];
+  __shared__ float smax[kBlock], sdu[kBlock];
   const CtrlSnap snap = ctrl_snap(c, par);
-  float rmax = -1.0f;
+  float rmax = -1.0f, du = 0.f;
   const int per = nparts / nfields;
   for (int f = threadIdx.x; f < nfields; f += kBlock) {
     float m = -__builtin_inff(), den = 0.f, num = 0.f;
-    for (int k = f * per; k < (f + 1) * per; ++k) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
+    for (int k = f * per; k < (f + 1) * per; ++k) {
+      res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
+      du = fmaxf(du, part[k].du);
+    }
     const float rf = float(res_ratio(double(num), double(den)));
     rmax = (rf != rf || rmax != rmax) ? rf : (rf > rmax ? rf : rmax);
   }
   smax[threadIdx.x] = rmax;
+  sdu[threadIdx.x] = du;
   __syncthreads();
   for (int off = kBlock / 2; off >= 1; off >>= 1) {
     if ((int)threadIdx.x < off) {
       const float a = smax[threadIdx.x], b = smax[threadIdx.x + off];
       smax[threadIdx.x] = (a != a || b != b) ? (a != a ? a : b) : (a > b ? a : b);
+      sdu[threadIdx.x] = fmaxf(sdu[threadIdx.x], sdu[threadIdx.x + off]);
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) control_finish(c, snap, double(smax[0]), hist, par);
+  if (threadIdx.x == 0) control_finish(c, snap, double(smax[0]), double(sdu[0]), hist, par);
 }
 
 // control step of iteration parity par as its own launch.  Single problem:
@@ -1082,14 +1087,14 @@ __global__ __launch_bounds__(kBlock) void k_control(Ctrl* __restrict__ c, const 
     return;
   }
   const CtrlSnap snap = ctrl_snap(c, par);
-  float m, den, num;
-  ctl_load(part, nparts, m, den, num);
-  asm volatile("" ::"v"(m), "v"(den), "v"(num));
+  float m, den, num, du;
+  ctl_load(part, nparts, m, den, num, du);
+  asm volatile("" ::"v"(m), "v"(den), "v"(num), "v"(du));
   if (c->skip[par]) {
     if (threadIdx.x == 0) control_skip(c, par);
     return;
   }
-  ctl_reduce_finish(c, snap, m, den, num, hist, par);
+  ctl_reduce_finish(c, snap, m, den, num, du, hist, par);
 }
 
 // plain reduction of residual partials into out[0] (single half-step entry)

@@ -50,7 +50,7 @@ class UotParams(ctypes.Structure):
 
 class UotResult(ctypes.Structure):
     _fields_ = [("iters", c_i64), ("residual", c_dbl), ("status", c_i32), ("reserved", c_i32),
-                ("elapsed_ms", c_dbl)]
+                ("elapsed_ms", c_dbl), ("du_inf", c_dbl)]
 
 
 class UotObjectiveValues(ctypes.Structure):
@@ -405,8 +405,8 @@ def solve(prob: Problem, eps, ctx: Optional[Context] = None, v0=None, record=Fal
     code = lib().uot_solve(ctx.handle, ctypes.byref(prob.c), ctypes.byref(pr), _ptr(u), _ptr(v), _ptr(ws),
                            ws.numel(), ctypes.byref(res))
     _check(code, "uot_solve")
-    info = dict(iters=res.iters, residual=res.residual, status=res.status, elapsed_ms=res.elapsed_ms,
-                converged=(code == UOT_OK))
+    info = dict(iters=res.iters, residual=res.residual, du_inf=res.du_inf, status=res.status,
+                elapsed_ms=res.elapsed_ms, converged=(code == UOT_OK))
     if record:
         info["res_hist"] = hist[:res.iters].cpu()
     if time_kernels:
@@ -492,8 +492,8 @@ def solve_mass(prob: Problem, F3: Div, mass, eps, ctx: Optional[Context] = None,
     code = lib().uot_solve_mass(ctx.handle, ctypes.byref(prob.c), ctypes.byref(f3), float(mass), ctypes.byref(pr),
                                 _ptr(u), _ptr(v), ctypes.byref(lz), _ptr(ws), ws.numel(), ctypes.byref(res))
     _check(code, "uot_solve_mass")
-    info = dict(iters=res.iters, residual=res.residual, status=res.status, elapsed_ms=res.elapsed_ms,
-                converged=(code == UOT_OK))
+    info = dict(iters=res.iters, residual=res.residual, du_inf=res.du_inf, status=res.status,
+                elapsed_ms=res.elapsed_ms, converged=(code == UOT_OK))
     if record:
         info["res_hist"] = hist[:res.iters].cpu()
     return u, v, lz.value, info
@@ -527,8 +527,8 @@ def barycenter(shape, h, p, alpha, dx, dy, F1: Div, F2: Div, eps, ctx: Optional[
     code = lib().uot_barycenter(ctx.handle, ctypes.byref(bp), ctypes.byref(pr), _ptr(u), _ptr(v), _ptr(logh),
                                 _ptr(ws), ws.numel(), ctypes.byref(res))
     _check(code, "uot_barycenter")
-    info = dict(iters=res.iters, residual=res.residual, status=res.status, elapsed_ms=res.elapsed_ms,
-                converged=(code == UOT_OK))
+    info = dict(iters=res.iters, residual=res.residual, du_inf=res.du_inf, status=res.status,
+                elapsed_ms=res.elapsed_ms, converged=(code == UOT_OK))
     if record:
         info["res_hist"] = hist[:res.iters].cpu()
     return u, v, logh, info
@@ -728,8 +728,8 @@ def solve_fields(shape, h, p, q, dx, dy, F1: Div, F2: Div, eps, ctx: Optional[Co
     code = lib().uot_solve_fields(ctx.handle, ctypes.byref(pb), nb, ctypes.byref(pr), _ptr(u), _ptr(v), _ptr(ws),
                                   ws.numel(), ctypes.byref(res))
     _check(code, "uot_solve_fields")
-    info = dict(iters=res.iters, residual=res.residual, status=res.status, elapsed_ms=res.elapsed_ms,
-                converged=(code == UOT_OK))
+    info = dict(iters=res.iters, residual=res.residual, du_inf=res.du_inf, status=res.status,
+                elapsed_ms=res.elapsed_ms, converged=(code == UOT_OK))
     if record:
         info["res_hist"] = hist[:res.iters].cpu()
     return u, v, info

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     L = uot.lib()
-    assert L.uot_abi_version() == 1
+    assert L.uot_abi_version() == 2
     for code in (0, 1, -1, -2, -3, -4, -5):
         assert len(L.uot_status_string(code)) > 0
 

@@ -575,3 +575,53 @@ def test_mass_penalty_free_mass_and_partial_transport():
     R = np.exp((u.cpu().numpy()[:, None] + v.cpu().numpy()[None, :] - C) / eps + lz)
     assert np.sum(R * dx[:, None] * dy[None, :]) == pytest.approx(m0, rel=1e-8)
     assert np.all(R @ dy <= p * (1 + 1e-8)) and np.all(R.T @ dx <= q * (1 + 1e-8))
+
+
+# ---------------------------------------------------------------------------
+# sup-norm of the potential change (Thm. convergenceKL), reduced on the device
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_du_inf_matches_oracle(dtype):
+    """info["du_inf"] = max_i |u_i^K - u_i^(K-1)| of the last iteration
+    against the oracle's recorded iterates: point clouds (KL 0.5, 30
+    iterations) and a grid (TV 0.1 and KL 0.5, 25 iterations).  Each GPU
+    potential is within the parity tolerance of the oracle's (1e-11 FP64,
+    1e-5 FP32 of max(|u|, eps)), so their difference is within twice that;
+    the reduction rounds du_inf once to FP32 (2^-24 relative, the FP64 paths
+    included).  With zero densities the first iteration moves those
+    potentials from 0 to -inf: du_inf is +inf there and finite afterwards."""
+    tol = 2e-11 if dtype == torch.float64 else 2e-5
+    rng = np.random.default_rng(41)
+    x, y, p, q, dx, dy = points_case(rng, 300, 257, 2, dtype)
+    F = U.KL(0.5)
+    eps = 0.02
+    say("case du_inf clouds", dtype)
+    prob = gpu_points(x, y, p, q, dx, dy, F, F, dtype)
+    _, _, info = U.solve(prob, eps, tol=0.0, max_iter=30)
+    ref = oracle_points_run(x, y, p, q, dx, dy, F, F, eps, 30, record=True)
+    u29, u30 = ref["hist"][-2][0], ref["hist"][-1][0]
+    d_ref = float(np.max(np.abs(u30 - u29)))
+    scale = max(float(np.max(np.abs(u30))), eps)
+    assert abs(info["du_inf"] - d_ref) <= tol * scale + 2.0 ** -23 * d_ref, (info["du_inf"], d_ref)
+    assert d_ref > 100 * tol * scale        # the comparison is not vacuous
+    # (40, 33): direct passes; (48, 32): tile-factored passes in FP32 (their
+    # first Y pass hosts the control step)
+    for shape in ((40, 33), (48, 32)):
+        h, pg, qg, dg = grid_case(rng, shape, dtype)
+        G = O.GridGeom(shape, h)
+        for Fg in (U.TV(0.1), U.KL(0.5)):
+            say("case du_inf grid", dtype, shape, Fg)
+            prob = U.grid_problem(shape, h, T(pg, dtype), T(qg, dtype), T(dg, dtype), T(dg, dtype), Fg, Fg)
+            _, _, info = U.solve(prob, 0.01, tol=0.0, max_iter=25)
+            ref = O.solve(G, np.log(pg), np.log(qg), np.log(dg), np.log(dg), oracle_div(Fg), oracle_div(Fg), 0.01,
+                          tol=0.0, max_iter=25, record=True)
+            d_ref = float(np.max(np.abs(ref["hist"][-1][0] - ref["hist"][-2][0])))
+            scale = max(float(np.max(np.abs(ref["u"]))), 0.01)
+            assert abs(info["du_inf"] - d_ref) <= tol * scale + 2.0 ** -23 * d_ref, (Fg, info["du_inf"], d_ref)
+    # zero densities: -inf potentials appear at the first iteration only
+    pz = p.copy()
+    pz[[5, 9]] = 0.0
+    prob = gpu_points(x, y, pz, q, dx, dy, F, F, dtype)
+    _, _, info1 = U.solve(prob, eps, tol=0.0, max_iter=1)
+    _, _, info2 = U.solve(prob, eps, tol=0.0, max_iter=4)
+    assert info1["du_inf"] == math.inf and math.isfinite(info2["du_inf"])
