@@ -16,10 +16,10 @@ each, in dispatch order); --match keeps kernels whose name holds S.
 
 --pmc: the counter_collection.csv files of two `rocprofv3 --pmc FETCH_SIZE`
 and `--pmc WRITE_SIZE` runs of the same program.  Both counters read KiB per
-dispatch; each is calibrated by the largest `__amd_rocclr_copyBuffer`
+dispatch; each is calibrated by the largest single `__amd_rocclr_copyBuffer`
 dispatch of the run, a plain device copy of --copy-bytes bytes (it fetches
 and writes exactly that many), and the table gives calibrated bytes per
-launch.
+launch (--match keeps kernels whose name holds S).
 """
 import argparse
 import collections
@@ -48,18 +48,27 @@ def _counter_means(path):
     return {k: sum(v) / len(v) for k, v in agg.items()}, {k: len(v) for k, v in agg.items()}
 
 
-def summarize_pmc(fetch_csv, write_csv, copy_bytes, top=12):
+def _largest_copy(path):
+    """Counter value of the largest single __amd_rocclr_copyBuffer dispatch
+    (the calibration copy; other copies of the run share its kernel and
+    sometimes its launch size, so dispatches are not averaged here)."""
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+            if r["Kernel_Name"].split("(")[0].replace("void ", "") == "__amd_rocclr_copyBuffer"]
+    return max(vals)
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_bytes, top=12, match=None):
     f, nf = _counter_means(fetch_csv)
     w, _ = _counter_means(write_csv)
-    copies = [k for k in f if k[0] == "__amd_rocclr_copyBuffer"]
-    cal = max(copies, key=lambda k: f[k])
-    kf = copy_bytes / (f[cal] * 1024.0)
-    kw = copy_bytes / (w[cal] * 1024.0)
+    cf, cw = _largest_copy(fetch_csv), _largest_copy(write_csv)
+    kf = copy_bytes / (cf * 1024.0)
+    kw = copy_bytes / (cw * 1024.0)
     out = ["Calibration: copy of %d bytes reads FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB -> factors %.4f (fetch), "
-           "%.4f (write)." % (copy_bytes, f[cal], w[cal], kf, kw), "",
+           "%.4f (write)." % (copy_bytes, cf, cw, kf, kw), "",
            "| kernel | grid (work-items) | launches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | read (bytes) | written (bytes) |",
            "|:--|:--|--:|--:|--:|--:|--:|"]
-    for k in sorted(f, key=lambda k: -f[k] * nf[k])[:top]:
+    keys = [k for k in f if not match or match in k[0]]
+    for k in sorted(keys, key=lambda k: -f[k] * nf[k])[:top]:
         wk = w.get(k, float("nan"))
         out.append("| `%s` | %d | %d | %.1f | %.1f | %.0f | %.0f |" % (k[0], k[1], nf[k], f[k], wk, f[k] * 1024 * kf,
                                                                    wk * 1024 * kw))
@@ -102,7 +111,7 @@ def main():
     if a.counters:
         print(summarize_counters(a.counters, a.match, a.last))
     elif a.pmc:
-        print(summarize_pmc(a.pmc[0], a.pmc[1], a.copy_bytes, a.top))
+        print(summarize_pmc(a.pmc[0], a.pmc[1], a.copy_bytes, a.top, a.match))
     else:
         print(summarize(a.db, a.top))
 
