@@ -229,6 +229,9 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, q = lane >> 4;
   const int wbase = wv * (16 * G);
+  // a wave with no valid row (the last rows of a ragged item) only helps to
+  // stage the column operands: its product passes are skipped (wave-uniform)
+  const bool wave_rows = wbase < nrow;
   // the block centre: middle of the box of its valid rows
   float xb[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -351,6 +354,7 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
       // chunk) takes the maximum pass first; others run the sum pass against
       // the running maxima and take the two passes only when a row's sum leaves
       // [0, 2^100) (a new maximum far above the old one)
+      if (!wave_rows) continue;             // (after the staging and its barriers)
       bool two = false;
 #pragma unroll
       for (int g = 0; g < G; ++g) two = two || m[g] == -__builtin_inff();
@@ -417,6 +421,7 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
       tot[g] = sum_over_rows(s[g]);
       redo = redo || (m[g] != -__builtin_inff() && !(tot[g] >= 0x1p-60f)) || !(tot[g] < 0x1p100f);
     }
+    redo = redo && wave_rows;
     if (attempt > 0 || !__syncthreads_or(redo)) break;
   }
   // row constants R_i = -c |e_i|^2
@@ -474,8 +479,9 @@ __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ x
 // the item's rows with all columns of the problem (the clouds in Morton
 // order per problem) and apply the proxdiv epilogue; pw: starting maxima per
 // row, left for the next iteration.
+// (4 row groups per wave fit 128 VGPRs: 4 waves per SIMD; 8 groups take 2)
 template <int DIM, int G, bool SPLIT>
-__global__ __launch_bounds__(kBlock) void k_batch_mf(const BItem* __restrict__ items, int n_items,
+__global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_batch_mf(const BItem* __restrict__ items, int n_items,
                                                       int* __restrict__ cursor, const int64_t* __restrict__ offR,
                                                       const int64_t* __restrict__ offC, const float* __restrict__ xr,
                                                       int64_t totR, const float* __restrict__ yc, int64_t totC,
@@ -505,13 +511,19 @@ __global__ __launch_bounds__(kBlock) void k_batch_mf(const BItem* __restrict__ i
                                 tot, rc);
     ResAcc<float> ra;
     ra.init();
+    // every lane of a row holds its (m, total); lane (q, l) finishes row
+    // 16 (4 h + q) + l of the wave, so each epilogue round has all 64 lanes
+    // busy (G / 4 rounds instead of G rounds of 16 lanes)
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int row = wv * (16 * G) + g * 16 + li;
-      if (q == 0 && row < I.nrows) {
-        const float lse = m[g] == -__builtin_inff() ? m[g] : m[g] + rc[g] + __builtin_log2f(tot[g]);
+    for (int h = 0; h < G / 4; ++h) {
+      const float mg = q == 0 ? m[4 * h] : (q == 1 ? m[4 * h + 1] : (q == 2 ? m[4 * h + 2] : m[4 * h + 3]));
+      const float tg = q == 0 ? tot[4 * h] : (q == 1 ? tot[4 * h + 1] : (q == 2 ? tot[4 * h + 2] : tot[4 * h + 3]));
+      const float rg = q == 0 ? rc[4 * h] : (q == 1 ? rc[4 * h + 1] : (q == 2 ? rc[4 * h + 2] : rc[4 * h + 3]));
+      const int row = wv * (16 * G) + (4 * h + q) * 16 + li;
+      if (row < I.nrows) {
+        const float lse = mg == -__builtin_inff() ? mg : mg + rg + __builtin_log2f(tg);
         epi_elem<float>(rb + row, lse, c, side, ep, ra);
-        pw[rb + row] = m[g];
+        pw[rb + row] = mg;
       }
     }
     epi_finish<float>(ep, ra, I.part);
