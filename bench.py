@@ -214,8 +214,12 @@ def ragged_headline(U, ctx, dev, np, torch, steps, warmup):
             "note": "average over every product launch of a warm solve (converged problems' items exit at once)"}
     tr = batch_traffic(kname, int(tk["tile_rows"]))
     if tr is not None:
-        roof["traffic"] = float(sum(tr))
-        roof["traffic_read_written"] = list(tr)
+        # counters were read on full launches; the average launch carries
+        # work_per_launch pairs, and the bytes scale with the pairs
+        per_pair = (tr[0] + tr[1]) / tr[2]
+        roof["traffic"] = per_pair * work / launches
+        roof["traffic_full_launch"] = {"read": tr[0], "written": tr[1], "pairs": tr[2]}
+        roof["traffic_note"] = "calibrated FETCH_SIZE + WRITE_SIZE of full launches, scaled by pairs"
     return {
         "value": len(probs) * steps / dt,
         "ms_per_step": dt / steps * 1e3,
@@ -344,8 +348,11 @@ TRAFFIC_BYTES = {
 # runs of `bench.py --pmc-workload batch`; valid for the source they were
 # taken on (sha256 of the product's file and the headers it includes).
 BATCH_TRAFFIC_SOURCES = ["uot_dense_mf.hip", "uot_epilogue.h", "uot_device.h", "uot_launch.h"]
-BATCH_TRAFFIC_SHA256 = None
-BATCH_TRAFFIC_BYTES = {}
+BATCH_TRAFFIC_SHA256 = "5a958ffcdce93c81f00f6fd9a988c2e7530deef7138925184d8d13a323dee636"
+# (kernel, rows per item) -> (bytes read, bytes written, pair evaluations) of
+# one launch that holds every problem (the counter workload: all 4096
+# problems active, warm maxima)
+BATCH_TRAFFIC_BYTES = {("k_batch_mf", 256): (247071674, 52733956, 3782323547)}
 
 
 def _sha256(names):
@@ -358,8 +365,8 @@ def _sha256(names):
 
 
 def batch_traffic(kernel, tile_rows):
-    """(bytes read, bytes written) per launch of the batched product, or None
-    once its source changed."""
+    """(bytes read, bytes written, pairs) of a full launch of the batched
+    product, or None once its source changed."""
     if BATCH_TRAFFIC_SHA256 is None or _sha256(BATCH_TRAFFIC_SOURCES) != BATCH_TRAFFIC_SHA256:
         return None
     return BATCH_TRAFFIC_BYTES.get((kernel, tile_rows))
