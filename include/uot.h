@@ -551,9 +551,15 @@ int uot_bary_estimate(uot_ctx *ctx, const float *p, int n, int64_t size, const d
 int uot_grid_upsample(uot_ctx *ctx, const float *y, int64_t nb, int r, int R, float *out);
 /* the MFMA BF16 GEMM of the network, exposed for checking:
  * C[M x N] = op(A) op(B), op(A)[m][k] = ta ? A[k*lda+m] : A[m*lda+k],
- * op(B)[k][n] = tb ? B[n*ldb+k] : B[k*ldb+n]; A, B BF16 bits, C FP32 */
+ * op(B)[k][n] = tb ? B[n*ldb+k] : B[k*ldb+n]; A, B BF16 bits, C FP32.
+ * A product with few output tiles and a long K splits K over blocks whose
+ * partial tiles go to the workspace (uot_gemm_workspace_size bytes, device,
+ * 256-byte aligned; 0 when it does not split) and are added in a fixed order;
+ * with ws NULL (or too small) it runs unsplit. */
+int uot_gemm_workspace_size(int M, int N, int K, size_t *bytes);
 int uot_gemm_bf16(uot_ctx *ctx, int ta, int tb, int M, int N, int K, const uint16_t *A,
-                  int64_t lda, const uint16_t *B, int64_t ldb, float *C, int64_t ldc);
+                  int64_t lda, const uint16_t *B, int64_t ldb, float *C, int64_t ldc,
+                  void *ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------------------
  * Measurement helpers (roofline evidence; not part of the iteration).
@@ -582,7 +588,7 @@ int uot_time_fields_half_step(uot_ctx *ctx, const uot_problem *pb, int nb, doubl
  * `reps` back-to-back launches on the library stream (HIP events). */
 int uot_time_gemm_bf16(uot_ctx *ctx, int ta, int tb, int M, int N, int K, const uint16_t *A,
                        int64_t lda, const uint16_t *B, int64_t ldb, float *C, int64_t ldc,
-                       int reps, double *ms);
+                       int reps, double *ms, void *ws, size_t ws_bytes);
 
 /* Throughput probe of the current device: v_exp_f32 results per second and
  * v_add_f32 results per second, from 8 independent dependency chains per lane

@@ -45,8 +45,10 @@ static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1
 //   TB = false: B[k][n] = B[k*ldb + n];  TB = true: B[k][n] = B[n*ldb + k]
 // Block tile 64 x 64, K tile 32, 4 waves of 32 x 32 (2 x 2 MFMA 16x16x32).
 // Split K (blockIdx.z): each block sums the K range [z kc, (z + 1) kc) and
-// adds its partial into C with FP32 atomics (C cleared beforehand; split 0
-// adds the bias); used when there are too few output tiles to fill the chip.
+// stores its partial tile in P[z] (M x N, row-major); k_splitk_reduce then
+// adds the partials in a fixed order, with the bias, into C.  Used when there
+// are too few output tiles to fill the chip and the caller gives room for the
+// partials.
 // Operands move as 16-byte vectors along their contiguous axis where the
 // leading dimension and the tile edge allow, element by element otherwise.
 // ---------------------------------------------------------------------------
@@ -101,11 +103,27 @@ __device__ __forceinline__ void store_tile(u16 (*T)[LK], const u16 (&v)[8]) {
   }
 }
 
+// store_tile into a whole-K LDS array (rows of LW elements) at column k0
+template <bool TRANS, int LD>
+__device__ __forceinline__ void store_tile_at(u16 (*T)[LD], int k0, const u16 (&v)[8]) {
+  const int tid = threadIdx.x;
+  if (!TRANS) {
+    const int r = tid >> 2, c = (tid & 3) * 8;
+    uint4 q;
+    __builtin_memcpy(&q, v, sizeof(q));
+    *reinterpret_cast<uint4*>(&T[r][k0 + c]) = q;
+  } else {
+    const int kk = tid >> 3, c = (tid & 7) * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) T[c + j][k0 + kk] = v[j];
+  }
+}
+
 template <bool TA, bool TB>
 __global__ __launch_bounds__(kB) void k_gemm(const u16* __restrict__ A, int64_t lda, const u16* __restrict__ Bm,
                                               int64_t ldb, int M, int N, int K, float* __restrict__ C, int64_t ldc,
                                               u16* __restrict__ Cb, const float* __restrict__ bias, int relu, int kc,
-                                              int split) {
+                                              float* __restrict__ P) {
   __shared__ __align__(16) u16 As[TM][LK];
   __shared__ __align__(16) u16 Bs[TN][LK];
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
@@ -156,10 +174,10 @@ __global__ __launch_bounds__(kB) void k_gemm(const u16* __restrict__ A, int64_t 
         const int n = n0 + wn + j * 16 + (lane & 15);
         if (m < M && n < N) {
           float x = acc[i][j][r];
-          if (bias && blockIdx.z == 0) x += bias[n];
-          if (split) {
-            atomicAdd(&C[(int64_t)m * ldc + n], x);
+          if (P) {
+            P[((int64_t)blockIdx.z * M + m) * N + n] = x;
           } else {
+            if (bias) x += bias[n];
             if (relu) x = x > 0.f ? x : 0.f;
             if (C) C[(int64_t)m * ldc + n] = x;
             if (Cb) Cb[(int64_t)m * ldc + n] = f2bf(x);
@@ -168,38 +186,148 @@ __global__ __launch_bounds__(kB) void k_gemm(const u16* __restrict__ A, int64_t 
       }
 }
 
-// C[m][n] = 0 for m < M, n < N
-__global__ void k_zero2d(float* __restrict__ C, int M, int N, int64_t ldc) {
+// The same product for a K range of at most kWholeK per block (every product
+// of the network at batch 256 after its K split): the block loads its whole
+// K range of both operands into LDS first (every global load in flight at
+// once, one memory round trip), then runs the MFMAs of all K tiles; the
+// stepped kernel above waits for one round trip per K tile.
+constexpr int kWholeK = 256, LW = kWholeK + 8;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(kB) void k_gemm_whole(const u16* __restrict__ A, int64_t lda,
+                                                    const u16* __restrict__ Bm, int64_t ldb, int M, int N, int K,
+                                                    float* __restrict__ C, int64_t ldc, u16* __restrict__ Cb,
+                                                    const float* __restrict__ bias, int relu, int kc,
+                                                    float* __restrict__ P) {
+  extern __shared__ __align__(16) u16 lds[];
+  u16(*As)[LW] = reinterpret_cast<u16(*)[LW]>(lds);
+  u16(*Bs)[LW] = reinterpret_cast<u16(*)[LW]>(lds + TM * LW);
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int kb = blockIdx.z * kc;
+  const int ke = kb + kc < K ? kb + kc : K;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  const bool va = (lda % 8) == 0 && (reinterpret_cast<uintptr_t>(A) % 16) == 0;
+  const bool vb = (ldb % 8) == 0 && (reinterpret_cast<uintptr_t>(Bm) % 16) == 0;
+  const int nkt = (ke - kb + TK - 1) / TK;   // K tiles of this block, <= kWholeK / TK
+  u16 ra[kWholeK / TK][8], rb[kWholeK / TK][8];
+#pragma unroll
+  for (int t = 0; t < kWholeK / TK; ++t) {
+    if (t < nkt) {
+      fetch_tile<TA>(ra[t], A, lda, m0, M, kb + t * TK, ke, va);
+      fetch_tile<!TB>(rb[t], Bm, ldb, n0, N, kb + t * TK, ke, vb);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kWholeK / TK; ++t) {
+    if (t < nkt) {
+      store_tile_at<TA>(As, t * TK, ra[t]);
+      store_tile_at<!TB>(Bs, t * TK, rb[t]);
+    }
+  }
+  __syncthreads();
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < nkt; ++t) {
+    const int kk = t * TK + (lane >> 4) * 8;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + (lane & 15)][kk]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 16 + (lane & 15)][kk]);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < M && n < N) {
+          float x = acc[i][j][r];
+          if (P) {
+            P[((int64_t)blockIdx.z * M + m) * N + n] = x;
+          } else {
+            if (bias) x += bias[n];
+            if (relu) x = x > 0.f ? x : 0.f;
+            if (C) C[(int64_t)m * ldc + n] = x;
+            if (Cb) Cb[(int64_t)m * ldc + n] = f2bf(x);
+          }
+        }
+      }
+}
+
+// C[m][n] = bias[n] + sum_z P[z][m][n] (z in order: the result does not
+// depend on the schedule)
+__global__ void k_splitk_reduce(const float* __restrict__ P, int S, int M, int N, const float* __restrict__ bias,
+                                float* __restrict__ C, int64_t ldc) {
   const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (t >= (int64_t)M * N) return;
-  C[(t / N) * ldc + t % N] = 0.f;
+  const int64_t mn = (int64_t)M * N;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  int z = 0;
+  for (; z + 4 <= S; z += 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += P[(z + k) * mn + t];
+  }
+  for (; z < S; ++z) acc[0] += P[z * mn + t];
+  const int n = (int)(t % N);
+  C[(t / N) * ldc + n] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + (bias ? bias[n] : 0.f);
 }
+
+constexpr int kMaxSplitK = 32;
 
 // K-splits for a product: enough blocks for the chip (>= 512) when the
 // output has few tiles and K is long; 1 when the result needs ReLU or BF16
-// (those are not additive), or when the caller asks for plain launches
+// (those are not additive)
 static int gemm_splits(int M, int N, int K, bool additive) {
-  static const int mode = [] {
-    const char* v = std::getenv("UOT_GEMM_SPLITK");
-    return v ? std::atoi(v) : 1;
-  }();
-  if (!additive || mode == 0) return 1;
+  if (!additive) return 1;
   const int64_t tiles = (int64_t)cdiv(M, TM) * cdiv(N, TN);
   int s = 1;
-  while (tiles * s < 512 && K / (2 * s) >= 256) s *= 2;
+  while (tiles * s < 512 && K / (2 * s) >= 256 && 2 * s <= kMaxSplitK) s *= 2;
   return s;
+}
+
+// floats of partials a product needs (0: no split)
+static int64_t gemm_partials(int M, int N, int K, bool additive) {
+  const int sp = gemm_splits(M, N, K, additive);
+  return sp > 1 ? (int64_t)sp * M * N : 0;
 }
 
 template <bool TA, bool TB>
 static void gemm(const u16* A, int64_t lda, const u16* B, int64_t ldb, int M, int N, int K, float* C, int64_t ldc,
-                 u16* Cb, const float* bias, int relu, hipStream_t s) {
-  const int sp = gemm_splits(M, N, K, C != nullptr && Cb == nullptr && !relu);
+                 u16* Cb, const float* bias, int relu, hipStream_t s, float* part = nullptr,
+                 int64_t part_floats = 0) {
+  const bool additive = C != nullptr && Cb == nullptr && !relu;
+  int sp = gemm_splits(M, N, K, additive);
+  if (!part || (int64_t)sp * M * N > part_floats) sp = 1;
   const int kc = sp > 1 ? (int)(cdiv(cdiv(K, sp), TK) * TK) : K;
   const int sz = sp > 1 ? (int)cdiv(K, kc) : 1;
+  const dim3 grid(cdiv(N, TN), cdiv(M, TM), sz);
+  constexpr int whole_lds = 2 * TM * LW * sizeof(u16);   // 66 KB: above the default 64 KB limit
+  static const bool whole_ok = [] {
+    const bool ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_whole<TA, TB>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, whole_lds) == hipSuccess;
+    if (!ok) (void)hipGetLastError();   // the stepped kernel runs instead; clear the error
+    return ok;
+  }();
+  if (kc <= kWholeK && whole_ok)
+    hipLaunchKernelGGL((k_gemm_whole<TA, TB>), grid, dim3(kB), whole_lds, s, A, lda, B, ldb, M, N, K, C, ldc, Cb, bias,
+                       relu, kc, sz > 1 ? part : nullptr);
+  else
+    hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(kB), 0, s, A, lda, B, ldb, M, N, K, C, ldc, Cb, bias, relu, kc,
+                       sz > 1 ? part : nullptr);
   if (sz > 1)
-    hipLaunchKernelGGL(k_zero2d, dim3(cdiv((int64_t)M * N, kB)), dim3(kB), 0, s, C, M, N, ldc);
-  hipLaunchKernelGGL((k_gemm<TA, TB>), dim3(cdiv(N, TN), cdiv(M, TM), sz), dim3(kB), 0, s, A, lda, B, ldb, M, N, K, C,
-                     ldc, Cb, bias, relu, kc, sz > 1 ? 1 : 0);
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(cdiv((int64_t)M * N, kB)), dim3(kB), 0, s, part, sz, M, N, bias, C,
+                       ldc);
 }
 
 // y = bf16(scale * x + shift)
@@ -452,6 +580,8 @@ struct Act {
   u16* g;           // batch x width
   double* part;     // loss partials
   float* grad;      // gradient (parameter-sized)
+  float* splitk;    // split-K partials of the long-K products
+  int64_t splitk_floats;
   size_t total;
 };
 
@@ -475,6 +605,11 @@ Act carve(const uot_net* n, int64_t batch, char* ws) {
   a.g = reinterpret_cast<u16*>(take(2 * batch * n->width));
   a.part = reinterpret_cast<double*>(take(8 * (size_t)cdiv(batch * n->n_out, kB)));
   a.grad = reinterpret_cast<float*>(take(4 * L.total));
+  // the additive products that can split: layer 1 forward, input gradients
+  int64_t sk = gemm_partials((int)batch, L.out[0], L.in[0], true);
+  for (int l = 1; l < 4; ++l) sk = std::max(sk, gemm_partials((int)batch, L.in[l], L.out[l], true));
+  a.splitk_floats = sk;
+  a.splitk = reinterpret_cast<float*>(take(4 * (size_t)sk));
   a.total = o;
   return a;
 }
@@ -492,7 +627,7 @@ void forward(const uot_net* n, const Layout& L, const Act& a, const float* x, in
   const u16* inp = a.xb;
   for (int l = 0; l < 3; ++l) {
     gemm<false, true>(inp, L.in[l], n->wbf16 + L.w[l], L.in[l], (int)batch, L.out[l], L.in[l], a.z[l], L.out[l],
-                      nullptr, n->master + L.b[l], 0, s);
+                      nullptr, n->master + L.b[l], 0, s, a.splitk, a.splitk_floats);
     // ReLU copy in BF16 (z keeps the pre-activation for the backward mask)
     hipLaunchKernelGGL(k_relu_grad, dim3(cdiv(batch * L.out[l], kB)), dim3(kB), 0, s, a.z[l], a.z[l], a.h[l],
                        batch * L.out[l]);
@@ -516,7 +651,7 @@ void backward(const uot_net* n, const Layout& L, const Act& a, const float* t, i
     if (l == 0) break;
     // dh_{l-1} [batch x in] = g [batch x out] * W_l [out x in], then the ReLU mask
     gemm<false, false>(g, L.out[l], n->wbf16 + L.w[l], L.in[l], (int)batch, L.in[l], L.out[l], a.dh, L.in[l], nullptr,
-                       nullptr, 0, s);
+                       nullptr, 0, s, a.splitk, a.splitk_floats);
     hipLaunchKernelGGL(k_relu_grad, dim3(cdiv(batch * L.in[l], kB)), dim3(kB), 0, s, a.dh, a.z[l - 1], a.g,
                        batch * L.in[l]);
     g = a.g;
@@ -711,31 +846,54 @@ int uot_bary_local_v0(uot_ctx* ctx, const float* p, const float* h0, int n, int 
   return finish(ctx);
 }
 
+int uot_gemm_workspace_size(int M, int N, int K, size_t* bytes) {
+  if (!bytes || M < 1 || N < 1 || K < 1) return fail(UOT_E_INVALID, "bad arguments");
+  *bytes = 4 * (size_t)gemm_partials(M, N, K, true);
+  return UOT_OK;
+}
+
+static int gemm_ws_check(const void* ws, size_t wsb, float*& part, int64_t& floats) {
+  part = nullptr;
+  floats = 0;
+  if (!ws) return UOT_OK;
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(UOT_E_WORKSPACE, "workspace must be 256-byte aligned");
+  part = static_cast<float*>(const_cast<void*>(ws));
+  floats = (int64_t)(wsb / 4);
+  return UOT_OK;
+}
+
 int uot_gemm_bf16(uot_ctx* ctx, int ta, int tb, int M, int N, int K, const uint16_t* A, int64_t lda, const uint16_t* B,
-                  int64_t ldb, float* C, int64_t ldc) {
+                  int64_t ldb, float* C, int64_t ldc, void* ws, size_t wsb) {
   if (!ctx || !A || !B || !C || M < 1 || N < 1 || K < 1) return fail(UOT_E_INVALID, "bad arguments");
-  int rc = begin(ctx);
+  float* part;
+  int64_t pf;
+  int rc = gemm_ws_check(ws, wsb, part, pf);
   if (rc) return rc;
+  if ((rc = begin(ctx))) return rc;
   hipStream_t s = ctx->work;
-  if (!ta && !tb) gemm<false, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
-  else if (!ta && tb) gemm<false, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
-  else if (ta && !tb) gemm<true, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
-  else gemm<true, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
+  if (!ta && !tb) gemm<false, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s, part, pf);
+  else if (!ta && tb) gemm<false, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s, part, pf);
+  else if (ta && !tb) gemm<true, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s, part, pf);
+  else gemm<true, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s, part, pf);
   HIP_TRY(hipGetLastError());
   return finish(ctx);
 }
 
 int uot_time_gemm_bf16(uot_ctx* ctx, int ta, int tb, int M, int N, int K, const uint16_t* A, int64_t lda,
-                       const uint16_t* B, int64_t ldb, float* C, int64_t ldc, int reps, double* ms) {
+                       const uint16_t* B, int64_t ldb, float* C, int64_t ldc, int reps, double* ms, void* ws,
+                       size_t wsb) {
   if (!ctx || !A || !B || !C || !ms || M < 1 || N < 1 || K < 1 || reps < 1) return fail(UOT_E_INVALID, "bad arguments");
-  int rc = begin(ctx);
+  float* part;
+  int64_t pf;
+  int rc = gemm_ws_check(ws, wsb, part, pf);
   if (rc) return rc;
+  if ((rc = begin(ctx))) return rc;
   hipStream_t s = ctx->work;
   auto run = [&] {
-    if (!ta && !tb) gemm<false, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
-    else if (!ta && tb) gemm<false, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
-    else if (ta && !tb) gemm<true, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
-    else gemm<true, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s);
+    if (!ta && !tb) gemm<false, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s, part, pf);
+    else if (!ta && tb) gemm<false, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s, part, pf);
+    else if (ta && !tb) gemm<true, false>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s, part, pf);
+    else gemm<true, true>(A, lda, B, ldb, M, N, K, C, ldc, nullptr, nullptr, 0, s, part, pf);
   };
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));

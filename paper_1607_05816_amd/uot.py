@@ -136,9 +136,11 @@ def lib():
         "uot_warmstart_features": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_i32, c_i32, c_vp]),
         "uot_grid_upsample": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, c_vp]),
         "uot_bary_estimate": (c_i32, [c_vp, c_vp, c_i32, c_i64, P(c_dbl), c_dbl, P(UotDiv), c_vp]),
-        "uot_gemm_bf16": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64]),
+        "uot_gemm_workspace_size": (c_i32, [c_i32, c_i32, c_i32, P(ctypes.c_size_t)]),
+        "uot_gemm_bf16": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,
+                                  c_vp, ctypes.c_size_t]),
         "uot_time_gemm_bf16": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,
-                                       c_i32, P(c_dbl)]),
+                                       c_i32, P(c_dbl), c_vp, ctypes.c_size_t]),
         "uot_bary_local_v0": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_dbl, c_dbl, c_dbl, c_dbl, c_vp]),
         "uot_batch_gibbs": (c_i32, [c_vp, P(UotBatchProblem), c_dbl, c_i32, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t]),
         "uot_cloud_features_workspace_size": (c_i32, [P(UotBatchProblem), P(ctypes.c_size_t)]),
@@ -743,13 +745,23 @@ def bf16_bits(t: torch.Tensor) -> torch.Tensor:
     return t.to(torch.bfloat16).view(torch.int16)
 
 
-def gemm_bf16(A_bits, B_bits, M, N, K, ta=False, tb=False, lda=None, ldb=None, ctx: Optional[Context] = None):
+def _gemm_workspace(M, N, K, device):
+    n = ctypes.c_size_t()
+    _check(lib().uot_gemm_workspace_size(M, N, K, ctypes.byref(n)), "uot_gemm_workspace_size", False)
+    return workspace(n.value, device) if n.value else None
+
+
+def gemm_bf16(A_bits, B_bits, M, N, K, ta=False, tb=False, lda=None, ldb=None, ctx: Optional[Context] = None,
+              split=True):
+    """C = op(A) op(B) on BF16 bits (uot_gemm_bf16); split=False runs it
+    without K splits (no workspace)."""
     ctx = ctx or default_context()
     C = torch.empty(M, N, dtype=torch.float32, device=A_bits.device)
     lda = lda if lda is not None else (M if ta else K)
     ldb = ldb if ldb is not None else (K if tb else N)
+    ws = _gemm_workspace(M, N, K, A_bits.device) if split else None
     _check(lib().uot_gemm_bf16(ctx.handle, int(ta), int(tb), M, N, K, _ptr(A_bits), lda, _ptr(B_bits), ldb, _ptr(C),
-                               N), "uot_gemm_bf16", False)
+                               N, _ptr(ws), 0 if ws is None else ws.numel()), "uot_gemm_bf16", False)
     return C
 
 
@@ -760,8 +772,10 @@ def time_gemm_bf16(A_bits, B_bits, M, N, K, ta=False, tb=False, reps=20, ctx: Op
     lda = M if ta else K
     ldb = K if tb else N
     ms = c_dbl()
+    ws = _gemm_workspace(M, N, K, A_bits.device)
     _check(lib().uot_time_gemm_bf16(ctx.handle, int(ta), int(tb), M, N, K, _ptr(A_bits), lda, _ptr(B_bits), ldb,
-                                    _ptr(C), N, int(reps), ctypes.byref(ms)), "uot_time_gemm_bf16", False)
+                                    _ptr(C), N, int(reps), ctypes.byref(ms), _ptr(ws), 0 if ws is None else ws.numel()),
+           "uot_time_gemm_bf16", False)
     return ms.value
 
 
