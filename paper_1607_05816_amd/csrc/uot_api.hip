@@ -1486,9 +1486,9 @@ struct BatchPlan {
   int64_t max_items = 0;       // items per side at R = 1 (upper bound for any R)
   int64_t nmaxN = 0, nmaxM = 0;   // largest problem per side
   bool mf = false;                // FP32: the matrix-core product is among the tuner's choices
-  size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_stop, o_yskip, o_status, o_iters, o_res, o_clock,
-      o_itx, o_ity, o_pstart, o_parts, o_curs, o_offN, o_offM, o_xs, o_ys, o_permx, o_permy, o_code, o_box, o_us,
-      o_vs, o_pw, total;
+  size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_stop, o_yskip, o_status, o_iters, o_res, o_clock, o_itx,
+      o_ity, o_pstart, o_parts, o_curs, o_offN, o_offM, o_ordx, o_ordy, o_xs, o_ys, o_permx, o_permy, o_code, o_box,
+      o_us, o_vs, o_pw, total;
 };
 
 int make_batch_plan(BatchPlan& P, const uot_batch_problem* pb) {
@@ -1538,9 +1538,11 @@ int make_batch_plan(BatchPlan& P, const uot_batch_problem* pb) {
   P.o_ity = take(sizeof(BItem) * P.max_items);
   P.o_pstart = take(4 * (P.B + 1));
   P.o_parts = take(sizeof(ResPart) * P.max_items);
-  P.o_curs = take(4 * 2);
+  P.o_curs = take(4 * 4);   // lengths of the two item lists, then their work cursors
   P.o_offN = take(8 * (P.B + 1));
   P.o_offM = take(8 * (P.B + 1));
+  P.o_ordx = take(4 * P.B);
+  P.o_ordy = take(4 * P.B);
   // FP32: Morton-ordered copies per problem for the matrix-core product
   // (coordinates, permutations, codes, boxes, potentials) and its row maxima
   P.mf = P.dtype == UOT_F32;
@@ -1558,17 +1560,14 @@ int make_batch_plan(BatchPlan& P, const uot_batch_problem* pb) {
   return UOT_OK;
 }
 
-// work items of one side for rows per item 256*R, sorted by cost (largest first);
-// X items also get problem-major residual slots (pstart)
-void build_items(const int64_t* offR, const int64_t* offC, int64_t B, int R, std::vector<BItem>& items,
-                 std::vector<int32_t>* pstart) {
+// every work item of one side for rows per item 256*R, sorted by cost
+// (largest first): the fixed lists of the plain batch Gibbs products
+void build_items(const int64_t* offR, const int64_t* offC, int64_t B, int R, std::vector<BItem>& items) {
   items.clear();
-  if (pstart) pstart->assign(B + 1, 0);
   const int rows = 256 * R;
   int32_t slot = 0;
   for (int64_t b = 0; b < B; ++b) {
     const int64_t n = offR[b + 1] - offR[b];
-    if (pstart) (*pstart)[b] = slot;
     for (int64_t r0 = 0; r0 < n; r0 += rows) {
       BItem it;
       it.prob = (int32_t)b;
@@ -1578,12 +1577,36 @@ void build_items(const int64_t* offR, const int64_t* offC, int64_t B, int R, std
       items.push_back(it);
     }
   }
-  if (pstart) (*pstart)[B] = slot;
   std::stable_sort(items.begin(), items.end(), [&](const BItem& a, const BItem& c) {
     const int64_t ca = (int64_t)a.nrows * (offC[a.prob + 1] - offC[a.prob]);
     const int64_t cc = (int64_t)c.nrows * (offC[c.prob + 1] - offC[c.prob]);
     return ca > cc;
   });
+}
+
+// Problem order of the item lists of one side (rows from offR, columns from
+// offC): largest column count first, then largest row count, so the rebuilt
+// lists run from the costliest row tiles down
+void build_order(const int64_t* offR, const int64_t* offC, int64_t B, std::vector<int32_t>& ord) {
+  ord.resize(B);
+  for (int64_t b = 0; b < B; ++b) ord[b] = (int32_t)b;
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t c) {
+    const int64_t ma = offC[a + 1] - offC[a], mc = offC[c + 1] - offC[c];
+    if (ma != mc) return ma > mc;
+    return offR[a + 1] - offR[a] > offR[c + 1] - offR[c];
+  });
+}
+
+// residual slots of the X items: problem-major, 256 R rows per item
+void build_pstart(const int64_t* offN, int64_t B, int R, std::vector<int32_t>& pstart) {
+  pstart.assign(B + 1, 0);
+  const int64_t rows = 256 * R;
+  int64_t slot = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    pstart[b] = (int32_t)slot;
+    slot += (offN[b + 1] - offN[b] + rows - 1) / rows;
+  }
+  pstart[B] = (int32_t)slot;
 }
 
 // Workspace views and one-time set-up shared by the plain Gibbs products of a
@@ -1595,7 +1618,7 @@ struct BatchGibbs {
   int64_t *offN_d, *offM_d;
   BItem *items[2];     // rows X, rows Y (columns of the other side or the same side, see gibbs_items)
   int n_items[2];
-  int* curs;
+  int* curs;           // list lengths, then work cursors, on the device
   int ncu;
 };
 
@@ -1629,7 +1652,7 @@ int batch_gibbs_setup(uot_ctx* ctx, const BatchPlan& P, const uot_batch_problem*
 // `cols`, uploaded into the items slot of the rows side
 int gibbs_items(const BatchPlan& P, const uot_batch_problem* pb, int rows, int cols, BatchGibbs& G) {
   std::vector<BItem> it;
-  build_items(rows ? pb->offM : pb->offN, cols ? pb->offM : pb->offN, P.B, 1, it, nullptr);
+  build_items(rows ? pb->offM : pb->offN, cols ? pb->offM : pb->offN, P.B, 1, it);
   HIP_TRY(hipMemcpy(G.items[rows], it.data(), sizeof(BItem) * it.size(), hipMemcpyHostToDevice));
   G.n_items[rows] = (int)it.size();
   return UOT_OK;
@@ -1642,15 +1665,17 @@ void gibbs_launch(const BatchPlan& P, const uot_batch_problem* pb, const BatchGi
                   const T* w, T* w2, T* out, hipStream_t s) {
   launch_ctrl_init(G.ctrl, make_ctrl(eps, 0, 0, 0, 0, 1), s);
   launch_batch_init(G.bc_dev, (int)P.B, G.ctrl, s);
-  launch_set_int(G.curs, 2, 0, s);
+  launch_set_int(G.curs + rows, 1, G.n_items[rows], s);
+  launch_set_int(G.curs + 2 + rows, 1, 0, s);
   const int64_t totR = rows ? P.totM : P.totN, totC = cols ? P.totM : P.totN;
   launch_init_pot<T>(nullptr, w, nullptr, w2, totC, totC, G.ctrl, 0, s);   // w2 = w log2(e)
   EpiArgs<T> ep{};
   ep.mode = EPI_RAW;
   ep.out = out;
-  launch_batch_lse<T>(P.dim, 1, G.ncu * 8, G.items[rows], G.n_items[rows], G.curs, rows ? G.offM_d : G.offN_d,
-                      cols ? G.offM_d : G.offN_d, static_cast<const T*>(rows ? pb->y : pb->x), totR,
-                      static_cast<const T*>(cols ? pb->y : pb->x), totC, w2, G.bc_dev, G.ctrl, 0, ep, s);
+  launch_batch_lse<T>(P.dim, 1, G.ncu * 8, G.items[rows], G.curs + rows, G.curs + 2 + rows,
+                      rows ? G.offM_d : G.offN_d, cols ? G.offM_d : G.offN_d,
+                      static_cast<const T*>(rows ? pb->y : pb->x), totR, static_cast<const T*>(cols ? pb->y : pb->x),
+                      totC, w2, G.bc_dev, G.ctrl, 0, ep, s);
   launch_scale<T>(out, totR, kLn2, s);
 }
 
@@ -1719,7 +1744,7 @@ int cloud_features_t(uot_ctx* ctx, const uot_batch_problem* pb, double eps, cons
   if ((rc = batch_gibbs_setup<float>(ctx, P, pb, ws, G))) return rc;
   // rows Y against columns X go to the X items slot, rows Y against columns Y to the Y slot
   std::vector<BItem> it;
-  build_items(pb->offM, pb->offN, P.B, 1, it, nullptr);
+  build_items(pb->offM, pb->offN, P.B, 1, it);
   HIP_TRY(hipMemcpy(G.items[0], it.data(), sizeof(BItem) * it.size(), hipMemcpyHostToDevice));
   G.n_items[0] = (int)it.size();
   if ((rc = gibbs_items(P, pb, 1, 1, G))) return rc;
@@ -1786,10 +1811,32 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
   int* curs = at<int>(ws, P.o_curs);
   int64_t* offN_d = at<int64_t>(ws, P.o_offN);
   int64_t* offM_d = at<int64_t>(ws, P.o_offM);
+  int32_t* ordx_d = at<int32_t>(ws, P.o_ordx);
+  int32_t* ordy_d = at<int32_t>(ws, P.o_ordy);
   BCtrl* bc_dev = nullptr;   // BCtrl itself travels by value inside a small device copy
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipMemcpy(offN_d, pb->offN, 8 * (P.B + 1), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(offM_d, pb->offM, 8 * (P.B + 1), hipMemcpyHostToDevice));
+  {
+    std::vector<int32_t> ord;
+    build_order(pb->offN, pb->offM, P.B, ord);
+    HIP_TRY(hipMemcpy(ordx_d, ord.data(), 4 * P.B, hipMemcpyHostToDevice));
+    build_order(pb->offM, pb->offN, P.B, ord);
+    HIP_TRY(hipMemcpy(ordy_d, ord.data(), 4 * P.B, hipMemcpyHostToDevice));
+  }
+  BatchLists lists;
+  lists.ord[0] = ordx_d;
+  lists.ord[1] = ordy_d;
+  lists.off[0] = offN_d;
+  lists.off[1] = offM_d;
+  lists.pstart = pstart_d;
+  lists.items[0] = itx;
+  lists.items[1] = ity;
+  lists.count[0] = curs;
+  lists.count[1] = curs + 1;
+  lists.cursor[0] = curs + 2;
+  lists.cursor[1] = curs + 3;
+  lists.rows = 256;
   // the BCtrl pointer block lives right after the Ctrl struct in the control slot
   bc_dev = reinterpret_cast<BCtrl*>(reinterpret_cast<char*>(ctrl) + align_up(sizeof(Ctrl), 64));
   HIP_TRY(hipMemcpy(bc_dev, &bc, sizeof(BCtrl), hipMemcpyHostToDevice));
@@ -1832,21 +1879,20 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
     }
   }
 
-  std::vector<BItem> hx, hy;
   std::vector<int32_t> pst;
+  // rows per item 256 R: the residual slots of the X items (the lists are
+  // rebuilt on the device)
   auto upload_items = [&](int R) -> int {
-    build_items(pb->offN, pb->offM, P.B, R, hx, &pst);
-    build_items(pb->offM, pb->offN, P.B, R, hy, nullptr);
-    HIP_TRY(hipMemcpy(itx, hx.data(), sizeof(BItem) * hx.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(ity, hy.data(), sizeof(BItem) * hy.size(), hipMemcpyHostToDevice));
+    build_pstart(pb->offN, P.B, R, pst);
     HIP_TRY(hipMemcpy(pstart_d, pst.data(), 4 * (P.B + 1), hipMemcpyHostToDevice));
+    lists.rows = 256 * R;
     return UOT_OK;
   };
   auto init_state = [&]() {
     Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, pr->tol, pr->max_iter);
     launch_ctrl_init(ctrl, init, s);
     launch_batch_init(bc_dev, (int)P.B, ctrl, s);
-    launch_set_int(curs, 2, 0, s);
+    launch_batch_compact(ctrl, bc_dev, (int)P.B, lists, s);   // every problem's items
     log_into<T>(pb->p, logp, P.totN, 1, px, uo, s);
     log_into<T>(pb->q, logq, P.totM, 1, py, vo, s);
     log_into<T>(pb->dx, logdx, P.totN, 0, px, uo, s);
@@ -1867,24 +1913,24 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
   auto iteration = [&](int par) {
     EpiArgs<T> epx = prox_epi<T>(uo, wu, logp, logdx, nullptr, parts, P.totN, pb->F1);
     EpiArgs<T> epy = prox_epi<T>(vo, wv, logq, logdy, nullptr, nullptr, P.totM, pb->F2);
-    auto product = [&](int half, const BItem* items, int n_items, int* cur, const int64_t* offR,
-                       const int64_t* offC, const T* xr, int64_t totR, const T* yc, int64_t totC, const T* w,
-                       float* pwr, const EpiArgs<T>& ep) {
+    auto product = [&](int half, const BItem* items, int* count, const int64_t* offR, const int64_t* offC,
+                       const T* xr, int64_t totR, const T* yc, int64_t totC, const T* w, float* pwr,
+                       const EpiArgs<T>& ep) {
       if constexpr (std::is_same<T, float>::value) {
         if (mfk) {
-          launch_batch_mf(P.dim, 4 * R, ncu * bpc, items, n_items, cur, offR, offC, xr, totR, yc, totC, w, pwr,
+          launch_batch_mf(P.dim, 4 * R, ncu * bpc, items, count, count + 2, offR, offC, xr, totR, yc, totC, w, pwr,
                           bc_dev, ctrl, half | par << 1, ep, s);
           return;
         }
       }
-      launch_batch_lse<T>(P.dim, R, ncu * bpc, items, n_items, cur, offR, offC, xr, totR, yc, totC, w, bc_dev, ctrl,
-                          half | par << 1, ep, s);
+      launch_batch_lse<T>(P.dim, R, ncu * bpc, items, count, count + 2, offR, offC, xr, totR, yc, totC, w, bc_dev,
+                          ctrl, half | par << 1, ep, s);
     };
-    timed(0, [&] { product(0, itx, (int)hx.size(), curs + 0, offN_d, offM_d, xo, P.totN, yo, P.totM, wv, pw, epx); });
-    timed(2, [&] { launch_batch_control(ctrl, bc_dev, (int)P.B, parts, pstart_d, curs, par, s); });
+    // (count + 2: the list's work cursor)
+    timed(0, [&] { product(0, itx, curs + 0, offN_d, offM_d, xo, P.totN, yo, P.totM, wv, pw, epx); });
+    timed(2, [&] { launch_batch_control(ctrl, bc_dev, (int)P.B, parts, pstart_d, lists, par, s); });
     timed(1, [&] {
-      product(1, ity, (int)hy.size(), curs + 1, offM_d, offN_d, yo, P.totM, xo, P.totN, wu,
-              pw ? pw + P.totN : nullptr, epy);
+      product(1, ity, curs + 1, offM_d, offN_d, yo, P.totM, xo, P.totN, wu, pw ? pw + P.totN : nullptr, epy);
     });
   };
 

@@ -475,14 +475,15 @@ __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ x
 }
 
 // Ragged batch on the matrix cores: persistent blocks pull (problem, 64 G
-// rows) items from an atomic cursor as k_batch_lse does, take the product of
-// the item's rows with all columns of the problem (the clouds in Morton
-// order per problem) and apply the proxdiv epilogue; pw: starting maxima per
-// row, left for the next iteration.
+// rows) items from the list as k_batch_lse does, take the product of the
+// item's rows with all columns of the problem (the clouds in Morton order per
+// problem) and apply the proxdiv epilogue; pw: starting maxima per row, left
+// for the next iteration.
 // (4 row groups per wave fit 128 VGPRs: 4 waves per SIMD; 8 groups take 2)
 template <int DIM, int G, bool SPLIT>
-__global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_batch_mf(const BItem* __restrict__ items, int n_items,
-                                                      int* __restrict__ cursor, const int64_t* __restrict__ offR,
+__global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_batch_mf(const BItem* __restrict__ items,
+                                                      const int* __restrict__ count, int* __restrict__ cursor,
+                                                      const int64_t* __restrict__ offR,
                                                       const int64_t* __restrict__ offC, const float* __restrict__ xr,
                                                       int64_t totR, const float* __restrict__ yc, int64_t totC,
                                                       const float* __restrict__ w, float* __restrict__ pw,
@@ -495,9 +496,10 @@ __global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_batch_mf(const BItem
   const float cc = float(kLog2e / eps_of(c, side));
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, q = lane >> 4;
+  const int n_items = *count;
   const int32_t* __restrict__ skip = half_of(side) == 0 ? bc->stop : bc->yskip;
   while (true) {
-    __syncthreads();
+    __syncthreads();   // the previous item's reads of the block's LDS are done
     if (threadIdx.x == 0) item_sh = atomicAdd(cursor, 1);
     __syncthreads();
     const int it = item_sh;
@@ -561,13 +563,13 @@ void launch_dense_mf(int dim, int groups, bool split, const float* xr, int64_t N
 
 namespace uot {
 
-void launch_batch_mf(int dim, int groups, int blocks, const BItem* items, int n_items, int* cursor,
+void launch_batch_mf(int dim, int groups, int blocks, const BItem* items, const int* count, int* cursor,
                      const int64_t* offR, const int64_t* offC, const float* xr, int64_t totR, const float* yc,
                      int64_t totC, const float* w, float* pw, const BCtrl* bc, const Ctrl* c, int side,
                      const EpiArgs<float>& ep, hipStream_t s) {
-#define UOT_BMF(D, G)                                                                                         \
-  hipLaunchKernelGGL((k_batch_mf<D, G, true>), dim3(blocks), dim3(kBlock), 0, s, items, n_items, cursor, offR, \
-                     offC, xr, totR, yc, totC, w, pw, bc, c, side, ep)
+#define UOT_BMF(D, G)                                                                                           \
+  hipLaunchKernelGGL((k_batch_mf<D, G, true>), dim3(blocks), dim3(kBlock), 0, s, items, count, cursor, offR, offC, \
+                     xr, totR, yc, totC, w, pw, bc, c, side, ep)
   if (groups == 8) {
     if (dim == 1) UOT_BMF(1, 8);
     else if (dim == 2) UOT_BMF(2, 8);

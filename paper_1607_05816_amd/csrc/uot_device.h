@@ -147,6 +147,8 @@ struct Ctrl {
   double zeta;       // log z of a total-mass penalty (Algorithm 4); 0 otherwise
   // ragged batches only
   int32_t active[2];  // problems still active after the last iteration (slot = iteration parity)
+  int32_t nstop;      // problems stopped so far
+  int32_t built[2];   // nstop when the item lists were last rebuilt (slot = iteration parity)
   uint64_t t0_clock;  // device wall clock at the start of the solve
 };
 
@@ -165,8 +167,9 @@ __device__ __forceinline__ double eps_next_of(const Ctrl* c, int side) {
 
 // per-problem state of a ragged batch (arrays of length B in the workspace)
 struct BCtrl {
-  int32_t* stop;
-  int32_t* yskip;
+  int32_t* stop;     // set by the control step of the iteration the problem stopped in
+  int32_t* yskip;    // stop as it was before the last control step: the Y half-step after that
+                     // step still runs for a problem that stopped in it
   int32_t* status;
   int64_t* iters;
   double* res;
@@ -177,6 +180,22 @@ struct BCtrl {
 // its residual partial goes to slot part
 struct BItem {
   int32_t prob, row0, nrows, part;
+};
+
+// Item lists of a ragged batch (k_batch_compact): each side's problems in a
+// fixed order (largest column count first, so the list runs from the
+// costliest row tiles down), every listed problem contributing its row
+// tiles.  The lists are rebuilt from the problems still running once enough
+// of the listed ones have stopped; until then the products skip the items of
+// stopped problems.
+struct BatchLists {
+  const int32_t* ord[2];   // problem order of the X-row and Y-row lists
+  const int64_t* off[2];   // row offsets of each side (offN, offM)
+  const int32_t* pstart;   // residual slot of the first X item of each problem
+  BItem* items[2];         // the lists (written)
+  int* count[2];           // their lengths (written)
+  int* cursor[2];          // the products' work cursors (reset every iteration)
+  int rows;                // rows per item
 };
 
 // residual partial (per block): value = 2^m * {den, num} (m in log2 units);

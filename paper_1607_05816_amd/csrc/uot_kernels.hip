@@ -1986,15 +1986,16 @@ void launch_probe(int which, float* out, int blocks, int iters, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // ragged batches of independent point-cloud problems.  One persistent launch
-// per half-step: each block pulls work items (problem, row tile) from an
-// atomic cursor until the list is exhausted; items of problems that already
-// stopped are skipped.  Items are pre-sorted by cost (rows x columns),
-// largest first, so the tail of the launch is made of small items.
+// per half-step over the item list (problem, row tile), *count items long:
+// each block pulls items from an atomic cursor until the list is exhausted
+// (a greedy list schedule: along a list that runs from the costliest items
+// down, the blocks finish within about one small item of each other).
+// Items of problems that stopped since the list was built are skipped.
 // ---------------------------------------------------------------------------
 namespace uot {
 
 template <typename T, int DIM, int R>
-__global__ __launch_bounds__(kBlock) void k_batch_lse(const BItem* __restrict__ items, int n_items,
+__global__ __launch_bounds__(kBlock) void k_batch_lse(const BItem* __restrict__ items, const int* __restrict__ count,
                                                        int* __restrict__ cursor, const int64_t* __restrict__ offR,
                                                        const int64_t* __restrict__ offC, const T* __restrict__ xr,
                                                        int64_t totR, const T* __restrict__ yc, int64_t totC,
@@ -2004,9 +2005,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_lse(const BItem* __restrict__ 
   __shared__ V4 tile[kBlock];
   __shared__ int item_sh;
   const T sc = T(kLog2e / eps_of(c, side));
+  const int n_items = *count;
   const int32_t* __restrict__ skip = half_of(side) == 0 ? bc->stop : bc->yskip;
   while (true) {
-    __syncthreads();
+    __syncthreads();   // the previous item's reads of the tile and item_sh are done
     if (threadIdx.x == 0) item_sh = atomicAdd(cursor, 1);
     __syncthreads();
     const int it = item_sh;
@@ -2073,26 +2075,24 @@ __global__ __launch_bounds__(kBlock) void k_batch_lse(const BItem* __restrict__ 
   }
 }
 
-// per-problem control (one thread per problem) between the X and Y half-steps
+// per-problem control between the X and Y half-steps, one wave per problem:
+// the residual of the X half-step from the problem's partials (Sec. 4.4's
+// stopping rule on the X marginal), its iteration count, and the stop
+// decision; a stopped problem leaves the item lists at the next compaction
 __global__ __launch_bounds__(kBlock) void k_batch_control(Ctrl* __restrict__ c, BCtrl* __restrict__ bc, int B,
                                                            const ResPart* __restrict__ part,
-                                                           const int32_t* __restrict__ pstart, int* __restrict__ cursors) {
-  const int b = blockIdx.x * kBlock + threadIdx.x;
-  const int64_t l_glob = c->iter;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    // cursors of the next launches, the global eps schedule and the counter slot
-    cursors[0] = 0;
-    cursors[1] = 0;
-    c->active[(l_glob + 1) & 1] = 0;
-  }
+                                                           const int32_t* __restrict__ pstart) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;   // uniform over the wave
   if (b >= B) return;
   if (bc->stop[b]) {
-    bc->yskip[b] = 1;
+    if (lane == 0) bc->yskip[b] = 1;
     return;
   }
-  bc->yskip[b] = 0;
-  float m = -__builtin_inff(), den = 0.f, num = 0.f;
-  for (int k = pstart[b]; k < pstart[b + 1]; ++k) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
+  float m = -__builtin_inff(), den = 0.f, num = 0.f, du = 0.f;
+  for (int k = pstart[b] + lane; k < pstart[b + 1]; k += 64) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
+  wave_res_reduce(m, den, num, du);
+  if (lane != 0) return;
   const double r = res_ratio(double(num), double(den));
   const int64_t l = bc->iters[b];
   bc->res[b] = r;
@@ -2105,20 +2105,100 @@ __global__ __launch_bounds__(kBlock) void k_batch_control(Ctrl* __restrict__ c, 
   if (stop) {
     bc->stop[b] = 1;
     bc->clock[b] = wall_clock64();
-  } else {
-    atomicAdd(&c->active[l & 1], 1);
+    atomicAdd(&c->nstop, 1);   // a few problems per iteration
   }
 }
 
-// global eps bookkeeping after the per-problem control (single thread)
-__global__ void k_batch_advance(Ctrl* __restrict__ c, int par) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int64_t l = c->iter;
-  c->iter = l + 1;
-  int64_t sn = c->iters_per_stage > 0 ? (l + 1) / c->iters_per_stage : c->n_stages;
-  if (sn > c->n_stages) sn = c->n_stages;
-  c->stage[par ^ 1] = (int)sn;
-  c->eps[par ^ 1] = c->eps_tab[sn];
+// After the control step of the iteration of parity par (advance = 1), or
+// at the start of a solve (advance = 0, every problem listed): reset the
+// work cursors, and rebuild both item lists (block 0: rows X, block 1: rows
+// Y) when at least 1/16 of the problems listed at the last rebuild have
+// stopped since, keeping each side's problem order (an exclusive scan of the
+// listed problems' item counts gives each problem its first position).  The
+// X list (next iteration) holds the problems not stopped, the Y list (this
+// iteration) also those that stopped in this iteration's control step
+// (yskip).  With advance, block 0 also records the number of active problems
+// for the host and does the global eps bookkeeping.
+constexpr int kCompactBlock = 1024;
+constexpr int kCompactPer = 4;   // problems per thread and pass
+__global__ __launch_bounds__(kCompactBlock) void k_batch_compact(Ctrl* __restrict__ c, const BCtrl* __restrict__ bc,
+                                                                 int B, BatchLists L, int par, int advance) {
+  const int side = blockIdx.x;
+  // (both blocks read the same counters; only the slot par ^ 1 is written)
+  const int nstop = c->nstop, built = c->built[par];
+  const bool rebuild = !advance || (nstop > built && (int64_t)(nstop - built) * 16 >= (int64_t)(B - built));
+  if (threadIdx.x == 0) {
+    *L.cursor[side] = 0;
+    if (side == 0 && advance) {
+      const int64_t l = c->iter;
+      c->active[l & 1] = B - nstop;
+      c->built[par ^ 1] = rebuild ? nstop : built;
+      c->iter = l + 1;
+      int64_t sn = c->iters_per_stage > 0 ? (l + 1) / c->iters_per_stage : c->n_stages;
+      if (sn > c->n_stages) sn = c->n_stages;
+      c->stage[par ^ 1] = (int)sn;
+      c->eps[par ^ 1] = c->eps_tab[sn];
+    }
+  }
+  if (!rebuild) return;
+  const int32_t* __restrict__ ord = L.ord[side];
+  const int64_t* __restrict__ off = L.off[side];
+  const int32_t* __restrict__ stop = side == 0 ? bc->stop : bc->yskip;
+  BItem* __restrict__ out = L.items[side];
+  constexpr int kWaves = kCompactBlock / 64;
+  __shared__ int wtot[kWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t carry = 0;
+  for (int64_t base = 0; base < B; base += (int64_t)kCompactBlock * kCompactPer) {
+    int prob[kCompactPer], cnt[kCompactPer];
+    int64_t nrow[kCompactPer];
+    int mine = 0;
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) {
+      const int64_t k = base + (int64_t)threadIdx.x * kCompactPer + j;
+      prob[j] = 0;
+      cnt[j] = 0;
+      nrow[j] = 0;
+      if (k < B) {
+        const int b = ord[k];
+        prob[j] = b;
+        if (!stop[b]) {
+          nrow[j] = off[b + 1] - off[b];
+          cnt[j] = (int)((nrow[j] + L.rows - 1) / L.rows);
+        }
+      }
+      mine += cnt[j];
+    }
+    // inclusive scan of the item counts over the wave, then over the waves
+    int incl = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
+    }
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      before += w < wv ? wtot[w] : 0;
+      total += wtot[w];
+    }
+    int64_t p = carry + before + incl - mine;
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j)
+      for (int q = 0; q < cnt[j]; ++q) {
+        BItem it;
+        it.prob = prob[j];
+        it.row0 = q * L.rows;
+        it.nrows = (int)(nrow[j] - it.row0 < L.rows ? nrow[j] - it.row0 : L.rows);
+        it.part = side == 0 ? L.pstart[prob[j]] + q : q;
+        out[p++] = it;
+      }
+    carry += total;
+    __syncthreads();   // wtot is rewritten by the next pass
+  }
+  if (threadIdx.x == 0) *L.count[side] = (int)carry;
 }
 
 __global__ void k_batch_init(BCtrl* __restrict__ bc, int B, Ctrl* __restrict__ c) {
@@ -2142,12 +2222,12 @@ __global__ void k_set_int(int* __restrict__ p, int n, int v) {
 }
 
 template <typename T>
-void launch_batch_lse(int dim, int R, int blocks, const BItem* items, int n_items, int* cursor, const int64_t* offR,
-                      const int64_t* offC, const T* xr, int64_t totR, const T* yc, int64_t totC, const T* w,
-                      const BCtrl* bc, const Ctrl* c, int side, const EpiArgs<T>& ep, hipStream_t s) {
+void launch_batch_lse(int dim, int R, int blocks, const BItem* items, const int* count, int* cursor,
+                      const int64_t* offR, const int64_t* offC, const T* xr, int64_t totR, const T* yc, int64_t totC,
+                      const T* w, const BCtrl* bc, const Ctrl* c, int side, const EpiArgs<T>& ep, hipStream_t s) {
 #define UOT_BL(D, RR)                                                                                          \
-  hipLaunchKernelGGL((k_batch_lse<T, D, RR>), dim3(blocks), dim3(kBlock), 0, s, items, n_items, cursor, offR, \
-                     offC, xr, totR, yc, totC, w, bc, c, side, ep)
+  hipLaunchKernelGGL((k_batch_lse<T, D, RR>), dim3(blocks), dim3(kBlock), 0, s, items, count, cursor, offR, offC, \
+                     xr, totR, yc, totC, w, bc, c, side, ep)
   if (R == 1) {
     if (dim == 1) UOT_BL(1, 1); else if (dim == 2) UOT_BL(2, 1); else UOT_BL(3, 1);
   } else if (R == 2) {
@@ -2158,10 +2238,15 @@ void launch_batch_lse(int dim, int R, int blocks, const BItem* items, int n_item
 #undef UOT_BL
 }
 
-void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const int32_t* pstart, int* cursors,
-                          int par, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_control, dim3(ceil_div(B, kBlock)), dim3(kBlock), 0, s, c, bc, B, part, pstart, cursors);
-  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, c, par);
+void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const int32_t* pstart,
+                          const BatchLists& L, int par, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_control, dim3((unsigned)ceil_div((int64_t)B * 64, kBlock)), dim3(kBlock), 0, s, c, bc, B,
+                     part, pstart);
+  hipLaunchKernelGGL(k_batch_compact, dim3(2), dim3(kCompactBlock), 0, s, c, bc, B, L, par, 1);
+}
+
+void launch_batch_compact(Ctrl* c, const BCtrl* bc, int B, const BatchLists& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_compact, dim3(2), dim3(kCompactBlock), 0, s, c, bc, B, L, 0, 0);
 }
 
 void launch_batch_init(BCtrl* bc, int B, Ctrl* c, hipStream_t s) {
@@ -2185,11 +2270,11 @@ template <typename T> void launch_scale(T* a, int64_t n, double f, hipStream_t s
 template void launch_scale<float>(float*, int64_t, double, hipStream_t);
 template void launch_scale<double>(double*, int64_t, double, hipStream_t);
 
-template void launch_batch_lse<float>(int, int, int, const BItem*, int, int*, const int64_t*, const int64_t*,
+template void launch_batch_lse<float>(int, int, int, const BItem*, const int*, int*, const int64_t*, const int64_t*,
                                       const float*, int64_t, const float*, int64_t, const float*, const BCtrl*,
                                       const Ctrl*, int, const EpiArgs<float>&, hipStream_t);
-template void launch_batch_lse<double>(int, int, int, const BItem*, int, int*, const int64_t*, const int64_t*,
-                                       const double*, int64_t, const double*, int64_t, const double*, const BCtrl*,
-                                       const Ctrl*, int, const EpiArgs<double>&, hipStream_t);
+template void launch_batch_lse<double>(int, int, int, const BItem*, const int*, int*, const int64_t*,
+                                       const int64_t*, const double*, int64_t, const double*, int64_t, const double*,
+                                       const BCtrl*, const Ctrl*, int, const EpiArgs<double>&, hipStream_t);
 
 }  // namespace uot

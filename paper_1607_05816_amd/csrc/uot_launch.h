@@ -111,8 +111,9 @@ void launch_spatial_order_batch(const T* x, int64_t tot, const int64_t* off, int
                                 T* box, uint32_t* code, int32_t* perm, hipStream_t s);
 // the ragged batch on the matrix cores (BF16 x 3 operands, FP32 data, squared
 // Euclidean): groups = 4 or 8 row groups of 16 per wave (items of 64 groups
-// rows); pw: starting row maxima (totR), kept between iterations
-void launch_batch_mf(int dim, int groups, int blocks, const BItem* items, int n_items, int* cursor,
+// rows); *count items of the list, pulled from *cursor (zero at launch);
+// pw: starting row maxima (totR), kept between iterations
+void launch_batch_mf(int dim, int groups, int blocks, const BItem* items, const int* count, int* cursor,
                      const int64_t* offR, const int64_t* offC, const float* xr, int64_t totR, const float* yc,
                      int64_t totC, const float* w, float* pw, const BCtrl* bc, const Ctrl* c, int side,
                      const EpiArgs<float>& ep, hipStream_t s);
@@ -159,12 +160,20 @@ void launch_probe(int which, float* out, int blocks, int iters, hipStream_t s);
 int grid_tf_parts(int n, int64_t A, int64_t B, bool strided);
 void launch_grid_tf(const float* in, int64_t A, int n, int64_t B, bool strided, bool half, double h, int side,
                     const Ctrl* c, const EpiArgs<float>& ep, hipStream_t s);
+// direct batch product over *count items of the list (256 R rows per item),
+// pulled from *cursor (zero at launch)
 template <typename T>
-void launch_batch_lse(int dim, int R, int blocks, const BItem* items, int n_items, int* cursor, const int64_t* offR,
-                      const int64_t* offC, const T* xr, int64_t totR, const T* yc, int64_t totC, const T* w,
-                      const BCtrl* bc, const Ctrl* c, int side, const EpiArgs<T>& ep, hipStream_t s);
-void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const int32_t* pstart, int* cursors,
-                          int par, hipStream_t s);
+void launch_batch_lse(int dim, int R, int blocks, const BItem* items, const int* count, int* cursor,
+                      const int64_t* offR, const int64_t* offC, const T* xr, int64_t totR, const T* yc, int64_t totC,
+                      const T* w, const BCtrl* bc, const Ctrl* c, int side, const EpiArgs<T>& ep, hipStream_t s);
+// per-problem control after the X half-step, then the work cursors, the item
+// lists (rebuilt when enough problems stopped) and the iteration's eps
+// bookkeeping
+void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const int32_t* pstart,
+                          const BatchLists& L, int par, hipStream_t s);
+// the item lists of every problem and zero cursors (no bookkeeping): the
+// start of a solve
+void launch_batch_compact(Ctrl* c, const BCtrl* bc, int B, const BatchLists& L, hipStream_t s);
 void launch_batch_init(BCtrl* bc, int B, Ctrl* c, hipStream_t s);
 void launch_set_int(int* p, int n, int v, hipStream_t s);
 template <typename T> void launch_scale(T* a, int64_t n, double f, hipStream_t s);
