@@ -940,6 +940,41 @@ def barycentric_map_rows(geom, v, logdy, eps, rows):
 # ---------------------------------------------------------------------------
 # batches: independent problems, one after the other
 # ---------------------------------------------------------------------------
+def mass_balance_shift(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, eps: float, v0) -> float:
+    """Constant shift s of a starting potential v0 (to be replaced by v0 - s)
+    that balances the two estimates of the plan's total mass, for KL penalties
+    on both marginals.  A refinement of a warm start: by Prop. "alternating"
+    only v^(0) enters the iterates, so the iteration and its fixed point are
+    unchanged.
+
+    KL row of Table proximalexplicit: a = (p / K b)^theta1, theta1 =
+    lam1/(lam1+eps), so the plan's first marginal a (K b) equals
+    p a^(-eps/lam1) = p e^(-u/lam1); likewise at the fixed point the second
+    marginal is q e^(-v/lam2), and both carry the plan's mass.  From v0, one
+    X half-step gives u1 and
+        P = sum_i p_i e^(-u1_i/lam1) dx_i,   Q = sum_j q_j e^(-v0_j/lam2) dy_j.
+    Replacing v0 by v0 - s turns u1 into u1 + theta1 s (log K(b e^(-s/eps))
+    = log K b - s/eps), P into P e^(-theta1 s/lam1) and Q into Q e^(s/lam2);
+    they agree for s = log(P/Q) / (theta1/lam1 + 1/lam2).  Returns 0 when P
+    or Q is 0.
+    """
+    if F1.kind != "kl" or F2.kind != "kl":
+        raise ValueError("the mass balance takes KL penalties on both marginals")
+    logp = np.asarray(logp, np.float64)
+    logq = np.asarray(logq, np.float64)
+    v0 = np.asarray(v0, np.float64)
+    S = geom.lse_x(v0 / eps + logdy, eps)
+    u1 = eps * proxdiv_log(F1, logp, S, 0.0, eps)
+    with np.errstate(invalid="ignore"):
+        tp = np.where(np.isneginf(logp), -np.inf, logp - u1 / F1.lam + logdx)
+        tq = np.where(np.isneginf(logq), -np.inf, logq - v0 / F2.lam + logdy)
+    lP, lQ = lse(tp, 0), lse(tq, 0)
+    if not (np.isfinite(lP) and np.isfinite(lQ)):
+        return 0.0
+    th1 = F1.lam / (F1.lam + eps)
+    return float((lP - lQ) / (th1 / F1.lam + 1.0 / F2.lam))
+
+
 def solve_batch(problems, F1, F2, eps, tol, max_iter, **kw):
     """problems: iterable of (x, y, p, q, dx, dy); dense squared-Euclidean cost."""
     out = []

@@ -760,3 +760,79 @@ def test_partial_transport_lp_limit():
         if prev is not None:
             assert cost - lp.fun <= prev + 1e-12
         prev = cost - lp.fun
+
+
+# ---------------------------------------------------------------------------
+# mass balance of a starting potential (KL on both marginals)
+# ---------------------------------------------------------------------------
+def _explicit_first_marginal(x, y, u, v, dy, eps):
+    """sum_j exp((u_i + v_j - |x_i - y_j|^2)/eps) dy_j from the plan itself."""
+    C = ((x[:, None, :] - y[None, :, :]) ** 2).sum(-1)
+    return (np.exp((u[:, None] + v[None, :] - C) / eps) * dy[None, :]).sum(1)
+
+
+def test_mass_balance_shift_vanishes_at_the_fixed_point():
+    """At the fixed point both marginals of the plan carry its mass, so the
+    shift is 0 (lam1 != lam2 and non-uniform dx, dy: a swapped lam, a dropped
+    reference weight or a wrong exponent sign leaves it non-zero)."""
+    rng = np.random.default_rng(21)
+    x, y, p, q, dx, dy = _rand_problem(rng, 30, 25)
+    g = O.PointsGeom(x, y)
+    lg = (np.log(p), np.log(q), np.log(dx), np.log(dy))
+    F1, F2, eps = O.KL(0.4), O.KL(0.9), 0.05
+    s = O.solve(g, *lg, F1, F2, eps, tol=1e-14, max_iter=100000)
+    assert abs(O.mass_balance_shift(g, *lg, F1, F2, eps, s["v"])) < 1e-10
+    # away from it the shift is not small
+    assert abs(O.mass_balance_shift(g, *lg, F1, F2, eps, s["v"] + 0.05)) > 1e-3
+
+
+@pytest.mark.parametrize("lams", [(0.4, 0.9), (1.0, 1.0), (2.0, 0.3)])
+def test_mass_balance_shift_is_the_root_of_the_mass_mismatch(lams):
+    """The shift against a root search: v0 - t for trial t, a full X
+    half-step, the first-marginal mass read off the explicit plan, against the
+    second-marginal mass q e^(-v/lam2) implied by v0 - t."""
+    rng = np.random.default_rng(22)
+    x, y, p, q, dx, dy = _rand_problem(rng, 20, 17)
+    g = O.PointsGeom(x, y)
+    lg = (np.log(p), np.log(q), np.log(dx), np.log(dy))
+    F1, F2, eps = O.KL(lams[0]), O.KL(lams[1]), 0.08
+    v0 = rng.normal(0.0, 0.2, len(y))
+
+    def mismatch(t):
+        v = v0 - t
+        _, u1, _ = O.half_step_x(g, lg[0], lg[2], lg[3], F1, eps, np.zeros(len(x)), v)
+        P = (_explicit_first_marginal(x, y, u1, v, dy, eps) * dx).sum()
+        Q = (q * np.exp(-v / F2.lam) * dy).sum()
+        return np.log(P) - np.log(Q)
+
+    t = optimize.brentq(mismatch, -20.0, 20.0, xtol=1e-14)
+    s = O.mass_balance_shift(g, *lg, F1, F2, eps, v0)
+    assert abs(s - t) < 1e-10
+    # exact along constants: a second shift from the shifted start is 0
+    assert abs(O.mass_balance_shift(g, *lg, F1, F2, eps, v0 - s)) < 1e-11
+
+
+def test_mass_balance_keeps_the_fixed_point():
+    """By Prop. alternating the start only changes the path: the balanced
+    start reaches the same potentials (and, the constant mode being the
+    slowest, in fewer iterations here)."""
+    rng = np.random.default_rng(23)
+    x, y, p, q, dx, dy = _rand_problem(rng, 40, 35)
+    g = O.PointsGeom(x, y)
+    lg = (np.log(p), np.log(q), np.log(dx), np.log(dy))
+    F, eps = O.KL(0.5), 0.02
+    cold = O.solve(g, *lg, F, F, eps, tol=1e-12, max_iter=100000)
+    s = O.mass_balance_shift(g, *lg, F, F, eps, np.zeros(len(y)))
+    bal = O.solve(g, *lg, F, F, eps, tol=1e-12, max_iter=100000, v0=np.full(len(y), -s))
+    np.testing.assert_allclose(bal["u"], cold["u"], atol=1e-9)
+    np.testing.assert_allclose(bal["v"], cold["v"], atol=1e-9)
+    assert bal["iters"] < cold["iters"]
+
+
+def test_mass_balance_rejects_other_penalties():
+    rng = np.random.default_rng(24)
+    x, y, p, q, dx, dy = _rand_problem(rng, 5, 4)
+    g = O.PointsGeom(x, y)
+    with pytest.raises(ValueError):
+        O.mass_balance_shift(g, np.log(p), np.log(q), np.log(dx), np.log(dy), O.TV(0.1), O.KL(1.0), 0.1,
+                             np.zeros(4))
