@@ -174,6 +174,17 @@ def ragged_headline(U, ctx, dev, np, torch, steps, warmup):
         torch.cuda.synchronize()
         cold_s.append(time.perf_counter() - t)
     it_cold = cold["iters"].astype(float)
+    # the warm start's parts: the mass balance without the network, and the
+    # network without the balance (start included in the time)
+    ablation = {}
+    for name, start in (("balance_only", lambda: CW.balanced_cold_v0(bp, ctx=ctx)),
+                        ("network_only", lambda: cw.v0(bp, ctx=ctx, balance=False))):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, inf = CW.solve(bp, v0=start(), ctx=ctx)
+        torch.cuda.synchronize()
+        ablation[name] = {"seconds": time.perf_counter() - t, "iters_mean": float(inf["iters"].mean()),
+                          "converged": int(inf["n_converged"])}
     # plain: cold single-problem solves of a stratified sample (one per
     # N*M stratum), each after an untimed first solve of its shape (the
     # product tuning, kept out as the batch's tuning is)
@@ -238,6 +249,7 @@ def ragged_headline(U, ctx, dev, np, torch, steps, warmup):
         "speedup_vs_plain": plain_s / (dt / steps),
         "speedup_batched_cold_vs_plain": plain_s / min(cold_s),
         "speedup_warm_vs_cold_batched": min(cold_s) / (dt / steps),
+        "warm_start_parts": ablation,
         "iters_ratio_cold_over_warm": float(it_cold.sum() / it_warm.sum()),
         "roofline": roof,
         "iters_cold": it_cold,

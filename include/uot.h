@@ -464,6 +464,24 @@ int uot_solve_batched(uot_ctx *ctx, const uot_batch_problem *pb, const uot_param
 int uot_batch_gibbs(uot_ctx *ctx, const uot_batch_problem *pb, double eps, int rows, int cols,
                     const void *w, void *out, void *ws, size_t ws_bytes);
 
+/* Mass balance of a starting potential v0 of an FP32 batch with KL(lambda1),
+ * KL(lambda2) marginal penalties (pb->F1, F2), in place: v0 <- v0 - s_b per
+ * problem.  By Prop. "alternating" only v^(0) enters the iterates, so this
+ * refines a warm start without touching the iteration or its fixed point.
+ * KL row of Table proximalexplicit: the plan's first marginal after an X
+ * half-step is p e^{-u/lambda1}, and at the fixed point the second is
+ * q e^{-v/lambda2}, both of the plan's mass.  With u1 the X half-step from
+ * v0, P = sum p e^{-u1/lambda1} dx and Q = sum q e^{-v0/lambda2} dy;
+ * replacing v0 by v0 - s moves u1 by theta1 s (theta1 = lambda1/(lambda1 +
+ * eps)), so s = log(P/Q) / (theta1/lambda1 + 1/lambda2) makes the two masses
+ * agree.  The constant direction is the one the iteration contracts most
+ * slowly (by theta1 theta2 per iteration).  s = 0 for a problem whose P or Q
+ * is 0.  v0: device offM[B] FP32; shift: device [B] FP32 or NULL, receives s.
+ * x, y, p, q, dx, dy are read.  Workspace: uot_batch_workspace_size.
+ * Errors: UOT_E_UNSUPPORTED for other penalties or FP64 data. */
+int uot_batch_balance(uot_ctx *ctx, const uot_batch_problem *pb, double eps, void *v0, void *shift,
+                      void *ws, size_t ws_bytes);
+
 /* ---------------------------------------------------------------------------
  * Warm-start network.  By Prop. "alternating" only v^(0) enters the iterates
  * (the first X half-step overwrites u), so predicting v from the two input

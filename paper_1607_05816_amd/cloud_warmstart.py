@@ -11,9 +11,14 @@ accumulation; kernels in csrc/uot_net.hip) predicts that smooth part point
 by point from 16 features (uot_cloud_features: the masses of both measures
 and of both reference measures near y_j at several kernel widths, Gibbs
 products of the library, and the problem's total masses and size ratio).
-v^(0) = z eps log q + prediction (uot_cloud_v0).
-The plain iteration then runs to the same tolerance, so the prediction
-changes the number of iterations, never the answer.
+v^(0) = z eps log q + prediction (uot_cloud_v0).  Last, each problem's
+constant is set by the mass balance (uot_batch_balance): one X half-step
+from v^(0), then the shift of v^(0) that makes the plan's first-marginal mass
+agree with the second-marginal mass v^(0) implies, as the two do at the fixed
+point.  The constant is the mode the iteration contracts most slowly (by
+z^2 per iteration), so the network predicts the shape and the balance sets
+the level.  The plain iteration then runs to the same tolerance, so the
+warm start changes the number of iterations, never the answer.
 
 Everything here is orchestration: every arithmetic step of the warm start
 runs in libuot.
@@ -61,13 +66,15 @@ class CloudWarmStart:
     def features(self, bp: U.BatchProblem, ctx=None):
         return U.cloud_features(bp, self.eps, self.shift, self.scale, ctx=ctx)
 
-    def v0(self, bp: U.BatchProblem, ctx=None, chunk=1 << 20):
-        """v^(0) (totM) for every problem of the batch."""
+    def v0(self, bp: U.BatchProblem, ctx=None, chunk=1 << 20, balance=True):
+        """v^(0) (totM) for every problem of the batch; balance: finish with
+        the mass balance of each problem's constant."""
         x = self.features(bp, ctx=ctx)
         y = torch.empty(bp.totM, dtype=torch.float32, device=x.device)
         for a in range(0, bp.totM, chunk):
             y[a:a + chunk] = self.net.infer(x[a:a + chunk].contiguous(), ctx=ctx).reshape(-1)
-        return U.cloud_v0(bp.q, zeps(self.eps, self.lam), y, self.out_scale, self.out_shift, ctx=ctx)
+        v0 = U.cloud_v0(bp.q, zeps(self.eps, self.lam), y, self.out_scale, self.out_shift, ctx=ctx)
+        return U.batch_balance(bp, self.eps, v0, ctx=ctx) if balance else v0
 
     def target(self, bp: U.BatchProblem, v, ctx=None):
         """Training target of the network for converged potentials v: the
@@ -87,6 +94,13 @@ class CloudWarmStart:
         z = np.load(path, allow_pickle=False)
         return CloudWarmStart(net, z["shift"], z["scale"], float(z["out_shift"]), float(z["out_scale"]),
                               float(z["eps"]), float(z["lam"]))
+
+
+def balanced_cold_v0(bp: U.BatchProblem, eps=EPS, ctx=None):
+    """The start without a network: v^(0) = 0 with each problem's constant
+    set by the mass balance."""
+    v0 = torch.zeros(bp.totM, dtype=torch.float32, device=bp.q.device)
+    return U.batch_balance(bp, eps, v0, ctx=ctx)
 
 
 def ragged(seed, B=4096, lo=64, hi=4096):

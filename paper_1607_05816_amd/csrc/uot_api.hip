@@ -1706,6 +1706,39 @@ int batch_gibbs_t(uot_ctx* ctx, const uot_batch_problem* pb, double eps, int row
   return finish(ctx);
 }
 
+int batch_balance_t(uot_ctx* ctx, const uot_batch_problem* pb, double eps, float* v0, float* shift, char* ws,
+                    size_t wsb) {
+  BatchPlan P;
+  int rc = make_batch_plan(P, pb);
+  if (rc) return rc;
+  if (P.dtype != UOT_F32) return fail(UOT_E_UNSUPPORTED, "the mass balance takes FP32 batches");
+  if (pb->F1.kind != UOT_DIV_KL || pb->F2.kind != UOT_DIV_KL)
+    return fail(UOT_E_UNSUPPORTED, "the mass balance takes KL penalties on both marginals");
+  if (!(pb->F1.lambda > 0) || !(pb->F2.lambda > 0) || !std::isfinite(pb->F1.lambda) || !std::isfinite(pb->F2.lambda))
+    return fail(UOT_E_INVALID, "KL lambda must be finite and > 0");
+  if ((rc = check_batch_ws(P, ws, wsb, P.total))) return rc;
+  if (!pb->x || !pb->y || !pb->p || !pb->q || !pb->dx || !pb->dy || !v0)
+    return fail(UOT_E_INVALID, "x, y, p, q, dx, dy and v0 are required");
+  if (!(eps > 0) || !std::isfinite(eps)) return fail(UOT_E_INVALID, "eps must be > 0");
+  hipStream_t s = ctx->work;
+  if ((rc = begin(ctx))) return rc;
+  BatchGibbs G;
+  if ((rc = batch_gibbs_setup<float>(ctx, P, pb, ws, G))) return rc;
+  if ((rc = gibbs_items(P, pb, 0, 1, G))) return rc;
+  // workspace slots of the solve reused here: w (totM), its log2 copy (totM), S (totN)
+  float* w = at<float>(ws, P.o_logq);
+  float* w2 = at<float>(ws, P.o_wv);
+  float* S = at<float>(ws, P.o_wu);
+  const float* dy = static_cast<const float*>(pb->dy);
+  launch_balance_w(v0, dy, P.totM, eps, w, s);
+  gibbs_launch<float>(P, pb, G, eps, 0, 1, w, w2, S, s);
+  launch_batch_balance(S, static_cast<const float*>(pb->p), static_cast<const float*>(pb->dx), G.offN_d,
+                       static_cast<const float*>(pb->q), dy, G.offM_d, P.B, eps, pb->F1.lambda, pb->F2.lambda, v0,
+                       shift, s);
+  HIP_TRY(hipGetLastError());
+  return finish(ctx);
+}
+
 static_assert(kCloudFeatures == UOT_CLOUD_FEATURES, "feature count of the C header");
 
 // the Gibbs products behind the cloud features (rows Y): columns, input and
@@ -2353,6 +2386,13 @@ int uot_batch_gibbs(uot_ctx* ctx, const uot_batch_problem* pb, double eps, int r
                                 static_cast<char*>(ws), wsb);
   return batch_gibbs_t<double>(ctx, pb, eps, rows, cols, static_cast<const double*>(w), static_cast<double*>(out),
                                static_cast<char*>(ws), wsb);
+}
+
+int uot_batch_balance(uot_ctx* ctx, const uot_batch_problem* pb, double eps, void* v0, void* shift, void* ws,
+                      size_t wsb) {
+  if (!ctx || !pb) return fail(UOT_E_INVALID, "ctx and problem are required");
+  return batch_balance_t(ctx, pb, eps, static_cast<float*>(v0), static_cast<float*>(shift), static_cast<char*>(ws),
+                         wsb);
 }
 
 int uot_cloud_features_workspace_size(const uot_batch_problem* pb, size_t* bytes) {

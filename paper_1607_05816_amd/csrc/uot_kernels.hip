@@ -2201,6 +2201,60 @@ __global__ __launch_bounds__(kCompactBlock) void k_batch_compact(Ctrl* __restric
   if (threadIdx.x == 0) *L.count[side] = (int)carry;
 }
 
+// column weights of the X half-step's product from a starting potential:
+// w_j = v0_j / eps + log dy_j (natural log)
+__global__ void k_balance_w(const float* __restrict__ v0, const float* __restrict__ dy, int64_t n, float inv_eps,
+                            float* __restrict__ w) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j < n) w[j] = v0[j] * inv_eps + logf(dy[j]);
+}
+
+// Mass balance of a starting potential v0 (KL on both marginals), one block
+// per problem.  S: log K(e^{v0/eps} dy) at every X point (natural log, from
+// the batch Gibbs product).  u1 = theta1 eps (log p - S) is the X half-step
+// from v0 (Table proximalexplicit, KL row); P = sum p e^{-u1/lam1} dx is the
+// mass of the plan's first marginal after it, Q = sum q e^{-v0/lam2} dy the
+// mass v0 gives the second; s = log(P/Q) / (theta1/lam1 + 1/lam2) makes them
+// agree once v0 is replaced by v0 - s (u1 then moves by theta1 s).  Points
+// of zero density carry no mass; s = 0 when P or Q is 0.
+__global__ __launch_bounds__(kBlock) void k_batch_balance(const float* __restrict__ S, const float* __restrict__ p,
+                                                           const float* __restrict__ dx,
+                                                           const int64_t* __restrict__ offN,
+                                                           const float* __restrict__ q, const float* __restrict__ dy,
+                                                           const int64_t* __restrict__ offM, float th1_eps,
+                                                           float inv_lam1, float inv_lam2, float inv_denom,
+                                                           float* __restrict__ v0, float* __restrict__ shift) {
+  const int64_t b = blockIdx.x;
+  __shared__ float lm[2], ls[2];
+  Lse2<float> a, c;
+  a.init();
+  c.init();
+  for (int64_t i = offN[b] + threadIdx.x; i < offN[b + 1]; i += kBlock) {
+    const float pi = p[i];
+    if (pi > 0.f) {
+      const float lp = logf(pi);
+      const float u1 = th1_eps * (lp - S[i]);
+      const float t = float(kLog2e) * (lp - u1 * inv_lam1 + logf(dx[i]));
+      a.add<1>(&t);
+    }
+  }
+  for (int64_t j = offM[b] + threadIdx.x; j < offM[b + 1]; j += kBlock) {
+    const float qj = q[j];
+    if (qj > 0.f) {
+      const float t = float(kLog2e) * (logf(qj) - v0[j] * inv_lam2 + logf(dy[j]));
+      c.add<1>(&t);
+    }
+  }
+  block_lse_reduce<float>(a.m, a.s, &lm[0], &ls[0]);
+  block_lse_reduce<float>(c.m, c.s, &lm[1], &ls[1]);
+  __syncthreads();   // (also: every thread's reads of v0 are done)
+  const float lP = lm[0] + log2f(ls[0]), lQ = lm[1] + log2f(ls[1]);
+  float sh = (lP - lQ) * float(kLn2) * inv_denom;
+  if (!(lP > -__builtin_inff() && lQ > -__builtin_inff()) || sh != sh) sh = 0.f;
+  for (int64_t j = offM[b] + threadIdx.x; j < offM[b + 1]; j += kBlock) v0[j] -= sh;
+  if (shift && threadIdx.x == 0) shift[b] = sh;
+}
+
 __global__ void k_batch_init(BCtrl* __restrict__ bc, int B, Ctrl* __restrict__ c) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b == 0) {
@@ -2247,6 +2301,19 @@ void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const 
 
 void launch_batch_compact(Ctrl* c, const BCtrl* bc, int B, const BatchLists& L, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_compact, dim3(2), dim3(kCompactBlock), 0, s, c, bc, B, L, 0, 0);
+}
+
+void launch_balance_w(const float* v0, const float* dy, int64_t n, double eps, float* w, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_balance_w, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, v0, dy, n, float(1.0 / eps), w);
+}
+
+void launch_batch_balance(const float* S, const float* p, const float* dx, const int64_t* offN, const float* q,
+                          const float* dy, const int64_t* offM, int64_t B, double eps, double lam1, double lam2,
+                          float* v0, float* shift, hipStream_t s) {
+  const double th1 = lam1 / (lam1 + eps);
+  hipLaunchKernelGGL(k_batch_balance, dim3((unsigned)B), dim3(kBlock), 0, s, S, p, dx, offN, q, dy, offM,
+                     float(th1 * eps), float(1.0 / lam1), float(1.0 / lam2), float(1.0 / (th1 / lam1 + 1.0 / lam2)),
+                     v0, shift);
 }
 
 void launch_batch_init(BCtrl* bc, int B, Ctrl* c, hipStream_t s) {

@@ -174,6 +174,12 @@ void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const 
 // the item lists of every problem and zero cursors (no bookkeeping): the
 // start of a solve
 void launch_batch_compact(Ctrl* c, const BCtrl* bc, int B, const BatchLists& L, hipStream_t s);
+void launch_balance_w(const float* v0, const float* dy, int64_t n, double eps, float* w, hipStream_t s);
+// mass balance of a starting potential v0 of a ragged batch (KL on both
+// marginals), in place; S: log K(e^{v0/eps} dy) per X point; shift: [B] or null
+void launch_batch_balance(const float* S, const float* p, const float* dx, const int64_t* offN, const float* q,
+                          const float* dy, const int64_t* offM, int64_t B, double eps, double lam1, double lam2,
+                          float* v0, float* shift, hipStream_t s);
 void launch_batch_init(BCtrl* bc, int B, Ctrl* c, hipStream_t s);
 void launch_set_int(int* p, int n, int v, hipStream_t s);
 template <typename T> void launch_scale(T* a, int64_t n, double f, hipStream_t s);

@@ -147,6 +147,7 @@ def lib():
         "uot_cloud_features": (c_i32, [c_vp, P(UotBatchProblem), c_dbl, P(ctypes.c_float), P(ctypes.c_float), c_vp,
                                        c_vp, ctypes.c_size_t]),
         "uot_cloud_v0": (c_i32, [c_vp, c_vp, c_i64, c_dbl, c_vp, c_dbl, c_dbl, c_vp]),
+        "uot_batch_balance": (c_i32, [c_vp, P(UotBatchProblem), c_dbl, c_vp, c_vp, c_vp, ctypes.c_size_t]),
         "uot_solve_batched": (c_i32, [c_vp, P(UotBatchProblem), P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t,
                                       P(UotBatchResult)]),
         "uot_flow_workspace_size": (c_i32, [P(UotFlowProblem), P(ctypes.c_size_t)]),
@@ -666,6 +667,20 @@ def batch_gibbs(bp: BatchProblem, eps, rows, cols, w, ctx: Optional[Context] = N
     _check(lib().uot_batch_gibbs(ctx.handle, ctypes.byref(bp.c), float(eps), int(rows), int(cols), _ptr(w), _ptr(out),
                                  _ptr(ws), ws.numel()), "uot_batch_gibbs", False)
     return out
+
+
+def batch_balance(bp: BatchProblem, eps, v0, ctx: Optional[Context] = None, with_shift=False):
+    """Mass balance of a starting potential v0 (device, totM, FP32; KL on both
+    marginals), in place (uot_batch_balance): v0 <- v0 - s per problem.
+    Returns v0, or (v0, s) with s the per-problem shifts when with_shift."""
+    ctx = ctx or default_context()
+    _dev(v0, torch.float32, bp.totM, "v0")
+    shift = torch.empty(bp.B, dtype=torch.float32, device=v0.device) if with_shift else None
+    ws = bp.workspace()
+    _check(lib().uot_batch_balance(ctx.handle, ctypes.byref(bp.c), float(eps), _ptr(v0),
+                                   _ptr(shift) if shift is not None else None, _ptr(ws), ws.numel()),
+           "uot_batch_balance", False)
+    return (v0, shift) if with_shift else v0
 
 
 CLOUD_FEATURES = 16

@@ -119,12 +119,59 @@ def test_cloud_v0_composition():
     assert np.max(np.abs(v0 - ref)) < 1e-8
 
 
+@pytest.mark.parametrize("lams", [(1.0, 1.0), (0.7, 1.3)])
+def test_batch_balance_matches_oracle(lams):
+    """uot_batch_balance against the oracle's mass_balance_shift, problem by
+    problem (a one-point cloud, a zero density and ragged sizes included).
+    FP32 error budget of the shift: the Gibbs product S to a few 2^-24 of
+    its term scale (max |w| + max C / eps), which moves u1 by theta1 eps dS,
+    each exponent of P and Q to a few 2^-24 of its size, all divided by
+    theta1/lam1 + 1/lam2."""
+    rng = np.random.default_rng(11)
+    sizes = ((40, 300), (257, 64), (1, 5), (700, 513), (3, 1))
+    probs = [synth.uniform_clouds(rng, n, m) for n, m in sizes]
+    probs[3].p[17] = 0.0
+    for p in probs:
+        for f in ("x", "y", "p", "q", "dx", "dy"):
+            setattr(p, f, rounded(getattr(p, f), np.float32))
+    cat = lambda f: torch.tensor(np.concatenate([f(p) for p in probs]), dtype=torch.float32, device=DEV)
+    F1, F2 = U.KL(lams[0]), U.KL(lams[1])
+    bp = U.BatchProblem([p.x.shape[0] for p in probs], [p.y.shape[0] for p in probs], cat(lambda p: p.x),
+                        cat(lambda p: p.y), cat(lambda p: p.p), cat(lambda p: p.q), cat(lambda p: p.dx),
+                        cat(lambda p: p.dy), F1, F2, layout="nd")
+    eps = 0.02
+    v0 = rounded(rng.normal(0.0, 0.05, bp.totM), np.float32)
+    say("case batch balance", lams)
+    out, sh = U.batch_balance(bp, eps, torch.tensor(v0, dtype=torch.float32, device=DEV), with_shift=True)
+    out, sh = out.cpu().numpy().astype(np.float64), sh.cpu().numpy().astype(np.float64)
+    th1 = lams[0] / (lams[0] + eps)
+    denom = th1 / lams[0] + 1.0 / lams[1]
+    for b, p in enumerate(probs):
+        vb = v0[bp.offM[b]:bp.offM[b + 1]].astype(np.float64)
+        with np.errstate(divide="ignore"):
+            lg = (np.log(p.p), np.log(p.q), np.log(p.dx), np.log(p.dy))
+        g = O.PointsGeom(p.x, p.y)
+        ref = O.mass_balance_shift(g, *lg, O.KL(lams[0]), O.KL(lams[1]), eps, vb)
+        w = vb / eps + lg[3]
+        scale_S = np.max(np.abs(w)) + np.max(O.sq_dist(p.x, p.y)) / eps
+        S = g.lse_x(w, eps)
+        u1 = eps * th1 * (lg[0] - S)
+        fin = np.isfinite(lg[0])
+        tP = np.abs(lg[0][fin] - u1[fin] / lams[0] + lg[2][fin])
+        tQ = np.abs(lg[1] - vb / lams[1] + lg[3])
+        tol = (eps * th1 / lams[0] * 8e-6 * scale_S + 8e-7 * (tP.max() + tQ.max())) / denom
+        assert abs(sh[b] - ref) <= tol, (b, sh[b], ref, tol)
+        np.testing.assert_allclose(out[bp.offM[b]:bp.offM[b + 1]], vb - ref, rtol=2e-7, atol=tol)
+
+
 def test_trained_cloud_warm_start_gains_over_cold_batch():
-    """Held-out ragged batches (sizes as the workload's, fewer problems):
-    the network's v^(0) needs fewer iterations in total than the cold start
-    (v^(0) = 0) and than the pointwise part alone (v^(0) = z eps log q, no
-    network), and the iteration lands on the same potentials (it decides the
-    answer, to the accuracy the tolerance allows)."""
+    """Held-out ragged batches (sizes as the workload's, fewer problems): the
+    warm start (network, then the mass balance) needs fewer iterations in
+    total than every start without the network: cold (v^(0) = 0), the
+    pointwise part alone (v^(0) = z eps log q) and the mass balance of the
+    cold start; and fewer than the network without the balance.  Every
+    start lands on the same potentials (the iteration decides the answer, to
+    the accuracy the tolerance allows)."""
     if not os.path.exists(CW.WEIGHTS):
         pytest.fail("missing trained weights %s" % CW.WEIGHTS)
     cw = CW.CloudWarmStart.load(CW.WEIGHTS, DEV)
@@ -132,16 +179,20 @@ def test_trained_cloud_warm_start_gains_over_cold_batch():
     for seed in (7, 8):
         bp = CW.batch_problem(CW.ragged(seed, B=512), DEV)
         say("case cloud warm start seed", seed)
-        _, vc, ic = CW.solve(bp)
         ones = torch.zeros(bp.totM, dtype=torch.float32, device=DEV)
-        vp = U.cloud_v0(bp.q, CW.zeps(), ones, 1.0, 0.0)
-        _, _, ip = CW.solve(bp, v0=vp)
-        v0 = cw.v0(bp)
-        _, vw, iw = CW.solve(bp, v0=v0)
-        assert ic["n_converged"] == bp.B and ip["n_converged"] == bp.B and iw["n_converged"] == bp.B
-        cold, point, warm = int(ic["iters"].sum()), int(ip["iters"].sum()), int(iw["iters"].sum())
-        say("  total iterations: cold %d, pointwise part %d, network %d" % (cold, point, warm))
-        ratios.append(min(cold, point) / warm)
-        dv = float((vw - vc).abs().max() / vc.abs().max())
-        assert dv < 1e-3, dv
-    assert min(ratios) > 1.1, ratios
+        starts = {"cold": None, "pointwise": U.cloud_v0(bp.q, CW.zeps(), ones, 1.0, 0.0),
+                  "balance": CW.balanced_cold_v0(bp), "network": cw.v0(bp, balance=False),
+                  "warm": cw.v0(bp)}
+        total, vs = {}, {}
+        for name, v0 in starts.items():
+            _, vs[name], info = CW.solve(bp, v0=v0)
+            assert info["n_converged"] == bp.B, name
+            total[name] = int(info["iters"].sum())
+        say("  total iterations: %s" % total)
+        for name in starts:
+            dv = float((vs[name] - vs["cold"]).abs().max() / vs["cold"].abs().max())
+            assert dv < 1e-3, (name, dv)
+        assert total["warm"] < total["network"], total
+        ratios.append(min(total["cold"], total["pointwise"], total["balance"]) / total["warm"])
+    say("gain over the best start without the network: %s" % ratios)
+    assert min(ratios) > 1.0, ratios
