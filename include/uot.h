@@ -158,7 +158,15 @@ typedef struct uot_params {
                             every launch per kernel class: [0] first Gibbs
                             pass / dense LSE, [1] later passes / split merge +
                             epilogue, [2] control, [3] unused              */
-  int64_t *kernel_launches; /* optional HOST array [4]: launches per class   */
+  int64_t *kernel_launches; /* optional HOST array [4]: launches per class
+                            [0..2]; [3] receives the pair evaluations the
+                            matrix-core products performed (they leave out
+                            16-column tiles whose terms are all below 2^-50
+                            of the row maxima: the on-the-fly form of the
+                            kernel truncation of the further tricks of the
+                            sparse scaling literature the paper discusses;
+                            UOT_TILE_SKIP=0 in the environment turns that
+                            off)                                            */
   int32_t grid_kernel;   /* grids: 0 default (2 for FP32, 1 for FP64), 1 direct log-sum-exp
                             passes, 2 tile-factored FP32 MFMA passes (FP32
                             problems, axes with a multiple of 16 cells and

@@ -600,6 +600,15 @@ CostArgs wf_cost(const Plan& P, const Bufs<T>& B, int half) {
   return ca;
 }
 
+// the matrix-core products' tile skipping, and their pair count in timed
+// solves (into the control block)
+MfSkip mf_skip(Ctrl* c, bool count) {
+  MfSkip k;
+  k.on = tile_skip_enabled() ? 1 : 0;
+  k.pairs = count && g_timer ? &c->pairs : nullptr;
+  return k;
+}
+
 // dense point-cloud product for one side; returns the residual partial count
 template <typename T>
 void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Bufs<T>& B, Ctrl* c,
@@ -617,7 +626,7 @@ void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Buf
       }
       if (P.dense_mf) {
         launch_dense_mf(P.dim, P.mf_groups, P.mf_split, rows, Nr, cols, w_cols, Mc, P.splits[half], P.cps[half], B.pm, B.ps,
-                        B.pw + half * P.np_pw, side, c, s);
+                        B.pw + half * P.np_pw, side, c, mf_skip(c, true), s);
         return;
       }
     }
@@ -781,6 +790,9 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
       pr->kernel_ms[k] = timer.ms[k];
       if (pr->kernel_launches) pr->kernel_launches[k] = timer.count[k];
     }
+    // class [3]: the matrix-core products' pair evaluations (the control
+    // block as copied back after the last chunk)
+    if (pr->kernel_launches) pr->kernel_launches[3] = (int64_t)ctx->pinned->pairs;
   }
   auto t1 = std::chrono::steady_clock::now();
   if (cache && !second) {
@@ -886,7 +898,7 @@ int tune_dense_mf(uot_ctx* ctx, Plan& P, const uot_geom& g, Bufs<T>& B, hipStrea
         last_sp = P.splits[half];
         auto launch = [&] {
           launch_dense_mf(P.dim, P.mf_groups, P.mf_split, rows, Nr, cols, wc, Mc, P.splits[half], P.cps[half], B.pm,
-                          B.ps, pw, half, B.ctrl, s);
+                          B.ps, pw, half, B.ctrl, mf_skip(B.ctrl, false), s);
         };
         HIP_TRY(hipMemsetAsync(pw, 0xFF, sizeof(float) * P.np_pw, s));
         launch();
@@ -1446,7 +1458,7 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
         }
         if (P.dense_mf) {
           launch_dense_mf(P.dim, P.mf_groups, P.mf_split, rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps,
-                          B.pw, 0, B.ctrl, s);
+                          B.pw, 0, B.ctrl, mf_skip(B.ctrl, false), s);
           return;
         }
       }
@@ -1952,7 +1964,7 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
       if constexpr (std::is_same<T, float>::value) {
         if (mfk) {
           launch_batch_mf(P.dim, 4 * R, ncu * bpc, items, count, count + 2, offR, offC, xr, totR, yc, totC, w, pwr,
-                          bc_dev, ctrl, half | par << 1, ep, s);
+                          bc_dev, ctrl, half | par << 1, ep, mf_skip(ctrl, true), s);
           return;
         }
       }
@@ -2085,6 +2097,9 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
       pr->kernel_ms[k] = timer.ms[k];
       if (pr->kernel_launches) pr->kernel_launches[k] = timer.count[k];
     }
+    // class [3]: the matrix-core products' pair evaluations (the control
+    // block as copied back after the last chunk)
+    if (pr->kernel_launches) pr->kernel_launches[3] = (int64_t)ctx->pinned->pairs;
   }
   std::vector<int64_t> it(P.B);
   std::vector<double> rs(P.B);

@@ -1,5 +1,7 @@
 // Dense point-cloud product of libuot with the squared Euclidean cost on the
 // gfx950 matrix cores, with its launcher.
+#include <cstdlib>
+
 #include "uot_device.h"
 #include "uot_epilogue.h"
 #include "uot_launch.h"
@@ -154,50 +156,60 @@ struct MfOps<true> {
   }
 };
 
-// The two product passes over the ntl tiles of a staged chunk.  Both are
-// software-pipelined by one row group: the products of group g are issued
-// before the vector work on group g - 1 (the last group's follower is group 0
-// of the next tile; the final followers read the two padding tiles after the
-// chunk and are discarded), so the exp2 of one group never waits on its own
-// product.
+// The two product passes over the tiles of a staged chunk that `mask` keeps
+// (bit t: tile t of 16 columns; wave-uniform).  Both are software-pipelined
+// by one row group: the products of group g are issued before the vector
+// work on group g - 1 (the last group's follower is group 0 of the next kept
+// tile; after the last tile it repeats that tile and is discarded), so the
+// exp2 of one group never waits on its own product.
 // maximum pass: mx[g] = this lane's maximum exponent of row 16 g + l
-template <bool SPLIT, int G>
+template <bool SPLIT, int G, int NT>
 __device__ __forceinline__ void mf_max_pass(const typename MfOps<SPLIT>::Op* base,
-                                            const typename MfOps<SPLIT>::Op (&E)[G], int ntl, float (&mx)[G]) {
+                                            const typename MfOps<SPLIT>::Op (&E)[G], uint32_t kept, float (&mx)[G]) {
   using O = MfOps<SPLIT>;
   const mf_f32x4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int g = 0; g < G; ++g) mx[g] = -__builtin_inff();
-  mf_f32x4 c0 = O::mma(O::col(base, 0), E[0], zero);
-  mf_f32x4 c1 = O::mma(O::col(base, 1), E[0], zero);
-  for (int jt = 0; jt < ntl; jt += 2) {
-    const auto b0 = O::col(base, jt), b1 = O::col(base, jt + 1);
-    const auto n0 = O::col(base, jt + 2), n1 = O::col(base, jt + 3);   // padding past the chunk
+  // a counted loop over the kept tiles; bit NT (the first padding tile)
+  // stays set, so the follower of the last kept tile is a padding tile
+  const int n = __builtin_popcount(kept);
+  if (n == 0) return;
+  uint64_t mask = (uint64_t)kept | (1ull << NT);
+  int jt = __builtin_ctzll(mask);
+  mask &= mask - 1;
+  mf_f32x4 c0 = O::mma(O::col(base, jt), E[0], zero);
+  for (int k = 0; k < n; ++k) {
+    const int jn = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    const auto b = O::col(base, jt), bn = O::col(base, jn);
 #pragma unroll
     for (int g = 1; g <= G; ++g) {
-      const mf_f32x4 e0 = O::mma(g < G ? b0 : n0, E[g % G], zero);
-      const mf_f32x4 e1 = O::mma(g < G ? b1 : n1, E[g % G], zero);
-      __builtin_amdgcn_sched_barrier(0);   // the products go out first
-      float t = fmaxf(fmaxf(mx[g - 1], c0[0]), c0[1]);
-      t = fmaxf(fmaxf(t, c0[2]), c0[3]);
-      t = fmaxf(fmaxf(t, c1[0]), c1[1]);
-      mx[g - 1] = fmaxf(fmaxf(t, c1[2]), c1[3]);
+      const mf_f32x4 e0 = O::mma(g < G ? b : bn, E[g % G], zero);
+      __builtin_amdgcn_sched_barrier(0);   // the product goes out first
+      const float t = fmaxf(fmaxf(mx[g - 1], c0[0]), c0[1]);
+      mx[g - 1] = fmaxf(fmaxf(t, c0[2]), c0[3]);
       c0 = e0;
-      c1 = e1;
       __builtin_amdgcn_sched_barrier(0);
     }
+    jt = jn;
   }
 }
 // sum pass: s[g] += sum of 2^{exponent - max} (nm = minus the row maxima)
-template <bool SPLIT, int G>
+template <bool SPLIT, int G, int NT>
 __device__ __forceinline__ void mf_sum_pass(const typename MfOps<SPLIT>::Op* base,
                                             const typename MfOps<SPLIT>::Op (&E)[G], const mf_f32x4 (&nm)[G],
-                                            int ntl, float (&s)[G]) {
+                                            uint32_t kept, float (&s)[G]) {
   using O = MfOps<SPLIT>;
-  mf_f32x4 dc = O::mma(O::col(base, 0), E[0], nm[0]);
-  for (int jt = 0; jt < ntl; ++jt) {
-    const auto b = O::col(base, jt);
-    const auto bn = O::col(base, jt + 1);   // padding past the chunk
+  const int n = __builtin_popcount(kept);
+  if (n == 0) return;
+  uint64_t mask = (uint64_t)kept | (1ull << NT);
+  int jt = __builtin_ctzll(mask);
+  mask &= mask - 1;
+  mf_f32x4 dc = O::mma(O::col(base, jt), E[0], nm[0]);
+  for (int k = 0; k < n; ++k) {
+    const int jn = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    const auto b = O::col(base, jt), bn = O::col(base, jn);
 #pragma unroll
     for (int g = 1; g <= G; ++g) {
       const mf_f32x4 dn = O::mma(g < G ? b : bn, E[g % G], nm[g % G]);
@@ -207,50 +219,92 @@ __device__ __forceinline__ void mf_sum_pass(const typename MfOps<SPLIT>::Op* bas
       dc = dn;
       __builtin_amdgcn_sched_barrier(0);
     }
+    jt = jn;
   }
 }
+
+// maximum over the 16 lanes of a DPP row (lanes 16 k .. 16 k + 15)
+__device__ __forceinline__ float row16_max(float v) {
+  v = fmaxf(v, dpp_mov<kDppXor1>(v));
+  v = fmaxf(v, dpp_mov<kDppXor2>(v));
+  v = fmaxf(v, dpp_mov<kDppHalfMirror>(v));
+  return fmaxf(v, dpp_mov<kDppMirror>(v));
+}
+__device__ __forceinline__ float row16_min(float v) {
+  v = fminf(v, dpp_mov<kDppXor1>(v));
+  v = fminf(v, dpp_mov<kDppXor2>(v));
+  v = fminf(v, dpp_mov<kDppHalfMirror>(v));
+  return fminf(v, dpp_mov<kDppMirror>(v));
+}
+
+// Negligible tiles (the adaptive truncation of the kernel discussed in the
+// section on the further tricks of the sparse scaling literature, applied on
+// the fly).  With e_i = x_i - xbar, the exponent a product pass evaluates is
+//   D_ij = w_j - c |x_i - y_j|^2 + c |e_i|^2,
+// and a row's sum is taken against its running maximum m_i.  For a wave's
+// rows (box Bx) and a 16-column tile (box By, largest weight wmax),
+//   D_ij - m_i <= wmax - c gap(Bx, By)^2 + max_i (c |e_i|^2 - m_i),
+// so a tile whose bound is below -kSkipLog2 contributes less than 2^-50 of
+// 2^{m_i} per column to every row of the wave and is left out.  m_i only
+// grows during a split, so a bound taken at its start stays valid.  A row
+// whose final total (relative to 2^{m_i}) is below 2^-8 after tiles were
+// left out started from a maximum far above its terms (the previous
+// product's, after a large move of the potentials): its split is summed
+// again with nothing left out.  Otherwise the left-out mass is below
+// ncol 2^-50 / 2^-8 <= 2^-27 of the row's total for ncol <= 2^15, under
+// the FP32 rounding of the total.
+constexpr float kSkipLog2 = 50.f;
+constexpr float kSkipCheck = 0x1p-8f;
 
 // The product of one block's rows (xr: first row, coordinate stride xs, nrow
 // of its 64 G rows valid) with ncol columns (yc: first column, stride ys; w
 // their log2 weights): for row 16 g + l of this wave, m[g] (the shift; -inf
 // if no term is finite), tot[g] (the total over the row's 4 lanes, relative
-// to 2^m) and rc[g] = R_i.  pw holds the rows' starting maxima on entry and
-// is not written.  st, sbox: the block's LDS.
+// to 2^m) and rc[g] = R_i.  Rows past nrow repeat the last valid row (their
+// results are not used).  pw holds the rows' starting maxima on entry and is
+// not written.  st, sbox, tb: the block's LDS.  skip_tiles: leave negligible
+// tiles out; evaluated (wave-uniform) counts the 16-column tiles the wave's
+// product passes take.
 template <int DIM, int G, bool SPLIT, int CHUNK>
 __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs, int nrow,
                                         const float* __restrict__ yc, int64_t ys, const float* __restrict__ w,
                                         int64_t ncol, float cc, const float* __restrict__ pw,
-                                        typename MfOps<SPLIT>::Op* st, float (*sbox)[6], float (&m)[G],
-                                        float (&tot)[G], float (&rc)[G]) {
-  static_assert(G % 4 == 0, "a block's rows are loaded 256 at a time");
+                                        typename MfOps<SPLIT>::Op* st, float (*sbox)[6], float (*tb)[8],
+                                        bool skip_tiles, float (&m)[G], float (&tot)[G], float (&rc)[G],
+                                        uint32_t& evaluated) {
+  static_assert(G % 4 == 0, "a wave's rows are loaded 64 at a time");
   using Op = typename MfOps<SPLIT>::Op;
   static_assert(CHUNK % kBlock == 0 && CHUNK / 16 <= 32, "chunks of 256 or 512 columns");
   constexpr int kCols = mf_cols(CHUNK);
+  constexpr int kTiles = CHUNK / 16;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, q = lane >> 4;
   const int wbase = wv * (16 * G);
   // a wave with no valid row (the last rows of a ragged item) only helps to
   // stage the column operands: its product passes are skipped (wave-uniform)
   const bool wave_rows = wbase < nrow;
-  // the block centre: middle of the box of its valid rows
+  // the box of this wave's valid rows, then the block centre: middle of the
+  // box of all valid rows
+  float wlo[3] = {0.f, 0.f, 0.f}, whi[3] = {0.f, 0.f, 0.f};
   float xb[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     float lo = __builtin_inff(), hi = -__builtin_inff();
 #pragma unroll
     for (int t = 0; t < G / 4; ++t) {
-      const int row = t * kBlock + threadIdx.x;
+      const int row = wbase + t * 64 + lane;
       if (row < nrow) {
         const float v = xr[d * xs + row];
         lo = fminf(lo, v);
         hi = fmaxf(hi, v);
       }
     }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
+    // (wave-uniform values live in scalar registers through the chunk loop)
+    wlo[d] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, wave_min(lo))));
+    whi[d] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, wave_max(hi))));
     if (lane == 0) {
-      sbox[wv][2 * d] = lo;
-      sbox[wv][2 * d + 1] = hi;
+      sbox[wv][2 * d] = wlo[d];
+      sbox[wv][2 * d + 1] = whi[d];
     }
   }
   __syncthreads();
@@ -259,16 +313,24 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
     const float lo = fminf(fminf(sbox[0][2 * d], sbox[1][2 * d]), fminf(sbox[2][2 * d], sbox[3][2 * d]));
     const float hi =
         fmaxf(fmaxf(sbox[0][2 * d + 1], sbox[1][2 * d + 1]), fmaxf(sbox[2][2 * d + 1], sbox[3][2 * d + 1]));
-    xb[d] = lo <= hi ? 0.5f * (lo + hi) : 0.f;
+    xb[d] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                          __builtin_bit_cast(int, lo <= hi ? 0.5f * (lo + hi) : 0.f)));
   }
-  // row operands of rows 16 g + l; rows past the end give e = 0
+  // row operands of rows 16 g + l (rows past the end repeat the last one);
+  // the running maxima start from the previous product's (pw) and the bound
+  // term max_i (c |e_i|^2 - m_i) of the wave from them
   Op E[G];
+  float s[G], wm[G];
+  float mw = -__builtin_inff();
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    const int row = wbase + g * 16 + li;
-    float e[3];
+    const int row = min(wbase + g * 16 + li, nrow - 1);
+    float e[3], e2 = 0.f;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) e[d] = (d < DIM && row < nrow) ? xr[d * xs + row] - xb[d] : 0.f;
+    for (int d = 0; d < 3; ++d) {
+      e[d] = d < DIM ? xr[d * xs + row] - xb[d] : 0.f;
+      e2 = __builtin_fmaf(e[d], e[d], e2);
+    }
     if constexpr (SPLIT) {
       __bf16 p[3][3];
 #pragma unroll
@@ -278,26 +340,28 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
     } else {
       E[g] = q == 3 ? 1.f : (q == 0 ? e[0] : (q == 1 ? e[1] : e[2]));
     }
-  }
-  // running (m, s) of row 16 g + l: m is the same in the 4 lanes of the row,
-  // s is this lane's share (its columns)
-  float s[G], wm[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const int row = wbase + g * 16 + li;
-    const float v = row < nrow ? pw[row] : -__builtin_inff();
+    const float v = pw[row];
     wm[g] = __builtin_isfinite(v) ? v : -__builtin_inff();
+    mw = fmaxf(mw, cc * e2 - wm[g]);
   }
+  // +inf when a row has no finite starting maximum
+  mw = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, wave_max(mw))));
   const Op* base = SPLIT ? &st[li * 4 + q] : &st[q * kCols + li];
   // a wave whose rows all start from a finite maximum sums every chunk
   // against it and checks its totals once, at the end of the split; a failed
-  // check sums the split again from no maximum, checking every chunk
+  // check sums the split again from no maximum, checking every chunk, with
+  // every tile
   bool cold = false;
 #pragma unroll
   for (int g = 0; g < G; ++g) cold = cold || wm[g] == -__builtin_inff();
   const bool warm_wave = !__any(cold);
   for (int attempt = 0;; ++attempt) {
     const bool unchecked = attempt == 0 && warm_wave;
+    // the tile records are staged by the whole block (block-uniform); each
+    // wave uses them when its rows all have a starting maximum
+    const bool records = skip_tiles && attempt == 0;
+    const bool skip_on = records && mw < __builtin_inff();
+    bool skipped = false;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       m[g] = attempt == 0 ? wm[g] : -__builtin_inff();
@@ -344,17 +408,54 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
           for (int d = 0; d < 3; ++d) st[d * kCols + lc] = bd[d];
           st[3 * kCols + lc] = gj;
         }
+        if (records) {
+          // the tile's box (columns of weight -inf left out) and largest weight
+          const bool live = wj[h] > -__builtin_inff();
+          float rec[7];
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            rec[d] = row16_min(live ? y[h][d] : __builtin_inff());
+            rec[3 + d] = row16_max(live ? y[h][d] : -__builtin_inff());
+          }
+          rec[6] = row16_max(wj[h]);
+          if (li == 0) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+              tb[lc >> 4][d] = rec[d];
+              tb[lc >> 4][3 + d] = rec[3 + d];
+            }
+            tb[lc >> 4][6] = rec[6];
+          }
+        }
       }
       __syncthreads();
       const int64_t rem = ncol - c0;
       const int cnt = rem < CHUNK ? (int)rem : CHUNK;
-      // an even tile count (the staged padding is -inf), uniform
-      const int ntl = __builtin_amdgcn_readfirstlane(((cnt + 31) >> 5) << 1);
+      const int ntl = (cnt + 15) >> 4;
+      if (!wave_rows) continue;             // (after the staging and its barriers)
+      // the tiles this wave evaluates: lane t tests tile t
+      uint32_t mask = ntl >= 32 ? 0xFFFFFFFFu : ((1u << ntl) - 1u);
+      if (skip_on) {
+        bool keep = false;
+        if (lane < ntl) {
+          float gap2 = 0.f;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            const float g = fmaxf(fmaxf(tb[lane][d] - whi[d], wlo[d] - tb[lane][3 + d]), 0.f);
+            gap2 = __builtin_fmaf(g, g, gap2);
+          }
+          keep = tb[lane][6] - cc * gap2 + mw >= -kSkipLog2;
+        }
+        const uint32_t kept = (uint32_t)__ballot(keep);
+        skipped = skipped || kept != mask;
+        mask = kept;
+      }
+      mask = __builtin_amdgcn_readfirstlane(mask);
+      evaluated += (uint32_t)__builtin_popcount(mask);
       // a chunk with a row that has no finite running maximum yet (the first
       // chunk) takes the maximum pass first; others run the sum pass against
       // the running maxima and take the two passes only when a row's sum leaves
       // [0, 2^100) (a new maximum far above the old one)
-      if (!wave_rows) continue;             // (after the staging and its barriers)
       bool two = false;
 #pragma unroll
       for (int g = 0; g < G; ++g) two = two || m[g] == -__builtin_inff();
@@ -363,7 +464,7 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
         mf_f32x4 nm[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
-        mf_sum_pass<SPLIT, G>(base, E, nm, ntl, s);
+        mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
       } else if (!two) {
         float s0[G];
         mf_f32x4 nm[G];
@@ -372,7 +473,7 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
           s0[g] = s[g];
           nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
         }
-        mf_sum_pass<SPLIT, G>(base, E, nm, ntl, s);
+        mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
         bool bad = false;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -397,7 +498,7 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
       }
       if (two) {
         float mx[G];
-        mf_max_pass<SPLIT, G>(base, E, ntl, mx);
+        mf_max_pass<SPLIT, G, kTiles>(base, E, mask, mx);
         // new running maxima; rescale the sums; accumulator input -max
         mf_f32x4 nm[G];
 #pragma unroll
@@ -408,18 +509,20 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
           m[g] = mn;
           nm[g] = mf_f32x4{-sh, -sh, -sh, -sh};
         }
-        mf_sum_pass<SPLIT, G>(base, E, nm, ntl, s);
+        mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
       }
     }
     // totals of each row over its 4 lanes; a total below 2^-60 under a finite
-    // maximum came from a starting maximum too high, one not below 2^100
-    // (unchecked chunks) from one too low: sum the split again from none (the
-    // whole block, as the chunk loop holds barriers)
+    // maximum came from a starting maximum too high (below 2^-8 once tiles
+    // were left out), one not below 2^100 (unchecked chunks) from one too
+    // low: sum the split again from none (the whole block, as the chunk loop
+    // holds barriers)
+    const float low = skipped ? kSkipCheck : 0x1p-60f;
     bool redo = false;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       tot[g] = sum_over_rows(s[g]);
-      redo = redo || (m[g] != -__builtin_inff() && !(tot[g] >= 0x1p-60f)) || !(tot[g] < 0x1p100f);
+      redo = redo || (m[g] != -__builtin_inff() && !(tot[g] >= low)) || !(tot[g] < 0x1p100f);
     }
     redo = redo && wave_rows;
     if (attempt > 0 || !__syncthreads_or(redo)) break;
@@ -427,11 +530,11 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
   // row constants R_i = -c |e_i|^2
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    const int row = wbase + g * 16 + li;
+    const int row = min(wbase + g * 16 + li, nrow - 1);
     float e2 = 0.f;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      const float e = row < nrow ? xr[d * xs + row] - xb[d] : 0.f;
+      const float e = xr[d * xs + row] - xb[d];
       e2 = __builtin_fmaf(e, e, e2);
     }
     rc[g] = -cc * e2;
@@ -439,18 +542,20 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
 }
 
 template <int DIM, int G, bool SPLIT>
-__global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ xr, int64_t Nr,
+__global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_dense_mf(const float* __restrict__ xr, int64_t Nr,
                                                       const float* __restrict__ yc, const float* __restrict__ w,
                                                       int64_t Mc, int64_t cols_per_split,
                                                       float* __restrict__ pm, float* __restrict__ ps,
-                                                      float* __restrict__ pw, int side, const Ctrl* __restrict__ c) {
+                                                      float* __restrict__ pw, int side, const Ctrl* __restrict__ c,
+                                                      int skip_tiles, unsigned long long* __restrict__ pairs) {
   using Op = typename MfOps<SPLIT>::Op;
   if (skip_side(c, side)) return;
   // column operands of a chunk of 512 columns and two padding tiles (read
   // by the discarded final products of the passes): FP32 [k][column], BF16
-  // x 3 [column][q]
+  // x 3 [column][q]; the chunk's tile records
   __shared__ Op st[4 * mf_cols(512)];
   __shared__ float sbox[4][6];
+  __shared__ float tb[32][8];
   const float cc = float(kLog2e / eps_of(c, side));
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, q = lane >> 4;
@@ -460,7 +565,10 @@ __global__ __launch_bounds__(kBlock) void k_dense_mf(const float* __restrict__ x
   const int nrow = (int)(Nr - bbase < 64 * G ? Nr - bbase : 64 * G);
   float* pws = pw + blockIdx.y * Nr + bbase;
   float m[G], tot[G], rc[G];
-  mf_tile<DIM, G, SPLIT, 512>(xr + bbase, Nr, nrow, yc + cb, Mc, w + cb, ce - cb, cc, pws, st, sbox, m, tot, rc);
+  uint32_t evaluated = 0;
+  mf_tile<DIM, G, SPLIT, 512>(xr + bbase, Nr, nrow, yc + cb, Mc, w + cb, ce - cb, cc, pws, st, sbox, tb,
+                              skip_tiles != 0, m, tot, rc, evaluated);
+  if (pairs && lane == 0 && evaluated) atomicAdd(pairs, (unsigned long long)evaluated * (256ull * G));
   // lanes q = 0 write row 16 g + l: (m + R_i, total), and m for the next
   // product of this side
 #pragma unroll
@@ -488,11 +596,14 @@ __global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_batch_mf(const BItem
                                                       int64_t totR, const float* __restrict__ yc, int64_t totC,
                                                       const float* __restrict__ w, float* __restrict__ pw,
                                                       const BCtrl* __restrict__ bc, const Ctrl* __restrict__ c,
-                                                      int side, EpiArgs<float> ep) {
+                                                      int side, EpiArgs<float> ep, int skip_tiles,
+                                                      unsigned long long* __restrict__ pairs) {
   using Op = typename MfOps<SPLIT>::Op;
   __shared__ Op st[4 * mf_cols(256)];   // chunks of 256 columns: batch problems are small
   __shared__ float sbox[4][6];
+  __shared__ float tb[16][8];
   __shared__ int item_sh;
+  uint32_t evaluated = 0;
   const float cc = float(kLog2e / eps_of(c, side));
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, q = lane >> 4;
@@ -509,8 +620,8 @@ __global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_batch_mf(const BItem
     const int64_t rb = offR[I.prob] + I.row0;
     const int64_t cb = offC[I.prob], ce = offC[I.prob + 1];
     float m[G], tot[G], rc[G];
-    mf_tile<DIM, G, SPLIT, 256>(xr + rb, totR, I.nrows, yc + cb, totC, w + cb, ce - cb, cc, pw + rb, st, sbox, m,
-                                tot, rc);
+    mf_tile<DIM, G, SPLIT, 256>(xr + rb, totR, I.nrows, yc + cb, totC, w + cb, ce - cb, cc, pw + rb, st, sbox, tb,
+                                skip_tiles != 0, m, tot, rc, evaluated);
     ResAcc<float> ra;
     ra.init();
     // every lane of a row holds its (m, total); lane (q, l) finishes row
@@ -530,14 +641,20 @@ __global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_batch_mf(const BItem
     }
     epi_finish<float>(ep, ra, I.part);
   }
+  if (pairs && lane == 0 && evaluated) atomicAdd(pairs, (unsigned long long)evaluated * (256ull * G));
+}
+
+bool tile_skip_enabled() {
+  const char* e = std::getenv("UOT_TILE_SKIP");
+  return !(e && e[0] == '0' && e[1] == 0);
 }
 
 void launch_dense_mf(int dim, int groups, bool split, const float* xr, int64_t Nr, const float* yc, const float* w,
                      int64_t Mc, int nsplit, int64_t cps, float* pm, float* ps, float* pw, int side, const Ctrl* c,
-                     hipStream_t s) {
+                     const MfSkip& sk, hipStream_t s) {
 #define UOT_MF(D, G, S)                                                                                        \
   hipLaunchKernelGGL((k_dense_mf<D, G, S>), dim3((unsigned)((Nr + 64 * G - 1) / (64 * G)), (unsigned)nsplit), \
-                     dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, pw, side, c)
+                     dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, pw, side, c, sk.on, sk.pairs)
 #define UOT_MF_DIM(G, S)              \
   if (dim == 1) UOT_MF(1, G, S);      \
   else if (dim == 2) UOT_MF(2, G, S); \
@@ -566,10 +683,10 @@ namespace uot {
 void launch_batch_mf(int dim, int groups, int blocks, const BItem* items, const int* count, int* cursor,
                      const int64_t* offR, const int64_t* offC, const float* xr, int64_t totR, const float* yc,
                      int64_t totC, const float* w, float* pw, const BCtrl* bc, const Ctrl* c, int side,
-                     const EpiArgs<float>& ep, hipStream_t s) {
+                     const EpiArgs<float>& ep, const MfSkip& sk, hipStream_t s) {
 #define UOT_BMF(D, G)                                                                                           \
   hipLaunchKernelGGL((k_batch_mf<D, G, true>), dim3(blocks), dim3(kBlock), 0, s, items, count, cursor, offR, offC, \
-                     xr, totR, yc, totC, w, pw, bc, c, side, ep)
+                     xr, totR, yc, totC, w, pw, bc, c, side, ep, sk.on, sk.pairs)
   if (groups == 8) {
     if (dim == 1) UOT_BMF(1, 8);
     else if (dim == 2) UOT_BMF(2, 8);

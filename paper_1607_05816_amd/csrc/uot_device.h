@@ -150,6 +150,8 @@ struct Ctrl {
   int32_t nstop;      // problems stopped so far
   int32_t built[2];   // nstop when the item lists were last rebuilt (slot = iteration parity)
   uint64_t t0_clock;  // device wall clock at the start of the solve
+  // timed solves: pair evaluations of the matrix-core products
+  unsigned long long pairs;
 };
 
 // A kernel's `side` argument: bit 0 the half-step (0: X, 1: Y), bit 1 the

@@ -109,6 +109,14 @@ void launch_dense_tf(int dim, const float* xr, int64_t Nr, const float* yc, cons
 template <typename T>
 void launch_spatial_order_batch(const T* x, int64_t tot, const int64_t* off, int64_t B, int64_t nmax, int dim,
                                 T* box, uint32_t* code, int32_t* perm, hipStream_t s);
+// the matrix-core products' negligible tiles: on leaves them out (the
+// UOT_TILE_SKIP environment switch, on unless it is 0); pairs (device, or
+// null) accumulates the pair evaluations the products perform
+struct MfSkip {
+  int on = 1;
+  unsigned long long* pairs = nullptr;
+};
+bool tile_skip_enabled();
 // the ragged batch on the matrix cores (BF16 x 3 operands, FP32 data, squared
 // Euclidean): groups = 4 or 8 row groups of 16 per wave (items of 64 groups
 // rows); *count items of the list, pulled from *cursor (zero at launch);
@@ -116,7 +124,7 @@ void launch_spatial_order_batch(const T* x, int64_t tot, const int64_t* off, int
 void launch_batch_mf(int dim, int groups, int blocks, const BItem* items, const int* count, int* cursor,
                      const int64_t* offR, const int64_t* offC, const float* xr, int64_t totR, const float* yc,
                      int64_t totC, const float* w, float* pw, const BCtrl* bc, const Ctrl* c, int side,
-                     const EpiArgs<float>& ep, hipStream_t s);
+                     const EpiArgs<float>& ep, const MfSkip& sk, hipStream_t s);
 // dense product on the matrix cores (FP32 data, squared Euclidean): groups =
 // 4 or 8 row groups of 16 per wave; split: BF16 x 3 operands on
 // v_mfma_f32_16x16x32_bf16, else FP32 operands on v_mfma_f32_16x16x4f32;
@@ -124,7 +132,7 @@ void launch_batch_mf(int dim, int groups, int blocks, const BItem* items, const 
 // the product starts from and leaves for the next one
 void launch_dense_mf(int dim, int groups, bool split, const float* xr, int64_t Nr, const float* yc, const float* w,
                      int64_t Mc, int nsplit, int64_t cps, float* pm, float* ps, float* pw, int side, const Ctrl* c,
-                     hipStream_t s);
+                     const MfSkip& sk, hipStream_t s);
 template <typename T>
 void launch_coord_weight(const T* w, T* out, int64_t M, int64_t stride, int64_t nk, double hk, const T* yk, int sign,
                          hipStream_t s);
