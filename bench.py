@@ -217,12 +217,16 @@ def ragged_headline(U, ctx, dev, np, torch, steps, warmup):
     avg_ms = kms / launches
     peak = exp_peak()
     kname = {1: "k_batch_lse", 4: "k_batch_mf"}.get(int(tk["product"]), str(tk["product"]))
+    executed = float(tk["kernel_launches"][3])   # exp2 the matrix-core product issued (tiles left out)
     roof = {"bound": "alu", "kernel": kname, "kernel_avg_ms": avg_ms, "launches": int(launches),
             "work_per_launch": work / launches, "work_unit": "exp (one per pair; both half-steps)",
             "achieved": work / launches / (avg_ms * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "Texp/s",
-            "frac": work / launches / (avg_ms * 1e-3) / peak, "traffic": None,
+            "frac": work / launches / (avg_ms * 1e-3) / peak,
+            "exp_executed_per_launch": executed / launches if executed else None,
+            "frac_executed": executed / launches / (avg_ms * 1e-3) / peak if executed else None,
+            "traffic": None,
             "product_ms_total": kms, "control_ms_total": tk["kernel_ms"][2],
-            "note": "average over every product launch of a warm solve (converged problems' items exit at once)"}
+            "note": "average over every product launch of a warm solve (stopped problems leave the item lists)"}
     tr = batch_traffic(kname, int(tk["tile_rows"]))
     if tr is not None:
         # counters were read on full launches; the average launch carries
@@ -488,10 +492,16 @@ def dense_roofline(U, torch, np, dev, ctx, n=20000, eps=1e-3):
         ms = U.time_half_step(pb, eps, v, reps=20, ctx=ctx, grid_kernel=k)
         by[name] = {"kernel": kern, "kernel_avg_ms": ms[0], "merge_epilogue_ms": ms[1],
                     "frac": pairs / (ms[0] * 1e-3) / peak}
+        if len(ms) > 2:
+            # matrix-core products leave out tiles of negligible terms: the
+            # exp2 they issue per launch, and that rate against the peak
+            by[name]["exp_executed_per_launch"] = ms[2]
+            by[name]["frac_executed"] = ms[2] / (ms[0] * 1e-3) / peak
     d = by["mfma_bf16x3"]
     return {"bound": "alu", "kernel": d["kernel"], "kernel_avg_ms": d["kernel_avg_ms"],
             "achieved": pairs / (d["kernel_avg_ms"] * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "Texp/s",
             "frac": d["frac"], "work_per_launch": pairs, "work_unit": "exp (one per pair)",
+            "exp_executed_per_launch": d.get("exp_executed_per_launch"), "frac_executed": d.get("frac_executed"),
             "epilogue_ms": d["merge_epilogue_ms"], "by_kernel": by,
             "workload": "clouds3d N=M=%d eps=%g FP32, v = 0" % (n, eps)}
 

@@ -595,7 +595,10 @@ int uot_gemm_bf16(uot_ctx *ctx, int ta, int tb, int M, int N, int K, const uint1
  * launches of that kernel alone on the library stream.
  *   grid   : ms[0] contiguous-axis pass, ms[1..] strided passes (the last
  *            one carries the proxdiv epilogue and residual partials);
- *   points : ms[0] column-split log-sum-exp, ms[1] split merge + epilogue.
+ *   points : ms[0] column-split log-sum-exp, ms[1] split merge + epilogue;
+ *            with the matrix-core products (grid_kernel 3, 4) ms[2] is no
+ *            time but the pair evaluations of one product launch (they
+ *            leave out tiles of negligible terms, see kernel_launches).
  * *n_kernels receives the number of entries written (<= 3). */
 int uot_time_half_step(uot_ctx *ctx, const uot_problem *pb, double eps, const void *v,
                        int reps, double *ms, int *n_kernels, void *ws, size_t ws_bytes,

@@ -1457,8 +1457,11 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
           return;
         }
         if (P.dense_mf) {
+          MfSkip sk;   // counted: ms[2] reports the pair evaluations per launch
+          sk.on = tile_skip_enabled() ? 1 : 0;
+          sk.pairs = &B.ctrl->pairs;
           launch_dense_mf(P.dim, P.mf_groups, P.mf_split, rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps,
-                          B.pw, 0, B.ctrl, mf_skip(B.ctrl, false), s);
+                          B.pw, 0, B.ctrl, sk, s);
           return;
         }
       }
@@ -1481,6 +1484,13 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
     ms[q] = double(t) / reps;
   }
   *nk = (int)ks.size();
+  if (P.geom == UOT_GEOM_POINTS && P.dense_mf) {
+    // the product ran once untimed and reps times timed
+    unsigned long long pairs = 0;
+    HIP_TRY(hipMemcpy(&pairs, &B.ctrl->pairs, sizeof(pairs), hipMemcpyDeviceToHost));
+    ms[2] = double(pairs) / double(reps + 1);
+    *nk = 3;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   HIP_TRY(hipGetLastError());

@@ -85,54 +85,63 @@ __device__ __forceinline__ float sum_over_rows(float x) {
   return r.a + r.b;
 }
 
-// a = p[0] + p[1] + p[2] to 24 significant bits; -inf -> (-inf, 0, 0)
-__device__ __forceinline__ void split3(float a, __bf16 (&p)[3]) {
-  if (!(a > -__builtin_inff())) {
-    p[0] = (__bf16)a;
-    p[1] = p[2] = (__bf16)0.f;
-    return;
-  }
-  p[0] = (__bf16)a;
-  const float r1 = a - (float)p[0];
-  p[1] = (__bf16)r1;
-  p[2] = (__bf16)(r1 - (float)p[1]);
+// Operands built as packed words.  split3f(a) gives the three bf16 parts of
+// a (a1 = bf16(a), a2 = bf16(a - a1), a3 = bf16(a - a1 - a2); together 24
+// significant bits) as floats, a1 and a2 exact and a3 left unrounded: pk2
+// rounds it to bf16, and every other value it packs is a bf16 value already.
+// pk2(lo, hi) is one v_cvt_pk_bf16_f32: the word of two K slots.
+typedef float mf_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 mf_bf16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t mf_u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t pk2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(mf_f32x2{lo, hi}, mf_bf16x2));
+}
+__device__ __forceinline__ float bf16r(float x) { return (float)(__bf16)x; }
+__device__ __forceinline__ void split3f(float a, float (&p)[3]) {
+  p[0] = bf16r(a);
+  const float r1 = a - p[0];
+  p[1] = bf16r(r1);
+  p[2] = r1 - p[1];
+}
+// -inf -> (-inf, 0, 0)
+__device__ __forceinline__ void split3f_inf(float a, float (&p)[3]) {
+  const bool fin = a > -__builtin_inff();
+  split3f(fin ? a : 0.f, p);
+  p[0] = fin ? p[0] : a;
 }
 
-// slot k of the K = 32 operands: k < 18 is part product u = k % 6 of
-// coordinate k / 6, with (row part, column part) = (1,1) (1,2) (2,1) (1,3)
-// (2,2) (3,1); k = 18, 19, 20 carry G's parts against 1; the rest are 0
-template <int K>
-__device__ __forceinline__ __bf16 row_slot(const __bf16 (&e)[3][3]) {
-  if constexpr (K < 18) {
-    constexpr int u = K % 6;
-    return e[K / 6][(u == 2 || u == 4) ? 1 : (u == 5 ? 2 : 0)];
-  } else if constexpr (K < 21) {
-    return (__bf16)1.f;
-  } else {
-    return (__bf16)0.f;
+// The K = 32 slots of both operands: slot k < 18 is part product u = k % 6
+// of coordinate k / 6, with (row part, column part) = (1,1) (1,2) (2,1)
+// (1,3) (2,2) (3,1); slots 18, 19, 20 carry G's three parts against 1; the
+// rest are 0.  Words (slot pairs) of a column with parts b[d][.] of 2c(y -
+// xbar)_d and g[.] of G, and of a row with parts e[d][.] of (x - xbar)_d;
+// lane quarter q holds words 4q .. 4q + 3.
+__device__ __forceinline__ void col_words(const float (&b)[3][3], const float (&g)[3], mf_u32x4 (&w)[4]) {
+  uint32_t c[9];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    c[3 * d] = pk2(b[d][0], b[d][1]);
+    c[3 * d + 1] = pk2(b[d][0], b[d][2]);
+    c[3 * d + 2] = pk2(b[d][1], b[d][0]);
   }
+  w[0] = mf_u32x4{c[0], c[1], c[2], c[3]};
+  w[1] = mf_u32x4{c[4], c[5], c[6], c[7]};
+  w[2] = mf_u32x4{c[8], pk2(g[0], g[1]), pk2(g[2], 0.f), 0u};
+  w[3] = mf_u32x4{0u, 0u, 0u, 0u};
 }
-template <int K>
-__device__ __forceinline__ __bf16 col_slot(const __bf16 (&b)[3][3], const __bf16 (&g)[3]) {
-  if constexpr (K < 18) {
-    constexpr int u = K % 6;
-    return b[K / 6][(u == 1 || u == 4) ? 1 : (u == 3 ? 2 : 0)];
-  } else if constexpr (K < 21) {
-    return g[K - 18];
-  } else {
-    return (__bf16)0.f;
+__device__ __forceinline__ void row_words(const float (&e)[3][3], mf_u32x4 (&w)[4]) {
+  uint32_t c[9];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    c[3 * d] = pk2(e[d][0], e[d][0]);
+    c[3 * d + 1] = pk2(e[d][1], e[d][0]);
+    c[3 * d + 2] = pk2(e[d][1], e[d][2]);
   }
-}
-template <int Q>
-__device__ __forceinline__ mf_bf16x8 row_chunk(const __bf16 (&e)[3][3]) {
-  return mf_bf16x8{row_slot<8 * Q>(e),     row_slot<8 * Q + 1>(e), row_slot<8 * Q + 2>(e), row_slot<8 * Q + 3>(e),
-                   row_slot<8 * Q + 4>(e), row_slot<8 * Q + 5>(e), row_slot<8 * Q + 6>(e), row_slot<8 * Q + 7>(e)};
-}
-template <int Q>
-__device__ __forceinline__ mf_bf16x8 col_chunk(const __bf16 (&b)[3][3], const __bf16 (&g)[3]) {
-  return mf_bf16x8{col_slot<8 * Q>(b, g),     col_slot<8 * Q + 1>(b, g), col_slot<8 * Q + 2>(b, g),
-                   col_slot<8 * Q + 3>(b, g), col_slot<8 * Q + 4>(b, g), col_slot<8 * Q + 5>(b, g),
-                   col_slot<8 * Q + 6>(b, g), col_slot<8 * Q + 7>(b, g)};
+  w[0] = mf_u32x4{c[0], c[1], c[2], c[3]};
+  w[1] = mf_u32x4{c[4], c[5], c[6], c[7]};
+  w[2] = mf_u32x4{c[8], pk2(1.f, 1.f), pk2(1.f, 0.f), 0u};
+  w[3] = mf_u32x4{0u, 0u, 0u, 0u};
 }
 
 // operand forms: the lane's column operand of tile t (16 columns) from its
@@ -332,11 +341,12 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
       e2 = __builtin_fmaf(e[d], e[d], e2);
     }
     if constexpr (SPLIT) {
-      __bf16 p[3][3];
+      float p[3][3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) split3(e[d], p[d]);
-      const mf_bf16x8 r0 = row_chunk<0>(p), r1 = row_chunk<1>(p), r2 = row_chunk<2>(p), r3 = row_chunk<3>(p);
-      E[g] = q == 0 ? r0 : (q == 1 ? r1 : (q == 2 ? r2 : r3));
+      for (int d = 0; d < 3; ++d) split3f(e[d], p[d]);
+      mf_u32x4 rw[4];
+      row_words(p, rw);
+      E[g] = __builtin_bit_cast(mf_bf16x8, q == 0 ? rw[0] : (q == 1 ? rw[1] : (q == 2 ? rw[2] : rw[3])));
     } else {
       E[g] = q == 3 ? 1.f : (q == 0 ? e[0] : (q == 1 ? e[1] : e[2]));
     }
@@ -395,14 +405,14 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
         }
         const float gj = wj[h] == -__builtin_inff() ? wj[h] : __builtin_fmaf(-cc, d2, wj[h]);
         if constexpr (SPLIT) {
-          __bf16 b[3][3], gp[3];
+          float b[3][3], gp[3];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) split3(bd[d], b[d]);
-          split3(gj, gp);
-          st[lc * 4 + 0] = col_chunk<0>(b, gp);
-          st[lc * 4 + 1] = col_chunk<1>(b, gp);
-          st[lc * 4 + 2] = col_chunk<2>(b, gp);
-          st[lc * 4 + 3] = col_chunk<3>(b, gp);
+          for (int d = 0; d < 3; ++d) split3f(bd[d], b[d]);
+          split3f_inf(gj, gp);
+          mf_u32x4 cw[4];
+          col_words(b, gp, cw);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) st[lc * 4 + k] = __builtin_bit_cast(mf_bf16x8, cw[k]);
         } else {
 #pragma unroll
           for (int d = 0; d < 3; ++d) st[d * kCols + lc] = bd[d];
