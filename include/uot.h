@@ -251,6 +251,25 @@ int uot_workspace_size(const uot_problem *pb, size_t *bytes);
 int uot_solve(uot_ctx *ctx, const uot_problem *pb, const uot_params *pr,
               void *u, void *v, void *ws, size_t ws_bytes, uot_result *res);
 
+/* uot_solve without waiting (the asynchronous calls of the boundary): the
+ * iteration is enqueued on the context's stream and the call returns.  It
+ * enqueues ceil(max_iter / check_every) replays of the check_every-iteration
+ * chunk without polling the device: the iterations after the stop cost only
+ * their launches (a stopped iteration's kernels return at once), so choose
+ * max_iter near the iterations expected (e.g. a fixed count with tol = 0).
+ * u and v are written when the stream gets there; uot_sync_result waits for
+ * it and fills res (elapsed_ms: device time of the enqueued iterations).
+ * One asynchronous solve may be pending per context: every other call on it
+ * returns UOT_E_INVALID until uot_sync_result.  The workspace must stay
+ * untouched until then.  Not for the mixed-precision grid passes
+ * (grid_kernel 4, UOT_E_UNSUPPORTED) or timed solves (kernel_ms). */
+int uot_solve_async(uot_ctx *ctx, const uot_problem *pb, const uot_params *pr,
+                    void *u, void *v, void *ws, size_t ws_bytes);
+/* Wait for the pending asynchronous solve of ctx and fill res; returns what
+ * uot_solve would have (UOT_OK, UOT_NOT_CONVERGED, UOT_E_NONFINITE), or
+ * UOT_E_INVALID when nothing is pending. */
+int uot_sync_result(uot_ctx *ctx, uot_result *res);
+
 /* nb independent problems on one regular grid, solved together: p and q
  * point to nb x size arrays (field k at offset k*size), dx and dy are shared
  * (size), F1/F2/eps/schedule are shared.  u, v: device nb x size outputs.

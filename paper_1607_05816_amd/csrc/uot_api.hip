@@ -812,6 +812,43 @@ int run_loop(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration, uot
   return UOT_OK;
 }
 
+// The asynchronous form of run_loop: enqueue ceil(max_iter / chunk) chunks
+// without polling (the iterations after the device stops are no-ops: each
+// kernel of a skipped iteration returns at once), then a stream-ordered copy
+// of the control block to the pinned mirror.  The context keeps the chunk
+// graph until uot_sync_result.
+template <typename F>
+int run_async(uot_ctx* ctx, Ctrl* dctrl, const uot_params* pr, F&& iteration) {
+  hipStream_t s = ctx->work;
+  const int chunk = even_chunk(pr->check_every);
+  const int64_t n = (pr->max_iter + chunk - 1) / chunk;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (pr->use_graph) {
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < chunk; ++k) iteration(k & 1);
+    HIP_TRY(hipStreamEndCapture(s, &graph));
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(UOT_E_HIP, "hipGraphInstantiate failed");
+    }
+  }
+  ctx->pending = true;   // from here the context owns the graph
+  ctx->pending_graph = graph;
+  ctx->pending_exec = exec;
+  HIP_TRY(hipEventRecord(ctx->ev_t0, s));
+  for (int64_t k = 0; k < n; ++k) {
+    if (exec) {
+      HIP_TRY(hipGraphLaunch(exec, s));
+    } else {
+      for (int j = 0; j < chunk; ++j) iteration(j & 1);
+    }
+  }
+  HIP_TRY(hipEventRecord(ctx->ev_t1, s));
+  HIP_TRY(hipMemcpyAsync(ctx->pinned, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  return UOT_OK;
+}
+
 // Morton-ordered copies of both clouds for the tile-factored dense product:
 // coordinates gathered into the workspace (permutations kept there), the
 // problem returned points at the copies
@@ -924,7 +961,8 @@ int tune_dense_mf(uot_ctx* ctx, Plan& P, const uot_geom& g, Bufs<T>& B, hipStrea
 
 template <typename T>
 int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* v, char* ws, size_t wsb,
-            uot_result* res, int nb = 1, const MassOpt* mass = nullptr, double* log_z = nullptr) {
+            uot_result* res, int nb = 1, const MassOpt* mass = nullptr, double* log_z = nullptr,
+            bool async = false) {
   Plan P;
   const bool anneal = pr->eps0 > pr->eps && pr->eps_stages > 0 && pr->iters_per_stage > 0;
   int rc = make_plan(P, pb->dtype, pb->geom, nb, anneal ? pr->eps_stages + 1 : 1, pr->grid_kernel, pr->eps,
@@ -951,6 +989,9 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   }
   // mixed precision: FP16 passes down to kMixedSwitchTol, then FP32 passes
   const bool mixed = P.gk == 4 && has_tf16(P) && pr->tol < kMixedSwitchTol;
+  if (async && mixed)
+    return fail(UOT_E_UNSUPPORTED, "the mixed-precision grid passes switch under host control: solve synchronously");
+  if (async && pr->kernel_ms) return fail(UOT_E_INVALID, "timed solves run synchronously");
   const double tol1 = mixed ? kMixedSwitchTol : pr->tol;
   Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, tol1, pr->max_iter);
   launch_ctrl_init(B.ctrl, init, s);
@@ -1000,13 +1041,18 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
   auto iteration = iteration_with(P);
   auto iteration2 = iteration_with(P2);
   const double final_tol = pr->tol;
-  rc = run_loop(ctx, B.ctrl, pr, iteration, res, mixed ? &iteration2 : nullptr, &final_tol);
-  if (rc) return rc;
+  if (async) {
+    if ((rc = run_async(ctx, B.ctrl, pr, iteration))) return rc;
+  } else {
+    rc = run_loop(ctx, B.ctrl, pr, iteration, res, mixed ? &iteration2 : nullptr, &final_tol);
+    if (rc) return rc;
+  }
   if (P.sorted()) {
     launch_scatter<T>(uo, px, P.N, u, s);
     launch_scatter<T>(vo, py, P.M, v, s);
     HIP_TRY(hipGetLastError());
   }
+  if (async) return finish(ctx);   // the result waits for uot_sync_result
   if (log_z) *log_z = ctx->pinned->zeta;
   if ((rc = finish(ctx))) return rc;
   if (res->status == -3) return fail(UOT_E_NONFINITE, "non-finite residual");
@@ -2179,6 +2225,8 @@ int uot_create(uot_ctx** out, void* stream) {
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev_t0);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev_t1);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->pinned), sizeof(Ctrl), hipHostMallocDefault);
   if (e != hipSuccess) {
     uot_destroy(c);
@@ -2191,6 +2239,10 @@ int uot_create(uot_ctx** out, void* stream) {
 int uot_destroy(uot_ctx* c) {
   if (!c) return UOT_OK;
   if (c->work) (void)hipStreamSynchronize(c->work);
+  if (c->pending_exec) (void)hipGraphExecDestroy(c->pending_exec);
+  if (c->pending_graph) (void)hipGraphDestroy(c->pending_graph);
+  if (c->ev_t0) (void)hipEventDestroy(c->ev_t0);
+  if (c->ev_t1) (void)hipEventDestroy(c->ev_t1);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
@@ -2217,6 +2269,43 @@ int uot_solve(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, void* u
   if (pb->dtype == UOT_F32)
     return solve_t<float>(ctx, pb, pr, static_cast<float*>(u), static_cast<float*>(v), static_cast<char*>(ws), wsb, res);
   return solve_t<double>(ctx, pb, pr, static_cast<double*>(u), static_cast<double*>(v), static_cast<char*>(ws), wsb, res);
+}
+
+int uot_solve_async(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, void* u, void* v, void* ws,
+                    size_t wsb) {
+  if (!ctx) return fail(UOT_E_INVALID, "ctx is required");
+  int rc = validate_problem(pb);
+  if (rc) return rc;
+  if ((rc = validate_params(pr))) return rc;
+  uot_result unused{};
+  if (pb->dtype == UOT_F32)
+    return solve_t<float>(ctx, pb, pr, static_cast<float*>(u), static_cast<float*>(v), static_cast<char*>(ws), wsb,
+                          &unused, 1, nullptr, nullptr, true);
+  return solve_t<double>(ctx, pb, pr, static_cast<double*>(u), static_cast<double*>(v), static_cast<char*>(ws), wsb,
+                         &unused, 1, nullptr, nullptr, true);
+}
+
+int uot_sync_result(uot_ctx* ctx, uot_result* res) {
+  if (!ctx || !res) return fail(UOT_E_INVALID, "ctx and res are required");
+  if (!ctx->pending) return fail(UOT_E_INVALID, "no asynchronous solve is pending on this context");
+  const hipError_t e = hipStreamSynchronize(ctx->work);
+  float ms = 0.f;
+  const hipError_t et = e == hipSuccess ? hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1) : e;
+  if (ctx->pending_exec) (void)hipGraphExecDestroy(ctx->pending_exec);
+  if (ctx->pending_graph) (void)hipGraphDestroy(ctx->pending_graph);
+  ctx->pending_exec = nullptr;
+  ctx->pending_graph = nullptr;
+  ctx->pending = false;
+  if (e != hipSuccess) return fail(UOT_E_HIP, std::string("asynchronous solve failed: ") + hipGetErrorString(e));
+  if (et != hipSuccess) return fail(UOT_E_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(et));
+  const Ctrl& c = *ctx->pinned;
+  res->iters = c.iter;
+  res->residual = c.res;
+  res->du_inf = c.du;
+  res->status = c.status;
+  res->elapsed_ms = ms;
+  if (c.status == -3) return fail(UOT_E_NONFINITE, "non-finite residual");
+  return c.status == 0 ? UOT_OK : UOT_NOT_CONVERGED;
 }
 
 int uot_fields_workspace_size(const uot_problem* pb, int nb, size_t* bytes) {

@@ -20,6 +20,13 @@ struct uot_ctx {
   hipError_t scratch_err = hipSuccess;     // why it is missing, if it is
   std::map<std::string, std::pair<int, int>> batch_tuned;   // batch signature -> (R, blocks per CU)
   std::map<std::string, int> dense_tuned;                    // matrix-core product shape -> block target
+  // an asynchronous solve whose result uot_sync_result has not collected:
+  // its chunk graph (kept until the stream has run it) and the events
+  // around its iterations
+  bool pending = false;
+  hipGraph_t pending_graph = nullptr;
+  hipGraphExec_t pending_exec = nullptr;
+  hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
 };
 
 namespace uot {
@@ -36,6 +43,8 @@ int fail(int code, const std::string& msg);
 // stream handshake: the library stream waits for the caller's stream at the
 // start of a call, and the caller's stream waits for the library's at the end
 inline int begin(uot_ctx* ctx) {
+  if (ctx->pending)
+    return fail(UOT_E_INVALID, "an asynchronous solve is pending on this context: call uot_sync_result first");
   HIP_TRY(hipEventRecord(ctx->ev_in, ctx->user));
   HIP_TRY(hipStreamWaitEvent(ctx->work, ctx->ev_in, 0));
   return UOT_OK;

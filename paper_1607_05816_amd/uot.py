@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libuot.so")
 
 UOT_OK, UOT_NOT_CONVERGED = 0, 1
+UOT_E_INVALID, UOT_E_UNSUPPORTED, UOT_E_NONFINITE, UOT_E_HIP, UOT_E_WORKSPACE = -1, -2, -3, -4, -5
 UOT_DIV_EQ, UOT_DIV_KL, UOT_DIV_TV, UOT_DIV_RG, UOT_DIV_GROWTH = 0, 1, 2, 3, 4
 UOT_F64, UOT_F32 = 0, 1
 UOT_GEOM_POINTS, UOT_GEOM_GRID = 0, 1
@@ -107,6 +108,8 @@ def lib():
         "uot_destroy": (c_i32, [c_vp]),
         "uot_workspace_size": (c_i32, [P(UotProblem), P(ctypes.c_size_t)]),
         "uot_solve": (c_i32, [c_vp, P(UotProblem), P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t, P(UotResult)]),
+        "uot_solve_async": (c_i32, [c_vp, P(UotProblem), P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t]),
+        "uot_sync_result": (c_i32, [c_vp, P(UotResult)]),
         "uot_half_step": (c_i32, [c_vp, P(UotProblem), c_dbl, c_i32, c_vp, c_vp, c_vp, P(c_dbl), c_vp,
                                   ctypes.c_size_t]),
         "uot_half_step_noalloc": (c_i32, [c_vp, P(UotProblem), c_dbl, c_i32, c_vp, c_vp, c_vp, P(c_dbl)]),
@@ -416,6 +419,42 @@ def solve(prob: Problem, eps, ctx: Optional[Context] = None, v0=None, record=Fal
         info["kernel_ms"] = [kms[k] for k in range(4)]
         info["kernel_launches"] = [kcnt[k] for k in range(4)]
     return u, v, info
+
+
+class PendingSolve:
+    """An asynchronous solve (uot_solve_async): u and v fill in on the
+    context's stream; result() waits (uot_sync_result) and returns the info
+    dict of solve.  Holds the workspace and v0 until then."""
+
+    def __init__(self, ctx, u, v, keep):
+        self.ctx, self.u, self.v, self._keep = ctx, u, v, keep
+        self._info = None
+
+    def result(self):
+        if self._info is None:
+            res = UotResult()
+            code = lib().uot_sync_result(self.ctx.handle, ctypes.byref(res))
+            self._keep = None
+            _check(code, "uot_sync_result")
+            self._info = dict(iters=res.iters, residual=res.residual, du_inf=res.du_inf, status=res.status,
+                              elapsed_ms=res.elapsed_ms, converged=(code == UOT_OK))
+        return self._info
+
+
+def solve_async(prob: Problem, eps, ctx: Optional[Context] = None, v0=None, **kw) -> PendingSolve:
+    """solve without waiting: enqueues ceil(max_iter / check_every) chunks of
+    iterations (no-ops after the stop) and returns a PendingSolve."""
+    ctx = ctx or default_context()
+    dev = prob.p.device
+    u = torch.empty(prob.N, dtype=prob.dtype, device=dev)
+    v = torch.empty(prob.M, dtype=prob.dtype, device=dev)
+    if v0 is not None:
+        _dev(v0, prob.dtype, prob.M, "v0")
+    pr = params(eps, v0=v0, **kw)
+    ws = prob.workspace()
+    _check(lib().uot_solve_async(ctx.handle, ctypes.byref(prob.c), ctypes.byref(pr), _ptr(u), _ptr(v), _ptr(ws),
+                                 ws.numel()), "uot_solve_async", False)
+    return PendingSolve(ctx, u, v, (ws, v0))
 
 
 def half_step(prob: Problem, eps, side, pot_in, pot_old, ctx: Optional[Context] = None):
