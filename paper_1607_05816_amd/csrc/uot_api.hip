@@ -1476,6 +1476,7 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
   EpiArgs<T> ep = prox_epi<T>(B.t3, B.wu, B.logp, B.logdx, nullptr, B.parts, P.N, pb->F1);
   EpiArgs<T> raw{};
   raw.mode = EPI_RAW;
+  bool count_pairs = false;   // the matrix-core product's pair counter, off while timed
   std::vector<std::function<void()>> ks;
   if (P.geom == UOT_GEOM_GRID) {
     const int64_t nbf = nb;
@@ -1503,9 +1504,9 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
           return;
         }
         if (P.dense_mf) {
-          MfSkip sk;   // counted: ms[2] reports the pair evaluations per launch
+          MfSkip sk;   // counted only in the extra launch after the timed ones
           sk.on = tile_skip_enabled() ? 1 : 0;
-          sk.pairs = &B.ctrl->pairs;
+          sk.pairs = count_pairs ? &B.ctrl->pairs : nullptr;
           launch_dense_mf(P.dim, P.mf_groups, P.mf_split, rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps,
                           B.pw, 0, B.ctrl, sk, s);
           return;
@@ -1531,10 +1532,14 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
   }
   *nk = (int)ks.size();
   if (P.geom == UOT_GEOM_POINTS && P.dense_mf) {
-    // the product ran once untimed and reps times timed
+    // one more launch of the product, counted and not timed (the same state
+    // as the timed ones: v fixed, the row maxima they left)
+    count_pairs = true;
+    ks[0]();
     unsigned long long pairs = 0;
-    HIP_TRY(hipMemcpy(&pairs, &B.ctrl->pairs, sizeof(pairs), hipMemcpyDeviceToHost));
-    ms[2] = double(pairs) / double(reps + 1);
+    HIP_TRY(hipMemcpyAsync(&pairs, &B.ctrl->pairs, sizeof(pairs), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    ms[2] = double(pairs);
     *nk = 3;
   }
   (void)hipEventDestroy(e0);

@@ -246,6 +246,21 @@ __device__ __forceinline__ float row16_min(float v) {
   return fminf(v, dpp_mov<kDppMirror>(v));
 }
 
+// the pair evaluations of a block (its waves' tile counts, wave-uniform) added
+// to *pairs with one atomic per block (every thread of the block calls it)
+template <int G>
+__device__ __forceinline__ void count_pairs(unsigned long long* pairs, uint32_t evaluated) {
+  __shared__ uint32_t wsum[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = evaluated;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; ++k) t += wsum[k];
+    if (t) atomicAdd(pairs, t * (256ull * G));
+  }
+}
+
 // Negligible tiles (the adaptive truncation of the kernel discussed in the
 // section on the further tricks of the sparse scaling literature, applied on
 // the fly).  With e_i = x_i - xbar, the exponent a product pass evaluates is
@@ -578,7 +593,7 @@ __global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_dense_mf(const float
   uint32_t evaluated = 0;
   mf_tile<DIM, G, SPLIT, 512>(xr + bbase, Nr, nrow, yc + cb, Mc, w + cb, ce - cb, cc, pws, st, sbox, tb,
                               skip_tiles != 0, m, tot, rc, evaluated);
-  if (pairs && lane == 0 && evaluated) atomicAdd(pairs, (unsigned long long)evaluated * (256ull * G));
+  if (pairs) count_pairs<G>(pairs, evaluated);
   // lanes q = 0 write row 16 g + l: (m + R_i, total), and m for the next
   // product of this side
 #pragma unroll
@@ -651,7 +666,7 @@ __global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_batch_mf(const BItem
     }
     epi_finish<float>(ep, ra, I.part);
   }
-  if (pairs && lane == 0 && evaluated) atomicAdd(pairs, (unsigned long long)evaluated * (256ull * G));
+  if (pairs) count_pairs<G>(pairs, evaluated);
 }
 
 bool tile_skip_enabled() {
@@ -662,9 +677,13 @@ bool tile_skip_enabled() {
 void launch_dense_mf(int dim, int groups, bool split, const float* xr, int64_t Nr, const float* yc, const float* w,
                      int64_t Mc, int nsplit, int64_t cps, float* pm, float* ps, float* pw, int side, const Ctrl* c,
                      const MfSkip& sk, hipStream_t s) {
+  // tiles are left out only within a single column split: with several,
+  // each split's bound is relative to its own maximum, whose tile is always
+  // kept, so little goes and the tile records cost more than they save
+  const int skip = sk.on && nsplit == 1 ? 1 : 0;
 #define UOT_MF(D, G, S)                                                                                        \
   hipLaunchKernelGGL((k_dense_mf<D, G, S>), dim3((unsigned)((Nr + 64 * G - 1) / (64 * G)), (unsigned)nsplit), \
-                     dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, pw, side, c, sk.on, sk.pairs)
+                     dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, pw, side, c, skip, sk.pairs)
 #define UOT_MF_DIM(G, S)              \
   if (dim == 1) UOT_MF(1, G, S);      \
   else if (dim == 2) UOT_MF(2, G, S); \

@@ -15,7 +15,8 @@ dispatches, one column per counter (--last N: over the last N dispatches of
 each, in dispatch order); --match keeps kernels whose name holds S.
 
 --pmc: the counter_collection.csv files of two `rocprofv3 --pmc FETCH_SIZE`
-and `--pmc WRITE_SIZE` runs of the same program.  Both counters read KiB per
+and `--pmc WRITE_SIZE` runs of the same program (--last N: means over the
+last N dispatches of each kernel and launch size).  Both counters read KiB per
 dispatch; each is calibrated by the largest single `__amd_rocclr_copyBuffer`
 dispatch of the run, a plain device copy of --copy-bytes bytes (it fetches
 and writes exactly that many), and the table gives calibrated bytes per
@@ -40,11 +41,17 @@ def summarize(path, top=12):
     return "\n".join(out)
 
 
-def _counter_means(path):
+def _counter_means(path, last=0):
+    """Mean counter value per (kernel, grid size), over the last `last`
+    dispatches of each in dispatch order (all when 0)."""
     agg = collections.defaultdict(list)
-    for r in csv.DictReader(open(path)):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: int(r.get("Dispatch_Id") or 0))
+    for r in rows:
         name = r["Kernel_Name"].split("(")[0].replace("void ", "")
         agg[(name, int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+    if last > 0:
+        agg = {k: v[-last:] for k, v in agg.items()}
     return {k: sum(v) / len(v) for k, v in agg.items()}, {k: len(v) for k, v in agg.items()}
 
 
@@ -57,9 +64,9 @@ def _largest_copy(path):
     return max(vals)
 
 
-def summarize_pmc(fetch_csv, write_csv, copy_bytes, top=12, match=None):
-    f, nf = _counter_means(fetch_csv)
-    w, _ = _counter_means(write_csv)
+def summarize_pmc(fetch_csv, write_csv, copy_bytes, top=12, match=None, last=0):
+    f, nf = _counter_means(fetch_csv, last)
+    w, _ = _counter_means(write_csv, last)
     cf, cw = _largest_copy(fetch_csv), _largest_copy(write_csv)
     kf = copy_bytes / (cf * 1024.0)
     kw = copy_bytes / (cw * 1024.0)
@@ -111,7 +118,7 @@ def main():
     if a.counters:
         print(summarize_counters(a.counters, a.match, a.last))
     elif a.pmc:
-        print(summarize_pmc(a.pmc[0], a.pmc[1], a.copy_bytes, a.top, a.match))
+        print(summarize_pmc(a.pmc[0], a.pmc[1], a.copy_bytes, a.top, a.match, a.last))
     else:
         print(summarize(a.db, a.top))
 
