@@ -364,11 +364,11 @@ TRAFFIC_BYTES = {
 # runs of `bench.py --pmc-workload batch`; valid for the source they were
 # taken on (sha256 of the product's file and the headers it includes).
 BATCH_TRAFFIC_SOURCES = ["uot_dense_mf.hip", "uot_epilogue.h", "uot_device.h", "uot_launch.h"]
-BATCH_TRAFFIC_SHA256 = "5a958ffcdce93c81f00f6fd9a988c2e7530deef7138925184d8d13a323dee636"
+BATCH_TRAFFIC_SHA256 = "a3ae54a411d7f83e7fb2c70ac48629872ae9cc6dffc53fee9b6e5e1731bbdf09"
 # (kernel, rows per item) -> (bytes read, bytes written, pair evaluations) of
 # one launch that holds every problem (the counter workload: all 4096
 # problems active, warm maxima)
-BATCH_TRAFFIC_BYTES = {("k_batch_mf", 256): (247071674, 52733956, 3782323547)}
+BATCH_TRAFFIC_BYTES = {("k_batch_mf", 256): (257609989, 56952992, 3782323547)}
 
 
 def _sha256(names):
