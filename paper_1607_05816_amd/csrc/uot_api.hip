@@ -2555,7 +2555,8 @@ int uot_solve_batched(uot_ctx* ctx, const uot_batch_problem* pb, const uot_param
 int uot_bary_workspace_size(const uot_bary_problem* pb, size_t* bytes) {
   if (!pb || !bytes) return fail(UOT_E_INVALID, "NULL argument");
   if (pb->geom.kind != UOT_GEOM_GRID) return fail(UOT_E_UNSUPPORTED, "barycentres need a grid geometry");
-  if (pb->n < 1 || pb->n > kMaxBary) return fail(UOT_E_UNSUPPORTED, "1 <= n <= 64 marginals");
+  if (pb->n < 1) return fail(UOT_E_INVALID, "a barycentre needs n >= 1 marginals");
+  if (pb->n > kMaxBary) return fail(UOT_E_UNSUPPORTED, "at most 64 marginals");
   Plan P;
   int rc = make_plan(P, pb->dtype, pb->geom, pb->n, kMaxStages + 1);
   if (rc) return rc;
@@ -2567,7 +2568,8 @@ int uot_barycenter(uot_ctx* ctx, const uot_bary_problem* pb, const uot_params* p
                    void* ws, size_t wsb, uot_result* res) {
   if (!ctx || !pb || !res) return fail(UOT_E_INVALID, "ctx, problem and res are required");
   if (pb->geom.kind != UOT_GEOM_GRID) return fail(UOT_E_UNSUPPORTED, "barycentres need a grid geometry");
-  if (pb->n < 1 || pb->n > kMaxBary) return fail(UOT_E_UNSUPPORTED, "1 <= n <= 64 marginals");
+  if (pb->n < 1) return fail(UOT_E_INVALID, "a barycentre needs n >= 1 marginals");
+  if (pb->n > kMaxBary) return fail(UOT_E_UNSUPPORTED, "at most 64 marginals");
   if (!pb->p || !pb->dx || !pb->dy || !pb->alpha) return fail(UOT_E_INVALID, "p, dx, dy, alpha are required");
   for (int k = 0; k < pb->n; ++k)
     if (!(pb->alpha[k] > 0)) return fail(UOT_E_INVALID, "alpha_k must be > 0");
