@@ -682,6 +682,16 @@ def pmc_workload_dense(U, torch, np, dev, ctx, n=20000):
     print("pmc dense workload done", flush=True)
 
 
+def calibration_copy(torch, dev):
+    """Three 256 MiB device copies: the kernel of known traffic the HBM
+    counters are calibrated on."""
+    src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def pmc_workload_batch(U, torch, np, dev, ctx, iters=10):
     """The launches the batched product's counters are read on: a 256 MiB
     device copy (the calibration kernel of known size), then one batched
@@ -689,11 +699,7 @@ def pmc_workload_batch(U, torch, np, dev, ctx, iters=10):
     from the warm start (no tolerance, so every launch holds every problem),
     after the batch signature's tuning solve."""
     from paper_1607_05816_amd import cloud_warmstart as CW
-    src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
+    calibration_copy(torch, dev)
     cw = CW.CloudWarmStart.load(CW.WEIGHTS, dev)
     bp = CW.batch_problem(CW.ragged(0, B=RAGGED_B), dev)
     CW.solve(bp, ctx=ctx, tol=0.0, max_iter=4)
@@ -833,9 +839,10 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-gemm", action="store_true")
     ap.add_argument("--no-extensions", action="store_true")
-    ap.add_argument("--pmc-workload", nargs="?", const="grid", choices=("grid", "dense", "batch"),
+    ap.add_argument("--pmc-workload", nargs="?", const="grid", choices=("grid", "dense", "batch", "gemm"),
                     help="only run the launches counters are read on: the grid passes (HBM traffic), "
-                         "the dense products at 20000^2 or the batched product of the ragged workload")
+                         "the dense products at 20000^2, the batched product of the ragged workload or the "
+                         "training GEMMs of the warm-start net")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; "
@@ -864,6 +871,10 @@ def main():
         return
     if args.pmc_workload == "batch":
         pmc_workload_batch(U, torch, np, dev, U.default_context())
+        return
+    if args.pmc_workload == "gemm":
+        calibration_copy(torch, dev)
+        print(json.dumps(gemm_roofline(U, torch, np, dev, U.default_context())), flush=True)
         return
     ctx = U.default_context()
     head = ragged_headline(U, ctx, dev, np, torch, args.steps, args.warmup)

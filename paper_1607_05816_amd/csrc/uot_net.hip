@@ -30,10 +30,10 @@ constexpr int kB = 256;
 
 // FP32 -> BF16 bits, round to nearest even (NaN stays NaN)
 __device__ __forceinline__ u16 f2bf(float f) {
-  uint32_t x = __float_as_uint(f);
-  if ((x & 0x7f800000u) == 0x7f800000u) return (u16)((x >> 16) | ((x & 0xffffu) ? 0x40u : 0u));
-  x += 0x7fffu + ((x >> 16) & 1u);
-  return (u16)(x >> 16);
+  const uint32_t x = __float_as_uint(f);
+  const uint32_t special = (x >> 16) | ((x & 0xffffu) ? 0x40u : 0u);   // Inf stays Inf, NaN stays NaN
+  const uint32_t rounded = (x + 0x7fffu + ((x >> 16) & 1u)) >> 16;
+  return (u16)((x & 0x7f800000u) == 0x7f800000u ? special : rounded);
 }
 __device__ __forceinline__ float bf2f(u16 b) { return __uint_as_float((uint32_t)b << 16); }
 
@@ -66,6 +66,16 @@ __device__ __forceinline__ void load8(const u16* __restrict__ p, int avail, bool
   }
 }
 
+// LDS tiles are stored with their 16-byte k chunks permuted per row: element
+// (row, k) sits at column k ^ (sw(row) << 3), which keeps every 8-element
+// chunk whole (the MFMA operand reads stay single 16-byte reads) and spreads
+// over the banks the rows that one store or read instruction touches: the
+// element-wise stores of transposed tiles (rows 8 apart), the 16-byte stores
+// (4 rows of 4 chunks) and the operand reads (16 rows, one chunk).  sw takes
+// row bits 5, 4 (and 0 for whole-K tiles, whose rows hold 32 chunks).
+__device__ __forceinline__ int sw_step(int r) { return ((r >> 5) & 1) | (((r >> 4) & 1) << 1); }
+__device__ __forceinline__ int sw_whole(int r) { return sw_step(r) | ((r & 1) << 2); }
+
 // One 64 x 32 operand tile, as T[row][k] in LDS, moved in two steps so the
 // global loads of the next K tile overlap the MFMAs of the current one:
 // fetch_tile (global -> 8 registers per thread), store_tile (registers ->
@@ -95,11 +105,11 @@ __device__ __forceinline__ void store_tile(u16 (*T)[LK], const u16 (&v)[8]) {
     const int r = tid >> 2, c = (tid & 3) * 8;
     uint4 q;
     __builtin_memcpy(&q, v, sizeof(q));
-    *reinterpret_cast<uint4*>(&T[r][c]) = q;
+    *reinterpret_cast<uint4*>(&T[r][c ^ (sw_step(r) << 3)]) = q;
   } else {
     const int kk = tid >> 3, c = (tid & 7) * 8;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) T[c + j][kk] = v[j];
+    for (int j = 0; j < 8; ++j) T[c + j][kk ^ (sw_step(c + j) << 3)] = v[j];
   }
 }
 
@@ -111,11 +121,11 @@ __device__ __forceinline__ void store_tile_at(u16 (*T)[LD], int k0, const u16 (&
     const int r = tid >> 2, c = (tid & 3) * 8;
     uint4 q;
     __builtin_memcpy(&q, v, sizeof(q));
-    *reinterpret_cast<uint4*>(&T[r][k0 + c]) = q;
+    *reinterpret_cast<uint4*>(&T[r][(k0 + c) ^ (sw_whole(r) << 3)]) = q;
   } else {
     const int kk = tid >> 3, c = (tid & 7) * 8;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) T[c + j][k0 + kk] = v[j];
+    for (int j = 0; j < 8; ++j) T[c + j][(k0 + kk) ^ (sw_whole(c + j) << 3)] = v[j];
   }
 }
 
@@ -154,10 +164,12 @@ __global__ __launch_bounds__(kB) void k_gemm(const u16* __restrict__ A, int64_t 
     // of A and column (l % 16) of B, k = 8 (l / 16) .. 8 (l / 16) + 7
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+      const int ra_ = wm + i * 16 + (lane & 15);
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[ra_][((lane >> 4) * 8) ^ (sw_step(ra_) << 3)]);
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 16 + (lane & 15)][(lane >> 4) * 8]);
+        const int rb_ = wn + j * 16 + (lane & 15);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[rb_][((lane >> 4) * 8) ^ (sw_step(rb_) << 3)]);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
       }
     }
@@ -193,7 +205,20 @@ __global__ __launch_bounds__(kB) void k_gemm(const u16* __restrict__ A, int64_t 
 // stepped kernel above waits for one round trip per K tile.
 constexpr int kWholeK = 256, LW = kWholeK + 8;
 
-template <bool TA, bool TB>
+// FULL: every tile of the launch lies inside both operands and the result
+// (M, N multiples of 64, K a multiple of kc, kc of 32) and both operands move
+// as 16-byte vectors: no bounds tests and no element-wise fallback, which
+// keeps the kernel a fraction of the general one's code.
+template <bool TRANS>
+__device__ __forceinline__ void fetch_full(u16 (&v)[8], const u16* __restrict__ X, int64_t ld, int r0, int k0) {
+  const int tid = threadIdx.x;
+  const u16* p = !TRANS ? X + (int64_t)(r0 + (tid >> 2)) * ld + k0 + (tid & 3) * 8
+                        : X + (int64_t)(k0 + (tid >> 3)) * ld + r0 + (tid & 7) * 8;
+  const uint4 q = *reinterpret_cast<const uint4*>(p);
+  __builtin_memcpy(v, &q, sizeof(q));
+}
+
+template <bool TA, bool TB, bool FULL>
 __global__ __launch_bounds__(kB) void k_gemm_whole(const u16* __restrict__ A, int64_t lda,
                                                     const u16* __restrict__ Bm, int64_t ldb, int M, int N, int K,
                                                     float* __restrict__ C, int64_t ldc, u16* __restrict__ Cb,
@@ -214,8 +239,13 @@ __global__ __launch_bounds__(kB) void k_gemm_whole(const u16* __restrict__ A, in
 #pragma unroll
   for (int t = 0; t < kWholeK / TK; ++t) {
     if (t < nkt) {
-      fetch_tile<TA>(ra[t], A, lda, m0, M, kb + t * TK, ke, va);
-      fetch_tile<!TB>(rb[t], Bm, ldb, n0, N, kb + t * TK, ke, vb);
+      if constexpr (FULL) {
+        fetch_full<TA>(ra[t], A, lda, m0, kb + t * TK);
+        fetch_full<!TB>(rb[t], Bm, ldb, n0, kb + t * TK);
+      } else {
+        fetch_tile<TA>(ra[t], A, lda, m0, M, kb + t * TK, ke, va);
+        fetch_tile<!TB>(rb[t], Bm, ldb, n0, N, kb + t * TK, ke, vb);
+      }
     }
   }
 #pragma unroll
@@ -235,34 +265,42 @@ __global__ __launch_bounds__(kB) void k_gemm_whole(const u16* __restrict__ A, in
     const int kk = t * TK + (lane >> 4) * 8;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + (lane & 15)][kk]);
+      const int ra_ = wm + i * 16 + (lane & 15);
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[ra_][kk ^ (sw_whole(ra_) << 3)]);
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 16 + (lane & 15)][kk]);
+        const int rb_ = wn + j * 16 + (lane & 15);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[rb_][kk ^ (sw_whole(rb_) << 3)]);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
       }
     }
   }
+  // result layout: lane l holds rows 4 (l / 16) + r (r = 0..3), column l % 16
+  float* const Pz = P ? P + (int64_t)blockIdx.z * M * N : nullptr;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < 2; ++j) {
+    const int n = n0 + wn + j * 16 + (lane & 15);
+    const float bn = (!P && bias && (FULL || n < N)) ? bias[n] : 0.f;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < 2; ++i) {
+      const int mb = m0 + wm + i * 16 + 4 * (lane >> 4);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
-        const int n = n0 + wn + j * 16 + (lane & 15);
-        if (m < M && n < N) {
+        const int m = mb + r;
+        if (FULL || (m < M && n < N)) {
           float x = acc[i][j][r];
-          if (P) {
-            P[((int64_t)blockIdx.z * M + m) * N + n] = x;
+          if (Pz) {
+            Pz[(int64_t)m * N + n] = x;
           } else {
-            if (bias) x += bias[n];
+            x += bn;
             if (relu) x = x > 0.f ? x : 0.f;
             if (C) C[(int64_t)m * ldc + n] = x;
             if (Cb) Cb[(int64_t)m * ldc + n] = f2bf(x);
           }
         }
       }
+    }
+  }
 }
 
 // C[m][n] = bias[n] + sum_z P[z][m][n] (z in order: the result does not
@@ -314,14 +352,24 @@ static void gemm(const u16* A, int64_t lda, const u16* B, int64_t ldb, int M, in
   const dim3 grid(cdiv(N, TN), cdiv(M, TM), sz);
   constexpr int whole_lds = 2 * TM * LW * sizeof(u16);   // 66 KB: above the default 64 KB limit
   static const bool whole_ok = [] {
-    const bool ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_whole<TA, TB>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, whole_lds) == hipSuccess;
+    bool ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_whole<TA, TB, false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, whole_lds) == hipSuccess;
+    ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_whole<TA, TB, true>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, whole_lds) == hipSuccess;
     if (!ok) (void)hipGetLastError();   // the stepped kernel runs instead; clear the error
     return ok;
   }();
-  if (kc <= kWholeK && whole_ok)
-    hipLaunchKernelGGL((k_gemm_whole<TA, TB>), grid, dim3(kB), whole_lds, s, A, lda, B, ldb, M, N, K, C, ldc, Cb, bias,
-                       relu, kc, sz > 1 ? part : nullptr);
+  // 16-byte rows (leading dimensions of 8 elements, 16-byte aligned bases)
+  // and whole tiles everywhere: the bounds-free kernel
+  const bool full = lda % 8 == 0 && ldb % 8 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
+                    reinterpret_cast<uintptr_t>(B) % 16 == 0 && M % TM == 0 && N % TN == 0 && kc % TK == 0 &&
+                    K % kc == 0;
+  if (kc <= kWholeK && whole_ok && full)
+    hipLaunchKernelGGL((k_gemm_whole<TA, TB, true>), grid, dim3(kB), whole_lds, s, A, lda, B, ldb, M, N, K, C, ldc,
+                       Cb, bias, relu, kc, sz > 1 ? part : nullptr);
+  else if (kc <= kWholeK && whole_ok)
+    hipLaunchKernelGGL((k_gemm_whole<TA, TB, false>), grid, dim3(kB), whole_lds, s, A, lda, B, ldb, M, N, K, C, ldc,
+                       Cb, bias, relu, kc, sz > 1 ? part : nullptr);
   else
     hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(kB), 0, s, A, lda, B, ldb, M, N, K, C, ldc, Cb, bias, relu, kc,
                        sz > 1 ? part : nullptr);
