@@ -713,6 +713,20 @@ def pmc_workload_batch(U, torch, np, dev, ctx, iters=10):
 BF16_MFMA_PEAK = 2.5e15     # MI355X dense BF16 MFMA, FLOP/s
 
 
+def library_gemms(torch, dev, batch=256, reps=20):
+    """Context for a kernel trace of the GEMM workload: the same four BF16
+    products through torch's matmul (the platform BLAS), `reps` times each;
+    their kernels appear in the trace beside the library's own."""
+    g = torch.Generator(device="cpu")
+    g.manual_seed(0)
+    for M, N, K in ((batch, 256, 8192), (batch, 256, 4096), (256, 8192, batch), (batch, 4096, 256)):
+        a = torch.randn(M, K, generator=g).to(dev).to(torch.bfloat16)
+        b = torch.randn(K, N, generator=g).to(dev).to(torch.bfloat16)
+        for _ in range(reps):
+            torch.matmul(a, b)
+    torch.cuda.synchronize()
+
+
 def gemm_roofline(U, torch, np, dev, ctx, batch=256):
     """Training GEMMs of the warm-start net (8192 -> 256 -> 256 -> 256 -> 4096,
     BF16 operands, FP32 accumulation) at batch 256: the four largest products
@@ -875,6 +889,7 @@ def main():
     if args.pmc_workload == "gemm":
         calibration_copy(torch, dev)
         print(json.dumps(gemm_roofline(U, torch, np, dev, U.default_context())), flush=True)
+        library_gemms(torch, dev)
         return
     ctx = U.default_context()
     head = ragged_headline(U, ctx, dev, np, torch, args.steps, args.warmup)

@@ -205,6 +205,28 @@ __global__ __launch_bounds__(kB) void k_gemm(const u16* __restrict__ A, int64_t 
 // stepped kernel above waits for one round trip per K tile.
 constexpr int kWholeK = 256, LW = kWholeK + 8;
 
+// Block coordinates (output tile column, row, K range).  Workgroups go to
+// the 8 XCDs round-robin by linear id; with a K split of a multiple of 8
+// ranges, the tiles of one K range are all placed on one XCD, so each K
+// slice of both operands is fetched into one L2 and read there by every tile
+// that needs it (the plain order spreads them over 2-4 XCDs, each fetching
+// its own copy).
+__device__ __forceinline__ void block_coords(int& bx, int& by, int& bz) {
+  const int nx = gridDim.x, ny = gridDim.y, nz = gridDim.z;
+  if (nz % 8 != 0) {
+    bx = blockIdx.x;
+    by = blockIdx.y;
+    bz = blockIdx.z;
+    return;
+  }
+  const int nxy = nx * ny;
+  const int id = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+  const int slot = id >> 3, t = slot % nxy;
+  bz = (id & 7) + 8 * (slot / nxy);
+  bx = t % nx;
+  by = t / nx;
+}
+
 // FULL: every tile of the launch lies inside both operands and the result
 // (M, N multiples of 64, K a multiple of kc, kc of 32) and both operands move
 // as 16-byte vectors: no bounds tests and no element-wise fallback, which
@@ -227,8 +249,10 @@ __global__ __launch_bounds__(kB) void k_gemm_whole(const u16* __restrict__ A, in
   extern __shared__ __align__(16) u16 lds[];
   u16(*As)[LW] = reinterpret_cast<u16(*)[LW]>(lds);
   u16(*Bs)[LW] = reinterpret_cast<u16(*)[LW]>(lds + TM * LW);
-  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-  const int kb = blockIdx.z * kc;
+  int bx, by, bz;
+  block_coords(bx, by, bz);
+  const int m0 = by * TM, n0 = bx * TN;
+  const int kb = bz * kc;
   const int ke = kb + kc < K ? kb + kc : K;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
@@ -276,7 +300,7 @@ __global__ __launch_bounds__(kB) void k_gemm_whole(const u16* __restrict__ A, in
     }
   }
   // result layout: lane l holds rows 4 (l / 16) + r (r = 0..3), column l % 16
-  float* const Pz = P ? P + (int64_t)blockIdx.z * M * N : nullptr;
+  float* const Pz = P ? P + (int64_t)bz * M * N : nullptr;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int n = n0 + wn + j * 16 + (lane & 15);
