@@ -607,6 +607,26 @@ int uot_gemm_bf16(uot_ctx *ctx, int ta, int tb, int M, int N, int K, const uint1
                   void *ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------------------
+ * Tuning table.  The built-in tuners (ragged batches: product, rows per work
+ * item and persistent blocks per compute unit, per batch signature; the
+ * matrix-core dense products: column-split block target, per shape) time
+ * their candidates on the first solve of a signature and keep the choice in
+ * the context.  The table moves between contexts and processes as text, one
+ * entry per line (signatures are opaque tokens without spaces):
+ *   batch <signature> <product: 1 direct, 4 matrix core> <rows per item / 256> <blocks per CU>
+ *   dense <shape> <block target>
+ * uot_tuning_export writes the table, NUL-terminated, into buf (cap bytes)
+ * and the bytes it needs (with the NUL) into *len; a buffer too small (or
+ * NULL with cap 0, to ask for the size) gives UOT_E_INVALID with *len set.
+ * uot_tuning_import merges a table into the context (an entry replaces one
+ * of the same signature; empty lines are skipped).  A line that does not
+ * parse, or names a choice the tuner does not make, gives UOT_E_INVALID and
+ * nothing is imported.
+ * ------------------------------------------------------------------------- */
+int uot_tuning_export(uot_ctx *ctx, char *buf, size_t cap, size_t *len);
+int uot_tuning_import(uot_ctx *ctx, const char *text);
+
+/* ---------------------------------------------------------------------------
  * Measurement helpers (roofline evidence; not part of the iteration).
  * ------------------------------------------------------------------------- */
 /* Average device time in ms of each Gibbs-product kernel of one X half-step

@@ -12,6 +12,7 @@
 #include <functional>
 #include <map>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -2456,6 +2457,69 @@ int uot_time_fields_half_step(uot_ctx* ctx, const uot_problem* pb, int nb, doubl
 int uot_time_half_step(uot_ctx* ctx, const uot_problem* pb, double eps, const void* v, int reps, double* ms,
                        int* n_kernels, void* ws, size_t wsb, int grid_kernel) {
   return uot_time_fields_half_step(ctx, pb, 1, eps, v, reps, ms, n_kernels, ws, wsb, grid_kernel);
+}
+
+int uot_tuning_export(uot_ctx* ctx, char* buf, size_t cap, size_t* len) {
+  if (!ctx || !len) return fail(UOT_E_INVALID, "ctx and len are required");
+  std::string t;
+  for (const auto& e : ctx->batch_tuned) {
+    const int R = e.second.first & 15;
+    const bool mf = (e.second.first & 16) != 0;
+    t += "batch " + e.first + " " + (mf ? "4" : "1") + " " + std::to_string(R) + " " + std::to_string(e.second.second) +
+         "\n";
+  }
+  for (const auto& e : ctx->dense_tuned) t += "dense " + e.first + " " + std::to_string(e.second) + "\n";
+  *len = t.size() + 1;
+  if (!buf || cap < t.size() + 1) return fail(UOT_E_INVALID, "buffer too small for the tuning table");
+  std::memcpy(buf, t.c_str(), t.size() + 1);
+  return UOT_OK;
+}
+
+int uot_tuning_import(uot_ctx* ctx, const char* text) {
+  if (!ctx || !text) return fail(UOT_E_INVALID, "ctx and text are required");
+  std::map<std::string, std::pair<int, int>> batch;
+  std::map<std::string, int> dense;
+  const std::string all(text);
+  size_t pos = 0;
+  int line_no = 0;
+  while (pos <= all.size()) {
+    size_t end = all.find('\n', pos);
+    if (end == std::string::npos) end = all.size();
+    const std::string line = all.substr(pos, end - pos);
+    pos = end + 1;
+    ++line_no;
+    if (line.find_first_not_of(" \t\r") == std::string::npos) {
+      if (end == all.size()) break;
+      continue;
+    }
+    std::istringstream in(line);
+    std::string kind, sig, extra;
+    if (!(in >> kind >> sig)) return fail(UOT_E_INVALID, "tuning table line " + std::to_string(line_no) + ": no signature");
+    if (kind == "batch") {
+      int product = 0, R = 0, bpc = 0;
+      if (!(in >> product >> R >> bpc) || (in >> extra))
+        return fail(UOT_E_INVALID, "tuning table line " + std::to_string(line_no) + ": expected three numbers");
+      const bool mf = product == 4;
+      const bool ok = (product == 1 && (R == 1 || R == 2 || R == 4)) || (mf && (R == 1 || R == 2));
+      if (!ok || !(bpc == 4 || bpc == 8 || bpc == 16))
+        return fail(UOT_E_INVALID, "tuning table line " + std::to_string(line_no) + ": not a choice of the batch tuner");
+      batch[sig] = {R | (mf ? 16 : 0), bpc};
+    } else if (kind == "dense") {
+      int target = 0;
+      if (!(in >> target) || (in >> extra))
+        return fail(UOT_E_INVALID, "tuning table line " + std::to_string(line_no) + ": expected one number");
+      bool ok = false;
+      for (int k = 0; k < kMfNTargets; ++k) ok = ok || target == kMfTargets[k];
+      if (!ok) return fail(UOT_E_INVALID, "tuning table line " + std::to_string(line_no) + ": not a block target");
+      dense[sig] = target;
+    } else {
+      return fail(UOT_E_INVALID, "tuning table line " + std::to_string(line_no) + ": unknown kind '" + kind + "'");
+    }
+    if (end == all.size()) break;
+  }
+  for (const auto& e : batch) ctx->batch_tuned[e.first] = e.second;
+  for (const auto& e : dense) ctx->dense_tuned[e.first] = e.second;
+  return UOT_OK;
 }
 
 int uot_probe_rates(uot_ctx* ctx, double* exp_per_s, double* add_per_s) {

@@ -123,6 +123,8 @@ def lib():
         "uot_time_fields_half_step": (c_i32, [c_vp, P(UotProblem), c_i32, c_dbl, c_vp, c_i32, P(c_dbl), P(c_i32), c_vp,
                                        ctypes.c_size_t, c_i32]),
         "uot_probe_rates": (c_i32, [c_vp, P(c_dbl), P(c_dbl)]),
+        "uot_tuning_export": (c_i32, [c_vp, ctypes.c_char_p, ctypes.c_size_t, P(ctypes.c_size_t)]),
+        "uot_tuning_import": (c_i32, [c_vp, ctypes.c_char_p]),
         "uot_fields_workspace_size": (c_i32, [P(UotProblem), c_i32, P(ctypes.c_size_t)]),
         "uot_solve_fields": (c_i32, [c_vp, P(UotProblem), c_i32, P(UotParams), c_vp, c_vp, c_vp, ctypes.c_size_t,
                                      P(UotResult)]),
@@ -621,6 +623,22 @@ def probe_rates(ctx: Optional[Context] = None):
     e, a = c_dbl(), c_dbl()
     _check(lib().uot_probe_rates(ctx.handle, ctypes.byref(e), ctypes.byref(a)), "uot_probe_rates", False)
     return e.value, a.value
+
+
+def export_tuning(ctx: Optional[Context] = None) -> str:
+    """The context's tuning table (uot_tuning_export) as text."""
+    ctx = ctx or default_context()
+    n = ctypes.c_size_t()
+    lib().uot_tuning_export(ctx.handle, None, 0, ctypes.byref(n))   # asks for the size
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().uot_tuning_export(ctx.handle, buf, n.value, ctypes.byref(n)), "uot_tuning_export", False)
+    return buf.value.decode()
+
+
+def import_tuning(text: str, ctx: Optional[Context] = None) -> None:
+    """Merge a tuning table (uot_tuning_import) into the context."""
+    ctx = ctx or default_context()
+    _check(lib().uot_tuning_import(ctx.handle, text.encode()), "uot_tuning_import", False)
 
 
 class BatchProblem:

@@ -229,3 +229,44 @@ def test_batch_matrix_core_converged_bench_eps():
             assert shape < 1e-5, (b, its[b], shape)
             assert abs(got.mean() - ref.mean()) <= level, (b, its[b], got.mean() - ref.mean(), level)
             assert pot_rel_err(got, ref, eps) < 1e-5 + level / max(np.abs(ref).max(), eps), (b, its[b])
+
+
+def test_tuning_table_round_trip():
+    """The tuners' choices move to a new context as text: the batch solve
+    there skips tuning, takes the same choice and gives the same potentials;
+    a matrix-core dense solve adds its block target; tables that name a
+    choice the tuners do not make are refused whole."""
+    npd = np.float32
+    Ns, Ms, probs = make_batch(11, 16, 40, 600, 2, npd)
+    F = U.KL(1.0)
+    bp = to_gpu(Ns, Ms, probs, F, F, torch.float32)
+    say("case tuning table round trip")
+    c1, c2 = U.Context(), U.Context()
+    u1, v1, i1 = U.solve_batched(bp, 0.05, ctx=c1, tol=0.0, max_iter=20)
+    assert i1["tune_ms"] > 0.0
+    rng = np.random.default_rng(2)
+    n, m = 2048, 2560   # two shapes: one block target per side
+    T = lambda a: torch.tensor(a, dtype=torch.float32, device=DEV)
+    pb = U.points_problem(T(rng.uniform(0, 1, (n, 2))), T(rng.uniform(0, 1, (m, 2))), T(np.full(n, 1.0)),
+                          T(np.full(m, 1.0)), T(np.full(n, 1.0 / n)), T(np.full(m, 1.0 / m)), F, F)
+    U.solve(pb, 0.05, ctx=c1, tol=0.0, max_iter=4, dense_kernel=4)
+    text = U.export_tuning(c1)
+    lines = [l.split() for l in text.splitlines()]
+    assert sum(l[0] == "batch" for l in lines) == 1 and sum(l[0] == "dense" for l in lines) == 2, text
+    batch_line = [l for l in lines if l[0] == "batch"][0]
+    assert int(batch_line[2]) == i1["product"] and int(batch_line[4]) == i1["blocks_per_cu"]
+    assert int(batch_line[3]) * 256 == i1["tile_rows"]
+    for bad in ("batch sig 3 1 4\n", "batch sig 4 4 8\n", "batch sig 1 1 5\n", "dense k 999\n", "dense k\n",
+                "other a 1\n", "batch sig 1 1 4 extra\n"):
+        with pytest.raises(U.UotError):
+            U.import_tuning(text + bad, c2)
+    assert U.export_tuning(c2) == ""
+    U.import_tuning("\n" + text + "\n", c2)
+    assert U.export_tuning(c2) == text
+    u2, v2, i2 = U.solve_batched(bp, 0.05, ctx=c2, tol=0.0, max_iter=20)
+    assert i2["tune_ms"] == 0.0
+    assert (i2["product"], i2["tile_rows"], i2["blocks_per_cu"]) == (i1["product"], i1["tile_rows"],
+                                                                      i1["blocks_per_cu"])
+    assert torch.equal(u1, u2) and torch.equal(v1, v2)
+    c1.close()
+    c2.close()
