@@ -79,11 +79,12 @@ enum uot_dtype { UOT_F64 = 0, UOT_F32 = 1 };
  * WF, eq. "logcost", C_ij = -log cos^2((pi/2) |x_i - y_j| / cut) for
  * |x_i - y_j| < cut and +inf beyond (cost = UOT_COST_WF; the distance is
  * rescaled so that the cut locus pi/2 sits at `cut`).  K then has exact zeros:
- * the dense product skips whole (256-row block, column split) pairs whose
- * boxes lie beyond the cut (flagged once per call) and, inside a block,
- * column tiles whose box lies beyond the cut from the rows' box (pays when
- * points are stored in a spatially coherent order); 1-D grid passes read
- * only the taps within the cut.  The WF cost is
+ * a solve puts both clouds in Morton order on the device and, once per call,
+ * lists the (64-row wave, 16-column group) pairs whose boxes lie within the
+ * cut; its products evaluate only those, in work units of up to 16 groups
+ * (results come back in the caller's order, so the storage order of the
+ * points does not matter); 1-D grid passes read only the taps within the
+ * cut.  The WF cost is
  * not separable over axes: on grids it needs dim = 1.  Ragged batches take
  * the squared Euclidean cost only.
  *   UOT_GEOM_POINTS: point clouds; x is dim x N, y is dim x M, coordinate-major

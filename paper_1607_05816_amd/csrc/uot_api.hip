@@ -173,15 +173,29 @@ struct Plan {
   int mf_target[2] = {0, 0};                 // its block target per side (0: 1024)
   // the factored products run on Morton-ordered copies of the clouds (rows
   // of a wave or block lie close together, so the factored exponents keep
-  // small magnitudes); results are scattered back to the caller's order
-  bool sorted() const { return dense_tf || dense_mf; }
+  // small magnitudes), and so do the WF products (the boxes of row waves and
+  // column groups stay small, so few pairs of them lie within the cut);
+  // results are scattered back to the caller's order
+  bool sorted() const { return dense_tf || dense_mf || (geom == UOT_GEOM_POINTS && cost.kind == UOT_COST_WF); }
   // workspace offsets
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_t1, o_t2, o_t3, o_pm, o_ps, o_parts, o_gtab[3],
-      o_gcost, o_obj, o_scal, o_mass, o_xs, o_ys, o_permx, o_permy, o_code, o_box, o_us, o_vs, o_pw, o_wfbox,
-      o_wfact, total;
+      o_gcost, o_obj, o_scal, o_mass, o_xs, o_ys, o_permx, o_permy, o_code, o_box, o_us, o_vs, o_pw, o_wfl[2],
+      o_wfpart, total;
   int64_t obj_doubles = 0;
   int64_t np_pw = 0;                         // points: row maxima per side (matrix-core product)
-  bool wfb = false;                          // WF points: block / split boxes computed for this call
+  int64_t wf_slots = 0;                      // WF points: unit slots of the larger side
+  bool wfl = false;                          // WF points: work lists built for this call
+  int wf_umax[2] = {0, 0};                   // ... and the largest unit count of a row wave per side
+};
+
+// WF points, one side (rows against columns): row waves of 64 rows, column
+// groups of 16, mask words of 32 groups per row wave, and unit slots (a unit
+// holds up to 16 groups within the cut)
+struct WfShape {
+  int64_t nrw, ngr, nwd;
+  explicit WfShape(int64_t Nr, int64_t Mc) : nrw((Nr + 63) / 64), ngr((Mc + 15) / 16), nwd((ngr + 31) / 32) {}
+  int64_t words() const { return nrw * nwd; }
+  int64_t slots() const { return nrw * ((ngr + 15) / 16); }
 };
 
 bool use_tf(const Plan& P, int axis) { return P.tf_axis[axis]; }
@@ -398,15 +412,15 @@ int make_plan(Plan& P, int dtype, const uot_geom& g, int nb, int nst, int grid_k
   // row maxima the matrix-core product leaves for the next product of the
   // same side (two sides)
   P.o_pw = take(pts ? sizeof(float) * 2 * P.np_pw : 0);
-  // WF points: boxes of the 256-row blocks and of the column splits, both
-  // sides (row blocks of x, splits of y, row blocks of y, splits of x)
-  P.o_wfbox = take(pts && P.cost.kind == UOT_COST_WF
-                       ? e * 6 * ((P.N + 255) / 256 + (P.M + 255) / 256 + P.splits[0] + P.splits[1])
-                       : 0);
-  // ... and the activity flag of every (row block, column split) pair
-  P.o_wfact = take(pts && P.cost.kind == UOT_COST_WF
-                       ? (size_t)((P.N + 255) / 256 * P.splits[0] + (P.M + 255) / 256 * P.splits[1])
-                       : 0);
+  // WF points: the work lists of both sides (boxes, masks, units, counts)
+  // and the unit partials (shared by the sides, which run one after the other)
+  const bool wf = pts && P.cost.kind == UOT_COST_WF;
+  for (int h = 0; h < 2; ++h) {
+    const WfShape sh(h == 0 ? P.N : P.M, h == 0 ? P.M : P.N);
+    P.o_wfl[h] = take(wf ? e * 6 * (sh.nrw + sh.ngr) + 8 * sh.slots() + 4 * sh.words() + 4 * sh.nrw + 512 : 0);
+    P.wf_slots = std::max(P.wf_slots, wf ? sh.slots() : 0);
+  }
+  P.o_wfpart = take(wf ? 2 * e * 64 * P.wf_slots : 0);
   P.total = o;
   return UOT_OK;
 }
@@ -456,8 +470,8 @@ template <typename T> struct Bufs {
   double* scal;
   T *mass_m, *mass_s;     // mass partials of Algorithm 4 (Y epilogue)
   float* pw;              // points: row maxima of the two sides' products
-  T* wfbox;               // WF points: block and split boxes (Plan::o_wfbox)
-  uint8_t* wfact;         // WF points: activity of (row block, split) pairs, side 0 then side 1
+  WfLists<T> wfl[2];      // WF points: work lists per side
+  T *wfpm, *wfps;         // WF points: unit partials
 };
 
 template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
@@ -475,8 +489,20 @@ template <typename T> Bufs<T> carve(const Plan& P, char* ws) {
   b.pm = at<T>(ws, P.o_pm);
   b.ps = at<T>(ws, P.o_ps);
   b.pw = at<float>(ws, P.o_pw);
-  b.wfbox = at<T>(ws, P.o_wfbox);
-  b.wfact = at<uint8_t>(ws, P.o_wfact);
+  for (int h = 0; h < 2; ++h) {
+    const WfShape sh(h == 0 ? P.N : P.M, h == 0 ? P.M : P.N);
+    char* base = ws + P.o_wfl[h];
+    b.wfl[h].rbox = reinterpret_cast<T*>(base);
+    b.wfl[h].gbox = b.wfl[h].rbox + 6 * sh.nrw;
+    char* q = reinterpret_cast<char*>(b.wfl[h].gbox + 6 * sh.ngr);
+    q = ws + align_up((size_t)(q - ws));
+    b.wfl[h].units = reinterpret_cast<int2*>(q);
+    b.wfl[h].mask = reinterpret_cast<uint32_t*>(b.wfl[h].units + sh.slots());
+    b.wfl[h].ucnt = reinterpret_cast<int*>(b.wfl[h].mask + sh.words());
+    b.wfl[h].umax = b.wfl[h].ucnt + sh.nrw;
+  }
+  b.wfpm = at<T>(ws, P.o_wfpart);
+  b.wfps = b.wfpm + 64 * P.wf_slots;
   b.parts = at<ResPart>(ws, P.o_parts);
   for (int k = 0; k < 3; ++k) b.gtab[k] = at<T>(ws, P.o_gtab[k]);
   b.gcost = at<T>(ws, P.o_gcost);
@@ -564,41 +590,21 @@ void grid_chain(const Plan& P, const T* w, T* const* tabs, int side, Ctrl* c, co
   }
 }
 
-// WF point clouds: which (block of 256 rows, column split) pairs of each
-// side have a pair within the cut, from the boxes of the row blocks (R = 1
-// for the WF cost) and of the splits; once per call (the geometry is fixed),
-// and P.wfb tells the products and merges of this call to use the flags
+// WF point clouds: the work lists of both sides (the (row wave, column
+// group) pairs within the cut and their units), once per call (the geometry
+// is fixed); P.wfl tells the products of this call to run on them
 template <typename T>
-void wf_boxes(Plan& P, const uot_geom& g, Bufs<T>& B, hipStream_t s) {
-  if (P.geom != UOT_GEOM_POINTS || P.cost.kind != UOT_COST_WF || P.R[0] != 1 || P.R[1] != 1) return;
+int wf_lists(Plan& P, const uot_geom& g, Bufs<T>& B, hipStream_t s) {
+  if (P.geom != UOT_GEOM_POINTS || P.cost.kind != UOT_COST_WF) return UOT_OK;
   const T* x = static_cast<const T*>(g.x);
   const T* y = static_cast<const T*>(g.y);
-  const int64_t rN = (P.N + 255) / 256, rM = (P.M + 255) / 256;
-  T* bxr = B.wfbox;                               // x by 256
-  T* byc = bxr + 6 * rN;                          // y by side 0's splits
-  T* byr = byc + 6 * P.splits[0];                 // y by 256
-  T* bxc = byr + 6 * rM;                          // x by side 1's splits
-  launch_chunk_boxes<T>(x, P.N, 256, P.dim, bxr, s);
-  launch_chunk_boxes<T>(y, P.M, P.cps[0], P.dim, byc, s);
-  launch_chunk_boxes<T>(y, P.M, 256, P.dim, byr, s);
-  launch_chunk_boxes<T>(x, P.N, P.cps[1], P.dim, bxc, s);
-  const double cut2 = P.cost.cut * P.cost.cut;
-  launch_box_pairs<T>(bxr, rN, byc, P.splits[0], P.dim, cut2, B.wfact, s);
-  launch_box_pairs<T>(byr, rM, bxc, P.splits[1], P.dim, cut2, B.wfact + rN * P.splits[0], s);
-  P.wfb = true;
-}
-
-template <typename T>
-const uint8_t* wf_act(const Plan& P, const Bufs<T>& B, int half) {
-  if (!P.wfb) return nullptr;
-  return half == 0 ? B.wfact : B.wfact + (P.N + 255) / 256 * P.splits[0];
-}
-
-template <typename T>
-CostArgs wf_cost(const Plan& P, const Bufs<T>& B, int half) {
-  CostArgs ca = P.cost;
-  ca.act = wf_act<T>(P, B, half);
-  return ca;
+  launch_wf_lists<T>(x, P.N, y, P.M, P.dim, P.cost.cut, B.wfl[0], s);
+  launch_wf_lists<T>(y, P.M, x, P.N, P.dim, P.cost.cut, B.wfl[1], s);
+  // the launch size of the products: the largest unit count of a row wave
+  for (int h = 0; h < 2; ++h) HIP_TRY(hipMemcpyAsync(&P.wf_umax[h], B.wfl[h].umax, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  P.wfl = true;
+  return UOT_OK;
 }
 
 // the matrix-core products' tile skipping, and their pair count in timed
@@ -631,10 +637,18 @@ void dense_half(const Plan& P, const uot_geom& g, int side, const T* w_cols, Buf
         return;
       }
     }
+    if (P.wfl) {
+      launch_wf_lse<T>(P.dim, rows, Nr, cols, w_cols, Mc, P.cost.cut, B.wfl[half], P.wf_umax[half], B.wfpm, B.wfps,
+                       side, c, s);
+      return;
+    }
     launch_dense_lse<T>(P.dim, P.R[half], rows, Nr, cols, w_cols, Mc, P.splits[half], P.cps[half], B.pm, B.ps, side,
-                        c, wf_cost<T>(P, B, half), s);
+                        c, P.cost, s);
   });
-  timed(1, [&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[half], Nr, side, c, ep, s, wf_act<T>(P, B, half)); });
+  timed(1, [&] {
+    if (P.wfl) launch_wf_epi<T>(B.wfpm, B.wfps, B.wfl[half], Nr, Mc, side, c, ep, s);
+    else launch_dense_epi<T>(B.pm, B.ps, P.splits[half], Nr, side, c, ep, s);
+  });
 }
 
 template <typename T>
@@ -1016,7 +1030,7 @@ int solve_t(uot_ctx* ctx, const uot_problem* pb, const uot_params* pr, T* u, T* 
     // set: not finite), so a solve does not depend on what the workspace held
     HIP_TRY(hipMemsetAsync(B.pw, 0xFF, sizeof(float) * 2 * P.np_pw, s));
   }
-  wf_boxes<T>(P, pbs.geom, B, s);
+  if ((rc = wf_lists<T>(P, pbs.geom, B, s))) return rc;
   Plan P2 = P;
   for (int k = 0; k < 3; ++k) P2.tf16_axis[k] = false;
   const int nfields = nb > 1 ? nb : 0;
@@ -1473,7 +1487,7 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
     if (rc2) return rc2;
     HIP_TRY(hipMemsetAsync(B.pw, 0xFF, sizeof(float) * 2 * P.np_pw, s));
   }
-  wf_boxes<T>(P, pbs.geom, B, s);
+  if (int rc3 = wf_lists<T>(P, pbs.geom, B, s)) return rc3;
   EpiArgs<T> ep = prox_epi<T>(B.t3, B.wu, B.logp, B.logdx, nullptr, B.parts, P.N, pb->F1);
   EpiArgs<T> raw{};
   raw.mode = EPI_RAW;
@@ -1513,10 +1527,18 @@ int time_half_step_t(uot_ctx* ctx, const uot_problem* pb, int nb, double eps, co
           return;
         }
       }
+      if (P.wfl) {
+        launch_wf_lse<T>(P.dim, rows, P.N, cols, B.wv, P.M, P.cost.cut, B.wfl[0], P.wf_umax[0], B.wfpm, B.wfps, 0,
+                         B.ctrl, s);
+        return;
+      }
       launch_dense_lse<T>(P.dim, P.R[0], rows, P.N, cols, B.wv, P.M, P.splits[0], P.cps[0], B.pm, B.ps, 0, B.ctrl,
-                          wf_cost<T>(P, B, 0), s);
+                          P.cost, s);
     });
-    ks.push_back([&] { launch_dense_epi<T>(B.pm, B.ps, P.splits[0], P.N, 0, B.ctrl, ep, s, wf_act<T>(P, B, 0)); });
+    ks.push_back([&] {
+      if (P.wfl) launch_wf_epi<T>(B.wfpm, B.wfps, B.wfl[0], P.N, P.M, 0, B.ctrl, ep, s);
+      else launch_dense_epi<T>(B.pm, B.ps, P.splits[0], P.N, 0, B.ctrl, ep, s);
+    });
   }
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));

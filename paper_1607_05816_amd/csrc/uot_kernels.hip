@@ -336,12 +336,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const T* __restrict__ xr, 
                                                        const T* __restrict__ yc, const T* __restrict__ w,
                                                        int64_t Mc, int64_t cols_per_split,
                                                        T* __restrict__ pm, T* __restrict__ ps, int side,
-                                                       const Ctrl* __restrict__ c, T a2, T cut2,
-                                                       const uint8_t* __restrict__ act) {
+                                                       const Ctrl* __restrict__ c, T a2, T cut2) {
   if (skip_side(c, side)) return;
-  // WF: a block whose rows and column split are beyond the cut as boxes has
-  // only exact zeros; its partial is neither written nor merged
-  if (COST == 1 && act != nullptr && !act[(int64_t)blockIdx.x * gridDim.y + blockIdx.y]) return;
   using V4 = typename Vec4<T>::type;
   __shared__ V4 tile[kBlock];
   const T sc = T(kLog2e / eps_of(c, side));
@@ -941,15 +937,14 @@ void launch_dense_tf(int dim, const float* xr, int64_t Nr, const float* yc, cons
   else hipLaunchKernelGGL((k_dense_tf<3, 2>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side, c);
 }
 
-// merge the column splits of k_dense_lse, then the epilogue; grid = ceil(Nr/256)
-// log2 of the sum of n split partials (m, s) of row i (2^m s each; split
-// idx(k) for k < n): chunks of 16 splits are loaded together (one memory
-// round trip per chunk; lanes past n read split idx(0)'s partial of the row,
-// in bounds, and drop it), the chunk's maximum taken, and the running sum
-// rescaled once per chunk
-template <typename T, typename Idx>
-__device__ __forceinline__ T merge_splits(const T* __restrict__ pm, const T* __restrict__ ps, int64_t Nr, int64_t i,
-                                          int n, Idx idx) {
+// log2 of the sum of n partials (m, s) of one row (2^m s each, partial k at
+// base + k stride), in order of k: chunks of 16 partials are loaded together
+// (one memory round trip per chunk; lanes past n read partial 0 again, in
+// bounds, and drop it), the chunk's maximum taken, and the running sum
+// rescaled once per chunk; -inf when n = 0 or every partial is -inf
+template <typename T>
+__device__ __forceinline__ T merge_parts(const T* __restrict__ pm, const T* __restrict__ ps, int64_t stride,
+                                         int64_t base, int n) {
   constexpr int C = 16;
   T m = Num<T>::ninf(), acc = T(0);
   for (int k0 = 0; k0 < n; k0 += C) {
@@ -957,7 +952,7 @@ __device__ __forceinline__ T merge_splits(const T* __restrict__ pm, const T* __r
 #pragma unroll
     for (int k = 0; k < C; ++k) {
       const bool ok = k0 + k < n;
-      const int64_t off = (int64_t)idx(ok ? k0 + k : 0) * Nr + i;
+      const int64_t off = base + (int64_t)(ok ? k0 + k : 0) * stride;
       const T pa = pm[off], pb = ps[off];
       a[k] = ok ? pa : Num<T>::ninf();
       b[k] = ok ? pb : T(0);
@@ -980,57 +975,14 @@ __device__ __forceinline__ T merge_splits(const T* __restrict__ pm, const T* __r
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dense_epi(const T* __restrict__ pm, const T* __restrict__ ps,
                                                        int nsplit, int64_t Nr, int side,
-                                                       const Ctrl* __restrict__ c, EpiArgs<T> ep,
-                                                       const uint8_t* __restrict__ act) {
+                                                       const Ctrl* __restrict__ c, EpiArgs<T> ep) {
   if (skip_side(c, side)) return;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool valid = i < Nr;
   ResAcc<T> ra;
   ra.init();
-  // WF: only the partials of active (row block, split) pairs exist; the
-  // block's 256 rows are one row block of the product, so the flags are the
-  // same for every thread.  Up to kEpiList splits, the active ones are listed
-  // in LDS in split order (ballots per wave), so the loads below stay
-  // independent; beyond, each split's flag is tested in the loop.
-  constexpr int kEpiList = 1024;
-  __shared__ int lst[kEpiList];
-  __shared__ int wcnt[kBlock / 64];
-  int nact = -1;
-  if (act != nullptr && nsplit <= kEpiList) {
-    const uint8_t* a = act + (int64_t)blockIdx.x * nsplit;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    nact = 0;
-    for (int c0 = 0; c0 < nsplit; c0 += kBlock) {
-      const int sp = c0 + threadIdx.x;
-      const bool f = sp < nsplit && a[sp] != 0;
-      const uint64_t m = __ballot(f);
-      if (lane == 0) wcnt[wv] = __popcll(m);
-      __syncthreads();
-      int off = nact;
-      for (int k = 0; k < wv; ++k) off += wcnt[k];
-      if (f) lst[off + __popcll(m & ((uint64_t(1) << lane) - 1))] = sp;
-      for (int k = 0; k < kBlock / 64; ++k) nact += wcnt[k];
-      __syncthreads();
-    }
-  }
-  if (valid && nact >= 0) {
-    epi_elem<T>(i, merge_splits<T>(pm, ps, Nr, i, nact, [&](int k) { return lst[k]; }), c, side, ep, ra);
-  } else if (valid && act != nullptr) {
-    const uint8_t* a = act + (int64_t)blockIdx.x * nsplit;
-    T mx = Num<T>::ninf();
-    for (int s = 0; s < nsplit; ++s)
-      if (a[s]) mx = Num<T>::fmax(mx, pm[s * Nr + i]);
-    T lse = mx;
-    if (mx != Num<T>::ninf()) {
-      T sum = T(0);
-      for (int s = 0; s < nsplit; ++s)
-        if (a[s]) sum += ps[s * Nr + i] * Num<T>::exp2(pm[s * Nr + i] - mx);
-      lse = mx + Num<T>::log2(sum);
-    }
-    epi_elem<T>(i, lse, c, side, ep, ra);
-  } else if (valid) {
-    epi_elem<T>(i, merge_splits<T>(pm, ps, Nr, i, nsplit, [](int k) { return k; }), c, side, ep, ra);
-  }
+  // the column splits of k_dense_lse (partial k of row i at k Nr + i)
+  if (valid) epi_elem<T>(i, merge_parts<T>(pm, ps, Nr, i, nsplit), c, side, ep, ra);
   epi_finish<T>(ep, ra, blockIdx.x);
 }
 
@@ -1722,34 +1674,11 @@ static void launch_dense_lse_t(const T* xr, int64_t Nr, const T* yc, const T* w,
   if (cost.kind == 1) {
     const T a2 = T(0.25 * M_PI * M_PI / (cost.cut * cost.cut)), cut2 = T(cost.cut * cost.cut);
     hipLaunchKernelGGL((k_dense_lse<T, DIM, R, 1>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side,
-                       c, a2, cut2, cost.act);
+                       c, a2, cut2);
   } else {
     hipLaunchKernelGGL((k_dense_lse<T, DIM, R, 0>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, cps, pm, ps, side,
-                       c, T(0), T(0), static_cast<const uint8_t*>(nullptr));
+                       c, T(0), T(0));
   }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_box_pairs(const T* __restrict__ rbox, int64_t nrb,
-                                                       const T* __restrict__ cbox, int nsp, int dim, T cut2,
-                                                       uint8_t* __restrict__ act) {
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k >= nrb * nsp) return;
-  const T* rb = rbox + 6 * (k / nsp);
-  const T* cb = cbox + 6 * (k % nsp);
-  T gap2 = T(0);
-  for (int d = 0; d < dim; ++d) {
-    const T g = Num<T>::fmax(Num<T>::fmax(cb[2 * d] - rb[2 * d + 1], rb[2 * d] - cb[2 * d + 1]), T(0));
-    gap2 = Num<T>::fma(g, g, gap2);
-  }
-  act[k] = gap2 < cut2 ? 1 : 0;
-}
-
-template <typename T>
-void launch_box_pairs(const T* rbox, int64_t nrb, const T* cbox, int nsp, int dim, double cut2, uint8_t* act,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_box_pairs<T>, dim3(ceil_div(nrb * nsp, kBlock)), dim3(kBlock), 0, s, rbox, nrb, cbox, nsp,
-                     dim, T(cut2), act);
 }
 
 template <typename T>
@@ -1788,6 +1717,215 @@ void launch_chunk_boxes(const T* pts, int64_t n, int64_t per, int dim, T* out, h
   hipLaunchKernelGGL(k_chunk_boxes<T>, dim3(ceil_div(n, per)), dim3(kBlock), 0, s, pts, n, per, dim, out);
 }
 
+// ---------------------------------------------------------------------------
+// WF point clouds on work lists.  K is exactly zero beyond the cut, so a
+// product only needs the (row wave of 64 rows, group of 16 columns) pairs
+// whose boxes lie within the cut of each other.  Once per solve (the
+// geometry is fixed): the boxes of the row waves and of the column groups,
+// one mask bit per (row wave, group) pair within the cut (k_wf_mask), and
+// the work units of every row wave: consecutive ranges [g0, g1) of its
+// groups that hold kWfUnitGroups groups within the cut, the last one
+// possibly fewer (k_wf_units).  Per half-step one wave per unit stages the
+// unit's columns in its own LDS and sums its row wave's 64 rows (one per
+// lane) over them (k_wf_lse), and k_wf_epi merges each row's units in unit
+// order and applies the epilogue.  Unit k of row wave rw sits in slot
+// k nrw + rw (at most ceil(groups / kWfUnitGroups) units per row wave), so
+// the busy slots come first in the launch.
+// ---------------------------------------------------------------------------
+constexpr int kWfUnitGroups = 16;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_wf_mask(const T* __restrict__ rbox, int64_t nrw,
+                                                     const T* __restrict__ gbox, int64_t ngr, int nwd, int dim, T cut2,
+                                                     uint32_t* __restrict__ mask) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nrw * nwd) return;
+  const int64_t rw = t / nwd;
+  const int wd = (int)(t % nwd);
+  const T* rb = rbox + 6 * rw;
+  uint32_t bits = 0;
+  for (int b = 0; b < 32; ++b) {
+    const int64_t g = (int64_t)wd * 32 + b;
+    if (g >= ngr) break;
+    const T* cb = gbox + 6 * g;
+    T gap2 = T(0);
+    for (int d = 0; d < dim; ++d) {
+      const T e = Num<T>::fmax(Num<T>::fmax(cb[2 * d] - rb[2 * d + 1], rb[2 * d] - cb[2 * d + 1]), T(0));
+      gap2 = Num<T>::fma(e, e, gap2);
+    }
+    if (gap2 < cut2) bits |= 1u << b;
+  }
+  mask[t] = bits;
+}
+
+__global__ __launch_bounds__(kBlock) void k_wf_units(const uint32_t* __restrict__ mask, int64_t nrw, int nwd,
+                                                      int2* __restrict__ units, int* __restrict__ ucnt,
+                                                      int* __restrict__ umax) {
+  const int64_t rw = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (rw >= nrw) return;
+  const uint32_t* m = mask + rw * nwd;
+  int n = 0, g0 = -1, cnt = 0, last = 0;
+  for (int wd = 0; wd < nwd; ++wd) {
+    uint32_t bits = m[wd];
+    while (bits) {
+      const int g = wd * 32 + __builtin_ctz(bits);
+      bits &= bits - 1;
+      if (g0 < 0) g0 = g;
+      last = g + 1;
+      if (++cnt == kWfUnitGroups) {
+        units[(int64_t)n++ * nrw + rw] = make_int2(g0, last);
+        g0 = -1;
+        cnt = 0;
+      }
+    }
+  }
+  if (g0 >= 0) units[(int64_t)n++ * nrw + rw] = make_int2(g0, last);
+  ucnt[rw] = n;
+  atomicMax(umax, n);
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_wf_lse(const T* __restrict__ xr, int64_t Nr, const T* __restrict__ yc,
+                                                    const T* __restrict__ w, int64_t Mc,
+                                                    const uint32_t* __restrict__ mask, const int2* __restrict__ units,
+                                                    const int* __restrict__ ucnt, int nwd, T* __restrict__ pm,
+                                                    T* __restrict__ ps, int side, const Ctrl* __restrict__ c, T a2,
+                                                    T cut2) {
+  using V4 = typename Vec4<T>::type;
+  // per wave: its unit's groups and their columns (x, y, z, w)
+  __shared__ int glist[kBlock / 64][kWfUnitGroups];
+  __shared__ V4 cols[kBlock / 64][kWfUnitGroups * 16];
+  if (skip_side(c, side)) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t nrw = (Nr + 63) / 64;
+  const int64_t slot = (int64_t)blockIdx.x * (kBlock / 64) + wv;
+  const int64_t rw = slot % nrw, k = slot / nrw;
+  // a wave past its row wave's units has no work, but takes part in the
+  // block's two barriers (wave-uniform)
+  const bool has = k < ucnt[rw];
+  int ng = 0;
+  if (has) {
+    const int2 un = units[slot];
+    for (int wd = un.x >> 5; wd <= (un.y - 1) >> 5; ++wd) {
+      uint32_t bits = mask[rw * nwd + wd];
+      while (bits) {
+        const int g = wd * 32 + __builtin_ctz(bits);
+        bits &= bits - 1;
+        if (g < un.x || g >= un.y) continue;
+        if (lane == 0) glist[wv][ng] = g;
+        ++ng;
+      }
+    }
+  }
+  __syncthreads();
+  // stage the unit's columns: every load in flight at once, then LDS
+  constexpr int NR = kWfUnitGroups * 16 / 64;
+  V4 rec[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int k = r * 64 + lane;
+    V4 q;
+    q.x = q.y = q.z = T(0);
+    q.w = Num<T>::ninf();
+    if (k < ng * 16) {
+      const int64_t col = (int64_t)glist[wv][k >> 4] * 16 + (k & 15);
+      if (col < Mc) {
+        q.x = yc[col];
+        if (DIM > 1) q.y = yc[Mc + col];
+        if (DIM > 2) q.z = yc[2 * Mc + col];
+        q.w = w[col];
+      }
+    }
+    rec[r] = q;
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    if (r * 64 + lane < ng * 16) cols[wv][r * 64 + lane] = rec[r];
+  __syncthreads();
+  if (!has) return;
+  const T ewf = T(2.0 / eps_of(c, side));
+  const int64_t i = rw * 64 + lane < Nr ? rw * 64 + lane : Nr - 1;
+  T xi[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) xi[d] = xr[d * Nr + i];
+  Lse2<T> acc;
+  acc.init();
+  for (int g = 0; g < ng; ++g) {
+    T t[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const V4 q = cols[wv][g * 16 + j];
+      T d2 = (xi[0] - q.x) * (xi[0] - q.x);
+      if (DIM > 1) d2 = Num<T>::fma(xi[1] - q.y, xi[1] - q.y, d2);
+      if (DIM > 2) d2 = Num<T>::fma(xi[2] - q.z, xi[2] - q.z, d2);
+      t[j] = q.w + wf_log2k<T>(d2, a2, cut2, ewf);
+    }
+    acc.template add<16>(t);
+  }
+  pm[slot * 64 + lane] = acc.m;
+  ps[slot * 64 + lane] = acc.s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_wf_epi(const T* __restrict__ pm, const T* __restrict__ ps,
+                                                    const int* __restrict__ ucnt, int64_t Nr, int side,
+                                                    const Ctrl* __restrict__ c, EpiArgs<T> ep) {
+  if (skip_side(c, side)) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  ResAcc<T> ra;
+  ra.init();
+  if (i < Nr) {
+    // the units of the row's wave (unit k at slot k nrw + rw, row i at lane
+    // i % 64); a row with no unit, or no term within the cut, gets -inf
+    const int64_t rw = i / 64, nrw = (Nr + 63) / 64;
+    epi_elem<T>(i, merge_parts<T>(pm, ps, 64 * nrw, rw * 64 + i % 64, ucnt[rw]), c, side, ep, ra);
+  }
+  epi_finish<T>(ep, ra, blockIdx.x);
+}
+
+template <typename T>
+void launch_wf_lists(const T* rows, int64_t Nr, const T* cols, int64_t Mc, int dim, double cut, const WfLists<T>& L,
+                     hipStream_t s) {
+  const int64_t nrw = (Nr + 63) / 64, ngr = (Mc + 15) / 16;
+  const int nwd = (int)((ngr + 31) / 32);
+  launch_chunk_boxes<T>(rows, Nr, 64, dim, L.rbox, s);
+  launch_chunk_boxes<T>(cols, Mc, 16, dim, L.gbox, s);
+  hipLaunchKernelGGL(k_wf_mask<T>, dim3(ceil_div(nrw * nwd, kBlock)), dim3(kBlock), 0, s, L.rbox, nrw, L.gbox, ngr,
+                     nwd, dim, T(cut * cut), L.mask);
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, L.umax);
+  hipLaunchKernelGGL(k_wf_units, dim3(ceil_div(nrw, kBlock)), dim3(kBlock), 0, s, L.mask, nrw, nwd, L.units, L.ucnt,
+                     L.umax);
+}
+
+template <typename T>
+void launch_wf_lse(int dim, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, double cut,
+                   const WfLists<T>& L, int umax, T* pm, T* ps, int side, const Ctrl* c, hipStream_t s) {
+  const int64_t nrw = (Nr + 63) / 64, ngr = (Mc + 15) / 16;
+  const int nwd = (int)((ngr + 31) / 32);
+  // the slots of the first umax units of every row wave (unit-major): the
+  // rest are empty
+  if (umax < 1) umax = 1;
+  const dim3 grid(ceil_div(nrw * umax, kBlock / 64));
+  const T a2 = T(0.25 * M_PI * M_PI / (cut * cut)), cut2 = T(cut * cut);
+#define UOT_WF(D)                                                                                                 \
+  hipLaunchKernelGGL((k_wf_lse<T, D>), grid, dim3(kBlock), 0, s, xr, Nr, yc, w, Mc, L.mask, L.units, L.ucnt, nwd, \
+                     pm, ps, side, c, a2, cut2)
+  if (dim == 1) UOT_WF(1);
+  else if (dim == 2) UOT_WF(2);
+  else UOT_WF(3);
+#undef UOT_WF
+}
+
+template <typename T>
+void launch_wf_epi(const T* pm, const T* ps, const WfLists<T>& L, int64_t Nr, int64_t Mc, int side, const Ctrl* c,
+                   const EpiArgs<T>& ep, hipStream_t s) {
+  (void)Mc;
+  hipLaunchKernelGGL(k_wf_epi<T>, dim3(ceil_div(Nr, kBlock)), dim3(kBlock), 0, s, pm, ps, L.ucnt, Nr, side, c, ep);
+}
+
 template <typename T>
 void launch_dense_lse(int dim, int R, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, int nsplit,
                       int64_t cps, T* pm, T* ps, int side, const Ctrl* c, const CostArgs& cost, hipStream_t s) {
@@ -1804,9 +1942,8 @@ void launch_dense_lse(int dim, int R, const T* xr, int64_t Nr, const T* yc, cons
 
 template <typename T>
 void launch_dense_epi(const T* pm, const T* ps, int nsplit, int64_t Nr, int side, const Ctrl* c,
-                      const EpiArgs<T>& ep, hipStream_t s, const uint8_t* act) {
-  hipLaunchKernelGGL(k_dense_epi<T>, dim3(ceil_div(Nr, kBlock)), dim3(kBlock), 0, s, pm, ps, nsplit, Nr, side, c, ep,
-                     act);
+                      const EpiArgs<T>& ep, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_epi<T>, dim3(ceil_div(Nr, kBlock)), dim3(kBlock), 0, s, pm, ps, nsplit, Nr, side, c, ep);
 }
 
 void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s, int nfields, int par) {
@@ -1926,9 +2063,14 @@ void launch_dense_cost(int dim, const T* xr, int64_t Nr, const T* yc, const T* w
   template void launch_dense_lse<T>(int, int, const T*, int64_t, const T*, const T*, int64_t, int, int64_t, T*,  \
                                     T*, int, const Ctrl*, const CostArgs&, hipStream_t);                          \
   template void launch_chunk_boxes<T>(const T*, int64_t, int64_t, int, T*, hipStream_t);                        \
-  template void launch_box_pairs<T>(const T*, int64_t, const T*, int, int, double, uint8_t*, hipStream_t);       \
+  template void launch_wf_lists<T>(const T*, int64_t, const T*, int64_t, int, double, const WfLists<T>&,          \
+                                   hipStream_t);                                                                  \
+  template void launch_wf_lse<T>(int, const T*, int64_t, const T*, const T*, int64_t, double, const WfLists<T>&, \
+                                 int, T*, T*, int, const Ctrl*, hipStream_t);                                     \
+  template void launch_wf_epi<T>(const T*, const T*, const WfLists<T>&, int64_t, int64_t, int, const Ctrl*,      \
+                                 const EpiArgs<T>&, hipStream_t);                                                 \
   template void launch_dense_epi<T>(const T*, const T*, int, int64_t, int, const Ctrl*, const EpiArgs<T>&,       \
-                                    hipStream_t, const uint8_t*);                                                 \
+                                    hipStream_t);                                                                 \
   template void launch_bary_combine<T>(const T*, int, int64_t, const BaryW&, double, const DivDev&, const T*,    \
                                        T*, T*, T*, const Ctrl*, int, hipStream_t);                               \
   template int launch_obj_side<T>(const T*, const T*, const T*, const T*, int64_t, double, const DivDev&, T*,    \

@@ -15,11 +15,6 @@ struct CostArgs {
   int kind;
   int pad;
   double cut;
-  // WF dense products: per (block of 256 rows, column split), 1 when some
-  // pair of the two boxes lies within the cut, 0 when every entry is exactly
-  // zero (the product skips the block, the split merge the partial); null:
-  // every block active
-  const uint8_t* act = nullptr;
 };
 
 // What the last pass of a Gibbs product does with S2 = log2 of the product.
@@ -81,14 +76,34 @@ void launch_dense_lse(int dim, int R, const T* xr, int64_t Nr, const T* yc, cons
 // out[6 b + 2 d], out[6 b + 2 d + 1] = min, max of coordinate d over chunk b
 template <typename T>
 void launch_chunk_boxes(const T* pts, int64_t n, int64_t per, int dim, T* out, hipStream_t s);
-// act[b * nsp + s] = 1 when box b of rbox and box s of cbox are closer than
-// cut (squared distance of the boxes below cut2), else 0
+// WF point clouds on work lists (one side: rows against columns): boxes of
+// the row waves (6 per 64 rows) and of the column groups (6 per 16
+// columns), the mask of (row wave, group) pairs within the cut (nwd =
+// ceil(groups / 32) words per row wave), the work units (group range
+// [g0, g1) holding up to 16 groups within the cut) of each row wave in
+// slots k nrw + rw, and their count per row wave
+template <typename T> struct WfLists {
+  T* rbox;
+  T* gbox;
+  uint32_t* mask;
+  int2* units;
+  int* ucnt;
+  int* umax;   // the largest unit count of a row wave
+};
 template <typename T>
-void launch_box_pairs(const T* rbox, int64_t nrb, const T* cbox, int nsp, int dim, double cut2, uint8_t* act,
-                      hipStream_t s);
+void launch_wf_lists(const T* rows, int64_t Nr, const T* cols, int64_t Mc, int dim, double cut, const WfLists<T>& L,
+                     hipStream_t s);
+// partial log2-sum-exp of every unit (pm, ps: 64 per unit slot)
+template <typename T>
+void launch_wf_lse(int dim, const T* xr, int64_t Nr, const T* yc, const T* w, int64_t Mc, double cut,
+                   const WfLists<T>& L, int umax, T* pm, T* ps, int side, const Ctrl* c, hipStream_t s);
+// merge of each row's units in unit order, then the epilogue
+template <typename T>
+void launch_wf_epi(const T* pm, const T* ps, const WfLists<T>& L, int64_t Nr, int64_t Mc, int side, const Ctrl* c,
+                   const EpiArgs<T>& ep, hipStream_t s);
 template <typename T>
 void launch_dense_epi(const T* pm, const T* ps, int nsplit, int64_t Nr, int side, const Ctrl* c,
-                      const EpiArgs<T>& ep, hipStream_t s, const uint8_t* act = nullptr);
+                      const EpiArgs<T>& ep, hipStream_t s);
 void launch_control(Ctrl* c, const ResPart* part, int nparts, double* hist, hipStream_t s, int nfields, int par);
 void launch_res_reduce(const ResPart* part, int nparts, double* out, hipStream_t s);
 void launch_ctrl_init(Ctrl* c, const Ctrl& init, hipStream_t s);
