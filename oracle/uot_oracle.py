@@ -416,7 +416,7 @@ def eps_schedule(eps: float, eps0: Optional[float], n_stages: int = 10, iters_pe
 def solve(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, eps: float,
           tol: float = 1e-6, max_iter: int = 10000, v0=None, u0=None,
           eps0: Optional[float] = None, n_stages: int = 10, iters_per_stage: int = 100,
-          record: bool = False):
+          record: bool = False, rebalance_at: Optional[int] = None):
     """Scaling iterations (S): each iteration is an X half-step
         S = log K(b (.) dy),  u <- eps log proxdiv_F1(e^S)
     followed by a Y half-step
@@ -426,8 +426,20 @@ def solve(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, eps: float,
     residual r <= tol at the final eps (annealing iterations count), or at
     max_iter.
 
+    rebalance_at = K (KL penalties on both marginals): the v that starts
+    iteration K is replaced by v - s with s the mass-balance shift of
+    `mass_balance_shift` (Prop. "alternating": only v enters the iterates, so
+    this is a restart from a better start, and the fixed point is unchanged).
+    As u is affine in a constant shift of v (KL row of Table
+    proximalexplicit), the restart is taken after the X half-step of
+    iteration K: u <- u + theta1 s, with P from that u and Q from the v it was
+    computed from.  The residual of iteration K is that of the unshifted u,
+    and an iteration that stops is not shifted.
+
     Returns dict(u, v, iters, res (list), converged, hist, S) with S the last X product.
     """
+    if rebalance_at is not None and (F1.kind != "kl" or F2.kind != "kl"):
+        raise ValueError("the mass balance takes KL penalties on both marginals")
     N = len(logp)
     M = len(logq)
     v = np.zeros(M) if v0 is None else np.array(v0, np.float64)
@@ -448,6 +460,14 @@ def solve(geom, logp, logq, logdx, logdy, F1: Div, F2: Div, eps: float,
             S = geom.lse_x(expo(v, T, logdy, e), e)
             u_new = e * proxdiv_log(F1, logp, S, 0.0, e)
             r = marginal_residual(S, u, u_new, logdx, e)
+            if rebalance_at is not None and it + 1 == rebalance_at and not (final and r <= tol and it + 1 >= 2):
+                with np.errstate(invalid="ignore"):
+                    tp = np.where(np.isneginf(logp), -np.inf, logp - u_new / F1.lam + logdx)
+                    tq = np.where(np.isneginf(logq), -np.inf, logq - v / F2.lam + logdy)
+                lP, lQ = lse(tp, 0), lse(tq, 0)
+                if np.isfinite(lP) and np.isfinite(lQ):
+                    th1 = F1.lam / (F1.lam + e)
+                    u_new = u_new + th1 * (lP - lQ) / (th1 / F1.lam + 1.0 / F2.lam)
             u = u_new
             T = geom.lse_y(expo(u, S, logdx, e), e)
             v = e * proxdiv_log(F2, logq, T, 0.0, e)

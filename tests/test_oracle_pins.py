@@ -836,3 +836,50 @@ def test_mass_balance_rejects_other_penalties():
     with pytest.raises(ValueError):
         O.mass_balance_shift(g, np.log(p), np.log(q), np.log(dx), np.log(dy), O.TV(0.1), O.KL(1.0), 0.1,
                              np.zeros(4))
+
+
+@pytest.mark.parametrize("K", [1, 2, 7])
+def test_solve_rebalance_is_a_restart_from_the_balanced_v(K):
+    """The in-solve mass balance at iteration K against its definition: the
+    plain iteration for K - 1 iterations, the start v - s of
+    `mass_balance_shift` (pinned above against a root search on the explicit
+    plan), and the plain iteration from there.  The rebalanced solve takes the
+    shift after the X half-step (u + theta1 s), so this also pins the affine
+    dependence of u on a constant shift of v; lam1 != lam2 and non-uniform
+    weights make a swapped lam or a wrong theta visible."""
+    rng = np.random.default_rng(25)
+    x, y, p, q, dx, dy = _rand_problem(rng, 30, 26)
+    g = O.PointsGeom(x, y)
+    lg = (np.log(p), np.log(q), np.log(dx), np.log(dy))
+    F1, F2, eps, n = O.KL(0.4), O.KL(0.9), 0.05, 12
+    reb = O.solve(g, *lg, F1, F2, eps, tol=0.0, max_iter=n, rebalance_at=K)
+    v, u = np.zeros(len(y)), np.zeros(len(x))
+    if K > 1:
+        first = O.solve(g, *lg, F1, F2, eps, tol=0.0, max_iter=K - 1)
+        v, u = first["v"], first["u"]
+    s = O.mass_balance_shift(g, *lg, F1, F2, eps, v)
+    assert abs(s) > 1e-3                     # a real shift
+    rest = O.solve(g, *lg, F1, F2, eps, tol=0.0, max_iter=n - K + 1, v0=v - s, u0=u)
+    np.testing.assert_allclose(reb["u"], rest["u"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(reb["v"], rest["v"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(reb["res"][K:], rest["res"][1:], rtol=1e-9, atol=0)
+
+
+def test_solve_rebalance_keeps_the_fixed_point_and_converges_faster():
+    """Only v enters the iterates (Prop. alternating): the rebalanced solve
+    reaches the plain solve's potentials; on this problem (KL 1, eps 5e-3,
+    uniform points) the balance once the shape has settled (iteration 30)
+    removes most of the slow constant mode."""
+    rng = np.random.default_rng(26)
+    x, y = rng.uniform(0, 1, (120, 2)), rng.uniform(0, 1, (100, 2))
+    p, q = rng.uniform(0.1, 1.0, 120), rng.uniform(0.1, 1.0, 100)
+    g = O.PointsGeom(x, y)
+    lg = (np.log(p), np.log(q), np.full(120, -np.log(120)), np.full(100, -np.log(100)))
+    F, eps = O.KL(1.0), 5e-3
+    plain = O.solve(g, *lg, F, F, eps, tol=1e-9, max_iter=100000)
+    s0 = O.mass_balance_shift(g, *lg, F, F, eps, np.zeros(100))
+    once = O.solve(g, *lg, F, F, eps, tol=1e-9, max_iter=100000, v0=np.full(100, -s0))
+    twice = O.solve(g, *lg, F, F, eps, tol=1e-9, max_iter=100000, v0=np.full(100, -s0), rebalance_at=30)
+    np.testing.assert_allclose(twice["u"], plain["u"], atol=1e-7)
+    np.testing.assert_allclose(twice["v"], plain["v"], atol=1e-7)
+    assert twice["iters"] < 0.7 * once["iters"] < 0.7 * plain["iters"]
