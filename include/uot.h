@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define UOT_ABI_VERSION 2
+#define UOT_ABI_VERSION 3
 
 enum uot_status_code {
   UOT_OK = 0,
@@ -206,6 +206,23 @@ typedef struct uot_params {
                             the first solve of a shape (4 candidates, a few
                             ms; kept in the context; UOT_DENSE_BLOCKS in
                             the environment fixes the block target)       */
+  int32_t rebalance_at;  /* ragged batches with KL on both marginals (ABI
+                            version 3): at iteration rebalance_at (>= 2,
+                            counted from 1; 0 = off) every running problem's
+                            v is replaced by v - s with the mass-balance
+                            shift of uot_batch_balance (the plan's two
+                            marginal masses made equal along the constant
+                            direction, the mode the iteration contracts
+                            slowest, by theta1 theta2 per iteration).  By
+                            Prop. "alternating" only v enters the iterates,
+                            so this restarts the iteration from a better v
+                            and leaves the fixed point unchanged.  It is
+                            taken after that iteration's X half-step as
+                            u <- u + theta1 s (u is affine in a constant
+                            shift of v under KL); the iteration's residual is
+                            that of the unshifted u, and a problem that stops
+                            there is not shifted.  Other entry points take 0. */
+  int32_t reserved;
 } uot_params;
 
 typedef struct uot_result {

@@ -695,8 +695,12 @@ int validate_problem(const uot_problem* pb) {
   return check_div(pb->F2, "F2");
 }
 
-int validate_params(const uot_params* pr) {
+int validate_params(const uot_params* pr, bool batch = false) {
   if (!pr) return fail(UOT_E_INVALID, "params is NULL");
+  if (pr->rebalance_at < 0 || pr->rebalance_at == 1)
+    return fail(UOT_E_INVALID, "rebalance_at must be 0 (off) or >= 2 (the start takes uot_batch_balance)");
+  if (pr->rebalance_at != 0 && !batch)
+    return fail(UOT_E_UNSUPPORTED, "rebalance_at applies to ragged batches only");
   if (!(pr->eps > 0 && std::isfinite(pr->eps))) return fail(UOT_E_INVALID, "eps must be finite and > 0");
   if (pr->max_iter < 1) return fail(UOT_E_INVALID, "max_iter must be >= 1");
   if (!(pr->tol >= 0)) return fail(UOT_E_INVALID, "tol must be >= 0");
@@ -1584,7 +1588,7 @@ struct BatchPlan {
   bool mf = false;                // FP32: the matrix-core product is among the tuner's choices
   size_t o_ctrl, o_logp, o_logq, o_logdx, o_logdy, o_wu, o_wv, o_stop, o_yskip, o_status, o_iters, o_res, o_clock, o_itx,
       o_ity, o_pstart, o_parts, o_curs, o_offN, o_offM, o_ordx, o_ordy, o_xs, o_ys, o_permx, o_permy, o_code, o_box,
-      o_us, o_vs, o_pw, total;
+      o_us, o_vs, o_pw, o_pstartY, o_bal, total;
 };
 
 int make_batch_plan(BatchPlan& P, const uot_batch_problem* pb) {
@@ -1652,6 +1656,10 @@ int make_batch_plan(BatchPlan& P, const uot_batch_problem* pb) {
   P.o_us = take(mf ? 4 * P.totN : 0);
   P.o_vs = take(mf ? 4 * P.totM : 0);
   P.o_pw = take(mf ? 4 * (P.totN + P.totM) : 0);
+  // the in-solve mass balance: first Y slot of each problem, and the mass
+  // partials of the X items, then of the Y items
+  P.o_pstartY = take(4 * (P.B + 1));
+  P.o_bal = take(4 * e * P.max_items);
   P.total = o;
   return UOT_OK;
 }
@@ -1936,7 +1944,12 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
   BItem* itx = at<BItem>(ws, P.o_itx);
   BItem* ity = at<BItem>(ws, P.o_ity);
   int32_t* pstart_d = at<int32_t>(ws, P.o_pstart);
+  int32_t* pstartY_d = at<int32_t>(ws, P.o_pstartY);
   ResPart* parts = at<ResPart>(ws, P.o_parts);
+  T* bal_xm = at<T>(ws, P.o_bal);   // mass partials: X (m, s), then Y (m, s)
+  T* bal_xs = bal_xm + P.max_items;
+  T* bal_ym = bal_xs + P.max_items;
+  T* bal_ys = bal_ym + P.max_items;
   int* curs = at<int>(ws, P.o_curs);
   int64_t* offN_d = at<int64_t>(ws, P.o_offN);
   int64_t* offM_d = at<int64_t>(ws, P.o_offM);
@@ -1959,6 +1972,7 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
   lists.off[0] = offN_d;
   lists.off[1] = offM_d;
   lists.pstart = pstart_d;
+  lists.pstartY = pstartY_d;
   lists.items[0] = itx;
   lists.items[1] = ity;
   lists.count[0] = curs;
@@ -2014,9 +2028,31 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
   auto upload_items = [&](int R) -> int {
     build_pstart(pb->offN, P.B, R, pst);
     HIP_TRY(hipMemcpy(pstart_d, pst.data(), 4 * (P.B + 1), hipMemcpyHostToDevice));
+    build_pstart(pb->offM, P.B, R, pst);
+    HIP_TRY(hipMemcpy(pstartY_d, pst.data(), 4 * (P.B + 1), hipMemcpyHostToDevice));
     lists.rows = 256 * R;
     return UOT_OK;
   };
+  // the in-solve mass balance at iteration rebalance_at (0-based index
+  // rebalance_at - 1: the X epilogue of that iteration and the Y epilogue of
+  // the one before run while the counter holds it)
+  const bool rebal = pr->rebalance_at >= 2;
+  if (rebal && (pb->F1.kind != UOT_DIV_KL || pb->F2.kind != UOT_DIV_KL))
+    return fail(UOT_E_UNSUPPORTED, "rebalance_at takes KL penalties on both marginals");
+  BatchBalance<T> bbal{};
+  if (rebal) {
+    bbal.pxm = bal_xm;
+    bbal.pxs = bal_xs;
+    bbal.pym = bal_ym;
+    bbal.pys = bal_ys;
+    bbal.pstartY = pstartY_d;
+    bbal.offN = offN_d;
+    bbal.pot = uo;
+    bbal.w = wu;
+    bbal.iter = pr->rebalance_at - 1;
+    bbal.lam1 = pb->F1.lambda;
+    bbal.lam2 = pb->F2.lambda;
+  }
   auto init_state = [&]() {
     Ctrl init = make_ctrl(pr->eps, pr->eps0, pr->eps_stages, pr->iters_per_stage, pr->tol, pr->max_iter);
     launch_ctrl_init(ctrl, init, s);
@@ -2042,6 +2078,13 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
   auto iteration = [&](int par) {
     EpiArgs<T> epx = prox_epi<T>(uo, wu, logp, logdx, nullptr, parts, P.totN, pb->F1);
     EpiArgs<T> epy = prox_epi<T>(vo, wv, logq, logdy, nullptr, nullptr, P.totM, pb->F2);
+    if (rebal) {
+      epx.bal_m = bal_xm;
+      epx.bal_s = bal_xs;
+      epy.bal_m = bal_ym;
+      epy.bal_s = bal_ys;
+      epx.bal_iter = epy.bal_iter = pr->rebalance_at - 1;
+    }
     auto product = [&](int half, const BItem* items, int* count, const int64_t* offR, const int64_t* offC,
                        const T* xr, int64_t totR, const T* yc, int64_t totC, const T* w, float* pwr,
                        const EpiArgs<T>& ep) {
@@ -2057,7 +2100,7 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
     };
     // (count + 2: the list's work cursor)
     timed(0, [&] { product(0, itx, curs + 0, offN_d, offM_d, xo, P.totN, yo, P.totM, wv, pw, epx); });
-    timed(2, [&] { launch_batch_control(ctrl, bc_dev, (int)P.B, parts, pstart_d, lists, par, s); });
+    timed(2, [&] { launch_batch_control<T>(ctrl, bc_dev, (int)P.B, parts, pstart_d, lists, par, bbal, s); });
     timed(1, [&] {
       product(1, ity, curs + 1, offM_d, offN_d, yo, P.totM, xo, P.totN, wu, pw ? pw + P.totN : nullptr, epy);
     });
@@ -2631,7 +2674,7 @@ int uot_solve_batched(uot_ctx* ctx, const uot_batch_problem* pb, const uot_param
   int rc = check_div(pb->F1, "F1");
   if (rc) return rc;
   if ((rc = check_div(pb->F2, "F2"))) return rc;
-  if ((rc = validate_params(pr))) return rc;
+  if ((rc = validate_params(pr, true))) return rc;
   if (pb->dtype == UOT_F32)
     return batch_t<float>(ctx, pb, pr, static_cast<float*>(u), static_cast<float*>(v), static_cast<char*>(ws), wsb, res);
   return batch_t<double>(ctx, pb, pr, static_cast<double*>(u), static_cast<double*>(v), static_cast<char*>(ws), wsb,

@@ -649,6 +649,9 @@ __global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_batch_mf(const BItem
                                 skip_tiles != 0, m, tot, rc, evaluated);
     ResAcc<float> ra;
     ra.init();
+    const bool bal = bal_on<float>(ep, c);   // (block-uniform)
+    MassAcc<float> mb;
+    mb.init();
     // every lane of a row holds its (m, total); lane (q, l) finishes row
     // 16 (4 h + q) + l of the wave, so each epilogue round has all 64 lanes
     // busy (G / 4 rounds instead of G rounds of 16 lanes)
@@ -661,10 +664,12 @@ __global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_batch_mf(const BItem
       if (row < I.nrows) {
         const float lse = mg == -__builtin_inff() ? mg : mg + rg + __builtin_log2f(tg);
         epi_elem<float>(rb + row, lse, c, side, ep, ra);
+        if (bal) bal_elem<float>(rb + row, lse, c, side, ep, mb);
         pw[rb + row] = mg;
       }
     }
     epi_finish<float>(ep, ra, I.part);
+    if (bal) block_lse_reduce<float>(mb.m, mb.s, ep.bal_m + I.part, ep.bal_s + I.part);
   }
   if (pairs) count_pairs<G>(pairs, evaluated);
 }

@@ -194,6 +194,7 @@ struct BatchLists {
   const int32_t* ord[2];   // problem order of the X-row and Y-row lists
   const int64_t* off[2];   // row offsets of each side (offN, offM)
   const int32_t* pstart;   // residual slot of the first X item of each problem
+  const int32_t* pstartY;  // mass-partial slot of the first Y item of each problem
   BItem* items[2];         // the lists (written)
   int* count[2];           // their lengths (written)
   int* cursor[2];          // the products' work cursors (reset every iteration)

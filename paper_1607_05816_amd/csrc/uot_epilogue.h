@@ -93,6 +93,37 @@ __device__ __forceinline__ void epi_elem(int64_t e, T S2, const Ctrl* __restrict
   epi_apply<T>(e, S2, epi_load<T>(e, ep), c, side, ep, ra);
 }
 
+// Ragged batches, the in-solve mass balance: in the half-steps that run
+// while the iteration counter equals ep.bal_iter, the plan's marginal mass
+// over an item's rows (log2 units: S2 + (pot/eps + log d) log2(e), the row's
+// a K b d, once its epilogue wrote the new potential) goes to one more
+// block partial.  Rows with no mass (p = 0, or a vanishing product) add
+// nothing.
+template <typename T>
+__device__ __forceinline__ bool bal_on(const EpiArgs<T>& ep, const Ctrl* __restrict__ c) {
+  return ep.bal_m != nullptr && c->iter == ep.bal_iter;
+}
+// (m, s): a running log2-sum-exp in T precision, m + log2 s
+template <typename T> struct MassAcc {
+  T m, s;
+  __device__ __forceinline__ void init() { m = Num<T>::ninf(); s = T(0); }
+  __device__ __forceinline__ void add(T t) {
+    if (t == Num<T>::ninf()) return;
+    const T mn = Num<T>::fmax(m, t);
+    s = s * Num<T>::exp2(m - mn) + Num<T>::exp2(t - mn);
+    m = mn;
+  }
+};
+template <typename T>
+__device__ __forceinline__ void bal_elem(int64_t e, T S2, const Ctrl* __restrict__ c, int side, const EpiArgs<T>& ep,
+                                         MassAcc<T>& mb) {
+  if (S2 == Num<T>::ninf()) return;
+  const T un = ep.pot[e];
+  if (un == Num<T>::ninf() || un == Num<T>::pinf()) return;
+  const T ld = ep.logd[e < ep.size ? e : e % ep.size];
+  mb.add(S2 + (un / T(eps_of(c, side)) + ld) * T(kLog2e));
+}
+
 // log2-sum-exp (m, s) over a block in T precision (every thread calls it);
 // thread 0 writes the result
 template <typename T>

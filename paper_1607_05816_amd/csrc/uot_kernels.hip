@@ -2210,20 +2210,56 @@ __global__ __launch_bounds__(kBlock) void k_batch_lse(const BItem* __restrict__ 
     }
     ResAcc<T> ra;
     ra.init();
+    const bool bal = bal_on<T>(ep, c);   // (block-uniform)
+    MassAcc<T> mb;
+    mb.init();
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (vr[r]) epi_elem<T>(rb + I.row0 + r * kBlock + threadIdx.x, acc[r].result(), c, side, ep, ra);
+      if (vr[r]) {
+        const int64_t e = rb + I.row0 + r * kBlock + threadIdx.x;
+        const T S2 = acc[r].result();
+        epi_elem<T>(e, S2, c, side, ep, ra);
+        if (bal) bal_elem<T>(e, S2, c, side, ep, mb);
+      }
     epi_finish<T>(ep, ra, I.part);
+    if (bal) block_lse_reduce<T>(mb.m, mb.s, ep.bal_m + I.part, ep.bal_s + I.part);
   }
+}
+
+// log2 of the sum of the partials (m, s)[k0 .. k1) over a wave, in FP64:
+// lane-strided merge, then a butterfly over the 64 lanes (every lane gets it)
+template <typename T>
+__device__ __forceinline__ double wave_lse_parts(const T* __restrict__ pm, const T* __restrict__ ps, int k0, int k1,
+                                                 int lane) {
+  double m = -__builtin_inf(), s = 0.0;
+  for (int k = k0 + lane; k < k1; k += 64) {
+    const double m2 = double(pm[k]), s2 = double(ps[k]);
+    const double mn = fmax(m, m2);
+    if (mn == -__builtin_inf()) continue;
+    s = s * exp2(m - mn) + s2 * exp2(m2 - mn);
+    m = mn;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double m2 = __shfl_xor(m, o), s2 = __shfl_xor(s, o);
+    const double mn = fmax(m, m2);
+    if (mn != -__builtin_inf()) {
+      s = s * exp2(m - mn) + s2 * exp2(m2 - mn);
+      m = mn;
+    }
+  }
+  return m + log2(s);
 }
 
 // per-problem control between the X and Y half-steps, one wave per problem:
 // the residual of the X half-step from the problem's partials (Sec. 4.4's
 // stopping rule on the X marginal), its iteration count, and the stop
 // decision; a stopped problem leaves the item lists at the next compaction
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_batch_control(Ctrl* __restrict__ c, BCtrl* __restrict__ bc, int B,
                                                            const ResPart* __restrict__ part,
-                                                           const int32_t* __restrict__ pstart) {
+                                                           const int32_t* __restrict__ pstart, int par,
+                                                           BatchBalance<T> bal) {
   const int lane = threadIdx.x & 63;
   const int64_t b = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;   // uniform over the wave
   if (b >= B) return;
@@ -2234,20 +2270,37 @@ __global__ __launch_bounds__(kBlock) void k_batch_control(Ctrl* __restrict__ c, 
   float m = -__builtin_inff(), den = 0.f, num = 0.f, du = 0.f;
   for (int k = pstart[b] + lane; k < pstart[b + 1]; k += 64) res_merge<float>(m, den, num, part[k].m, part[k].den, part[k].num);
   wave_res_reduce(m, den, num, du);
-  if (lane != 0) return;
+  // (every lane holds the totals and takes the same decision; lane 0 writes)
   const double r = res_ratio(double(num), double(den));
   const int64_t l = bc->iters[b];
-  bc->res[b] = r;
-  bc->iters[b] = l + 1;
   const bool final_stage = c->iters_per_stage <= 0 || l >= (int64_t)c->n_stages * c->iters_per_stage;
-  int stop = 0;
-  if (r != r) { stop = 1; bc->status[b] = -3; }
-  else if (final_stage && r <= c->tol && l >= 1) { stop = 1; bc->status[b] = 0; }
-  else if (l + 1 >= c->max_iter) { stop = 1; bc->status[b] = 1; }
-  if (stop) {
-    bc->stop[b] = 1;
-    bc->clock[b] = wall_clock64();
-    atomicAdd(&c->nstop, 1);   // a few problems per iteration
+  int stop = 0, status = 1;
+  if (r != r) { stop = 1; status = -3; }
+  else if (final_stage && r <= c->tol && l >= 1) { stop = 1; status = 0; }
+  else if (l + 1 >= c->max_iter) { stop = 1; status = 1; }
+  if (lane == 0) {
+    bc->res[b] = r;
+    bc->iters[b] = l + 1;
+    if (stop) {
+      bc->status[b] = status;
+      bc->stop[b] = 1;
+      bc->clock[b] = wall_clock64();
+      atomicAdd(&c->nstop, 1);   // a few problems per iteration
+    }
+  }
+  if (stop || bal.pxm == nullptr || c->iter != bal.iter) return;
+  // the in-solve mass balance: P from this X half-step's items, Q from the
+  // previous Y half-step's (log2 sums, merged in FP64)
+  const double lP = wave_lse_parts<T>(bal.pxm, bal.pxs, pstart[b], pstart[b + 1], lane);
+  const double lQ = wave_lse_parts<T>(bal.pym, bal.pys, bal.pstartY[b], bal.pstartY[b + 1], lane);
+  if (!(__builtin_isfinite(lP) && __builtin_isfinite(lQ))) return;
+  const double eps = c->eps[par];
+  const double th1 = double(bal.lam1) / (double(bal.lam1) + eps);
+  const double sh = (lP - lQ) * kLn2 / (th1 / double(bal.lam1) + 1.0 / double(bal.lam2));
+  const T du_ = T(th1 * sh), dw = T(th1 * sh / eps * kLog2e);
+  for (int64_t i = bal.offN[b] + lane; i < bal.offN[b + 1]; i += 64) {
+    bal.pot[i] += du_;
+    bal.w[i] += dw;
   }
 }
 
@@ -2334,7 +2387,7 @@ __global__ __launch_bounds__(kCompactBlock) void k_batch_compact(Ctrl* __restric
         it.prob = prob[j];
         it.row0 = q * L.rows;
         it.nrows = (int)(nrow[j] - it.row0 < L.rows ? nrow[j] - it.row0 : L.rows);
-        it.part = side == 0 ? L.pstart[prob[j]] + q : q;
+        it.part = (side == 0 ? L.pstart[prob[j]] : L.pstartY[prob[j]]) + q;
         out[p++] = it;
       }
     carry += total;
@@ -2434,12 +2487,17 @@ void launch_batch_lse(int dim, int R, int blocks, const BItem* items, const int*
 #undef UOT_BL
 }
 
+template <typename T>
 void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const int32_t* pstart,
-                          const BatchLists& L, int par, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_control, dim3((unsigned)ceil_div((int64_t)B * 64, kBlock)), dim3(kBlock), 0, s, c, bc, B,
-                     part, pstart);
+                          const BatchLists& L, int par, const BatchBalance<T>& bal, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_control<T>, dim3((unsigned)ceil_div((int64_t)B * 64, kBlock)), dim3(kBlock), 0, s, c, bc,
+                     B, part, pstart, par, bal);
   hipLaunchKernelGGL(k_batch_compact, dim3(2), dim3(kCompactBlock), 0, s, c, bc, B, L, par, 1);
 }
+template void launch_batch_control<float>(Ctrl*, BCtrl*, int, const ResPart*, const int32_t*, const BatchLists&, int,
+                                          const BatchBalance<float>&, hipStream_t);
+template void launch_batch_control<double>(Ctrl*, BCtrl*, int, const ResPart*, const int32_t*, const BatchLists&,
+                                           int, const BatchBalance<double>&, hipStream_t);
 
 void launch_batch_compact(Ctrl* c, const BCtrl* bc, int B, const BatchLists& L, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_compact, dim3(2), dim3(kCompactBlock), 0, s, c, bc, B, L, 0, 0);

@@ -46,6 +46,28 @@ template <typename T> struct EpiArgs {
   // T + v/eps + log d, the log mass of the plan without the factor z
   T* mass_m;
   T* mass_s;
+  // ragged batches: in the half-steps that run while the control block's
+  // iteration counter equals bal_iter, each work item also writes the plan's
+  // marginal mass over its rows, the log2-sum-exp (bal_m, bal_s)[item part]
+  // of S2 + (pot/eps + log d) log2(e); null: off
+  T* bal_m;
+  T* bal_s;
+  int64_t bal_iter;
+};
+
+// the in-solve mass balance of a ragged batch (KL on both marginals), taken
+// by the control step of iteration `iter`: per running problem the X and Y
+// mass partials give s = log(P/Q) / (theta1/lam1 + 1/lam2), and the X side's
+// potentials and column weights move by theta1 s; px null: off
+template <typename T> struct BatchBalance {
+  const T *pxm, *pxs;       // X items' partials (m, s), slots pstart; null: off
+  const T *pym, *pys;       // Y items' partials, slots pstartY
+  const int32_t* pstartY;   // first Y slot of each problem
+  const int64_t* offN;      // X rows of each problem
+  T* pot;                   // X potentials (u)
+  T* w;                     // X column weights (u/eps + log dx) log2(e)
+  int64_t iter;
+  double lam1, lam2;
 };
 
 template <typename T> void launch_log(const T* src, T* dst, int64_t n, int zero_is_ninf, hipStream_t s);
@@ -192,8 +214,9 @@ void launch_batch_lse(int dim, int R, int blocks, const BItem* items, const int*
 // per-problem control after the X half-step, then the work cursors, the item
 // lists (rebuilt when enough problems stopped) and the iteration's eps
 // bookkeeping
+template <typename T>
 void launch_batch_control(Ctrl* c, BCtrl* bc, int B, const ResPart* part, const int32_t* pstart,
-                          const BatchLists& L, int par, hipStream_t s);
+                          const BatchLists& L, int par, const BatchBalance<T>& bal, hipStream_t s);
 // the item lists of every problem and zero cursors (no bookkeeping): the
 // start of a solve
 void launch_batch_compact(Ctrl* c, const BCtrl* bc, int B, const BatchLists& L, hipStream_t s);

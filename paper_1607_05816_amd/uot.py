@@ -46,7 +46,8 @@ class UotParams(ctypes.Structure):
     _fields_ = [("eps", c_dbl), ("eps0", c_dbl), ("eps_stages", c_i32), ("iters_per_stage", c_i32),
                 ("tol", c_dbl), ("max_iter", c_i64), ("check_every", c_i32), ("use_graph", c_i32),
                 ("v0", c_vp), ("res_hist", c_vp), ("kernel_ms", ctypes.POINTER(c_dbl)),
-                ("kernel_launches", ctypes.POINTER(c_i64)), ("grid_kernel", c_i32), ("dense_kernel", c_i32)]
+                ("kernel_launches", ctypes.POINTER(c_i64)), ("grid_kernel", c_i32), ("dense_kernel", c_i32),
+                ("rebalance_at", c_i32), ("reserved", c_i32)]
 
 
 class UotResult(ctypes.Structure):
@@ -387,10 +388,10 @@ DENSE_AUTO, DENSE_DIRECT, DENSE_TF, DENSE_MF, DENSE_MF3 = 0, 1, 2, 3, 4
 
 def params(eps, tol=1e-6, max_iter=10000, eps0=None, eps_stages=10, iters_per_stage=100, check_every=50,
            use_graph=True, v0=None, res_hist=None, kernel_ms=None, kernel_launches=None,
-           grid_kernel=GRID_AUTO, dense_kernel=0) -> UotParams:
+           grid_kernel=GRID_AUTO, dense_kernel=0, rebalance_at=0) -> UotParams:
     return UotParams(float(eps), float(eps0 or 0.0), int(eps_stages if eps0 else 0), int(iters_per_stage),
                      float(tol), int(max_iter), int(check_every), int(bool(use_graph)), _ptr(v0), _ptr(res_hist),
-                     kernel_ms, kernel_launches, int(grid_kernel), int(dense_kernel))
+                     kernel_ms, kernel_launches, int(grid_kernel), int(dense_kernel), int(rebalance_at), 0)
 
 
 def solve(prob: Problem, eps, ctx: Optional[Context] = None, v0=None, record=False, time_kernels=False, **kw):

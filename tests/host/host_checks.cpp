@@ -55,7 +55,7 @@ static uot_problem grid(int dtype, int dim, const int64_t* n) {
 
 int main() {
   size_t n = 0;
-  EXPECT(uot_abi_version() == 2);
+  EXPECT(uot_abi_version() == 3);
   for (int s = -6; s <= 2; ++s) EXPECT(uot_status_string(s) != nullptr && std::strlen(uot_status_string(s)) > 0);
 
   // point clouds: every dtype, dimension and a range of sizes

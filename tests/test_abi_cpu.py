@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     L = uot.lib()
-    assert L.uot_abi_version() == 2
+    assert L.uot_abi_version() == 3
     for code in (0, 1, -1, -2, -3, -4, -5):
         assert len(L.uot_status_string(code)) > 0
 
@@ -52,7 +52,7 @@ int main(void) {
   O(uot_flow_problem, alpha)
   O(uot_batch_problem, F2) O(uot_batch_problem, dy) O(uot_batch_result, tune_ms) O(uot_batch_result, tile_rows) O(uot_batch_result, product)
   O(uot_geom, n) O(uot_geom, h) O(uot_problem, geom) O(uot_problem, F1) O(uot_problem, F2)
-  O(uot_params, v0) O(uot_params, res_hist) O(uot_params, check_every) O(uot_params, kernel_ms) O(uot_params, kernel_launches) O(uot_params, grid_kernel)
+  O(uot_params, v0) O(uot_params, res_hist) O(uot_params, check_every) O(uot_params, kernel_ms) O(uot_params, kernel_launches) O(uot_params, grid_kernel) O(uot_params, rebalance_at)
   O(uot_bary_problem, alpha) O(uot_bary_problem, F2) O(uot_result, elapsed_ms)
   return 0;
 }

@@ -270,3 +270,84 @@ def test_tuning_table_round_trip():
     assert torch.equal(u1, u2) and torch.equal(v1, v2)
     c1.close()
     c2.close()
+
+
+@pytest.mark.parametrize("dtype,tolr,kern", [(torch.float32, 1e-5, 1), (torch.float32, 1e-5, 4),
+                                             (torch.float64, 1e-11, 1)])
+def test_batch_rebalance_matches_oracle(dtype, tolr, kern):
+    """The in-solve mass balance (rebalance_at = 9) against the oracle's, problem
+    by problem, for a fixed 24 iterations from a random start (so the shift is
+    large): the X and Y mass partials, the per-problem shift in the control
+    step and the moved potentials and column weights all enter."""
+    npd = np.float32 if dtype == torch.float32 else np.float64
+    Ns, Ms, probs = make_batch(41, 25, 20, 700, 2, npd, extra=[(1, 3), (300, 1), (513, 257)])
+    F1, F2 = U.KL(0.7), U.KL(1.3)
+    bp = to_gpu(Ns, Ms, probs, F1, F2, dtype)
+    eps = 0.04
+    rng = np.random.default_rng(42)
+    v0 = [rounded(rng.normal(0.0, 0.3, m), npd) for m in Ms]
+    say("case batch rebalance", dtype, kern)
+    u, v, info = U.solve_batched(bp, eps, v0=torch.tensor(np.concatenate(v0), dtype=dtype, device=DEV), tol=0.0,
+                                 max_iter=24, dense_kernel=kern, rebalance_at=9)
+    # a problem with a single point on one side is solved exactly by the
+    # balance (its constant is the only freedom there): its residual reaches
+    # 0 <= tol and it stops; the others run the 24 iterations
+    its = info["iters"]
+    assert (its == 24).sum() >= len(probs) - 2 and (its > 9).all()
+    us, vs = split(u, bp.offN), split(v, bp.offM)
+    moved = 0
+    for b, (x, y, p, q, dx, dy) in enumerate(probs):
+        args = (O.PointsGeom(x, y), np.log(p), np.log(q), np.log(dx), np.log(dy), O.KL(0.7), O.KL(1.3), eps)
+        ref = O.solve(*args, tol=-1.0, max_iter=int(its[b]), v0=v0[b], rebalance_at=9)
+        plain = O.solve(*args, tol=-1.0, max_iter=int(its[b]), v0=v0[b])
+        assert pot_rel_err(us[b], ref["u"], eps) < tolr, (b, Ns[b], Ms[b])
+        assert pot_rel_err(vs[b], ref["v"], eps) < tolr, (b, Ns[b], Ms[b])
+        moved += pot_rel_err(plain["v"], ref["v"], eps) > 100 * tolr
+    assert moved >= len(probs) // 2
+
+
+@pytest.mark.parametrize("kern", [1, 4])
+def test_batch_rebalance_converged_fewer_iterations(kern):
+    """Converged solves with the balance at the start and again at iteration
+    30: every problem stops within a few iterations of the oracle's own
+    rebalanced solve, at the oracle's potentials, and in fewer iterations than
+    without the second balance."""
+    npd = np.float32
+    Ns, Ms, probs = make_batch(43, 16, 40, 600, 2, npd)
+    F = U.KL(1.0)
+    bp = to_gpu(Ns, Ms, probs, F, F, torch.float32)
+    eps = 0.02   # (the matrix-core product's FP32 error model holds 1e-5 here)
+    say("case batch rebalance converged", kern)
+    v0 = torch.zeros(bp.totM, dtype=torch.float32, device=DEV)
+    U.batch_balance(bp, eps, v0)
+    kw = dict(tol=1e-6, max_iter=20000, check_every=32, dense_kernel=kern)
+    u, v, info = U.solve_batched(bp, eps, v0=v0.clone(), rebalance_at=30, **kw)
+    _, _, once = U.solve_batched(bp, eps, v0=v0.clone(), **kw)
+    assert info["converged"] and info["n_converged"] == bp.B
+    assert info["iters"].sum() < 0.85 * once["iters"].sum()
+    us, vs = split(u, bp.offN), split(v, bp.offM)
+    v0s = split(v0, bp.offM)
+    for b, (x, y, p, q, dx, dy) in enumerate(probs):
+        args = (O.PointsGeom(x, y), np.log(p), np.log(q), np.log(dx), np.log(dy), O.KL(1.0), O.KL(1.0), eps)
+        ref = O.solve(*args, tol=1e-6, max_iter=20000, v0=v0s[b], rebalance_at=30)
+        its = int(info["iters"][b])
+        assert abs(its - ref["iters"]) <= max(2, ref["iters"] // 50), (b, its, ref["iters"])
+        same = O.solve(*args, tol=0.0, max_iter=its, v0=v0s[b], rebalance_at=30)
+        assert pot_rel_err(us[b], same["u"], eps) < 1e-5, (b, its)
+        assert pot_rel_err(vs[b], same["v"], eps) < 1e-5, (b, its)
+
+
+def test_rebalance_argument_checks():
+    npd = np.float32
+    Ns, Ms, probs = make_batch(44, 3, 20, 60, 2, npd)
+    bp = to_gpu(Ns, Ms, probs, U.KL(1.0), U.TV(0.5), torch.float32)
+    with pytest.raises(U.UotError):
+        U.solve_batched(bp, 0.05, tol=0.0, max_iter=5, rebalance_at=3)     # TV: no closed form
+    bp = to_gpu(Ns, Ms, probs, U.KL(1.0), U.KL(1.0), torch.float32)
+    with pytest.raises(U.UotError):
+        U.solve_batched(bp, 0.05, tol=0.0, max_iter=5, rebalance_at=1)     # the start takes uot_batch_balance
+    x, y, p, q, dx, dy = probs[0]
+    T = lambda a: torch.tensor(a, dtype=torch.float32, device=DEV)
+    pb = U.points_problem(T(x), T(y), T(p), T(q), T(dx), T(dy), U.KL(1.0), U.KL(1.0))
+    with pytest.raises(U.UotError):
+        U.solve(pb, 0.05, tol=0.0, max_iter=5, rebalance_at=3)            # batches only
