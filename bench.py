@@ -46,6 +46,10 @@ def exp_peak():
 
 
 RAGGED_B, RAGGED_EPS = 4096, 5e-3
+# the warm+batched form balances each problem's constant again at this
+# iteration, once the shape of v has settled (any iteration from 15 to 100
+# gives the same count on the bench batch)
+RAGGED_REBALANCE = 30
 
 
 def _oracle_iter_seconds(prob, eps, iters):
@@ -146,7 +150,7 @@ def ragged_headline(U, ctx, dev, np, torch, steps, warmup):
 
     def step():
         v0 = cw.v0(bp, ctx=ctx)
-        return CW.solve(bp, v0=v0, ctx=ctx)[2]
+        return CW.solve(bp, v0=v0, ctx=ctx, rebalance_at=RAGGED_REBALANCE)[2]
 
     CW.solve(bp, ctx=ctx)                # the batch signature's one-time product tuning
     for _ in range(warmup):
@@ -174,17 +178,20 @@ def ragged_headline(U, ctx, dev, np, torch, steps, warmup):
         torch.cuda.synchronize()
         cold_s.append(time.perf_counter() - t)
     it_cold = cold["iters"].astype(float)
-    # the warm start's parts: the mass balance without the network, and the
-    # network without the balance (start included in the time)
+    # the warm start's parts (start included in the time): the mass balance
+    # without the network (at the start and again at RAGGED_REBALANCE), the
+    # network without any balance, and the network with the balance at the
+    # start only
     ablation = {}
-    for name, start in (("balance_only", lambda: CW.balanced_cold_v0(bp, ctx=ctx)),
-                        ("network_only", lambda: cw.v0(bp, ctx=ctx, balance=False))):
+    for name, start, reb in (("balance_only", lambda: CW.balanced_cold_v0(bp, ctx=ctx), RAGGED_REBALANCE),
+                             ("network_only", lambda: cw.v0(bp, ctx=ctx, balance=False), 0),
+                             ("no_rebalance", lambda: cw.v0(bp, ctx=ctx), 0)):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        _, _, inf = CW.solve(bp, v0=start(), ctx=ctx)
+        _, _, inf = CW.solve(bp, v0=start(), ctx=ctx, rebalance_at=reb)
         torch.cuda.synchronize()
         ablation[name] = {"seconds": time.perf_counter() - t, "iters_mean": float(inf["iters"].mean()),
-                          "converged": int(inf["n_converged"])}
+                          "converged": int(inf["n_converged"]), "rebalance_at": reb}
     # plain: cold single-problem solves of a stratified sample (one per
     # N*M stratum), each after an untimed first solve of its shape (the
     # product tuning, kept out as the batch's tuning is)
@@ -209,7 +216,7 @@ def ragged_headline(U, ctx, dev, np, torch, steps, warmup):
     # roofline of the batched product: one warm solve with every launch
     # between HIP events on the library stream (no graphs)
     v0 = cw.v0(bp, ctx=ctx)
-    _, _, tk = CW.solve(bp, v0=v0, ctx=ctx, time_kernels=True)
+    _, _, tk = CW.solve(bp, v0=v0, ctx=ctx, time_kernels=True, rebalance_at=RAGGED_REBALANCE)
     it_tk = tk["iters"].astype(float)
     launches = tk["kernel_launches"][0] + tk["kernel_launches"][1]
     kms = tk["kernel_ms"][0] + tk["kernel_ms"][1]
@@ -244,7 +251,8 @@ def ragged_headline(U, ctx, dev, np, torch, steps, warmup):
                  "pair_evals_per_s": 2.0 * float((pairs * it_warm).sum()) / (dt / steps),
                  "latency_ms_p50": float(np.percentile(warm["latency_ms"], 50)),
                  "latency_ms_p99": float(np.percentile(warm["latency_ms"], 99)),
-                 "product": kname, "tile_rows": int(warm["tile_rows"]), "blocks_per_cu": int(warm["blocks_per_cu"])},
+                 "product": kname, "tile_rows": int(warm["tile_rows"]), "blocks_per_cu": int(warm["blocks_per_cu"]),
+                 "rebalance_at": RAGGED_REBALANCE},
         "cold_batched": {"seconds": min(cold_s), "iters_mean": float(it_cold.mean()),
                          "iters_total": int(it_cold.sum()), "converged": int(cold["n_converged"]),
                          "problem_iters_per_s": float(it_cold.sum()) / min(cold_s)},
