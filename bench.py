@@ -358,12 +358,12 @@ PASS_NAMES = ["k_grid_tf<false, 4>", "k_grid_tf<true, 4>"]
 # on (sha256 of the pass's file and the headers it includes) and are reported
 # as null otherwise.
 TRAFFIC_SOURCES = ["uot_grid_tf.hip", "uot_epilogue.h", "uot_device.h", "uot_launch.h"]
-TRAFFIC_SOURCE_SHA256 = "38bc0ed204173d6a9cc25effd79c3265698ce3347e6b5fafe54186552afeb729"
+TRAFFIC_SOURCE_SHA256 = "50f8d82d2f210de957a6a5b75197e5fc363d635f02faad890fcd174f13677023"
 TRAFFIC_BYTES = {
-    ('k_grid_tf<false, 4>', 1): (2273408, 259840),
-    ('k_grid_tf<false, 4>', 256): (67287172, 67108864),
-    ('k_grid_tf<true, 4>', 1): (3096797, 523671),
-    ('k_grid_tf<true, 4>', 256): (406346152, 134348800),
+    ('k_grid_tf<false, 4>', 1): (2251969, 259840),
+    ('k_grid_tf<false, 4>', 256): (67281653, 67108864),
+    ('k_grid_tf<true, 4>', 1): (3097181, 523671),
+    ('k_grid_tf<true, 4>', 256): (406626417, 134348800),
 }
 
 
@@ -372,11 +372,11 @@ TRAFFIC_BYTES = {
 # runs of `bench.py --pmc-workload batch`; valid for the source they were
 # taken on (sha256 of the product's file and the headers it includes).
 BATCH_TRAFFIC_SOURCES = ["uot_dense_mf.hip", "uot_epilogue.h", "uot_device.h", "uot_launch.h"]
-BATCH_TRAFFIC_SHA256 = "a3ae54a411d7f83e7fb2c70ac48629872ae9cc6dffc53fee9b6e5e1731bbdf09"
+BATCH_TRAFFIC_SHA256 = "3442360a169840e785a486c2f68a096aea275c5dc12a22ea6327d8a360b61d15"
 # (kernel, rows per item) -> (bytes read, bytes written, pair evaluations) of
 # one launch that holds every problem (the counter workload: all 4096
 # problems active, warm maxima)
-BATCH_TRAFFIC_BYTES = {("k_batch_mf", 256): (257609989, 56952992, 3782323547)}
+BATCH_TRAFFIC_BYTES = {("k_batch_mf", 256): (262499079, 56965050, 3782323547)}
 
 
 def _sha256(names):
