@@ -392,10 +392,14 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
       m[g] = attempt == 0 ? wm[g] : -__builtin_inff();
       s[g] = 0.f;
     }
-    for (int64_t c0 = 0; c0 < ncol; c0 += CHUNK) {
-      // this thread's columns h kBlock + t of the chunk
-      constexpr int H = CHUNK / kBlock;
-      float y[H][3], wj[H];
+    // this thread's columns h kBlock + t of a chunk; with chunks of 256
+    // columns (the batch form) loaded one chunk ahead, in flight during the
+    // previous chunk's products (the 512-column dense form has no registers
+    // to spare for it)
+    constexpr bool kAhead = CHUNK == 256;
+    constexpr int H = CHUNK / kBlock;
+    float y[H][3], wj[H];
+    auto load_cols = [&](int64_t c0) {
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         const int64_t col = c0 + h * kBlock + threadIdx.x;
@@ -407,6 +411,13 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
           wj[h] = w[col];
         }
       }
+    };
+    if constexpr (kAhead) load_cols(0);
+    // chunk c0: staged by the whole block (two barriers), the loads of the
+    // next chunk started, and the tiles this wave evaluates returned (bit t:
+    // tile t; wave-uniform; 0 for a wave with no valid row)
+    auto stage = [&](int64_t c0) -> uint32_t {
+      if constexpr (!kAhead) load_cols(c0);
       __syncthreads();                     // the previous chunk's reads are done
 #pragma unroll
       for (int h = 0; h < H; ++h) {
@@ -454,10 +465,13 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
         }
       }
       __syncthreads();
+      if constexpr (kAhead) {
+        if (c0 + CHUNK < ncol) load_cols(c0 + CHUNK);
+      }
       const int64_t rem = ncol - c0;
       const int cnt = rem < CHUNK ? (int)rem : CHUNK;
       const int ntl = (cnt + 15) >> 4;
-      if (!wave_rows) continue;             // (after the staging and its barriers)
+      if (!wave_rows) return 0u;            // (after the staging and its barriers)
       // the tiles this wave evaluates: lane t tests tile t
       uint32_t mask = ntl >= 32 ? 0xFFFFFFFFu : ((1u << ntl) - 1u);
       if (skip_on) {
@@ -477,64 +491,83 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
       }
       mask = __builtin_amdgcn_readfirstlane(mask);
       evaluated += (uint32_t)__builtin_popcount(mask);
-      // a chunk with a row that has no finite running maximum yet (the first
-      // chunk) takes the maximum pass first; others run the sum pass against
-      // the running maxima and take the two passes only when a row's sum leaves
-      // [0, 2^100) (a new maximum far above the old one)
-      bool two = false;
+      return mask;
+    };
+    if (kAhead && unchecked) {
+      // every row of the wave starts from a finite m, fixed through the
+      // split: the accumulator inputs -m are built once
+      mf_f32x4 nm[G];
 #pragma unroll
-      for (int g = 0; g < G; ++g) two = two || m[g] == -__builtin_inff();
-      two = __any(two);
-      if (!two && unchecked) {
-        mf_f32x4 nm[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
+      for (int g = 0; g < G; ++g) nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
+      for (int64_t c0 = 0; c0 < ncol; c0 += CHUNK) {
+        const uint32_t mask = __builtin_amdgcn_readfirstlane(stage(c0));
         mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
-      } else if (!two) {
-        float s0[G];
-        mf_f32x4 nm[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-          s0[g] = s[g];
-          nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
-        }
-        mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
-        bool bad = false;
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-          tot[g] = sum_over_rows(s[g]);
-          bad = bad || !(tot[g] < 0x1p100f);
-        }
-        if (__any(bad)) {
-#pragma unroll
-          for (int g = 0; g < G; ++g) s[g] = s0[g];
-          two = true;
-        } else {
-          // keep the sums near 1: move whole powers of two into the maxima (the
-          // same in the 4 lanes of a row, whose totals are equal)
-#pragma unroll
-          for (int g = 0; g < G; ++g)
-            if (tot[g] > 0x1p32f) {
-              const int k = __builtin_amdgcn_frexp_expf(tot[g]);
-              m[g] += float(k);
-              s[g] = __builtin_amdgcn_ldexpf(s[g], -k);
-            }
-        }
       }
-      if (two) {
-        float mx[G];
-        mf_max_pass<SPLIT, G, kTiles>(base, E, mask, mx);
-        // new running maxima; rescale the sums; accumulator input -max
-        mf_f32x4 nm[G];
+    } else {
+      for (int64_t c0 = 0; c0 < ncol; c0 += CHUNK) {
+        const uint32_t mask = __builtin_amdgcn_readfirstlane(stage(c0));
+        if (!wave_rows) continue;
+        if (!kAhead && unchecked) {
+          mf_f32x4 nm[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          const float mn = fmaxf(m[g], max_over_rows(mx[g]));
-          const float sh = mn == -__builtin_inff() ? 0.f : mn;
-          s[g] *= __builtin_amdgcn_exp2f(m[g] - sh);
-          m[g] = mn;
-          nm[g] = mf_f32x4{-sh, -sh, -sh, -sh};
+          for (int g = 0; g < G; ++g) nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
+          mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
+          continue;
         }
-        mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
+        // a chunk with a row that has no finite running maximum yet (the
+        // first chunk) takes the maximum pass first; others run the sum pass
+        // against the running maxima and take the two passes only when a
+        // row's sum leaves [0, 2^100) (a new maximum far above the old one)
+        bool two = false;
+#pragma unroll
+        for (int g = 0; g < G; ++g) two = two || m[g] == -__builtin_inff();
+        two = __any(two);
+        if (!two) {
+          float s0[G];
+          mf_f32x4 nm[G];
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            s0[g] = s[g];
+            nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
+          }
+          mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
+          bool bad = false;
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            tot[g] = sum_over_rows(s[g]);
+            bad = bad || !(tot[g] < 0x1p100f);
+          }
+          if (__any(bad)) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) s[g] = s0[g];
+            two = true;
+          } else {
+            // keep the sums near 1: move whole powers of two into the maxima (the
+            // same in the 4 lanes of a row, whose totals are equal)
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+              if (tot[g] > 0x1p32f) {
+                const int k = __builtin_amdgcn_frexp_expf(tot[g]);
+                m[g] += float(k);
+                s[g] = __builtin_amdgcn_ldexpf(s[g], -k);
+              }
+          }
+        }
+        if (two) {
+          float mx[G];
+          mf_max_pass<SPLIT, G, kTiles>(base, E, mask, mx);
+          // new running maxima; rescale the sums; accumulator input -max
+          mf_f32x4 nm[G];
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const float mn = fmaxf(m[g], max_over_rows(mx[g]));
+            const float sh = mn == -__builtin_inff() ? 0.f : mn;
+            s[g] *= __builtin_amdgcn_exp2f(m[g] - sh);
+            m[g] = mn;
+            nm[g] = mf_f32x4{-sh, -sh, -sh, -sh};
+          }
+          mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
+        }
       }
     }
     // totals of each row over its 4 lanes; a total below 2^-60 under a finite
