@@ -13,7 +13,7 @@ import pytest
 import torch
 
 from oracle import uot_oracle as O
-from tests.helpers import rounded
+from tests.helpers import pot_rel_err, rounded
 
 pytestmark = pytest.mark.gpu
 
@@ -196,3 +196,50 @@ def test_trained_cloud_warm_start_gains_over_cold_batch():
         ratios.append(min(total["cold"], total["pointwise"], total["balance"]) / total["warm"])
     say("gain over the best start without the network: %s" % ratios)
     assert min(ratios) > 1.0, ratios
+
+
+def test_bench_batch_full_size_sampled_problems_match_oracle():
+    """The bench's own configuration at full size: the 4096-problem ragged
+    batch (seed 0), the trained warm start, the mass balance again at
+    iteration 30, the tuned product, residual 1e-6.  Every problem converges;
+    problems sampled across the range of N M (the smallest, and the nearest to
+    1e4, 1e5, 4e5 and 1.2e6 pairs) are run on the oracle from the same v^(0),
+    with the same in-solve balance, for the iterations each took on the GPU.
+    The bar is the converged FP32 one of the batch tests: the shape of each
+    potential (minus its mean) within 1e-5, its level within the FP32
+    rounding the slowest mode collects, 4 2^-24 L theta eps ln2 / (1 -
+    theta^2) (Thm. convergenceKL's rate for KL on both sides)."""
+    if not os.path.exists(CW.WEIGHTS):
+        pytest.fail("missing trained weights %s" % CW.WEIGHTS)
+    cw = CW.CloudWarmStart.load(CW.WEIGHTS, DEV)
+    probs = CW.ragged(0, B=4096)
+    bp = CW.batch_problem(probs, DEV)
+    say("case bench batch full size")
+    v0 = cw.v0(bp)
+    u, v, info = CW.solve(bp, v0=v0, rebalance_at=30)
+    assert info["n_converged"] == bp.B
+    us, vs, v0h = u.cpu().numpy(), v.cpu().numpy(), v0.cpu().numpy().astype(np.float64)
+    its = np.asarray(info["iters"])
+    pairs = np.array([p.x.shape[0] * p.y.shape[0] for p in probs])
+    # (a problem that stops at the balance iteration itself is not shifted;
+    # the oracle below runs without a tolerance, so those are left out)
+    cand = np.where((pairs <= 1.3e6) & (its > 31))[0]
+    pick = [int(cand[np.argmin(pairs[cand])])]
+    for t in (1e4, 1e5, 4e5, 1.2e6):
+        pick.append(int(cand[np.argmin(np.abs(pairs[cand] - t))]))
+    eps, th = CW.EPS, CW.LAM / (CW.LAM + CW.EPS)
+    F = O.KL(CW.LAM)
+    for b in pick:
+        p = probs[b]
+        x, y = rounded(p.x, np.float32), rounded(p.y, np.float32)
+        lg = [np.log(rounded(a, np.float32)) for a in (p.p, p.q, p.dx, p.dy)]
+        say("  problem %d: %d x %d, %d iterations" % (b, x.shape[0], y.shape[0], its[b]))
+        ref = O.solve(O.PointsGeom(x, y), *lg, F, F, eps, tol=-1.0, max_iter=int(its[b]),
+                      v0=v0h[bp.offM[b]:bp.offM[b + 1]], rebalance_at=30)
+        L = float(np.max(np.abs(ref["S"]))) / np.log(2.0)
+        level = 4 * 2.0 ** -24 * L * th * eps * np.log(2.0) / (1 - th * th)
+        for got, want in ((us[bp.offN[b]:bp.offN[b + 1]], ref["u"]), (vs[bp.offM[b]:bp.offM[b + 1]], ref["v"])):
+            got = np.asarray(got, np.float64)
+            shape = pot_rel_err(got - got.mean(), want - want.mean(), eps)
+            assert shape < 1e-5, (b, its[b], shape)
+            assert abs(got.mean() - want.mean()) <= level, (b, its[b], got.mean() - want.mean(), level)
