@@ -286,7 +286,8 @@ constexpr float kSkipCheck = 0x1p-8f;
 // if no term is finite), tot[g] (the total over the row's 4 lanes, relative
 // to 2^m) and rc[g] = R_i.  Rows past nrow repeat the last valid row (their
 // results are not used).  pw holds the rows' starting maxima on entry and is
-// not written.  st, sbox, tb: the block's LDS.  skip_tiles: leave negligible
+// not written.  st, sbox, tb: the block's LDS (st and tb hold two buffers
+// for chunks of 256 columns).  skip_tiles: leave negligible
 // tiles out; evaluated (wave-uniform) counts the 16-column tiles the wave's
 // product passes take.
 template <int DIM, int G, bool SPLIT, int CHUNK>
@@ -398,6 +399,11 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
     // to spare for it)
     constexpr bool kAhead = CHUNK == 256;
     constexpr int H = CHUNK / kBlock;
+    // the batch form also stages into two LDS buffers in turn (one barrier
+    // per chunk: a buffer is written again only after the barrier that
+    // follows the next chunk's staging, which every wave reaches after its
+    // products on that buffer); the dense form has one
+    auto buf_of = [](int64_t c0) -> int { return kAhead ? (int)((c0 / CHUNK) & 1) : 0; };
     float y[H][3], wj[H];
     auto load_cols = [&](int64_t c0) {
 #pragma unroll
@@ -417,8 +423,12 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
     // next chunk started, and the tiles this wave evaluates returned (bit t:
     // tile t; wave-uniform; 0 for a wave with no valid row)
     auto stage = [&](int64_t c0) -> uint32_t {
-      if constexpr (!kAhead) load_cols(c0);
-      __syncthreads();                     // the previous chunk's reads are done
+      Op* const sb = st + buf_of(c0) * (4 * kCols);
+      float(*const tbb)[8] = tb + buf_of(c0) * kTiles;
+      if constexpr (!kAhead) {
+        load_cols(c0);
+        __syncthreads();                   // the previous chunk's reads are done
+      }
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         const int lc = h * kBlock + threadIdx.x;
@@ -438,11 +448,11 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
           mf_u32x4 cw[4];
           col_words(b, gp, cw);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) st[lc * 4 + k] = __builtin_bit_cast(mf_bf16x8, cw[k]);
+          for (int k = 0; k < 4; ++k) sb[lc * 4 + k] = __builtin_bit_cast(mf_bf16x8, cw[k]);
         } else {
 #pragma unroll
-          for (int d = 0; d < 3; ++d) st[d * kCols + lc] = bd[d];
-          st[3 * kCols + lc] = gj;
+          for (int d = 0; d < 3; ++d) sb[d * kCols + lc] = bd[d];
+          sb[3 * kCols + lc] = gj;
         }
         if (records) {
           // the tile's box (columns of weight -inf left out) and largest weight
@@ -457,10 +467,10 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
           if (li == 0) {
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
-              tb[lc >> 4][d] = rec[d];
-              tb[lc >> 4][3 + d] = rec[3 + d];
+              tbb[lc >> 4][d] = rec[d];
+              tbb[lc >> 4][3 + d] = rec[3 + d];
             }
-            tb[lc >> 4][6] = rec[6];
+            tbb[lc >> 4][6] = rec[6];
           }
         }
       }
@@ -480,10 +490,10 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
           float gap2 = 0.f;
 #pragma unroll
           for (int d = 0; d < DIM; ++d) {
-            const float g = fmaxf(fmaxf(tb[lane][d] - whi[d], wlo[d] - tb[lane][3 + d]), 0.f);
+            const float g = fmaxf(fmaxf(tbb[lane][d] - whi[d], wlo[d] - tbb[lane][3 + d]), 0.f);
             gap2 = __builtin_fmaf(g, g, gap2);
           }
-          keep = tb[lane][6] - cc * gap2 + mw >= -kSkipLog2;
+          keep = tbb[lane][6] - cc * gap2 + mw >= -kSkipLog2;
         }
         const uint32_t kept = (uint32_t)__ballot(keep);
         skipped = skipped || kept != mask;
@@ -501,7 +511,7 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
       for (int g = 0; g < G; ++g) nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
       for (int64_t c0 = 0; c0 < ncol; c0 += CHUNK) {
         const uint32_t mask = __builtin_amdgcn_readfirstlane(stage(c0));
-        mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
+        mf_sum_pass<SPLIT, G, kTiles>(base + buf_of(c0) * (4 * kCols), E, nm, mask, s);
       }
     } else {
       for (int64_t c0 = 0; c0 < ncol; c0 += CHUNK) {
@@ -511,7 +521,7 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
           mf_f32x4 nm[G];
 #pragma unroll
           for (int g = 0; g < G; ++g) nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
-          mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
+          mf_sum_pass<SPLIT, G, kTiles>(base + buf_of(c0) * (4 * kCols), E, nm, mask, s);
           continue;
         }
         // a chunk with a row that has no finite running maximum yet (the
@@ -530,7 +540,7 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
             s0[g] = s[g];
             nm[g] = mf_f32x4{-m[g], -m[g], -m[g], -m[g]};
           }
-          mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
+          mf_sum_pass<SPLIT, G, kTiles>(base + buf_of(c0) * (4 * kCols), E, nm, mask, s);
           bool bad = false;
 #pragma unroll
           for (int g = 0; g < G; ++g) {
@@ -555,7 +565,7 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
         }
         if (two) {
           float mx[G];
-          mf_max_pass<SPLIT, G, kTiles>(base, E, mask, mx);
+          mf_max_pass<SPLIT, G, kTiles>(base + buf_of(c0) * (4 * kCols), E, mask, mx);
           // new running maxima; rescale the sums; accumulator input -max
           mf_f32x4 nm[G];
 #pragma unroll
@@ -566,7 +576,7 @@ __device__ __forceinline__ void mf_tile(const float* __restrict__ xr, int64_t xs
             m[g] = mn;
             nm[g] = mf_f32x4{-sh, -sh, -sh, -sh};
           }
-          mf_sum_pass<SPLIT, G, kTiles>(base, E, nm, mask, s);
+          mf_sum_pass<SPLIT, G, kTiles>(base + buf_of(c0) * (4 * kCols), E, nm, mask, s);
         }
       }
     }
@@ -657,9 +667,9 @@ __global__ __launch_bounds__(kBlock, G == 4 ? 4 : 2) void k_batch_mf(const BItem
                                                       int side, EpiArgs<float> ep, int skip_tiles,
                                                       unsigned long long* __restrict__ pairs) {
   using Op = typename MfOps<SPLIT>::Op;
-  __shared__ Op st[4 * mf_cols(256)];   // chunks of 256 columns: batch problems are small
+  __shared__ Op st[2 * 4 * mf_cols(256)];   // two buffers of 256 columns: batch problems are small
   __shared__ float sbox[4][6];
-  __shared__ float tb[16][8];
+  __shared__ float tb[2 * 16][8];
   __shared__ int item_sh;
   uint32_t evaluated = 0;
   const float cc = float(kLog2e / eps_of(c, side));
