@@ -67,16 +67,6 @@ typedef __bf16 mf_bf16x8 __attribute__((ext_vector_type(8)));
 // LDS columns for chunks of C columns: C staged plus two padding tiles of 16
 constexpr int mf_cols(int C) { return C + 32; }
 
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
-}
 // sum over the four lanes l % 16 + {0, 16, 32, 48}
 __device__ __forceinline__ float sum_over_rows(float x) {
   const LanePair p = lane_xor16(x);
@@ -245,6 +235,15 @@ __device__ __forceinline__ float row16_min(float v) {
   v = fminf(v, dpp_mov<kDppHalfMirror>(v));
   return fminf(v, dpp_mov<kDppMirror>(v));
 }
+// minimum / maximum over the wave (every lane gets it): DPP within each row
+// of 16 lanes, then the lane swaps across rows (no LDS crossbar)
+__device__ __forceinline__ float wave_min(float v) {
+  v = row16_min(v);
+  const LanePair p = lane_xor16(v);
+  const LanePair r = lane_xor32(fminf(p.a, p.b));
+  return fminf(r.a, r.b);
+}
+__device__ __forceinline__ float wave_max(float v) { return max_over_rows(row16_max(v)); }
 
 // the pair evaluations of a block (its waves' tile counts, wave-uniform) added
 // to *pairs with one atomic per block (every thread of the block calls it)
