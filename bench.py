@@ -372,11 +372,11 @@ TRAFFIC_BYTES = {
 # runs of `bench.py --pmc-workload batch`; valid for the source they were
 # taken on (sha256 of the product's file and the headers it includes).
 BATCH_TRAFFIC_SOURCES = ["uot_dense_mf.hip", "uot_epilogue.h", "uot_device.h", "uot_launch.h"]
-BATCH_TRAFFIC_SHA256 = "3442360a169840e785a486c2f68a096aea275c5dc12a22ea6327d8a360b61d15"
+BATCH_TRAFFIC_SHA256 = "8a63a115300e9991087e43e200b805e5b921b38ed6faf0865bd023a7efd01bf4"
 # (kernel, rows per item) -> (bytes read, bytes written, pair evaluations) of
 # one launch that holds every problem (the counter workload: all 4096
 # problems active, warm maxima)
-BATCH_TRAFFIC_BYTES = {("k_batch_mf", 256): (262499079, 56965050, 3782323547)}
+BATCH_TRAFFIC_BYTES = {("k_batch_mf", 256): (283037066, 81724012, 3782323547)}
 
 
 def _sha256(names):
