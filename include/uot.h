@@ -504,8 +504,10 @@ int uot_solve_batched(uot_ctx *ctx, const uot_batch_problem *pb, const uot_param
  * over the points c of its `cols` cloud (0: X, 1: Y) of the same problem.
  * w: device, concatenated over the problems on the cols side (natural log,
  * -inf allowed); out: device, concatenated on the rows side (natural log;
- * -inf where every term is -inf).  Problem dtype; direct product.
- * Workspace: uot_batch_workspace_size.  F1, F2, p, q, dx, dy are not read. */
+ * -inf where every term is -inf).  Problem dtype; FP32 batches take the
+ * matrix-core product (BF16 x 3 operands, FP32 accumulation), FP64 ones the
+ * direct product.  Workspace: uot_batch_workspace_size.  F1, F2, p, q, dx, dy
+ * are not read. */
 int uot_batch_gibbs(uot_ctx *ctx, const uot_batch_problem *pb, double eps, int rows, int cols,
                     const void *w, void *out, void *ws, size_t ws_bytes);
 

@@ -1766,7 +1766,7 @@ int gibbs_items(const BatchPlan& P, const uot_batch_problem* pb, int rows, int c
 // (natural log), direct product; w2 is workspace for the log2 input
 template <typename T>
 void gibbs_launch(const BatchPlan& P, const uot_batch_problem* pb, const BatchGibbs& G, double eps, int rows, int cols,
-                  const T* w, T* w2, T* out, hipStream_t s) {
+                  const T* w, T* w2, T* out, char* ws, hipStream_t s) {
   launch_ctrl_init(G.ctrl, make_ctrl(eps, 0, 0, 0, 0, 1), s);
   launch_batch_init(G.bc_dev, (int)P.B, G.ctrl, s);
   launch_set_int(G.curs + rows, 1, G.n_items[rows], s);
@@ -1776,9 +1776,26 @@ void gibbs_launch(const BatchPlan& P, const uot_batch_problem* pb, const BatchGi
   EpiArgs<T> ep{};
   ep.mode = EPI_RAW;
   ep.out = out;
-  launch_batch_lse<T>(P.dim, 1, G.ncu * 8, G.items[rows], G.curs + rows, G.curs + 2 + rows,
-                      rows ? G.offM_d : G.offN_d, cols ? G.offM_d : G.offN_d,
-                      static_cast<const T*>(rows ? pb->y : pb->x), totR, static_cast<const T*>(cols ? pb->y : pb->x),
+  const int64_t* offR = rows ? G.offM_d : G.offN_d;
+  const int64_t* offC = cols ? G.offM_d : G.offN_d;
+  const T* xr = static_cast<const T*>(rows ? pb->y : pb->x);
+  const T* yc = static_cast<const T*>(cols ? pb->y : pb->x);
+  if constexpr (std::is_same<T, float>::value) {
+    if (P.mf) {
+      // FP32: the matrix-core product (items of 256 rows, 4 blocks per CU),
+      // from no starting maxima; with none, no tile could be left out, so
+      // the tile records are not staged
+      float* pw = at<float>(ws, P.o_pw) + (rows ? P.totN : 0);
+      (void)hipMemsetAsync(pw, 0xFF, sizeof(float) * totR, s);
+      MfSkip sk;
+      sk.on = 0;
+      launch_batch_mf(P.dim, 4, G.ncu * 4, G.items[rows], G.curs + rows, G.curs + 2 + rows, offR, offC, xr, totR, yc,
+                      totC, w2, pw, G.bc_dev, G.ctrl, 0, ep, sk, s);
+      launch_scale<T>(out, totR, kLn2, s);
+      return;
+    }
+  }
+  launch_batch_lse<T>(P.dim, 1, G.ncu * 8, G.items[rows], G.curs + rows, G.curs + 2 + rows, offR, offC, xr, totR, yc,
                       totC, w2, G.bc_dev, G.ctrl, 0, ep, s);
   launch_scale<T>(out, totR, kLn2, s);
 }
@@ -1805,7 +1822,7 @@ int batch_gibbs_t(uot_ctx* ctx, const uot_batch_problem* pb, double eps, int row
   BatchGibbs G;
   if ((rc = batch_gibbs_setup<T>(ctx, P, pb, ws, G))) return rc;
   if ((rc = gibbs_items(P, pb, rows, cols, G))) return rc;
-  gibbs_launch<T>(P, pb, G, eps, rows, cols, w, at<T>(ws, cols ? P.o_wv : P.o_wu), out, ctx->work);
+  gibbs_launch<T>(P, pb, G, eps, rows, cols, w, at<T>(ws, cols ? P.o_wv : P.o_wu), out, ws, ctx->work);
   HIP_TRY(hipGetLastError());
   return finish(ctx);
 }
@@ -1835,7 +1852,7 @@ int batch_balance_t(uot_ctx* ctx, const uot_batch_problem* pb, double eps, float
   float* S = at<float>(ws, P.o_wu);
   const float* dy = static_cast<const float*>(pb->dy);
   launch_balance_w(v0, dy, P.totM, eps, w, s);
-  gibbs_launch<float>(P, pb, G, eps, 0, 1, w, w2, S, s);
+  gibbs_launch<float>(P, pb, G, eps, 0, 1, w, w2, S, ws, s);
   launch_batch_balance(S, static_cast<const float*>(pb->p), static_cast<const float*>(pb->dx), G.offN_d,
                        static_cast<const float*>(pb->q), dy, G.offM_d, P.B, eps, pb->F1.lambda, pb->F2.lambda, v0,
                        shift, s);
@@ -1852,7 +1869,7 @@ struct CloudProd {
   int input;     // 0: log p + log dx, 1: log q + log dy, 2: log dx, 3: log dy
   double a;      // product at eps a (kCloudWhole: the total over the problem)
 };
-constexpr double kCloudWhole = 1e30;   // the kernel is 1 to FP32 precision: log of the total mass
+constexpr double kCloudWhole = -1.0;   // a kernel equal to 1: the log of the total mass, per problem
 constexpr CloudProd kCloudProds[kCloudFeatures - 2] = {
     {0, 0, 0.5}, {0, 0, 1.0}, {0, 0, 2.0}, {0, 0, 4.0},   // mass of the first measure near y_j
     {1, 1, 0.5}, {1, 1, 1.0}, {1, 1, 2.0}, {1, 1, 4.0},   // mass of the second measure near y_j
@@ -1904,13 +1921,17 @@ int cloud_features_t(uot_ctx* ctx, const uot_batch_problem* pb, double eps, cons
   const float* inputs[4] = {in_x[0], in_y[0], in_x[1], in_y[1]};
   for (int k = 0; k < kCloudFeatures - 2; ++k) {
     const CloudProd& c = kCloudProds[k];
+    if (c.a == kCloudWhole) {
+      launch_problem_lse(inputs[c.input], c.cols ? G.offM_d : G.offN_d, G.offM_d, P.B, prod + (int64_t)k * P.totM, s);
+      continue;
+    }
     // rows Y; the items slot of the columns' side holds the matching list
     BatchGibbs Gk = G;
     Gk.items[1] = G.items[c.cols];
     Gk.n_items[1] = G.n_items[c.cols];
-    gibbs_launch<float>(P, pb, Gk, c.a == kCloudWhole ? c.a : c.a * eps, 1, c.cols, inputs[c.input],
+    gibbs_launch<float>(P, pb, Gk, c.a * eps, 1, c.cols, inputs[c.input],
                         at<float>(ws, c.cols ? P.o_wv : P.o_wu),
-                        prod + (int64_t)k * P.totM, s);
+                        prod + (int64_t)k * P.totM, ws, s);
   }
   launch_cloud_assemble(prod, kCloudFeatures - 2, in_y[2], G.offN_d, G.offM_d, P.B, P.totM, (float)eps, shift, scale,
                         x, s);

@@ -236,6 +236,8 @@ void launch_log_sum(const float* a, const float* b, float* out, int64_t n, hipSt
 void launch_cloud_assemble(const float* prod, int n_prod, const float* logq, const int64_t* offN, const int64_t* offM,
                            int64_t B, int64_t totM, float eps, const float* shift, const float* scale, float* x,
                            hipStream_t s);
+void launch_problem_lse(const float* w, const int64_t* offC, const int64_t* offR, int64_t B, float* out,
+                        hipStream_t s);
 void launch_cloud_v0(const float* y, const float* q, int64_t n, float zeps, float out_scale, float out_shift,
                      float* v0, hipStream_t s);
 

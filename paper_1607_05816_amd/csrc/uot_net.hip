@@ -609,6 +609,36 @@ __global__ void k_cloud_assemble(const float* __restrict__ prod, int n_prod, con
   for (int k = 0; k < kCloudFeatures; ++k) xo[k] = (c[k] - nm.shift[k]) * nm.scale[k];
 }
 
+// out_i = log sum_j exp(w_j) over the columns j of the problem that row i
+// belongs to, on every row of it: the product of a kernel equal to 1 (a
+// total mass), which needs no pair.  One block per problem: the maximum,
+// then the sum of exp(w_j - max) accumulated in FP64.
+__global__ void k_problem_lse(const float* __restrict__ w, const int64_t* __restrict__ offC,
+                              const int64_t* __restrict__ offR, float* __restrict__ out) {
+  __shared__ float sm[kB / 64];
+  __shared__ double ss[kB / 64];
+  const int64_t b = blockIdx.x;
+  const int64_t c0 = offC[b], c1 = offC[b + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float m = -__builtin_inff();
+  for (int64_t j = c0 + threadIdx.x; j < c1; j += kB) m = fmaxf(m, w[j]);
+  for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (lane == 0) sm[wv] = m;
+  __syncthreads();
+  m = sm[0];
+  for (int k = 1; k < kB / 64; ++k) m = fmaxf(m, sm[k]);
+  double acc = 0.0;
+  if (m > -__builtin_inff())
+    for (int64_t j = c0 + threadIdx.x; j < c1; j += kB) acc += (double)expf(w[j] - m);
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) ss[wv] = acc;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < kB / 64; ++k) t += ss[k];
+  const float r = m > -__builtin_inff() ? m + (float)log(t) : m;
+  for (int64_t i = offR[b] + threadIdx.x; i < offR[b + 1]; i += kB) out[i] = r;
+}
+
 // v0_j = z eps log q_j + out_scale y_j + out_shift (the network predicts the
 // smooth part of v, the pointwise part z eps log q_j is exact)
 __global__ void k_cloud_v0(const float* __restrict__ y, const float* __restrict__ q, int64_t n, float zeps,
@@ -760,6 +790,11 @@ void launch_cloud_assemble(const float* prod, int n_prod, const float* logq, con
   if (totM > 0)
     hipLaunchKernelGGL(net::k_cloud_assemble, dim3(net::cdiv(totM, net::kB)), dim3(net::kB), 0, s, prod, n_prod, logq,
                        offN, offM, B, totM, eps, nm, x);
+}
+
+void launch_problem_lse(const float* w, const int64_t* offC, const int64_t* offR, int64_t B, float* out,
+                        hipStream_t s) {
+  if (B > 0) hipLaunchKernelGGL(net::k_problem_lse, dim3((unsigned)B), dim3(net::kB), 0, s, w, offC, offR, out);
 }
 
 void launch_cloud_v0(const float* y, const float* q, int64_t n, float zeps, float out_scale, float out_shift,
