@@ -723,11 +723,21 @@ int check_net(const uot_net* n) {
   return UOT_OK;
 }
 
-void forward(const uot_net* n, const Layout& L, const Act& a, const float* x, int64_t batch, hipStream_t s) {
+// train: keep the FP32 pre-activations z for the backward pass; inference
+// writes only the BF16 activations, bias and ReLU applied in the product's
+// epilogue (the same values: bf16(max(z, 0)))
+void forward(const uot_net* n, const Layout& L, const Act& a, const float* x, int64_t batch, hipStream_t s,
+             bool train = true) {
   hipLaunchKernelGGL(k_cast, dim3(cdiv(batch * n->n_in, kB)), dim3(kB), 0, s, x, a.xb, batch * n->n_in, n->in_scale,
                      n->in_shift);
   const u16* inp = a.xb;
   for (int l = 0; l < 3; ++l) {
+    if (!train) {
+      gemm<false, true>(inp, L.in[l], n->wbf16 + L.w[l], L.in[l], (int)batch, L.out[l], L.in[l], nullptr, L.out[l],
+                        a.h[l], n->master + L.b[l], 1, s);
+      inp = a.h[l];
+      continue;
+    }
     gemm<false, true>(inp, L.in[l], n->wbf16 + L.w[l], L.in[l], (int)batch, L.out[l], L.in[l], a.z[l], L.out[l],
                       nullptr, n->master + L.b[l], 0, s, a.splitk, a.splitk_floats);
     // ReLU copy in BF16 (z keeps the pre-activation for the backward mask)
@@ -848,7 +858,7 @@ int uot_warmstart_infer(uot_ctx* ctx, const uot_net* n, const float* x, float* y
   if ((rc = begin(ctx))) return rc;
   const Layout L = layout(n);
   Act a = carve(n, batch, static_cast<char*>(ws));
-  forward(n, L, a, x, batch, ctx->work);
+  forward(n, L, a, x, batch, ctx->work, false);
   HIP_TRY(hipMemcpyAsync(y, a.y, 4 * batch * n->n_out, hipMemcpyDeviceToDevice, ctx->work));
   HIP_TRY(hipGetLastError());
   return finish(ctx);
