@@ -2161,7 +2161,19 @@ int batch_t(uot_ctx* ctx, const uot_batch_problem* pb, const uot_params* pr, T* 
     const int r_hi = pr->dense_kernel == 1 || !P.mf ? 3 : 5;
     for (int ri = r_lo; ri < r_hi; ++ri) {
       if ((rc = upload_items(Rs[ri]))) return rc;
-      for (int bi = 0; bi < 3; ++bi) {
+      // persistent blocks of the matrix-core product: none beyond what a
+      // compute unit holds at once (4 of 4 row groups per wave, 2 of 8: its
+      // launch bounds and LDS), or 4 when it holds fewer; blocks past that
+      // only queue until the list is empty (measured at 8 per CU: about 5 %
+      // slower per warm launch than at 4, a choice two timed iterations did
+      // not reliably see)
+      int nb = 3;
+      if (ri >= 3) {
+        const int res = batch_mf_resident_blocks(P.dim, 4 * Rs[ri]);
+        nb = 0;
+        while (nb < 3 && Bs[nb] <= std::max(res, 4)) ++nb;
+      }
+      for (int bi = 0; bi < nb; ++bi) {
         R = Rs[ri];
         mfk = ri >= 3;
         bpc = Bs[bi];

@@ -756,6 +756,23 @@ void launch_dense_mf(int dim, int groups, bool split, const float* xr, int64_t N
 
 namespace uot {
 
+int batch_mf_resident_blocks(int dim, int groups) {
+  int n = 0;
+  hipError_t e = hipSuccess;
+#define UOT_BMF_OCC(D, G) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_mf<D, G, true>, kBlock, 0)
+  if (groups == 8) {
+    if (dim == 1) UOT_BMF_OCC(1, 8);
+    else if (dim == 2) UOT_BMF_OCC(2, 8);
+    else UOT_BMF_OCC(3, 8);
+  } else {
+    if (dim == 1) UOT_BMF_OCC(1, 4);
+    else if (dim == 2) UOT_BMF_OCC(2, 4);
+    else UOT_BMF_OCC(3, 4);
+  }
+#undef UOT_BMF_OCC
+  return e == hipSuccess && n > 0 ? n : 0;
+}
+
 void launch_batch_mf(int dim, int groups, int blocks, const BItem* items, const int* count, int* cursor,
                      const int64_t* offR, const int64_t* offC, const float* xr, int64_t totR, const float* yc,
                      int64_t totC, const float* w, float* pw, const BCtrl* bc, const Ctrl* c, int side,

@@ -158,6 +158,9 @@ bool tile_skip_enabled();
 // Euclidean): groups = 4 or 8 row groups of 16 per wave (items of 64 groups
 // rows); *count items of the list, pulled from *cursor (zero at launch);
 // pw: starting row maxima (totR), kept between iterations
+// blocks of launch_batch_mf's kernel that one compute unit holds at once
+// (its launch bounds, registers and LDS), 0 if the query fails
+int batch_mf_resident_blocks(int dim, int groups);
 void launch_batch_mf(int dim, int groups, int blocks, const BItem* items, const int* count, int* cursor,
                      const int64_t* offR, const int64_t* offC, const float* xr, int64_t totR, const float* yc,
                      int64_t totC, const float* w, float* pw, const BCtrl* bc, const Ctrl* c, int side,
