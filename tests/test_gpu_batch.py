@@ -85,6 +85,10 @@ def test_batch_converged_each_problem_stops_on_its_own(kern):
     u, v, info = U.solve_batched(bp, eps, tol=1e-6, max_iter=4000, check_every=32, dense_kernel=kern)
     assert info["converged"] and info["n_converged"] == bp.B
     assert info["tile_rows"] in (256, 512, 1024) and info["blocks_per_cu"] in (4, 8, 16)
+    # the matrix-core product gets no more persistent blocks than a compute
+    # unit holds at once (4 with 256 rows per item, 2 with 512: then 4)
+    if info["product"] == 4:
+        assert info["blocks_per_cu"] == 4, info["blocks_per_cu"]
     us, vs = split(u, bp.offN), split(v, bp.offM)
     lat = info["latency_ms"]
     assert np.all(lat > 0)
