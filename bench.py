@@ -358,12 +358,12 @@ PASS_NAMES = ["k_grid_tf<false, 4>", "k_grid_tf<true, 4>"]
 # on (sha256 of the pass's file and the headers it includes) and are reported
 # as null otherwise.
 TRAFFIC_SOURCES = ["uot_grid_tf.hip", "uot_epilogue.h", "uot_device.h", "uot_launch.h"]
-TRAFFIC_SOURCE_SHA256 = "50f8d82d2f210de957a6a5b75197e5fc363d635f02faad890fcd174f13677023"
+TRAFFIC_SOURCE_SHA256 = "d9b3651b18eab72e4f6947301386994449ffd7a674a62e3dfb3e752cbb12d178"
 TRAFFIC_BYTES = {
-    ('k_grid_tf<false, 4>', 1): (2251969, 259840),
-    ('k_grid_tf<false, 4>', 256): (67281653, 67108864),
-    ('k_grid_tf<true, 4>', 1): (3097181, 523671),
-    ('k_grid_tf<true, 4>', 256): (406626417, 134348800),
+    ('k_grid_tf<false, 4>', 1): (2251937, 259840),
+    ('k_grid_tf<false, 4>', 256): (67279922, 67108864),
+    ('k_grid_tf<true, 4>', 1): (3097137, 523671),
+    ('k_grid_tf<true, 4>', 256): (406611194, 134348800),
 }
 
 
